@@ -1,0 +1,109 @@
+"""Modal closed forms of the semi-discrete problems (oracle, test infrastructure).
+
+For du/dt = K u with a diagonalisable K = Q diag(lambda) Q^{-1}, one step of a
+Runge--Kutta method with exact stage solves multiplies each mode by R(tau lambda),
+R the stability function of Section "Method stability in the context of mixed
+precision".  Hence u_N = Q diag(R(tau lambda)^N) Q^{-1} u_0 exactly, at any size.
+
+  * Dirichlet heat: the sine modes phi_k(x) = prod_d sin(k_d pi x_d), k_d = 1..n_d,
+    are eigenvectors of the 7-point Laplacian with
+    lambda_k = -kappa sum_d (4/h_d^2) sin^2(k_d pi h_d / 2); the transform is the
+    type-I discrete sine transform.  (The paper's heat solution is a sine mode,
+    Section "Heat equation".)
+  * Periodic advection-diffusion: the DFT diagonalises K, with, per axis,
+    nu (2 cos theta - 2)/h^2 - b (1 - e^{-i theta})/h for b >= 0 (backward
+    upwind difference) and - b (e^{i theta} - 1)/h for b < 0, theta = 2 pi m / n
+    (numpy's FFT sign convention).
+The continuum decay of the lowest heat mode is exp(-3 pi^2 kappa t) (Section
+"Heat equation": the analytic solution decays at rate 3 pi^2).
+Fields are arrays of shape (nz, ny, nx) (x fastest when flattened).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft as sfft
+
+from .tableaus import stability_function
+
+
+def _spacing(n: int, periodic: bool) -> float:
+    return 1.0 / n if periodic else 1.0 / (n + 1)
+
+
+def heat_eigenvalues(shape, kappa: float) -> np.ndarray:
+    """lambda[kz-1, ky-1, kx-1] of kappa Lap_h with zero Dirichlet, shape = (nx, ny, nz)."""
+    lam1 = []
+    for n in shape:
+        h = _spacing(n, False)
+        k = np.arange(1, n + 1)
+        lam1.append(-(4.0 / h ** 2) * np.sin(k * np.pi * h / 2.0) ** 2)
+    lx, ly, lz = lam1
+    return kappa * (lz[:, None, None] + ly[None, :, None] + lx[None, None, :])
+
+
+def heat_sine_mode(shape, kvec) -> np.ndarray:
+    """prod_d sin(k_d pi x_d), x_d = (i+1) h_d, as an array (nz, ny, nx)."""
+    f = []
+    for n, k in zip(shape, kvec):
+        h = _spacing(n, False)
+        f.append(np.sin(k * np.pi * h * np.arange(1, n + 1)))
+    fx, fy, fz = f
+    return fz[:, None, None] * fy[None, :, None] * fx[None, None, :]
+
+
+def periodic_eigenvalues(shape, nu: float, b) -> np.ndarray:
+    """DFT symbol of nu Lap_h - sum_d b_d D_d^upwind, as an array (nz, ny, nx)."""
+    parts = []
+    for d, n in enumerate(shape):
+        h = _spacing(n, True)
+        theta = 2.0 * np.pi * np.arange(n) / n
+        lam = nu * (2.0 * np.cos(theta) - 2.0) / h ** 2
+        if b[d] >= 0.0:
+            lam = lam - b[d] * (1.0 - np.exp(-1j * theta)) / h
+        else:
+            lam = lam - b[d] * (np.exp(1j * theta) - 1.0) / h
+        parts.append(lam)
+    lx, ly, lz = parts
+    return lz[:, None, None] + ly[None, :, None] + lx[None, None, :]
+
+
+def evolve_heat(u0: np.ndarray, kappa: float, tau: float, nsteps: int, tab) -> np.ndarray:
+    """u_N of the DIRK with exact solves for Dirichlet heat, via DST-I."""
+    nz, ny, nx = u0.shape
+    lam = heat_eigenvalues((nx, ny, nz), kappa)
+    amp = np.real(stability_function(tab, tau * lam)) ** nsteps
+    c = sfft.dstn(u0, type=1)
+    return sfft.idstn(c * amp, type=1)
+
+
+def evolve_heat_exact(u0: np.ndarray, kappa: float, t: float) -> np.ndarray:
+    """Semi-discrete exact solution exp(t K) u0 for Dirichlet heat."""
+    nz, ny, nx = u0.shape
+    lam = heat_eigenvalues((nx, ny, nz), kappa)
+    c = sfft.dstn(u0, type=1)
+    return sfft.idstn(c * np.exp(t * lam), type=1)
+
+
+def evolve_periodic(u0: np.ndarray, nu: float, b, tau: float, nsteps: int, tab) -> np.ndarray:
+    """u_N of the DIRK with exact solves for periodic advection-diffusion, via FFT."""
+    nz, ny, nx = u0.shape
+    lam = periodic_eigenvalues((nx, ny, nz), nu, b)
+    amp = stability_function(tab, tau * lam) ** nsteps
+    return np.real(sfft.ifftn(sfft.fftn(u0) * amp))
+
+
+def evolve_periodic_exact(u0: np.ndarray, nu: float, b, t: float) -> np.ndarray:
+    """Semi-discrete exact solution exp(t K) u0 for periodic advection-diffusion."""
+    nz, ny, nx = u0.shape
+    lam = periodic_eigenvalues((nx, ny, nz), nu, b)
+    return np.real(sfft.ifftn(sfft.fftn(u0) * np.exp(t * lam)))
+
+
+def evolve(u0: np.ndarray, kind: int, bc: int, diff: float, b, tau: float, nsteps: int, tab):
+    """Dispatch to the closed form matching (kind, bc); kind 0 heat, bc 0 Dirichlet."""
+    if kind == 0 and bc == 0:
+        return evolve_heat(u0, diff, tau, nsteps, tab)
+    if bc == 1:
+        bb = (0.0, 0.0, 0.0) if kind == 0 else b
+        return evolve_periodic(u0, diff, bb, tau, nsteps, tab)
+    raise ValueError('no closed form for Dirichlet advection-diffusion')
