@@ -1,0 +1,225 @@
+/*
+ * mprk.h -- C ABI of the MI355X (gfx950) mixed-precision Runge--Kutta library.
+ *
+ * What it computes.  du/dt = K u for a 3-D finite-difference operator K on the
+ * unit cube (the semi-discrete form of Section "Problem setting and solver
+ * design" of arXiv 2412.16638), advanced by a diagonally implicit Runge--Kutta
+ * method given by a Butcher tableau (eq. RKstep, Table Butchertab) whose matrix is
+ * split A = A^(h) + A^(eps) (Section "Method stability in the context of mixed
+ * precision").  Each implicit stage is the linear system
+ *     (I - tau a_ii K) y_i = rhs_i,   rhs_i = u_n + tau sum_{j<i} (a^h_ij k_j + a^eps_ij k^eps_j)
+ * (eq. corelinear, sign convention y = rhs + sigma K y), solved by a preconditioned
+ * Krylov method (CG for SPD heat systems, GMRES for advection) in LOW precision
+ * (FP32, or FP16 storage with FP32 arithmetic); the explicit evaluations k_i = K y_i,
+ * the stage right-hand sides, the step combination u_{n+1} = u_n + tau sum b_i k_i
+ * and an outer residual check stay in FP64 on the GPU (Section "Implementation of
+ * the Mixed-precision Runge--Kutta methods": explicit parts and stage vectors in
+ * double, implicit solves converted to float).  k^eps_j, the low-precision slope of
+ * an implicit stage j, is (y_j - rhs_j)/(tau a_jj).
+ *
+ * Conventions.
+ *   - All device pointers are HIP device addresses on the current device.  The
+ *     library never allocates device memory: the state u and one workspace blob
+ *     are caller-owned (e.g. torch tensors) and handed over with mprk_bind.
+ *   - Vectors are lexicographic, x fastest: x_{ijk} = x[i + nx j + nx ny k]
+ *     (the ordering stated with the tensor kernels T_L/T_M/T_R of the paper).
+ *   - Every call returns an int32 status: MPRK_OK (0) or a negative error code;
+ *     mprk_last_error() returns a thread-local message for the last failure.
+ *   - Work is enqueued on the hip stream given at creation.  One handle per
+ *     stream; a handle is not thread-safe.
+ */
+#ifndef MPRK_H
+#define MPRK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPRK_MAX_STAGES 8
+#define MPRK_MAX_RESTART 32
+
+enum mprk_status {
+  MPRK_OK = 0,
+  MPRK_EINVAL = -1,        /* invalid argument, shape or tableau */
+  MPRK_ENOMEM = -2,        /* host allocation failed or workspace too small */
+  MPRK_EDEVICE = -3,       /* a HIP runtime call failed */
+  MPRK_ENONFINITE = -4,    /* a residual became Inf/NaN; u is left at the last completed step */
+  MPRK_ENOTCONV = -5,      /* a stage missed outer_tol (only with precisions.strict != 0) */
+  MPRK_EUNSUPPORTED = -6,  /* valid but not implemented combination */
+  MPRK_ESTATE = -7         /* call out of order (e.g. step before bind) */
+};
+
+enum { MPRK_BC_DIRICHLET0 = 0, MPRK_BC_PERIODIC = 1 };
+enum { MPRK_OP_HEAT = 0, MPRK_OP_ADVDIFF = 1 };
+enum { MPRK_FMT_STENCIL = 0, MPRK_FMT_CSR = 1 };
+enum { MPRK_FP64 = 0, MPRK_FP32 = 1, MPRK_FP16 = 2 };
+enum { MPRK_CG = 0, MPRK_GMRES = 1 };
+enum { MPRK_PRECOND_NONE = 0, MPRK_PRECOND_BJ = 1 };
+enum { MPRK_TAB_SDIRK2 = 0, MPRK_TAB_SDIRK3 = 1, MPRK_TAB_MID = 2,
+       MPRK_TAB_4S3PA = 3, MPRK_TAB_4S3PB = 4, MPRK_TAB_4S3PC = 5 };
+enum { MPRK_APPLY_K64 = 0,     /* y = K x, FP64 in/out */
+       MPRK_APPLY_M_LP = 1,    /* y = (I - sigma_stage K) x in the LP storage type, compute type arithmetic */
+       MPRK_APPLY_BJ_LP = 2,   /* y = blockdiag(M)^{-1} x, LP storage type */
+       MPRK_APPLY_M64 = 3 };   /* y = (I - sigma_stage K) x, FP64 */
+
+/* Grid: nx*ny*nz unknowns on the unit cube.  bc = MPRK_BC_DIRICHLET0: zero
+ * Dirichlet, n interior nodes per axis, h = 1/(n+1).  bc = MPRK_BC_PERIODIC:
+ * h = 1/n.  (The paper's h = 1/(n-1) counts boundary nodes; Section "Heat equation".) */
+typedef struct { int32_t nx, ny, nz, bc; } mprk_grid;
+
+/* Operator K.  kind = MPRK_OP_HEAT: K = diff * Lap_h (7-point, second-order central;
+ * Section "Test cases").  kind = MPRK_OP_ADVDIFF: K = diff * Lap_h - sum_d b[d] D_d, D_d the
+ * first-order upwind difference (backward for b[d] >= 0, forward for b[d] < 0).
+ * format: MPRK_FMT_STENCIL (matrix-free) or MPRK_FMT_CSR (int32 row pointers and
+ * column indices; FP64 values for the explicit parts, LP values for the solve). */
+typedef struct { int32_t kind, format; double diff; double b[3]; } mprk_operator;
+
+/* Split Butcher tableau: s stages, s*s row-major lower-triangular a_hi (A^(h)) and a_lo
+ * (A^(eps)), weights b (high precision); c is not needed (autonomous f).  Stage i is
+ * implicit iff a_hi[i*s+i] + a_lo[i*s+i] != 0. */
+typedef struct {
+  int32_t s;
+  double a_hi[MPRK_MAX_STAGES * MPRK_MAX_STAGES];
+  double a_lo[MPRK_MAX_STAGES * MPRK_MAX_STAGES];
+  double b[MPRK_MAX_STAGES];
+} mprk_tableau;
+
+/* Solver precisions and parameters of the implicit stage solves.
+ *  storage: MPRK_FP64 | MPRK_FP32 | MPRK_FP16 -- storage of Krylov vectors, LP matrix values
+ *           and block-Jacobi inverses.  compute: MPRK_FP64 (only with FP64 storage) | MPRK_FP32.
+ *  krylov: MPRK_CG (SPD only) | MPRK_GMRES (right preconditioned, restart = cycle length m).
+ *  precond: MPRK_PRECOND_NONE | MPRK_PRECOND_BJ with block in {1,2,4,8}: consecutive blocks of
+ *           `block` rows in lexicographic order, inverses computed in FP64 per block.
+ *  rtol/atol/maxit: inner Krylov stop ||r|| <= max(rtol ||b||, atol) or maxit iterations per
+ *           outer pass (the paper stops on the absolute or the relative residual with at most 40
+ *           iterations; Section "Linear solvers and setup of the numerical experiments").
+ *  refine_max/outer_tol: the FP64 outer residual loop.  Each pass computes the FP64 residual
+ *           res = rhs - (I - sigma K) y, solves the scaled correction system in LP and adds it
+ *           to y.  The stage stops when ||res|| <= outer_tol ||rhs|| or after refine_max passes.
+ *           refine_max = 0 is the paper's one-shot mode: exactly one LP solve (for GMRES one
+ *           cycle) on the converted right-hand side, no residual check.
+ *  strict: make a stage that misses outer_tol an error (MPRK_ENOTCONV).
+ *  reorth: GMRES classical Gram-Schmidt with one re-orthogonalisation pass (CGS2). */
+typedef struct {
+  int32_t storage, compute;
+  int32_t krylov, restart;
+  int32_t precond, block;
+  double rtol, atol;
+  int32_t maxit;
+  int32_t refine_max;
+  double outer_tol;
+  int32_t strict;
+  int32_t reorth;
+} mprk_precisions;
+
+/* Statistics.  Per-stage entries describe the most recent step. */
+typedef struct {
+  int64_t steps;                    /* steps completed on this handle (see mprk_set_state) */
+  double t;                         /* simulated time */
+  int32_t stages;                   /* s */
+  int32_t iters[MPRK_MAX_STAGES];   /* Krylov iterations summed over the outer passes */
+  int32_t passes[MPRK_MAX_STAGES];  /* LP solves (outer passes) */
+  double resid[MPRK_MAX_STAGES];    /* final FP64 ||res|| / ||rhs|| */
+  int32_t converged[MPRK_MAX_STAGES]; /* 1 if resid <= outer_tol (or paper mode finished) */
+  int64_t total_iters;              /* cumulative over all steps */
+  int64_t total_passes;
+  int32_t nonfinite;                /* 1 if the last step hit a non-finite residual */
+} mprk_stats;
+
+typedef struct { int32_t iters, passes, converged; double resid; } mprk_solve_info;
+
+typedef struct mprk_handle mprk_handle;
+
+/* Builtin tableaus.  id = MPRK_TAB_SDIRK2 (Alexander, gamma = 1 - 1/sqrt 2), MPRK_TAB_SDIRK3
+ * (Alexander, L-stable order 3), MPRK_TAB_MID (implicit midpoint with `param` corrector steps,
+ * Figure fig_Aq_rat and Appendix A; param in [0, 7]), MPRK_TAB_4S3PA / 4S3PB / 4S3PC
+ * (Tables ButchertabA/B/C; 4s3pB with a42^(eps) = -3/2 - a42, the printed value breaking
+ * order 2).  The SDIRKs put the diagonal in A^(eps) and the rest in A^(h).
+ * Returns MPRK_EINVAL for an unknown id or param. */
+int32_t mprk_tableau_builtin(int32_t id, int32_t param, mprk_tableau *out);
+
+/* Fill *out with the library defaults for a storage precision and Krylov method. */
+int32_t mprk_precisions_default(int32_t storage, int32_t krylov, mprk_precisions *out);
+
+/* Validate the problem and create a handle (host memory only).  dt is the time step tau;
+ * hip_stream is a hipStream_t (NULL = the null stream).  Errors: MPRK_EINVAL (bad shape,
+ * non-lower-triangular tableau, FP16 values that would overflow, CG on a nonsymmetric
+ * operator, index range beyond int32 for CSR), MPRK_EUNSUPPORTED, MPRK_EDEVICE. */
+int32_t mprk_create(const mprk_grid *grid, const mprk_operator *op, const mprk_tableau *tab,
+                    const mprk_precisions *prec, double dt, void *hip_stream, mprk_handle **out);
+
+/* Exact number of bytes of device workspace the handle needs (<0 on error). */
+int64_t mprk_workspace_bytes(const mprk_handle *h);
+
+/* Attach caller-owned device memory and run the setup (CSR assembly, block-Jacobi
+ * inverses) on the handle's stream.  u_dev: N doubles, the state, updated in place by
+ * mprk_step.  workspace_dev: >= mprk_workspace_bytes bytes, 256-byte aligned.  The
+ * library keeps both pointers until mprk_destroy or the next bind; it never frees them.
+ * Synchronises the stream before returning.  Errors: MPRK_EINVAL, MPRK_ENOMEM (bytes too
+ * small), MPRK_EDEVICE. */
+int32_t mprk_bind(mprk_handle *h, double *u_dev, void *workspace_dev, int64_t bytes);
+
+/* Advance u by nsteps time steps.  The calling thread steers the Krylov loops by polling
+ * small device-side status records; all arithmetic runs in the library's kernels on the
+ * bound stream.  Returns when the last step's work is enqueued (the step combination may
+ * still be running).  If stats_or_null is given the call waits for the stream and fills it.
+ * Errors: MPRK_ESTATE (not bound), MPRK_ENONFINITE (u left at the last good step),
+ * MPRK_ENOTCONV (strict only), MPRK_EDEVICE. */
+int32_t mprk_step(mprk_handle *h, int32_t nsteps, mprk_stats *stats_or_null);
+
+/* Solve one stage system (I - dt a_ii K) x = rhs with the handle's implicit solver
+ * (LP Krylov inside the FP64 outer loop), stage in [0, s) with a_ii != 0.  rhs_dev, x_dev:
+ * N doubles each (may not alias u or the workspace).  Waits for completion; fills *info
+ * if given.  Errors: MPRK_EINVAL (explicit stage), MPRK_ESTATE, MPRK_ENONFINITE, MPRK_EDEVICE. */
+int32_t mprk_solve(mprk_handle *h, int32_t stage, const double *rhs_dev, double *x_dev,
+                   mprk_solve_info *info);
+
+/* Apply one component operator (kernel-level access for verification):
+ * MPRK_APPLY_K64 / MPRK_APPLY_M64: x, y are N doubles; MPRK_APPLY_M_LP / MPRK_APPLY_BJ_LP:
+ * x, y are N values of the LP storage type (FP16 = IEEE binary16).  `stage` selects
+ * sigma = dt a_ii (ignored for K64).  Enqueued on the stream; waits before returning. */
+int32_t mprk_apply(mprk_handle *h, int32_t op, int32_t stage, const void *x_dev, void *y_dev);
+
+/* Time and step counter (u itself lives in the bound buffer).  mprk_get_state waits for
+ * the stream.  mprk_set_state resets the counters, e.g. after the caller restores u from a
+ * checkpoint; it does not touch u. */
+int32_t mprk_get_state(const mprk_handle *h, double *t, int64_t *step);
+int32_t mprk_set_state(mprk_handle *h, double t, int64_t step);
+
+/* Wait for the stream and return the statistics of the most recent step. */
+int32_t mprk_stats_sync(mprk_handle *h, mprk_stats *out);
+
+/* Thread-local description of the last error ("" if none). */
+const char *mprk_last_error(void);
+
+/* Release host resources.  Caller-owned device memory is untouched. */
+void mprk_destroy(mprk_handle *h);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched form: many independent problems (own grid, operator coefficients and dt; shared
+ * tableau and precisions; stencil format; CG) advanced together.  Each stage is one
+ * persistent kernel launch in which every problem owns a group of workgroups with its own
+ * group barrier and reductions; a step is captured once as a hipGraph and replayed.
+ * --------------------------------------------------------------------------------------- */
+typedef struct { mprk_grid grid; mprk_operator op; double dt; } mprk_problem;
+typedef struct mprk_batch mprk_batch;
+
+/* Create a batch of `count` problems (count >= 1).  Errors as mprk_create; MPRK_EUNSUPPORTED
+ * for GMRES, CSR or FP16/FP32 compute combinations the batched kernel does not implement. */
+int32_t mprk_batch_create(int32_t count, const mprk_problem *problems, const mprk_tableau *tab,
+                          const mprk_precisions *prec, void *hip_stream, mprk_batch **out);
+int64_t mprk_batch_workspace_bytes(const mprk_batch *b);
+/* u_dev: array of `count` device pointers (problem p's state, N_p doubles each). */
+int32_t mprk_batch_bind(mprk_batch *b, double *const *u_dev, void *workspace_dev, int64_t bytes);
+/* Advance every problem by nsteps steps (graph replays); asynchronous on the stream. */
+int32_t mprk_batch_step(mprk_batch *b, int32_t nsteps);
+/* Wait and return problem idx's statistics of its most recent step. */
+int32_t mprk_batch_stats_sync(mprk_batch *b, int32_t idx, mprk_stats *out);
+void mprk_batch_destroy(mprk_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPRK_H */

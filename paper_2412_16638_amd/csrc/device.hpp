@@ -1,0 +1,357 @@
+// device.hpp -- shared device-side types and helpers of the gfx950 kernels.
+//
+// Layout and launch conventions used by every grid kernel:
+//   * vectors are lexicographic, x fastest (index i + nx j + nx ny k);
+//   * a thread owns "groups" of VEC consecutive x-values (VEC = 4 when nx % 4 == 0,
+//     else 1), so a group never straddles an x-row;
+//   * a block owns a contiguous range of nit*TPB groups; the block index is remapped so
+//     that the 8 XCDs (each with its own L2) each own one contiguous eighth of the grid
+//     (hardware dispatch sends block b to XCD b % 8), which keeps stencil halo planes of
+//     neighbouring blocks in the same L2;
+//   * reductions are deterministic: per-thread partial -> wave64 shuffle tree -> fixed-order
+//     block sum -> per-block partials -> the last block to finish (atomic ticket) adds the
+//     partials in block order in FP64 and computes the dependent scalars.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mprk {
+
+typedef _Float16 half_t;
+
+constexpr int TPB = 256;             // threads per block of every grid kernel
+constexpr int NWAVE = TPB / 64;
+constexpr int MAXM = 32;             // max GMRES cycle length
+constexpr int MAXD = MAXM + 1;       // max simultaneous dot products
+constexpr int MAXS = 8;              // max RK stages
+constexpr int BJ_MAX = 8;            // max block-Jacobi block size
+
+struct Geo {
+  int nx, ny, nz, bc;  // bc: 0 zero Dirichlet, 1 periodic
+  int N, plane;        // nx*ny*nz, nx*ny
+};
+
+struct Launch {
+  int ng;   // number of groups (N / VEC, or rows for CSR kernels)
+  int nit;  // groups per thread
+  int G;    // blocks (a multiple of 8)
+};
+
+// 7-point stencil coefficients: w = c v + xm v[x-1] + xp v[x+1] + ym v[y-1] + ...
+template <typename C>
+struct Coef {
+  C c, xm, xp, ym, yp, zm, zp;
+};
+
+struct Csr {
+  const int* rowptr;
+  const int* col;
+};
+
+// Device control record of one solve context (one per problem).  The first 64 bytes
+// are the head the host polls.
+struct Ctl {
+  // ---- head polled by the host (64 bytes) ----
+  int outer_done;     // stage finished (converged, pass limit, or non-finite)
+  int inner_done;     // current LP solve finished
+  int passes;         // LP solves completed in this stage
+  int iters;          // Krylov iterations of the current LP solve
+  int total_iters;    // Krylov iterations of this stage (all passes)
+  int nonfinite;      // a non-finite FP64 residual was seen in this stage
+  int converged;      // outer residual reached outer_tol
+  int J;              // GMRES: Arnoldi vectors in the current cycle
+  double outer_rel;   // ||res|| / ||rhs|| of the last FP64 residual
+  double res_norm;    // ||res||_2
+  long long good_steps;  // steps whose combination was applied
+  int bad_steps;         // steps skipped because of a non-finite residual
+  int step_nonfinite;    // sticky for the current step (gates the combination)
+  // ---- body ----
+  long long life_iters;   // Krylov iterations since bind
+  long long life_passes;  // LP solves since bind
+  double rhs_norm;    // ||rhs||_2
+  double scale;       // LP right-hand side = res / scale (scale = ||res||_2 / sqrt(N))
+  double tol;         // inner stopping tolerance in LP units
+  double rz, pq, alpha, beta, rr;
+  double hcol[MAXD];                 // current Hessenberg column
+  double H[(MAXM + 1) * MAXM];       // Hessenberg matrix, column-major (MAXM+1 rows)
+  double cs[MAXM], sn[MAXM];         // Givens rotations
+  double g[MAXM + 1];                // rotated right-hand side
+  double ysol[MAXM];                 // least-squares solution of the cycle
+  double vscale[MAXM + 1];           // basis vector i = vscale[i] * stored vector i
+  unsigned int ticket;               // last-block counter (self-resetting)
+};
+
+// The host polls this prefix of Ctl.
+struct CtlHead {
+  int outer_done, inner_done, passes, iters, total_iters, nonfinite, converged, J;
+  double outer_rel, res_norm;
+  long long good_steps;
+  int bad_steps, step_nonfinite;
+};
+static_assert(sizeof(CtlHead) == 64, "poll head must be 64 bytes");
+
+struct SolveCfg {
+  double sigma;        // tau a_ii
+  double outer_tol;
+  int max_passes;      // LP solves per stage (>= 1)
+  int paper_mode;      // refine_max == 0
+  double rtol, atol;
+  int maxit;           // Krylov iterations per LP solve
+  int m;               // GMRES cycle length
+  double sqrtN;
+  double invN;
+};
+
+template <typename T, int V>
+struct alignas(sizeof(T) * V) Vec {
+  T v[V];
+};
+
+template <typename C, typename S, int V>
+__device__ __forceinline__ void loadv(const S* __restrict__ p, C (&o)[V]) {
+  Vec<S, V> t = *reinterpret_cast<const Vec<S, V>*>(p);
+#pragma unroll
+  for (int i = 0; i < V; ++i) o[i] = (C)t.v[i];
+}
+
+template <typename S, typename C, int V>
+__device__ __forceinline__ void storev(S* __restrict__ p, const C (&o)[V]) {
+  Vec<S, V> t;
+#pragma unroll
+  for (int i = 0; i < V; ++i) t.v[i] = (S)o[i];
+  *reinterpret_cast<Vec<S, V>*>(p) = t;
+}
+
+// round a compute value through the storage type (what a store + reload would give)
+template <typename S, typename C>
+__device__ __forceinline__ C rnd(C x) {
+  return (C)(S)x;
+}
+
+__device__ __forceinline__ int xcd_block(int G) {
+  const int b = blockIdx.x;
+  return (b & 7) * (G >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Block-level fixed-order reduction of nd (<= ND) per-thread values into partials[d*pstride + L];
+// returns true in the last block, where tot[0..nd) (shared memory) then holds the grand totals.
+template <int ND>
+__device__ bool reduce_to_last(const double (&v)[ND], int nd, double* __restrict__ partials,
+                               int pstride, unsigned int* ticket, int L, int G, double* tot) {
+  __shared__ double wsum[NWAVE][ND];
+  __shared__ bool am_last;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    if (d < nd) {
+      double s = wave_sum(v[d]);
+      if (lane == 0) wsum[wave][d] = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nd) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) s += wsum[w][threadIdx.x];
+    // agent-scope store: visible to the last block whichever XCD (L2) it runs on
+    __hip_atomic_store(partials + threadIdx.x * pstride + L, s, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int t = atomicAdd(ticket, 1u);
+    am_last = (t == (unsigned int)(G - 1));
+  }
+  __syncthreads();
+  if (!am_last) return false;
+  __threadfence();
+  // fixed-order total: 8 lanes per value, strided over blocks, then an ordered combine
+  __shared__ double part8[ND][8];
+  for (int task = threadIdx.x; task < nd * 8; task += TPB) {
+    const int d = task >> 3, r = task & 7;
+    const double* p = partials + d * pstride;
+    double s = 0.0;
+    for (int b = r; b < G; b += 8)
+      s += __hip_atomic_load(p + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    part8[d][r] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < nd) {
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) s += part8[threadIdx.x][r];
+    tot[threadIdx.x] = s;
+  }
+  if (threadIdx.x == 0) *ticket = 0u;
+  __syncthreads();
+  return true;
+}
+
+// Neighbour indices of the group starting at element e (x0 = e % nx, ...); -1 = outside
+// a zero-Dirichlet boundary.
+struct Nbr {
+  int xm, xp, ym, yp, zm, zp;
+};
+
+template <int VEC>
+__device__ __forceinline__ Nbr neighbours(const Geo& g, int e) {
+  const int x0 = e % g.nx;
+  const int t = e / g.nx;
+  const int y = t % g.ny;
+  const int z = t / g.ny;
+  const bool per = g.bc == 1;
+  Nbr n;
+  n.xm = x0 > 0 ? e - 1 : (per ? e + g.nx - 1 : -1);
+  n.xp = x0 + VEC < g.nx ? e + VEC : (per ? e + VEC - g.nx : -1);
+  n.ym = y > 0 ? e - g.nx : (per ? e + (g.ny - 1) * g.nx : -1);
+  n.yp = y < g.ny - 1 ? e + g.nx : (per ? e - (g.ny - 1) * g.nx : -1);
+  n.zm = z > 0 ? e - g.plane : (per ? e + (g.nz - 1) * g.plane : -1);
+  n.zp = z < g.nz - 1 ? e + g.plane : (per ? e - (g.nz - 1) * g.plane : -1);
+  return n;
+}
+
+// Apply a 7-point stencil to the group at e.  `F` supplies input values:
+//   F::vec(idx, C (&)[VEC]) -- VEC consecutive values starting at idx (aligned group)
+//   F::one(idx) -> C        -- one value
+template <typename C, int VEC, typename F>
+__device__ __forceinline__ void stencil_group(const Geo& g, const Coef<C>& k, int e, const F& f,
+                                              C (&ctr)[VEC], C (&out)[VEC]) {
+  const Nbr n = neighbours<VEC>(g, e);
+  f.vec(e, ctr);
+  C l = n.xm >= 0 ? f.one(n.xm) : C(0);
+  C r = n.xp >= 0 ? f.one(n.xp) : C(0);
+  C ym[VEC], yp[VEC], zm[VEC], zp[VEC];
+  if (n.ym >= 0) f.vec(n.ym, ym); else {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) ym[v] = C(0);
+  }
+  if (n.yp >= 0) f.vec(n.yp, yp); else {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) yp[v] = C(0);
+  }
+  if (n.zm >= 0) f.vec(n.zm, zm); else {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) zm[v] = C(0);
+  }
+  if (n.zp >= 0) f.vec(n.zp, zp); else {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) zp[v] = C(0);
+  }
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    const C left = v > 0 ? ctr[v - 1] : l;
+    const C right = v < VEC - 1 ? ctr[v + 1] : r;
+    C acc = k.c * ctr[v];
+    acc += k.xm * left;
+    acc += k.xp * right;
+    acc += k.ym * ym[v];
+    acc += k.yp * yp[v];
+    acc += k.zm * zm[v];
+    acc += k.zp * zp[v];
+    out[v] = acc;
+  }
+}
+
+// Input functor: plain array in storage type S, converted to C.
+template <typename C, typename S, int VEC>
+struct In1 {
+  const S* __restrict__ a;
+  __device__ __forceinline__ void vec(int i, C (&o)[VEC]) const { loadv<C, S, VEC>(a + i, o); }
+  __device__ __forceinline__ C one(int i) const { return (C)a[i]; }
+};
+
+// Input functor: a + beta * b (CG search direction), with rounding through S so that every
+// reader sees exactly the values the owner stores.
+template <typename C, typename S, int VEC>
+struct InAxpy {
+  const S* __restrict__ a;
+  const S* __restrict__ b;
+  C beta;
+  int use_b;
+  __device__ __forceinline__ void vec(int i, C (&o)[VEC]) const {
+    loadv<C, S, VEC>(a + i, o);
+    if (use_b) {
+      C t[VEC];
+      loadv<C, S, VEC>(b + i, t);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) o[v] = rnd<S, C>(o[v] + beta * t[v]);
+    }
+  }
+  __device__ __forceinline__ C one(int i) const {
+    C o = (C)a[i];
+    if (use_b) o = rnd<S, C>(o + beta * (C)b[i]);
+    return o;
+  }
+};
+
+// Input functor: s * a (a scaled stored vector)
+template <typename C, typename S, int VEC>
+struct InScaled {
+  const S* __restrict__ a;
+  C s;
+  __device__ __forceinline__ void vec(int i, C (&o)[VEC]) const {
+    loadv<C, S, VEC>(a + i, o);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) o[v] *= s;
+  }
+  __device__ __forceinline__ C one(int i) const { return s * (C)a[i]; }
+};
+
+// CSR row product sum_k val[k] * x[col[k]] with x provided by functor F (scalar access).
+template <typename C, typename SV, typename F>
+__device__ __forceinline__ C csr_row(const Csr& m, const SV* __restrict__ val, int row, const F& f) {
+  const int b = m.rowptr[row], e = m.rowptr[row + 1];
+  C acc = C(0);
+  for (int k = b; k < e; ++k) acc += (C)val[k] * f.one(m.col[k]);
+  return acc;
+}
+
+// Block-Jacobi: z = D^{-1} r for the VEC rows of this lane.  Inverse rows are stored
+// contiguously: row i's BS entries at dinv[i*BS].  Blocks of BS rows; when BS > VEC a block
+// spans BS/VEC consecutive lanes whose values are exchanged by shuffles (every lane of the
+// wave must call this).
+template <typename C, typename S, int VEC, int BS>
+__device__ __forceinline__ void bj_apply_lane(const S* __restrict__ dinv, int e, bool valid,
+                                              const C (&r)[VEC], C (&z)[VEC]) {
+  if constexpr (BS <= VEC) {
+#pragma unroll
+    for (int sb = 0; sb < VEC / BS; ++sb) {
+#pragma unroll
+      for (int i = 0; i < BS; ++i) {
+        C row[BS];
+        if (valid) loadv<C, S, BS>(dinv + (size_t)(e + sb * BS + i) * BS, row);
+        C acc = C(0);
+#pragma unroll
+        for (int k = 0; k < BS; ++k) acc += row[k] * r[sb * BS + k];
+        z[sb * BS + i] = valid ? acc : C(0);
+      }
+    }
+  } else {
+    constexpr int LPB = BS / VEC;  // lanes per block
+    const int lane = threadIdx.x & 63;
+    const int base = lane & ~(LPB - 1);
+    C rb[BS];
+#pragma unroll
+    for (int k = 0; k < BS; ++k) rb[k] = __shfl(r[k % VEC], base + k / VEC);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      C row[BS];
+      if (valid) loadv<C, S, BS>(dinv + (size_t)(e + i) * BS, row);
+      C acc = C(0);
+#pragma unroll
+      for (int k = 0; k < BS; ++k) acc += row[k] * rb[k];
+      z[i] = valid ? acc : C(0);
+    }
+  }
+}
+
+}  // namespace mprk

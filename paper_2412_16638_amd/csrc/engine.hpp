@@ -1,0 +1,253 @@
+// engine.hpp -- host-side launchers of the LP (low-precision) solve kernels, one instance per
+// (storage type S, compute type C): (double, double), (float, float), (half, float).
+// Each instance lives in its own translation unit so the three precisions compile in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace mprk {
+
+// What the engine needs to know about the problem and the workspace.
+struct EngineCtx {
+  hipStream_t stream;
+  Geo geo;
+  int fmt;            // 0 stencil, 1 CSR
+  int vec;            // 4 or 1 (vector kernels)
+  Launch ln_vec;      // groups of `vec` elements
+  Launch ln_row;      // CSR rows (VEC = 1)
+  Launch ln_mv;       // launch of the SpMV kernels (= ln_vec for stencil, ln_row for CSR)
+  int bs;             // block-Jacobi block size (0 = no preconditioner)
+  Csr csr;
+  const void* mval;   // LP CSR values of K / kscale (S)
+  double kscale;
+  Ctl* ctl;
+  double* partials;
+  int pstride;
+  // LP vectors (S*)
+  void *r, *z, *p0, *p1, *q, *x;
+  void* V;
+  size_t vstride;     // elements between GMRES basis vectors
+  double* res;        // FP64 residual
+  double* y;          // FP64 stage solution
+};
+
+class Engine {
+ public:
+  virtual ~Engine() {}
+  // setup
+  virtual hipError_t bj_setup_stencil(const EngineCtx& c, const Coef<double>& Mc, void* dinv, int* fail) = 0;
+  virtual hipError_t bj_setup_csr(const EngineCtx& c, const double* kval, double sigma, void* dinv, int* fail) = 0;
+  virtual hipError_t csr_values(const EngineCtx& c, long nnz, const double* kval, void* out) = 0;
+  // CG
+  virtual hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) = 0;
+  virtual hipError_t cg_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
+                             const void* dinv, int it) = 0;
+  virtual hipError_t cg_finish(const EngineCtx& c) = 0;
+  // GMRES
+  virtual hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg) = 0;
+  virtual hipError_t gm_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
+                             const void* dinv) = 0;
+  virtual hipError_t gm_finish(const EngineCtx& c, const void* dinv) = 0;
+  // verification access
+  virtual hipError_t apply_m(const EngineCtx& c, const Coef<double>& Mc, double sigma,
+                             const void* x, void* y) = 0;
+  virtual hipError_t apply_bj(const EngineCtx& c, const void* dinv, const void* x, void* y) = 0;
+  virtual int elem_bytes() const = 0;
+};
+
+Engine* make_engine_fp64();
+Engine* make_engine_fp32();
+Engine* make_engine_fp16();
+
+template <typename C>
+inline Coef<C> cast_coef(const Coef<double>& a) {
+  return Coef<C>{(C)a.c, (C)a.xm, (C)a.xp, (C)a.ym, (C)a.yp, (C)a.zm, (C)a.zp};
+}
+
+#define MPRK_LAUNCH(kern, ln, stream, ...)                                              \
+  do {                                                                                   \
+    hipLaunchKernelGGL((kern), dim3((ln).G), dim3(TPB), 0, (stream), __VA_ARGS__);        \
+  } while (0)
+
+template <typename S, typename C>
+class EngineT final : public Engine {
+ public:
+  int elem_bytes() const override { return (int)sizeof(S); }
+
+  hipError_t bj_setup_stencil(const EngineCtx& c, const Coef<double>& Mc, void* dinv, int* fail) override {
+    const int nblk = (c.geo.N + c.bs - 1) / c.bs;
+    hipLaunchKernelGGL(k_bj_setup_stencil<S>, dim3((nblk + 127) / 128), dim3(128), 0, c.stream,
+                       nblk, c.bs, c.geo, Mc, (S*)dinv, fail);
+    return hipGetLastError();
+  }
+  hipError_t bj_setup_csr(const EngineCtx& c, const double* kval, double sigma, void* dinv, int* fail) override {
+    const int nblk = (c.geo.N + c.bs - 1) / c.bs;
+    hipLaunchKernelGGL(k_bj_setup_csr<S>, dim3((nblk + 127) / 128), dim3(128), 0, c.stream, nblk,
+                       c.bs, c.geo.N, c.csr, kval, sigma, (S*)dinv, fail);
+    return hipGetLastError();
+  }
+  hipError_t csr_values(const EngineCtx& c, long nnz, const double* kval, void* out) override {
+    const long nb = (nnz + 255) / 256;
+    hipLaunchKernelGGL(k_csr_lp_values<S>, dim3((unsigned)nb), dim3(256), 0, c.stream, nnz, kval,
+                       1.0 / c.kscale, (S*)out);
+    return hipGetLastError();
+  }
+
+  // ---------------- CG ----------------
+  template <int VEC, int BS>
+  void cg_begin_t(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) {
+    S* z = BS > 0 ? (S*)c.z : (S*)c.r;
+    MPRK_LAUNCH((k_cg_begin<S, C, VEC, BS>), c.ln_vec, c.stream, c.ln_vec, c.res, (S*)c.r, z,
+                (const S*)dinv, cfg, c.ctl, c.partials, c.pstride);
+  }
+  hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) override {
+    dispatch_vec_bs(c, [&](auto vec, auto bs) { cg_begin_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
+    return hipGetLastError();
+  }
+
+  template <int VEC, int FMT>
+  void cg_dir_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc, const S* z,
+                const S* pold, S* pnew) {
+    const Coef<C> M = cast_coef<C>(Mc);
+    const C msig = (C)(cfg.sigma * c.kscale);
+    MPRK_LAUNCH((k_cg_dir<S, C, VEC, FMT>), c.ln_mv, c.stream, c.ln_mv, c.geo, M, c.csr,
+                (const S*)c.mval, msig, z, pold, pnew, (S*)c.q, c.ctl, c.partials, c.pstride);
+  }
+  template <int VEC, int BS>
+  void cg_upd_t(const EngineCtx& c, const SolveCfg& cfg, const S* p, const void* dinv) {
+    S* z = BS > 0 ? (S*)c.z : (S*)c.r;
+    MPRK_LAUNCH((k_cg_upd<S, C, VEC, BS>), c.ln_vec, c.stream, c.ln_vec, (S*)c.x, p, (S*)c.r,
+                (const S*)c.q, z, (const S*)dinv, cfg, c.ctl, c.partials, c.pstride);
+  }
+  hipError_t cg_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
+                     const void* dinv, int it) override {
+    const S* z = c.bs > 0 ? (const S*)c.z : (const S*)c.r;
+    const S* pold = (it & 1) ? (const S*)c.p1 : (const S*)c.p0;
+    S* pnew = (it & 1) ? (S*)c.p0 : (S*)c.p1;
+    if (c.fmt == 1) cg_dir_t<1, 1>(c, cfg, Mc, z, pold, pnew);
+    else if (c.vec == 4) cg_dir_t<4, 0>(c, cfg, Mc, z, pold, pnew);
+    else cg_dir_t<1, 0>(c, cfg, Mc, z, pold, pnew);
+    dispatch_vec_bs(c, [&](auto vec, auto bs) {
+      cg_upd_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, pnew, dinv);
+    });
+    return hipGetLastError();
+  }
+  hipError_t cg_finish(const EngineCtx& c) override {
+    if (c.vec == 4)
+      MPRK_LAUNCH((k_promote<S, C, 4>), c.ln_vec, c.stream, c.ln_vec, c.y, (const S*)c.x, c.ctl);
+    else
+      MPRK_LAUNCH((k_promote<S, C, 1>), c.ln_vec, c.stream, c.ln_vec, c.y, (const S*)c.x, c.ctl);
+    return hipGetLastError();
+  }
+
+  // ---------------- GMRES ----------------
+  hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg) override {
+    if (c.vec == 4)
+      MPRK_LAUNCH((k_gm_begin<S, C, 4>), c.ln_vec, c.stream, c.ln_vec, c.res, (S*)c.V, cfg, c.ctl,
+                  c.partials, c.pstride);
+    else
+      MPRK_LAUNCH((k_gm_begin<S, C, 1>), c.ln_vec, c.stream, c.ln_vec, c.res, (S*)c.V, cfg, c.ctl,
+                  c.partials, c.pstride);
+    return hipGetLastError();
+  }
+  template <int VEC, int FMT, int PREC>
+  void gm_matvec_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc) {
+    const Coef<C> M = cast_coef<C>(Mc);
+    const C msig = (C)(cfg.sigma * c.kscale);
+    MPRK_LAUNCH((k_gm_matvec<S, C, VEC, FMT, PREC>), c.ln_mv, c.stream, c.ln_mv, c.geo, M, c.csr,
+                (const S*)c.mval, msig, (const S*)c.z, (S*)c.V, c.vstride, cfg, c.ctl, c.partials,
+                c.pstride);
+  }
+  template <int VEC, int BS>
+  void gm_prec_t(const EngineCtx& c, const void* dinv) {
+    if constexpr (BS > 0)
+      MPRK_LAUNCH((k_gm_prec<S, C, VEC, BS>), c.ln_vec, c.stream, c.ln_vec, (const S*)c.V,
+                  c.vstride, (S*)c.z, (const S*)dinv, c.ctl);
+  }
+  hipError_t gm_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
+                     const void* dinv) override {
+    if (c.bs > 0)
+      dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_prec_t<decltype(vec)::value, decltype(bs)::value>(c, dinv); });
+    const bool prec = c.bs > 0;
+    if (c.fmt == 1) {
+      if (prec) gm_matvec_t<1, 1, 1>(c, cfg, Mc); else gm_matvec_t<1, 1, 0>(c, cfg, Mc);
+    } else if (c.vec == 4) {
+      if (prec) gm_matvec_t<4, 0, 1>(c, cfg, Mc); else gm_matvec_t<4, 0, 0>(c, cfg, Mc);
+    } else {
+      if (prec) gm_matvec_t<1, 0, 1>(c, cfg, Mc); else gm_matvec_t<1, 0, 0>(c, cfg, Mc);
+    }
+    if (c.vec == 4)
+      MPRK_LAUNCH((k_gm_orth<S, C, 4>), c.ln_vec, c.stream, c.ln_vec, (S*)c.V, c.vstride, cfg,
+                  c.ctl, c.partials, c.pstride);
+    else
+      MPRK_LAUNCH((k_gm_orth<S, C, 1>), c.ln_vec, c.stream, c.ln_vec, (S*)c.V, c.vstride, cfg,
+                  c.ctl, c.partials, c.pstride);
+    return hipGetLastError();
+  }
+  template <int VEC, int BS>
+  void gm_finish_t(const EngineCtx& c, const void* dinv) {
+    MPRK_LAUNCH((k_gm_finish<S, C, VEC, BS>), c.ln_vec, c.stream, c.ln_vec, c.y, (const S*)c.V,
+                c.vstride, (const S*)dinv, c.ctl);
+  }
+  hipError_t gm_finish(const EngineCtx& c, const void* dinv) override {
+    dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_finish_t<decltype(vec)::value, decltype(bs)::value>(c, dinv); });
+    return hipGetLastError();
+  }
+
+  // ---------------- verification ----------------
+  template <int VEC, int FMT>
+  void apply_m_t(const EngineCtx& c, const Coef<double>& Mc, double sigma, const void* x, void* y) {
+    const Coef<C> M = cast_coef<C>(Mc);
+    const C msig = (C)(sigma * c.kscale);
+    MPRK_LAUNCH((k_apply_lp<S, C, VEC, FMT>), c.ln_mv, c.stream, c.ln_mv, c.geo, M, c.csr,
+                (const S*)c.mval, msig, (const S*)x, (S*)y);
+  }
+  hipError_t apply_m(const EngineCtx& c, const Coef<double>& Mc, double sigma, const void* x,
+                     void* y) override {
+    if (c.fmt == 1) apply_m_t<1, 1>(c, Mc, sigma, x, y);
+    else if (c.vec == 4) apply_m_t<4, 0>(c, Mc, sigma, x, y);
+    else apply_m_t<1, 0>(c, Mc, sigma, x, y);
+    return hipGetLastError();
+  }
+  template <int VEC, int BS>
+  void apply_bj_t(const EngineCtx& c, const void* dinv, const void* x, void* y) {
+    if constexpr (BS > 0)
+      MPRK_LAUNCH((k_bj_apply<S, C, VEC, BS>), c.ln_vec, c.stream, c.ln_vec, (const S*)x, (S*)y,
+                  (const S*)dinv);
+  }
+  hipError_t apply_bj(const EngineCtx& c, const void* dinv, const void* x, void* y) override {
+    if (c.bs == 0) return hipErrorInvalidValue;
+    dispatch_vec_bs(c, [&](auto vec, auto bs) { apply_bj_t<decltype(vec)::value, decltype(bs)::value>(c, dinv, x, y); });
+    return hipGetLastError();
+  }
+
+ private:
+  template <int V>
+  struct IC {
+    static constexpr int value = V;
+  };
+  template <typename F>
+  static void dispatch_vec_bs(const EngineCtx& c, F&& f) {
+    if (c.vec == 4) {
+      switch (c.bs) {
+        case 0: f(IC<4>{}, IC<0>{}); break;
+        case 1: f(IC<4>{}, IC<1>{}); break;
+        case 2: f(IC<4>{}, IC<2>{}); break;
+        case 4: f(IC<4>{}, IC<4>{}); break;
+        default: f(IC<4>{}, IC<8>{}); break;
+      }
+    } else {
+      switch (c.bs) {
+        case 0: f(IC<1>{}, IC<0>{}); break;
+        case 1: f(IC<1>{}, IC<1>{}); break;
+        case 2: f(IC<1>{}, IC<2>{}); break;
+        case 4: f(IC<1>{}, IC<4>{}); break;
+        default: f(IC<1>{}, IC<8>{}); break;
+      }
+    }
+  }
+};
+
+}  // namespace mprk

@@ -1,0 +1,832 @@
+// kernels.hpp -- the gfx950 kernels of one time step.
+//
+// Per implicit stage i (sigma = tau a_ii), following the paper's split of explicit FP64
+// work and implicit low-precision (LP) solves (Section "Implementation of the
+// Mixed-precision Runge--Kutta methods"):
+//   k_stage_rhs  (FP64)  rhs = u + tau sum_{j<i}(a^h_ij k_j + a^eps_ij k^eps_j); y = rhs
+//   k_residual   (FP64)  k = K y ; res = rhs - y + sigma k ; ||res||, ||rhs|| ; outer decision
+//   k_cg_begin / k_gm_begin   res -> LP, scaled to unit RMS (FP16 range; Section "Method
+//                        stability in the context of mixed precision" on rescaling)
+//   k_cg_dir, k_cg_upd   fused preconditioned CG iteration (heat, SPD)
+//   k_gm_prec, k_gm_matvec, k_gm_orth   one right-preconditioned GMRES Arnoldi step
+//   k_promote / k_gm_finish   y += scale * delta (LP -> FP64)
+//   ... k_residual again; the stage ends when ||res|| <= outer_tol ||rhs||.
+//   k_keps       (FP64)  k^eps_i = (y - rhs) / sigma (only for tableaus with eps off-diagonals)
+// and per step k_combine (FP64) u += tau sum_i b_i k_i.
+// All kernels of a solve read the device control record first and return at once when the
+// phase they belong to has finished, so the host may enqueue ahead of the convergence test.
+#pragma once
+
+#include "device.hpp"
+
+namespace mprk {
+
+struct CombArgs {
+  const double* v[2 * MAXS];
+  double c[2 * MAXS];
+  int nv;
+};
+
+// ------------------------------------------------------------------------------------------
+// FP64 explicit parts
+// ------------------------------------------------------------------------------------------
+
+// rhs = u + sum_j c_j v_j ; y = rhs.  reset: 1 = new stage, 2 = new step (also clears the
+// step's non-finite flag).
+template <int VEC>
+__global__ __launch_bounds__(TPB) void k_stage_rhs(Launch ln, const double* __restrict__ u,
+                                                   CombArgs a, double* __restrict__ rhs,
+                                                   double* __restrict__ y, Ctl* ctl, int reset) {
+  if (reset && blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->outer_done = 0;
+    ctl->inner_done = 0;
+    ctl->passes = 0;
+    ctl->iters = 0;
+    ctl->total_iters = 0;
+    ctl->nonfinite = 0;
+    ctl->converged = 0;
+    ctl->J = 0;
+    ctl->outer_rel = 0.0;
+    ctl->res_norm = 0.0;
+    ctl->rhs_norm = 0.0;
+    if (reset == 2) ctl->step_nonfinite = 0;
+  }
+  const int L = xcd_block(ln.G);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    const int e = g * VEC;
+    double acc[VEC];
+    loadv<double, double, VEC>(u + e, acc);
+    for (int j = 0; j < a.nv; ++j) {
+      double t[VEC];
+      loadv<double, double, VEC>(a.v[j] + e, t);
+      const double c = a.c[j];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] += c * t[v];
+    }
+    storev<double, double, VEC>(rhs + e, acc);
+    storev<double, double, VEC>(y + e, acc);
+  }
+}
+
+// FMT 0: matrix-free stencil (VEC values per thread); FMT 1: CSR (one row per group, VEC = 1)
+template <int VEC, int FMT>
+__device__ __forceinline__ void k64_group(const Geo& geo, const Coef<double>& K, const Csr& csr,
+                                          const double* __restrict__ kval,
+                                          const double* __restrict__ y, int g,
+                                          double (&yc)[VEC], double (&ky)[VEC]) {
+  if constexpr (FMT == 0) {
+    In1<double, double, VEC> f{y};
+    stencil_group<double, VEC>(geo, K, g * VEC, f, yc, ky);
+  } else {
+    static_assert(VEC == 1, "CSR kernels use one row per group");
+    In1<double, double, 1> f{y};
+    yc[0] = y[g];
+    ky[0] = csr_row<double, double>(csr, kval, g, f);
+  }
+}
+
+// A2: k = K y ; res = rhs - y + sigma k ; ||res||^2, ||rhs||^2, non-finite count.
+// The last block decides whether the stage is finished (outer residual loop).
+template <int VEC, int FMT>
+__global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<double> K, Csr csr,
+                                                  const double* __restrict__ kval,
+                                                  const double* __restrict__ y,
+                                                  const double* __restrict__ rhs,
+                                                  double* __restrict__ kout,
+                                                  double* __restrict__ res, SolveCfg cfg, Ctl* ctl,
+                                                  double* partials, int pstride) {
+  if (ctl->outer_done) return;
+  const int L = xcd_block(ln.G);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    const int e = g * VEC;
+    double yc[VEC], ky[VEC], b[VEC], rr[VEC];
+    k64_group<VEC, FMT>(geo, K, csr, kval, y, g, yc, ky);
+    loadv<double, double, VEC>(rhs + e, b);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      rr[v] = b[v] - yc[v] + cfg.sigma * ky[v];
+      acc[0] += rr[v] * rr[v];
+      acc[1] += b[v] * b[v];
+      acc[2] += (__builtin_isfinite(rr[v]) && __builtin_isfinite(ky[v])) ? 0.0 : 1.0;
+    }
+    storev<double, double, VEC>(kout + e, ky);
+    storev<double, double, VEC>(res + e, rr);
+  }
+  __shared__ double tot[3];
+  if (!reduce_to_last<3>(acc, 3, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (threadIdx.x == 0) {
+    const double rn = sqrt(tot[0]), bn = sqrt(tot[1]);
+    const double rel = bn > 0.0 ? rn / bn : rn;
+    ctl->res_norm = rn;
+    ctl->rhs_norm = bn;
+    ctl->outer_rel = rel;
+    int done = 0;
+    if (tot[2] != 0.0 || !__builtin_isfinite(rn) || !__builtin_isfinite(bn)) {
+      ctl->nonfinite = 1;
+      ctl->step_nonfinite = 1;
+      done = 1;
+    } else {
+      ctl->converged = rel <= cfg.outer_tol;
+      if (cfg.paper_mode) {
+        done = ctl->passes >= 1;
+        ctl->converged = done;
+      } else {
+        done = ctl->converged || ctl->passes >= cfg.max_passes || rn == 0.0;
+      }
+    }
+    ctl->scale = rn > 0.0 ? rn / cfg.sqrtN : 1.0;
+    ctl->outer_done = done;
+  }
+}
+
+// y = K x (mode 0) or y = x - sigma K x (mode 1), FP64, no reduction (verification access).
+template <int VEC, int FMT>
+__global__ __launch_bounds__(TPB) void k_apply64(Launch ln, Geo geo, Coef<double> K, Csr csr,
+                                                 const double* __restrict__ kval,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ y, double sigma, int mode) {
+  const int L = xcd_block(ln.G);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    double xc[VEC], kx[VEC];
+    k64_group<VEC, FMT>(geo, K, csr, kval, x, g, xc, kx);
+    if (mode == 1) {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) kx[v] = xc[v] - sigma * kx[v];
+    }
+    storev<double, double, VEC>(y + g * VEC, kx);
+  }
+}
+
+// k^eps = (y - rhs) / sigma : the low-precision slope of an implicit stage.
+template <int VEC>
+__global__ __launch_bounds__(TPB) void k_keps(Launch ln, const double* __restrict__ y,
+                                              const double* __restrict__ rhs, double inv_sigma,
+                                              double* __restrict__ keps) {
+  const int L = xcd_block(ln.G);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    double a[VEC], b[VEC];
+    loadv<double, double, VEC>(y + g * VEC, a);
+    loadv<double, double, VEC>(rhs + g * VEC, b);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) a[v] = (a[v] - b[v]) * inv_sigma;
+    storev<double, double, VEC>(keps + g * VEC, a);
+  }
+}
+
+// u += sum_j c_j v_j (step combination), skipped when the step hit a non-finite residual.
+template <int VEC>
+__global__ __launch_bounds__(TPB) void k_combine(Launch ln, double* __restrict__ u, CombArgs a,
+                                                 Ctl* ctl) {
+  const int bad = ctl->step_nonfinite;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bad) ctl->bad_steps += 1;
+    else ctl->good_steps += 1;
+  }
+  if (bad) return;
+  const int L = xcd_block(ln.G);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    const int e = g * VEC;
+    double acc[VEC];
+    loadv<double, double, VEC>(u + e, acc);
+    for (int j = 0; j < a.nv; ++j) {
+      double t[VEC];
+      loadv<double, double, VEC>(a.v[j] + e, t);
+      const double c = a.c[j];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] += c * t[v];
+    }
+    storev<double, double, VEC>(u + e, acc);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// LP operators
+// ------------------------------------------------------------------------------------------
+
+// w = M v for one group; for CSR M v = v - msig * (Kt v) with Kt the scaled LP values.
+template <typename S, typename C, int VEC, int FMT, typename F>
+__device__ __forceinline__ void mlp_group(const Geo& geo, const Coef<C>& M, const Csr& csr,
+                                          const S* __restrict__ mval, C msig, int g, const F& f,
+                                          C (&ctr)[VEC], C (&w)[VEC]) {
+  if constexpr (FMT == 0) {
+    stencil_group<C, VEC>(geo, M, g * VEC, f, ctr, w);
+  } else {
+    static_assert(VEC == 1, "CSR kernels use one row per group");
+    ctr[0] = f.one(g);
+    w[0] = ctr[0] - msig * csr_row<C, S>(csr, mval, g, f);
+  }
+}
+
+template <typename S, typename C, int VEC, int FMT>
+__global__ __launch_bounds__(TPB) void k_apply_lp(Launch ln, Geo geo, Coef<C> M, Csr csr,
+                                                  const S* __restrict__ mval, C msig,
+                                                  const S* __restrict__ x, S* __restrict__ y) {
+  const int L = xcd_block(ln.G);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    In1<C, S, VEC> f{x};
+    C ctr[VEC], w[VEC];
+    mlp_group<S, C, VEC, FMT>(geo, M, csr, mval, msig, g, f, ctr, w);
+    storev<S, C, VEC>(y + g * VEC, w);
+  }
+}
+
+template <typename S, typename C, int VEC, int BS>
+__global__ __launch_bounds__(TPB) void k_bj_apply(Launch ln, const S* __restrict__ r,
+                                                  S* __restrict__ z, const S* __restrict__ dinv) {
+  const int L = xcd_block(ln.G);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    const bool valid = g < ln.ng;
+    C rv[VEC], zv[VEC];
+    if (valid) loadv<C, S, VEC>(r + g * VEC, rv);
+    else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) rv[v] = C(0);
+    }
+    bj_apply_lane<C, S, VEC, BS>(dinv, g * VEC, valid, rv, zv);
+    if (valid) storev<S, C, VEC>(z + g * VEC, zv);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Preconditioned CG in LP (heat).  BS = 0: no preconditioner (z is r).
+// ------------------------------------------------------------------------------------------
+
+// A3 for CG: r = LP(res / scale), z = BJ(r), rz = (r, z), rr = (r, r)
+template <typename S, typename C, int VEC, int BS>
+__global__ __launch_bounds__(TPB) void k_cg_begin(Launch ln, const double* __restrict__ res,
+                                                  S* __restrict__ r, S* __restrict__ z,
+                                                  const S* __restrict__ dinv, SolveCfg cfg,
+                                                  Ctl* ctl, double* partials, int pstride) {
+  if (ctl->outer_done) return;
+  const double inv = 1.0 / ctl->scale;
+  const int L = xcd_block(ln.G);
+  double acc[2] = {0.0, 0.0};
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    const bool valid = g < ln.ng;
+    C rv[VEC], zv[VEC];
+    if (valid) {
+      double t[VEC];
+      loadv<double, double, VEC>(res + g * VEC, t);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) rv[v] = rnd<S, C>((C)(t[v] * inv));
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) rv[v] = C(0);
+    }
+    C prz = C(0), prr = C(0);
+    if constexpr (BS > 0) {
+      bj_apply_lane<C, S, VEC, BS>(dinv, g * VEC, valid, rv, zv);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) zv[v] = rnd<S, C>(zv[v]);
+    }
+    if (valid) {
+      storev<S, C, VEC>(r + g * VEC, rv);
+      if constexpr (BS > 0) storev<S, C, VEC>(z + g * VEC, zv);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        prr += rv[v] * rv[v];
+        if constexpr (BS > 0) prz += rv[v] * zv[v];
+      }
+    }
+    acc[0] += (double)prz;
+    acc[1] += (double)prr;
+  }
+  __shared__ double tot[2];
+  if (!reduce_to_last<2>(acc, 2, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (threadIdx.x == 0) {
+    const double rr = tot[1];
+    const double rz = BS > 0 ? tot[0] : rr;
+    const double bn = sqrt(rr);
+    ctl->rz = rz;
+    ctl->rr = rr;
+    ctl->beta = 0.0;
+    ctl->iters = 0;
+    ctl->tol = fmax(cfg.rtol * bn, cfg.atol / ctl->scale);
+    ctl->inner_done = (bn <= ctl->tol) || cfg.maxit <= 0;
+  }
+}
+
+// p_new = z + beta p_old (p_new = z in the first iteration), q = M p_new, pq = (p_new, q).
+// p is double-buffered because neighbours read p_old at the halo while p_new is written.
+template <typename S, typename C, int VEC, int FMT>
+__global__ __launch_bounds__(TPB) void k_cg_dir(Launch ln, Geo geo, Coef<C> M, Csr csr,
+                                                const S* __restrict__ mval, C msig,
+                                                const S* __restrict__ z,
+                                                const S* __restrict__ pold, S* __restrict__ pnew,
+                                                S* __restrict__ q, Ctl* ctl, double* partials,
+                                                int pstride) {
+  if (ctl->outer_done | ctl->inner_done) return;
+  const int first = ctl->iters == 0;
+  InAxpy<C, S, VEC> f{z, pold, (C)ctl->beta, !first};
+  const int L = xcd_block(ln.G);
+  double acc[1] = {0.0};
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    C p[VEC], w[VEC];
+    mlp_group<S, C, VEC, FMT>(geo, M, csr, mval, msig, g, f, p, w);
+    C s = C(0);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      w[v] = rnd<S, C>(w[v]);
+      s += p[v] * w[v];
+    }
+    storev<S, C, VEC>(pnew + g * VEC, p);
+    storev<S, C, VEC>(q + g * VEC, w);
+    acc[0] += (double)s;
+  }
+  __shared__ double tot[1];
+  if (!reduce_to_last<1>(acc, 1, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (threadIdx.x == 0) {
+    const double pq = tot[0];
+    ctl->pq = pq;
+    if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
+      ctl->inner_done = 1;  // breakdown: keep the current iterate
+      ctl->alpha = 0.0;
+    } else {
+      ctl->alpha = ctl->rz / pq;
+    }
+  }
+}
+
+// x += alpha p (x = alpha p first), r -= alpha q, z = BJ(r), rz, rr; convergence test.
+template <typename S, typename C, int VEC, int BS>
+__global__ __launch_bounds__(TPB) void k_cg_upd(Launch ln, S* __restrict__ x,
+                                                const S* __restrict__ p, S* __restrict__ r,
+                                                const S* __restrict__ q, S* __restrict__ z,
+                                                const S* __restrict__ dinv, SolveCfg cfg,
+                                                Ctl* ctl, double* partials, int pstride) {
+  if (ctl->outer_done | ctl->inner_done) return;
+  const int first = ctl->iters == 0;
+  const C alpha = (C)ctl->alpha;
+  const int L = xcd_block(ln.G);
+  double acc[2] = {0.0, 0.0};
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    const bool valid = g < ln.ng;
+    const int e = g * VEC;
+    C rv[VEC], zv[VEC];
+    if (valid) {
+      C pv[VEC], qv[VEC], xv[VEC];
+      loadv<C, S, VEC>(p + e, pv);
+      loadv<C, S, VEC>(q + e, qv);
+      loadv<C, S, VEC>(r + e, rv);
+      if (!first) loadv<C, S, VEC>(x + e, xv);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        xv[v] = first ? alpha * pv[v] : xv[v] + alpha * pv[v];
+        rv[v] = rnd<S, C>(rv[v] - alpha * qv[v]);
+      }
+      storev<S, C, VEC>(x + e, xv);
+      storev<S, C, VEC>(r + e, rv);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) rv[v] = C(0);
+    }
+    C prz = C(0), prr = C(0);
+    if constexpr (BS > 0) {
+      bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, rv, zv);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) zv[v] = rnd<S, C>(zv[v]);
+      if (valid) storev<S, C, VEC>(z + e, zv);
+    }
+    if (valid) {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        prr += rv[v] * rv[v];
+        if constexpr (BS > 0) prz += rv[v] * zv[v];
+      }
+    }
+    acc[0] += (double)prz;
+    acc[1] += (double)prr;
+  }
+  __shared__ double tot[2];
+  if (!reduce_to_last<2>(acc, 2, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (threadIdx.x == 0) {
+    const double rr = tot[1];
+    const double rz = BS > 0 ? tot[0] : rr;
+    const int its = ctl->iters + 1;
+    ctl->iters = its;
+    ctl->total_iters += 1;
+    ctl->life_iters += 1;
+    ctl->beta = rz / ctl->rz;
+    ctl->rz = rz;
+    ctl->rr = rr;
+    const bool fin = __builtin_isfinite(rr) && __builtin_isfinite(rz);
+    ctl->inner_done = !fin || sqrt(rr) <= ctl->tol || its >= cfg.maxit;
+  }
+}
+
+// A8 for CG: y += scale * x ; one LP pass done.
+template <typename S, typename C, int VEC>
+__global__ __launch_bounds__(TPB) void k_promote(Launch ln, double* __restrict__ y,
+                                                 const S* __restrict__ x, Ctl* ctl) {
+  if (ctl->outer_done) return;
+  const double s = ctl->scale;
+  const int have = ctl->iters > 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->passes += 1;
+    ctl->life_passes += 1;
+  }
+  if (!have) return;
+  const int L = xcd_block(ln.G);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    double yv[VEC];
+    C xv[VEC];
+    loadv<double, double, VEC>(y + g * VEC, yv);
+    loadv<C, S, VEC>(x + g * VEC, xv);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) yv[v] += s * (double)xv[v];
+    storev<double, double, VEC>(y + g * VEC, yv);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Right-preconditioned GMRES(m) in LP (advection-diffusion).  Inner products are taken in
+// the RMS sense ((x, y) / N) so stored basis vectors have O(1) entries (FP16 range); basis
+// vector i is vscale[i] times the stored vector i.  One cycle per outer pass: the restart
+// residual is the FP64 residual of the outer loop.
+// ------------------------------------------------------------------------------------------
+
+template <typename S, typename C, int VEC>
+__global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __restrict__ res,
+                                                  S* __restrict__ v0, SolveCfg cfg, Ctl* ctl,
+                                                  double* partials, int pstride) {
+  if (ctl->outer_done) return;
+  const double inv = 1.0 / ctl->scale;
+  const int L = xcd_block(ln.G);
+  double acc[1] = {0.0};
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    double t[VEC];
+    C rv[VEC];
+    loadv<double, double, VEC>(res + g * VEC, t);
+    C s = C(0);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      rv[v] = rnd<S, C>((C)(t[v] * inv));
+      s += rv[v] * rv[v];
+    }
+    storev<S, C, VEC>(v0 + g * VEC, rv);
+    acc[0] += (double)s;
+  }
+  __shared__ double tot[1];
+  if (!reduce_to_last<1>(acc, 1, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(tot[0] * cfg.invN);
+    ctl->vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+    ctl->g[0] = beta;
+    for (int i = 1; i <= MAXM; ++i) ctl->g[i] = 0.0;
+    ctl->J = 0;
+    ctl->iters = 0;
+    ctl->tol = fmax(cfg.rtol * beta, cfg.atol / (ctl->scale * cfg.sqrtN));
+    ctl->inner_done = (beta <= ctl->tol) || beta == 0.0 || cfg.maxit <= 0;
+  }
+}
+
+// z = BJ(v_j), v_j = vscale[j] * V_j
+template <typename S, typename C, int VEC, int BS>
+__global__ __launch_bounds__(TPB) void k_gm_prec(Launch ln, const S* __restrict__ V,
+                                                 size_t vstride, S* __restrict__ z,
+                                                 const S* __restrict__ dinv, Ctl* ctl) {
+  if (ctl->outer_done | ctl->inner_done) return;
+  const int j = ctl->J;
+  const C s = (C)ctl->vscale[j];
+  const S* vj = V + (size_t)j * vstride;
+  const int L = xcd_block(ln.G);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    const bool valid = g < ln.ng;
+    C rv[VEC], zv[VEC];
+    if (valid) {
+      loadv<C, S, VEC>(vj + g * VEC, rv);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) rv[v] *= s;
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) rv[v] = C(0);
+    }
+    bj_apply_lane<C, S, VEC, BS>(dinv, g * VEC, valid, rv, zv);
+    if (valid) storev<S, C, VEC>(z + g * VEC, zv);
+  }
+}
+
+// w = M z (PREC) or w = M v_j ; V_{j+1} := LP(w) ; d_i = (V_i, LP(w)) for i <= j.
+template <typename S, typename C, int VEC, int FMT, int PREC>
+__global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M, Csr csr,
+                                                   const S* __restrict__ mval, C msig,
+                                                   const S* __restrict__ z, S* __restrict__ V,
+                                                   size_t vstride, SolveCfg cfg, Ctl* ctl,
+                                                   double* partials, int pstride) {
+  if (ctl->outer_done | ctl->inner_done) return;
+  const int j = ctl->J;
+  const int nd = j + 1;
+  S* wout = V + (size_t)(j + 1) * vstride;
+  const int L = xcd_block(ln.G);
+  C dacc[MAXD];
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i) dacc[i] = C(0);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    const int e = g * VEC;
+    C ctr[VEC], w[VEC];
+    if constexpr (PREC) {
+      In1<C, S, VEC> f{z};
+      mlp_group<S, C, VEC, FMT>(geo, M, csr, mval, msig, g, f, ctr, w);
+    } else {
+      InScaled<C, S, VEC> f{V + (size_t)j * vstride, (C)ctl->vscale[j]};
+      mlp_group<S, C, VEC, FMT>(geo, M, csr, mval, msig, g, f, ctr, w);
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) w[v] = rnd<S, C>(w[v]);
+    storev<S, C, VEC>(wout + e, w);
+#pragma unroll
+    for (int i = 0; i < MAXD; ++i) {
+      if (i < nd) {
+        C vi[VEC];
+        loadv<C, S, VEC>(V + (size_t)i * vstride + e, vi);
+        C s = C(0);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) s += vi[v] * w[v];
+        dacc[i] += s;
+      }
+    }
+  }
+  double acc[MAXD];
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i) acc[i] = (double)dacc[i];
+  __shared__ double tot[MAXD];
+  if (!reduce_to_last<MAXD>(acc, nd, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (threadIdx.x < nd) ctl->hcol[threadIdx.x] = ctl->vscale[threadIdx.x] * tot[threadIdx.x] * cfg.invN;
+}
+
+// Solve the J x J upper-triangular system H y = g (column-major, leading dim MAXM+1).
+__device__ inline void gm_backsolve(Ctl* ctl, int J) {
+  for (int i = J - 1; i >= 0; --i) {
+    double s = ctl->g[i];
+    for (int k = i + 1; k < J; ++k) s -= ctl->H[k * (MAXM + 1) + i] * ctl->ysol[k];
+    const double d = ctl->H[i * (MAXM + 1) + i];
+    ctl->ysol[i] = d != 0.0 ? s / d : 0.0;
+  }
+}
+
+// w -= sum_{i<=j} h_ij v_i (classical Gram-Schmidt, coefficients from k_gm_matvec);
+// h_{j+1,j} = ||w||; Givens update of the Hessenberg column; residual estimate |g_{j+1}|.
+template <typename S, typename C, int VEC>
+__global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, size_t vstride,
+                                                 SolveCfg cfg, Ctl* ctl, double* partials,
+                                                 int pstride) {
+  if (ctl->outer_done | ctl->inner_done) return;
+  const int j = ctl->J;
+  const int nd = j + 1;
+  C cf[MAXD];
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i) cf[i] = i < nd ? (C)(ctl->hcol[i] * ctl->vscale[i]) : C(0);
+  S* w = V + (size_t)(j + 1) * vstride;
+  const int L = xcd_block(ln.G);
+  double acc[1] = {0.0};
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    const int e = g * VEC;
+    C wv[VEC];
+    loadv<C, S, VEC>(w + e, wv);
+#pragma unroll
+    for (int i = 0; i < MAXD; ++i) {
+      if (i < nd) {
+        C vi[VEC];
+        loadv<C, S, VEC>(V + (size_t)i * vstride + e, vi);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) wv[v] -= cf[i] * vi[v];
+      }
+    }
+    C s = C(0);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      wv[v] = rnd<S, C>(wv[v]);
+      s += wv[v] * wv[v];
+    }
+    storev<S, C, VEC>(w + e, wv);
+    acc[0] += (double)s;
+  }
+  __shared__ double tot[1];
+  if (!reduce_to_last<1>(acc, 1, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (threadIdx.x == 0) {
+    const double hn = sqrt(tot[0] * cfg.invN);
+    double* col = ctl->H + j * (MAXM + 1);
+    for (int i = 0; i <= j; ++i) col[i] = ctl->hcol[i];
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {  // previous rotations
+      const double a = col[i], b = col[i + 1];
+      col[i] = ctl->cs[i] * a + ctl->sn[i] * b;
+      col[i + 1] = -ctl->sn[i] * a + ctl->cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double den = sqrt(a * a + b * b);
+    const double c = den > 0.0 ? a / den : 1.0;
+    const double sn = den > 0.0 ? b / den : 0.0;
+    ctl->cs[j] = c;
+    ctl->sn[j] = sn;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    ctl->g[j + 1] = -sn * ctl->g[j];
+    ctl->g[j] = c * ctl->g[j];
+    const int its = ctl->iters + 1;
+    ctl->iters = its;
+    ctl->total_iters += 1;
+    ctl->life_iters += 1;
+    const int J = j + 1;
+    ctl->J = J;
+    ctl->vscale[J] = hn > 0.0 ? 1.0 / hn : 0.0;
+    const double resid = fabs(ctl->g[J]);
+    const bool fin = __builtin_isfinite(resid) && __builtin_isfinite(den);
+    const bool stop = !fin || resid <= ctl->tol || hn == 0.0 || J >= cfg.m || its >= cfg.maxit;
+    if (stop) {
+      gm_backsolve(ctl, J);
+      if (!fin)
+        for (int i = 0; i < J; ++i) ctl->ysol[i] = 0.0;
+      ctl->inner_done = 1;
+    }
+  }
+}
+
+// A8 for GMRES: y += scale * BJ(sum_{i<J} ysol_i v_i) ; one LP pass done.
+template <typename S, typename C, int VEC, int BS>
+__global__ __launch_bounds__(TPB) void k_gm_finish(Launch ln, double* __restrict__ y,
+                                                   const S* __restrict__ V, size_t vstride,
+                                                   const S* __restrict__ dinv, Ctl* ctl) {
+  if (ctl->outer_done) return;
+  const int J = ctl->J;
+  const double sc = ctl->scale;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->passes += 1;
+    ctl->life_passes += 1;
+  }
+  if (J == 0) return;
+  C cf[MAXM];
+#pragma unroll
+  for (int i = 0; i < MAXM; ++i) cf[i] = i < J ? (C)(ctl->ysol[i] * ctl->vscale[i]) : C(0);
+  const int L = xcd_block(ln.G);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    const bool valid = g < ln.ng;
+    const int e = g * VEC;
+    C t[VEC], zv[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) t[v] = C(0);
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) {
+        if (i < J) {
+          C vi[VEC];
+          loadv<C, S, VEC>(V + (size_t)i * vstride + e, vi);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) t[v] += cf[i] * vi[v];
+        }
+      }
+    }
+    if constexpr (BS > 0) {
+      bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, t, zv);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) zv[v] = t[v];
+    }
+    if (valid) {
+      double yv[VEC];
+      loadv<double, double, VEC>(y + e, yv);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) yv[v] += sc * (double)zv[v];
+      storev<double, double, VEC>(y + e, yv);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Setup (not on the timed path)
+// ------------------------------------------------------------------------------------------
+
+// In-place Gauss-Jordan inverse of an n x n (n <= BJ_MAX) matrix with partial pivoting.
+__device__ inline int gj_invert(double (&a)[BJ_MAX][BJ_MAX], double (&inv)[BJ_MAX][BJ_MAX], int n) {
+  for (int i = 0; i < BJ_MAX; ++i)
+    for (int k = 0; k < BJ_MAX; ++k) inv[i][k] = (i == k) ? 1.0 : 0.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    double best = fabs(a[col][col]);
+    for (int i = col + 1; i < n; ++i)
+      if (fabs(a[i][col]) > best) {
+        best = fabs(a[i][col]);
+        piv = i;
+      }
+    if (!(best > 0.0)) return 1;
+    if (piv != col)
+      for (int k = 0; k < BJ_MAX; ++k) {
+        double t = a[col][k];
+        a[col][k] = a[piv][k];
+        a[piv][k] = t;
+        t = inv[col][k];
+        inv[col][k] = inv[piv][k];
+        inv[piv][k] = t;
+      }
+    const double d = 1.0 / a[col][col];
+    for (int k = 0; k < BJ_MAX; ++k) {
+      a[col][k] *= d;
+      inv[col][k] *= d;
+    }
+    for (int i = 0; i < n; ++i) {
+      if (i == col) continue;
+      const double f = a[i][col];
+      if (f == 0.0) continue;
+      for (int k = 0; k < BJ_MAX; ++k) {
+        a[i][k] -= f * a[col][k];
+        inv[i][k] -= f * inv[col][k];
+      }
+    }
+  }
+  return 0;
+}
+
+template <typename S>
+__device__ inline void bj_store(S* dinv, int blk, int BS, int n, const double (&inv)[BJ_MAX][BJ_MAX]) {
+  for (int i = 0; i < BS; ++i)
+    for (int k = 0; k < BS; ++k) {
+      double v = (i < n && k < n) ? inv[i][k] : (i == k ? 1.0 : 0.0);
+      dinv[((size_t)blk * BS + i) * BS + k] = (S)v;
+    }
+}
+
+// Diagonal blocks of M = I - sigma K for the stencil operator (Mc = stencil of M in FP64).
+template <typename S>
+__global__ void k_bj_setup_stencil(int nblk, int BS, Geo geo, Coef<double> Mc, S* dinv,
+                                   int* fail) {
+  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= nblk) return;
+  const int r0 = blk * BS;
+  const int n = min(BS, geo.N - r0);
+  double a[BJ_MAX][BJ_MAX], inv[BJ_MAX][BJ_MAX];
+  for (int i = 0; i < BJ_MAX; ++i)
+    for (int k = 0; k < BJ_MAX; ++k) a[i][k] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const int row = r0 + i;
+    const Nbr nb = neighbours<1>(geo, row);
+    a[i][i] += Mc.c;
+    const int idx[6] = {nb.xm, nb.xp, nb.ym, nb.yp, nb.zm, nb.zp};
+    const double cf[6] = {Mc.xm, Mc.xp, Mc.ym, Mc.yp, Mc.zm, Mc.zp};
+    for (int d = 0; d < 6; ++d) {
+      const int c = idx[d];
+      if (c >= r0 && c < r0 + n) a[i][c - r0] += cf[d];
+    }
+  }
+  if (gj_invert(a, inv, n)) atomicOr(fail, 1);
+  bj_store<S>(dinv, blk, BS, n, inv);
+}
+
+// Diagonal blocks of M = I - sigma K from the FP64 CSR values of K.
+template <typename S>
+__global__ void k_bj_setup_csr(int nblk, int BS, int N, Csr csr, const double* kval, double sigma,
+                               S* dinv, int* fail) {
+  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= nblk) return;
+  const int r0 = blk * BS;
+  const int n = min(BS, N - r0);
+  double a[BJ_MAX][BJ_MAX], inv[BJ_MAX][BJ_MAX];
+  for (int i = 0; i < BJ_MAX; ++i)
+    for (int k = 0; k < BJ_MAX; ++k) a[i][k] = (i == k && i < n) ? 1.0 : 0.0;
+  for (int i = 0; i < n; ++i) {
+    const int row = r0 + i;
+    for (int k = csr.rowptr[row]; k < csr.rowptr[row + 1]; ++k) {
+      const int c = csr.col[k];
+      if (c >= r0 && c < r0 + n) a[i][c - r0] -= sigma * kval[k];
+    }
+  }
+  if (gj_invert(a, inv, n)) atomicOr(fail, 1);
+  bj_store<S>(dinv, blk, BS, n, inv);
+}
+
+// LP copy of the CSR values of K, scaled by a power of two into [-1, 1].
+template <typename S>
+__global__ void k_csr_lp_values(long nnz, const double* __restrict__ kval, double inv_kscale,
+                                S* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nnz) out[i] = (S)(kval[i] * inv_kscale);
+}
+
+}  // namespace mprk

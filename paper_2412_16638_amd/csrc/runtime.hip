@@ -1,0 +1,923 @@
+// runtime.hip -- the C ABI of include/mprk.h: problem set-up, workspace layout, operator
+// assembly, and the host driver that enqueues one time step and steers the Krylov loops by
+// polling the 64-byte device control head.
+//
+// The DIRK step (eq. RKstep) is organised as in the paper's implementation: explicit
+// operations and stage vectors in FP64, implicit stage systems (eq. corelinear) solved in the
+// low precision after converting the right-hand side, result converted back (Section
+// "Implementation of the Mixed-precision Runge--Kutta methods").  Here the conversion is of
+// the FP64 stage residual, and the stage is repeated until the FP64 residual meets
+// outer_tol (refine_max = 0 keeps the paper's single conversion).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "../../include/mprk.h"
+#include "engine.hpp"
+#include "runtime_internal.hpp"
+
+using namespace mprk;
+
+#define HIPCHK(x)                                                                       \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      return set_error(MPRK_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+namespace mprk {
+
+thread_local std::string g_err;
+
+int set_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+Launch make_launch(long ng) {
+  const long target_blocks = 2048;  // 8 resident 256-thread blocks on each of 256 CUs
+  long nit = (ng + (long)TPB * target_blocks - 1) / ((long)TPB * target_blocks);
+  nit = std::max(1L, std::min(nit, 8L));
+  long G = (ng + nit * TPB - 1) / (nit * TPB);
+  G = std::max(8L, (G + 7) / 8 * 8);
+  return Launch{(int)ng, (int)nit, (int)G};
+}
+
+// 7-point coefficients of K (FP64): K u = kc u + sum_d (km_d u[-e_d] + kp_d u[+e_d]).
+Coef<double> operator_coef(const mprk_grid& g, const mprk_operator& op) {
+  const int n[3] = {g.nx, g.ny, g.nz};
+  double km[3], kp[3], kc = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double h = g.bc == MPRK_BC_DIRICHLET0 ? 1.0 / (n[d] + 1) : 1.0 / n[d];
+    const double b = op.kind == MPRK_OP_ADVDIFF ? op.b[d] : 0.0;
+    const double dif = op.diff / (h * h);
+    km[d] = dif + (b >= 0.0 ? b / h : 0.0);
+    kp[d] = dif + (b < 0.0 ? -b / h : 0.0);
+    kc -= 2.0 * dif + std::fabs(b) / h;
+  }
+  return Coef<double>{kc, km[0], kp[0], km[1], kp[1], km[2], kp[2]};
+}
+
+// M = I - sigma K
+Coef<double> stage_coef(const Coef<double>& K, double sigma) {
+  return Coef<double>{1.0 - sigma * K.c, -sigma * K.xm, -sigma * K.xp, -sigma * K.ym,
+                      -sigma * K.yp,     -sigma * K.zm, -sigma * K.zp};
+}
+
+// Entries of row r of K from the stencil: sorted columns, duplicates merged (periodic axes
+// with fewer than 3 points), exact zeros dropped.  Returns the count (<= 7).
+static int csr_row_entries(const Geo& geo, const Coef<double>& K, int r, int* col, double* val) {
+  const bool per = geo.bc == MPRK_BC_PERIODIC;
+  const int x = r % geo.nx, t = r / geo.nx, y = t % geo.ny, z = t / geo.ny;
+  int ne = 0;
+  auto add = [&](int c, double v) {
+    for (int i = 0; i < ne; ++i)
+      if (col[i] == c) {
+        val[i] += v;
+        return;
+      }
+    col[ne] = c;
+    val[ne] = v;
+    ++ne;
+  };
+  add(r, K.c);
+  if (x > 0) add(r - 1, K.xm); else if (per) add(r + geo.nx - 1, K.xm);
+  if (x < geo.nx - 1) add(r + 1, K.xp); else if (per) add(r - geo.nx + 1, K.xp);
+  if (y > 0) add(r - geo.nx, K.ym); else if (per) add(r + (geo.ny - 1) * geo.nx, K.ym);
+  if (y < geo.ny - 1) add(r + geo.nx, K.yp); else if (per) add(r - (geo.ny - 1) * geo.nx, K.yp);
+  if (z > 0) add(r - geo.plane, K.zm); else if (per) add(r + (geo.nz - 1) * geo.plane, K.zm);
+  if (z < geo.nz - 1) add(r + geo.plane, K.zp); else if (per) add(r - (geo.nz - 1) * geo.plane, K.zp);
+  for (int i = 1; i < ne; ++i) {  // insertion sort by column
+    const int c = col[i];
+    const double v = val[i];
+    int k = i - 1;
+    while (k >= 0 && col[k] > c) {
+      col[k + 1] = col[k];
+      val[k + 1] = val[k];
+      --k;
+    }
+    col[k + 1] = c;
+    val[k + 1] = v;
+  }
+  int m = 0;
+  for (int i = 0; i < ne; ++i)
+    if (val[i] != 0.0) {
+      col[m] = col[i];
+      val[m] = val[i];
+      ++m;
+    }
+  return m;
+}
+
+// Number of stored entries and max |K_ij| of the CSR form of K.
+long csr_count(const Geo& geo, const Coef<double>& K, double* maxabs) {
+  long nnz = 0;
+  double mx = 0.0;
+  int c[7];
+  double v[7];
+  for (int r = 0; r < geo.N; ++r) {
+    const int m = csr_row_entries(geo, K, r, c, v);
+    nnz += m;
+    for (int i = 0; i < m; ++i) mx = std::max(mx, std::fabs(v[i]));
+  }
+  if (maxabs) *maxabs = mx;
+  return nnz;
+}
+
+// Host CSR assembly of K from the stencil.
+void assemble_csr(const Geo& geo, const Coef<double>& K, std::vector<int>& rowptr,
+                  std::vector<int>& col, std::vector<double>& val) {
+  const int N = geo.N;
+  rowptr.assign((size_t)N + 1, 0);
+  const long nnz = csr_count(geo, K, nullptr);
+  col.resize((size_t)nnz);
+  val.resize((size_t)nnz);
+  long pos = 0;
+  for (int r = 0; r < N; ++r) {
+    const int m = csr_row_entries(geo, K, r, col.data() + pos, val.data() + pos);
+    pos += m;
+    rowptr[(size_t)r + 1] = (int)pos;
+  }
+}
+
+}  // namespace mprk
+
+// ------------------------------------------------------------------------------------------
+// tableaus and defaults
+// ------------------------------------------------------------------------------------------
+
+extern "C" int32_t mprk_tableau_builtin(int32_t id, int32_t param, mprk_tableau* out) {
+  if (!out) return set_error(MPRK_EINVAL, "mprk_tableau_builtin: out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  auto HI = [&](int i, int j, double v) { out->a_hi[i * out->s + j] = v; };
+  auto LO = [&](int i, int j, double v) { out->a_lo[i * out->s + j] = v; };
+  switch (id) {
+    case MPRK_TAB_SDIRK2: {  // Alexander's L-stable two-stage SDIRK, gamma = 1 - 1/sqrt(2)
+      out->s = 2;
+      const double g = 1.0 - 1.0 / std::sqrt(2.0);
+      LO(0, 0, g);
+      HI(1, 0, 1.0 - g);
+      LO(1, 1, g);
+      out->b[0] = 1.0 - g;
+      out->b[1] = g;
+      return MPRK_OK;
+    }
+    case MPRK_TAB_SDIRK3: {  // Alexander's L-stable three-stage SDIRK of order 3
+      out->s = 3;
+      const double g = 0.43586652150845899941601945;
+      const double b1 = -1.5 * g * g + 4.0 * g - 0.25;
+      const double b2 = 1.5 * g * g - 5.0 * g + 1.25;
+      LO(0, 0, g);
+      HI(1, 0, 0.5 * (1.0 - g));
+      LO(1, 1, g);
+      HI(2, 0, b1);
+      HI(2, 1, b2);
+      LO(2, 2, g);
+      out->b[0] = b1;
+      out->b[1] = b2;
+      out->b[2] = g;
+      return MPRK_OK;
+    }
+    case MPRK_TAB_MID: {  // implicit midpoint + `param` FP64 corrector steps (Appendix A)
+      if (param < 0 || param > MPRK_MAX_STAGES - 1)
+        return set_error(MPRK_EINVAL, "MID: corrector count must be in [0, 7]");
+      out->s = param + 1;
+      LO(0, 0, 0.5);
+      for (int i = 1; i <= param; ++i) HI(i, i - 1, 0.5);
+      out->b[param] = 1.0;
+      return MPRK_OK;
+    }
+    case MPRK_TAB_4S3PA: {  // Table ButchertabA
+      out->s = 4;
+      LO(0, 0, 0.788675134594813);
+      HI(1, 0, 0.211324865405187);
+      HI(2, 0, 0.709495523817170);
+      LO(2, 0, 0.051944240459852);
+      HI(2, 1, -0.86531425061942);
+      LO(2, 2, 0.788675134594813);
+      HI(3, 0, 0.705123240545107);
+      HI(3, 1, 0.943370088535775);
+      HI(3, 2, -0.859818194486069);
+      out->b[1] = 0.5;
+      out->b[3] = 0.5;
+      return MPRK_OK;
+    }
+    case MPRK_TAB_4S3PB: {  // Table ButchertabB, a42^(eps) = -3/2 - a42
+      out->s = 4;
+      for (int i = 0; i < 4; ++i) LO(i, i, 0.5);
+      HI(1, 0, 2.543016042796356);
+      LO(1, 0, -2.376349376129689);
+      HI(2, 0, 2.451484396921318);
+      LO(2, 0, -2.951484396921318);
+      HI(2, 1, 0.024108961241221);
+      LO(2, 1, 0.475891038758779);
+      HI(3, 0, 2.073861819468268);
+      LO(3, 0, -0.573861819468268);
+      HI(3, 1, 2.367724727682735);
+      LO(3, 1, -1.5 - 2.367724727682735);
+      HI(3, 2, 1.711868223075524);
+      LO(3, 2, -1.211868223075524);
+      out->b[0] = 1.5;
+      out->b[1] = -1.5;
+      out->b[2] = 0.5;
+      out->b[3] = 0.5;
+      return MPRK_OK;
+    }
+    case MPRK_TAB_4S3PC: {  // Table ButchertabC
+      out->s = 4;
+      LO(0, 0, 0.511243008730995);
+      LO(1, 0, -1.999347282862640);
+      HI(1, 0, -0.050470366527530);
+      LO(1, 1, 1.957161067302390);
+      LO(2, 0, 0.443312893511937);
+      HI(2, 0, 0.368613367355336);
+      LO(2, 1, -0.573131033672219);
+      HI(2, 1, 0.273504374252976);
+      LO(2, 2, 0.128283796414019);
+      LO(3, 0, -2.0);
+      HI(3, 0, 1.803794668975043);
+      LO(3, 1, -0.160330320741428);
+      HI(3, 1, 0.097485042980759);
+      LO(3, 2, 0.579597314161362);
+      HI(3, 2, -1.895660952342050);
+      LO(3, 3, 1.484688928981990);
+      out->b[0] = 0.002837446974069;
+      out->b[1] = 0.336264433650450;
+      out->b[2] = 0.806376720267787;
+      out->b[3] = -0.145478600892306;
+      return MPRK_OK;
+    }
+    default:
+      return set_error(MPRK_EINVAL, "unknown tableau id");
+  }
+}
+
+extern "C" int32_t mprk_precisions_default(int32_t storage, int32_t krylov, mprk_precisions* out) {
+  if (!out) return set_error(MPRK_EINVAL, "mprk_precisions_default: out is NULL");
+  if (storage < MPRK_FP64 || storage > MPRK_FP16 || krylov < MPRK_CG || krylov > MPRK_GMRES)
+    return set_error(MPRK_EINVAL, "mprk_precisions_default: bad storage or krylov");
+  std::memset(out, 0, sizeof(*out));
+  out->storage = storage;
+  out->compute = storage == MPRK_FP64 ? MPRK_FP64 : MPRK_FP32;
+  out->krylov = krylov;
+  out->restart = 30;
+  out->precond = MPRK_PRECOND_BJ;
+  out->block = 8;
+  out->atol = 0.0;
+  out->strict = 0;
+  out->reorth = 0;
+  if (storage == MPRK_FP64) {
+    out->rtol = 1e-12;
+    out->outer_tol = 1e-11;
+    out->refine_max = krylov == MPRK_CG ? 4 : 20;
+  } else if (storage == MPRK_FP32) {
+    out->rtol = krylov == MPRK_CG ? 1e-5 : 1e-4;
+    out->outer_tol = 1e-10;
+    out->refine_max = krylov == MPRK_CG ? 8 : 20;
+  } else {
+    out->rtol = 1e-2;
+    out->outer_tol = 1e-6;
+    out->refine_max = 20;
+  }
+  out->maxit = krylov == MPRK_CG ? 1000 : 30;
+  return MPRK_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// create / layout
+// ------------------------------------------------------------------------------------------
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tableau* tab,
+                    const mprk_precisions* p, double dt) {
+  if (!g || !op || !tab || !p) return set_error(MPRK_EINVAL, "NULL argument");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return set_error(MPRK_EINVAL, "grid extents must be >= 1");
+  if (g->bc != MPRK_BC_DIRICHLET0 && g->bc != MPRK_BC_PERIODIC) return set_error(MPRK_EINVAL, "bad bc");
+  const double N = (double)g->nx * g->ny * g->nz;
+  if (N * 7.0 >= 2147483647.0) return set_error(MPRK_EINVAL, "grid too large for int32 indexing");
+  if (op->kind != MPRK_OP_HEAT && op->kind != MPRK_OP_ADVDIFF) return set_error(MPRK_EINVAL, "bad operator kind");
+  if (op->format != MPRK_FMT_STENCIL && op->format != MPRK_FMT_CSR) return set_error(MPRK_EINVAL, "bad format");
+  if (!(op->diff >= 0.0) || !std::isfinite(op->diff)) return set_error(MPRK_EINVAL, "diffusion must be finite and >= 0");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(op->b[d])) return set_error(MPRK_EINVAL, "velocity must be finite");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(MPRK_EINVAL, "dt must be > 0");
+  if (tab->s < 1 || tab->s > MPRK_MAX_STAGES) return set_error(MPRK_EINVAL, "tableau stages must be in [1, 8]");
+  for (int i = 0; i < tab->s; ++i) {
+    for (int j = 0; j < tab->s; ++j) {
+      const double a = tab->a_hi[i * tab->s + j] + tab->a_lo[i * tab->s + j];
+      if (!std::isfinite(a)) return set_error(MPRK_EINVAL, "tableau entries must be finite");
+      if (j > i && a != 0.0) return set_error(MPRK_EINVAL, "tableau must be lower triangular (DIRK)");
+    }
+    if (!std::isfinite(tab->b[i])) return set_error(MPRK_EINVAL, "tableau weights must be finite");
+  }
+  if (p->storage < MPRK_FP64 || p->storage > MPRK_FP16) return set_error(MPRK_EINVAL, "bad storage");
+  if (p->compute != MPRK_FP64 && p->compute != MPRK_FP32) return set_error(MPRK_EINVAL, "bad compute");
+  if (p->compute == MPRK_FP64 && p->storage != MPRK_FP64)
+    return set_error(MPRK_EUNSUPPORTED, "FP64 compute needs FP64 storage");
+  if (p->storage == MPRK_FP64 && p->compute != MPRK_FP64)
+    return set_error(MPRK_EUNSUPPORTED, "FP64 storage needs FP64 compute");
+  if (p->krylov != MPRK_CG && p->krylov != MPRK_GMRES) return set_error(MPRK_EINVAL, "bad krylov");
+  if (p->krylov == MPRK_GMRES && (p->restart < 1 || p->restart > MPRK_MAX_RESTART))
+    return set_error(MPRK_EINVAL, "GMRES restart must be in [1, 32]");
+  if (p->precond != MPRK_PRECOND_NONE && p->precond != MPRK_PRECOND_BJ) return set_error(MPRK_EINVAL, "bad precond");
+  if (p->precond == MPRK_PRECOND_BJ && !(p->block == 1 || p->block == 2 || p->block == 4 || p->block == 8))
+    return set_error(MPRK_EINVAL, "block size must be 1, 2, 4 or 8");
+  if (!(p->rtol >= 0.0) || !(p->atol >= 0.0) || !(p->outer_tol >= 0.0))
+    return set_error(MPRK_EINVAL, "tolerances must be >= 0");
+  if (p->maxit < 0 || p->refine_max < 0) return set_error(MPRK_EINVAL, "maxit and refine_max must be >= 0");
+  if (p->krylov == MPRK_CG && op->kind == MPRK_OP_ADVDIFF &&
+      (op->b[0] != 0.0 || op->b[1] != 0.0 || op->b[2] != 0.0))
+    return set_error(MPRK_EINVAL, "CG needs a symmetric operator; use GMRES for advection");
+  if (p->reorth) return set_error(MPRK_EUNSUPPORTED, "CGS2 re-orthogonalisation is not implemented");
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_create(const mprk_grid* grid, const mprk_operator* op,
+                               const mprk_tableau* tab, const mprk_precisions* prec, double dt,
+                               void* hip_stream, mprk_handle** out) {
+  if (!out) return set_error(MPRK_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(grid, op, tab, prec, dt);
+  if (rc) return rc;
+  mprk_handle* h = new (std::nothrow) mprk_handle();
+  if (!h) return set_error(MPRK_ENOMEM, "host allocation failed");
+  rc = h->init(*grid, *op, *tab, *prec, dt, (hipStream_t)hip_stream);
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return MPRK_OK;
+}
+
+int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tableau& t,
+                      const mprk_precisions& p, double dt_, hipStream_t s) {
+  grid = g;
+  op = o;
+  tab = t;
+  prec = p;
+  dt = dt_;
+  stream = s;
+  geo = Geo{g.nx, g.ny, g.nz, g.bc, g.nx * g.ny * g.nz, g.nx * g.ny};
+  N = geo.N;
+  vec = (g.nx % 4 == 0) ? 4 : 1;
+  Kc = operator_coef(g, o);
+  switch (p.storage) {
+    case MPRK_FP64: eng.reset(make_engine_fp64()); break;
+    case MPRK_FP32: eng.reset(make_engine_fp32()); break;
+    default: eng.reset(make_engine_fp16()); break;
+  }
+  lp_bytes = eng->elem_bytes();
+  nstages = t.s;
+  need_keps = false;
+  sigmas.clear();
+  for (int i = 0; i < t.s; ++i) {
+    const double aii = t.a_hi[i * t.s + i] + t.a_lo[i * t.s + i];
+    implicit_[i] = aii != 0.0;
+    sig_idx[i] = -1;
+    if (implicit_[i]) {
+      const double sg = dt * aii;
+      int k = -1;
+      for (size_t q = 0; q < sigmas.size(); ++q)
+        if (sigmas[q] == sg) k = (int)q;
+      if (k < 0) {
+        sigmas.push_back(sg);
+        k = (int)sigmas.size() - 1;
+      }
+      sig_idx[i] = k;
+    }
+    for (int j = 0; j < i; ++j)
+      if (t.a_lo[i * t.s + j] != 0.0 && (t.a_hi[j * t.s + j] + t.a_lo[j * t.s + j]) != 0.0)
+        need_keps = true;
+  }
+  // launches
+  ln_vec = make_launch(N / vec);
+  ln_row = make_launch(N);
+  pstride = std::max(ln_vec.G, ln_row.G);
+  bs = p.precond == MPRK_PRECOND_BJ ? p.block : 0;
+  nblk = bs ? (N + bs - 1) / bs : 0;
+  // CSR size (assembled at bind)
+  nnz = 0;
+  if (o.format == MPRK_FMT_CSR) {
+    double mx = 0.0;
+    nnz = csr_count(geo, Kc, &mx);
+    kscale = mx > 0.0 ? std::ldexp(1.0, (int)std::ceil(std::log2(mx))) : 1.0;
+  } else {
+    kscale = 1.0;
+  }
+  // layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o2 = off;
+    off += align256(bytes);
+    return o2;
+  };
+  const size_t v64 = (size_t)N * 8;
+  const size_t vlp = align256((size_t)N * lp_bytes);
+  o_rhs = take(v64);
+  o_y = take(v64);
+  o_res = take(v64);
+  o_k = take(v64 * nstages);
+  o_keps = need_keps ? take(v64 * nstages) : 0;
+  o_scr = take(v64);  // scratch FP64 vector (solve output of k, verification)
+  if (p.krylov == MPRK_CG) {
+    o_r = take(vlp);
+    o_z = bs ? take(vlp) : o_r;
+    o_p0 = take(vlp);
+    o_p1 = take(vlp);
+    o_q = take(vlp);
+    o_x = take(vlp);
+    o_V = 0;
+  } else {
+    o_V = take(vlp * (size_t)(p.restart + 1));
+    o_z = bs ? take(vlp) : 0;
+    o_r = o_p0 = o_p1 = o_q = o_x = 0;
+  }
+  vstride = vlp / lp_bytes;
+  o_dinv = bs ? take((size_t)nblk * bs * bs * lp_bytes * sigmas.size()) : 0;
+  dinv_stride = (size_t)nblk * bs * bs * lp_bytes;
+  if (o.format == MPRK_FMT_CSR) {
+    o_rowptr = take((size_t)(N + 1) * 4);
+    o_col = take((size_t)nnz * 4);
+    o_kval = take((size_t)nnz * 8);
+    o_mval = take((size_t)nnz * lp_bytes);
+  }
+  o_ctl = take(sizeof(Ctl));
+  o_flag = take(256);
+  o_part = take((size_t)MAXD * pstride * 8);
+  ws_bytes = off;
+  // per-sigma solve configurations
+  cfgs.clear();
+  for (double sg : sigmas) {
+    SolveCfg c{};
+    c.sigma = sg;
+    c.outer_tol = p.outer_tol;
+    c.max_passes = std::max(p.refine_max, 1);
+    c.paper_mode = p.refine_max == 0;
+    c.rtol = p.rtol;
+    c.atol = p.atol;
+    c.m = p.krylov == MPRK_GMRES ? p.restart : 0;
+    c.maxit = p.krylov == MPRK_GMRES ? std::min(p.maxit, p.restart) : p.maxit;
+    c.sqrtN = std::sqrt((double)N);
+    c.invN = 1.0 / (double)N;
+    cfgs.push_back(c);
+  }
+  return MPRK_OK;
+}
+
+// Pinned poll slots and events: made on the first bind (the first call that needs a device).
+int mprk_handle::make_device_resources() {
+  if (events_made) return MPRK_OK;
+  if (!slots) {
+    HIPCHK(hipHostMalloc((void**)&slots, sizeof(CtlHead) * (NSLOT + MPRK_MAX_STAGES + 1)));
+    std::memset(slots, 0, sizeof(CtlHead) * (NSLOT + MPRK_MAX_STAGES + 1));
+  }
+  for (int i = 0; i < NSLOT; ++i) HIPCHK(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+  events_made = true;
+  return MPRK_OK;
+}
+
+mprk_handle::~mprk_handle() {
+  if (events_made)
+    for (int i = 0; i < NSLOT; ++i) (void)hipEventDestroy(ev[i]);
+  if (slots) (void)hipHostFree(slots);
+}
+
+extern "C" int64_t mprk_workspace_bytes(const mprk_handle* h) {
+  if (!h) return set_error(MPRK_EINVAL, "NULL handle");
+  return (int64_t)h->ws_bytes;
+}
+
+
+EngineCtx mprk_handle::ctx() const {
+  EngineCtx c{};
+  c.stream = stream;
+  c.geo = geo;
+  c.fmt = op.format;
+  c.vec = vec;
+  c.ln_vec = ln_vec;
+  c.ln_row = ln_row;
+  c.ln_mv = op.format == MPRK_FMT_CSR ? ln_row : ln_vec;
+  c.bs = bs;
+  c.csr = Csr{(const int*)(ws + o_rowptr), (const int*)(ws + o_col)};
+  c.mval = ws + o_mval;
+  c.kscale = kscale;
+  c.ctl = (Ctl*)(ws + o_ctl);
+  c.partials = (double*)(ws + o_part);
+  c.pstride = pstride;
+  c.r = ws + o_r;
+  c.z = ws + o_z;
+  c.p0 = ws + o_p0;
+  c.p1 = ws + o_p1;
+  c.q = ws + o_q;
+  c.x = ws + o_x;
+  c.V = ws + o_V;
+  c.vstride = vstride;
+  c.res = (double*)(ws + o_res);
+  c.y = (double*)(ws + o_y);
+  return c;
+}
+
+extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev, int64_t bytes) {
+  if (!h || !u_dev || !workspace_dev) return set_error(MPRK_EINVAL, "NULL argument");
+  if (bytes < (int64_t)h->ws_bytes) return set_error(MPRK_ENOMEM, "workspace smaller than mprk_workspace_bytes");
+  if (((uintptr_t)workspace_dev & 255) != 0) return set_error(MPRK_EINVAL, "workspace must be 256-byte aligned");
+  if (((uintptr_t)u_dev & 31) != 0) return set_error(MPRK_EINVAL, "u must be 32-byte aligned");
+  int rc0 = h->make_device_resources();
+  if (rc0) return rc0;
+  h->u = u_dev;
+  h->ws = (char*)workspace_dev;
+  h->bound = false;
+  HIPCHK(hipMemsetAsync(h->ws + h->o_ctl, 0, sizeof(Ctl), h->stream));
+  HIPCHK(hipMemsetAsync(h->ws + h->o_flag, 0, 256, h->stream));
+  EngineCtx c = h->ctx();
+  if (h->op.format == MPRK_FMT_CSR) {
+    std::vector<int> rp, cl;
+    std::vector<double> vl;
+    assemble_csr(h->geo, h->Kc, rp, cl, vl);
+    if ((long)cl.size() != h->nnz) return set_error(MPRK_EINVAL, "CSR size mismatch");
+    HIPCHK(hipMemcpyAsync(h->ws + h->o_rowptr, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->ws + h->o_col, cl.data(), cl.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->ws + h->o_kval, vl.data(), vl.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h->eng->csr_values(c, h->nnz, (const double*)(h->ws + h->o_kval), h->ws + h->o_mval));
+    HIPCHK(hipStreamSynchronize(h->stream));  // host vectors go out of scope
+  }
+  int* fail = (int*)(h->ws + h->o_flag);
+  if (h->bs) {
+    for (size_t q = 0; q < h->sigmas.size(); ++q) {
+      void* dinv = h->ws + h->o_dinv + q * h->dinv_stride;
+      if (h->op.format == MPRK_FMT_CSR)
+        HIPCHK(h->eng->bj_setup_csr(c, (const double*)(h->ws + h->o_kval), h->sigmas[q], dinv, fail));
+      else
+        HIPCHK(h->eng->bj_setup_stencil(c, stage_coef(h->Kc, h->sigmas[q]), dinv, fail));
+    }
+  }
+  int hfail = 0;
+  HIPCHK(hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (hfail) return set_error(MPRK_EINVAL, "singular block-Jacobi block");
+  h->bound = true;
+  return MPRK_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// polling
+// ------------------------------------------------------------------------------------------
+
+int mprk_handle::poll_enqueue(int* slot) {
+  const int s = slot_next;
+  slot_next = (slot_next + 1) % NSLOT;
+  // the slot's previous copy must have landed before it is overwritten
+  if (slot_used[s]) HIPCHK(hipEventSynchronize(ev[s]));
+  HIPCHK(hipMemcpyAsync(&slots[s], ws + o_ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipEventRecord(ev[s], stream));
+  slot_used[s] = true;
+  *slot = s;
+  return MPRK_OK;
+}
+
+int mprk_handle::poll_wait(int s, CtlHead* out) {
+  HIPCHK(hipEventSynchronize(ev[s]));
+  std::atomic_thread_fence(std::memory_order_acquire);
+  std::memcpy(out, (const void*)&slots[s], sizeof(*out));
+  return MPRK_OK;
+}
+
+int mprk_handle::stage_record(int i) {
+  HIPCHK(hipMemcpyAsync(&slots[NSLOT + i], ws + o_ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, stream));
+  return MPRK_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// the stage solve (outer FP64 residual loop around the LP Krylov solve)
+// ------------------------------------------------------------------------------------------
+
+int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* kout) {
+  const SolveCfg& cfg = cfgs[si];
+  Ctl* ctl = (Ctl*)(ws + o_ctl);
+  double* part = (double*)(ws + o_part);
+  double* res = (double*)(ws + o_res);
+  const Csr csr{(const int*)(ws + o_rowptr), (const int*)(ws + o_col)};
+  const double* kval = (const double*)(ws + o_kval);
+  if (op.format == MPRK_FMT_CSR)
+    hipLaunchKernelGGL((k_residual<1, 1>), dim3(ln_row.G), dim3(TPB), 0, stream, ln_row, geo, Kc, csr,
+                       kval, y, rhs, kout, res, cfg, ctl, part, pstride);
+  else if (vec == 4)
+    hipLaunchKernelGGL((k_residual<4, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr,
+                       kval, y, rhs, kout, res, cfg, ctl, part, pstride);
+  else
+    hipLaunchKernelGGL((k_residual<1, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr,
+                       kval, y, rhs, kout, res, cfg, ctl, part, pstride);
+  HIPCHK(hipGetLastError());
+  return MPRK_OK;
+}
+
+int mprk_handle::run_solve(int si, const double* rhs, double* y, double* kout) {
+  const SolveCfg& cfg = cfgs[si];
+  EngineCtx c = ctx();
+  c.y = y;
+  const void* dinv = bs ? (const void*)(ws + o_dinv + si * dinv_stride) : nullptr;
+  const Coef<double> Mc = stage_coef(Kc, cfg.sigma);
+  const bool cg = prec.krylov == MPRK_CG;
+  const int P = cfg.paper_mode ? 1 : cfg.max_passes;
+  const int maxp = cfg.maxit;
+  const int chunk = cg ? cg_chunk : gm_chunk;
+  bool finished = false;
+  for (int pass = 0; pass <= P && !finished; ++pass) {
+    int rc = launch_residual(si, rhs, y, kout);
+    if (rc) return rc;
+    if (pass == P) break;
+    struct Pend {
+      int slot;
+      bool krylov;
+    };
+    std::deque<Pend> pend;
+    int slot = 0;
+    rc = poll_enqueue(&slot);
+    if (rc) return rc;
+    pend.push_back({slot, false});
+    if (cg) HIPCHK(eng->cg_begin(c, cfg, dinv));
+    else HIPCHK(eng->gm_begin(c, cfg));
+    int its = 0;
+    bool inner = false;
+    while (its < maxp && !inner && !finished) {
+      const int cnt = std::min(chunk, maxp - its);
+      for (int k = 0; k < cnt; ++k) {
+        if (cg) HIPCHK(eng->cg_iter(c, cfg, Mc, dinv, its + k));
+        else HIPCHK(eng->gm_iter(c, cfg, Mc, dinv));
+      }
+      its += cnt;
+      rc = poll_enqueue(&slot);
+      if (rc) return rc;
+      pend.push_back({slot, true});
+      while ((int)pend.size() > lookahead) {
+        const Pend pd = pend.front();
+        pend.pop_front();
+        CtlHead hd;
+        rc = poll_wait(pd.slot, &hd);
+        if (rc) return rc;
+        if (hd.outer_done) {
+          finished = true;
+          break;
+        }
+        if (pd.krylov && hd.inner_done) {
+          inner = true;
+          break;
+        }
+      }
+    }
+    if (finished) break;
+    if (cg) HIPCHK(eng->cg_finish(c));
+    else HIPCHK(eng->gm_finish(c, dinv));
+  }
+  return MPRK_OK;
+}
+
+int mprk_handle::enqueue_step() {
+  Ctl* ctl = (Ctl*)(ws + o_ctl);
+  double* rhs = (double*)(ws + o_rhs);
+  double* y = (double*)(ws + o_y);
+  auto kvec = [&](int j) { return (double*)(ws + o_k + (size_t)j * N * 8); };
+  auto evec = [&](int j) { return (double*)(ws + o_keps + (size_t)j * N * 8); };
+  const int s = nstages;
+  for (int i = 0; i < s; ++i) {
+    CombArgs a{};
+    a.nv = 0;
+    for (int j = 0; j < i; ++j) {
+      const double ah = tab.a_hi[i * s + j], al = tab.a_lo[i * s + j];
+      if (!implicit_[j]) {  // f^eps = f for an explicit stage
+        if (ah + al != 0.0) {
+          a.v[a.nv] = kvec(j);
+          a.c[a.nv++] = dt * (ah + al);
+        }
+        continue;
+      }
+      if (ah != 0.0) {
+        a.v[a.nv] = kvec(j);
+        a.c[a.nv++] = dt * ah;
+      }
+      if (al != 0.0) {
+        a.v[a.nv] = evec(j);
+        a.c[a.nv++] = dt * al;
+      }
+    }
+    const int reset = i == 0 ? 2 : 1;
+    if (vec == 4)
+      hipLaunchKernelGGL((k_stage_rhs<4>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, rhs, y, ctl, reset);
+    else
+      hipLaunchKernelGGL((k_stage_rhs<1>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, rhs, y, ctl, reset);
+    HIPCHK(hipGetLastError());
+    if (!implicit_[i]) {
+      int rc = launch_apply64(y, kvec(i), 0.0, 0);
+      if (rc) return rc;
+      continue;
+    }
+    int rc = run_solve(sig_idx[i], rhs, y, kvec(i));
+    if (rc) return rc;
+    rc = stage_record(i);
+    if (rc) return rc;
+    if (need_keps) {
+      const double inv = 1.0 / cfgs[sig_idx[i]].sigma;
+      if (vec == 4)
+        hipLaunchKernelGGL((k_keps<4>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, y, rhs, inv, evec(i));
+      else
+        hipLaunchKernelGGL((k_keps<1>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, y, rhs, inv, evec(i));
+      HIPCHK(hipGetLastError());
+    }
+  }
+  CombArgs a{};
+  a.nv = 0;
+  for (int i = 0; i < s; ++i)
+    if (tab.b[i] != 0.0) {
+      a.v[a.nv] = kvec(i);
+      a.c[a.nv++] = dt * tab.b[i];
+    }
+  if (vec == 4)
+    hipLaunchKernelGGL((k_combine<4>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, ctl);
+  else
+    hipLaunchKernelGGL((k_combine<1>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, ctl);
+  HIPCHK(hipGetLastError());
+  return MPRK_OK;
+}
+
+int mprk_handle::launch_apply64(const double* x, double* y, double sigma, int mode) {
+  const Csr csr{(const int*)(ws + o_rowptr), (const int*)(ws + o_col)};
+  const double* kval = (const double*)(ws + o_kval);
+  if (op.format == MPRK_FMT_CSR)
+    hipLaunchKernelGGL((k_apply64<1, 1>), dim3(ln_row.G), dim3(TPB), 0, stream, ln_row, geo, Kc, csr, kval,
+                       x, y, sigma, mode);
+  else if (vec == 4)
+    hipLaunchKernelGGL((k_apply64<4, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr, kval,
+                       x, y, sigma, mode);
+  else
+    hipLaunchKernelGGL((k_apply64<1, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr, kval,
+                       x, y, sigma, mode);
+  HIPCHK(hipGetLastError());
+  return MPRK_OK;
+}
+
+void mprk_handle::fill_stats(mprk_stats* st) {
+  std::memset(st, 0, sizeof(*st));
+  const CtlHead* hd = (const CtlHead*)slots;
+  st->stages = nstages;
+  for (int i = 0; i < nstages && hd; ++i) {
+    if (!implicit_[i]) {
+      st->converged[i] = 1;
+      continue;
+    }
+    const CtlHead& r = hd[NSLOT + i];
+    st->iters[i] = r.total_iters;
+    st->passes[i] = r.passes;
+    st->resid[i] = r.outer_rel;
+    st->converged[i] = r.converged && !r.nonfinite;
+  }
+  st->steps = step_count;
+  st->t = t_now;
+  st->total_iters = life_iters;
+  st->total_passes = life_passes;
+  st->nonfinite = last_nonfinite;
+}
+
+int mprk_handle::sync_counters() {
+  Ctl* ctl = (Ctl*)(ws + o_ctl);
+  long long lf[2];
+  CtlHead hd;
+  HIPCHK(hipMemcpyAsync(&hd, ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(lf, &ctl->life_iters, sizeof(lf), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const long long good = hd.good_steps - good_base;
+  const int bad = hd.bad_steps - bad_base;
+  good_base = hd.good_steps;
+  bad_base = hd.bad_steps;
+  step_count += good;
+  t_now += dt * (double)good;
+  life_iters = lf[0];
+  life_passes = lf[1];
+  last_nonfinite = bad > 0;
+  return bad > 0 ? MPRK_ENONFINITE : MPRK_OK;
+}
+
+extern "C" int32_t mprk_step(mprk_handle* h, int32_t nsteps, mprk_stats* stats) {
+  if (!h) return set_error(MPRK_EINVAL, "NULL handle");
+  if (!h->bound) return set_error(MPRK_ESTATE, "mprk_step before mprk_bind");
+  if (nsteps < 0) return set_error(MPRK_EINVAL, "nsteps must be >= 0");
+  for (int n = 0; n < nsteps; ++n) {
+    int rc = h->enqueue_step();
+    if (rc) return rc;
+  }
+  int rc = h->sync_counters();
+  if (stats) h->fill_stats(stats);
+  if (rc == MPRK_ENONFINITE) return set_error(rc, "non-finite residual: u left at the last completed step");
+  if (h->prec.strict) {
+    mprk_stats st;
+    h->fill_stats(&st);
+    for (int i = 0; i < h->nstages; ++i)
+      if (!st.converged[i]) return set_error(MPRK_ENOTCONV, "a stage missed outer_tol");
+  }
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_solve(mprk_handle* h, int32_t stage, const double* rhs_dev, double* x_dev,
+                              mprk_solve_info* info) {
+  if (!h || !rhs_dev || !x_dev) return set_error(MPRK_EINVAL, "NULL argument");
+  if (!h->bound) return set_error(MPRK_ESTATE, "mprk_solve before mprk_bind");
+  if (stage < 0 || stage >= h->nstages || !h->implicit_[stage])
+    return set_error(MPRK_EINVAL, "stage must be an implicit stage of the tableau");
+  Ctl* ctl = (Ctl*)(h->ws + h->o_ctl);
+  CombArgs a{};
+  a.nv = 0;
+  // x = rhs (initial guess), rhs copy into the workspace; resets the stage record
+  double* rhs = (double*)(h->ws + h->o_rhs);
+  if (h->vec == 4)
+    hipLaunchKernelGGL((k_stage_rhs<4>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, rhs_dev, a, rhs,
+                       x_dev, ctl, 1);
+  else
+    hipLaunchKernelGGL((k_stage_rhs<1>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, rhs_dev, a, rhs,
+                       x_dev, ctl, 1);
+  HIPCHK(hipGetLastError());
+  int rc = h->run_solve(h->sig_idx[stage], rhs, x_dev, (double*)(h->ws + h->o_scr));
+  if (rc) return rc;
+  CtlHead hd;
+  HIPCHK(hipMemcpyAsync(&hd, ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (info) {
+    info->iters = hd.total_iters;
+    info->passes = hd.passes;
+    info->converged = hd.converged && !hd.nonfinite;
+    info->resid = hd.outer_rel;
+  }
+  if (hd.nonfinite) return set_error(MPRK_ENONFINITE, "non-finite residual in mprk_solve");
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_apply(mprk_handle* h, int32_t which, int32_t stage, const void* x, void* y) {
+  if (!h || !x || !y) return set_error(MPRK_EINVAL, "NULL argument");
+  if (!h->bound) return set_error(MPRK_ESTATE, "mprk_apply before mprk_bind");
+  double sigma = 0.0;
+  int si = -1;
+  if (which != MPRK_APPLY_K64) {
+    if (stage < 0 || stage >= h->nstages || !h->implicit_[stage])
+      return set_error(MPRK_EINVAL, "stage must be an implicit stage of the tableau");
+    si = h->sig_idx[stage];
+    sigma = h->sigmas[si];
+  }
+  EngineCtx c = h->ctx();
+  switch (which) {
+    case MPRK_APPLY_K64: {
+      int rc = h->launch_apply64((const double*)x, (double*)y, 0.0, 0);
+      if (rc) return rc;
+      break;
+    }
+    case MPRK_APPLY_M64: {
+      int rc = h->launch_apply64((const double*)x, (double*)y, sigma, 1);
+      if (rc) return rc;
+      break;
+    }
+    case MPRK_APPLY_M_LP:
+      HIPCHK(h->eng->apply_m(c, stage_coef(h->Kc, sigma), sigma, x, y));
+      break;
+    case MPRK_APPLY_BJ_LP:
+      if (!h->bs) return set_error(MPRK_EINVAL, "no block-Jacobi preconditioner configured");
+      HIPCHK(h->eng->apply_bj(c, h->ws + h->o_dinv + si * h->dinv_stride, x, y));
+      break;
+    default:
+      return set_error(MPRK_EINVAL, "unknown apply op");
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_get_state(const mprk_handle* h, double* t, int64_t* step) {
+  if (!h) return set_error(MPRK_EINVAL, "NULL handle");
+  if (h->bound) HIPCHK(hipStreamSynchronize(h->stream));
+  if (t) *t = h->t_now;
+  if (step) *step = h->step_count;
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_set_state(mprk_handle* h, double t, int64_t step) {
+  if (!h) return set_error(MPRK_EINVAL, "NULL handle");
+  if (!std::isfinite(t) || step < 0) return set_error(MPRK_EINVAL, "bad state");
+  h->t_now = t;
+  h->step_count = step;
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_stats_sync(mprk_handle* h, mprk_stats* out) {
+  if (!h || !out) return set_error(MPRK_EINVAL, "NULL argument");
+  if (h->bound) HIPCHK(hipStreamSynchronize(h->stream));
+  h->fill_stats(out);
+  return MPRK_OK;
+}
+
+extern "C" const char* mprk_last_error(void) { return g_err.c_str(); }
+
+extern "C" void mprk_destroy(mprk_handle* h) { delete h; }

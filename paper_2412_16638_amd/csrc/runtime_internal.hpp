@@ -1,0 +1,97 @@
+// runtime_internal.hpp -- host-side handle of one problem (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mprk.h"
+#include "engine.hpp"
+
+namespace mprk {
+
+int set_error(int code, const std::string& msg);
+Launch make_launch(long ng);
+Coef<double> operator_coef(const mprk_grid& g, const mprk_operator& op);
+Coef<double> stage_coef(const Coef<double>& K, double sigma);
+long csr_count(const Geo& geo, const Coef<double>& K, double* maxabs);
+void assemble_csr(const Geo& geo, const Coef<double>& K, std::vector<int>& rowptr,
+                  std::vector<int>& col, std::vector<double>& val);
+
+constexpr int NSLOT = 64;  // pinned poll slots
+
+}  // namespace mprk
+
+struct mprk_handle {
+  // problem
+  mprk_grid grid{};
+  mprk_operator op{};
+  mprk_tableau tab{};
+  mprk_precisions prec{};
+  double dt = 0.0;
+  hipStream_t stream = nullptr;
+  mprk::Geo geo{};
+  int N = 0;
+  int vec = 1;
+  mprk::Coef<double> Kc{};
+  std::unique_ptr<mprk::Engine> eng;
+  int lp_bytes = 8;
+  int nstages = 0;
+  bool implicit_[MPRK_MAX_STAGES] = {};
+  int sig_idx[MPRK_MAX_STAGES] = {};
+  std::vector<double> sigmas;
+  std::vector<mprk::SolveCfg> cfgs;
+  bool need_keps = false;
+  // launch shapes
+  mprk::Launch ln_vec{}, ln_row{};
+  int pstride = 8;
+  int bs = 0;
+  int nblk = 0;
+  long nnz = 0;
+  double kscale = 1.0;
+  // workspace layout (byte offsets)
+  size_t o_rhs = 0, o_y = 0, o_res = 0, o_k = 0, o_keps = 0, o_scr = 0;
+  size_t o_r = 0, o_z = 0, o_p0 = 0, o_p1 = 0, o_q = 0, o_x = 0, o_V = 0;
+  size_t vstride = 0;
+  size_t o_dinv = 0, dinv_stride = 0;
+  size_t o_rowptr = 0, o_col = 0, o_kval = 0, o_mval = 0;
+  size_t o_ctl = 0, o_flag = 0, o_part = 0;
+  size_t ws_bytes = 0;
+  // binding
+  double* u = nullptr;
+  char* ws = nullptr;
+  bool bound = false;
+  // host steering
+  mprk::CtlHead* slots = nullptr;   // pinned: NSLOT poll slots + one record per stage
+  hipEvent_t ev[mprk::NSLOT] = {};
+  bool slot_used[mprk::NSLOT] = {};
+  bool events_made = false;
+  int slot_next = 0;
+  int cg_chunk = 4;
+  int gm_chunk = 2;
+  int lookahead = 1;
+  // state
+  double t_now = 0.0;
+  long long step_count = 0;
+  long long good_base = 0;
+  int bad_base = 0;
+  long long life_iters = 0, life_passes = 0;
+  int last_nonfinite = 0;
+
+  int init(const mprk_grid& g, const mprk_operator& o, const mprk_tableau& t,
+           const mprk_precisions& p, double dt_, hipStream_t s);
+  ~mprk_handle();
+  int make_device_resources();
+  mprk::EngineCtx ctx() const;
+  int poll_enqueue(int* slot);
+  int poll_wait(int s, mprk::CtlHead* out);
+  int stage_record(int i);
+  int launch_residual(int si, const double* rhs, double* y, double* kout);
+  int launch_apply64(const double* x, double* y, double sigma, int mode);
+  int run_solve(int si, const double* rhs, double* y, double* kout);
+  int enqueue_step();
+  int sync_counters();
+  void fill_stats(mprk_stats* st);
+};

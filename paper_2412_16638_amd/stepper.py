@@ -1,0 +1,120 @@
+"""Torch-memory plumbing around the C ABI: one problem = one handle + two device tensors.
+
+PyTorch supplies only device memory (the FP64 state u and one workspace blob) and the HIP
+stream; every arithmetic step runs in libmprk.so.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+TABLEAUS = {'SDIRK2': (A.TAB_SDIRK2, 0), 'SDIRK3': (A.TAB_SDIRK3, 0), '4S3PA': (A.TAB_4S3PA, 0),
+            '4S3PB': (A.TAB_4S3PB, 0), '4S3PC': (A.TAB_4S3PC, 0)}
+STORAGE = {'fp64': A.FP64, 'fp32': A.FP32, 'fp16': A.FP16}
+KRYLOV = {'cg': A.CG, 'gmres': A.GMRES}
+LP_DTYPE = {A.FP64: torch.float64, A.FP32: torch.float32, A.FP16: torch.float16}
+
+
+def tableau(name: str) -> A.mprk_tableau:
+    name = name.upper()
+    if name.startswith('MID'):
+        return A.mprk_tableau_builtin(A.TAB_MID, int(name[3:] or 0))
+    tid, param = TABLEAUS[name]
+    return A.mprk_tableau_builtin(tid, param)
+
+
+def precisions(storage: str = 'fp64', krylov: str = 'cg', **overrides) -> A.mprk_precisions:
+    p = A.mprk_precisions_default(STORAGE[storage], KRYLOV[krylov])
+    for k, v in overrides.items():
+        if k == 'precond':
+            v = {'none': A.PRECOND_NONE, 'bj': A.PRECOND_BJ}.get(v, v)
+        setattr(p, k, v)
+    return p
+
+
+class Stepper:
+    """One time-integration problem bound to torch-owned device memory."""
+
+    def __init__(self, shape, bc: int, kind: int, diff: float, b=(0.0, 0.0, 0.0),
+                 fmt: int = A.FMT_STENCIL, tab='SDIRK3', prec=None, dt: float = 1e-3,
+                 device: str = 'cuda:0'):
+        if not torch.cuda.is_available():
+            raise RuntimeError('mprk needs a HIP device (torch.cuda.is_available() is False)')
+        if isinstance(shape, int):
+            shape = (shape, shape, shape)
+        self.shape = tuple(int(s) for s in shape)
+        self.N = self.shape[0] * self.shape[1] * self.shape[2]
+        self.device = torch.device(device)
+        self.grid = A.mprk_grid(self.shape[0], self.shape[1], self.shape[2], bc)
+        self.op = A.mprk_operator(kind, fmt, diff, (A.C.c_double * 3)(*b))
+        self.tab = tableau(tab) if isinstance(tab, str) else tab
+        self.prec = prec if prec is not None else precisions()
+        self.dt = dt
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.h = A.mprk_create(self.grid, self.op, self.tab, self.prec, dt, self.stream.cuda_stream)
+            self.ws_bytes = A.mprk_workspace_bytes(self.h)
+            self.u = torch.zeros(self.N, dtype=torch.float64, device=self.device)
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            A.mprk_bind(self.h, self.u.data_ptr(), self.ws.data_ptr(), self.ws_bytes)
+
+    @property
+    def lp_dtype(self):
+        return LP_DTYPE[self.prec.storage]
+
+    def set_u(self, u) -> None:
+        if isinstance(u, np.ndarray):
+            u = torch.from_numpy(np.ascontiguousarray(u, dtype=np.float64).ravel())
+        self.u.copy_(u.reshape(-1).to(self.device, torch.float64))
+        torch.cuda.synchronize(self.device)
+
+    def get_u(self) -> np.ndarray:
+        torch.cuda.synchronize(self.device)
+        return self.u.detach().cpu().numpy().reshape(self.shape[2], self.shape[1], self.shape[0])
+
+    def step(self, nsteps: int = 1, check: bool = True):
+        rc, st = A.mprk_step(self.h, nsteps, True)
+        if check:
+            A.check(rc, 'mprk_step')
+        return (rc, st) if not check else st
+
+    def solve(self, stage: int, rhs: torch.Tensor):
+        x = torch.empty_like(rhs)
+        rc, info = A.mprk_solve(self.h, stage, rhs.data_ptr(), x.data_ptr())
+        A.check(rc, 'mprk_solve')
+        return x, info
+
+    def apply(self, which: int, x: torch.Tensor, stage: int = 0) -> torch.Tensor:
+        y = torch.empty_like(x)
+        A.mprk_apply(self.h, which, stage, x.data_ptr(), y.data_ptr())
+        return y
+
+    def state(self):
+        return A.mprk_get_state(self.h)
+
+    def set_state(self, t: float, step: int) -> None:
+        A.mprk_set_state(self.h, t, step)
+
+    def close(self) -> None:
+        if getattr(self, 'h', None):
+            A.mprk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def from_problem(p, fmt: int = A.FMT_STENCIL, prec=None, device: str = 'cuda:0', **prec_overrides):
+    """Stepper for a problem description with fields n, bc, kind, diff, b, tableau, dt,
+    precision, krylov, precond (e.g. a workloads.Problem); u is initialised from p.u0."""
+    if prec is None:
+        prec = precisions(p.precision, p.krylov, precond=p.precond, **prec_overrides)
+    s = Stepper(p.n, p.bc, p.kind, p.diff, p.b, fmt, p.tableau, prec, p.dt, device)
+    if p.u0 is not None:
+        s.set_u(p.u0)
+    return s

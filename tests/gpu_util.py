@@ -1,0 +1,30 @@
+"""Helpers shared by the GPU tests (input preparation and oracle evaluation only)."""
+import numpy as np
+
+import workloads as W
+from oracle import closed_form, dirk, operators, tableaus
+
+
+def oracle_K(shape, bc, kind, diff, b):
+    return operators.operator(shape, bc, kind, diff, b)
+
+
+def oracle_tableau(name):
+    return tableaus.by_name(name)
+
+
+def reference_solution(p, method='closed'):
+    """FP64 oracle u_N for a workloads.Problem (closed form where one exists)."""
+    tab = tableaus.by_name(p.tableau)
+    if method == 'closed':
+        return closed_form.evolve(p.u0, p.kind, p.bc, p.diff, p.b, p.dt, p.nsteps, tab)
+    K = oracle_K((p.n,) * 3, p.bc, p.kind, p.diff, p.b)
+    return dirk.integrate(K, p.u0, p.dt, p.nsteps, tab, method).reshape(p.u0.shape)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def log_case(case_name, **kw):
+    print(f'[gpu-case] {case_name} ' + ' '.join(f'{k}={v}' for k, v in kw.items()), flush=True)

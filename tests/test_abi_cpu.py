@@ -1,0 +1,124 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared entry point, and the
+host-only calls (builtin tableaus, defaults, validation, workspace sizing) behave."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, 'include', 'mprk.h')
+
+A = pytest.importorskip('paper_2412_16638_amd._abi')
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)
+    return sorted(set(re.findall(r'\b(mprk_[a-z_0-9]+)\s*\(', text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(A.lib, n), n
+    assert set(names) == set(A.EXPORTED)
+
+
+def test_builtin_tableaus_equal_oracle_tableaus():
+    # two independent transcriptions of the paper's tables (C library vs oracle)
+    from oracle import tableaus as T
+    pairs = [(A.TAB_SDIRK2, 0, T.sdirk2()), (A.TAB_SDIRK3, 0, T.sdirk3()),
+             (A.TAB_4S3PA, 0, T.s4p3a()), (A.TAB_4S3PB, 0, T.s4p3b()), (A.TAB_4S3PC, 0, T.s4p3c()),
+             (A.TAB_MID, 0, T.mid(0)), (A.TAB_MID, 3, T.mid(3))]
+    for tid, par, ref in pairs:
+        t = A.mprk_tableau_builtin(tid, par)
+        s = t.s
+        assert s == ref.s
+        hi = np.array(t.a_hi[:s * s]).reshape(s, s)
+        lo = np.array(t.a_lo[:s * s]).reshape(s, s)
+        np.testing.assert_allclose(hi, ref.A_hi, atol=2e-15, rtol=0)
+        np.testing.assert_allclose(lo, ref.A_lo, atol=2e-15, rtol=0)
+        np.testing.assert_allclose(np.array(t.b[:s]), ref.b, atol=2e-15, rtol=0)
+
+
+def _create(grid=(16, 16, 16), bc=0, kind=0, diff=1.0, b=(0, 0, 0), fmt=0, tab=None, prec=None,
+            dt=1e-3):
+    g = A.mprk_grid(*grid, bc)
+    o = A.mprk_operator(kind, fmt, diff, (C.c_double * 3)(*b))
+    t = tab or A.mprk_tableau_builtin(A.TAB_SDIRK3)
+    p = prec or A.mprk_precisions_default(A.FP32, A.CG)
+    h = C.c_void_p()
+    rc = A.lib.mprk_create(C.byref(g), C.byref(o), C.byref(t), C.byref(p), dt, None, C.byref(h))
+    return rc, h
+
+
+def test_create_and_workspace_bytes_on_host():
+    rc, h = _create()
+    assert rc == A.OK
+    n = A.lib.mprk_workspace_bytes(h)
+    N = 16 ** 3
+    # 3 + s FP64 vectors + scratch, 6 FP32 Krylov vectors, BJ inverses (8 per row, FP32)
+    assert n >= (3 + 3 + 1) * N * 8 + 6 * N * 4 + N * 8 * 4
+    A.lib.mprk_destroy(h)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(grid=(0, 4, 4)),
+    dict(bc=7),
+    dict(kind=1, b=(1.0, 0, 0)),            # CG on a nonsymmetric operator
+    dict(dt=-1.0),
+    dict(diff=float('nan')),
+])
+def test_create_rejects_invalid_problems(bad):
+    rc, h = _create(**bad)
+    assert rc == A.EINVAL, A.mprk_last_error()
+    assert h.value is None
+
+
+def test_create_rejects_upper_triangular_tableau():
+    t = A.mprk_tableau_builtin(A.TAB_SDIRK2)
+    t.a_hi[1] = 0.3   # entry (0, 1)
+    rc, _ = _create(tab=t)
+    assert rc == A.EINVAL
+    assert 'lower triangular' in A.mprk_last_error()
+
+
+def test_create_rejects_bad_precisions():
+    p = A.mprk_precisions_default(A.FP16, A.CG)
+    p.compute = A.FP64
+    rc, _ = _create(prec=p)
+    assert rc == A.EUNSUPPORTED
+    p = A.mprk_precisions_default(A.FP32, A.GMRES)
+    p.restart = 99
+    rc, _ = _create(prec=p, kind=1, b=(1.0, 0, 0))
+    assert rc == A.EINVAL
+    p = A.mprk_precisions_default(A.FP32, A.CG)
+    p.block = 3
+    rc, _ = _create(prec=p)
+    assert rc == A.EINVAL
+
+
+def test_step_before_bind_is_a_state_error():
+    rc, h = _create()
+    st = A.mprk_stats()
+    assert A.lib.mprk_step(h, 1, C.byref(st)) == A.ESTATE
+    A.lib.mprk_destroy(h)
+
+
+def test_builtin_rejects_unknown_ids():
+    t = A.mprk_tableau()
+    assert A.lib.mprk_tableau_builtin(99, 0, C.byref(t)) == A.EINVAL
+    assert A.lib.mprk_tableau_builtin(A.TAB_MID, 8, C.byref(t)) == A.EINVAL
+
+
+def test_csr_workspace_accounts_for_exact_nnz():
+    rc1, h1 = _create(grid=(8, 8, 8), fmt=0)
+    rc2, h2 = _create(grid=(8, 8, 8), fmt=1)
+    extra = A.lib.mprk_workspace_bytes(h2) - A.lib.mprk_workspace_bytes(h1)
+    nnz = 7 * 512 - 6 * 64
+    assert extra >= nnz * (4 + 8 + 4) + 513 * 4
+    A.lib.mprk_destroy(h1)
+    A.lib.mprk_destroy(h2)

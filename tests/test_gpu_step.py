@@ -1,0 +1,167 @@
+"""Time-step parity through the C ABI (mprk_step) against the FP64 oracle.
+
+Tolerances: relative L2 over the grid at the final time, <= 1e-12 for the all-FP64 path,
+<= 1e-6 with FP32 stage solves, <= 1e-3 with FP16 storage.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests.gpu_util import log_case, reference_solution, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+M = pytest.importorskip('paper_2412_16638_amd')
+A = M._abi
+
+TOL = {'fp64': 1e-12, 'fp32': 1e-6, 'fp16': 1e-3}
+
+
+def run(p, fmt=A.FMT_STENCIL, **over):
+    st = M.from_problem(p, fmt=fmt, **over)
+    stats = st.step(p.nsteps)
+    u = st.get_u()
+    st.close()
+    return u, stats
+
+
+@pytest.mark.parametrize("fmt", [A.FMT_CSR, A.FMT_STENCIL])
+def test_heat_sine_16_fp64_unpreconditioned_cg(fmt):
+    # 16^3 interior grid, SDIRK2, dt 1e-3, 10 steps, all FP64, CG to rel. residual 1e-12
+    p = W.heat_sine_16()
+    log_case('heat_sine_16', fmt=fmt)
+    u, stats = run(p, fmt, rtol=1e-12, outer_tol=1e-12)
+    ref = reference_solution(p)
+    err = rel_l2(u, ref)
+    print('rel-L2', err, stats)
+    assert err <= TOL['fp64']
+    assert stats['steps'] == 10
+
+
+@pytest.mark.parametrize("fmt", [A.FMT_CSR, A.FMT_STENCIL])
+def test_heat_random_16_fp64_cg_genuinely_iterates(fmt):
+    p = W.heat_sine_16()
+    p.u0 = W.random_field(16, 7)
+    log_case('heat_random_16', fmt=fmt)
+    u, stats = run(p, fmt, rtol=1e-12, outer_tol=1e-12)
+    err = rel_l2(u, reference_solution(p))
+    assert min(stats['iters']) > 5
+    assert err <= TOL['fp64'], err
+
+
+@pytest.mark.parametrize("storage", ['fp64', 'fp32', 'fp16'])
+@pytest.mark.parametrize("fmt", [A.FMT_STENCIL, A.FMT_CSR])
+def test_heat_modes_small(storage, fmt):
+    # the 128^3 heat workload's recipe on 24^3 and 8 steps (mixed: BJ(8) PCG)
+    p = W.heat_modes(n=24, nsteps=8)
+    p.precision = storage
+    log_case('heat_modes_24', storage=storage, fmt=fmt)
+    u, stats = run(p, fmt)
+    err = rel_l2(u, reference_solution(p))
+    print(storage, err, stats)
+    assert err <= TOL[storage], err
+
+
+@pytest.mark.parametrize("storage", ['fp64', 'fp32', 'fp16'])
+@pytest.mark.parametrize("fmt", [A.FMT_STENCIL, A.FMT_CSR])
+def test_advdiff_bump_small(storage, fmt):
+    # the 256^3 advection-diffusion recipe on 32^3 and 5 steps (GMRES(30) + BJ(8))
+    p = W.advdiff_bump(n=32, nsteps=5)
+    p.precision = storage
+    log_case('advdiff_bump_32', storage=storage, fmt=fmt)
+    u, stats = run(p, fmt)
+    err = rel_l2(u, reference_solution(p))
+    print(storage, err, stats)
+    assert err <= TOL[storage], err
+
+
+@pytest.mark.parametrize("name", ['4S3PA', '4S3PB', '4S3PC', 'MID2', 'SDIRK2'])
+@pytest.mark.parametrize("storage", ['fp64', 'fp32'])
+def test_paper_tableaus_periodic(name, storage):
+    p = W.advdiff_bump(n=16, nsteps=4, dt=2e-3)
+    p.tableau = name
+    p.precision = storage
+    log_case('tableau', name=name, storage=storage)
+    u, stats = run(p)
+    err = rel_l2(u, reference_solution(p))
+    print(name, storage, err)
+    assert err <= TOL[storage], err
+
+
+@pytest.mark.parametrize("name", ['4S3PB', '4S3PC', 'MID1'])
+def test_paper_tableaus_heat_fp64(name):
+    p = W.heat_modes(n=12, nsteps=3)
+    p.tableau = name
+    p.precision = 'fp64'
+    log_case('tableau_heat', name=name)
+    u, _ = run(p)
+    assert rel_l2(u, reference_solution(p)) <= TOL['fp64']
+
+
+def test_ragged_grid_vec1_path():
+    # nx % 4 != 0 (scalar groups) and N % 8 != 0 (short last block-Jacobi block)
+    p = W.heat_modes(n=13, nsteps=3)
+    log_case('ragged13')
+    u, _ = run(p)
+    assert rel_l2(u, reference_solution(p)) <= TOL['fp32']
+
+
+def test_paper_mode_one_shot_solve_runs_and_is_close():
+    # refine_max = 0: one LP solve per stage, no FP64 residual loop (the paper's conversion)
+    p = W.heat_modes(n=16, nsteps=4)
+    log_case('paper_mode')
+    u, stats = run(p, refine_max=0, rtol=1e-6)
+    assert all(x == 1 for x in stats['passes'])
+    assert rel_l2(u, reference_solution(p)) <= 1e-4
+
+
+def test_zero_initial_state_stays_zero():
+    p = W.heat_modes(n=16, nsteps=2)
+    p.u0 = np.zeros_like(p.u0)
+    log_case('zero_u0')
+    u, stats = run(p)
+    assert np.all(u == 0.0)
+
+
+def test_bitwise_reproducible():
+    p = W.advdiff_bump(n=24, nsteps=2)
+    log_case('repro')
+    u1, _ = run(p)
+    u2, _ = run(p)
+    assert np.array_equal(u1, u2)
+
+
+def test_nonfinite_state_is_reported_and_u_kept():
+    p = W.heat_modes(n=16, nsteps=2)
+    log_case('nonfinite')
+    st = M.from_problem(p)
+    u = p.u0.copy().ravel()
+    u[100] = np.nan
+    st.set_u(u)
+    before = st.get_u().copy()
+    rc, stats = st.step(2, check=False)
+    after = st.get_u()
+    assert rc == A.ENONFINITE
+    assert stats['nonfinite'] == 1 and stats['steps'] == 0
+    assert np.array_equal(np.isnan(before), np.isnan(after))
+    assert np.array_equal(np.nan_to_num(before), np.nan_to_num(after))
+    st.close()
+
+
+def test_state_counters_and_resume_match():
+    p = W.heat_modes(n=16, nsteps=4)
+    log_case('resume')
+    st = M.from_problem(p)
+    st.step(2)
+    mid = st.get_u().copy()
+    t, k = st.state()
+    assert k == 2 and abs(t - 2 * p.dt) < 1e-15
+    st.step(2)
+    full = st.get_u().copy()
+    st.set_u(mid)
+    st.set_state(t, k)
+    st.step(2)
+    assert np.array_equal(st.get_u(), full)
+    assert st.state()[1] == 4
+    st.close()
