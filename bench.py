@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Benchmark: DOF-steps/s of mixed-precision DIRK time stepping on one MI355X.
+
+Workload (default): 256^3 periodic upwind advection-diffusion (nu = 1e-2, b = (1, 0.5, 0.25)),
+seeded Gaussian bump, SDIRK3, dt = 2e-3; implicit stages by GMRES(30) + block-Jacobi(8) with
+FP16 storage / FP32 arithmetic inside the FP64 residual loop; FP64 explicit corrections and
+step combination; matrix-free stencil.  One bench "step" is one Runge--Kutta time step of the
+whole grid.  Also reported: the error of a full 20-step integration against the FP64 oracle,
+the all-FP64 GPU path at matched error, the dominant kernel against the HBM roofline (HIP
+events on the library's stream), and the oracle's own time on the host (cpu_baseline).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-steps/s mixed vs FP64 at matched error; % peak HBM; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print('[bench]', *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ('device.hpp', 'kernels.hpp', 'engine.hpp'):
+        with open(os.path.join(ROOT, 'paper_2412_16638_amd', 'csrc', f), 'rb') as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, units: int,
+                      nv_total: int = 0) -> float:
+    """Bytes each kernel class must move per its definition (each array touched once; halos
+    and reduction partials not counted).  s = LP storage bytes, m = LP matrix bytes, bs = block."""
+    inv = bs * m  # block-Jacobi inverse row per unknown
+    pre = (inv + s) if bs else 0  # fused block-Jacobi: inverse row read + preconditioned write
+    if kc == 'gm_matvec':
+        return N * (worked * (s + s) + units * s)
+    if kc == 'gm_orth':
+        return N * (worked * (s + s + pre) + units * s)
+    if kc == 'gm_finish':
+        return N * (worked * (inv + 16) + units * s)
+    if kc == 'gm_begin':
+        return N * worked * (8 + s + pre)
+    if kc == 'residual':
+        return N * worked * 32
+    if kc == 'cg_begin':
+        return N * worked * (8 + s + (inv + s if bs else 0))
+    if kc == 'cg_dir':
+        return N * worked * 4 * s
+    if kc == 'cg_upd':
+        return N * worked * (7 * s + inv)
+    if kc == 'promote':
+        return N * worked * (16 + s)
+    if kc == 'stage_rhs':
+        return N * 8 * (worked * 3 + nv_total)
+    if kc == 'combine':
+        return N * 8 * (worked * 2 + nv_total)
+    return 0.0
+
+
+def make_problem(name: str):
+    import workloads as W
+    if name == 'advdiff256':
+        return W.advdiff_bump()
+    if name == 'heat128':
+        return W.heat_modes()
+    raise SystemExit(f'unknown workload {name}')
+
+
+def oracle_reference(p):
+    """Exact FP64 DIRK result of the full integration, by the oracle's modal closed form."""
+    from oracle import closed_form, tableaus
+    tab = tableaus.by_name(p.tableau)
+    t0 = time.perf_counter()
+    ref = closed_form.evolve(p.u0, p.kind, p.bc, p.diff, p.b, p.dt, p.nsteps, tab)
+    return ref, time.perf_counter() - t0
+
+
+def run_integration(M, p, fmt, **over):
+    st = M.from_problem(p, fmt=fmt, **over)
+    stats = st.step(p.nsteps)
+    u = st.get_u()
+    st.close()
+    return u, stats
+
+
+def time_steps(st, u0, K: int, W: int, profile: bool = False):
+    import torch
+    st.set_u(u0)
+    st.set_state(0.0, 0)
+    if W:
+        st.step(W)
+    torch.cuda.synchronize()
+    from paper_2412_16638_amd import _abi as AB
+    if profile:
+        AB.mprk_profile(st.h, True)
+    t0 = time.perf_counter()
+    stats = st.step(K)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = None
+    if profile:
+        AB.mprk_profile(st.h, False)
+        prof = {name: AB.mprk_profile_read(st.h, i) for i, name in enumerate(AB.KC_NAMES)}
+    return dt, stats, prof
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=20)
+    ap.add_argument('--warmup', type=int, default=3)
+    ap.add_argument('--workload', default='advdiff256', choices=['advdiff256', 'heat128'])
+    ap.add_argument('--fmt', default='stencil', choices=['stencil', 'csr'])
+    ap.add_argument('--no-fp64', action='store_true', help='skip the FP64 matched-error leg')
+    ap.add_argument('--no-cpu', action='store_true', help='skip the oracle / cpu_baseline leg')
+    ap.add_argument('--calib-copy', type=int, default=0, metavar='MIB',
+                    help='first run a plain device copy of this many MiB (counter calibration)')
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
+        print('bench.py measures one GPU: this build has no multi-GPU path (each problem runs on '
+              'one device; sharding is a design note only). Run with --gpus 1.', file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2412_16638_amd as M
+    from paper_2412_16638_amd import _abi as AB
+
+    assert torch.cuda.is_available(), 'bench.py needs a GPU'
+    fmt = AB.FMT_STENCIL if args.fmt == 'stencil' else AB.FMT_CSR
+    if args.calib_copy:
+        n = args.calib_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device='cuda')
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f'calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written')
+        del src, dst
+    p = make_problem(args.workload)
+    N = p.N
+    K, Wm = args.steps, args.warmup
+    log(f'workload {args.workload}: N={N} ({p.n}^3), {p.tableau}, dt={p.dt}, {p.krylov}, '
+        f'{p.precision} storage, fmt={args.fmt}')
+
+    # ---- oracle reference of the full integration (also the cpu_baseline sample) ----
+    ref, t_oracle = (None, None)
+    if not args.no_cpu:
+        log('oracle: exact modal evaluation of the full integration ...')
+        ref, t_oracle = oracle_reference(p)
+        log(f'oracle done in {t_oracle:.1f} s')
+
+    # ---- mixed path: parity run of the full integration ----
+    log('mixed path: full integration for the error check ...')
+    u_mixed, st_mixed = run_integration(M, p, fmt)
+    err_mixed = None
+    if ref is not None:
+        err_mixed = float(np.linalg.norm(u_mixed - ref) / np.linalg.norm(ref))
+        log(f'mixed rel-L2 vs oracle = {err_mixed:.3e}  iters/stage={st_mixed["iters"]} '
+            f'passes/stage={st_mixed["passes"]}')
+
+    # ---- timed mixed run ----
+    st = M.from_problem(p, fmt=fmt)
+    t_mixed, stats, _ = time_steps(st, p.u0, K, Wm)
+    value = N * K / t_mixed
+    log(f'mixed: {K} steps in {t_mixed * 1e3:.2f} ms -> {value:.4e} DOF-steps/s')
+
+    # ---- roofline pass (per-kernel HIP events on the library stream) ----
+    t_prof, _, prof = time_steps(st, p.u0, K, 1, profile=True)
+    s_bytes = {'fp64': 8, 'fp32': 4, 'fp16': 2}[p.precision]
+    bs = st.prec.block if st.prec.precond == AB.PRECOND_BJ else 0
+    nv = {'stage_rhs': 3, 'combine': 3}  # SDIRK3: sum over stages of rhs terms; b has 3 terms
+    rows = []
+    for kc, r in prof.items():
+        if r['launches'] == 0:
+            continue
+        nv_total = 0
+        if kc == 'stage_rhs':
+            nv_total = r['worked'] // p_stages(p) * nv['stage_rhs']
+        if kc == 'combine':
+            nv_total = r['worked'] * nv['combine']
+        b = algorithmic_bytes(kc, N, s_bytes, s_bytes, bs, r['worked'], r['units'], nv_total)
+        rows.append((kc, r, b))
+    total_ms = sum(r['ms'] for _, r, _ in rows)
+    dom = max(rows, key=lambda x: x[1]['ms'])
+    kc, r, b = dom
+    avg_ms = r['ms'] / r['launches']
+    bytes_per_launch = b / max(r['worked'], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    kernel_table = {k: {'launches': rr['launches'], 'worked': rr['worked'],
+                        'ms': round(rr['ms'], 3),
+                        'share': round(rr['ms'] / total_ms, 4) if total_ms else None,
+                        'GBps': round(bb / (rr['ms'] * 1e-3) / 1e9, 1) if rr['ms'] else None}
+                    for k, rr, bb in rows}
+    log('per-kernel: ' + json.dumps(kernel_table))
+    traffic = None
+    tpath = os.path.join(ROOT, 'profiles', f'traffic_{kc}_{args.workload}.json')
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            tr = json.load(fh)
+        if tr.get('kernel_hash') == kernel_source_hash():
+            traffic = tr.get('bytes_per_launch')
+    roofline = {'bound': 'hbm', 'kernel': kc, 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS,
+                'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4), 'traffic': traffic,
+                'bytes_per_launch': bytes_per_launch, 'avg_launch_us': round(avg_ms * 1e3, 2),
+                'launches': r['launches'], 'worked': r['worked'],
+                'all_kernels_GBps': round(sum(bb for _, _, bb in rows) / (total_ms * 1e-3) / 1e9, 1)}
+    st.close()
+
+    # ---- FP64 path at matched error ----
+    fp64 = None
+    if not args.no_fp64 and ref is not None:
+        for tol in (1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8, 1e-9, 1e-10):
+            over = dict(rtol=tol, outer_tol=tol)
+            q = make_problem(args.workload)
+            q.precision = 'fp64'
+            u64, s64 = run_integration(M, q, fmt, **over)
+            e64 = float(np.linalg.norm(u64 - ref) / np.linalg.norm(ref))
+            log(f'fp64 rtol={tol:.0e}: rel-L2 {e64:.3e} iters/stage={s64["iters"]}')
+            if e64 <= err_mixed:
+                st64 = M.from_problem(q, fmt=fmt, **over)
+                t64, _, _ = time_steps(st64, q.u0, K, Wm)
+                st64.close()
+                v64 = N * K / t64
+                fp64 = {'value': v64, 'rtol': tol, 'err_vs_oracle': e64,
+                        'ms_per_step': t64 * 1e3 / K}
+                log(f'fp64 matched: {v64:.4e} DOF-steps/s; mixed speedup {value / v64:.2f}x')
+                break
+
+    cpu = None
+    if t_oracle is not None:
+        cpu = {'value': N * p.nsteps / t_oracle, 'unit': 'DOF-steps/s', 'cores': 1,
+               'kind': 'oracle',
+               'sample': f'the full {p.nsteps}-step {p.n}^3 integration, evaluated by the FP64 '
+                         f'oracle through its exact modal closed form (scipy.fft, 1 worker; '
+                         f'{t_oracle:.1f} s on {os.cpu_count()} host cores, single-threaded)'}
+
+    out = {
+        'metric': METRIC, 'value': value, 'unit': 'DOF-steps/s', 'n_gpus': 1, 'steps': K,
+        'warmup': Wm, 'ms_per_step': t_mixed * 1e3 / K, 'higher_is_better': True,
+        'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f32',
+        'data': 'synthetic',
+        'config': {'workload': ('advdiff_upwind_periodic_256^3_sdirk3_dt2e-3_gmres30_bj8_fp16'
+                                if args.workload == 'advdiff256'
+                                else 'heat_dirichlet_128^3_sdirk3_dt5e-4_cg_bj8_fp32'),
+                   'N': N, 'format': args.fmt, 'lp_storage': p.precision, 'lp_compute': 'f32',
+                   'explicit_parts': 'f64', 'krylov': p.krylov},
+        'err_vs_oracle': err_mixed,
+        'iters_per_stage': stats['iters'], 'passes_per_stage': stats['passes'],
+        'fp64_matched': fp64,
+        'speedup_vs_fp64_matched': (value / fp64['value']) if fp64 else None,
+        'roofline': roofline,
+        'cpu_baseline': cpu,
+        'kernels': kernel_table,
+    }
+    prec = M.precisions(p.precision, p.krylov)
+    out['config']['outer_tol'] = prec.outer_tol
+    out['config']['inner_rtol'] = prec.rtol
+    print(json.dumps(out), flush=True)
+
+
+def p_stages(p) -> int:
+    return {'SDIRK2': 2, 'SDIRK3': 3}.get(p.tableau.upper(), 4)
+
+
+if __name__ == '__main__':
+    main()

@@ -191,6 +191,23 @@ int32_t mprk_set_state(mprk_handle *h, double t, int64_t step);
 /* Wait for the stream and return the statistics of the most recent step. */
 int32_t mprk_stats_sync(mprk_handle *h, mprk_stats *out);
 
+/* Kernel classes for mprk_profile_read. */
+enum { MPRK_KC_STAGE_RHS = 0, MPRK_KC_RESIDUAL, MPRK_KC_CG_BEGIN, MPRK_KC_CG_DIR, MPRK_KC_CG_UPD,
+       MPRK_KC_PROMOTE, MPRK_KC_GM_BEGIN, MPRK_KC_GM_PREC, MPRK_KC_GM_MATVEC, MPRK_KC_GM_ORTH,
+       MPRK_KC_GM_FINISH, MPRK_KC_KEPS, MPRK_KC_COMBINE, MPRK_KC_APPLY, MPRK_KC_COUNT };
+
+/* Per-kernel timing.  enable = 1 waits for the stream, clears the records and starts
+ * recording a HIP event immediately before and after every kernel the handle launches (on its
+ * stream); enable = 0 stops recording (records are kept for mprk_profile_read). */
+int32_t mprk_profile(mprk_handle *h, int32_t enable);
+
+/* Waits for the stream and returns, for kernel class `kclass` since the last mprk_profile(h, 1):
+ * launches = kernels launched, worked = launches that did work (the rest returned at once
+ * because their solve phase had finished), units = basis vectors touched summed over working
+ * launches (GMRES kernels; = worked for the others), total_ms = summed event-to-event time. */
+int32_t mprk_profile_read(mprk_handle *h, int32_t kclass, int64_t *launches, int64_t *worked,
+                          int64_t *units, double *total_ms);
+
 /* Thread-local description of the last error ("" if none). */
 const char *mprk_last_error(void);
 

@@ -5,4 +5,4 @@ this package is its Python binding.  Importing it without the built library rais
 """
 from . import _abi  # noqa: F401  (raises ImportError when libmprk.so is missing)
 from ._abi import *  # noqa: F401,F403
-from .stepper import Stepper, from_problem, precisions, tableau  # noqa: F401
+from .stepper import Batch, Stepper, from_problem, precisions, tableau  # noqa: F401

@@ -25,6 +25,9 @@ CG, GMRES = 0, 1
 PRECOND_NONE, PRECOND_BJ = 0, 1
 TAB_SDIRK2, TAB_SDIRK3, TAB_MID, TAB_4S3PA, TAB_4S3PB, TAB_4S3PC = range(6)
 APPLY_K64, APPLY_M_LP, APPLY_BJ_LP, APPLY_M64 = range(4)
+KC_NAMES = ('stage_rhs', 'residual', 'cg_begin', 'cg_dir', 'cg_upd', 'promote', 'gm_begin',
+            'gm_prec', 'gm_matvec', 'gm_orth', 'gm_finish', 'keps', 'combine', 'apply')
+KC = {n: i for i, n in enumerate(KC_NAMES)}
 
 STATUS_NAMES = {OK: 'MPRK_OK', EINVAL: 'MPRK_EINVAL', ENOMEM: 'MPRK_ENOMEM', EDEVICE: 'MPRK_EDEVICE',
                 ENONFINITE: 'MPRK_ENONFINITE', ENOTCONV: 'MPRK_ENOTCONV',
@@ -106,6 +109,9 @@ _sig = {
     'mprk_get_state': (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     'mprk_set_state': (C.c_int32, [_P, C.c_double, C.c_int64]),
     'mprk_stats_sync': (C.c_int32, [_P, C.POINTER(mprk_stats)]),
+    'mprk_profile': (C.c_int32, [_P, C.c_int32]),
+    'mprk_profile_read': (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     'mprk_last_error': (C.c_char_p, []),
     'mprk_destroy': (None, [_P]),
     'mprk_batch_create': (C.c_int32, [C.c_int32, C.POINTER(mprk_problem), C.POINTER(mprk_tableau),
@@ -202,6 +208,17 @@ def mprk_stats_sync(h: int) -> dict:
     st = mprk_stats()
     check(lib.mprk_stats_sync(_P(h), C.byref(st)), 'mprk_stats_sync')
     return st.as_dict()
+
+
+def mprk_profile(h: int, enable: bool) -> None:
+    check(lib.mprk_profile(_P(h), 1 if enable else 0), 'mprk_profile')
+
+
+def mprk_profile_read(h: int, kclass: int) -> dict:
+    n, w, u, ms = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
+    check(lib.mprk_profile_read(_P(h), kclass, C.byref(n), C.byref(w), C.byref(u), C.byref(ms)),
+          'mprk_profile_read')
+    return {'launches': n.value, 'worked': w.value, 'units': u.value, 'ms': ms.value}
 
 
 def mprk_last_error() -> str:

@@ -1,26 +1,707 @@
-// batch.hip -- batched form of include/mprk.h (many independent problems per launch).
+// batch.hip -- batched form of include/mprk.h: many independent heat / advection-diffusion
+// problems of uneven size advanced together, one persistent kernel launch per RK stage.
+//
+// Each problem owns a contiguous group of workgroups (its "CTA group").  Inside the stage
+// kernel a group runs the whole implicit stage on its own: stage right-hand side (FP64),
+// the FP64 residual loop, and preconditioned CG in the LP storage type, with group barriers
+// between phases and group reductions (per-workgroup partials, double-buffered, summed in fixed
+// order by every workgroup of the group, so all workgroups take identical decisions).  The
+// last stage ends with the FP64 step combination.  One step = s launches, captured once as a
+// hipGraph and replayed.  All workgroups of the launch must be co-resident: the grid is sized
+// from the occupancy query, and every barrier wait is bounded (a timeout raises an error flag
+// and the kernel still runs to its end).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
 
 #include "../../include/mprk.h"
 #include "runtime_internal.hpp"
 
 using namespace mprk;
 
-extern "C" int32_t mprk_batch_create(int32_t, const mprk_problem*, const mprk_tableau*,
-                                     const mprk_precisions*, void*, mprk_batch** out) {
-  if (out) *out = nullptr;
-  return set_error(MPRK_EUNSUPPORTED, "batched form not built yet");
+namespace mprk {
+
+constexpr int BND = 4;            // values per group reduction
+constexpr long BAR_SPIN_LIMIT = 1L << 22;
+
+struct BCtl {
+  unsigned int bar_count;
+  unsigned int bar_gen;
+  int error;                     // a group barrier timed out
+  int step_nonfinite;
+  long long good_steps, bad_steps, life_iters, life_passes;
+  int iters[MAXS], passes[MAXS], converged[MAXS], nonfinite[MAXS];
+  double resid[MAXS];
+};
+
+struct BProb {
+  Geo geo;
+  Coef<double> K;                // FP64 operator
+  double sigma;                  // dt * a_ii (single distinct diagonal)
+  double dt;
+  double *u, *rhs, *y, *res, *k; // FP64; k holds s vectors of stride N
+  void *r, *z, *p0, *p1, *q, *x; // LP vectors
+  void* dinv;                    // block-Jacobi inverses (LP)
+  double* part;                  // 2 * BND * nwg partials
+  BCtl* ctl;
+  int wg0, nwg, chunk;           // workgroup range and rows per workgroup (multiple of 64)
+};
+
+struct BArgs {
+  const BProb* probs;
+  const int* wg2prob;
+  int s;
+  double A[MAXS][MAXS];          // full tableau (a_hi + a_lo)
+  double b[MAXS];
+  double rtol, atol, outer_tol;
+  int maxit, max_passes, paper_mode, bs;
+};
+
+__device__ bool group_barrier(BCtl* c, int nwg) {
+  __syncthreads();
+  if (nwg > 1) {
+    if (threadIdx.x == 0) {
+      __threadfence();
+      const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned arrived = atomicAdd(&c->bar_count, 1u);
+      if (arrived == (unsigned)nwg - 1u) {
+        __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        atomicAdd(&c->bar_gen, 1u);
+      } else {
+        long spins = 0;
+        while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++spins > BAR_SPIN_LIMIT) {
+            __hip_atomic_store(&c->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+        }
+      }
+      __threadfence();
+    }
+    __syncthreads();
+  }
+  return true;
 }
-extern "C" int64_t mprk_batch_workspace_bytes(const mprk_batch*) {
-  return set_error(MPRK_EUNSUPPORTED, "batched form not built yet");
+
+// Group reduction of nd values; every workgroup of the group returns the same totals.
+template <int ND>
+__device__ void group_reduce(const double (&v)[ND], int nd, const BProb& P, int wl, int& parity,
+                             double (&out)[ND]) {
+  __shared__ double wsum[NWAVE][BND];
+  __shared__ double tot[BND];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    if (d < nd) {
+      const double s = wave_sum(v[d]);
+      if (lane == 0) wsum[wave][d] = s;
+    }
+  }
+  __syncthreads();
+  double* part = P.part + (size_t)parity * BND * P.nwg;
+  if (threadIdx.x < nd) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) s += wsum[w][threadIdx.x];
+    if (P.nwg > 1)
+      __hip_atomic_store(part + threadIdx.x * P.nwg + wl, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      tot[threadIdx.x] = s;
+  }
+  if (P.nwg > 1) {
+    group_barrier(P.ctl, P.nwg);
+    if (threadIdx.x < nd) {
+      double s = 0.0;
+      for (int w = 0; w < P.nwg; ++w)
+        s += __hip_atomic_load(part + threadIdx.x * P.nwg + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      tot[threadIdx.x] = s;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < ND; ++d) out[d] = d < nd ? tot[d] : 0.0;
+  __syncthreads();
+  parity ^= 1;
 }
-extern "C" int32_t mprk_batch_bind(mprk_batch*, double* const*, void*, int64_t) {
-  return set_error(MPRK_EUNSUPPORTED, "batched form not built yet");
+
+// one FP64 stencil row of K
+__device__ __forceinline__ double k64_row(const Geo& geo, const Coef<double>& K,
+                                          const double* __restrict__ y, int r, double& yc) {
+  In1<double, double, 1> f{y};
+  double c[1], o[1];
+  stencil_group<double, 1>(geo, K, r, f, c, o);
+  yc = c[0];
+  return o[0];
 }
-extern "C" int32_t mprk_batch_step(mprk_batch*, int32_t) {
-  return set_error(MPRK_EUNSUPPORTED, "batched form not built yet");
+
+template <typename S, typename C, int BS>
+__global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
+  const int pid = a.wg2prob[blockIdx.x];
+  const BProb P = a.probs[pid];
+  BCtl* ctl = P.ctl;
+  const int wl = blockIdx.x - P.wg0;
+  const int N = P.geo.N;
+  const int r0 = wl * P.chunk;
+  const int r1 = min(N, r0 + P.chunk);
+  const int nit = (P.chunk + TPB - 1) / TPB;
+  int parity = 0;
+  const double sigma = P.sigma;
+  const double sqrtN = sqrt((double)N);
+  double* kout = P.k + (size_t)stage * N;
+  const S* dinv = (const S*)P.dinv;
+  S* r = (S*)P.r;
+  S* z = BS > 0 ? (S*)P.z : (S*)P.r;
+  S* q = (S*)P.q;
+  S* x = (S*)P.x;
+  const Coef<C> M = coef_cast<C>(coef_stage(P.K, sigma));
+
+  if (stage == 0 && wl == 0 && threadIdx.x == 0) ctl->step_nonfinite = 0;
+  // ---- A1: rhs = u + dt sum_{j<stage} a_ij k_j ; y = rhs ----
+  for (int it = 0; it < nit; ++it) {
+    const int row = r0 + it * TPB + threadIdx.x;
+    if (row >= r1) break;
+    double acc = P.u[row];
+    for (int j = 0; j < stage; ++j) acc += P.dt * a.A[stage][j] * P.k[(size_t)j * N + row];
+    P.rhs[row] = acc;
+    P.y[row] = acc;
+  }
+  group_barrier(ctl, P.nwg);
+
+  int passes = 0, total_iters = 0, converged = 0, nonfinite = 0;
+  double rel = 0.0;
+  const int P_max = a.paper_mode ? 1 : a.max_passes;
+  for (int pass = 0;; ++pass) {
+    // ---- A2: k = K y ; res = rhs - y + sigma k ----
+    double acc[BND] = {0.0, 0.0, 0.0, 0.0};
+    for (int it = 0; it < nit; ++it) {
+      const int row = r0 + it * TPB + threadIdx.x;
+      if (row >= r1) break;
+      double yc;
+      const double ky = k64_row(P.geo, P.K, P.y, row, yc);
+      const double b = P.rhs[row];
+      const double rr = b - yc + sigma * ky;
+      kout[row] = ky;
+      P.res[row] = rr;
+      acc[0] += rr * rr;
+      acc[1] += b * b;
+      acc[2] += (__builtin_isfinite(rr) && __builtin_isfinite(ky)) ? 0.0 : 1.0;
+    }
+    double t[BND];
+    group_reduce<BND>(acc, 3, P, wl, parity, t);
+    const double rn = sqrt(t[0]), bn = sqrt(t[1]);
+    rel = bn > 0.0 ? rn / bn : rn;
+    if (t[2] != 0.0 || !__builtin_isfinite(rn)) {
+      nonfinite = 1;
+      break;
+    }
+    converged = a.paper_mode ? (passes >= 1) : (rel <= a.outer_tol);
+    if (converged || passes >= P_max || rn == 0.0) break;
+    const double scale = rn / sqrtN;
+    const double inv = 1.0 / scale;
+    // ---- CG begin: r = LP(res / scale), z = BJ(r) ----
+    double acc2[BND] = {0.0, 0.0, 0.0, 0.0};
+    for (int it = 0; it < nit; ++it) {
+      const int row = r0 + it * TPB + threadIdx.x;
+      const bool valid = row < r1;
+      C rv[1], zv[1];
+      rv[0] = valid ? rnd<S, C>((C)(P.res[row] * inv)) : C(0);
+      if constexpr (BS > 0) {
+        bj_apply_lane<C, S, 1, BS>(dinv, row, valid, rv, zv);
+        zv[0] = rnd<S, C>(zv[0]);
+      } else {
+        zv[0] = rv[0];
+      }
+      if (valid) {
+        r[row] = (S)rv[0];
+        if constexpr (BS > 0) z[row] = (S)zv[0];
+        acc2[0] += (double)(rv[0] * zv[0]);
+        acc2[1] += (double)(rv[0] * rv[0]);
+      }
+    }
+    group_reduce<BND>(acc2, 2, P, wl, parity, t);
+    double rz = t[0];
+    const double tol = fmax(a.rtol * sqrt(t[1]), a.atol / scale);
+    bool inner_done = sqrt(t[1]) <= tol;
+    double beta = 0.0;
+    int its = 0;
+    while (!inner_done && its < a.maxit) {
+      // ---- C1: p_new = z + beta p_old ; q = M p_new ; (p, q) ----
+      const S* pold = (its & 1) ? (const S*)P.p1 : (const S*)P.p0;
+      S* pnew = (its & 1) ? (S*)P.p0 : (S*)P.p1;
+      InAxpy<C, S, 1> f{z, pold, (C)beta, its > 0};
+      double acc3[BND] = {0.0, 0.0, 0.0, 0.0};
+      for (int it = 0; it < nit; ++it) {
+        const int row = r0 + it * TPB + threadIdx.x;
+        if (row >= r1) break;
+        C pc[1], w[1];
+        stencil_group<C, 1>(P.geo, M, row, f, pc, w);
+        w[0] = rnd<S, C>(w[0]);
+        pnew[row] = (S)pc[0];
+        q[row] = (S)w[0];
+        acc3[0] += (double)(pc[0] * w[0]);
+      }
+      group_reduce<BND>(acc3, 1, P, wl, parity, t);
+      const double pq = t[0];
+      if (!(pq > 0.0) || !__builtin_isfinite(pq)) break;
+      const C alpha = (C)(rz / pq);
+      // ---- C2: x += alpha p ; r -= alpha q ; z = BJ(r) ; (r, z), (r, r) ----
+      double acc4[BND] = {0.0, 0.0, 0.0, 0.0};
+      for (int it = 0; it < nit; ++it) {
+        const int row = r0 + it * TPB + threadIdx.x;
+        const bool valid = row < r1;
+        C rv[1], zv[1];
+        if (valid) {
+          const C pv = (C)pnew[row];
+          const C xv = its == 0 ? alpha * pv : (C)x[row] + alpha * pv;
+          x[row] = (S)xv;
+          rv[0] = rnd<S, C>((C)r[row] - alpha * (C)q[row]);
+          r[row] = (S)rv[0];
+        } else {
+          rv[0] = C(0);
+        }
+        if constexpr (BS > 0) {
+          bj_apply_lane<C, S, 1, BS>(dinv, row, valid, rv, zv);
+          zv[0] = rnd<S, C>(zv[0]);
+          if (valid) z[row] = (S)zv[0];
+        } else {
+          zv[0] = rv[0];
+        }
+        if (valid) {
+          acc4[0] += (double)(rv[0] * zv[0]);
+          acc4[1] += (double)(rv[0] * rv[0]);
+        }
+      }
+      group_reduce<BND>(acc4, 2, P, wl, parity, t);
+      ++its;
+      const double rz_new = t[0];
+      beta = rz_new / rz;
+      rz = rz_new;
+      inner_done = !__builtin_isfinite(t[1]) || sqrt(t[1]) <= tol;
+    }
+    total_iters += its;
+    // ---- promote: y += scale * x ----
+    if (its > 0) {
+      for (int it = 0; it < nit; ++it) {
+        const int row = r0 + it * TPB + threadIdx.x;
+        if (row >= r1) break;
+        P.y[row] += scale * (double)(C)x[row];
+      }
+    }
+    ++passes;
+    group_barrier(ctl, P.nwg);
+  }
+  if (wl == 0 && threadIdx.x == 0) {
+    ctl->iters[stage] = total_iters;
+    ctl->passes[stage] = passes;
+    ctl->resid[stage] = rel;
+    ctl->converged[stage] = converged && !nonfinite;
+    ctl->nonfinite[stage] = nonfinite;
+    ctl->life_iters += total_iters;
+    ctl->life_passes += passes;
+    if (nonfinite) ctl->step_nonfinite = 1;
+  }
+  if (stage == a.s - 1) {
+    // ---- step combination u += dt sum_i b_i k_i (skipped after a non-finite residual) ----
+    group_barrier(ctl, P.nwg);
+    const int bad = __hip_atomic_load(&ctl->step_nonfinite, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!bad) {
+      for (int it = 0; it < nit; ++it) {
+        const int row = r0 + it * TPB + threadIdx.x;
+        if (row >= r1) break;
+        double acc = P.u[row];
+        for (int i = 0; i < a.s; ++i) acc += P.dt * a.b[i] * P.k[(size_t)i * N + row];
+        P.u[row] = acc;
+      }
+    }
+    if (wl == 0 && threadIdx.x == 0) {
+      if (bad) ctl->bad_steps += 1;
+      else ctl->good_steps += 1;
+    }
+  }
 }
-extern "C" int32_t mprk_batch_stats_sync(mprk_batch*, int32_t, mprk_stats*) {
-  return set_error(MPRK_EUNSUPPORTED, "batched form not built yet");
+
+}  // namespace mprk
+
+// ------------------------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------------------------
+
+struct mprk_batch {
+  int count = 0;
+  std::vector<mprk_problem> probs;
+  mprk_tableau tab{};
+  mprk_precisions prec{};
+  hipStream_t stream = nullptr;
+  int lp_bytes = 4;
+  int bs = 0;
+  std::vector<size_t> off_r, off_dinv, off_part, off_k, off_rhs;
+  std::vector<int> N, nwg, chunk;
+  size_t o_probs = 0, o_map = 0, o_ctl = 0, o_flag = 0, ws_bytes = 0;
+  size_t lp_vec_bytes_total = 0;
+  int G = 0;
+  char* ws = nullptr;
+  std::vector<double*> u;
+  bool bound = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  long long good_base = 0;
+  std::vector<long long> good_seen, bad_seen;
+  ~mprk_batch() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+namespace mprk {
+Coef<double> operator_coef(const mprk_grid& g, const mprk_operator& op);
 }
-extern "C" void mprk_batch_destroy(mprk_batch*) {}
+
+template <typename S, typename C>
+static const void* kb_kernel_ptr(int bs) {
+  switch (bs) {
+    case 0: return (const void*)kb_stage<S, C, 0>;
+    case 1: return (const void*)kb_stage<S, C, 1>;
+    case 2: return (const void*)kb_stage<S, C, 2>;
+    case 4: return (const void*)kb_stage<S, C, 4>;
+    default: return (const void*)kb_stage<S, C, 8>;
+  }
+}
+
+static const void* batch_kernel(int storage, int bs) {
+  if (storage == MPRK_FP64) return kb_kernel_ptr<double, double>(bs);
+  if (storage == MPRK_FP32) return kb_kernel_ptr<float, float>(bs);
+  return kb_kernel_ptr<half_t, float>(bs);
+}
+
+// Weight of a problem's stage solve: unknowns x an estimate of CG iterations, which grow
+// like the square root of the stage matrix's condition number 1 + sigma * 4 * diff * sum 1/h^2.
+static double work_weight(const mprk_problem& p, double a) {
+  const mprk_grid& g = p.grid;
+  const double N = (double)g.nx * g.ny * g.nz;
+  double s = 0.0;
+  const int n[3] = {g.nx, g.ny, g.nz};
+  for (int d = 0; d < 3; ++d) {
+    const double h = g.bc == MPRK_BC_DIRICHLET0 ? 1.0 / (n[d] + 1) : 1.0 / n[d];
+    s += 4.0 * p.op.diff / (h * h);
+  }
+  return N * std::sqrt(1.0 + p.dt * a * s);
+}
+
+extern "C" int32_t mprk_batch_create(int32_t count, const mprk_problem* problems,
+                                     const mprk_tableau* tab, const mprk_precisions* prec,
+                                     void* hip_stream, mprk_batch** out) {
+  if (!out) return set_error(MPRK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || !problems || !tab || !prec) return set_error(MPRK_EINVAL, "bad batch arguments");
+  if (prec->krylov != MPRK_CG) return set_error(MPRK_EUNSUPPORTED, "batched form implements CG only");
+  if (prec->storage == MPRK_FP64 && prec->compute != MPRK_FP64)
+    return set_error(MPRK_EUNSUPPORTED, "FP64 storage needs FP64 compute");
+  if (prec->storage != MPRK_FP64 && prec->compute != MPRK_FP32)
+    return set_error(MPRK_EUNSUPPORTED, "LP storage needs FP32 compute");
+  if (prec->reorth) return set_error(MPRK_EUNSUPPORTED, "reorth is a GMRES option");
+  // one distinct nonzero diagonal, no eps off-diagonals needing k^eps, all stages implicit
+  double diag = 0.0;
+  for (int i = 0; i < tab->s; ++i) {
+    const double aii = tab->a_hi[i * tab->s + i] + tab->a_lo[i * tab->s + i];
+    if (aii == 0.0) return set_error(MPRK_EUNSUPPORTED, "batched form needs every stage implicit");
+    if (i == 0) diag = aii;
+    else if (aii != diag) return set_error(MPRK_EUNSUPPORTED, "batched form needs a single diagonal value (SDIRK)");
+    for (int j = 0; j < i; ++j)
+      if (tab->a_lo[i * tab->s + j] != 0.0)
+        return set_error(MPRK_EUNSUPPORTED, "batched form does not implement eps off-diagonals");
+  }
+  mprk_batch* b = new (std::nothrow) mprk_batch();
+  if (!b) return set_error(MPRK_ENOMEM, "host allocation failed");
+  b->count = count;
+  b->probs.assign(problems, problems + count);
+  b->tab = *tab;
+  b->prec = *prec;
+  b->stream = (hipStream_t)hip_stream;
+  for (int p = 0; p < count; ++p) {
+    const mprk_problem& q = problems[p];
+    if (q.op.format != MPRK_FMT_STENCIL) {
+      delete b;
+      return set_error(MPRK_EUNSUPPORTED, "batched form uses the matrix-free stencil");
+    }
+    if (q.op.kind == MPRK_OP_ADVDIFF && (q.op.b[0] != 0.0 || q.op.b[1] != 0.0 || q.op.b[2] != 0.0)) {
+      delete b;
+      return set_error(MPRK_EINVAL, "CG needs a symmetric operator");
+    }
+    if (q.grid.nx < 1 || q.grid.ny < 1 || q.grid.nz < 1 || !(q.dt > 0.0) || !(q.op.diff >= 0.0)) {
+      delete b;
+      return set_error(MPRK_EINVAL, "bad problem in batch");
+    }
+  }
+  b->lp_bytes = prec->storage == MPRK_FP64 ? 8 : (prec->storage == MPRK_FP32 ? 4 : 2);
+  b->bs = prec->precond == MPRK_PRECOND_BJ ? prec->block : 0;
+  if (b->bs && !(b->bs == 1 || b->bs == 2 || b->bs == 4 || b->bs == 8)) {
+    delete b;
+    return set_error(MPRK_EINVAL, "block size must be 1, 2, 4 or 8");
+  }
+  *out = b;
+  return MPRK_OK;
+}
+
+// Workgroups per problem: proportional to the work estimate, at least one, at most one per
+// 64 rows, in total at most the co-resident capacity of the device.
+static int plan_groups(mprk_batch* b, int capacity) {
+  const int s = b->tab.s;
+  const double a = b->tab.a_hi[0] + b->tab.a_lo[0];
+  std::vector<double> w(b->count);
+  double W = 0.0;
+  for (int p = 0; p < b->count; ++p) {
+    w[p] = work_weight(b->probs[p], a);
+    W += w[p];
+  }
+  (void)s;
+  b->nwg.assign(b->count, 1);
+  b->chunk.assign(b->count, 0);
+  b->N.assign(b->count, 0);
+  int avail = capacity - b->count;
+  if (avail < 0) return set_error(MPRK_EUNSUPPORTED, "more problems than co-resident workgroups");
+  for (int p = 0; p < b->count; ++p) {
+    const mprk_grid& g = b->probs[p].grid;
+    const int N = g.nx * g.ny * g.nz;
+    b->N[p] = N;
+    const int maxwg = std::max(1, (N + 63) / 64);
+    int extra = (int)std::floor(avail * w[p] / W);
+    b->nwg[p] = std::min(maxwg, 1 + extra);
+  }
+  int G = 0;
+  for (int p = 0; p < b->count; ++p) {
+    const int N = b->N[p];
+    int ch = (N + b->nwg[p] - 1) / b->nwg[p];
+    ch = (ch + 63) / 64 * 64;  // block-Jacobi blocks (<= 8 rows) never straddle workgroups
+    b->chunk[p] = ch;
+    b->nwg[p] = (N + ch - 1) / ch;
+    G += b->nwg[p];
+  }
+  b->G = G;
+  return MPRK_OK;
+}
+
+static int batch_layout(mprk_batch* b) {
+  const int s = b->tab.s;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  b->off_rhs.resize(b->count);
+  b->off_k.resize(b->count);
+  b->off_r.resize(b->count);
+  b->off_dinv.resize(b->count);
+  b->off_part.resize(b->count);
+  for (int p = 0; p < b->count; ++p) {
+    const size_t N = (size_t)b->N[p];
+    b->off_rhs[p] = take(3 * N * 8);          // rhs, y, res
+    b->off_k[p] = take((size_t)s * N * 8);
+    const size_t vlp = (N * b->lp_bytes + 255) & ~(size_t)255;
+    b->off_r[p] = take(6 * vlp);              // r, z, p0, p1, q, x
+    b->off_dinv[p] = b->bs ? take(((N + b->bs - 1) / b->bs) * (size_t)b->bs * b->bs * b->lp_bytes) : 0;
+    b->off_part[p] = take(2 * BND * (size_t)b->nwg[p] * 8);
+  }
+  b->o_probs = take(sizeof(BProb) * b->count);
+  b->o_map = take(sizeof(int) * b->G);
+  b->o_ctl = take(sizeof(BCtl) * b->count);
+  b->o_flag = take(256);
+  b->ws_bytes = off;
+  return MPRK_OK;
+}
+
+static int batch_capacity(mprk_batch* b, int* cap) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return set_error(MPRK_EDEVICE, "hipGetDevice failed");
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return set_error(MPRK_EDEVICE, "CU count query failed");
+  const void* k = batch_kernel(b->prec.storage, b->bs);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, TPB, 0) != hipSuccess)
+    return set_error(MPRK_EDEVICE, "occupancy query failed");
+  // stay one workgroup per CU below the occupancy bound
+  *cap = std::max(1, cus * std::max(1, per - 1));
+  return MPRK_OK;
+}
+
+extern "C" int64_t mprk_batch_workspace_bytes(const mprk_batch* cb) {
+  if (!cb) return set_error(MPRK_EINVAL, "NULL batch");
+  mprk_batch* b = const_cast<mprk_batch*>(cb);
+  if (b->ws_bytes == 0) {
+    int cap = 0;
+    int rc = batch_capacity(b, &cap);
+    if (rc) return rc;
+    rc = plan_groups(b, cap);
+    if (rc) return rc;
+    rc = batch_layout(b);
+    if (rc) return rc;
+  }
+  return (int64_t)b->ws_bytes;
+}
+
+#define BHIP(x)                                                                        \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      return set_error(MPRK_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+static BArgs batch_args(mprk_batch* b) {
+  BArgs a{};
+  a.probs = (const BProb*)(b->ws + b->o_probs);
+  a.wg2prob = (const int*)(b->ws + b->o_map);
+  a.s = b->tab.s;
+  for (int i = 0; i < a.s; ++i) {
+    for (int j = 0; j < a.s; ++j) a.A[i][j] = b->tab.a_hi[i * a.s + j] + b->tab.a_lo[i * a.s + j];
+    a.b[i] = b->tab.b[i];
+  }
+  a.rtol = b->prec.rtol;
+  a.atol = b->prec.atol;
+  a.outer_tol = b->prec.outer_tol;
+  a.maxit = b->prec.maxit;
+  a.max_passes = std::max(b->prec.refine_max, 1);
+  a.paper_mode = b->prec.refine_max == 0;
+  a.bs = b->bs;
+  return a;
+}
+
+extern "C" int32_t mprk_batch_bind(mprk_batch* b, double* const* u_dev, void* workspace_dev,
+                                   int64_t bytes) {
+  if (!b || !u_dev || !workspace_dev) return set_error(MPRK_EINVAL, "NULL argument");
+  int64_t need = mprk_batch_workspace_bytes(b);
+  if (need < 0) return (int32_t)need;
+  if (bytes < need) return set_error(MPRK_ENOMEM, "workspace smaller than mprk_batch_workspace_bytes");
+  if (((uintptr_t)workspace_dev & 255) != 0) return set_error(MPRK_EINVAL, "workspace must be 256-byte aligned");
+  b->ws = (char*)workspace_dev;
+  b->u.assign(u_dev, u_dev + b->count);
+  for (int p = 0; p < b->count; ++p)
+    if (!b->u[p]) return set_error(MPRK_EINVAL, "NULL state pointer");
+  const double a = b->tab.a_hi[0] + b->tab.a_lo[0];
+  std::vector<BProb> hp(b->count);
+  std::vector<int> map(b->G);
+  int wg = 0;
+  for (int p = 0; p < b->count; ++p) {
+    const mprk_problem& q = b->probs[p];
+    BProb& P = hp[p];
+    const int N = b->N[p];
+    P.geo = Geo{q.grid.nx, q.grid.ny, q.grid.nz, q.grid.bc, N, q.grid.nx * q.grid.ny};
+    P.K = operator_coef(q.grid, q.op);
+    P.sigma = q.dt * a;
+    P.dt = q.dt;
+    P.u = b->u[p];
+    P.rhs = (double*)(b->ws + b->off_rhs[p]);
+    P.y = P.rhs + N;
+    P.res = P.y + N;
+    P.k = (double*)(b->ws + b->off_k[p]);
+    const size_t vlp = ((size_t)N * b->lp_bytes + 255) & ~(size_t)255;
+    char* lp = b->ws + b->off_r[p];
+    P.r = lp;
+    P.z = lp + vlp;
+    P.p0 = lp + 2 * vlp;
+    P.p1 = lp + 3 * vlp;
+    P.q = lp + 4 * vlp;
+    P.x = lp + 5 * vlp;
+    P.dinv = b->bs ? (void*)(b->ws + b->off_dinv[p]) : nullptr;
+    P.part = (double*)(b->ws + b->off_part[p]);
+    P.ctl = (BCtl*)(b->ws + b->o_ctl) + p;
+    P.wg0 = wg;
+    P.nwg = b->nwg[p];
+    P.chunk = b->chunk[p];
+    for (int i = 0; i < P.nwg; ++i) map[wg + i] = p;
+    wg += P.nwg;
+  }
+  BHIP(hipMemcpyAsync(b->ws + b->o_probs, hp.data(), sizeof(BProb) * b->count, hipMemcpyHostToDevice, b->stream));
+  BHIP(hipMemcpyAsync(b->ws + b->o_map, map.data(), sizeof(int) * b->G, hipMemcpyHostToDevice, b->stream));
+  BHIP(hipMemsetAsync(b->ws + b->o_ctl, 0, sizeof(BCtl) * b->count, b->stream));
+  BHIP(hipMemsetAsync(b->ws + b->o_flag, 0, 256, b->stream));
+  // block-Jacobi inverses with the single-problem setup kernel
+  int* fail = nullptr;
+  if (b->bs) {
+    Engine* eng = b->prec.storage == MPRK_FP64 ? make_engine_fp64()
+                  : b->prec.storage == MPRK_FP32 ? make_engine_fp32() : make_engine_fp16();
+    std::unique_ptr<Engine> guard(eng);
+    fail = (int*)(b->ws + b->o_flag);
+    for (int p = 0; p < b->count; ++p) {
+      EngineCtx c{};
+      c.stream = b->stream;
+      c.geo = hp[p].geo;
+      c.bs = b->bs;
+      BHIP(eng->bj_setup_stencil(c, stage_coef(hp[p].K, hp[p].sigma), hp[p].dinv, fail));
+    }
+  }
+  int hfail = 0;
+  if (fail) {
+    BHIP(hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  }
+  BHIP(hipStreamSynchronize(b->stream));
+  if (hfail) return set_error(MPRK_EINVAL, "singular block-Jacobi block in batch");
+  // capture one step (s stage launches) as a graph
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  const BArgs args = batch_args(b);
+  const void* kern = batch_kernel(b->prec.storage, b->bs);
+  hipStream_t cs;
+  BHIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int st = 0; st < b->tab.s && e == hipSuccess; ++st) {
+      void* kargs[] = {(void*)&args, (void*)&st};
+      e = hipLaunchKernel(kern, dim3(b->G), dim3(TPB), kargs, 0, cs);
+    }
+    hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return set_error(MPRK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  b->good_seen.assign(b->count, 0);
+  b->bad_seen.assign(b->count, 0);
+  b->bound = true;
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_batch_step(mprk_batch* b, int32_t nsteps) {
+  if (!b) return set_error(MPRK_EINVAL, "NULL batch");
+  if (!b->bound) return set_error(MPRK_ESTATE, "mprk_batch_step before mprk_batch_bind");
+  if (nsteps < 0) return set_error(MPRK_EINVAL, "nsteps must be >= 0");
+  for (int n = 0; n < nsteps; ++n) BHIP(hipGraphLaunch(b->gexec, b->stream));
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_batch_stats_sync(mprk_batch* b, int32_t idx, mprk_stats* out) {
+  if (!b || !out) return set_error(MPRK_EINVAL, "NULL argument");
+  if (!b->bound) return set_error(MPRK_ESTATE, "not bound");
+  if (idx < 0 || idx >= b->count) return set_error(MPRK_EINVAL, "problem index out of range");
+  BCtl c;
+  BHIP(hipMemcpyAsync(&c, (BCtl*)(b->ws + b->o_ctl) + idx, sizeof(BCtl), hipMemcpyDeviceToHost, b->stream));
+  BHIP(hipStreamSynchronize(b->stream));
+  std::memset(out, 0, sizeof(*out));
+  out->steps = c.good_steps;
+  out->t = c.good_steps * b->probs[idx].dt;
+  out->stages = b->tab.s;
+  for (int i = 0; i < b->tab.s; ++i) {
+    out->iters[i] = c.iters[i];
+    out->passes[i] = c.passes[i];
+    out->resid[i] = c.resid[i];
+    out->converged[i] = c.converged[i];
+  }
+  out->total_iters = c.life_iters;
+  out->total_passes = c.life_passes;
+  out->nonfinite = c.bad_steps > 0;
+  if (c.error) return set_error(MPRK_EDEVICE, "a batched group barrier timed out (workgroups not co-resident)");
+  return MPRK_OK;
+}
+
+extern "C" void mprk_batch_destroy(mprk_batch* b) { delete b; }

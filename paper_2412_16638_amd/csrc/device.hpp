@@ -44,9 +44,29 @@ struct Coef {
   C c, xm, xp, ym, yp, zm, zp;
 };
 
+template <typename C>
+__host__ __device__ inline Coef<C> coef_cast(const Coef<double>& a) {
+  return Coef<C>{(C)a.c, (C)a.xm, (C)a.xp, (C)a.ym, (C)a.yp, (C)a.zm, (C)a.zp};
+}
+
+// stencil of M = I - sigma K from the stencil of K
+__host__ __device__ inline Coef<double> coef_stage(const Coef<double>& K, double sigma) {
+  return Coef<double>{1.0 - sigma * K.c, -sigma * K.xm, -sigma * K.xp, -sigma * K.ym,
+                      -sigma * K.yp,     -sigma * K.zm, -sigma * K.zp};
+}
+
 struct Csr {
   const int* rowptr;
   const int* col;
+};
+
+constexpr int MAXPASS = 32;  // passes whose iteration counts are recorded
+
+// Kernel classes counted for profiling (launches that did work).
+enum KClass {
+  KC_STAGE_RHS = 0, KC_RESIDUAL, KC_CG_BEGIN, KC_CG_DIR, KC_CG_UPD, KC_PROMOTE,
+  KC_GM_BEGIN, KC_GM_PREC, KC_GM_MATVEC, KC_GM_ORTH, KC_GM_FINISH, KC_KEPS, KC_COMBINE,
+  KC_APPLY64, KC_COUNT
 };
 
 // Device control record of one solve context (one per problem).  The first 64 bytes
@@ -80,7 +100,17 @@ struct Ctl {
   double ysol[MAXM];                 // least-squares solution of the cycle
   double vscale[MAXM + 1];           // basis vector i = vscale[i] * stored vector i
   unsigned int ticket;               // last-block counter (self-resetting)
+  int pass_iters[MAXPASS];           // Krylov iterations of each pass of the current stage
+  long long worked[KC_COUNT];        // launches per kernel class that did work (profiling)
+  long long units[KC_COUNT];         // basis vectors touched (GMRES kernels), else launches
 };
+
+__device__ __forceinline__ void count_work(Ctl* ctl, int kc, int units = 1) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->worked[kc] += 1;
+    ctl->units[kc] += units;
+  }
+}
 
 // The host polls this prefix of Ctl.
 struct CtlHead {
@@ -90,6 +120,7 @@ struct CtlHead {
   int bad_steps, step_nonfinite;
 };
 static_assert(sizeof(CtlHead) == 64, "poll head must be 64 bytes");
+
 
 struct SolveCfg {
   double sigma;        // tau a_ii

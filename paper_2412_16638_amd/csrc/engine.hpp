@@ -5,12 +5,58 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "kernels.hpp"
 
 namespace mprk {
 
+// Optional per-launch event timing (bench/profiling).  Events are recorded on the launch
+// stream immediately before and after each kernel of a class.
+struct Profiler {
+  hipStream_t stream = nullptr;
+  std::vector<hipEvent_t> pool;
+  struct Rec {
+    int kc, e0, e1;
+  };
+  std::vector<Rec> recs;
+  size_t used = 0;
+  int cur_kc = -1, cur_e0 = -1;
+  bool failed = false;
+  int next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        failed = true;
+        return -1;
+      }
+      pool.push_back(e);
+    }
+    return (int)used++;
+  }
+  void before(int kc) {
+    cur_kc = kc;
+    cur_e0 = next();
+    if (cur_e0 >= 0 && hipEventRecord(pool[cur_e0], stream) != hipSuccess) failed = true;
+  }
+  void after() {
+    const int e1 = next();
+    if (e1 >= 0 && hipEventRecord(pool[e1], stream) != hipSuccess) failed = true;
+    if (cur_e0 >= 0 && e1 >= 0) recs.push_back(Rec{cur_kc, cur_e0, e1});
+  }
+  void reset() {
+    recs.clear();
+    used = 0;
+    failed = false;
+  }
+  ~Profiler() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 // What the engine needs to know about the problem and the workspace.
 struct EngineCtx {
+  Profiler* prof = nullptr;
   hipStream_t stream;
   Geo geo;
   int fmt;            // 0 stencil, 1 CSR
@@ -46,7 +92,7 @@ class Engine {
                              const void* dinv, int it) = 0;
   virtual hipError_t cg_finish(const EngineCtx& c) = 0;
   // GMRES
-  virtual hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg) = 0;
+  virtual hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) = 0;
   virtual hipError_t gm_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
                              const void* dinv) = 0;
   virtual hipError_t gm_finish(const EngineCtx& c, const void* dinv) = 0;
@@ -66,9 +112,11 @@ inline Coef<C> cast_coef(const Coef<double>& a) {
   return Coef<C>{(C)a.c, (C)a.xm, (C)a.xp, (C)a.ym, (C)a.yp, (C)a.zm, (C)a.zp};
 }
 
-#define MPRK_LAUNCH(kern, ln, stream, ...)                                              \
+#define MPRK_LAUNCH_KC(c, kc, kern, ln, ...)                                            \
   do {                                                                                   \
-    hipLaunchKernelGGL((kern), dim3((ln).G), dim3(TPB), 0, (stream), __VA_ARGS__);        \
+    if ((c).prof) (c).prof->before(kc);                                                  \
+    hipLaunchKernelGGL((kern), dim3((ln).G), dim3(TPB), 0, (c).stream, __VA_ARGS__);      \
+    if ((c).prof) (c).prof->after();                                                     \
   } while (0)
 
 template <typename S, typename C>
@@ -99,7 +147,7 @@ class EngineT final : public Engine {
   template <int VEC, int BS>
   void cg_begin_t(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) {
     S* z = BS > 0 ? (S*)c.z : (S*)c.r;
-    MPRK_LAUNCH((k_cg_begin<S, C, VEC, BS>), c.ln_vec, c.stream, c.ln_vec, c.res, (S*)c.r, z,
+    MPRK_LAUNCH_KC(c, KC_CG_BEGIN, (k_cg_begin<S, C, VEC, BS>), c.ln_vec, c.ln_vec, c.res, (S*)c.r, z,
                 (const S*)dinv, cfg, c.ctl, c.partials, c.pstride);
   }
   hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) override {
@@ -112,13 +160,13 @@ class EngineT final : public Engine {
                 const S* pold, S* pnew) {
     const Coef<C> M = cast_coef<C>(Mc);
     const C msig = (C)(cfg.sigma * c.kscale);
-    MPRK_LAUNCH((k_cg_dir<S, C, VEC, FMT>), c.ln_mv, c.stream, c.ln_mv, c.geo, M, c.csr,
+    MPRK_LAUNCH_KC(c, KC_CG_DIR, (k_cg_dir<S, C, VEC, FMT>), c.ln_mv, c.ln_mv, c.geo, M, c.csr,
                 (const S*)c.mval, msig, z, pold, pnew, (S*)c.q, c.ctl, c.partials, c.pstride);
   }
   template <int VEC, int BS>
   void cg_upd_t(const EngineCtx& c, const SolveCfg& cfg, const S* p, const void* dinv) {
     S* z = BS > 0 ? (S*)c.z : (S*)c.r;
-    MPRK_LAUNCH((k_cg_upd<S, C, VEC, BS>), c.ln_vec, c.stream, c.ln_vec, (S*)c.x, p, (S*)c.r,
+    MPRK_LAUNCH_KC(c, KC_CG_UPD, (k_cg_upd<S, C, VEC, BS>), c.ln_vec, c.ln_vec, (S*)c.x, p, (S*)c.r,
                 (const S*)c.q, z, (const S*)dinv, cfg, c.ctl, c.partials, c.pstride);
   }
   hipError_t cg_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
@@ -136,40 +184,37 @@ class EngineT final : public Engine {
   }
   hipError_t cg_finish(const EngineCtx& c) override {
     if (c.vec == 4)
-      MPRK_LAUNCH((k_promote<S, C, 4>), c.ln_vec, c.stream, c.ln_vec, c.y, (const S*)c.x, c.ctl);
+      MPRK_LAUNCH_KC(c, KC_PROMOTE, (k_promote<S, C, 4>), c.ln_vec, c.ln_vec, c.y, (const S*)c.x, c.ctl);
     else
-      MPRK_LAUNCH((k_promote<S, C, 1>), c.ln_vec, c.stream, c.ln_vec, c.y, (const S*)c.x, c.ctl);
+      MPRK_LAUNCH_KC(c, KC_PROMOTE, (k_promote<S, C, 1>), c.ln_vec, c.ln_vec, c.y, (const S*)c.x, c.ctl);
     return hipGetLastError();
   }
 
   // ---------------- GMRES ----------------
-  hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg) override {
-    if (c.vec == 4)
-      MPRK_LAUNCH((k_gm_begin<S, C, 4>), c.ln_vec, c.stream, c.ln_vec, c.res, (S*)c.V, cfg, c.ctl,
-                  c.partials, c.pstride);
-    else
-      MPRK_LAUNCH((k_gm_begin<S, C, 1>), c.ln_vec, c.stream, c.ln_vec, c.res, (S*)c.V, cfg, c.ctl,
-                  c.partials, c.pstride);
+  template <int VEC, int BS>
+  void gm_begin_t(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) {
+    MPRK_LAUNCH_KC(c, KC_GM_BEGIN, (k_gm_begin<S, C, VEC, BS>), c.ln_vec, c.ln_vec, c.res, (S*)c.V,
+                   (S*)c.z, (const S*)dinv, cfg, c.ctl, c.partials, c.pstride);
+  }
+  hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) override {
+    dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_begin_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
     return hipGetLastError();
   }
   template <int VEC, int FMT, int PREC>
   void gm_matvec_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc) {
     const Coef<C> M = cast_coef<C>(Mc);
     const C msig = (C)(cfg.sigma * c.kscale);
-    MPRK_LAUNCH((k_gm_matvec<S, C, VEC, FMT, PREC>), c.ln_mv, c.stream, c.ln_mv, c.geo, M, c.csr,
+    MPRK_LAUNCH_KC(c, KC_GM_MATVEC, (k_gm_matvec<S, C, VEC, FMT, PREC>), c.ln_mv, c.ln_mv, c.geo, M, c.csr,
                 (const S*)c.mval, msig, (const S*)c.z, (S*)c.V, c.vstride, cfg, c.ctl, c.partials,
                 c.pstride);
   }
   template <int VEC, int BS>
-  void gm_prec_t(const EngineCtx& c, const void* dinv) {
-    if constexpr (BS > 0)
-      MPRK_LAUNCH((k_gm_prec<S, C, VEC, BS>), c.ln_vec, c.stream, c.ln_vec, (const S*)c.V,
-                  c.vstride, (S*)c.z, (const S*)dinv, c.ctl);
+  void gm_orth_t(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) {
+    MPRK_LAUNCH_KC(c, KC_GM_ORTH, (k_gm_orth<S, C, VEC, BS>), c.ln_vec, c.ln_vec, (S*)c.V, c.vstride,
+                   (S*)c.z, (const S*)dinv, cfg, c.ctl, c.partials, c.pstride);
   }
   hipError_t gm_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
                      const void* dinv) override {
-    if (c.bs > 0)
-      dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_prec_t<decltype(vec)::value, decltype(bs)::value>(c, dinv); });
     const bool prec = c.bs > 0;
     if (c.fmt == 1) {
       if (prec) gm_matvec_t<1, 1, 1>(c, cfg, Mc); else gm_matvec_t<1, 1, 0>(c, cfg, Mc);
@@ -178,17 +223,12 @@ class EngineT final : public Engine {
     } else {
       if (prec) gm_matvec_t<1, 0, 1>(c, cfg, Mc); else gm_matvec_t<1, 0, 0>(c, cfg, Mc);
     }
-    if (c.vec == 4)
-      MPRK_LAUNCH((k_gm_orth<S, C, 4>), c.ln_vec, c.stream, c.ln_vec, (S*)c.V, c.vstride, cfg,
-                  c.ctl, c.partials, c.pstride);
-    else
-      MPRK_LAUNCH((k_gm_orth<S, C, 1>), c.ln_vec, c.stream, c.ln_vec, (S*)c.V, c.vstride, cfg,
-                  c.ctl, c.partials, c.pstride);
+    dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_orth_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
     return hipGetLastError();
   }
   template <int VEC, int BS>
   void gm_finish_t(const EngineCtx& c, const void* dinv) {
-    MPRK_LAUNCH((k_gm_finish<S, C, VEC, BS>), c.ln_vec, c.stream, c.ln_vec, c.y, (const S*)c.V,
+    MPRK_LAUNCH_KC(c, KC_GM_FINISH, (k_gm_finish<S, C, VEC, BS>), c.ln_vec, c.ln_vec, c.y, (const S*)c.V,
                 c.vstride, (const S*)dinv, c.ctl);
   }
   hipError_t gm_finish(const EngineCtx& c, const void* dinv) override {
@@ -201,7 +241,7 @@ class EngineT final : public Engine {
   void apply_m_t(const EngineCtx& c, const Coef<double>& Mc, double sigma, const void* x, void* y) {
     const Coef<C> M = cast_coef<C>(Mc);
     const C msig = (C)(sigma * c.kscale);
-    MPRK_LAUNCH((k_apply_lp<S, C, VEC, FMT>), c.ln_mv, c.stream, c.ln_mv, c.geo, M, c.csr,
+    MPRK_LAUNCH_KC(c, KC_APPLY64, (k_apply_lp<S, C, VEC, FMT>), c.ln_mv, c.ln_mv, c.geo, M, c.csr,
                 (const S*)c.mval, msig, (const S*)x, (S*)y);
   }
   hipError_t apply_m(const EngineCtx& c, const Coef<double>& Mc, double sigma, const void* x,
@@ -214,7 +254,7 @@ class EngineT final : public Engine {
   template <int VEC, int BS>
   void apply_bj_t(const EngineCtx& c, const void* dinv, const void* x, void* y) {
     if constexpr (BS > 0)
-      MPRK_LAUNCH((k_bj_apply<S, C, VEC, BS>), c.ln_vec, c.stream, c.ln_vec, (const S*)x, (S*)y,
+      MPRK_LAUNCH_KC(c, KC_APPLY64, (k_bj_apply<S, C, VEC, BS>), c.ln_vec, c.ln_vec, (const S*)x, (S*)y,
                   (const S*)dinv);
   }
   hipError_t apply_bj(const EngineCtx& c, const void* dinv, const void* x, void* y) override {

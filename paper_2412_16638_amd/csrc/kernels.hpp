@@ -8,7 +8,8 @@
 //   k_cg_begin / k_gm_begin   res -> LP, scaled to unit RMS (FP16 range; Section "Method
 //                        stability in the context of mixed precision" on rescaling)
 //   k_cg_dir, k_cg_upd   fused preconditioned CG iteration (heat, SPD)
-//   k_gm_prec, k_gm_matvec, k_gm_orth   one right-preconditioned GMRES Arnoldi step
+//   k_gm_matvec, k_gm_orth   one right-preconditioned GMRES Arnoldi step (the block-Jacobi
+//                        apply of the next direction is fused into k_gm_orth / k_gm_begin)
 //   k_promote / k_gm_finish   y += scale * delta (LP -> FP64)
 //   ... k_residual again; the stage ends when ||res|| <= outer_tol ||rhs||.
 //   k_keps       (FP64)  k^eps_i = (y - rhs) / sigma (only for tableaus with eps off-diagonals)
@@ -37,6 +38,7 @@ template <int VEC>
 __global__ __launch_bounds__(TPB) void k_stage_rhs(Launch ln, const double* __restrict__ u,
                                                    CombArgs a, double* __restrict__ rhs,
                                                    double* __restrict__ y, Ctl* ctl, int reset) {
+  count_work(ctl, KC_STAGE_RHS);
   if (reset && blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->outer_done = 0;
     ctl->inner_done = 0;
@@ -98,6 +100,7 @@ __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<doubl
                                                   double* __restrict__ res, SolveCfg cfg, Ctl* ctl,
                                                   double* partials, int pstride) {
   if (ctl->outer_done) return;
+  count_work(ctl, KC_RESIDUAL);
   const int L = xcd_block(ln.G);
   double acc[3] = {0.0, 0.0, 0.0};
   for (int it = 0; it < ln.nit; ++it) {
@@ -187,6 +190,7 @@ template <int VEC>
 __global__ __launch_bounds__(TPB) void k_combine(Launch ln, double* __restrict__ u, CombArgs a,
                                                  Ctl* ctl) {
   const int bad = ctl->step_nonfinite;
+  count_work(ctl, KC_COMBINE);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (bad) ctl->bad_steps += 1;
     else ctl->good_steps += 1;
@@ -272,6 +276,7 @@ __global__ __launch_bounds__(TPB) void k_cg_begin(Launch ln, const double* __res
                                                   const S* __restrict__ dinv, SolveCfg cfg,
                                                   Ctl* ctl, double* partials, int pstride) {
   if (ctl->outer_done) return;
+  count_work(ctl, KC_CG_BEGIN);
   const double inv = 1.0 / ctl->scale;
   const int L = xcd_block(ln.G);
   double acc[2] = {0.0, 0.0};
@@ -331,6 +336,7 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(Launch ln, Geo geo, Coef<C> M, C
                                                 S* __restrict__ q, Ctl* ctl, double* partials,
                                                 int pstride) {
   if (ctl->outer_done | ctl->inner_done) return;
+  count_work(ctl, KC_CG_DIR);
   const int first = ctl->iters == 0;
   InAxpy<C, S, VEC> f{z, pold, (C)ctl->beta, !first};
   const int L = xcd_block(ln.G);
@@ -372,6 +378,7 @@ __global__ __launch_bounds__(TPB) void k_cg_upd(Launch ln, S* __restrict__ x,
                                                 const S* __restrict__ dinv, SolveCfg cfg,
                                                 Ctl* ctl, double* partials, int pstride) {
   if (ctl->outer_done | ctl->inner_done) return;
+  count_work(ctl, KC_CG_UPD);
   const int first = ctl->iters == 0;
   const C alpha = (C)ctl->alpha;
   const int L = xcd_block(ln.G);
@@ -437,9 +444,11 @@ template <typename S, typename C, int VEC>
 __global__ __launch_bounds__(TPB) void k_promote(Launch ln, double* __restrict__ y,
                                                  const S* __restrict__ x, Ctl* ctl) {
   if (ctl->outer_done) return;
+  count_work(ctl, KC_PROMOTE);
   const double s = ctl->scale;
   const int have = ctl->iters > 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (ctl->passes < MAXPASS) ctl->pass_iters[ctl->passes] = ctl->iters;
     ctl->passes += 1;
     ctl->life_passes += 1;
   }
@@ -465,27 +474,41 @@ __global__ __launch_bounds__(TPB) void k_promote(Launch ln, double* __restrict__
 // residual is the FP64 residual of the outer loop.
 // ------------------------------------------------------------------------------------------
 
-template <typename S, typename C, int VEC>
+// A3 for GMRES: V_0 = LP(res / scale) ; zt = BJ(V_0) (the preconditioned direction of the first
+// Arnoldi step, before normalisation; BJ is linear) ; beta = ||V_0||_rms.
+template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __restrict__ res,
-                                                  S* __restrict__ v0, SolveCfg cfg, Ctl* ctl,
-                                                  double* partials, int pstride) {
+                                                  S* __restrict__ v0, S* __restrict__ zt,
+                                                  const S* __restrict__ dinv, SolveCfg cfg,
+                                                  Ctl* ctl, double* partials, int pstride) {
   if (ctl->outer_done) return;
+  count_work(ctl, KC_GM_BEGIN);
   const double inv = 1.0 / ctl->scale;
   const int L = xcd_block(ln.G);
   double acc[1] = {0.0};
   for (int it = 0; it < ln.nit; ++it) {
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;
-    if (g >= ln.ng) break;
-    double t[VEC];
+    const bool valid = g < ln.ng;
     C rv[VEC];
-    loadv<double, double, VEC>(res + g * VEC, t);
     C s = C(0);
+    if (valid) {
+      double t[VEC];
+      loadv<double, double, VEC>(res + g * VEC, t);
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      rv[v] = rnd<S, C>((C)(t[v] * inv));
-      s += rv[v] * rv[v];
+      for (int v = 0; v < VEC; ++v) {
+        rv[v] = rnd<S, C>((C)(t[v] * inv));
+        s += rv[v] * rv[v];
+      }
+      storev<S, C, VEC>(v0 + g * VEC, rv);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) rv[v] = C(0);
     }
-    storev<S, C, VEC>(v0 + g * VEC, rv);
+    if constexpr (BS > 0) {
+      C zv[VEC];
+      bj_apply_lane<C, S, VEC, BS>(dinv, g * VEC, valid, rv, zv);
+      if (valid) storev<S, C, VEC>(zt + g * VEC, zv);
+    }
     acc[0] += (double)s;
   }
   __shared__ double tot[1];
@@ -502,34 +525,8 @@ __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __res
   }
 }
 
-// z = BJ(v_j), v_j = vscale[j] * V_j
-template <typename S, typename C, int VEC, int BS>
-__global__ __launch_bounds__(TPB) void k_gm_prec(Launch ln, const S* __restrict__ V,
-                                                 size_t vstride, S* __restrict__ z,
-                                                 const S* __restrict__ dinv, Ctl* ctl) {
-  if (ctl->outer_done | ctl->inner_done) return;
-  const int j = ctl->J;
-  const C s = (C)ctl->vscale[j];
-  const S* vj = V + (size_t)j * vstride;
-  const int L = xcd_block(ln.G);
-  for (int it = 0; it < ln.nit; ++it) {
-    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
-    const bool valid = g < ln.ng;
-    C rv[VEC], zv[VEC];
-    if (valid) {
-      loadv<C, S, VEC>(vj + g * VEC, rv);
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) rv[v] *= s;
-    } else {
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) rv[v] = C(0);
-    }
-    bj_apply_lane<C, S, VEC, BS>(dinv, g * VEC, valid, rv, zv);
-    if (valid) storev<S, C, VEC>(z + g * VEC, zv);
-  }
-}
-
-// w = M z (PREC) or w = M v_j ; V_{j+1} := LP(w) ; d_i = (V_i, LP(w)) for i <= j.
+// w = M BJ(v_j) (PREC: zt holds BJ of the stored vector j, scaled here by vscale[j]) or
+// w = M v_j ; V_{j+1} := LP(w) ; d_i = (V_i, LP(w)) for i <= j.
 template <typename S, typename C, int VEC, int FMT, int PREC>
 __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M, Csr csr,
                                                    const S* __restrict__ mval, C msig,
@@ -538,6 +535,7 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
                                                    double* partials, int pstride) {
   if (ctl->outer_done | ctl->inner_done) return;
   const int j = ctl->J;
+  count_work(ctl, KC_GM_MATVEC, j + 1);
   const int nd = j + 1;
   S* wout = V + (size_t)(j + 1) * vstride;
   const int L = xcd_block(ln.G);
@@ -550,7 +548,7 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
     const int e = g * VEC;
     C ctr[VEC], w[VEC];
     if constexpr (PREC) {
-      In1<C, S, VEC> f{z};
+      InScaled<C, S, VEC> f{z, (C)ctl->vscale[j]};
       mlp_group<S, C, VEC, FMT>(geo, M, csr, mval, msig, g, f, ctr, w);
     } else {
       InScaled<C, S, VEC> f{V + (size_t)j * vstride, (C)ctl->vscale[j]};
@@ -579,24 +577,18 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
   if (threadIdx.x < nd) ctl->hcol[threadIdx.x] = ctl->vscale[threadIdx.x] * tot[threadIdx.x] * cfg.invN;
 }
 
-// Solve the J x J upper-triangular system H y = g (column-major, leading dim MAXM+1).
-__device__ inline void gm_backsolve(Ctl* ctl, int J) {
-  for (int i = J - 1; i >= 0; --i) {
-    double s = ctl->g[i];
-    for (int k = i + 1; k < J; ++k) s -= ctl->H[k * (MAXM + 1) + i] * ctl->ysol[k];
-    const double d = ctl->H[i * (MAXM + 1) + i];
-    ctl->ysol[i] = d != 0.0 ? s / d : 0.0;
-  }
-}
-
 // w -= sum_{i<=j} h_ij v_i (classical Gram-Schmidt, coefficients from k_gm_matvec);
 // h_{j+1,j} = ||w||; Givens update of the Hessenberg column; residual estimate |g_{j+1}|.
-template <typename S, typename C, int VEC>
+// With a preconditioner (BS > 0) also zt = BJ(w), the next step's preconditioned direction
+// before normalisation.
+template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, size_t vstride,
+                                                 S* __restrict__ zt, const S* __restrict__ dinv,
                                                  SolveCfg cfg, Ctl* ctl, double* partials,
                                                  int pstride) {
   if (ctl->outer_done | ctl->inner_done) return;
   const int j = ctl->J;
+  count_work(ctl, KC_GM_ORTH, j + 1);
   const int nd = j + 1;
   C cf[MAXD];
 #pragma unroll
@@ -606,26 +598,36 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
   double acc[1] = {0.0};
   for (int it = 0; it < ln.nit; ++it) {
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;
-    if (g >= ln.ng) break;
+    const bool valid = g < ln.ng;
     const int e = g * VEC;
     C wv[VEC];
-    loadv<C, S, VEC>(w + e, wv);
-#pragma unroll
-    for (int i = 0; i < MAXD; ++i) {
-      if (i < nd) {
-        C vi[VEC];
-        loadv<C, S, VEC>(V + (size_t)i * vstride + e, vi);
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) wv[v] -= cf[i] * vi[v];
-      }
-    }
     C s = C(0);
+    if (valid) {
+      loadv<C, S, VEC>(w + e, wv);
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      wv[v] = rnd<S, C>(wv[v]);
-      s += wv[v] * wv[v];
+      for (int i = 0; i < MAXD; ++i) {
+        if (i < nd) {
+          C vi[VEC];
+          loadv<C, S, VEC>(V + (size_t)i * vstride + e, vi);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) wv[v] -= cf[i] * vi[v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        wv[v] = rnd<S, C>(wv[v]);
+        s += wv[v] * wv[v];
+      }
+      storev<S, C, VEC>(w + e, wv);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) wv[v] = C(0);
     }
-    storev<S, C, VEC>(w + e, wv);
+    if constexpr (BS > 0) {
+      C zv[VEC];
+      bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, wv, zv);
+      if (valid) storev<S, C, VEC>(zt + e, zv);
+    }
     acc[0] += (double)s;
   }
   __shared__ double tot[1];
@@ -660,31 +662,43 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
     const double resid = fabs(ctl->g[J]);
     const bool fin = __builtin_isfinite(resid) && __builtin_isfinite(den);
     const bool stop = !fin || resid <= ctl->tol || hn == 0.0 || J >= cfg.m || its >= cfg.maxit;
-    if (stop) {
-      gm_backsolve(ctl, J);
-      if (!fin)
-        for (int i = 0; i < J; ++i) ctl->ysol[i] = 0.0;
-      ctl->inner_done = 1;
+    if (stop) ctl->inner_done = 1;
+    if (!fin) {  // drop this cycle: the promoted correction is zero
+      for (int i = 0; i <= J; ++i) ctl->g[i] = 0.0;
     }
   }
 }
 
-// A8 for GMRES: y += scale * BJ(sum_{i<J} ysol_i v_i) ; one LP pass done.
+// A8 for GMRES: y += scale * BJ(sum_{i<J} ysol_i v_i) ; one LP pass done.  The J x J
+// triangular least-squares system is solved here by every block (J <= 32), so a cycle the
+// host ends early (fewer iterations enqueued than the device would run) is still promoted.
 template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_gm_finish(Launch ln, double* __restrict__ y,
                                                    const S* __restrict__ V, size_t vstride,
                                                    const S* __restrict__ dinv, Ctl* ctl) {
   if (ctl->outer_done) return;
   const int J = ctl->J;
+  count_work(ctl, KC_GM_FINISH, J);
   const double sc = ctl->scale;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (ctl->passes < MAXPASS) ctl->pass_iters[ctl->passes] = ctl->iters;
     ctl->passes += 1;
     ctl->life_passes += 1;
   }
   if (J == 0) return;
+  __shared__ double ys[MAXM];
+  if (threadIdx.x == 0) {
+    for (int i = J - 1; i >= 0; --i) {
+      double acc = ctl->g[i];
+      for (int k = i + 1; k < J; ++k) acc -= ctl->H[k * (MAXM + 1) + i] * ys[k];
+      const double d = ctl->H[i * (MAXM + 1) + i];
+      ys[i] = (d != 0.0 && __builtin_isfinite(acc)) ? acc / d : 0.0;
+    }
+  }
+  __syncthreads();
   C cf[MAXM];
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) cf[i] = i < J ? (C)(ctl->ysol[i] * ctl->vscale[i]) : C(0);
+  for (int i = 0; i < MAXM; ++i) cf[i] = i < J ? (C)(ys[i] * ctl->vscale[i]) : C(0);
   const int L = xcd_block(ln.G);
   for (int it = 0; it < ln.nit; ++it) {
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;

@@ -25,6 +25,14 @@
 
 using namespace mprk;
 
+// launch with optional per-kernel event timing (member functions of mprk_handle)
+#define PLAUNCH(kc, ...)                   \
+  do {                                     \
+    if (prof_on) prof.before(kc);          \
+    hipLaunchKernelGGL(__VA_ARGS__);       \
+    if (prof_on) prof.after();             \
+  } while (0)
+
 #define HIPCHK(x)                                                                       \
   do {                                                                                  \
     hipError_t e_ = (x);                                                                \
@@ -481,14 +489,21 @@ int mprk_handle::make_device_resources() {
     std::memset(slots, 0, sizeof(CtlHead) * (NSLOT + MPRK_MAX_STAGES + 1));
   }
   for (int i = 0; i < NSLOT; ++i) HIPCHK(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+  HIPCHK(hipHostMalloc((void**)&rec_iters, sizeof(int) * MAXPASS * (MPRK_MAX_STAGES + 1)));
+  for (int i = 0; i <= MPRK_MAX_STAGES; ++i)
+    HIPCHK(hipEventCreateWithFlags(&rec_ev[i], hipEventDisableTiming));
+  prof.stream = stream;
   events_made = true;
   return MPRK_OK;
 }
 
 mprk_handle::~mprk_handle() {
-  if (events_made)
+  if (events_made) {
     for (int i = 0; i < NSLOT; ++i) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i <= MPRK_MAX_STAGES; ++i) (void)hipEventDestroy(rec_ev[i]);
+  }
   if (slots) (void)hipHostFree(slots);
+  if (rec_iters) (void)hipHostFree(rec_iters);
 }
 
 extern "C" int64_t mprk_workspace_bytes(const mprk_handle* h) {
@@ -499,6 +514,7 @@ extern "C" int64_t mprk_workspace_bytes(const mprk_handle* h) {
 
 EngineCtx mprk_handle::ctx() const {
   EngineCtx c{};
+  c.prof = prof_on ? const_cast<Profiler*>(&prof) : nullptr;
   c.stream = stream;
   c.geo = geo;
   c.fmt = op.format;
@@ -591,8 +607,33 @@ int mprk_handle::poll_wait(int s, CtlHead* out) {
   return MPRK_OK;
 }
 
-int mprk_handle::stage_record(int i) {
-  HIPCHK(hipMemcpyAsync(&slots[NSLOT + i], ws + o_ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, stream));
+int mprk_handle::stage_record(int slot) {
+  Ctl* ctl = (Ctl*)(ws + o_ctl);
+  HIPCHK(hipMemcpyAsync(&slots[NSLOT + slot], ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(rec_iters + slot * MAXPASS, ctl->pass_iters, sizeof(int) * MAXPASS,
+                        hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipEventRecord(rec_ev[slot], stream));
+  rec_pending[slot] = true;
+  return MPRK_OK;
+}
+
+// Fold the last record of `slot` into its history (waits for the record's copy, which has
+// normally landed long before).
+int mprk_handle::update_hist(int slot) {
+  if (!rec_pending[slot]) return MPRK_OK;
+  HIPCHK(hipEventSynchronize(rec_ev[slot]));
+  std::atomic_thread_fence(std::memory_order_acquire);
+  rec_pending[slot] = false;
+  CtlHead hd;
+  std::memcpy(&hd, (const void*)&slots[NSLOT + slot], sizeof(hd));
+  StageHist& H = hist[slot];
+  if (hd.nonfinite || !hd.converged || hd.passes <= 0 || hd.passes > MAXPASS) {
+    H.valid = false;
+    return MPRK_OK;
+  }
+  H.valid = true;
+  H.passes = hd.passes;
+  for (int p = 0; p < hd.passes; ++p) H.iters[p] = rec_iters[slot * MAXPASS + p];
   return MPRK_OK;
 }
 
@@ -608,19 +649,27 @@ int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* k
   const Csr csr{(const int*)(ws + o_rowptr), (const int*)(ws + o_col)};
   const double* kval = (const double*)(ws + o_kval);
   if (op.format == MPRK_FMT_CSR)
-    hipLaunchKernelGGL((k_residual<1, 1>), dim3(ln_row.G), dim3(TPB), 0, stream, ln_row, geo, Kc, csr,
+    PLAUNCH(KC_RESIDUAL, (k_residual<1, 1>), dim3(ln_row.G), dim3(TPB), 0, stream, ln_row, geo, Kc, csr,
                        kval, y, rhs, kout, res, cfg, ctl, part, pstride);
   else if (vec == 4)
-    hipLaunchKernelGGL((k_residual<4, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr,
+    PLAUNCH(KC_RESIDUAL, (k_residual<4, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr,
                        kval, y, rhs, kout, res, cfg, ctl, part, pstride);
   else
-    hipLaunchKernelGGL((k_residual<1, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr,
+    PLAUNCH(KC_RESIDUAL, (k_residual<1, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr,
                        kval, y, rhs, kout, res, cfg, ctl, part, pstride);
   HIPCHK(hipGetLastError());
   return MPRK_OK;
 }
 
-int mprk_handle::run_solve(int si, const double* rhs, double* y, double* kout) {
+// One implicit stage: FP64 residual -> LP Krylov solve -> FP64 update, repeated until the
+// device marks the stage finished.  With a valid history of this stage, each predicted pass
+// enqueues its Krylov iterations (last count + margin) and its promotion without waiting: an
+// inner solve cut short only leaves a larger FP64 residual for the next pass.  The host waits
+// for the device only where the history says the stage may already be finished.
+int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, double* kout) {
+  int rc = update_hist(slot);
+  if (rc) return rc;
+  const StageHist H = hist[slot];
   const SolveCfg& cfg = cfgs[si];
   EngineCtx c = ctx();
   c.y = y;
@@ -630,55 +679,59 @@ int mprk_handle::run_solve(int si, const double* rhs, double* y, double* kout) {
   const int P = cfg.paper_mode ? 1 : cfg.max_passes;
   const int maxp = cfg.maxit;
   const int chunk = cg ? cg_chunk : gm_chunk;
-  bool finished = false;
-  for (int pass = 0; pass <= P && !finished; ++pass) {
-    int rc = launch_residual(si, rhs, y, kout);
+  for (int pass = 0; pass <= P; ++pass) {
+    rc = launch_residual(si, rhs, y, kout);
     if (rc) return rc;
     if (pass == P) break;
-    struct Pend {
-      int slot;
-      bool krylov;
-    };
-    std::deque<Pend> pend;
-    int slot = 0;
-    rc = poll_enqueue(&slot);
-    if (rc) return rc;
-    pend.push_back({slot, false});
+    const bool certain = H.valid && pass < H.passes;
+    int slot_id = 0;
+    if (!certain) {
+      rc = poll_enqueue(&slot_id);
+      if (rc) return rc;
+      CtlHead hd;
+      rc = poll_wait(slot_id, &hd);
+      if (rc) return rc;
+      if (hd.outer_done) break;
+    }
     if (cg) HIPCHK(eng->cg_begin(c, cfg, dinv));
-    else HIPCHK(eng->gm_begin(c, cfg));
-    int its = 0;
-    bool inner = false;
-    while (its < maxp && !inner && !finished) {
-      const int cnt = std::min(chunk, maxp - its);
-      for (int k = 0; k < cnt; ++k) {
-        if (cg) HIPCHK(eng->cg_iter(c, cfg, Mc, dinv, its + k));
+    else HIPCHK(eng->gm_begin(c, cfg, dinv));
+    if (certain) {
+      const int n = std::min(maxp, H.iters[pass] + predict_margin);
+      for (int k = 0; k < n; ++k) {
+        if (cg) HIPCHK(eng->cg_iter(c, cfg, Mc, dinv, k));
         else HIPCHK(eng->gm_iter(c, cfg, Mc, dinv));
       }
-      its += cnt;
-      rc = poll_enqueue(&slot);
-      if (rc) return rc;
-      pend.push_back({slot, true});
-      while ((int)pend.size() > lookahead) {
-        const Pend pd = pend.front();
-        pend.pop_front();
-        CtlHead hd;
-        rc = poll_wait(pd.slot, &hd);
-        if (rc) return rc;
-        if (hd.outer_done) {
-          finished = true;
-          break;
+    } else {
+      std::deque<int> pend;
+      int its = 0;
+      bool inner = false, outer = false;
+      while (its < maxp && !inner && !outer) {
+        const int cnt = std::min(chunk, maxp - its);
+        for (int k = 0; k < cnt; ++k) {
+          if (cg) HIPCHK(eng->cg_iter(c, cfg, Mc, dinv, its + k));
+          else HIPCHK(eng->gm_iter(c, cfg, Mc, dinv));
         }
-        if (pd.krylov && hd.inner_done) {
-          inner = true;
-          break;
+        its += cnt;
+        rc = poll_enqueue(&slot_id);
+        if (rc) return rc;
+        pend.push_back(slot_id);
+        while ((int)pend.size() > lookahead) {
+          const int sl = pend.front();
+          pend.pop_front();
+          CtlHead hd;
+          rc = poll_wait(sl, &hd);
+          if (rc) return rc;
+          if (hd.outer_done) outer = true;
+          if (hd.inner_done) inner = true;
+          if (inner || outer) break;
         }
       }
+      if (outer) break;
     }
-    if (finished) break;
     if (cg) HIPCHK(eng->cg_finish(c));
     else HIPCHK(eng->gm_finish(c, dinv));
   }
-  return MPRK_OK;
+  return stage_record(slot);
 }
 
 int mprk_handle::enqueue_step() {
@@ -711,25 +764,23 @@ int mprk_handle::enqueue_step() {
     }
     const int reset = i == 0 ? 2 : 1;
     if (vec == 4)
-      hipLaunchKernelGGL((k_stage_rhs<4>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, rhs, y, ctl, reset);
+      PLAUNCH(KC_STAGE_RHS, (k_stage_rhs<4>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, rhs, y, ctl, reset);
     else
-      hipLaunchKernelGGL((k_stage_rhs<1>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, rhs, y, ctl, reset);
+      PLAUNCH(KC_STAGE_RHS, (k_stage_rhs<1>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, rhs, y, ctl, reset);
     HIPCHK(hipGetLastError());
     if (!implicit_[i]) {
       int rc = launch_apply64(y, kvec(i), 0.0, 0);
       if (rc) return rc;
       continue;
     }
-    int rc = run_solve(sig_idx[i], rhs, y, kvec(i));
-    if (rc) return rc;
-    rc = stage_record(i);
+    int rc = run_solve(sig_idx[i], i, rhs, y, kvec(i));
     if (rc) return rc;
     if (need_keps) {
       const double inv = 1.0 / cfgs[sig_idx[i]].sigma;
       if (vec == 4)
-        hipLaunchKernelGGL((k_keps<4>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, y, rhs, inv, evec(i));
+        PLAUNCH(KC_KEPS, (k_keps<4>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, y, rhs, inv, evec(i));
       else
-        hipLaunchKernelGGL((k_keps<1>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, y, rhs, inv, evec(i));
+        PLAUNCH(KC_KEPS, (k_keps<1>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, y, rhs, inv, evec(i));
       HIPCHK(hipGetLastError());
     }
   }
@@ -741,9 +792,9 @@ int mprk_handle::enqueue_step() {
       a.c[a.nv++] = dt * tab.b[i];
     }
   if (vec == 4)
-    hipLaunchKernelGGL((k_combine<4>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, ctl);
+    PLAUNCH(KC_COMBINE, (k_combine<4>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, ctl);
   else
-    hipLaunchKernelGGL((k_combine<1>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, ctl);
+    PLAUNCH(KC_COMBINE, (k_combine<1>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, ctl);
   HIPCHK(hipGetLastError());
   return MPRK_OK;
 }
@@ -752,13 +803,13 @@ int mprk_handle::launch_apply64(const double* x, double* y, double sigma, int mo
   const Csr csr{(const int*)(ws + o_rowptr), (const int*)(ws + o_col)};
   const double* kval = (const double*)(ws + o_kval);
   if (op.format == MPRK_FMT_CSR)
-    hipLaunchKernelGGL((k_apply64<1, 1>), dim3(ln_row.G), dim3(TPB), 0, stream, ln_row, geo, Kc, csr, kval,
+    PLAUNCH(KC_APPLY64, (k_apply64<1, 1>), dim3(ln_row.G), dim3(TPB), 0, stream, ln_row, geo, Kc, csr, kval,
                        x, y, sigma, mode);
   else if (vec == 4)
-    hipLaunchKernelGGL((k_apply64<4, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr, kval,
+    PLAUNCH(KC_APPLY64, (k_apply64<4, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr, kval,
                        x, y, sigma, mode);
   else
-    hipLaunchKernelGGL((k_apply64<1, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr, kval,
+    PLAUNCH(KC_APPLY64, (k_apply64<1, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr, kval,
                        x, y, sigma, mode);
   HIPCHK(hipGetLastError());
   return MPRK_OK;
@@ -843,7 +894,7 @@ extern "C" int32_t mprk_solve(mprk_handle* h, int32_t stage, const double* rhs_d
     hipLaunchKernelGGL((k_stage_rhs<1>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, rhs_dev, a, rhs,
                        x_dev, ctl, 1);
   HIPCHK(hipGetLastError());
-  int rc = h->run_solve(h->sig_idx[stage], rhs, x_dev, (double*)(h->ws + h->o_scr));
+  int rc = h->run_solve(h->sig_idx[stage], MPRK_MAX_STAGES, rhs, x_dev, (double*)(h->ws + h->o_scr));
   if (rc) return rc;
   CtlHead hd;
   HIPCHK(hipMemcpyAsync(&hd, ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, h->stream));
@@ -915,6 +966,54 @@ extern "C" int32_t mprk_stats_sync(mprk_handle* h, mprk_stats* out) {
   if (!h || !out) return set_error(MPRK_EINVAL, "NULL argument");
   if (h->bound) HIPCHK(hipStreamSynchronize(h->stream));
   h->fill_stats(out);
+  return MPRK_OK;
+}
+
+static int read_counters(mprk_handle* h, long long* worked, long long* units) {
+  Ctl* ctl = (Ctl*)(h->ws + h->o_ctl);
+  HIPCHK(hipMemcpyAsync(worked, ctl->worked, sizeof(long long) * KC_COUNT, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(units, ctl->units, sizeof(long long) * KC_COUNT, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_profile(mprk_handle* h, int32_t enable) {
+  if (!h) return set_error(MPRK_EINVAL, "NULL handle");
+  if (!h->bound) return set_error(MPRK_ESTATE, "mprk_profile before mprk_bind");
+  if (enable) {
+    int rc = read_counters(h, h->worked0, h->units0);
+    if (rc) return rc;
+    h->prof.stream = h->stream;
+    h->prof.reset();
+    h->prof_on = true;
+  } else {
+    h->prof_on = false;
+  }
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_profile_read(mprk_handle* h, int32_t kclass, int64_t* launches,
+                                     int64_t* worked, int64_t* units, double* total_ms) {
+  if (!h) return set_error(MPRK_EINVAL, "NULL handle");
+  if (!h->bound) return set_error(MPRK_ESTATE, "mprk_profile_read before mprk_bind");
+  if (kclass < 0 || kclass >= KC_COUNT) return set_error(MPRK_EINVAL, "bad kernel class");
+  long long w[KC_COUNT], u[KC_COUNT];
+  int rc = read_counters(h, w, u);
+  if (rc) return rc;
+  if (h->prof.failed) return set_error(MPRK_EDEVICE, "profiling event creation/record failed");
+  double ms = 0.0;
+  long long n = 0;
+  for (const auto& r : h->prof.recs) {
+    if (r.kc != kclass) continue;
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, h->prof.pool[r.e0], h->prof.pool[r.e1]));
+    ms += t;
+    ++n;
+  }
+  if (launches) *launches = n;
+  if (worked) *worked = w[kclass] - h->worked0[kclass];
+  if (units) *units = u[kclass] - h->units0[kclass];
+  if (total_ms) *total_ms = ms;
   return MPRK_OK;
 }
 

@@ -72,6 +72,22 @@ struct mprk_handle {
   int cg_chunk = 4;
   int gm_chunk = 2;
   int lookahead = 1;
+  int predict_margin = 1;
+  // per-stage history of the last completed solve (slot s = mprk_solve), used to enqueue each
+  // pass's Krylov iterations without waiting for the device
+  struct StageHist {
+    bool valid = false;
+    int passes = 0;
+    int iters[mprk::MAXPASS] = {};
+  };
+  StageHist hist[MPRK_MAX_STAGES + 1];
+  bool rec_pending[MPRK_MAX_STAGES + 1] = {};
+  int* rec_iters = nullptr;                   // pinned: MAXPASS ints per slot
+  hipEvent_t rec_ev[MPRK_MAX_STAGES + 1] = {};
+  // profiling
+  mprk::Profiler prof;
+  bool prof_on = false;
+  long long worked0[mprk::KC_COUNT] = {}, units0[mprk::KC_COUNT] = {};
   // state
   double t_now = 0.0;
   long long step_count = 0;
@@ -87,10 +103,11 @@ struct mprk_handle {
   mprk::EngineCtx ctx() const;
   int poll_enqueue(int* slot);
   int poll_wait(int s, mprk::CtlHead* out);
-  int stage_record(int i);
+  int stage_record(int slot);
+  int update_hist(int slot);
   int launch_residual(int si, const double* rhs, double* y, double* kout);
   int launch_apply64(const double* x, double* y, double sigma, int mode);
-  int run_solve(int si, const double* rhs, double* y, double* kout);
+  int run_solve(int si, int slot, const double* rhs, double* y, double* kout);
   int enqueue_step();
   int sync_counters();
   void fill_stats(mprk_stats* st);

@@ -118,3 +118,60 @@ def from_problem(p, fmt: int = A.FMT_STENCIL, prec=None, device: str = 'cuda:0',
     if p.u0 is not None:
         s.set_u(p.u0)
     return s
+
+
+class Batch:
+    """Many independent problems advanced together (one persistent launch per stage)."""
+
+    def __init__(self, problems, tab='SDIRK3', prec=None, device: str = 'cuda:0'):
+        if not torch.cuda.is_available():
+            raise RuntimeError('mprk needs a HIP device (torch.cuda.is_available() is False)')
+        self.device = torch.device(device)
+        self.tab = tableau(tab) if isinstance(tab, str) else tab
+        self.prec = prec if prec is not None else precisions('fp32', 'cg')
+        descs = []
+        self.shapes = []
+        for p in problems:
+            sh = (p['shape'],) * 3 if isinstance(p['shape'], int) else tuple(p['shape'])
+            self.shapes.append(sh)
+            g = A.mprk_grid(sh[0], sh[1], sh[2], p.get('bc', A.BC_DIRICHLET0))
+            o = A.mprk_operator(p.get('kind', A.OP_HEAT), A.FMT_STENCIL, p['diff'],
+                                (A.C.c_double * 3)(*p.get('b', (0.0, 0.0, 0.0))))
+            descs.append(A.mprk_problem(g, o, p['dt']))
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.h = A.mprk_batch_create(descs, self.tab, self.prec, self.stream.cuda_stream)
+            self.ws_bytes = A.mprk_batch_workspace_bytes(self.h)
+            self.u = [torch.zeros(s[0] * s[1] * s[2], dtype=torch.float64, device=self.device)
+                      for s in self.shapes]
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            A.mprk_batch_bind(self.h, [t.data_ptr() for t in self.u], self.ws.data_ptr(),
+                              self.ws_bytes)
+
+    def set_u(self, i: int, u) -> None:
+        if isinstance(u, np.ndarray):
+            u = torch.from_numpy(np.ascontiguousarray(u, dtype=np.float64).ravel())
+        self.u[i].copy_(u.reshape(-1).to(self.device, torch.float64))
+        torch.cuda.synchronize(self.device)
+
+    def get_u(self, i: int) -> np.ndarray:
+        torch.cuda.synchronize(self.device)
+        s = self.shapes[i]
+        return self.u[i].cpu().numpy().reshape(s[2], s[1], s[0])
+
+    def step(self, nsteps: int = 1) -> None:
+        A.check(A.mprk_batch_step(self.h, nsteps), 'mprk_batch_step')
+
+    def stats(self, i: int) -> dict:
+        return A.mprk_batch_stats_sync(self.h, i)
+
+    def close(self) -> None:
+        if getattr(self, 'h', None):
+            A.mprk_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

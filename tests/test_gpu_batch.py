@@ -1,0 +1,79 @@
+"""Batched form (one persistent launch per stage, hipGraph replay) vs the FP64 oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import log_case, reference_solution, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+M = pytest.importorskip('paper_2412_16638_amd')
+A = M._abi
+
+
+def _run_batch(probs, prec, nsteps):
+    b = M.Batch([{'shape': p.n, 'diff': p.diff, 'dt': p.dt} for p in probs], 'SDIRK3', prec)
+    for i, p in enumerate(probs):
+        b.set_u(i, p.u0)
+    b.step(nsteps)
+    us = [b.get_u(i) for i in range(len(probs))]
+    st = [b.stats(i) for i in range(len(probs))]
+    b.close()
+    return us, st
+
+
+def test_small_uneven_batch_matches_oracle():
+    probs = W.heat_batch(count=6, nmin=13, nmax=40, nsteps=5)
+    log_case('batch6', sizes=[p.n for p in probs])
+    us, st = _run_batch(probs, M.precisions('fp32', 'cg'), 5)
+    for p, u, s in zip(probs, us, st):
+        p.nsteps = 5
+        err = rel_l2(u, reference_solution(p))
+        print(p.n, round(p.diff, 3), err, s['iters'], s['passes'])
+        assert s['steps'] == 5
+        assert err <= 1e-6
+
+
+def test_batch_fp64_matches_oracle_tightly():
+    probs = W.heat_batch(count=3, nmin=16, nmax=24, nsteps=3)
+    log_case('batch3_fp64')
+    us, st = _run_batch(probs, M.precisions('fp64', 'cg'), 3)
+    for p, u in zip(probs, us):
+        p.nsteps = 3
+        assert rel_l2(u, reference_solution(p)) <= 1e-12
+
+
+def test_batch_is_deterministic():
+    probs = W.heat_batch(count=4, nmin=16, nmax=48, nsteps=2)
+    log_case('batch_repro')
+    a, _ = _run_batch(probs, M.precisions('fp32', 'cg'), 2)
+    b, _ = _run_batch(probs, M.precisions('fp32', 'cg'), 2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_batch_result_equals_single_problem_within_tolerance():
+    probs = W.heat_batch(count=3, nmin=20, nmax=32, nsteps=4)
+    log_case('batch_vs_alone')
+    us, _ = _run_batch(probs, M.precisions('fp32', 'cg'), 4)
+    for p, u in zip(probs, us):
+        p.nsteps = 4
+        st = M.from_problem(p)
+        st.step(4)
+        alone = st.get_u()
+        st.close()
+        assert rel_l2(u, alone) <= 1e-6
+
+
+def test_full_batch_64_problems():
+    # 64 heat problems, n uniform in [16, 96], kappa log-uniform in [0.1, 10], 20 steps
+    probs = W.heat_batch()
+    log_case('batch64', total_dof=sum(p.N for p in probs))
+    us, st = _run_batch(probs, M.precisions('fp32', 'cg'), 20)
+    worst = 0.0
+    for p, u, s in zip(probs, us, st):
+        err = rel_l2(u, reference_solution(p))
+        worst = max(worst, err)
+        assert s['steps'] == 20
+    print('batch64 worst rel-L2', worst)
+    assert worst <= 1e-6
