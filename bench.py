@@ -128,6 +128,10 @@ def main():
     ap.add_argument('--fmt', default='stencil', choices=['stencil', 'csr'])
     ap.add_argument('--no-fp64', action='store_true', help='skip the FP64 matched-error leg')
     ap.add_argument('--no-cpu', action='store_true', help='skip the oracle / cpu_baseline leg')
+    ap.add_argument('--quick', action='store_true',
+                    help='profiling runs: skip the full-integration error check and side legs')
+    ap.add_argument('--bj', default='per-block', choices=['per-block', 'shared'],
+                    help='block-Jacobi inverse storage of the headline run')
     ap.add_argument('--calib-copy', type=int, default=0, metavar='MIB',
                     help='first run a plain device copy of this many MiB (counter calibration)')
     args = ap.parse_args()
@@ -143,6 +147,7 @@ def main():
 
     assert torch.cuda.is_available(), 'bench.py needs a GPU'
     fmt = AB.FMT_STENCIL if args.fmt == 'stencil' else AB.FMT_CSR
+    bjs = 1 if args.bj == 'shared' else 0
     if args.calib_copy:
         n = args.calib_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device='cuda')
@@ -165,16 +170,20 @@ def main():
         log(f'oracle done in {t_oracle:.1f} s')
 
     # ---- mixed path: parity run of the full integration ----
-    log('mixed path: full integration for the error check ...')
-    u_mixed, st_mixed = run_integration(M, p, fmt)
     err_mixed = None
-    if ref is not None:
+    st_mixed = None
+    if not args.quick:
+        log('mixed path: full integration for the error check ...')
+        u_mixed, st_mixed = run_integration(M, p, fmt, bj_shared=bjs)
+    if ref is not None and st_mixed is not None:
         err_mixed = float(np.linalg.norm(u_mixed - ref) / np.linalg.norm(ref))
         log(f'mixed rel-L2 vs oracle = {err_mixed:.3e}  iters/stage={st_mixed["iters"]} '
             f'passes/stage={st_mixed["passes"]}')
 
     # ---- timed mixed run ----
-    st = M.from_problem(p, fmt=fmt)
+    st = M.from_problem(p, fmt=fmt, bj_shared=bjs)
+    tuned = st.autotune()
+    log(f'autotuned groups per thread (vector, row) = {tuned}')
     t_mixed, stats, _ = time_steps(st, p.u0, K, Wm)
     value = N * K / t_mixed
     log(f'mixed: {K} steps in {t_mixed * 1e3:.2f} ms -> {value:.4e} DOF-steps/s')
@@ -225,7 +234,7 @@ def main():
     fp64 = None
     if not args.no_fp64 and ref is not None:
         for tol in (1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8, 1e-9, 1e-10):
-            over = dict(rtol=tol, outer_tol=tol)
+            over = dict(rtol=tol, outer_tol=tol, bj_shared=bjs)
             q = make_problem(args.workload)
             q.precision = 'fp64'
             u64, s64 = run_integration(M, q, fmt, **over)
@@ -233,6 +242,7 @@ def main():
             log(f'fp64 rtol={tol:.0e}: rel-L2 {e64:.3e} iters/stage={s64["iters"]}')
             if e64 <= err_mixed:
                 st64 = M.from_problem(q, fmt=fmt, **over)
+                st64.autotune()
                 t64, _, _ = time_steps(st64, q.u0, K, Wm)
                 st64.close()
                 v64 = N * K / t64
@@ -240,6 +250,17 @@ def main():
                         'ms_per_step': t64 * 1e3 / K}
                 log(f'fp64 matched: {v64:.4e} DOF-steps/s; mixed speedup {value / v64:.2f}x')
                 break
+
+    # ---- the other block-Jacobi storage (same values; per-block inverse stream or not) ----
+    other = None
+    if not args.no_fp64 and not args.quick:
+        st2 = M.from_problem(p, fmt=fmt, bj_shared=1 - bjs)
+        st2.autotune()
+        t2, _, _ = time_steps(st2, p.u0, K, Wm)
+        st2.close()
+        other = {'bj': 'per-block' if bjs else 'shared', 'value': N * K / t2,
+                 'ms_per_step': t2 * 1e3 / K}
+        log(f'other block-Jacobi storage ({other["bj"]}): {other["value"]:.4e} DOF-steps/s')
 
     cpu = None
     if t_oracle is not None:
@@ -262,6 +283,9 @@ def main():
         'err_vs_oracle': err_mixed,
         'iters_per_stage': stats['iters'], 'passes_per_stage': stats['passes'],
         'fp64_matched': fp64,
+        'bj_storage': args.bj,
+        'autotuned_groups_per_thread': list(tuned),
+        'other_bj_storage': other,
         'speedup_vs_fp64_matched': (value / fp64['value']) if fp64 else None,
         'roofline': roofline,
         'cpu_baseline': cpu,

@@ -101,7 +101,11 @@ typedef struct {
  *           refine_max = 0 is the paper's one-shot mode: exactly one LP solve (for GMRES one
  *           cycle) on the converted right-hand side, no residual check.
  *  strict: make a stage that misses outer_tol an error (MPRK_ENOTCONV).
- *  reorth: GMRES classical Gram-Schmidt with one re-orthogonalisation pass (CGS2). */
+ *  reorth: GMRES classical Gram-Schmidt with one re-orthogonalisation pass (CGS2).
+ *  bj_shared: 0 = one stored inverse per block-Jacobi block (default); 1 = store each distinct
+ *           diagonal block's inverse once plus a per-block index (a single shared inverse when
+ *           all blocks coincide, e.g. constant coefficients with block | nx).  Both modes give
+ *           bitwise-identical inverses; mode 1 removes the inverse stream from the apply. */
 typedef struct {
   int32_t storage, compute;
   int32_t krylov, restart;
@@ -112,6 +116,7 @@ typedef struct {
   double outer_tol;
   int32_t strict;
   int32_t reorth;
+  int32_t bj_shared;
 } mprk_precisions;
 
 /* Statistics.  Per-stage entries describe the most recent step. */
@@ -191,6 +196,14 @@ int32_t mprk_set_state(mprk_handle *h, double t, int64_t step);
 /* Wait for the stream and return the statistics of the most recent step. */
 int32_t mprk_stats_sync(mprk_handle *h, mprk_stats *out);
 
+/* Autotuner: times candidate launch shapes (groups of unknowns per thread, hence workgroups
+ * per launch, for the vector/stencil kernels and, with CSR, rows per thread) on the bound
+ * workspace with the handle's own LP SpMV and FP64 operator kernels, keeps the fastest, and
+ * caches the choice per (grid, operator, precision, format) for the life of the process.
+ * Uses the workspace's Krylov vectors as scratch (state u is not touched).  Waits for the
+ * stream.  *nit_vec / *nit_row (may be NULL) receive the chosen groups per thread. */
+int32_t mprk_autotune(mprk_handle *h, int32_t *nit_vec, int32_t *nit_row);
+
 /* Kernel classes for mprk_profile_read. */
 enum { MPRK_KC_STAGE_RHS = 0, MPRK_KC_RESIDUAL, MPRK_KC_CG_BEGIN, MPRK_KC_CG_DIR, MPRK_KC_CG_UPD,
        MPRK_KC_PROMOTE, MPRK_KC_GM_BEGIN, MPRK_KC_GM_PREC, MPRK_KC_GM_MATVEC, MPRK_KC_GM_ORTH,
@@ -227,6 +240,12 @@ typedef struct mprk_batch mprk_batch;
  * for GMRES, CSR or FP16/FP32 compute combinations the batched kernel does not implement. */
 int32_t mprk_batch_create(int32_t count, const mprk_problem *problems, const mprk_tableau *tab,
                           const mprk_precisions *prec, void *hip_stream, mprk_batch **out);
+/* CTA-group schedule: workgroups per problem.  By default they are planned in proportion to an
+ * estimate of each problem's work (unknowns x sqrt of the stage matrix's condition number),
+ * at least one each, within the device's co-resident capacity.  set_schedule (before sizing or
+ * binding; NULL restores the plan) fixes them; get_schedule returns the plan in use. */
+int32_t mprk_batch_set_schedule(mprk_batch *b, const int32_t *wg_per_problem);
+int32_t mprk_batch_get_schedule(mprk_batch *b, int32_t *wg_per_problem);
 int64_t mprk_batch_workspace_bytes(const mprk_batch *b);
 /* u_dev: array of `count` device pointers (problem p's state, N_p doubles each). */
 int32_t mprk_batch_bind(mprk_batch *b, double *const *u_dev, void *workspace_dev, int64_t bytes);

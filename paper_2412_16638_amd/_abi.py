@@ -53,7 +53,7 @@ class mprk_precisions(C.Structure):
                 ('restart', C.c_int32), ('precond', C.c_int32), ('block', C.c_int32),
                 ('rtol', C.c_double), ('atol', C.c_double), ('maxit', C.c_int32),
                 ('refine_max', C.c_int32), ('outer_tol', C.c_double), ('strict', C.c_int32),
-                ('reorth', C.c_int32)]
+                ('reorth', C.c_int32), ('bj_shared', C.c_int32)]
 
 
 class mprk_stats(C.Structure):
@@ -109,6 +109,7 @@ _sig = {
     'mprk_get_state': (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     'mprk_set_state': (C.c_int32, [_P, C.c_double, C.c_int64]),
     'mprk_stats_sync': (C.c_int32, [_P, C.POINTER(mprk_stats)]),
+    'mprk_autotune': (C.c_int32, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     'mprk_profile': (C.c_int32, [_P, C.c_int32]),
     'mprk_profile_read': (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -116,6 +117,8 @@ _sig = {
     'mprk_destroy': (None, [_P]),
     'mprk_batch_create': (C.c_int32, [C.c_int32, C.POINTER(mprk_problem), C.POINTER(mprk_tableau),
                                       C.POINTER(mprk_precisions), _P, C.POINTER(_P)]),
+    'mprk_batch_set_schedule': (C.c_int32, [_P, C.POINTER(C.c_int32)]),
+    'mprk_batch_get_schedule': (C.c_int32, [_P, C.POINTER(C.c_int32)]),
     'mprk_batch_workspace_bytes': (C.c_int64, [_P]),
     'mprk_batch_bind': (C.c_int32, [_P, C.POINTER(_P), _P, C.c_int64]),
     'mprk_batch_step': (C.c_int32, [_P, C.c_int32]),
@@ -210,6 +213,12 @@ def mprk_stats_sync(h: int) -> dict:
     return st.as_dict()
 
 
+def mprk_autotune(h: int):
+    a, b = C.c_int32(), C.c_int32()
+    check(lib.mprk_autotune(_P(h), C.byref(a), C.byref(b)), 'mprk_autotune')
+    return a.value, b.value
+
+
 def mprk_profile(h: int, enable: bool) -> None:
     check(lib.mprk_profile(_P(h), 1 if enable else 0), 'mprk_profile')
 
@@ -235,6 +244,20 @@ def mprk_batch_create(problems, tab: mprk_tableau, prec: mprk_precisions, stream
     check(lib.mprk_batch_create(len(problems), arr, C.byref(tab), C.byref(prec), _P(stream),
                                 C.byref(h)), 'mprk_batch_create')
     return h.value
+
+
+def mprk_batch_set_schedule(b: int, wg_per_problem) -> None:
+    if wg_per_problem is None:
+        check(lib.mprk_batch_set_schedule(_P(b), None), 'mprk_batch_set_schedule')
+        return
+    arr = (C.c_int32 * len(wg_per_problem))(*wg_per_problem)
+    check(lib.mprk_batch_set_schedule(_P(b), arr), 'mprk_batch_set_schedule')
+
+
+def mprk_batch_get_schedule(b: int, count: int):
+    arr = (C.c_int32 * count)()
+    check(lib.mprk_batch_get_schedule(_P(b), arr), 'mprk_batch_get_schedule')
+    return list(arr)
 
 
 def mprk_batch_workspace_bytes(b: int) -> int:

@@ -62,20 +62,25 @@ struct BArgs {
   int maxit, max_passes, paper_mode, bs;
 };
 
+// Barrier over the nwg workgroups of one problem.  Every thread fences before the workgroup
+// barrier (its own global stores must reach the device-coherent level: the workgroup barrier
+// alone does not wait for other waves' stores, and the group's workgroups may sit on other XCDs
+// with their own L2) and again after it (acquire before reading halo data written by others).
 __device__ bool group_barrier(BCtl* c, int nwg) {
+  if (nwg > 1) __threadfence();
   __syncthreads();
   if (nwg > 1) {
     if (threadIdx.x == 0) {
-      __threadfence();
-      const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned arrived = atomicAdd(&c->bar_count, 1u);
+      // acquire: the generation must be read before this workgroup's arrival is counted
+      const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
       if (arrived == (unsigned)nwg - 1u) {
         __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        atomicAdd(&c->bar_gen, 1u);
+        __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         long spins = 0;
-        while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
           __builtin_amdgcn_s_sleep(2);
           if (++spins > BAR_SPIN_LIMIT) {
             __hip_atomic_store(&c->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -83,9 +88,9 @@ __device__ bool group_barrier(BCtl* c, int nwg) {
           }
         }
       }
-      __threadfence();
     }
     __syncthreads();
+    __threadfence();
   }
   return true;
 }
@@ -155,7 +160,7 @@ __global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
   const double sigma = P.sigma;
   const double sqrtN = sqrt((double)N);
   double* kout = P.k + (size_t)stage * N;
-  const S* dinv = (const S*)P.dinv;
+  const BJ<S> dinv{(const S*)P.dinv, nullptr, 0};
   S* r = (S*)P.r;
   S* z = BS > 0 ? (S*)P.z : (S*)P.r;
   S* q = (S*)P.q;
@@ -353,6 +358,7 @@ struct mprk_batch {
   hipGraphExec_t gexec = nullptr;
   long long good_base = 0;
   std::vector<long long> good_seen, bad_seen;
+  std::vector<int> fixed_wg;  // caller-chosen workgroups per problem (empty: planned)
   ~mprk_batch() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -466,14 +472,21 @@ static int plan_groups(mprk_batch* b, int capacity) {
   b->N.assign(b->count, 0);
   int avail = capacity - b->count;
   if (avail < 0) return set_error(MPRK_EUNSUPPORTED, "more problems than co-resident workgroups");
+  int fixed_total = 0;
   for (int p = 0; p < b->count; ++p) {
     const mprk_grid& g = b->probs[p].grid;
     const int N = g.nx * g.ny * g.nz;
     b->N[p] = N;
     const int maxwg = std::max(1, (N + 63) / 64);
+    if (!b->fixed_wg.empty()) {
+      b->nwg[p] = std::min(maxwg, std::max(1, b->fixed_wg[p]));
+      fixed_total += b->nwg[p];
+      continue;
+    }
     int extra = (int)std::floor(avail * w[p] / W);
     b->nwg[p] = std::min(maxwg, 1 + extra);
   }
+  if (fixed_total > capacity) return set_error(MPRK_EINVAL, "schedule exceeds co-resident workgroups");
   int G = 0;
   for (int p = 0; p < b->count; ++p) {
     const int N = b->N[p];
@@ -527,6 +540,24 @@ static int batch_capacity(mprk_batch* b, int* cap) {
     return set_error(MPRK_EDEVICE, "occupancy query failed");
   // stay one workgroup per CU below the occupancy bound
   *cap = std::max(1, cus * std::max(1, per - 1));
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_batch_set_schedule(mprk_batch* b, const int32_t* wg_per_problem) {
+  if (!b) return set_error(MPRK_EINVAL, "NULL batch");
+  if (b->ws_bytes) return set_error(MPRK_ESTATE, "schedule must be set before sizing/binding");
+  if (!wg_per_problem) {
+    b->fixed_wg.clear();
+    return MPRK_OK;
+  }
+  b->fixed_wg.assign(wg_per_problem, wg_per_problem + b->count);
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_batch_get_schedule(mprk_batch* b, int32_t* wg_per_problem) {
+  if (!b || !wg_per_problem) return set_error(MPRK_EINVAL, "NULL argument");
+  if (mprk_batch_workspace_bytes(b) < 0) return MPRK_EINVAL;
+  for (int p = 0; p < b->count; ++p) wg_per_problem[p] = b->nwg[p];
   return MPRK_OK;
 }
 
@@ -632,7 +663,8 @@ extern "C" int32_t mprk_batch_bind(mprk_batch* b, double* const* u_dev, void* wo
       c.stream = b->stream;
       c.geo = hp[p].geo;
       c.bs = b->bs;
-      BHIP(eng->bj_setup_stencil(c, stage_coef(hp[p].K, hp[p].sigma), hp[p].dinv, fail));
+      const int nblk = (c.geo.N + b->bs - 1) / b->bs;
+      BHIP(eng->bj_setup_stencil(c, stage_coef(hp[p].K, hp[p].sigma), hp[p].dinv, fail, nblk, nullptr));
     }
   }
   int hfail = 0;

@@ -204,22 +204,22 @@ __device__ bool reduce_to_last(const double (&v)[ND], int nd, double* __restrict
   }
   __syncthreads();
   if (!am_last) return false;
-  __threadfence();
-  // fixed-order total: 8 lanes per value, strided over blocks, then an ordered combine
-  __shared__ double part8[ND][8];
-  for (int task = threadIdx.x; task < nd * 8; task += TPB) {
-    const int d = task >> 3, r = task & 7;
+  __threadfence();  // acquire: the other blocks' partials are visible after this
+  // fixed-order total: every thread sums a strided, coalesced slice of each value's partials,
+  // then a fixed shuffle tree and a fixed-order combine of the waves
+  __shared__ double wtot[NWAVE][ND];
+  for (int d = 0; d < nd; ++d) {
     const double* p = partials + d * pstride;
     double s = 0.0;
-    for (int b = r; b < G; b += 8)
-      s += __hip_atomic_load(p + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    part8[d][r] = s;
+    for (int b = threadIdx.x; b < G; b += TPB) s += p[b];
+    s = wave_sum(s);
+    if (lane == 0) wtot[wave][d] = s;
   }
   __syncthreads();
   if (threadIdx.x < nd) {
     double s = 0.0;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) s += part8[threadIdx.x][r];
+    for (int w = 0; w < NWAVE; ++w) s += wtot[w][threadIdx.x];
     tot[threadIdx.x] = s;
   }
   if (threadIdx.x == 0) *ticket = 0u;
@@ -346,12 +346,41 @@ __device__ __forceinline__ C csr_row(const Csr& m, const SV* __restrict__ val, i
   return acc;
 }
 
+// Block-Jacobi inverses.  mode 0: one stored inverse per block (row r's BS entries at
+// inv[r * BS]); mode 1: a table of distinct inverses and idx[block] selecting one; mode 2: a
+// single inverse shared by every block (constant-coefficient operators with BS | nx).
+struct BJDesc {
+  const void* inv;
+  const int* idx;
+  int mode;
+};
+
+template <typename S>
+struct BJ {
+  const S* __restrict__ inv;
+  const int* __restrict__ idx;
+  int mode;
+};
+
+template <typename S>
+__host__ __device__ inline BJ<S> bj_typed(const BJDesc& d) {
+  return BJ<S>{(const S*)d.inv, d.idx, d.mode};
+}
+
+template <typename S, int BS>
+__device__ __forceinline__ const S* bj_row(const BJ<S>& bj, int r) {
+  if (bj.mode == 0) return bj.inv + (size_t)r * BS;
+  const int within = r & (BS - 1);
+  const int b = bj.mode == 2 ? 0 : bj.idx[r / BS];
+  return bj.inv + ((size_t)b * BS + within) * BS;
+}
+
 // Block-Jacobi: z = D^{-1} r for the VEC rows of this lane.  Inverse rows are stored
 // contiguously: row i's BS entries at dinv[i*BS].  Blocks of BS rows; when BS > VEC a block
 // spans BS/VEC consecutive lanes whose values are exchanged by shuffles (every lane of the
 // wave must call this).
 template <typename C, typename S, int VEC, int BS>
-__device__ __forceinline__ void bj_apply_lane(const S* __restrict__ dinv, int e, bool valid,
+__device__ __forceinline__ void bj_apply_lane(const BJ<S>& dinv, int e, bool valid,
                                               const C (&r)[VEC], C (&z)[VEC]) {
   if constexpr (BS <= VEC) {
 #pragma unroll
@@ -359,7 +388,7 @@ __device__ __forceinline__ void bj_apply_lane(const S* __restrict__ dinv, int e,
 #pragma unroll
       for (int i = 0; i < BS; ++i) {
         C row[BS];
-        if (valid) loadv<C, S, BS>(dinv + (size_t)(e + sb * BS + i) * BS, row);
+        if (valid) loadv<C, S, BS>(bj_row<S, BS>(dinv, e + sb * BS + i), row);
         C acc = C(0);
 #pragma unroll
         for (int k = 0; k < BS; ++k) acc += row[k] * r[sb * BS + k];
@@ -376,7 +405,7 @@ __device__ __forceinline__ void bj_apply_lane(const S* __restrict__ dinv, int e,
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
       C row[BS];
-      if (valid) loadv<C, S, BS>(dinv + (size_t)(e + i) * BS, row);
+      if (valid) loadv<C, S, BS>(bj_row<S, BS>(dinv, e + i), row);
       C acc = C(0);
 #pragma unroll
       for (int k = 0; k < BS; ++k) acc += row[k] * rb[k];

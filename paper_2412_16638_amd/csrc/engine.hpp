@@ -61,9 +61,11 @@ struct EngineCtx {
   Geo geo;
   int fmt;            // 0 stencil, 1 CSR
   int vec;            // 4 or 1 (vector kernels)
-  Launch ln_vec;      // groups of `vec` elements
+  Launch ln_vec;      // groups of `vec` elements (streaming kernels)
   Launch ln_row;      // CSR rows (VEC = 1)
   Launch ln_mv;       // launch of the SpMV kernels (= ln_vec for stencil, ln_row for CSR)
+  Launch ln_red;      // groups of `vec` elements, kernels with a grid reduction (<= 2048 blocks)
+  Launch ln_mv_red;   // SpMV kernels with a grid reduction
   int bs;             // block-Jacobi block size (0 = no preconditioner)
   Csr csr;
   const void* mval;   // LP CSR values of K / kscale (S)
@@ -83,23 +85,26 @@ class Engine {
  public:
   virtual ~Engine() {}
   // setup
-  virtual hipError_t bj_setup_stencil(const EngineCtx& c, const Coef<double>& Mc, void* dinv, int* fail) = 0;
-  virtual hipError_t bj_setup_csr(const EngineCtx& c, const double* kval, double sigma, void* dinv, int* fail) = 0;
+  // invert nslot diagonal blocks (block reps[i] into slot i; reps == nullptr: every block)
+  virtual hipError_t bj_setup_stencil(const EngineCtx& c, const Coef<double>& Mc, void* dinv,
+                                      int* fail, int nslot, const int* reps) = 0;
+  virtual hipError_t bj_setup_csr(const EngineCtx& c, const double* kval, double sigma, void* dinv,
+                                  int* fail, int nslot, const int* reps) = 0;
   virtual hipError_t csr_values(const EngineCtx& c, long nnz, const double* kval, void* out) = 0;
   // CG
-  virtual hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) = 0;
+  virtual hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) = 0;
   virtual hipError_t cg_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
-                             const void* dinv, int it) = 0;
+                             const BJDesc& dinv, int it) = 0;
   virtual hipError_t cg_finish(const EngineCtx& c) = 0;
   // GMRES
-  virtual hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) = 0;
+  virtual hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) = 0;
   virtual hipError_t gm_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
-                             const void* dinv) = 0;
-  virtual hipError_t gm_finish(const EngineCtx& c, const void* dinv) = 0;
+                             const BJDesc& dinv) = 0;
+  virtual hipError_t gm_finish(const EngineCtx& c, const BJDesc& dinv) = 0;
   // verification access
   virtual hipError_t apply_m(const EngineCtx& c, const Coef<double>& Mc, double sigma,
                              const void* x, void* y) = 0;
-  virtual hipError_t apply_bj(const EngineCtx& c, const void* dinv, const void* x, void* y) = 0;
+  virtual hipError_t apply_bj(const EngineCtx& c, const BJDesc& dinv, const void* x, void* y) = 0;
   virtual int elem_bytes() const = 0;
 };
 
@@ -124,16 +129,16 @@ class EngineT final : public Engine {
  public:
   int elem_bytes() const override { return (int)sizeof(S); }
 
-  hipError_t bj_setup_stencil(const EngineCtx& c, const Coef<double>& Mc, void* dinv, int* fail) override {
-    const int nblk = (c.geo.N + c.bs - 1) / c.bs;
-    hipLaunchKernelGGL(k_bj_setup_stencil<S>, dim3((nblk + 127) / 128), dim3(128), 0, c.stream,
-                       nblk, c.bs, c.geo, Mc, (S*)dinv, fail);
+  hipError_t bj_setup_stencil(const EngineCtx& c, const Coef<double>& Mc, void* dinv, int* fail,
+                              int nslot, const int* reps) override {
+    hipLaunchKernelGGL(k_bj_setup_stencil<S>, dim3((nslot + 127) / 128), dim3(128), 0, c.stream,
+                       nslot, c.bs, c.geo, Mc, (S*)dinv, fail, reps);
     return hipGetLastError();
   }
-  hipError_t bj_setup_csr(const EngineCtx& c, const double* kval, double sigma, void* dinv, int* fail) override {
-    const int nblk = (c.geo.N + c.bs - 1) / c.bs;
-    hipLaunchKernelGGL(k_bj_setup_csr<S>, dim3((nblk + 127) / 128), dim3(128), 0, c.stream, nblk,
-                       c.bs, c.geo.N, c.csr, kval, sigma, (S*)dinv, fail);
+  hipError_t bj_setup_csr(const EngineCtx& c, const double* kval, double sigma, void* dinv, int* fail,
+                          int nslot, const int* reps) override {
+    hipLaunchKernelGGL(k_bj_setup_csr<S>, dim3((nslot + 127) / 128), dim3(128), 0, c.stream, nslot,
+                       c.bs, c.geo.N, c.csr, kval, sigma, (S*)dinv, fail, reps);
     return hipGetLastError();
   }
   hipError_t csr_values(const EngineCtx& c, long nnz, const double* kval, void* out) override {
@@ -145,12 +150,12 @@ class EngineT final : public Engine {
 
   // ---------------- CG ----------------
   template <int VEC, int BS>
-  void cg_begin_t(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) {
+  void cg_begin_t(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) {
     S* z = BS > 0 ? (S*)c.z : (S*)c.r;
-    MPRK_LAUNCH_KC(c, KC_CG_BEGIN, (k_cg_begin<S, C, VEC, BS>), c.ln_vec, c.ln_vec, c.res, (S*)c.r, z,
-                (const S*)dinv, cfg, c.ctl, c.partials, c.pstride);
+    MPRK_LAUNCH_KC(c, KC_CG_BEGIN, (k_cg_begin<S, C, VEC, BS>), c.ln_red, c.ln_red, c.res, (S*)c.r, z,
+                bj_typed<S>(dinv), cfg, c.ctl, c.partials, c.pstride);
   }
-  hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) override {
+  hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) override {
     dispatch_vec_bs(c, [&](auto vec, auto bs) { cg_begin_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
     return hipGetLastError();
   }
@@ -160,17 +165,17 @@ class EngineT final : public Engine {
                 const S* pold, S* pnew) {
     const Coef<C> M = cast_coef<C>(Mc);
     const C msig = (C)(cfg.sigma * c.kscale);
-    MPRK_LAUNCH_KC(c, KC_CG_DIR, (k_cg_dir<S, C, VEC, FMT>), c.ln_mv, c.ln_mv, c.geo, M, c.csr,
+    MPRK_LAUNCH_KC(c, KC_CG_DIR, (k_cg_dir<S, C, VEC, FMT>), c.ln_mv_red, c.ln_mv_red, c.geo, M, c.csr,
                 (const S*)c.mval, msig, z, pold, pnew, (S*)c.q, c.ctl, c.partials, c.pstride);
   }
   template <int VEC, int BS>
-  void cg_upd_t(const EngineCtx& c, const SolveCfg& cfg, const S* p, const void* dinv) {
+  void cg_upd_t(const EngineCtx& c, const SolveCfg& cfg, const S* p, const BJDesc& dinv) {
     S* z = BS > 0 ? (S*)c.z : (S*)c.r;
-    MPRK_LAUNCH_KC(c, KC_CG_UPD, (k_cg_upd<S, C, VEC, BS>), c.ln_vec, c.ln_vec, (S*)c.x, p, (S*)c.r,
-                (const S*)c.q, z, (const S*)dinv, cfg, c.ctl, c.partials, c.pstride);
+    MPRK_LAUNCH_KC(c, KC_CG_UPD, (k_cg_upd<S, C, VEC, BS>), c.ln_red, c.ln_red, (S*)c.x, p, (S*)c.r,
+                (const S*)c.q, z, bj_typed<S>(dinv), cfg, c.ctl, c.partials, c.pstride);
   }
   hipError_t cg_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
-                     const void* dinv, int it) override {
+                     const BJDesc& dinv, int it) override {
     const S* z = c.bs > 0 ? (const S*)c.z : (const S*)c.r;
     const S* pold = (it & 1) ? (const S*)c.p1 : (const S*)c.p0;
     S* pnew = (it & 1) ? (S*)c.p0 : (S*)c.p1;
@@ -192,11 +197,11 @@ class EngineT final : public Engine {
 
   // ---------------- GMRES ----------------
   template <int VEC, int BS>
-  void gm_begin_t(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) {
-    MPRK_LAUNCH_KC(c, KC_GM_BEGIN, (k_gm_begin<S, C, VEC, BS>), c.ln_vec, c.ln_vec, c.res, (S*)c.V,
-                   (S*)c.z, (const S*)dinv, cfg, c.ctl, c.partials, c.pstride);
+  void gm_begin_t(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) {
+    MPRK_LAUNCH_KC(c, KC_GM_BEGIN, (k_gm_begin<S, C, VEC, BS>), c.ln_red, c.ln_red, c.res, (S*)c.V,
+                   (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.partials, c.pstride);
   }
-  hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) override {
+  hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) override {
     dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_begin_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
     return hipGetLastError();
   }
@@ -204,17 +209,17 @@ class EngineT final : public Engine {
   void gm_matvec_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc) {
     const Coef<C> M = cast_coef<C>(Mc);
     const C msig = (C)(cfg.sigma * c.kscale);
-    MPRK_LAUNCH_KC(c, KC_GM_MATVEC, (k_gm_matvec<S, C, VEC, FMT, PREC>), c.ln_mv, c.ln_mv, c.geo, M, c.csr,
+    MPRK_LAUNCH_KC(c, KC_GM_MATVEC, (k_gm_matvec<S, C, VEC, FMT, PREC>), c.ln_mv_red, c.ln_mv_red, c.geo, M, c.csr,
                 (const S*)c.mval, msig, (const S*)c.z, (S*)c.V, c.vstride, cfg, c.ctl, c.partials,
                 c.pstride);
   }
   template <int VEC, int BS>
-  void gm_orth_t(const EngineCtx& c, const SolveCfg& cfg, const void* dinv) {
-    MPRK_LAUNCH_KC(c, KC_GM_ORTH, (k_gm_orth<S, C, VEC, BS>), c.ln_vec, c.ln_vec, (S*)c.V, c.vstride,
-                   (S*)c.z, (const S*)dinv, cfg, c.ctl, c.partials, c.pstride);
+  void gm_orth_t(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) {
+    MPRK_LAUNCH_KC(c, KC_GM_ORTH, (k_gm_orth<S, C, VEC, BS>), c.ln_red, c.ln_red, (S*)c.V, c.vstride,
+                   (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.partials, c.pstride);
   }
   hipError_t gm_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
-                     const void* dinv) override {
+                     const BJDesc& dinv) override {
     const bool prec = c.bs > 0;
     if (c.fmt == 1) {
       if (prec) gm_matvec_t<1, 1, 1>(c, cfg, Mc); else gm_matvec_t<1, 1, 0>(c, cfg, Mc);
@@ -227,11 +232,11 @@ class EngineT final : public Engine {
     return hipGetLastError();
   }
   template <int VEC, int BS>
-  void gm_finish_t(const EngineCtx& c, const void* dinv) {
+  void gm_finish_t(const EngineCtx& c, const BJDesc& dinv) {
     MPRK_LAUNCH_KC(c, KC_GM_FINISH, (k_gm_finish<S, C, VEC, BS>), c.ln_vec, c.ln_vec, c.y, (const S*)c.V,
-                c.vstride, (const S*)dinv, c.ctl);
+                c.vstride, bj_typed<S>(dinv), c.ctl);
   }
-  hipError_t gm_finish(const EngineCtx& c, const void* dinv) override {
+  hipError_t gm_finish(const EngineCtx& c, const BJDesc& dinv) override {
     dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_finish_t<decltype(vec)::value, decltype(bs)::value>(c, dinv); });
     return hipGetLastError();
   }
@@ -252,12 +257,12 @@ class EngineT final : public Engine {
     return hipGetLastError();
   }
   template <int VEC, int BS>
-  void apply_bj_t(const EngineCtx& c, const void* dinv, const void* x, void* y) {
+  void apply_bj_t(const EngineCtx& c, const BJDesc& dinv, const void* x, void* y) {
     if constexpr (BS > 0)
       MPRK_LAUNCH_KC(c, KC_APPLY64, (k_bj_apply<S, C, VEC, BS>), c.ln_vec, c.ln_vec, (const S*)x, (S*)y,
-                  (const S*)dinv);
+                  bj_typed<S>(dinv));
   }
-  hipError_t apply_bj(const EngineCtx& c, const void* dinv, const void* x, void* y) override {
+  hipError_t apply_bj(const EngineCtx& c, const BJDesc& dinv, const void* x, void* y) override {
     if (c.bs == 0) return hipErrorInvalidValue;
     dispatch_vec_bs(c, [&](auto vec, auto bs) { apply_bj_t<decltype(vec)::value, decltype(bs)::value>(c, dinv, x, y); });
     return hipGetLastError();

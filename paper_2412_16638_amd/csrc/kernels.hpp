@@ -249,7 +249,7 @@ __global__ __launch_bounds__(TPB) void k_apply_lp(Launch ln, Geo geo, Coef<C> M,
 
 template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_bj_apply(Launch ln, const S* __restrict__ r,
-                                                  S* __restrict__ z, const S* __restrict__ dinv) {
+                                                  S* __restrict__ z, BJ<S> dinv) {
   const int L = xcd_block(ln.G);
   for (int it = 0; it < ln.nit; ++it) {
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(TPB) void k_bj_apply(Launch ln, const S* __restrict
 template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_cg_begin(Launch ln, const double* __restrict__ res,
                                                   S* __restrict__ r, S* __restrict__ z,
-                                                  const S* __restrict__ dinv, SolveCfg cfg,
+                                                  BJ<S> dinv, SolveCfg cfg,
                                                   Ctl* ctl, double* partials, int pstride) {
   if (ctl->outer_done) return;
   count_work(ctl, KC_CG_BEGIN);
@@ -375,7 +375,7 @@ template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_cg_upd(Launch ln, S* __restrict__ x,
                                                 const S* __restrict__ p, S* __restrict__ r,
                                                 const S* __restrict__ q, S* __restrict__ z,
-                                                const S* __restrict__ dinv, SolveCfg cfg,
+                                                BJ<S> dinv, SolveCfg cfg,
                                                 Ctl* ctl, double* partials, int pstride) {
   if (ctl->outer_done | ctl->inner_done) return;
   count_work(ctl, KC_CG_UPD);
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(TPB) void k_promote(Launch ln, double* __restrict__
 template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __restrict__ res,
                                                   S* __restrict__ v0, S* __restrict__ zt,
-                                                  const S* __restrict__ dinv, SolveCfg cfg,
+                                                  BJ<S> dinv, SolveCfg cfg,
                                                   Ctl* ctl, double* partials, int pstride) {
   if (ctl->outer_done) return;
   count_work(ctl, KC_GM_BEGIN);
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
 // before normalisation.
 template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, size_t vstride,
-                                                 S* __restrict__ zt, const S* __restrict__ dinv,
+                                                 S* __restrict__ zt, BJ<S> dinv,
                                                  SolveCfg cfg, Ctl* ctl, double* partials,
                                                  int pstride) {
   if (ctl->outer_done | ctl->inner_done) return;
@@ -675,7 +675,7 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
 template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_gm_finish(Launch ln, double* __restrict__ y,
                                                    const S* __restrict__ V, size_t vstride,
-                                                   const S* __restrict__ dinv, Ctl* ctl) {
+                                                   BJ<S> dinv, Ctl* ctl) {
   if (ctl->outer_done) return;
   const int J = ctl->J;
   count_work(ctl, KC_GM_FINISH, J);
@@ -788,11 +788,14 @@ __device__ inline void bj_store(S* dinv, int blk, int BS, int n, const double (&
 }
 
 // Diagonal blocks of M = I - sigma K for the stencil operator (Mc = stencil of M in FP64).
+// Slot i receives the inverse of block reps[i] (reps == nullptr: block i), so the per-block
+// table and the table of distinct blocks come from the same arithmetic.
 template <typename S>
-__global__ void k_bj_setup_stencil(int nblk, int BS, Geo geo, Coef<double> Mc, S* dinv,
-                                   int* fail) {
-  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blk >= nblk) return;
+__global__ void k_bj_setup_stencil(int nslot, int BS, Geo geo, Coef<double> Mc, S* dinv,
+                                   int* fail, const int* reps) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslot) return;
+  const int blk = reps ? reps[slot] : slot;
   const int r0 = blk * BS;
   const int n = min(BS, geo.N - r0);
   double a[BJ_MAX][BJ_MAX], inv[BJ_MAX][BJ_MAX];
@@ -810,15 +813,16 @@ __global__ void k_bj_setup_stencil(int nblk, int BS, Geo geo, Coef<double> Mc, S
     }
   }
   if (gj_invert(a, inv, n)) atomicOr(fail, 1);
-  bj_store<S>(dinv, blk, BS, n, inv);
+  bj_store<S>(dinv, slot, BS, n, inv);
 }
 
-// Diagonal blocks of M = I - sigma K from the FP64 CSR values of K.
+// Diagonal blocks of M = I - sigma K from the FP64 CSR values of K (slots as above).
 template <typename S>
-__global__ void k_bj_setup_csr(int nblk, int BS, int N, Csr csr, const double* kval, double sigma,
-                               S* dinv, int* fail) {
-  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blk >= nblk) return;
+__global__ void k_bj_setup_csr(int nslot, int BS, int N, Csr csr, const double* kval, double sigma,
+                               S* dinv, int* fail, const int* reps) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslot) return;
+  const int blk = reps ? reps[slot] : slot;
   const int r0 = blk * BS;
   const int n = min(BS, N - r0);
   double a[BJ_MAX][BJ_MAX], inv[BJ_MAX][BJ_MAX];
@@ -832,7 +836,7 @@ __global__ void k_bj_setup_csr(int nblk, int BS, int N, Csr csr, const double* k
     }
   }
   if (gj_invert(a, inv, n)) atomicOr(fail, 1);
-  bj_store<S>(dinv, blk, BS, n, inv);
+  bj_store<S>(dinv, slot, BS, n, inv);
 }
 
 // LP copy of the CSR values of K, scaled by a power of two into [-1, 1].

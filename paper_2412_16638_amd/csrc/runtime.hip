@@ -16,7 +16,11 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mprk.h"
@@ -47,6 +51,19 @@ thread_local std::string g_err;
 int set_error(int code, const std::string& msg) {
   g_err = msg;
   return code;
+}
+
+Launch make_launch_nit(long ng, int nit) {
+  long G = (ng + (long)nit * TPB - 1) / ((long)nit * TPB);
+  G = std::max(8L, (G + 7) / 8 * 8);
+  return Launch{(int)ng, nit, (int)G};
+}
+
+// Launch of a kernel with a last-block reduction: at most `max_blocks` blocks (the last block
+// reads every block's partials).
+Launch make_launch_red(long ng, int max_blocks) {
+  long nit = (ng + (long)TPB * max_blocks - 1) / ((long)TPB * max_blocks);
+  return make_launch_nit(ng, (int)std::max(1L, nit));
 }
 
 Launch make_launch(long ng) {
@@ -152,6 +169,50 @@ void assemble_csr(const Geo& geo, const Coef<double>& K, std::vector<int>& rowpt
     const int m = csr_row_entries(geo, K, r, col.data() + pos, val.data() + pos);
     pos += m;
     rowptr[(size_t)r + 1] = (int)pos;
+  }
+}
+
+// Distinct diagonal blocks of M = I - sigma K (block size bs, lexicographic blocks).  reps[i] is
+// the first block with the i-th distinct value set; idx[b] the distinct slot of block b.  The key
+// is the exact FP64 block, so equal keys give equal inverses.
+static void bj_dedup(const Geo& geo, const Coef<double>& K, double sigma, int bs,
+                     std::vector<int>& reps, std::vector<int>& idx) {
+  const int N = geo.N;
+  const int nblk = (N + bs - 1) / bs;
+  reps.clear();
+  idx.assign((size_t)nblk, 0);
+  std::unordered_map<std::string, int> seen;
+  std::string key, last_key;
+  int last = -1;
+  int c[7];
+  double v[7];
+  for (int b = 0; b < nblk; ++b) {
+    const int r0 = b * bs, n = std::min(bs, N - r0);
+    double D[BJ_MAX * BJ_MAX] = {};
+    for (int i = 0; i < n; ++i) {
+      D[i * BJ_MAX + i] += 1.0;
+      const int m = csr_row_entries(geo, K, r0 + i, c, v);
+      for (int e = 0; e < m; ++e)
+        if (c[e] >= r0 && c[e] < r0 + n) D[i * BJ_MAX + (c[e] - r0)] -= sigma * v[e];
+    }
+    key.assign((const char*)D, sizeof(D));
+    key.push_back((char)n);
+    if (last >= 0 && key == last_key) {
+      idx[(size_t)b] = last;
+      continue;
+    }
+    auto it = seen.find(key);
+    int slot;
+    if (it == seen.end()) {
+      slot = (int)reps.size();
+      reps.push_back(b);
+      seen.emplace(key, slot);
+    } else {
+      slot = it->second;
+    }
+    idx[(size_t)b] = slot;
+    last = slot;
+    last_key = key;
   }
 }
 
@@ -409,7 +470,9 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   // launches
   ln_vec = make_launch(N / vec);
   ln_row = make_launch(N);
-  pstride = std::max(ln_vec.G, ln_row.G);
+  ln_vec_red = make_launch_red(N / vec, RED_MAX_BLOCKS);
+  ln_row_red = make_launch_red(N, RED_MAX_BLOCKS);
+  pstride = std::max(ln_vec_red.G, ln_row_red.G);
   bs = p.precond == MPRK_PRECOND_BJ ? p.block : 0;
   nblk = bs ? (N + bs - 1) / bs : 0;
   // CSR size (assembled at bind)
@@ -450,8 +513,22 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
     o_r = o_p0 = o_p1 = o_q = o_x = 0;
   }
   vstride = vlp / lp_bytes;
-  o_dinv = bs ? take((size_t)nblk * bs * bs * lp_bytes * sigmas.size()) : 0;
-  dinv_stride = (size_t)nblk * bs * bs * lp_bytes;
+  bjsets.assign(bs ? sigmas.size() : 0, BJSet());
+  for (size_t q = 0; q < bjsets.size(); ++q) {
+    BJSet& B = bjsets[q];
+    if (p.bj_shared) {
+      bj_dedup(geo, Kc, sigmas[q], bs, B.reps, B.idx);
+      B.nslot = (int)B.reps.size();
+      B.mode = B.nslot == 1 ? 2 : 1;
+      if (B.mode == 2) B.idx.clear();
+    } else {
+      B.nslot = nblk;
+      B.mode = 0;
+    }
+    B.o_inv = take((size_t)B.nslot * bs * bs * lp_bytes);
+    if (B.mode) B.o_reps = take((size_t)B.nslot * 4);
+    if (B.mode == 1) B.o_idx = take((size_t)nblk * 4);
+  }
   if (o.format == MPRK_FMT_CSR) {
     o_rowptr = take((size_t)(N + 1) * 4);
     o_col = take((size_t)nnz * 4);
@@ -522,6 +599,8 @@ EngineCtx mprk_handle::ctx() const {
   c.ln_vec = ln_vec;
   c.ln_row = ln_row;
   c.ln_mv = op.format == MPRK_FMT_CSR ? ln_row : ln_vec;
+  c.ln_red = ln_vec_red;
+  c.ln_mv_red = op.format == MPRK_FMT_CSR ? ln_row_red : ln_vec_red;
   c.bs = bs;
   c.csr = Csr{(const int*)(ws + o_rowptr), (const int*)(ws + o_col)};
   c.mval = ws + o_mval;
@@ -567,14 +646,21 @@ extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev,
     HIPCHK(hipStreamSynchronize(h->stream));  // host vectors go out of scope
   }
   int* fail = (int*)(h->ws + h->o_flag);
-  if (h->bs) {
-    for (size_t q = 0; q < h->sigmas.size(); ++q) {
-      void* dinv = h->ws + h->o_dinv + q * h->dinv_stride;
-      if (h->op.format == MPRK_FMT_CSR)
-        HIPCHK(h->eng->bj_setup_csr(c, (const double*)(h->ws + h->o_kval), h->sigmas[q], dinv, fail));
-      else
-        HIPCHK(h->eng->bj_setup_stencil(c, stage_coef(h->Kc, h->sigmas[q]), dinv, fail));
+  for (size_t q = 0; q < h->bjsets.size(); ++q) {
+    const mprk_handle::BJSet& B = h->bjsets[q];
+    void* dinv = h->ws + B.o_inv;
+    const int* reps = nullptr;
+    if (B.mode) {
+      HIPCHK(hipMemcpyAsync(h->ws + B.o_reps, B.reps.data(), B.reps.size() * 4, hipMemcpyHostToDevice, h->stream));
+      reps = (const int*)(h->ws + B.o_reps);
     }
+    if (B.mode == 1)
+      HIPCHK(hipMemcpyAsync(h->ws + B.o_idx, B.idx.data(), B.idx.size() * 4, hipMemcpyHostToDevice, h->stream));
+    if (h->op.format == MPRK_FMT_CSR)
+      HIPCHK(h->eng->bj_setup_csr(c, (const double*)(h->ws + h->o_kval), h->sigmas[q], dinv, fail,
+                                  B.nslot, reps));
+    else
+      HIPCHK(h->eng->bj_setup_stencil(c, stage_coef(h->Kc, h->sigmas[q]), dinv, fail, B.nslot, reps));
   }
   int hfail = 0;
   HIPCHK(hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -641,6 +727,12 @@ int mprk_handle::update_hist(int slot) {
 // the stage solve (outer FP64 residual loop around the LP Krylov solve)
 // ------------------------------------------------------------------------------------------
 
+BJDesc mprk_handle::bj_desc(int si) const {
+  if (!bs || si < 0 || si >= (int)bjsets.size()) return BJDesc{nullptr, nullptr, 0};
+  const BJSet& B = bjsets[si];
+  return BJDesc{ws + B.o_inv, B.mode == 1 ? (const int*)(ws + B.o_idx) : nullptr, B.mode};
+}
+
 int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* kout) {
   const SolveCfg& cfg = cfgs[si];
   Ctl* ctl = (Ctl*)(ws + o_ctl);
@@ -649,13 +741,13 @@ int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* k
   const Csr csr{(const int*)(ws + o_rowptr), (const int*)(ws + o_col)};
   const double* kval = (const double*)(ws + o_kval);
   if (op.format == MPRK_FMT_CSR)
-    PLAUNCH(KC_RESIDUAL, (k_residual<1, 1>), dim3(ln_row.G), dim3(TPB), 0, stream, ln_row, geo, Kc, csr,
+    PLAUNCH(KC_RESIDUAL, (k_residual<1, 1>), dim3(ln_row_red.G), dim3(TPB), 0, stream, ln_row_red, geo, Kc, csr,
                        kval, y, rhs, kout, res, cfg, ctl, part, pstride);
   else if (vec == 4)
-    PLAUNCH(KC_RESIDUAL, (k_residual<4, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr,
+    PLAUNCH(KC_RESIDUAL, (k_residual<4, 0>), dim3(ln_vec_red.G), dim3(TPB), 0, stream, ln_vec_red, geo, Kc, csr,
                        kval, y, rhs, kout, res, cfg, ctl, part, pstride);
   else
-    PLAUNCH(KC_RESIDUAL, (k_residual<1, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr,
+    PLAUNCH(KC_RESIDUAL, (k_residual<1, 0>), dim3(ln_vec_red.G), dim3(TPB), 0, stream, ln_vec_red, geo, Kc, csr,
                        kval, y, rhs, kout, res, cfg, ctl, part, pstride);
   HIPCHK(hipGetLastError());
   return MPRK_OK;
@@ -673,7 +765,7 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
   const SolveCfg& cfg = cfgs[si];
   EngineCtx c = ctx();
   c.y = y;
-  const void* dinv = bs ? (const void*)(ws + o_dinv + si * dinv_stride) : nullptr;
+  const BJDesc dinv = bj_desc(si);
   const Coef<double> Mc = stage_coef(Kc, cfg.sigma);
   const bool cg = prec.krylov == MPRK_CG;
   const int P = cfg.paper_mode ? 1 : cfg.max_passes;
@@ -937,7 +1029,7 @@ extern "C" int32_t mprk_apply(mprk_handle* h, int32_t which, int32_t stage, cons
       break;
     case MPRK_APPLY_BJ_LP:
       if (!h->bs) return set_error(MPRK_EINVAL, "no block-Jacobi preconditioner configured");
-      HIPCHK(h->eng->apply_bj(c, h->ws + h->o_dinv + si * h->dinv_stride, x, y));
+      HIPCHK(h->eng->apply_bj(c, h->bj_desc(si), x, y));
       break;
     default:
       return set_error(MPRK_EINVAL, "unknown apply op");
@@ -1014,6 +1106,131 @@ extern "C" int32_t mprk_profile_read(mprk_handle* h, int32_t kclass, int64_t* la
   if (worked) *worked = w[kclass] - h->worked0[kclass];
   if (units) *units = u[kclass] - h->units0[kclass];
   if (total_ms) *total_ms = ms;
+  return MPRK_OK;
+}
+
+// ---- autotuner ----
+namespace {
+struct TuneKey {
+  int nx, ny, nz, bc, kind, fmt, storage;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(nx, ny, nz, bc, kind, fmt, storage) < std::tie(o.nx, o.ny, o.nz, o.bc, o.kind, o.fmt, o.storage);
+  }
+};
+struct TuneVal {
+  int nv, nr, nvr, nrr;  // groups per thread: streaming vector/row, reducing vector/row
+};
+std::map<TuneKey, TuneVal> g_tuned;
+std::mutex g_tune_mu;
+}  // namespace
+
+extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_row) {
+  if (!h) return set_error(MPRK_EINVAL, "NULL handle");
+  if (!h->bound) return set_error(MPRK_ESTATE, "mprk_autotune before mprk_bind");
+  const bool csr = h->op.format == MPRK_FMT_CSR;
+  const long ngv = h->N / h->vec, ngr = h->N;
+  const TuneKey key{h->grid.nx, h->grid.ny, h->grid.nz, h->grid.bc, h->op.kind, h->op.format, h->prec.storage};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      const TuneVal& v = it->second;
+      h->ln_vec = make_launch_nit(ngv, v.nv);
+      h->ln_row = make_launch_nit(ngr, v.nr);
+      h->ln_vec_red = make_launch_nit(ngv, v.nvr);
+      h->ln_row_red = make_launch_nit(ngr, v.nrr);
+      if (nit_vec) *nit_vec = v.nv;
+      if (nit_row) *nit_row = v.nr;
+      return MPRK_OK;
+    }
+  }
+  // scratch: LP Krylov vectors, the FP64 residual/scratch vectors (no step is in flight)
+  const size_t vlp = ((size_t)h->N * h->lp_bytes + 255) & ~(size_t)255;
+  void* x_lp = h->ws + (h->prec.krylov == MPRK_CG ? h->o_r : h->o_V);
+  void* y_lp = (char*)x_lp + vlp;
+  double* x64 = (double*)(h->ws + h->o_y);
+  double* y64 = (double*)(h->ws + h->o_scr);
+  double* rhs = (double*)(h->ws + h->o_rhs);
+  HIPCHK(hipMemsetAsync(x_lp, 0, 2 * vlp, h->stream));
+  HIPCHK(hipMemsetAsync(x64, 0, (size_t)h->N * 8, h->stream));
+  HIPCHK(hipMemsetAsync(rhs, 0, (size_t)h->N * 8, h->stream));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int si = 0;
+  const double sigma = h->sigmas.empty() ? 0.0 : h->sigmas[0];
+  const Coef<double> Mc = stage_coef(h->Kc, sigma);
+  int rc = MPRK_OK;
+  auto time_it = [&](auto&& body, float* out) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && rc == MPRK_OK; ++rep) {  // rep 0 warms up
+      if (hipEventRecord(e0, h->stream) != hipSuccess) rc = MPRK_EDEVICE;
+      for (int k = 0; k < 4 && rc == MPRK_OK; ++k) rc = body();
+      if (rc == MPRK_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = MPRK_EDEVICE;
+      if (rc == MPRK_OK && hipEventSynchronize(e1) != hipSuccess) rc = MPRK_EDEVICE;
+      if (rc == MPRK_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MPRK_EDEVICE;
+    }
+    *out = ms;
+  };
+  // streaming kernels: LP SpMV + FP64 operator, groups per thread in {1..16}
+  TuneVal best{h->ln_vec.nit, h->ln_row.nit, h->ln_vec_red.nit, h->ln_row_red.nit};
+  float bv = 1e30f;
+  for (int nit : {1, 2, 4, 8, 16}) {
+    const Launch sv = h->ln_vec, sr = h->ln_row;
+    h->ln_vec = make_launch_nit(ngv, nit);
+    if (csr) h->ln_row = make_launch_nit(ngr, nit);
+    EngineCtx c = h->ctx();
+    float ms;
+    time_it([&]() {
+      if (h->eng->apply_m(c, Mc, sigma, x_lp, y_lp) != hipSuccess) return (int)MPRK_EDEVICE;
+      return h->launch_apply64(x64, y64, 0.0, 0);
+    }, &ms);
+    h->ln_vec = sv;
+    h->ln_row = sr;
+    if (rc) break;
+    if (ms < bv) {
+      bv = ms;
+      best.nv = nit;
+      if (csr) best.nr = nit;
+    }
+  }
+  // kernels with a grid reduction: the FP64 residual, 2048 / 1024 / 512 blocks
+  float br = 1e30f;
+  Ctl* ctl = (Ctl*)(h->ws + h->o_ctl);
+  for (int blocks : {RED_MAX_BLOCKS, RED_MAX_BLOCKS / 2, RED_MAX_BLOCKS / 4}) {
+    if (rc || h->cfgs.empty()) break;
+    const Launch sv = h->ln_vec_red, sr = h->ln_row_red;
+    h->ln_vec_red = make_launch_red(ngv, blocks);
+    h->ln_row_red = make_launch_red(ngr, blocks);
+    float ms;
+    time_it([&]() {
+      // the residual kernel runs only while the stage is open; open it (first 4 bytes)
+      if (hipMemsetAsync(&ctl->outer_done, 0, sizeof(int), h->stream) != hipSuccess) return (int)MPRK_EDEVICE;
+      return h->launch_residual(si, rhs, x64, y64);
+    }, &ms);
+    const int nvr = h->ln_vec_red.nit, nrr = h->ln_row_red.nit;
+    h->ln_vec_red = sv;
+    h->ln_row_red = sr;
+    if (rc) break;
+    if (ms < br) {
+      br = ms;
+      best.nvr = nvr;
+      best.nrr = nrr;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return set_error(MPRK_EDEVICE, "autotune launch failed");
+  h->ln_vec = make_launch_nit(ngv, best.nv);
+  h->ln_row = make_launch_nit(ngr, best.nr);
+  h->ln_vec_red = make_launch_nit(ngv, best.nvr);
+  h->ln_row_red = make_launch_nit(ngr, best.nrr);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = best;
+  }
+  if (nit_vec) *nit_vec = best.nv;
+  if (nit_row) *nit_row = best.nr;
   return MPRK_OK;
 }
 

@@ -14,6 +14,9 @@ namespace mprk {
 
 int set_error(int code, const std::string& msg);
 Launch make_launch(long ng);
+Launch make_launch_nit(long ng, int nit);
+Launch make_launch_red(long ng, int max_blocks);
+constexpr int RED_MAX_BLOCKS = 2048;  // grid size cap of kernels with a last-block reduction
 Coef<double> operator_coef(const mprk_grid& g, const mprk_operator& op);
 Coef<double> stage_coef(const Coef<double>& K, double sigma);
 long csr_count(const Geo& geo, const Coef<double>& K, double* maxabs);
@@ -45,7 +48,8 @@ struct mprk_handle {
   std::vector<mprk::SolveCfg> cfgs;
   bool need_keps = false;
   // launch shapes
-  mprk::Launch ln_vec{}, ln_row{};
+  mprk::Launch ln_vec{}, ln_row{};          // streaming kernels
+  mprk::Launch ln_vec_red{}, ln_row_red{};  // kernels with a grid reduction
   int pstride = 8;
   int bs = 0;
   int nblk = 0;
@@ -55,7 +59,15 @@ struct mprk_handle {
   size_t o_rhs = 0, o_y = 0, o_res = 0, o_k = 0, o_keps = 0, o_scr = 0;
   size_t o_r = 0, o_z = 0, o_p0 = 0, o_p1 = 0, o_q = 0, o_x = 0, o_V = 0;
   size_t vstride = 0;
-  size_t o_dinv = 0, dinv_stride = 0;
+  // block-Jacobi inverse sets, one per distinct sigma
+  struct BJSet {
+    int mode = 0;          // 0 per-block, 1 distinct table + index, 2 one shared inverse
+    int nslot = 0;         // inverses stored
+    size_t o_inv = 0, o_reps = 0, o_idx = 0;
+    std::vector<int> reps; // representative block of each slot (modes 1, 2)
+    std::vector<int> idx;  // slot of each block (mode 1)
+  };
+  std::vector<BJSet> bjsets;
   size_t o_rowptr = 0, o_col = 0, o_kval = 0, o_mval = 0;
   size_t o_ctl = 0, o_flag = 0, o_part = 0;
   size_t ws_bytes = 0;
@@ -105,6 +117,7 @@ struct mprk_handle {
   int poll_wait(int s, mprk::CtlHead* out);
   int stage_record(int slot);
   int update_hist(int slot);
+  mprk::BJDesc bj_desc(int si) const;
   int launch_residual(int si, const double* rhs, double* y, double* kout);
   int launch_apply64(const double* x, double* y, double sigma, int mode);
   int run_solve(int si, int slot, const double* rhs, double* y, double* kout);

@@ -65,14 +65,18 @@ class Stepper:
         return LP_DTYPE[self.prec.storage]
 
     def set_u(self, u) -> None:
+        """Copy a host or device field into the state (on the handle's stream)."""
         if isinstance(u, np.ndarray):
             u = torch.from_numpy(np.ascontiguousarray(u, dtype=np.float64).ravel())
-        self.u.copy_(u.reshape(-1).to(self.device, torch.float64))
-        torch.cuda.synchronize(self.device)
+        with torch.cuda.stream(self.stream):
+            self.u.copy_(u.reshape(-1).to(self.device, torch.float64))
+        self.stream.synchronize()
 
     def get_u(self) -> np.ndarray:
-        torch.cuda.synchronize(self.device)
-        return self.u.detach().cpu().numpy().reshape(self.shape[2], self.shape[1], self.shape[0])
+        self.stream.synchronize()
+        with torch.cuda.stream(self.stream):
+            out = self.u.detach().cpu().numpy()
+        return out.reshape(self.shape[2], self.shape[1], self.shape[0])
 
     def step(self, nsteps: int = 1, check: bool = True):
         rc, st = A.mprk_step(self.h, nsteps, True)
@@ -90,6 +94,10 @@ class Stepper:
         y = torch.empty_like(x)
         A.mprk_apply(self.h, which, stage, x.data_ptr(), y.data_ptr())
         return y
+
+    def autotune(self):
+        """Pick the launch shape (groups per thread) by timing candidates; returns (vec, row)."""
+        return A.mprk_autotune(self.h)
 
     def state(self):
         return A.mprk_get_state(self.h)
@@ -123,7 +131,7 @@ def from_problem(p, fmt: int = A.FMT_STENCIL, prec=None, device: str = 'cuda:0',
 class Batch:
     """Many independent problems advanced together (one persistent launch per stage)."""
 
-    def __init__(self, problems, tab='SDIRK3', prec=None, device: str = 'cuda:0'):
+    def __init__(self, problems, tab='SDIRK3', prec=None, device: str = 'cuda:0', schedule=None):
         if not torch.cuda.is_available():
             raise RuntimeError('mprk needs a HIP device (torch.cuda.is_available() is False)')
         self.device = torch.device(device)
@@ -141,7 +149,10 @@ class Batch:
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             self.h = A.mprk_batch_create(descs, self.tab, self.prec, self.stream.cuda_stream)
+            if schedule is not None:
+                A.mprk_batch_set_schedule(self.h, schedule)
             self.ws_bytes = A.mprk_batch_workspace_bytes(self.h)
+            self.schedule = A.mprk_batch_get_schedule(self.h, len(descs))
             self.u = [torch.zeros(s[0] * s[1] * s[2], dtype=torch.float64, device=self.device)
                       for s in self.shapes]
             self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)

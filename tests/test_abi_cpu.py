@@ -122,3 +122,15 @@ def test_csr_workspace_accounts_for_exact_nnz():
     assert extra >= nnz * (4 + 8 + 4) + 513 * 4
     A.lib.mprk_destroy(h1)
     A.lib.mprk_destroy(h2)
+
+
+def test_shared_block_inverses_shrink_the_workspace():
+    p = A.mprk_precisions_default(A.FP16, A.GMRES)
+    rc, h1 = _create(grid=(32, 32, 32), bc=1, kind=1, b=(1.0, 0.5, 0.25), prec=p)
+    p.bj_shared = 1
+    rc2, h2 = _create(grid=(32, 32, 32), bc=1, kind=1, b=(1.0, 0.5, 0.25), prec=p)
+    assert rc == rc2 == A.OK
+    saved = A.lib.mprk_workspace_bytes(h1) - A.lib.mprk_workspace_bytes(h2)
+    assert saved >= 32 ** 3 * 8 * 2 - 4096     # the per-block FP16 table (8 values per row)
+    A.lib.mprk_destroy(h1)
+    A.lib.mprk_destroy(h2)

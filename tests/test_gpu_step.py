@@ -165,3 +165,32 @@ def test_state_counters_and_resume_match():
     assert np.array_equal(st.get_u(), full)
     assert st.state()[1] == 4
     st.close()
+
+
+@pytest.mark.parametrize("fmt", [A.FMT_STENCIL, A.FMT_CSR])
+@pytest.mark.parametrize("which", ['adv32_fp16', 'heat13_fp32'])
+def test_shared_block_inverses_bitwise_equal_per_block(which, fmt):
+    # one stored inverse per block vs a table of the distinct blocks (13^3: several distinct
+    # blocks straddle x-rows, so the indexed table is used)
+    if which == 'adv32_fp16':
+        p = W.advdiff_bump(n=32, nsteps=3)
+    else:
+        p = W.heat_modes(n=13, nsteps=3)
+    log_case('bj_shared', which=which, fmt=fmt)
+    u1, s1 = run(p, fmt, bj_shared=0)
+    u2, s2 = run(p, fmt, bj_shared=1)
+    assert np.array_equal(u1, u2)
+    assert s1['iters'] == s2['iters']
+
+
+@pytest.mark.parametrize("fmt", [A.FMT_STENCIL, A.FMT_CSR])
+def test_autotuned_launch_shape_keeps_parity(fmt):
+    p = W.advdiff_bump(n=48, nsteps=3)
+    log_case('autotune', fmt=fmt)
+    st = M.from_problem(p, fmt=fmt)
+    nv, nr = st.autotune()
+    assert nv in (1, 2, 4, 8, 16) and nr in (1, 2, 4, 8, 16)
+    st.step(p.nsteps)
+    err = rel_l2(st.get_u(), reference_solution(p))
+    st.close()
+    assert err <= TOL['fp16']

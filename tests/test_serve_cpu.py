@@ -1,0 +1,77 @@
+"""Serving scheduler on the CPU: admission, footprint accounting, latency statistics
+(deterministic fake backend with a virtual clock)."""
+import importlib.util
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# load serve.py without importing the package (which needs the built library)
+_spec = importlib.util.spec_from_file_location(
+    'mprk_serve', os.path.join(ROOT, 'paper_2412_16638_amd', 'serve.py'))
+S = importlib.util.module_from_spec(_spec)
+sys.modules['mprk_serve'] = S
+_spec.loader.exec_module(S)
+
+
+def _req(rid, t, n, steps):
+    p = W.Problem(f'r{rid}', n, W.DIRICHLET, W.HEAT, 1.0, (0, 0, 0), 'SDIRK3', 1e-3, steps, None)
+    return W.Request(rid, t, p)
+
+
+def test_single_slot_is_a_fifo_queue():
+    be = S.FakeBackend(sec_per_dof_step=1e-6, bytes_per_dof=1, budget=10 ** 9)
+    reqs = [_req(0, 0.0, 10, 1), _req(1, 0.1, 10, 1), _req(2, 0.2, 10, 1)]   # 1 ms each
+    reqs[0].problem.nsteps = 1000  # 1 s
+    out = S.Server(be, max_active=1).simulate(reqs)
+    res = out['results']
+    assert [round(r.finished, 9) for r in res] == [1.0, 1.001, 1.002]
+    assert [round(r.admitted, 9) for r in res] == [0.0, 1.0, 1.001]
+    assert out['peak_active'] == 1
+
+
+def test_processor_sharing_and_latency_percentiles():
+    be = S.FakeBackend(sec_per_dof_step=1e-5, bytes_per_dof=1, budget=10 ** 9)
+    # two equal jobs arriving together share the device: both finish at 2x their solo time
+    reqs = [_req(0, 0.0, 10, 100), _req(1, 0.0, 10, 100)]   # 1000 DOF x 100 steps: solo 1 s
+    out = S.Server(be, max_active=4).simulate(reqs)
+    assert all(abs(r.finished - 2.0) < 1e-12 for r in out['results'])
+    assert abs(out['p50_s'] - 2.0) < 1e-12 and abs(out['p99_s'] - 2.0) < 1e-12
+    assert abs(out['dof_steps_per_s'] - 2 * 1000 * 100 / 2.0) < 1e-6
+
+
+def test_memory_budget_limits_concurrency():
+    be = S.FakeBackend(sec_per_dof_step=1e-6, bytes_per_dof=100, budget=250_000)
+    reqs = [_req(i, 0.0, 10, 10) for i in range(6)]   # footprint 100 * 1000 = 100 kB each
+    out = S.Server(be, max_active=8).simulate(reqs)
+    assert out['peak_active'] == 2
+    assert out['peak_resident_bytes'] <= 250_000
+    assert out['n'] == 6 and out['failed'] == 0
+
+
+def test_request_that_never_fits_is_rejected():
+    be = S.FakeBackend(bytes_per_dof=100, budget=1000)
+    with pytest.raises(ValueError):
+        S.Server(be).simulate([_req(0, 0.0, 10, 1)])
+
+
+def test_seeded_request_mix_statistics():
+    reqs = W.request_stream(materialize_u0=False)
+    assert len(reqs) == 512
+    arr = np.array([r.arrival for r in reqs])
+    assert np.all(np.diff(arr) >= 0)
+    assert 8.0 < arr[-1] < 12.5                       # ~512 / 50 s
+    ns = np.array([r.problem.n for r in reqs])
+    assert ns.min() >= 32 and ns.max() <= 192
+    kinds = np.array([r.problem.kind for r in reqs])
+    assert 0.4 < kinds.mean() < 0.6
+    be = S.FakeBackend(sec_per_dof_step=2e-10, bytes_per_dof=120, budget=64 << 30)
+    out = S.Server(be, max_active=16).simulate(reqs)
+    assert out['n'] == 512
+    lat = np.array([r.latency for r in out['results']])
+    assert out['p50_s'] == pytest.approx(np.percentile(lat, 50))
+    assert out['p99_s'] >= out['p50_s']
