@@ -60,7 +60,7 @@ struct EngineCtx {
   hipStream_t stream;
   Geo geo;
   int fmt;            // 0 stencil, 1 CSR
-  int vec;            // 4 or 1 (vector kernels)
+  int vec;            // values per group of the LP kernels: 8 (FP16, nx % 8 == 0), 4 or 1
   Launch ln_vec;      // groups of `vec` elements (streaming kernels)
   Launch ln_row;      // CSR rows (VEC = 1)
   Launch ln_mv;       // launch of the SpMV kernels (= ln_vec for stencil, ln_row for CSR)
@@ -126,6 +126,9 @@ inline Coef<C> cast_coef(const Coef<double>& a) {
 
 template <typename S, typename C>
 class EngineT final : public Engine {
+  // 16-byte groups for 2-byte storage; wider types never use an 8-wide group
+  static constexpr int V8 = sizeof(S) == 2 ? 8 : 4;
+
  public:
   int elem_bytes() const override { return (int)sizeof(S); }
 
@@ -180,6 +183,7 @@ class EngineT final : public Engine {
     const S* pold = (it & 1) ? (const S*)c.p1 : (const S*)c.p0;
     S* pnew = (it & 1) ? (S*)c.p0 : (S*)c.p1;
     if (c.fmt == 1) cg_dir_t<1, 1>(c, cfg, Mc, z, pold, pnew);
+    else if (c.vec == 8) cg_dir_t<V8, 0>(c, cfg, Mc, z, pold, pnew);
     else if (c.vec == 4) cg_dir_t<4, 0>(c, cfg, Mc, z, pold, pnew);
     else cg_dir_t<1, 0>(c, cfg, Mc, z, pold, pnew);
     dispatch_vec_bs(c, [&](auto vec, auto bs) {
@@ -188,7 +192,9 @@ class EngineT final : public Engine {
     return hipGetLastError();
   }
   hipError_t cg_finish(const EngineCtx& c) override {
-    if (c.vec == 4)
+    if (c.vec == 8)
+      MPRK_LAUNCH_KC(c, KC_PROMOTE, (k_promote<S, C, V8>), c.ln_vec, c.ln_vec, c.y, (const S*)c.x, c.ctl);
+    else if (c.vec == 4)
       MPRK_LAUNCH_KC(c, KC_PROMOTE, (k_promote<S, C, 4>), c.ln_vec, c.ln_vec, c.y, (const S*)c.x, c.ctl);
     else
       MPRK_LAUNCH_KC(c, KC_PROMOTE, (k_promote<S, C, 1>), c.ln_vec, c.ln_vec, c.y, (const S*)c.x, c.ctl);
@@ -223,6 +229,8 @@ class EngineT final : public Engine {
     const bool prec = c.bs > 0;
     if (c.fmt == 1) {
       if (prec) gm_matvec_t<1, 1, 1>(c, cfg, Mc); else gm_matvec_t<1, 1, 0>(c, cfg, Mc);
+    } else if (c.vec == 8) {
+      if (prec) gm_matvec_t<V8, 0, 1>(c, cfg, Mc); else gm_matvec_t<V8, 0, 0>(c, cfg, Mc);
     } else if (c.vec == 4) {
       if (prec) gm_matvec_t<4, 0, 1>(c, cfg, Mc); else gm_matvec_t<4, 0, 0>(c, cfg, Mc);
     } else {
@@ -252,6 +260,7 @@ class EngineT final : public Engine {
   hipError_t apply_m(const EngineCtx& c, const Coef<double>& Mc, double sigma, const void* x,
                      void* y) override {
     if (c.fmt == 1) apply_m_t<1, 1>(c, Mc, sigma, x, y);
+    else if (c.vec == 8) apply_m_t<V8, 0>(c, Mc, sigma, x, y);
     else if (c.vec == 4) apply_m_t<4, 0>(c, Mc, sigma, x, y);
     else apply_m_t<1, 0>(c, Mc, sigma, x, y);
     return hipGetLastError();
@@ -275,7 +284,15 @@ class EngineT final : public Engine {
   };
   template <typename F>
   static void dispatch_vec_bs(const EngineCtx& c, F&& f) {
-    if (c.vec == 4) {
+    if (c.vec == 8) {
+      switch (c.bs) {
+        case 0: f(IC<V8>{}, IC<0>{}); break;
+        case 1: f(IC<V8>{}, IC<1>{}); break;
+        case 2: f(IC<V8>{}, IC<2>{}); break;
+        case 4: f(IC<V8>{}, IC<4>{}); break;
+        default: f(IC<V8>{}, IC<8>{}); break;
+      }
+    } else if (c.vec == 4) {
       switch (c.bs) {
         case 0: f(IC<4>{}, IC<0>{}); break;
         case 1: f(IC<4>{}, IC<1>{}); break;

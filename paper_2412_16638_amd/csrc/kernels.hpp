@@ -738,6 +738,12 @@ __global__ __launch_bounds__(TPB) void k_gm_finish(Launch ln, double* __restrict
 // Setup (not on the timed path)
 // ------------------------------------------------------------------------------------------
 
+// Deterministic non-constant fill (autotuner test state): x[i] = sin(a i) + 0.5 cos(b i).
+static __global__ void k_fill_pattern(long n, double a, double b, double* __restrict__ x) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = sin(a * (double)i) + 0.5 * cos(b * (double)i);
+}
+
 // In-place Gauss-Jordan inverse of an n x n (n <= BJ_MAX) matrix with partial pivoting.
 __device__ inline int gj_invert(double (&a)[BJ_MAX][BJ_MAX], double (&inv)[BJ_MAX][BJ_MAX], int n) {
   for (int i = 0; i < BJ_MAX; ++i)

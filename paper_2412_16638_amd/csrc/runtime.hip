@@ -438,6 +438,7 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   geo = Geo{g.nx, g.ny, g.nz, g.bc, g.nx * g.ny * g.nz, g.nx * g.ny};
   N = geo.N;
   vec = (g.nx % 4 == 0) ? 4 : 1;
+  vec_lp = (p.storage == MPRK_FP16 && g.nx % 8 == 0) ? 8 : vec;
   Kc = operator_coef(g, o);
   switch (p.storage) {
     case MPRK_FP64: eng.reset(make_engine_fp64()); break;
@@ -472,7 +473,11 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   ln_row = make_launch(N);
   ln_vec_red = make_launch_red(N / vec, RED_MAX_BLOCKS);
   ln_row_red = make_launch_red(N, RED_MAX_BLOCKS);
-  pstride = std::max(ln_vec_red.G, ln_row_red.G);
+  ln_lp = make_launch(N / vec_lp);
+  ln_lp_red = make_launch_red(N / vec_lp, RED_MAX_BLOCKS);
+  // partials cover every reducing launch shape the autotuner may pick
+  pstride = std::max(make_launch_red(N / vec, 2 * RED_MAX_BLOCKS).G,
+                     make_launch_red(N, 2 * RED_MAX_BLOCKS).G);
   bs = p.precond == MPRK_PRECOND_BJ ? p.block : 0;
   nblk = bs ? (N + bs - 1) / bs : 0;
   // CSR size (assembled at bind)
@@ -595,12 +600,12 @@ EngineCtx mprk_handle::ctx() const {
   c.stream = stream;
   c.geo = geo;
   c.fmt = op.format;
-  c.vec = vec;
-  c.ln_vec = ln_vec;
+  c.vec = vec_lp;
+  c.ln_vec = ln_lp;
   c.ln_row = ln_row;
-  c.ln_mv = op.format == MPRK_FMT_CSR ? ln_row : ln_vec;
-  c.ln_red = ln_vec_red;
-  c.ln_mv_red = op.format == MPRK_FMT_CSR ? ln_row_red : ln_vec_red;
+  c.ln_mv = op.format == MPRK_FMT_CSR ? ln_row : ln_lp;
+  c.ln_red = ln_lp_red;
+  c.ln_mv_red = op.format == MPRK_FMT_CSR ? ln_row_red : ln_lp_red;
   c.bs = bs;
   c.csr = Csr{(const int*)(ws + o_rowptr), (const int*)(ws + o_col)};
   c.mval = ws + o_mval;
@@ -1119,6 +1124,7 @@ struct TuneKey {
 };
 struct TuneVal {
   int nv, nr, nvr, nrr;  // groups per thread: streaming vector/row, reducing vector/row
+  int nl, nlr;           // LP kernels: streaming / reducing
 };
 std::map<TuneKey, TuneVal> g_tuned;
 std::mutex g_tune_mu;
@@ -1128,7 +1134,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
   if (!h) return set_error(MPRK_EINVAL, "NULL handle");
   if (!h->bound) return set_error(MPRK_ESTATE, "mprk_autotune before mprk_bind");
   const bool csr = h->op.format == MPRK_FMT_CSR;
-  const long ngv = h->N / h->vec, ngr = h->N;
+  const long ngv = h->N / h->vec, ngr = h->N, ngl = h->N / h->vec_lp;
   const TuneKey key{h->grid.nx, h->grid.ny, h->grid.nz, h->grid.bc, h->op.kind, h->op.format, h->prec.storage};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1139,6 +1145,8 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
       h->ln_row = make_launch_nit(ngr, v.nr);
       h->ln_vec_red = make_launch_nit(ngv, v.nvr);
       h->ln_row_red = make_launch_nit(ngr, v.nrr);
+      h->ln_lp = make_launch_nit(ngl, v.nl);
+      h->ln_lp_red = make_launch_nit(ngl, v.nlr);
       if (nit_vec) *nit_vec = v.nv;
       if (nit_row) *nit_row = v.nr;
       return MPRK_OK;
@@ -1158,6 +1166,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   const int si = 0;
+  Ctl* ctl = (Ctl*)(h->ws + h->o_ctl);
   const double sigma = h->sigmas.empty() ? 0.0 : h->sigmas[0];
   const Coef<double> Mc = stage_coef(h->Kc, sigma);
   int rc = MPRK_OK;
@@ -1173,11 +1182,13 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
     *out = ms;
   };
   // streaming kernels: LP SpMV + FP64 operator, groups per thread in {1..16}
-  TuneVal best{h->ln_vec.nit, h->ln_row.nit, h->ln_vec_red.nit, h->ln_row_red.nit};
+  TuneVal best{h->ln_vec.nit, h->ln_row.nit, h->ln_vec_red.nit, h->ln_row_red.nit,
+               h->ln_lp.nit, h->ln_lp_red.nit};
   float bv = 1e30f;
   for (int nit : {1, 2, 4, 8, 16}) {
-    const Launch sv = h->ln_vec, sr = h->ln_row;
+    const Launch sv = h->ln_vec, sr = h->ln_row, sl = h->ln_lp;
     h->ln_vec = make_launch_nit(ngv, nit);
+    h->ln_lp = make_launch_nit(ngl, nit);
     if (csr) h->ln_row = make_launch_nit(ngr, nit);
     EngineCtx c = h->ctx();
     float ms;
@@ -1187,37 +1198,72 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
     }, &ms);
     h->ln_vec = sv;
     h->ln_row = sr;
+    h->ln_lp = sl;
     if (rc) break;
     if (ms < bv) {
       bv = ms;
       best.nv = nit;
+      best.nl = nit;
       if (csr) best.nr = nit;
     }
   }
-  // kernels with a grid reduction: the FP64 residual, 2048 / 1024 / 512 blocks
+  // kernels with a grid reduction: time the real Krylov iteration (4 iterations after a
+  // residual + begin on a patterned state) for 4096 / 2048 / 1024 / 512 blocks
   float br = 1e30f;
-  Ctl* ctl = (Ctl*)(h->ws + h->o_ctl);
-  for (int blocks : {RED_MAX_BLOCKS, RED_MAX_BLOCKS / 2, RED_MAX_BLOCKS / 4}) {
+  for (int blocks : {2 * RED_MAX_BLOCKS, RED_MAX_BLOCKS, RED_MAX_BLOCKS / 2, RED_MAX_BLOCKS / 4}) {
     if (rc || h->cfgs.empty()) break;
-    const Launch sv = h->ln_vec_red, sr = h->ln_row_red;
+    const Launch sv = h->ln_vec_red, sr = h->ln_row_red, sl = h->ln_lp_red;
     h->ln_vec_red = make_launch_red(ngv, blocks);
     h->ln_row_red = make_launch_red(ngr, blocks);
-    float ms;
-    time_it([&]() {
-      // the residual kernel runs only while the stage is open; open it (first 4 bytes)
-      if (hipMemsetAsync(&ctl->outer_done, 0, sizeof(int), h->stream) != hipSuccess) return (int)MPRK_EDEVICE;
-      return h->launch_residual(si, rhs, x64, y64);
-    }, &ms);
-    const int nvr = h->ln_vec_red.nit, nrr = h->ln_row_red.nit;
+    h->ln_lp_red = make_launch_red(ngl, blocks);
+    if (h->ln_vec_red.G > h->pstride || h->ln_row_red.G > h->pstride || h->ln_lp_red.G > h->pstride) {
+      h->ln_vec_red = sv;
+      h->ln_row_red = sr;
+      h->ln_lp_red = sl;
+      continue;
+    }
+    const SolveCfg& cfg = h->cfgs[si];
+    EngineCtx c = h->ctx();
+    c.y = x64;
+    const BJDesc dinv = h->bj_desc(si);
+    const bool cg = h->prec.krylov == MPRK_CG;
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && rc == MPRK_OK; ++rep) {
+      // state: rhs = pattern A (via the stage-rhs kernel, which also reopens the stage record),
+      // y = pattern B, so the first residual is non-zero
+      CombArgs ca{};
+      ca.nv = 0;
+      const unsigned nb = (unsigned)((h->N + 255) / 256);
+      hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.37, 0.011, y64);
+      if (h->vec == 4)
+        hipLaunchKernelGGL((k_stage_rhs<4>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, y64, ca, rhs, x64, ctl, 1);
+      else
+        hipLaunchKernelGGL((k_stage_rhs<1>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, y64, ca, rhs, x64, ctl, 1);
+      hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.23, 0.017, x64);
+      if (hipGetLastError() != hipSuccess) { rc = MPRK_EDEVICE; break; }
+      rc = h->launch_residual(si, rhs, x64, y64);
+      if (rc) break;
+      if ((cg ? h->eng->cg_begin(c, cfg, dinv) : h->eng->gm_begin(c, cfg, dinv)) != hipSuccess) { rc = MPRK_EDEVICE; break; }
+      if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = MPRK_EDEVICE; break; }
+      for (int k = 0; k < 4 && rc == MPRK_OK; ++k)
+        if ((cg ? h->eng->cg_iter(c, cfg, Mc, dinv, k) : h->eng->gm_iter(c, cfg, Mc, dinv)) != hipSuccess) rc = MPRK_EDEVICE;
+      if (rc == MPRK_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = MPRK_EDEVICE;
+      if (rc == MPRK_OK && hipEventSynchronize(e1) != hipSuccess) rc = MPRK_EDEVICE;
+      if (rc == MPRK_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MPRK_EDEVICE;
+    }
+    const int nvr = h->ln_vec_red.nit, nrr = h->ln_row_red.nit, nlr = h->ln_lp_red.nit;
     h->ln_vec_red = sv;
     h->ln_row_red = sr;
+    h->ln_lp_red = sl;
     if (rc) break;
     if (ms < br) {
       br = ms;
       best.nvr = nvr;
       best.nrr = nrr;
+      best.nlr = nlr;
     }
   }
+  // leave no open stage behind: the next step's first kernel resets the record anyway
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return set_error(MPRK_EDEVICE, "autotune launch failed");
@@ -1225,6 +1271,8 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
   h->ln_row = make_launch_nit(ngr, best.nr);
   h->ln_vec_red = make_launch_nit(ngv, best.nvr);
   h->ln_row_red = make_launch_nit(ngr, best.nrr);
+  h->ln_lp = make_launch_nit(ngl, best.nl);
+  h->ln_lp_red = make_launch_nit(ngl, best.nlr);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[key] = best;

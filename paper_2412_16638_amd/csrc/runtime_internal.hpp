@@ -37,7 +37,8 @@ struct mprk_handle {
   hipStream_t stream = nullptr;
   mprk::Geo geo{};
   int N = 0;
-  int vec = 1;
+  int vec = 1;      // values per group of the FP64 kernels (4 when nx % 4 == 0)
+  int vec_lp = 1;   // values per group of the LP kernels (8 for FP16 storage when nx % 8 == 0)
   mprk::Coef<double> Kc{};
   std::unique_ptr<mprk::Engine> eng;
   int lp_bytes = 8;
@@ -50,6 +51,7 @@ struct mprk_handle {
   // launch shapes
   mprk::Launch ln_vec{}, ln_row{};          // streaming kernels
   mprk::Launch ln_vec_red{}, ln_row_red{};  // kernels with a grid reduction
+  mprk::Launch ln_lp{}, ln_lp_red{};        // LP kernels (groups of vec_lp)
   int pstride = 8;
   int bs = 0;
   int nblk = 0;

@@ -40,7 +40,8 @@ class JobResult:
 class GpuBackend:
     """Runs a job as one handle on its own stream; the footprint comes from the library."""
 
-    def __init__(self, device: str = 'cuda:0', steps_per_call: int = 10, keep_u: bool = False):
+    def __init__(self, device: str = 'cuda:0', steps_per_call: int = 10, keep_u: bool = False,
+                 u0_fn=None):
         import torch
         from . import _abi as A
         from .stepper import Stepper, precisions
@@ -48,6 +49,7 @@ class GpuBackend:
         self.device = torch.device(device)
         self.steps_per_call = steps_per_call
         self.keep_u = keep_u
+        self.u0_fn = u0_fn  # builds a job's initial field when the job starts (if p.u0 is None)
 
     def _args(self, p):
         A = self.A
@@ -80,7 +82,7 @@ class GpuBackend:
             st = self.Stepper(p.n, p.bc, kind, p.diff, p.b, self.A.FMT_STENCIL, p.tableau, prec,
                               p.dt, str(self.device))
             try:
-                st.set_u(p.u0)
+                st.set_u(p.u0 if p.u0 is not None else self.u0_fn(p))
                 left = p.nsteps
                 stats = None
                 ok = True

@@ -191,3 +191,16 @@ def request_stream(count: int = 512, rate: float = 50.0, seed: int = 5,
                         meta={'center': c})
         reqs.append(Request(r, t, p))
     return reqs
+
+
+def initial_field(p: Problem) -> np.ndarray:
+    """Rebuild a request's initial field from its recorded draws (requests made with
+    materialize_u0=False keep only the seeds' outcomes in p.meta)."""
+    if p.u0 is not None:
+        return p.u0
+    if p.kind == HEAT:
+        u = np.zeros((p.n, p.n, p.n))
+        for m in range(len(p.meta['a'])):
+            u += p.meta['a'][m] * sine_mode((p.n, p.n, p.n), p.meta['k'][m], DIRICHLET)
+        return u
+    return gaussian_bump(p.n, p.meta['center'], 100.0, PERIODIC)
