@@ -22,6 +22,12 @@
 
 namespace mprk {
 
+// Basis vectors handled per chunk in the GMRES kernels: their loads are issued back to back.
+template <int VEC>
+__host__ __device__ constexpr int basis_chunk() {
+  return VEC >= 8 ? 4 : 8;
+}
+
 struct CombArgs {
   const double* v[2 * MAXS];
   double c[2 * MAXS];
@@ -557,15 +563,25 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
 #pragma unroll
     for (int v = 0; v < VEC; ++v) w[v] = rnd<S, C>(w[v]);
     storev<S, C, VEC>(wout + e, w);
+    // basis vectors in chunks of CH whose loads are issued together (indices past nd are
+    // clamped to a valid vector and their contribution discarded)
 #pragma unroll
-    for (int i = 0; i < MAXD; ++i) {
-      if (i < nd) {
-        C vi[VEC];
-        loadv<C, S, VEC>(V + (size_t)i * vstride + e, vi);
-        C s = C(0);
+    for (int c = 0; c < MAXD; c += basis_chunk<VEC>()) {
+      if (c < nd) {
+        constexpr int CH = basis_chunk<VEC>();
+        C vv[CH][VEC];
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) s += vi[v] * w[v];
-        dacc[i] += s;
+        for (int k = 0; k < CH; ++k)
+          loadv<C, S, VEC>(V + (size_t)min(c + k, nd - 1) * vstride + e, vv[k]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (c + k < MAXD) {
+            C s = C(0);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s += vv[k][v] * w[v];
+            dacc[c + k] += (c + k < nd) ? s : C(0);
+          }
+        }
       }
     }
   }
@@ -605,12 +621,20 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
     if (valid) {
       loadv<C, S, VEC>(w + e, wv);
 #pragma unroll
-      for (int i = 0; i < MAXD; ++i) {
-        if (i < nd) {
-          C vi[VEC];
-          loadv<C, S, VEC>(V + (size_t)i * vstride + e, vi);
+      for (int c = 0; c < MAXD; c += basis_chunk<VEC>()) {
+        if (c < nd) {
+          constexpr int CH = basis_chunk<VEC>();
+          C vv[CH][VEC];
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) wv[v] -= cf[i] * vi[v];
+          for (int k = 0; k < CH; ++k)
+            loadv<C, S, VEC>(V + (size_t)min(c + k, nd - 1) * vstride + e, vv[k]);
+#pragma unroll
+          for (int k = 0; k < CH; ++k) {
+            if (c + k < MAXD) {  // cf is zero past nd
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) wv[v] -= cf[c + k] * vv[k][v];
+            }
+          }
         }
       }
 #pragma unroll
@@ -709,12 +733,20 @@ __global__ __launch_bounds__(TPB) void k_gm_finish(Launch ln, double* __restrict
     for (int v = 0; v < VEC; ++v) t[v] = C(0);
     if (valid) {
 #pragma unroll
-      for (int i = 0; i < MAXM; ++i) {
-        if (i < J) {
-          C vi[VEC];
-          loadv<C, S, VEC>(V + (size_t)i * vstride + e, vi);
+      for (int c = 0; c < MAXM; c += basis_chunk<VEC>()) {
+        if (c < J) {
+          constexpr int CH = basis_chunk<VEC>();
+          C vv[CH][VEC];
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) t[v] += cf[i] * vi[v];
+          for (int k = 0; k < CH; ++k)
+            loadv<C, S, VEC>(V + (size_t)min(c + k, J - 1) * vstride + e, vv[k]);
+#pragma unroll
+          for (int k = 0; k < CH; ++k) {
+            if (c + k < MAXM) {  // cf is zero past J
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) t[v] += cf[c + k] * vv[k][v];
+            }
+          }
         }
       }
     }

@@ -1,0 +1,143 @@
+"""Summaries of rocprofv3 output for the library's kernels.
+
+Two inputs are understood:
+- the `*_kernel_stats.csv` of a `rocprofv3 --kernel-trace --stats --output-format csv` run, turned
+  into a short text table (calls, average and total duration, share) with the command that made it;
+- two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of a command that starts with a plain
+  device copy of known size (`bench.py --calib-copy MIB`), turned into the HBM bytes one dispatch of
+  a kernel moves.  Each counter is scaled by what it reads for that copy: the copy reads MIB and
+  writes MIB, so factor = MIB * 1024 / counter (both counters are in KiB).
+
+Usage:
+  python -m paper_2412_16638_amd.profiling stats STATS_CSV --command CMD --out FILE
+  python -m paper_2412_16638_amd.profiling traffic FETCH_CSV WRITE_CSV --kernel gm_orth \
+      --workload advdiff256 --calib-mib 1024 --command-fetch CMD --command-write CMD --out FILE
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def kernel_source_hash() -> str:
+    """Hash of the device sources; a traffic figure is valid only for the sources it was taken on."""
+    h = hashlib.sha256()
+    for f in ('device.hpp', 'kernels.hpp', 'engine.hpp'):
+        with open(os.path.join(ROOT, 'paper_2412_16638_amd', 'csrc', f), 'rb') as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    """`mprk::k_gm_orth<...>(...)` or its mangled form `_ZN4mprk9k_gm_orth...` -> `gm_orth`;
+    names outside the library pass through."""
+    ident = ''
+    if name.startswith('_ZN4mprk'):
+        rest = name[len('_ZN4mprk'):]
+        k = 0
+        while k < len(rest) and rest[k].isdigit():
+            k += 1
+        if k:
+            ident = rest[k:k + int(rest[:k])]
+    else:
+        i = name.find('mprk::')
+        if i >= 0:
+            for c in name[i + len('mprk::'):]:
+                if not (c.isalnum() or c == '_'):
+                    break
+                ident += c
+    if ident.startswith('k_'):
+        return ident[2:]
+    return ident or name
+
+
+def stats_summary(stats_csv: str, command: str, top: int = 14) -> str:
+    rows = list(csv.DictReader(open(stats_csv)))
+    total = sum(float(r['TotalDurationNs']) for r in rows)
+    lines = ['# rocprofv3 kernel statistics', '', f'command: {command}', '',
+             f'{"kernel":<24} {"calls":>6} {"avg_us":>10} {"total_ms":>10} {"share":>7}  template']
+    for r in rows[:top]:
+        nm = r['Name']
+        lines.append(f'{short_name(nm):<24} {int(r["Calls"]):>6} '
+                     f'{float(r["AverageNs"]) / 1e3:>10.2f} {float(r["TotalDurationNs"]) / 1e6:>10.3f} '
+                     f'{float(r["TotalDurationNs"]) / total:>7.2%}  {nm[:110]}')
+    return '\n'.join(lines) + '\n'
+
+
+def _counter_rows(path: str, counter: str):
+    out = []
+    for r in csv.DictReader(open(path)):
+        if r['Counter_Name'] == counter:
+            out.append(r)
+    return out
+
+
+def _calibration(rows, mib: int) -> float:
+    """Largest __amd_rocclr_copyBuffer dispatch is the calibration copy of `mib` MiB."""
+    copies = [float(r['Counter_Value']) for r in rows if 'copyBuffer' in r['Kernel_Name']]
+    if not copies:
+        raise ValueError('no calibration copy in the counter file')
+    return mib * 1024.0 / max(copies)
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, calib_mib: int,
+            worked_frac: float = 0.01) -> dict:
+    """Mean HBM bytes per working dispatch of `kernel` (dispatches that fetched less than
+    `worked_frac` of the largest one had nothing left to do and are counted apart)."""
+    fr = _counter_rows(fetch_csv, 'FETCH_SIZE')
+    wr = _counter_rows(write_csv, 'WRITE_SIZE')
+    ff, fw = _calibration(fr, calib_mib), _calibration(wr, calib_mib)
+    fmine = [float(r['Counter_Value']) for r in fr if short_name(r['Kernel_Name']) == kernel]
+    wmine = [float(r['Counter_Value']) for r in wr if short_name(r['Kernel_Name']) == kernel]
+    if not fmine or not wmine:
+        raise ValueError(f'kernel {kernel} not found in the counter files')
+    big = max(fmine)
+    fw_ = [v for v in fmine if v >= worked_frac * big]
+    wbig = max(wmine)
+    ww_ = [v for v in wmine if v >= worked_frac * wbig]
+    fetch_b = sum(fw_) / len(fw_) * 1024 * ff
+    write_b = sum(ww_) / len(ww_) * 1024 * fw
+    return {'kernel': kernel, 'fetch_factor': ff, 'write_factor': fw,
+            'dispatches': len(fmine), 'working_dispatches': len(fw_),
+            'fetch_bytes_per_worked_launch': fetch_b, 'write_bytes_per_worked_launch': write_b,
+            'bytes_per_worked_launch': fetch_b + write_b}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest='what', required=True)
+    a = sub.add_parser('stats')
+    a.add_argument('csv')
+    a.add_argument('--command', required=True)
+    a.add_argument('--out', required=True)
+    b = sub.add_parser('traffic')
+    b.add_argument('fetch_csv')
+    b.add_argument('write_csv')
+    b.add_argument('--kernel', required=True)
+    b.add_argument('--workload', required=True)
+    b.add_argument('--calib-mib', type=int, required=True)
+    b.add_argument('--command-fetch', required=True)
+    b.add_argument('--command-write', required=True)
+    b.add_argument('--out', required=True)
+    args = ap.parse_args()
+    if args.what == 'stats':
+        with open(args.out, 'w') as fh:
+            fh.write(stats_summary(args.csv, args.command))
+    else:
+        t = traffic(args.fetch_csv, args.write_csv, args.kernel, args.calib_mib)
+        t.update({'workload': args.workload, 'kernel_hash': kernel_source_hash(),
+                  'command_fetch': args.command_fetch, 'command_write': args.command_write,
+                  'calibration': f'plain device copy of {args.calib_mib} MiB (reads and writes '
+                                 f'{args.calib_mib} MiB)'})
+        with open(args.out, 'w') as fh:
+            json.dump(t, fh, indent=1)
+            fh.write('\n')
+
+
+if __name__ == '__main__':
+    main()
