@@ -664,7 +664,7 @@ extern "C" int32_t mprk_batch_bind(mprk_batch* b, double* const* u_dev, void* wo
       c.geo = hp[p].geo;
       c.bs = b->bs;
       const int nblk = (c.geo.N + b->bs - 1) / b->bs;
-      BHIP(eng->bj_setup_stencil(c, stage_coef(hp[p].K, hp[p].sigma), hp[p].dinv, fail, nblk, nullptr));
+      BHIP(eng->bj_setup_stencil(c, stage_coef(hp[p].K, hp[p].sigma), hp[p].dinv, fail, nblk, nullptr, 0));
     }
   }
   int hfail = 0;

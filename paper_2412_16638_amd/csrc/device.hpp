@@ -257,25 +257,24 @@ template <typename C, int VEC, typename F>
 __device__ __forceinline__ void stencil_group(const Geo& g, const Coef<C>& k, int e, const F& f,
                                               C (&ctr)[VEC], C (&out)[VEC]) {
   const Nbr n = neighbours<VEC>(g, e);
-  f.vec(e, ctr);
-  C l = n.xm >= 0 ? f.one(n.xm) : C(0);
-  C r = n.xp >= 0 ? f.one(n.xp) : C(0);
+  // every load is issued unconditionally (a missing Dirichlet neighbour reads the group itself)
+  // and masked afterwards, so the seven loads are in flight together
+  C l = f.one(n.xm >= 0 ? n.xm : e);
+  C r = f.one(n.xp >= 0 ? n.xp : e);
   C ym[VEC], yp[VEC], zm[VEC], zp[VEC];
-  if (n.ym >= 0) f.vec(n.ym, ym); else {
+  f.vec(e, ctr);
+  f.vec(n.ym >= 0 ? n.ym : e, ym);
+  f.vec(n.yp >= 0 ? n.yp : e, yp);
+  f.vec(n.zm >= 0 ? n.zm : e, zm);
+  f.vec(n.zp >= 0 ? n.zp : e, zp);
+  if (n.xm < 0) l = C(0);
+  if (n.xp < 0) r = C(0);
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) ym[v] = C(0);
-  }
-  if (n.yp >= 0) f.vec(n.yp, yp); else {
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) yp[v] = C(0);
-  }
-  if (n.zm >= 0) f.vec(n.zm, zm); else {
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) zm[v] = C(0);
-  }
-  if (n.zp >= 0) f.vec(n.zp, zp); else {
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) zp[v] = C(0);
+  for (int v = 0; v < VEC; ++v) {
+    if (n.ym < 0) ym[v] = C(0);
+    if (n.yp < 0) yp[v] = C(0);
+    if (n.zm < 0) zm[v] = C(0);
+    if (n.zp < 0) zp[v] = C(0);
   }
 #pragma unroll
   for (int v = 0; v < VEC; ++v) {
@@ -348,7 +347,21 @@ __device__ __forceinline__ C csr_row(const Csr& m, const SV* __restrict__ val, i
 
 // Block-Jacobi inverses.  mode 0: one stored inverse per block (row r's BS entries at
 // inv[r * BS]); mode 1: a table of distinct inverses and idx[block] selecting one; mode 2: a
-// single inverse shared by every block (constant-coefficient operators with BS | nx).
+// single inverse shared by every block (constant-coefficient operators with BS | nx); mode 3:
+// one inverse per block, rows interleaved for kernels whose lanes own VEC consecutive rows:
+// row r = VEC g + q is the chunk ((g / 64) VEC + q) 64 + g % 64 (chunks of BS entries), so the
+// q-th row load of the 64 lanes of a wave reads one contiguous 64-chunk run.
+template <int VEC>
+__host__ __device__ __forceinline__ size_t bj_chunk(int r) {
+  const int g = r / VEC, q = r % VEC;
+  return ((size_t)(g >> 6) * VEC + q) * 64 + (g & 63);
+}
+
+// Rows the interleaved layout spans for nrows rows: whole 64-lane runs of VEC rows.
+__host__ __device__ inline size_t bj_chunks(long nrows, int vec) {
+  const long groups = (nrows + vec - 1) / vec;
+  return (size_t)((groups + 63) / 64) * 64 * vec;
+}
 struct BJDesc {
   const void* inv;
   const int* idx;
@@ -367,49 +380,106 @@ __host__ __device__ inline BJ<S> bj_typed(const BJDesc& d) {
   return BJ<S>{(const S*)d.inv, d.idx, d.mode};
 }
 
-template <typename S, int BS>
-__device__ __forceinline__ const S* bj_row(const BJ<S>& bj, int r) {
-  if (bj.mode == 0) return bj.inv + (size_t)r * BS;
-  const int within = r & (BS - 1);
-  const int b = bj.mode == 2 ? 0 : bj.idx[r / BS];
-  return bj.inv + ((size_t)b * BS + within) * BS;
+// Offsets (in entries) of the stored inverse rows of this lane's VEC rows e .. e+VEC-1; an
+// invalid lane gets offset 0 (the first stored row) so that its loads stay in bounds.
+template <typename S, int VEC, int BS>
+__device__ __forceinline__ void bj_offsets(const BJ<S>& dinv, int e, bool valid, size_t (&off)[VEC]) {
+  if (dinv.mode == 3) {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) off[i] = bj_chunk<VEC>(e + i) * BS;
+  } else if (dinv.mode == 0) {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) off[i] = (size_t)(e + i) * BS;
+  } else {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      const int row = e + i;
+      const int b = (dinv.mode == 2 || !valid) ? 0 : dinv.idx[row / BS];
+      off[i] = ((size_t)b * BS + (row & (BS - 1))) * BS;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) off[i] = valid ? off[i] : 0;
 }
 
-// Block-Jacobi: z = D^{-1} r for the VEC rows of this lane.  Inverse rows are stored
-// contiguously: row i's BS entries at dinv[i*BS].  Blocks of BS rows; when BS > VEC a block
-// spans BS/VEC consecutive lanes whose values are exchanged by shuffles (every lane of the
-// wave must call this).
+// Row q (0 <= q < NR, lane row i0 + q) of the lane's block-Jacobi product, from its stored
+// inverse row `row` and the lane's inputs r (BS <= VEC) or the block's gathered inputs rb.
 template <typename C, typename S, int VEC, int BS>
-__device__ __forceinline__ void bj_apply_lane(const BJ<S>& dinv, int e, bool valid,
-                                              const C (&r)[VEC], C (&z)[VEC]) {
-  if constexpr (BS <= VEC) {
+__device__ __forceinline__ C bj_row_dot(const Vec<S, BS>& row, int q, const C (&r)[VEC],
+                                        const C* rb) {
+  C acc = C(0);
+  if constexpr (BS > VEC) {
 #pragma unroll
-    for (int sb = 0; sb < VEC / BS; ++sb) {
-#pragma unroll
-      for (int i = 0; i < BS; ++i) {
-        C row[BS];
-        if (valid) loadv<C, S, BS>(bj_row<S, BS>(dinv, e + sb * BS + i), row);
-        C acc = C(0);
-#pragma unroll
-        for (int k = 0; k < BS; ++k) acc += row[k] * r[sb * BS + k];
-        z[sb * BS + i] = valid ? acc : C(0);
-      }
-    }
+    for (int k = 0; k < BS; ++k) acc += (C)row.v[k] * rb[k];
   } else {
+    const int sb = q / BS;  // block within the lane
+#pragma unroll
+    for (int k = 0; k < BS; ++k) acc += (C)row.v[k] * r[sb * BS + k];
+  }
+  return acc;
+}
+
+// The BS inputs of the block of this lane's rows when a block spans BS/VEC lanes (every lane
+// of the wave must call this).
+template <typename C, int VEC, int BS>
+__device__ __forceinline__ void bj_gather(const C (&r)[VEC], C (&rb)[BS > VEC ? BS : 1]) {
+  if constexpr (BS > VEC) {
     constexpr int LPB = BS / VEC;  // lanes per block
     const int lane = threadIdx.x & 63;
     const int base = lane & ~(LPB - 1);
-    C rb[BS];
 #pragma unroll
     for (int k = 0; k < BS; ++k) rb[k] = __shfl(r[k % VEC], base + k / VEC);
+  }
+}
+
+// Block-Jacobi rows of one lane, loaded ahead of the values they multiply.
+template <typename S, int VEC, int BS>
+struct BJRows {
+  Vec<S, BS> row[VEC];
+};
+
+template <typename S, int VEC, int BS>
+__device__ __forceinline__ void bj_load(const BJ<S>& dinv, int e, bool valid, BJRows<S, VEC, BS>& R) {
+  size_t off[VEC];
+  bj_offsets<S, VEC, BS>(dinv, e, valid, off);
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-      C row[BS];
-      if (valid) loadv<C, S, BS>(bj_row<S, BS>(dinv, e + i), row);
-      C acc = C(0);
+  for (int i = 0; i < VEC; ++i) R.row[i] = *reinterpret_cast<const Vec<S, BS>*>(dinv.inv + off[i]);
+}
+
+// z = D^{-1} r with rows loaded by bj_load (every lane of the wave must call this).
+template <typename C, typename S, int VEC, int BS>
+__device__ __forceinline__ void bj_mul(const BJRows<S, VEC, BS>& R, bool valid, const C (&r)[VEC],
+                                       C (&z)[VEC]) {
+  C rb[BS > VEC ? BS : 1];
+  bj_gather<C, VEC, BS>(r, rb);
 #pragma unroll
-      for (int k = 0; k < BS; ++k) acc += row[k] * rb[k];
-      z[i] = valid ? acc : C(0);
+  for (int q = 0; q < VEC; ++q) {
+    const C acc = bj_row_dot<C, S, VEC, BS>(R.row[q], q, r, rb);
+    z[q] = valid ? acc : C(0);
+  }
+}
+
+// Block-Jacobi: z = D^{-1} r for the VEC rows of this lane (rows e .. e+VEC-1).  Blocks of BS
+// rows; when BS > VEC a block spans BS/VEC consecutive lanes whose values are exchanged by
+// shuffles (every lane of the wave must call this).  Inverse rows are loaded without branches,
+// RCH rows in flight at a time.
+template <typename C, typename S, int VEC, int BS>
+__device__ __forceinline__ void bj_apply_lane(const BJ<S>& dinv, int e, bool valid,
+                                              const C (&r)[VEC], C (&z)[VEC]) {
+  size_t off[VEC];
+  bj_offsets<S, VEC, BS>(dinv, e, valid, off);
+  C rb[BS > VEC ? BS : 1];
+  bj_gather<C, VEC, BS>(r, rb);
+  constexpr int RCH = VEC < 4 ? VEC : 4;
+#pragma unroll
+  for (int i0 = 0; i0 < VEC; i0 += RCH) {
+    Vec<S, BS> row[RCH];
+#pragma unroll
+    for (int i = 0; i < RCH; ++i) row[i] = *reinterpret_cast<const Vec<S, BS>*>(dinv.inv + off[i0 + i]);
+#pragma unroll
+    for (int i = 0; i < RCH; ++i) {
+      const C acc = bj_row_dot<C, S, VEC, BS>(row[i], i0 + i, r, rb);
+      z[i0 + i] = valid ? acc : C(0);
     }
   }
 }

@@ -86,10 +86,11 @@ class Engine {
   virtual ~Engine() {}
   // setup
   // invert nslot diagonal blocks (block reps[i] into slot i; reps == nullptr: every block)
+  // lay: row layout of a per-block table (0 row-major, else interleaved for lanes of lay rows)
   virtual hipError_t bj_setup_stencil(const EngineCtx& c, const Coef<double>& Mc, void* dinv,
-                                      int* fail, int nslot, const int* reps) = 0;
+                                      int* fail, int nslot, const int* reps, int lay) = 0;
   virtual hipError_t bj_setup_csr(const EngineCtx& c, const double* kval, double sigma, void* dinv,
-                                  int* fail, int nslot, const int* reps) = 0;
+                                  int* fail, int nslot, const int* reps, int lay) = 0;
   virtual hipError_t csr_values(const EngineCtx& c, long nnz, const double* kval, void* out) = 0;
   // CG
   virtual hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) = 0;
@@ -98,9 +99,11 @@ class Engine {
   virtual hipError_t cg_finish(const EngineCtx& c) = 0;
   // GMRES
   virtual hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) = 0;
+  // Arnoldi step k of the cycle (k = the device's j for every step that does work)
   virtual hipError_t gm_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
-                             const BJDesc& dinv) = 0;
-  virtual hipError_t gm_finish(const EngineCtx& c, const BJDesc& dinv) = 0;
+                             const BJDesc& dinv, int k) = 0;
+  // nsteps: Arnoldi steps enqueued in this cycle (an upper bound on the device's J)
+  virtual hipError_t gm_finish(const EngineCtx& c, const BJDesc& dinv, int nsteps) = 0;
   // verification access
   virtual hipError_t apply_m(const EngineCtx& c, const Coef<double>& Mc, double sigma,
                              const void* x, void* y) = 0;
@@ -133,15 +136,15 @@ class EngineT final : public Engine {
   int elem_bytes() const override { return (int)sizeof(S); }
 
   hipError_t bj_setup_stencil(const EngineCtx& c, const Coef<double>& Mc, void* dinv, int* fail,
-                              int nslot, const int* reps) override {
+                              int nslot, const int* reps, int lay) override {
     hipLaunchKernelGGL(k_bj_setup_stencil<S>, dim3((nslot + 127) / 128), dim3(128), 0, c.stream,
-                       nslot, c.bs, c.geo, Mc, (S*)dinv, fail, reps);
+                       nslot, c.bs, c.geo, Mc, (S*)dinv, fail, reps, lay);
     return hipGetLastError();
   }
   hipError_t bj_setup_csr(const EngineCtx& c, const double* kval, double sigma, void* dinv, int* fail,
-                          int nslot, const int* reps) override {
+                          int nslot, const int* reps, int lay) override {
     hipLaunchKernelGGL(k_bj_setup_csr<S>, dim3((nslot + 127) / 128), dim3(128), 0, c.stream, nslot,
-                       c.bs, c.geo.N, c.csr, kval, sigma, (S*)dinv, fail, reps);
+                       c.bs, c.geo.N, c.csr, kval, sigma, (S*)dinv, fail, reps, lay);
     return hipGetLastError();
   }
   hipError_t csr_values(const EngineCtx& c, long nnz, const double* kval, void* out) override {
@@ -211,41 +214,60 @@ class EngineT final : public Engine {
     dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_begin_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
     return hipGetLastError();
   }
-  template <int VEC, int FMT, int PREC>
+  template <int VEC, int FMT, int PREC, int NDM>
   void gm_matvec_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc) {
     const Coef<C> M = cast_coef<C>(Mc);
     const C msig = (C)(cfg.sigma * c.kscale);
-    MPRK_LAUNCH_KC(c, KC_GM_MATVEC, (k_gm_matvec<S, C, VEC, FMT, PREC>), c.ln_mv_red, c.ln_mv_red, c.geo, M, c.csr,
+    MPRK_LAUNCH_KC(c, KC_GM_MATVEC, (k_gm_matvec<S, C, VEC, FMT, PREC, NDM>), c.ln_mv_red, c.ln_mv_red, c.geo, M, c.csr,
                 (const S*)c.mval, msig, (const S*)c.z, (S*)c.V, c.vstride, cfg, c.ctl, c.partials,
                 c.pstride);
   }
-  template <int VEC, int BS>
+  template <int VEC, int BS, int NDM>
   void gm_orth_t(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) {
-    MPRK_LAUNCH_KC(c, KC_GM_ORTH, (k_gm_orth<S, C, VEC, BS>), c.ln_red, c.ln_red, (S*)c.V, c.vstride,
+    MPRK_LAUNCH_KC(c, KC_GM_ORTH, (k_gm_orth<S, C, VEC, BS, NDM>), c.ln_red, c.ln_red, (S*)c.V, c.vstride,
                    (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.partials, c.pstride);
   }
-  hipError_t gm_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
-                     const BJDesc& dinv) override {
+  template <int NDM>
+  void gm_iter_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc, const BJDesc& dinv) {
     const bool prec = c.bs > 0;
     if (c.fmt == 1) {
-      if (prec) gm_matvec_t<1, 1, 1>(c, cfg, Mc); else gm_matvec_t<1, 1, 0>(c, cfg, Mc);
+      if (prec) gm_matvec_t<1, 1, 1, NDM>(c, cfg, Mc); else gm_matvec_t<1, 1, 0, NDM>(c, cfg, Mc);
     } else if (c.vec == 8) {
-      if (prec) gm_matvec_t<V8, 0, 1>(c, cfg, Mc); else gm_matvec_t<V8, 0, 0>(c, cfg, Mc);
+      if (prec) gm_matvec_t<V8, 0, 1, NDM>(c, cfg, Mc); else gm_matvec_t<V8, 0, 0, NDM>(c, cfg, Mc);
     } else if (c.vec == 4) {
-      if (prec) gm_matvec_t<4, 0, 1>(c, cfg, Mc); else gm_matvec_t<4, 0, 0>(c, cfg, Mc);
+      if (prec) gm_matvec_t<4, 0, 1, NDM>(c, cfg, Mc); else gm_matvec_t<4, 0, 0, NDM>(c, cfg, Mc);
     } else {
-      if (prec) gm_matvec_t<1, 0, 1>(c, cfg, Mc); else gm_matvec_t<1, 0, 0>(c, cfg, Mc);
+      if (prec) gm_matvec_t<1, 0, 1, NDM>(c, cfg, Mc); else gm_matvec_t<1, 0, 0, NDM>(c, cfg, Mc);
     }
-    dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_orth_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
+    dispatch_vec_bs(c, [&](auto vec, auto bs) {
+      gm_orth_t<decltype(vec)::value, decltype(bs)::value, NDM>(c, cfg, dinv);
+    });
+  }
+  hipError_t gm_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
+                     const BJDesc& dinv, int k) override {
+    // smallest compiled bound on the basis size that covers step k
+    if (k < 4) gm_iter_t<4>(c, cfg, Mc, dinv);
+    else if (k < 8) gm_iter_t<8>(c, cfg, Mc, dinv);
+    else if (k < 16) gm_iter_t<16>(c, cfg, Mc, dinv);
+    else gm_iter_t<MAXD>(c, cfg, Mc, dinv);
     return hipGetLastError();
   }
-  template <int VEC, int BS>
+  template <int VEC, int BS, int NDM>
   void gm_finish_t(const EngineCtx& c, const BJDesc& dinv) {
-    MPRK_LAUNCH_KC(c, KC_GM_FINISH, (k_gm_finish<S, C, VEC, BS>), c.ln_vec, c.ln_vec, c.y, (const S*)c.V,
+    MPRK_LAUNCH_KC(c, KC_GM_FINISH, (k_gm_finish<S, C, VEC, BS, NDM>), c.ln_vec, c.ln_vec, c.y, (const S*)c.V,
                 c.vstride, bj_typed<S>(dinv), c.ctl);
   }
-  hipError_t gm_finish(const EngineCtx& c, const BJDesc& dinv) override {
-    dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_finish_t<decltype(vec)::value, decltype(bs)::value>(c, dinv); });
+  template <int NDM>
+  void gm_finish_n(const EngineCtx& c, const BJDesc& dinv) {
+    dispatch_vec_bs(c, [&](auto vec, auto bs) {
+      gm_finish_t<decltype(vec)::value, decltype(bs)::value, NDM>(c, dinv);
+    });
+  }
+  hipError_t gm_finish(const EngineCtx& c, const BJDesc& dinv, int nsteps) override {
+    if (nsteps <= 4) gm_finish_n<4>(c, dinv);
+    else if (nsteps <= 8) gm_finish_n<8>(c, dinv);
+    else if (nsteps <= 16) gm_finish_n<16>(c, dinv);
+    else gm_finish_n<MAXM>(c, dinv);
     return hipGetLastError();
   }
 

@@ -22,10 +22,18 @@
 
 namespace mprk {
 
-// Basis vectors handled per chunk in the GMRES kernels: their loads are issued back to back.
-template <int VEC>
+// Basis vectors handled per chunk in the GMRES kernels (their loads are issued back to back):
+// 64 bytes per lane per chunk.
+template <typename S, int VEC>
 __host__ __device__ constexpr int basis_chunk() {
-  return VEC >= 8 ? 4 : 8;
+  return 64 / (int)(sizeof(S) * VEC) < 1 ? 1 : 64 / (int)(sizeof(S) * VEC) > 8 ? 8 : 64 / (int)(sizeof(S) * VEC);
+}
+
+// Whether a kernel loads this lane's block-Jacobi rows up front, together with its other
+// independent loads (when they fit in 128 bytes per lane), or after its vector work.
+template <typename S, int VEC, int BS>
+__host__ __device__ constexpr bool bj_early() {
+  return BS > 0 && sizeof(S) * VEC * BS <= 128;
 }
 
 struct CombArgs {
@@ -289,25 +297,24 @@ __global__ __launch_bounds__(TPB) void k_cg_begin(Launch ln, const double* __res
   for (int it = 0; it < ln.nit; ++it) {
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;
     const bool valid = g < ln.ng;
+    const int e = valid ? g * VEC : 0;  // an invalid lane reads group 0 and discards it
+    double t[VEC];
+    loadv<double, double, VEC>(res + e, t);
+    BJRows<S, VEC, bj_early<S, VEC, BS>() ? BS : 1> R;
+    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS>(dinv, e, valid, R);
     C rv[VEC], zv[VEC];
-    if (valid) {
-      double t[VEC];
-      loadv<double, double, VEC>(res + g * VEC, t);
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) rv[v] = rnd<S, C>((C)(t[v] * inv));
-    } else {
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) rv[v] = C(0);
-    }
+    for (int v = 0; v < VEC; ++v) rv[v] = valid ? rnd<S, C>((C)(t[v] * inv)) : C(0);
     C prz = C(0), prr = C(0);
     if constexpr (BS > 0) {
-      bj_apply_lane<C, S, VEC, BS>(dinv, g * VEC, valid, rv, zv);
+      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS>(R, valid, rv, zv);
+      else bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, rv, zv);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) zv[v] = rnd<S, C>(zv[v]);
     }
     if (valid) {
-      storev<S, C, VEC>(r + g * VEC, rv);
-      if constexpr (BS > 0) storev<S, C, VEC>(z + g * VEC, zv);
+      storev<S, C, VEC>(r + e, rv);
+      if constexpr (BS > 0) storev<S, C, VEC>(z + e, zv);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         prr += rv[v] * rv[v];
@@ -392,28 +399,28 @@ __global__ __launch_bounds__(TPB) void k_cg_upd(Launch ln, S* __restrict__ x,
   for (int it = 0; it < ln.nit; ++it) {
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;
     const bool valid = g < ln.ng;
-    const int e = g * VEC;
-    C rv[VEC], zv[VEC];
-    if (valid) {
-      C pv[VEC], qv[VEC], xv[VEC];
-      loadv<C, S, VEC>(p + e, pv);
-      loadv<C, S, VEC>(q + e, qv);
-      loadv<C, S, VEC>(r + e, rv);
-      if (!first) loadv<C, S, VEC>(x + e, xv);
+    const int e = valid ? g * VEC : 0;  // an invalid lane reads group 0 and discards it
+    // all loads first (x is read but unused in the first iteration)
+    C rv[VEC], zv[VEC], pv[VEC], qv[VEC], xv[VEC];
+    loadv<C, S, VEC>(p + e, pv);
+    loadv<C, S, VEC>(q + e, qv);
+    loadv<C, S, VEC>(r + e, rv);
+    loadv<C, S, VEC>(x + e, xv);
+    BJRows<S, VEC, bj_early<S, VEC, BS>() ? BS : 1> R;
+    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS>(dinv, e, valid, R);
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) {
-        xv[v] = first ? alpha * pv[v] : xv[v] + alpha * pv[v];
-        rv[v] = rnd<S, C>(rv[v] - alpha * qv[v]);
-      }
+    for (int v = 0; v < VEC; ++v) {
+      xv[v] = first ? alpha * pv[v] : xv[v] + alpha * pv[v];
+      rv[v] = valid ? rnd<S, C>(rv[v] - alpha * qv[v]) : C(0);
+    }
+    if (valid) {
       storev<S, C, VEC>(x + e, xv);
       storev<S, C, VEC>(r + e, rv);
-    } else {
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) rv[v] = C(0);
     }
     C prz = C(0), prr = C(0);
     if constexpr (BS > 0) {
-      bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, rv, zv);
+      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS>(R, valid, rv, zv);
+      else bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, rv, zv);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) zv[v] = rnd<S, C>(zv[v]);
       if (valid) storev<S, C, VEC>(z + e, zv);
@@ -495,25 +502,24 @@ __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __res
   for (int it = 0; it < ln.nit; ++it) {
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;
     const bool valid = g < ln.ng;
+    const int e = valid ? g * VEC : 0;  // an invalid lane reads group 0 and discards it
+    double t[VEC];
+    loadv<double, double, VEC>(res + e, t);
+    BJRows<S, VEC, bj_early<S, VEC, BS>() ? BS : 1> R;
+    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS>(dinv, e, valid, R);
     C rv[VEC];
     C s = C(0);
-    if (valid) {
-      double t[VEC];
-      loadv<double, double, VEC>(res + g * VEC, t);
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) {
-        rv[v] = rnd<S, C>((C)(t[v] * inv));
-        s += rv[v] * rv[v];
-      }
-      storev<S, C, VEC>(v0 + g * VEC, rv);
-    } else {
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) rv[v] = C(0);
+    for (int v = 0; v < VEC; ++v) {
+      rv[v] = valid ? rnd<S, C>((C)(t[v] * inv)) : C(0);
+      s += rv[v] * rv[v];
     }
+    if (valid) storev<S, C, VEC>(v0 + e, rv);
     if constexpr (BS > 0) {
       C zv[VEC];
-      bj_apply_lane<C, S, VEC, BS>(dinv, g * VEC, valid, rv, zv);
-      if (valid) storev<S, C, VEC>(zt + g * VEC, zv);
+      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS>(R, valid, rv, zv);
+      else bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, rv, zv);
+      if (valid) storev<S, C, VEC>(zt + e, zv);
     }
     acc[0] += (double)s;
   }
@@ -531,9 +537,23 @@ __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __res
   }
 }
 
+// The launch of Arnoldi step j is compiled for a bound NDM >= j + 1 on the number of basis
+// vectors it touches (the host knows j: every step of a cycle is enqueued in order), so that
+// its per-lane dot accumulators and coefficients take NDM registers, not MAXD.  A launch whose
+// step exceeds its bound flags the solve as failed instead of computing.
+__device__ __forceinline__ bool gm_bound_exceeded(Ctl* ctl, int nd, int ndm) {
+  if (nd <= ndm) return false;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->nonfinite = 1;
+    ctl->step_nonfinite = 1;
+    ctl->inner_done = 1;
+  }
+  return true;
+}
+
 // w = M BJ(v_j) (PREC: zt holds BJ of the stored vector j, scaled here by vscale[j]) or
 // w = M v_j ; V_{j+1} := LP(w) ; d_i = (V_i, LP(w)) for i <= j.
-template <typename S, typename C, int VEC, int FMT, int PREC>
+template <typename S, typename C, int VEC, int FMT, int PREC, int NDM>
 __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M, Csr csr,
                                                    const S* __restrict__ mval, C msig,
                                                    const S* __restrict__ z, S* __restrict__ V,
@@ -541,17 +561,24 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
                                                    double* partials, int pstride) {
   if (ctl->outer_done | ctl->inner_done) return;
   const int j = ctl->J;
-  count_work(ctl, KC_GM_MATVEC, j + 1);
   const int nd = j + 1;
+  if (gm_bound_exceeded(ctl, nd, NDM)) return;
+  count_work(ctl, KC_GM_MATVEC, nd);
   S* wout = V + (size_t)(j + 1) * vstride;
   const int L = xcd_block(ln.G);
-  C dacc[MAXD];
+  C dacc[NDM];
 #pragma unroll
-  for (int i = 0; i < MAXD; ++i) dacc[i] = C(0);
+  for (int i = 0; i < NDM; ++i) dacc[i] = C(0);
+  constexpr int CH = basis_chunk<S, VEC>() < NDM ? basis_chunk<S, VEC>() : NDM;
   for (int it = 0; it < ln.nit; ++it) {
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;
     if (g >= ln.ng) break;
     const int e = g * VEC;
+    // the first chunk of basis vectors (nd >= 1) is loaded together with the stencil inputs
+    Vec<S, VEC> v0[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+      v0[k] = *reinterpret_cast<const Vec<S, VEC>*>(V + (size_t)min(k, nd - 1) * vstride + e);
     C ctr[VEC], w[VEC];
     if constexpr (PREC) {
       InScaled<C, S, VEC> f{z, (C)ctl->vscale[j]};
@@ -563,19 +590,25 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
 #pragma unroll
     for (int v = 0; v < VEC; ++v) w[v] = rnd<S, C>(w[v]);
     storev<S, C, VEC>(wout + e, w);
-    // basis vectors in chunks of CH whose loads are issued together (indices past nd are
-    // clamped to a valid vector and their contribution discarded)
 #pragma unroll
-    for (int c = 0; c < MAXD; c += basis_chunk<VEC>()) {
+    for (int k = 0; k < CH; ++k) {
+      C s = C(0);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) s += (C)v0[k].v[v] * w[v];
+      dacc[k] += (k < nd) ? s : C(0);
+    }
+    // remaining basis vectors in chunks of CH whose loads are issued together (indices past
+    // nd are clamped to a valid vector and their contribution discarded)
+#pragma unroll
+    for (int c = CH; c < NDM; c += CH) {
       if (c < nd) {
-        constexpr int CH = basis_chunk<VEC>();
         C vv[CH][VEC];
 #pragma unroll
         for (int k = 0; k < CH; ++k)
           loadv<C, S, VEC>(V + (size_t)min(c + k, nd - 1) * vstride + e, vv[k]);
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-          if (c + k < MAXD) {
+          if (c + k < NDM) {
             C s = C(0);
 #pragma unroll
             for (int v = 0; v < VEC; ++v) s += vv[k][v] * w[v];
@@ -585,11 +618,11 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
       }
     }
   }
-  double acc[MAXD];
+  double acc[NDM];
 #pragma unroll
-  for (int i = 0; i < MAXD; ++i) acc[i] = (double)dacc[i];
-  __shared__ double tot[MAXD];
-  if (!reduce_to_last<MAXD>(acc, nd, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  for (int i = 0; i < NDM; ++i) acc[i] = (double)dacc[i];
+  __shared__ double tot[NDM];
+  if (!reduce_to_last<NDM>(acc, nd, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
   if (threadIdx.x < nd) ctl->hcol[threadIdx.x] = ctl->vscale[threadIdx.x] * tot[threadIdx.x] * cfg.invN;
 }
 
@@ -597,59 +630,72 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
 // h_{j+1,j} = ||w||; Givens update of the Hessenberg column; residual estimate |g_{j+1}|.
 // With a preconditioner (BS > 0) also zt = BJ(w), the next step's preconditioned direction
 // before normalisation.
-template <typename S, typename C, int VEC, int BS>
+template <typename S, typename C, int VEC, int BS, int NDM>
 __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, size_t vstride,
                                                  S* __restrict__ zt, BJ<S> dinv,
                                                  SolveCfg cfg, Ctl* ctl, double* partials,
                                                  int pstride) {
   if (ctl->outer_done | ctl->inner_done) return;
   const int j = ctl->J;
-  count_work(ctl, KC_GM_ORTH, j + 1);
   const int nd = j + 1;
-  C cf[MAXD];
+  if (gm_bound_exceeded(ctl, nd, NDM)) return;
+  count_work(ctl, KC_GM_ORTH, nd);
+  C cf[NDM];
 #pragma unroll
-  for (int i = 0; i < MAXD; ++i) cf[i] = i < nd ? (C)(ctl->hcol[i] * ctl->vscale[i]) : C(0);
+  for (int i = 0; i < NDM; ++i) cf[i] = i < nd ? (C)(ctl->hcol[i] * ctl->vscale[i]) : C(0);
   S* w = V + (size_t)(j + 1) * vstride;
   const int L = xcd_block(ln.G);
+  constexpr int CH = basis_chunk<S, VEC>() < NDM ? basis_chunk<S, VEC>() : NDM;
+  constexpr bool EARLY = bj_early<S, VEC, BS>();
   double acc[1] = {0.0};
   for (int it = 0; it < ln.nit; ++it) {
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;
     const bool valid = g < ln.ng;
-    const int e = g * VEC;
+    const int e = valid ? g * VEC : 0;  // an invalid lane reads group 0 and discards it
+    // every load that does not depend on a value is issued first: w, the first chunk of basis
+    // vectors (nd >= 1) and the block-Jacobi rows
+    Vec<S, VEC> wr = *reinterpret_cast<const Vec<S, VEC>*>(w + e);
+    Vec<S, VEC> v0[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+      v0[k] = *reinterpret_cast<const Vec<S, VEC>*>(V + (size_t)min(k, nd - 1) * vstride + e);
+    BJRows<S, VEC, EARLY ? BS : 1> R;
+    if constexpr (EARLY) bj_load<S, VEC, BS>(dinv, e, valid, R);
     C wv[VEC];
-    C s = C(0);
-    if (valid) {
-      loadv<C, S, VEC>(w + e, wv);
 #pragma unroll
-      for (int c = 0; c < MAXD; c += basis_chunk<VEC>()) {
-        if (c < nd) {
-          constexpr int CH = basis_chunk<VEC>();
-          C vv[CH][VEC];
+    for (int v = 0; v < VEC; ++v) wv[v] = (C)wr.v[v];
 #pragma unroll
-          for (int k = 0; k < CH; ++k)
-            loadv<C, S, VEC>(V + (size_t)min(c + k, nd - 1) * vstride + e, vv[k]);
+    for (int k = 0; k < CH; ++k) {  // cf is zero past nd
 #pragma unroll
-          for (int k = 0; k < CH; ++k) {
-            if (c + k < MAXD) {  // cf is zero past nd
+      for (int v = 0; v < VEC; ++v) wv[v] -= cf[k] * (C)v0[k].v[v];
+    }
 #pragma unroll
-              for (int v = 0; v < VEC; ++v) wv[v] -= cf[c + k] * vv[k][v];
-            }
+    for (int c = CH; c < NDM; c += CH) {
+      if (c < nd) {
+        C vv[CH][VEC];
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          loadv<C, S, VEC>(V + (size_t)min(c + k, nd - 1) * vstride + e, vv[k]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (c + k < NDM) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) wv[v] -= cf[c + k] * vv[k][v];
           }
         }
       }
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) {
-        wv[v] = rnd<S, C>(wv[v]);
-        s += wv[v] * wv[v];
-      }
-      storev<S, C, VEC>(w + e, wv);
-    } else {
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) wv[v] = C(0);
     }
+    C s = C(0);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      wv[v] = valid ? rnd<S, C>(wv[v]) : C(0);
+      s += wv[v] * wv[v];
+    }
+    if (valid) storev<S, C, VEC>(w + e, wv);
     if constexpr (BS > 0) {
       C zv[VEC];
-      bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, wv, zv);
+      if constexpr (EARLY) bj_mul<C, S, VEC, BS>(R, valid, wv, zv);
+      else bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, wv, zv);
       if (valid) storev<S, C, VEC>(zt + e, zv);
     }
     acc[0] += (double)s;
@@ -696,7 +742,8 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
 // A8 for GMRES: y += scale * BJ(sum_{i<J} ysol_i v_i) ; one LP pass done.  The J x J
 // triangular least-squares system is solved here by every block (J <= 32), so a cycle the
 // host ends early (fewer iterations enqueued than the device would run) is still promoted.
-template <typename S, typename C, int VEC, int BS>
+// NDM bounds J: the host passes the number of Arnoldi steps it enqueued in this cycle.
+template <typename S, typename C, int VEC, int BS, int NDM>
 __global__ __launch_bounds__(TPB) void k_gm_finish(Launch ln, double* __restrict__ y,
                                                    const S* __restrict__ V, size_t vstride,
                                                    BJ<S> dinv, Ctl* ctl) {
@@ -710,6 +757,13 @@ __global__ __launch_bounds__(TPB) void k_gm_finish(Launch ln, double* __restrict
     ctl->life_passes += 1;
   }
   if (J == 0) return;
+  if (J > NDM) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctl->nonfinite = 1;
+      ctl->step_nonfinite = 1;
+    }
+    return;
+  }
   __shared__ double ys[MAXM];
   if (threadIdx.x == 0) {
     for (int i = J - 1; i >= 0; --i) {
@@ -720,45 +774,59 @@ __global__ __launch_bounds__(TPB) void k_gm_finish(Launch ln, double* __restrict
     }
   }
   __syncthreads();
-  C cf[MAXM];
+  C cf[NDM];
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) cf[i] = i < J ? (C)(ys[i] * ctl->vscale[i]) : C(0);
+  for (int i = 0; i < NDM; ++i) cf[i] = i < J ? (C)(ys[i] * ctl->vscale[i]) : C(0);
   const int L = xcd_block(ln.G);
+  constexpr int CH = basis_chunk<S, VEC>() < NDM ? basis_chunk<S, VEC>() : NDM;
   for (int it = 0; it < ln.nit; ++it) {
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;
     const bool valid = g < ln.ng;
-    const int e = g * VEC;
+    const int e = valid ? g * VEC : 0;  // an invalid lane reads group 0 and discards it
+    // independent loads first: the first chunk of basis vectors (J >= 1), the block-Jacobi
+    // rows and y
+    Vec<S, VEC> v0[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+      v0[k] = *reinterpret_cast<const Vec<S, VEC>*>(V + (size_t)min(k, J - 1) * vstride + e);
+    BJRows<S, VEC, bj_early<S, VEC, BS>() ? BS : 1> R;
+    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS>(dinv, e, valid, R);
+    double yv[VEC];
+    loadv<double, double, VEC>(y + e, yv);
     C t[VEC], zv[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) t[v] = C(0);
-    if (valid) {
 #pragma unroll
-      for (int c = 0; c < MAXM; c += basis_chunk<VEC>()) {
-        if (c < J) {
-          constexpr int CH = basis_chunk<VEC>();
-          C vv[CH][VEC];
+    for (int k = 0; k < CH; ++k) {  // cf is zero past J
 #pragma unroll
-          for (int k = 0; k < CH; ++k)
-            loadv<C, S, VEC>(V + (size_t)min(c + k, J - 1) * vstride + e, vv[k]);
+      for (int v = 0; v < VEC; ++v) t[v] += cf[k] * (C)v0[k].v[v];
+    }
 #pragma unroll
-          for (int k = 0; k < CH; ++k) {
-            if (c + k < MAXM) {  // cf is zero past J
+    for (int c = CH; c < NDM; c += CH) {
+      if (c < J) {
+        C vv[CH][VEC];
 #pragma unroll
-              for (int v = 0; v < VEC; ++v) t[v] += cf[c + k] * vv[k][v];
-            }
+        for (int k = 0; k < CH; ++k)
+          loadv<C, S, VEC>(V + (size_t)min(c + k, J - 1) * vstride + e, vv[k]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (c + k < NDM) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) t[v] += cf[c + k] * vv[k][v];
           }
         }
       }
     }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) t[v] = valid ? t[v] : C(0);
     if constexpr (BS > 0) {
-      bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, t, zv);
+      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS>(R, valid, t, zv);
+      else bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, t, zv);
     } else {
 #pragma unroll
       for (int v = 0; v < VEC; ++v) zv[v] = t[v];
     }
     if (valid) {
-      double yv[VEC];
-      loadv<double, double, VEC>(y + e, yv);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) yv[v] += sc * (double)zv[v];
       storev<double, double, VEC>(y + e, yv);
@@ -816,21 +884,29 @@ __device__ inline int gj_invert(double (&a)[BJ_MAX][BJ_MAX], double (&inv)[BJ_MA
   return 0;
 }
 
+// Row i of slot blk's inverse goes to chunk blk * BS + i (lay == 0) or to its place in the
+// interleaved layout for lanes of `lay` rows (lay = 1, 4 or 8).
 template <typename S>
-__device__ inline void bj_store(S* dinv, int blk, int BS, int n, const double (&inv)[BJ_MAX][BJ_MAX]) {
-  for (int i = 0; i < BS; ++i)
+__device__ inline void bj_store(S* dinv, int blk, int BS, int n, const double (&inv)[BJ_MAX][BJ_MAX],
+                                int lay) {
+  for (int i = 0; i < BS; ++i) {
+    const int r = blk * BS + i;
+    const size_t chunk = lay == 8 ? bj_chunk<8>(r) : lay == 4 ? bj_chunk<4>(r)
+                       : lay == 1 ? bj_chunk<1>(r) : (size_t)r;
     for (int k = 0; k < BS; ++k) {
       double v = (i < n && k < n) ? inv[i][k] : (i == k ? 1.0 : 0.0);
-      dinv[((size_t)blk * BS + i) * BS + k] = (S)v;
+      dinv[chunk * BS + k] = (S)v;
     }
+  }
 }
 
 // Diagonal blocks of M = I - sigma K for the stencil operator (Mc = stencil of M in FP64).
-// Slot i receives the inverse of block reps[i] (reps == nullptr: block i), so the per-block
-// table and the table of distinct blocks come from the same arithmetic.
+// Slot i receives the inverse of block reps[i] (reps == nullptr: block i, stored in the
+// layout `lay`), so the per-block table and the table of distinct blocks come from the same
+// arithmetic.
 template <typename S>
 __global__ void k_bj_setup_stencil(int nslot, int BS, Geo geo, Coef<double> Mc, S* dinv,
-                                   int* fail, const int* reps) {
+                                   int* fail, const int* reps, int lay) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= nslot) return;
   const int blk = reps ? reps[slot] : slot;
@@ -851,13 +927,13 @@ __global__ void k_bj_setup_stencil(int nslot, int BS, Geo geo, Coef<double> Mc, 
     }
   }
   if (gj_invert(a, inv, n)) atomicOr(fail, 1);
-  bj_store<S>(dinv, slot, BS, n, inv);
+  bj_store<S>(dinv, slot, BS, n, inv, reps ? 0 : lay);
 }
 
 // Diagonal blocks of M = I - sigma K from the FP64 CSR values of K (slots as above).
 template <typename S>
 __global__ void k_bj_setup_csr(int nslot, int BS, int N, Csr csr, const double* kval, double sigma,
-                               S* dinv, int* fail, const int* reps) {
+                               S* dinv, int* fail, const int* reps, int lay) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= nslot) return;
   const int blk = reps ? reps[slot] : slot;
@@ -874,7 +950,7 @@ __global__ void k_bj_setup_csr(int nslot, int BS, int N, Csr csr, const double* 
     }
   }
   if (gj_invert(a, inv, n)) atomicOr(fail, 1);
-  bj_store<S>(dinv, slot, BS, n, inv);
+  bj_store<S>(dinv, slot, BS, n, inv, reps ? 0 : lay);
 }
 
 // LP copy of the CSR values of K, scaled by a power of two into [-1, 1].

@@ -528,10 +528,12 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
       if (B.mode == 2) B.idx.clear();
     } else {
       B.nslot = nblk;
-      B.mode = 0;
+      B.mode = 3;  // rows interleaved for the LP kernels' lanes of vec_lp rows
     }
-    B.o_inv = take((size_t)B.nslot * bs * bs * lp_bytes);
-    if (B.mode) B.o_reps = take((size_t)B.nslot * 4);
+    const size_t rows = B.mode == 3 ? std::max((size_t)nblk * bs, bj_chunks((long)nblk * bs, vec_lp))
+                                    : (size_t)B.nslot * bs;
+    B.o_inv = take(rows * bs * lp_bytes);
+    if (B.table()) B.o_reps = take((size_t)B.nslot * 4);
     if (B.mode == 1) B.o_idx = take((size_t)nblk * 4);
   }
   if (o.format == MPRK_FMT_CSR) {
@@ -655,7 +657,7 @@ extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev,
     const mprk_handle::BJSet& B = h->bjsets[q];
     void* dinv = h->ws + B.o_inv;
     const int* reps = nullptr;
-    if (B.mode) {
+    if (B.table()) {
       HIPCHK(hipMemcpyAsync(h->ws + B.o_reps, B.reps.data(), B.reps.size() * 4, hipMemcpyHostToDevice, h->stream));
       reps = (const int*)(h->ws + B.o_reps);
     }
@@ -663,9 +665,10 @@ extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev,
       HIPCHK(hipMemcpyAsync(h->ws + B.o_idx, B.idx.data(), B.idx.size() * 4, hipMemcpyHostToDevice, h->stream));
     if (h->op.format == MPRK_FMT_CSR)
       HIPCHK(h->eng->bj_setup_csr(c, (const double*)(h->ws + h->o_kval), h->sigmas[q], dinv, fail,
-                                  B.nslot, reps));
+                                  B.nslot, reps, B.mode == 3 ? h->vec_lp : 0));
     else
-      HIPCHK(h->eng->bj_setup_stencil(c, stage_coef(h->Kc, h->sigmas[q]), dinv, fail, B.nslot, reps));
+      HIPCHK(h->eng->bj_setup_stencil(c, stage_coef(h->Kc, h->sigmas[q]), dinv, fail, B.nslot, reps,
+                                      B.mode == 3 ? h->vec_lp : 0));
   }
   int hfail = 0;
   HIPCHK(hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -792,11 +795,13 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
     }
     if (cg) HIPCHK(eng->cg_begin(c, cfg, dinv));
     else HIPCHK(eng->gm_begin(c, cfg, dinv));
+    int enq = 0;  // Krylov iterations enqueued in this pass
     if (certain) {
       const int n = std::min(maxp, H.iters[pass] + predict_margin);
+      enq = n;
       for (int k = 0; k < n; ++k) {
         if (cg) HIPCHK(eng->cg_iter(c, cfg, Mc, dinv, k));
-        else HIPCHK(eng->gm_iter(c, cfg, Mc, dinv));
+        else HIPCHK(eng->gm_iter(c, cfg, Mc, dinv, k));
       }
     } else {
       std::deque<int> pend;
@@ -806,9 +811,10 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
         const int cnt = std::min(chunk, maxp - its);
         for (int k = 0; k < cnt; ++k) {
           if (cg) HIPCHK(eng->cg_iter(c, cfg, Mc, dinv, its + k));
-          else HIPCHK(eng->gm_iter(c, cfg, Mc, dinv));
+          else HIPCHK(eng->gm_iter(c, cfg, Mc, dinv, its + k));
         }
         its += cnt;
+        enq = its;
         rc = poll_enqueue(&slot_id);
         if (rc) return rc;
         pend.push_back(slot_id);
@@ -826,7 +832,7 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
       if (outer) break;
     }
     if (cg) HIPCHK(eng->cg_finish(c));
-    else HIPCHK(eng->gm_finish(c, dinv));
+    else HIPCHK(eng->gm_finish(c, dinv, enq));
   }
   return stage_record(slot);
 }
@@ -1246,7 +1252,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
       if ((cg ? h->eng->cg_begin(c, cfg, dinv) : h->eng->gm_begin(c, cfg, dinv)) != hipSuccess) { rc = MPRK_EDEVICE; break; }
       if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = MPRK_EDEVICE; break; }
       for (int k = 0; k < 4 && rc == MPRK_OK; ++k)
-        if ((cg ? h->eng->cg_iter(c, cfg, Mc, dinv, k) : h->eng->gm_iter(c, cfg, Mc, dinv)) != hipSuccess) rc = MPRK_EDEVICE;
+        if ((cg ? h->eng->cg_iter(c, cfg, Mc, dinv, k) : h->eng->gm_iter(c, cfg, Mc, dinv, k)) != hipSuccess) rc = MPRK_EDEVICE;
       if (rc == MPRK_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = MPRK_EDEVICE;
       if (rc == MPRK_OK && hipEventSynchronize(e1) != hipSuccess) rc = MPRK_EDEVICE;
       if (rc == MPRK_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MPRK_EDEVICE;

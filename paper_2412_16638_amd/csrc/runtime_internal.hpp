@@ -63,8 +63,10 @@ struct mprk_handle {
   size_t vstride = 0;
   // block-Jacobi inverse sets, one per distinct sigma
   struct BJSet {
-    int mode = 0;          // 0 per-block, 1 distinct table + index, 2 one shared inverse
+    int mode = 0;          // 0 per-block (row-major), 1 distinct table + index, 2 one shared
+                           // inverse, 3 per-block with rows interleaved for lanes of vec_lp rows
     int nslot = 0;         // inverses stored
+    bool table() const { return mode == 1 || mode == 2; }  // slots hold distinct inverses
     size_t o_inv = 0, o_reps = 0, o_idx = 0;
     std::vector<int> reps; // representative block of each slot (modes 1, 2)
     std::vector<int> idx;  // slot of each block (mode 1)

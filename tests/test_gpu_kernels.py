@@ -153,3 +153,31 @@ def test_block_covering_everything_needs_one_iteration():
     x, info = st.solve(0, torch.from_numpy(rhs).cuda())
     assert info['iters'] == 1, info
     st.close()
+
+
+@pytest.mark.parametrize("restart", [30, 10, 6])
+def test_long_gmres_cycles_match_sparse_lu(restart):
+    # unpreconditioned GMRES on a stiff advection-diffusion stage matrix: about 29 Arnoldi steps
+    # per cycle to 1e-12, so every compiled bound on the basis size (4, 8, 16, 33) is used;
+    # shorter cycles (restart 10, 6) need many outer passes
+    shape = (16, 16, 16)
+    log_case('gmres_long', restart=restart)
+    prec = M.precisions('fp64', 'gmres', precond='none', rtol=1e-12, outer_tol=1e-11,
+                        restart=restart, maxit=restart, refine_max=200)
+    dt = 5e-2
+    st = M.Stepper(shape, W.PERIODIC, W.ADVDIFF, 1e-2, (1.0, 0.5, 0.25), A.FMT_STENCIL, 'SDIRK3',
+                   prec, dt)
+    rhs = np.random.default_rng(4).standard_normal(st.N)
+    x, info = st.solve(1, torch.from_numpy(rhs).cuda())
+    K = operators.operator(shape, W.PERIODIC, W.ADVDIFF, 1e-2, (1.0, 0.5, 0.25))
+    Mx = operators.stage_matrix(K, dt * st.tab.a_lo[st.tab.s + 1])
+    import scipy.sparse.linalg as spla
+    ref = spla.spsolve(Mx.tocsc(), rhs)
+    err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    st.close()
+    assert info['converged'] == 1, info
+    assert err <= 1e-9, (err, info)
+    if restart == 30:
+        assert info['iters'] >= 20, info
+    else:
+        assert info['passes'] >= 2, info
