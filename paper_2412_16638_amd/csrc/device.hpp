@@ -9,8 +9,9 @@
 //     (hardware dispatch sends block b to XCD b % 8), which keeps stencil halo planes of
 //     neighbouring blocks in the same L2;
 //   * reductions are deterministic: per-thread partial -> wave64 shuffle tree -> fixed-order
-//     block sum -> per-block partials -> the last block to finish (atomic ticket) adds the
-//     partials in block order in FP64 and computes the dependent scalars.
+//     block sum -> per-block partials -> per-group sums (groups of 64 blocks, summed by the
+//     group's last block) -> the last group to finish adds the group sums in group order in
+//     FP64 and computes the dependent scalars (see reduce_to_last).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -99,7 +100,6 @@ struct Ctl {
   double g[MAXM + 1];                // rotated right-hand side
   double ysol[MAXM];                 // least-squares solution of the cycle
   double vscale[MAXM + 1];           // basis vector i = vscale[i] * stored vector i
-  unsigned int ticket;               // last-block counter (self-resetting)
   int pass_iters[MAXPASS];           // Krylov iterations of each pass of the current stage
   long long worked[KC_COUNT];        // launches per kernel class that did work (profiling)
   long long units[KC_COUNT];         // basis vectors touched (GMRES kernels), else launches
@@ -171,13 +171,58 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block-level fixed-order reduction of nd (<= ND) per-thread values into partials[d*pstride + L];
-// returns true in the last block, where tot[0..nd) (shared memory) then holds the grand totals.
+// Workspace of a grid reduction.  Level 1: one partial per block, p1[d * s1 + L]; level 2: one
+// sum per group of RGRP consecutive blocks, p2[d * s2 + group].  Counters: tick[0] counts the
+// groups done, tick[TSTRIDE * (1 + group)] the blocks of a group done (256 bytes apart, so that
+// concurrent tickets of different groups do not share a line).  All counters are zero between
+// launches (each is reset by the block that completes it).
+constexpr int RGRP = 64;
+constexpr int TSTRIDE = 64;
+
+struct Red {
+  double* p1;
+  double* p2;
+  unsigned int* tick;
+  int s1, s2;
+};
+
+// Number of counters a reduction over at most G blocks needs.
+__host__ __device__ inline size_t red_ticks(long G) {
+  return (size_t)TSTRIDE * (size_t)(1 + (G + RGRP - 1) / RGRP);
+}
+
+// Publish the calling wave's device-scope partial stores, then take a ticket.  The partials are
+// written with device-scope atomic stores, which are coherent across the XCDs once complete;
+// s_waitcnt 0 waits for their completion before the ticket is taken, so whoever draws the last
+// ticket reads (with device-scope loads) every published value.  No L2 writeback is needed:
+// only these partials cross blocks, never the kernel's plain data stores.
+__device__ __forceinline__ unsigned int publish_ticket(unsigned int* ctr) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  return __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double load_dev(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid reduction of nd (<= ND <= 64) per-thread values in fixed order: wave64 shuffle tree,
+// block sum over the waves, one partial per block; the last block of each group of RGRP blocks
+// sums the group's partials (one wave, lane = block within the group); the last group to finish
+// sums the group sums.  Returns true in that final block, where tot[0..nd) (shared memory)
+// holds the totals.  The order of every addition depends only on G and the block indices, so
+// results are bitwise reproducible for a given launch shape.
 template <int ND>
-__device__ bool reduce_to_last(const double (&v)[ND], int nd, double* __restrict__ partials,
-                               int pstride, unsigned int* ticket, int L, int G, double* tot) {
+__device__ bool reduce_to_last(const double (&v)[ND], int nd, const Red& red, int L, int G,
+                               double* tot) {
+  static_assert(ND <= 64, "one wave publishes all values of a block");
   __shared__ double wsum[NWAVE][ND];
-  __shared__ bool am_last;
+  __shared__ int stage;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
 #pragma unroll
@@ -188,30 +233,47 @@ __device__ bool reduce_to_last(const double (&v)[ND], int nd, double* __restrict
     }
   }
   __syncthreads();
-  if (threadIdx.x < nd) {
-    double s = 0.0;
+  const int grp = L / RGRP, g0 = grp * RGRP, gn = min(RGRP, G - g0);
+  const int ngrp = (G + RGRP - 1) / RGRP;
+  if (wave == 0) {
+    if (lane < nd) {
+      double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < NWAVE; ++w) s += wsum[w][threadIdx.x];
-    // agent-scope store: visible to the last block whichever XCD (L2) it runs on
-    __hip_atomic_store(partials + threadIdx.x * pstride + L, s, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
+      for (int w = 0; w < NWAVE; ++w) s += wsum[w][lane];
+      store_dev(red.p1 + (size_t)lane * red.s1 + L, s);
+    }
+    if (lane == 0) stage = publish_ticket(red.tick + TSTRIDE * (1 + grp)) == (unsigned)(gn - 1);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int t = atomicAdd(ticket, 1u);
-    am_last = (t == (unsigned int)(G - 1));
+  if (!stage) return false;
+  // last block of its group: group sums (wave 0, lane = block of the group)
+  if (wave == 0) {
+    double x[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+      x[d] = (d < nd && lane < gn) ? load_dev(red.p1 + (size_t)d * red.s1 + g0 + lane) : 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      if (d < nd) {
+        const double s = wave_sum(x[d]);
+        if (lane == d) store_dev(red.p2 + (size_t)d * red.s2 + grp, s);
+      }
+    }
+    if (lane == 0) {
+      __hip_atomic_store(red.tick + TSTRIDE * (1 + grp), 0u, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      stage = publish_ticket(red.tick) == (unsigned)(ngrp - 1) ? 2 : 0;
+    }
   }
   __syncthreads();
-  if (!am_last) return false;
-  __threadfence();  // acquire: the other blocks' partials are visible after this
-  // fixed-order total: every thread sums a strided, coalesced slice of each value's partials,
-  // then a fixed shuffle tree and a fixed-order combine of the waves
+  if (stage != 2) return false;
+  // final block: every thread sums a strided slice of each value's group sums, then a fixed
+  // shuffle tree and a fixed-order combine of the waves
   __shared__ double wtot[NWAVE][ND];
   for (int d = 0; d < nd; ++d) {
-    const double* p = partials + d * pstride;
+    const double* p = red.p2 + (size_t)d * red.s2;
     double s = 0.0;
-    for (int b = threadIdx.x; b < G; b += TPB) s += p[b];
+    for (int b = threadIdx.x; b < ngrp; b += TPB) s += load_dev(p + b);
     s = wave_sum(s);
     if (lane == 0) wtot[wave][d] = s;
   }
@@ -222,7 +284,7 @@ __device__ bool reduce_to_last(const double (&v)[ND], int nd, double* __restrict
     for (int w = 0; w < NWAVE; ++w) s += wtot[w][threadIdx.x];
     tot[threadIdx.x] = s;
   }
-  if (threadIdx.x == 0) *ticket = 0u;
+  if (threadIdx.x == 0) __hip_atomic_store(red.tick, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   return true;
 }

@@ -64,15 +64,14 @@ struct EngineCtx {
   Launch ln_vec;      // groups of `vec` elements (streaming kernels)
   Launch ln_row;      // CSR rows (VEC = 1)
   Launch ln_mv;       // launch of the SpMV kernels (= ln_vec for stencil, ln_row for CSR)
-  Launch ln_red;      // groups of `vec` elements, kernels with a grid reduction (<= 2048 blocks)
+  Launch ln_red;      // groups of `vec` elements, kernels with a grid reduction
   Launch ln_mv_red;   // SpMV kernels with a grid reduction
   int bs;             // block-Jacobi block size (0 = no preconditioner)
   Csr csr;
   const void* mval;   // LP CSR values of K / kscale (S)
   double kscale;
   Ctl* ctl;
-  double* partials;
-  int pstride;
+  Red red;            // grid-reduction workspace
   // LP vectors (S*)
   void *r, *z, *p0, *p1, *q, *x;
   void* V;
@@ -159,7 +158,7 @@ class EngineT final : public Engine {
   void cg_begin_t(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) {
     S* z = BS > 0 ? (S*)c.z : (S*)c.r;
     MPRK_LAUNCH_KC(c, KC_CG_BEGIN, (k_cg_begin<S, C, VEC, BS>), c.ln_red, c.ln_red, c.res, (S*)c.r, z,
-                bj_typed<S>(dinv), cfg, c.ctl, c.partials, c.pstride);
+                bj_typed<S>(dinv), cfg, c.ctl, c.red);
   }
   hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) override {
     dispatch_vec_bs(c, [&](auto vec, auto bs) { cg_begin_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
@@ -172,13 +171,13 @@ class EngineT final : public Engine {
     const Coef<C> M = cast_coef<C>(Mc);
     const C msig = (C)(cfg.sigma * c.kscale);
     MPRK_LAUNCH_KC(c, KC_CG_DIR, (k_cg_dir<S, C, VEC, FMT>), c.ln_mv_red, c.ln_mv_red, c.geo, M, c.csr,
-                (const S*)c.mval, msig, z, pold, pnew, (S*)c.q, c.ctl, c.partials, c.pstride);
+                (const S*)c.mval, msig, z, pold, pnew, (S*)c.q, c.ctl, c.red);
   }
   template <int VEC, int BS>
   void cg_upd_t(const EngineCtx& c, const SolveCfg& cfg, const S* p, const BJDesc& dinv) {
     S* z = BS > 0 ? (S*)c.z : (S*)c.r;
     MPRK_LAUNCH_KC(c, KC_CG_UPD, (k_cg_upd<S, C, VEC, BS>), c.ln_red, c.ln_red, (S*)c.x, p, (S*)c.r,
-                (const S*)c.q, z, bj_typed<S>(dinv), cfg, c.ctl, c.partials, c.pstride);
+                (const S*)c.q, z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
   }
   hipError_t cg_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
                      const BJDesc& dinv, int it) override {
@@ -208,7 +207,7 @@ class EngineT final : public Engine {
   template <int VEC, int BS>
   void gm_begin_t(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) {
     MPRK_LAUNCH_KC(c, KC_GM_BEGIN, (k_gm_begin<S, C, VEC, BS>), c.ln_red, c.ln_red, c.res, (S*)c.V,
-                   (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.partials, c.pstride);
+                   (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
   }
   hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) override {
     dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_begin_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
@@ -219,13 +218,12 @@ class EngineT final : public Engine {
     const Coef<C> M = cast_coef<C>(Mc);
     const C msig = (C)(cfg.sigma * c.kscale);
     MPRK_LAUNCH_KC(c, KC_GM_MATVEC, (k_gm_matvec<S, C, VEC, FMT, PREC, NDM>), c.ln_mv_red, c.ln_mv_red, c.geo, M, c.csr,
-                (const S*)c.mval, msig, (const S*)c.z, (S*)c.V, c.vstride, cfg, c.ctl, c.partials,
-                c.pstride);
+                (const S*)c.mval, msig, (const S*)c.z, (S*)c.V, c.vstride, cfg, c.ctl, c.red);
   }
   template <int VEC, int BS, int NDM>
   void gm_orth_t(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) {
     MPRK_LAUNCH_KC(c, KC_GM_ORTH, (k_gm_orth<S, C, VEC, BS, NDM>), c.ln_red, c.ln_red, (S*)c.V, c.vstride,
-                   (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.partials, c.pstride);
+                   (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
   }
   template <int NDM>
   void gm_iter_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc, const BJDesc& dinv) {

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<doubl
                                                   const double* __restrict__ rhs,
                                                   double* __restrict__ kout,
                                                   double* __restrict__ res, SolveCfg cfg, Ctl* ctl,
-                                                  double* partials, int pstride) {
+                                                  Red red) {
   if (ctl->outer_done) return;
   count_work(ctl, KC_RESIDUAL);
   const int L = xcd_block(ln.G);
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<doubl
     storev<double, double, VEC>(res + e, rr);
   }
   __shared__ double tot[3];
-  if (!reduce_to_last<3>(acc, 3, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (!reduce_to_last<3>(acc, 3, red, L, ln.G, tot)) return;
   if (threadIdx.x == 0) {
     const double rn = sqrt(tot[0]), bn = sqrt(tot[1]);
     const double rel = bn > 0.0 ? rn / bn : rn;
@@ -288,7 +288,7 @@ template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_cg_begin(Launch ln, const double* __restrict__ res,
                                                   S* __restrict__ r, S* __restrict__ z,
                                                   BJ<S> dinv, SolveCfg cfg,
-                                                  Ctl* ctl, double* partials, int pstride) {
+                                                  Ctl* ctl, Red red) {
   if (ctl->outer_done) return;
   count_work(ctl, KC_CG_BEGIN);
   const double inv = 1.0 / ctl->scale;
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(TPB) void k_cg_begin(Launch ln, const double* __res
     acc[1] += (double)prr;
   }
   __shared__ double tot[2];
-  if (!reduce_to_last<2>(acc, 2, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (!reduce_to_last<2>(acc, 2, red, L, ln.G, tot)) return;
   if (threadIdx.x == 0) {
     const double rr = tot[1];
     const double rz = BS > 0 ? tot[0] : rr;
@@ -346,8 +346,7 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(Launch ln, Geo geo, Coef<C> M, C
                                                 const S* __restrict__ mval, C msig,
                                                 const S* __restrict__ z,
                                                 const S* __restrict__ pold, S* __restrict__ pnew,
-                                                S* __restrict__ q, Ctl* ctl, double* partials,
-                                                int pstride) {
+                                                S* __restrict__ q, Ctl* ctl, Red red) {
   if (ctl->outer_done | ctl->inner_done) return;
   count_work(ctl, KC_CG_DIR);
   const int first = ctl->iters == 0;
@@ -370,7 +369,7 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(Launch ln, Geo geo, Coef<C> M, C
     acc[0] += (double)s;
   }
   __shared__ double tot[1];
-  if (!reduce_to_last<1>(acc, 1, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (!reduce_to_last<1>(acc, 1, red, L, ln.G, tot)) return;
   if (threadIdx.x == 0) {
     const double pq = tot[0];
     ctl->pq = pq;
@@ -389,7 +388,7 @@ __global__ __launch_bounds__(TPB) void k_cg_upd(Launch ln, S* __restrict__ x,
                                                 const S* __restrict__ p, S* __restrict__ r,
                                                 const S* __restrict__ q, S* __restrict__ z,
                                                 BJ<S> dinv, SolveCfg cfg,
-                                                Ctl* ctl, double* partials, int pstride) {
+                                                Ctl* ctl, Red red) {
   if (ctl->outer_done | ctl->inner_done) return;
   count_work(ctl, KC_CG_UPD);
   const int first = ctl->iters == 0;
@@ -436,7 +435,7 @@ __global__ __launch_bounds__(TPB) void k_cg_upd(Launch ln, S* __restrict__ x,
     acc[1] += (double)prr;
   }
   __shared__ double tot[2];
-  if (!reduce_to_last<2>(acc, 2, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (!reduce_to_last<2>(acc, 2, red, L, ln.G, tot)) return;
   if (threadIdx.x == 0) {
     const double rr = tot[1];
     const double rz = BS > 0 ? tot[0] : rr;
@@ -493,7 +492,7 @@ template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __restrict__ res,
                                                   S* __restrict__ v0, S* __restrict__ zt,
                                                   BJ<S> dinv, SolveCfg cfg,
-                                                  Ctl* ctl, double* partials, int pstride) {
+                                                  Ctl* ctl, Red red) {
   if (ctl->outer_done) return;
   count_work(ctl, KC_GM_BEGIN);
   const double inv = 1.0 / ctl->scale;
@@ -524,7 +523,7 @@ __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __res
     acc[0] += (double)s;
   }
   __shared__ double tot[1];
-  if (!reduce_to_last<1>(acc, 1, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (!reduce_to_last<1>(acc, 1, red, L, ln.G, tot)) return;
   if (threadIdx.x == 0) {
     const double beta = sqrt(tot[0] * cfg.invN);
     ctl->vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
@@ -558,7 +557,7 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
                                                    const S* __restrict__ mval, C msig,
                                                    const S* __restrict__ z, S* __restrict__ V,
                                                    size_t vstride, SolveCfg cfg, Ctl* ctl,
-                                                   double* partials, int pstride) {
+                                                   Red red) {
   if (ctl->outer_done | ctl->inner_done) return;
   const int j = ctl->J;
   const int nd = j + 1;
@@ -622,7 +621,7 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
 #pragma unroll
   for (int i = 0; i < NDM; ++i) acc[i] = (double)dacc[i];
   __shared__ double tot[NDM];
-  if (!reduce_to_last<NDM>(acc, nd, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (!reduce_to_last<NDM>(acc, nd, red, L, ln.G, tot)) return;
   if (threadIdx.x < nd) ctl->hcol[threadIdx.x] = ctl->vscale[threadIdx.x] * tot[threadIdx.x] * cfg.invN;
 }
 
@@ -633,8 +632,7 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
 template <typename S, typename C, int VEC, int BS, int NDM>
 __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, size_t vstride,
                                                  S* __restrict__ zt, BJ<S> dinv,
-                                                 SolveCfg cfg, Ctl* ctl, double* partials,
-                                                 int pstride) {
+                                                 SolveCfg cfg, Ctl* ctl, Red red) {
   if (ctl->outer_done | ctl->inner_done) return;
   const int j = ctl->J;
   const int nd = j + 1;
@@ -701,7 +699,7 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
     acc[0] += (double)s;
   }
   __shared__ double tot[1];
-  if (!reduce_to_last<1>(acc, 1, partials, pstride, &ctl->ticket, L, ln.G, tot)) return;
+  if (!reduce_to_last<1>(acc, 1, red, L, ln.G, tot)) return;
   if (threadIdx.x == 0) {
     const double hn = sqrt(tot[0] * cfg.invN);
     double* col = ctl->H + j * (MAXM + 1);

@@ -59,13 +59,6 @@ Launch make_launch_nit(long ng, int nit) {
   return Launch{(int)ng, nit, (int)G};
 }
 
-// Launch of a kernel with a last-block reduction: at most `max_blocks` blocks (the last block
-// reads every block's partials).
-Launch make_launch_red(long ng, int max_blocks) {
-  long nit = (ng + (long)TPB * max_blocks - 1) / ((long)TPB * max_blocks);
-  return make_launch_nit(ng, (int)std::max(1L, nit));
-}
-
 Launch make_launch(long ng) {
   const long target_blocks = 2048;  // 8 resident 256-thread blocks on each of 256 CUs
   long nit = (ng + (long)TPB * target_blocks - 1) / ((long)TPB * target_blocks);
@@ -471,13 +464,15 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   // launches
   ln_vec = make_launch(N / vec);
   ln_row = make_launch(N);
-  ln_vec_red = make_launch_red(N / vec, RED_MAX_BLOCKS);
-  ln_row_red = make_launch_red(N, RED_MAX_BLOCKS);
+  // kernels with a grid reduction: one group per thread by default (the two-level reduction
+  // keeps its cost independent of the number of blocks)
+  ln_vec_red = make_launch_nit(N / vec, 1);
+  ln_row_red = make_launch_nit(N, 1);
   ln_lp = make_launch(N / vec_lp);
-  ln_lp_red = make_launch_red(N / vec_lp, RED_MAX_BLOCKS);
-  // partials cover every reducing launch shape the autotuner may pick
-  pstride = std::max(make_launch_red(N / vec, 2 * RED_MAX_BLOCKS).G,
-                     make_launch_red(N, 2 * RED_MAX_BLOCKS).G);
+  ln_lp_red = make_launch_nit(N / vec_lp, 1);
+  // partials cover every reducing launch shape the autotuner may pick (nit >= 1)
+  pstride = std::max({ln_vec_red.G, ln_row_red.G, ln_lp_red.G});
+  pstride2 = (pstride + RGRP - 1) / RGRP;
   bs = p.precond == MPRK_PRECOND_BJ ? p.block : 0;
   nblk = bs ? (N + bs - 1) / bs : 0;
   // CSR size (assembled at bind)
@@ -545,6 +540,8 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   o_ctl = take(sizeof(Ctl));
   o_flag = take(256);
   o_part = take((size_t)MAXD * pstride * 8);
+  o_part2 = take((size_t)MAXD * pstride2 * 8);
+  o_tick = take(red_ticks(pstride) * 4);
   ws_bytes = off;
   // per-sigma solve configurations
   cfgs.clear();
@@ -613,8 +610,7 @@ EngineCtx mprk_handle::ctx() const {
   c.mval = ws + o_mval;
   c.kscale = kscale;
   c.ctl = (Ctl*)(ws + o_ctl);
-  c.partials = (double*)(ws + o_part);
-  c.pstride = pstride;
+  c.red = red();
   c.r = ws + o_r;
   c.z = ws + o_z;
   c.p0 = ws + o_p0;
@@ -640,6 +636,7 @@ extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev,
   h->bound = false;
   HIPCHK(hipMemsetAsync(h->ws + h->o_ctl, 0, sizeof(Ctl), h->stream));
   HIPCHK(hipMemsetAsync(h->ws + h->o_flag, 0, 256, h->stream));
+  HIPCHK(hipMemsetAsync(h->ws + h->o_tick, 0, red_ticks(h->pstride) * 4, h->stream));
   EngineCtx c = h->ctx();
   if (h->op.format == MPRK_FMT_CSR) {
     std::vector<int> rp, cl;
@@ -735,6 +732,11 @@ int mprk_handle::update_hist(int slot) {
 // the stage solve (outer FP64 residual loop around the LP Krylov solve)
 // ------------------------------------------------------------------------------------------
 
+Red mprk_handle::red() const {
+  return Red{(double*)(ws + o_part), (double*)(ws + o_part2), (unsigned int*)(ws + o_tick), pstride,
+             pstride2};
+}
+
 BJDesc mprk_handle::bj_desc(int si) const {
   if (!bs || si < 0 || si >= (int)bjsets.size()) return BJDesc{nullptr, nullptr, 0};
   const BJSet& B = bjsets[si];
@@ -744,19 +746,19 @@ BJDesc mprk_handle::bj_desc(int si) const {
 int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* kout) {
   const SolveCfg& cfg = cfgs[si];
   Ctl* ctl = (Ctl*)(ws + o_ctl);
-  double* part = (double*)(ws + o_part);
+  const Red rd = red();
   double* res = (double*)(ws + o_res);
   const Csr csr{(const int*)(ws + o_rowptr), (const int*)(ws + o_col)};
   const double* kval = (const double*)(ws + o_kval);
   if (op.format == MPRK_FMT_CSR)
     PLAUNCH(KC_RESIDUAL, (k_residual<1, 1>), dim3(ln_row_red.G), dim3(TPB), 0, stream, ln_row_red, geo, Kc, csr,
-                       kval, y, rhs, kout, res, cfg, ctl, part, pstride);
+                       kval, y, rhs, kout, res, cfg, ctl, rd);
   else if (vec == 4)
     PLAUNCH(KC_RESIDUAL, (k_residual<4, 0>), dim3(ln_vec_red.G), dim3(TPB), 0, stream, ln_vec_red, geo, Kc, csr,
-                       kval, y, rhs, kout, res, cfg, ctl, part, pstride);
+                       kval, y, rhs, kout, res, cfg, ctl, rd);
   else
     PLAUNCH(KC_RESIDUAL, (k_residual<1, 0>), dim3(ln_vec_red.G), dim3(TPB), 0, stream, ln_vec_red, geo, Kc, csr,
-                       kval, y, rhs, kout, res, cfg, ctl, part, pstride);
+                       kval, y, rhs, kout, res, cfg, ctl, rd);
   HIPCHK(hipGetLastError());
   return MPRK_OK;
 }
@@ -1214,14 +1216,14 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
     }
   }
   // kernels with a grid reduction: time the real Krylov iteration (4 iterations after a
-  // residual + begin on a patterned state) for 4096 / 2048 / 1024 / 512 blocks
+  // residual + begin on a patterned state) for 1, 2, 4 or 8 groups per thread
   float br = 1e30f;
-  for (int blocks : {2 * RED_MAX_BLOCKS, RED_MAX_BLOCKS, RED_MAX_BLOCKS / 2, RED_MAX_BLOCKS / 4}) {
+  for (int nit : {1, 2, 4, 8}) {
     if (rc || h->cfgs.empty()) break;
     const Launch sv = h->ln_vec_red, sr = h->ln_row_red, sl = h->ln_lp_red;
-    h->ln_vec_red = make_launch_red(ngv, blocks);
-    h->ln_row_red = make_launch_red(ngr, blocks);
-    h->ln_lp_red = make_launch_red(ngl, blocks);
+    h->ln_vec_red = make_launch_nit(ngv, nit);
+    h->ln_row_red = make_launch_nit(ngr, nit);
+    h->ln_lp_red = make_launch_nit(ngl, nit);
     if (h->ln_vec_red.G > h->pstride || h->ln_row_red.G > h->pstride || h->ln_lp_red.G > h->pstride) {
       h->ln_vec_red = sv;
       h->ln_row_red = sr;

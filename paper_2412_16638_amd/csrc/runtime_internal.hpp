@@ -15,8 +15,6 @@ namespace mprk {
 int set_error(int code, const std::string& msg);
 Launch make_launch(long ng);
 Launch make_launch_nit(long ng, int nit);
-Launch make_launch_red(long ng, int max_blocks);
-constexpr int RED_MAX_BLOCKS = 2048;  // grid size cap of kernels with a last-block reduction
 Coef<double> operator_coef(const mprk_grid& g, const mprk_operator& op);
 Coef<double> stage_coef(const Coef<double>& K, double sigma);
 long csr_count(const Geo& geo, const Coef<double>& K, double* maxabs);
@@ -52,7 +50,8 @@ struct mprk_handle {
   mprk::Launch ln_vec{}, ln_row{};          // streaming kernels
   mprk::Launch ln_vec_red{}, ln_row_red{};  // kernels with a grid reduction
   mprk::Launch ln_lp{}, ln_lp_red{};        // LP kernels (groups of vec_lp)
-  int pstride = 8;
+  int pstride = 8;   // level-1 partials per reduced value (max blocks of a reducing launch)
+  int pstride2 = 1;  // level-2 partials per reduced value
   int bs = 0;
   int nblk = 0;
   long nnz = 0;
@@ -73,7 +72,7 @@ struct mprk_handle {
   };
   std::vector<BJSet> bjsets;
   size_t o_rowptr = 0, o_col = 0, o_kval = 0, o_mval = 0;
-  size_t o_ctl = 0, o_flag = 0, o_part = 0;
+  size_t o_ctl = 0, o_flag = 0, o_part = 0, o_part2 = 0, o_tick = 0;
   size_t ws_bytes = 0;
   // binding
   double* u = nullptr;
@@ -122,6 +121,7 @@ struct mprk_handle {
   int stage_record(int slot);
   int update_hist(int slot);
   mprk::BJDesc bj_desc(int si) const;
+  mprk::Red red() const;
   int launch_residual(int si, const double* rhs, double* y, double* kout);
   int launch_apply64(const double* x, double* y, double sigma, int mode);
   int run_solve(int si, int slot, const double* rhs, double* y, double* kout);

@@ -57,10 +57,22 @@ def short_name(name: str) -> str:
 
 
 def stats_summary(stats_csv: str, command: str, top: int = 14) -> str:
+    """Per kernel (template variants of one kernel summed), then per variant."""
     rows = list(csv.DictReader(open(stats_csv)))
     total = sum(float(r['TotalDurationNs']) for r in rows)
+    agg = {}
+    for r in rows:
+        k = short_name(r['Name'])
+        a = agg.setdefault(k, [0, 0.0])
+        a[0] += int(r['Calls'])
+        a[1] += float(r['TotalDurationNs'])
     lines = ['# rocprofv3 kernel statistics', '', f'command: {command}', '',
-             f'{"kernel":<24} {"calls":>6} {"avg_us":>10} {"total_ms":>10} {"share":>7}  template']
+             '## per kernel (all template variants)', '',
+             f'{"kernel":<24} {"calls":>6} {"avg_us":>10} {"total_ms":>10} {"share":>7}']
+    for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+        lines.append(f'{k:<24} {n:>6} {t / n / 1e3:>10.2f} {t / 1e6:>10.3f} {t / total:>7.2%}')
+    lines += ['', '## per template variant', '',
+              f'{"kernel":<24} {"calls":>6} {"avg_us":>10} {"total_ms":>10} {"share":>7}  template']
     for r in rows[:top]:
         nm = r['Name']
         lines.append(f'{short_name(nm):<24} {int(r["Calls"]):>6} '
