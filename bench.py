@@ -358,7 +358,14 @@ def bench_serve(args):
     be = serve.GpuBackend(steps_per_call=10, u0_fn=W.initial_field)
     srv = serve.Server(be, max_active=8)
     log(f'serve: {len(reqs)} requests over {reqs[-1].arrival:.1f} s, budget {srv.budget / 2**30:.1f} GiB')
-    out = srv.run(reqs, log=None)
+    seen = [0]
+
+    def progress(msg):  # one line per 64 admissions
+        seen[0] += 1
+        if seen[0] % 64 == 0:
+            log(f'serve progress: {seen[0]} admitted; {msg}')
+
+    out = srv.run(reqs, log=progress)
     offered = sum(r.problem.N * r.problem.nsteps for r in reqs) / reqs[-1].arrival
     res = {'metric': METRIC, 'value': out['dof_steps_per_s'], 'unit': 'DOF-steps/s', 'n_gpus': 1,
            'steps': None, 'warmup': 0, 'ms_per_step': None, 'higher_is_better': True,
