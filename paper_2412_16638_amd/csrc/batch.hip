@@ -62,25 +62,53 @@ struct BArgs {
   int maxit, max_passes, paper_mode, bs;
 };
 
-// Barrier over the nwg workgroups of one problem.  Every thread fences before the workgroup
-// barrier (its own global stores must reach the device-coherent level: the workgroup barrier
-// alone does not wait for other waves' stores, and the group's workgroups may sit on other XCDs
-// with their own L2) and again after it (acquire before reading halo data written by others).
+// Data one workgroup writes and another reads inside a stage launch (the stencil inputs y, p
+// and z, and the reduction partials) are written with device-scope stores, which are coherent
+// across the XCDs once complete.  A barrier therefore needs no L2 writeback: every wave waits
+// for its own stores to complete before its workgroup arrives, and after the barrier every wave
+// invalidates its non-coherent cached lines (agent-scope acquire) before reading other
+// workgroups' rows.  Data a thread writes and only the same thread reads back (its own rows of
+// r, x, q, res, rhs, k) stay plain stores.
+template <typename T>
+__device__ __forceinline__ void store_shared(T* p, T v) {
+  if constexpr (sizeof(T) == 2) {
+    unsigned short b;
+    __builtin_memcpy(&b, &v, 2);
+    __hip_atomic_store(reinterpret_cast<unsigned short*>(p), b, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ void wait_own_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ unsigned int load_u32_dev(const unsigned int* p) {
+  return __hip_atomic_load(const_cast<unsigned int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier over the nwg workgroups of one problem (generation counter; bounded spin).
 __device__ bool group_barrier(BCtl* c, int nwg) {
-  if (nwg > 1) __threadfence();
+  if (nwg > 1) wait_own_stores();
   __syncthreads();
   if (nwg > 1) {
     if (threadIdx.x == 0) {
-      // acquire: the generation must be read before this workgroup's arrival is counted
-      const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL,
+      // the generation is read (and the read completed) before this arrival is counted
+      const unsigned gen = load_u32_dev(&c->bar_gen);
+      wait_own_stores();
+      const unsigned arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
       if (arrived == (unsigned)nwg - 1u) {
         __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        wait_own_stores();  // the reset is visible before the next generation opens
+        __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         long spins = 0;
-        while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        while (load_u32_dev(&c->bar_gen) == gen) {
           __builtin_amdgcn_s_sleep(2);
           if (++spins > BAR_SPIN_LIMIT) {
             __hip_atomic_store(&c->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -90,7 +118,7 @@ __device__ bool group_barrier(BCtl* c, int nwg) {
       }
     }
     __syncthreads();
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   return true;
 }
@@ -167,7 +195,8 @@ __global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
   S* x = (S*)P.x;
   const Coef<C> M = coef_cast<C>(coef_stage(P.K, sigma));
 
-  if (stage == 0 && wl == 0 && threadIdx.x == 0) ctl->step_nonfinite = 0;
+  if (stage == 0 && wl == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&ctl->step_nonfinite, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // ---- A1: rhs = u + dt sum_{j<stage} a_ij k_j ; y = rhs ----
   for (int it = 0; it < nit; ++it) {
     const int row = r0 + it * TPB + threadIdx.x;
@@ -175,7 +204,7 @@ __global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
     double acc = P.u[row];
     for (int j = 0; j < stage; ++j) acc += P.dt * a.A[stage][j] * P.k[(size_t)j * N + row];
     P.rhs[row] = acc;
-    P.y[row] = acc;
+    store_shared(P.y + row, acc);
   }
   group_barrier(ctl, P.nwg);
 
@@ -224,8 +253,12 @@ __global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
         zv[0] = rv[0];
       }
       if (valid) {
-        r[row] = (S)rv[0];
-        if constexpr (BS > 0) z[row] = (S)zv[0];
+        if constexpr (BS > 0) {
+          r[row] = (S)rv[0];
+          store_shared(z + row, (S)zv[0]);
+        } else {
+          store_shared(r + row, (S)rv[0]);  // z aliases r
+        }
         acc2[0] += (double)(rv[0] * zv[0]);
         acc2[1] += (double)(rv[0] * rv[0]);
       }
@@ -248,7 +281,7 @@ __global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
         C pc[1], w[1];
         stencil_group<C, 1>(P.geo, M, row, f, pc, w);
         w[0] = rnd<S, C>(w[0]);
-        pnew[row] = (S)pc[0];
+        store_shared(pnew + row, (S)pc[0]);
         q[row] = (S)w[0];
         acc3[0] += (double)(pc[0] * w[0]);
       }
@@ -267,14 +300,15 @@ __global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
           const C xv = its == 0 ? alpha * pv : (C)x[row] + alpha * pv;
           x[row] = (S)xv;
           rv[0] = rnd<S, C>((C)r[row] - alpha * (C)q[row]);
-          r[row] = (S)rv[0];
+          if constexpr (BS > 0) r[row] = (S)rv[0];
+          else store_shared(r + row, (S)rv[0]);  // z aliases r
         } else {
           rv[0] = C(0);
         }
         if constexpr (BS > 0) {
           bj_apply_lane<C, S, 1, BS>(dinv, row, valid, rv, zv);
           zv[0] = rnd<S, C>(zv[0]);
-          if (valid) z[row] = (S)zv[0];
+          if (valid) store_shared(z + row, (S)zv[0]);
         } else {
           zv[0] = rv[0];
         }
@@ -296,7 +330,7 @@ __global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
       for (int it = 0; it < nit; ++it) {
         const int row = r0 + it * TPB + threadIdx.x;
         if (row >= r1) break;
-        P.y[row] += scale * (double)(C)x[row];
+        store_shared(P.y + row, P.y[row] + scale * (double)(C)x[row]);
       }
     }
     ++passes;
@@ -310,7 +344,7 @@ __global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
     ctl->nonfinite[stage] = nonfinite;
     ctl->life_iters += total_iters;
     ctl->life_passes += passes;
-    if (nonfinite) ctl->step_nonfinite = 1;
+    if (nonfinite) __hip_atomic_store(&ctl->step_nonfinite, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (stage == a.s - 1) {
     // ---- step combination u += dt sum_i b_i k_i (skipped after a non-finite residual) ----
