@@ -327,14 +327,25 @@ def bench_batch(args):
             worst = max(worst, float(d))
         log(f'worst floored rel-L2 vs oracle over the batch: {worst:.3e}')
     K, Wm = args.steps, args.warmup
+
+    def timed():
+        for i, p in enumerate(probs):
+            b.set_u(i, p.u0)
+        b.step(Wm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(K)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    t_plan = timed()
+    log(f'planned schedule (2 rows per thread, work model e = 0.5): {dof * K / t_plan:.4e} DOF-steps/s')
     for i, p in enumerate(probs):
         b.set_u(i, p.u0)
-    b.step(Wm)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(K)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
+    expo, ru = b.autotune()
+    log(f'autotuned: {ru} rows per thread per CG sweep, work-model exponent {expo}; workgroups '
+        f'per problem {min(b.schedule)}..{max(b.schedule)}, total {sum(b.schedule)}')
+    t = timed()
     st = [b.stats(i) for i in range(len(probs))]
     b.close()
     out = {'metric': METRIC, 'value': dof * K / t, 'unit': 'DOF-steps/s', 'n_gpus': 1, 'steps': K,
@@ -344,6 +355,10 @@ def bench_batch(args):
                       'problems': len(probs), 'N_total': dof,
                       'launch': 'one persistent kernel per stage, hipGraph per step'},
            'first_integration_s': t_full,
+           'planned_schedule_value': dof * K / t_plan,
+           'autotuned_work_exponent': expo,
+           'autotuned_rows_per_thread': ru,
+           'workgroups': sum(b.schedule),
            'worst_err_vs_oracle': worst if not args.no_cpu else None,
            'iters_per_stage_max': max(max(s['iters']) for s in st)}
     print(json.dumps(out), flush=True)

@@ -246,6 +246,14 @@ int32_t mprk_batch_create(int32_t count, const mprk_problem *problems, const mpr
  * binding; NULL restores the plan) fixes them; get_schedule returns the plan in use. */
 int32_t mprk_batch_set_schedule(mprk_batch *b, const int32_t *wg_per_problem);
 int32_t mprk_batch_get_schedule(mprk_batch *b, int32_t *wg_per_problem);
+/* Autotune a bound batch by replaying one step from the current states per candidate: first
+ * the rows a thread handles together in the CG phases (1, 2 or 4: loads in flight vs
+ * registers, hence co-resident workgroups), then the planned schedule's work model, unknowns x
+ * (condition-number estimate)^e for e in {0, 1/4, 1/2, 3/4, 1}.  The fastest choice is kept and
+ * written to *exponent_out / *rows_out (either may be NULL).  States and statistics are
+ * restored; the call synchronises the stream.  MPRK_ESTATE if unbound or if set_schedule fixed
+ * the schedule. */
+int32_t mprk_batch_autotune(mprk_batch *b, double *exponent_out, int32_t *rows_out);
 int64_t mprk_batch_workspace_bytes(const mprk_batch *b);
 /* u_dev: array of `count` device pointers (problem p's state, N_p doubles each). */
 int32_t mprk_batch_bind(mprk_batch *b, double *const *u_dev, void *workspace_dev, int64_t bytes);

@@ -119,6 +119,7 @@ _sig = {
                                       C.POINTER(mprk_precisions), _P, C.POINTER(_P)]),
     'mprk_batch_set_schedule': (C.c_int32, [_P, C.POINTER(C.c_int32)]),
     'mprk_batch_get_schedule': (C.c_int32, [_P, C.POINTER(C.c_int32)]),
+    'mprk_batch_autotune': (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     'mprk_batch_workspace_bytes': (C.c_int64, [_P]),
     'mprk_batch_bind': (C.c_int32, [_P, C.POINTER(_P), _P, C.c_int64]),
     'mprk_batch_step': (C.c_int32, [_P, C.c_int32]),
@@ -258,6 +259,13 @@ def mprk_batch_get_schedule(b: int, count: int):
     arr = (C.c_int32 * count)()
     check(lib.mprk_batch_get_schedule(_P(b), arr), 'mprk_batch_get_schedule')
     return list(arr)
+
+
+def mprk_batch_autotune(b: int):
+    e = C.c_double(0.0)
+    ru = C.c_int32(0)
+    check(lib.mprk_batch_autotune(_P(b), C.byref(e), C.byref(ru)), 'mprk_batch_autotune')
+    return e.value, ru.value
 
 
 def mprk_batch_workspace_bytes(b: int) -> int:

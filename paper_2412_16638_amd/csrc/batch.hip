@@ -174,7 +174,21 @@ __device__ __forceinline__ double k64_row(const Geo& geo, const Coef<double>& K,
   return o[0];
 }
 
-template <typename S, typename C, int BS>
+// Rows it0 .. it0+RU-1 of this thread in [r0, r1) (nit rows per thread); a row past the end is
+// replaced by r0 (a valid row) and flagged invalid.  RU rows are handled together by a thread
+// in the CG phases, their loads issued together (RU = 1, 2 or 4, picked by the autotuner).
+template <int RU>
+__device__ __forceinline__ void rows_of(int r0, int r1, int nit, int it0, int (&row)[RU],
+                                        bool (&val)[RU]) {
+#pragma unroll
+  for (int k = 0; k < RU; ++k) {
+    const int rr = r0 + (it0 + k) * TPB + (int)threadIdx.x;
+    val[k] = it0 + k < nit && rr < r1;
+    row[k] = val[k] ? rr : r0;
+  }
+}
+
+template <typename S, typename C, int BS, int RU>
 __global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
   const int pid = a.wg2prob[blockIdx.x];
   const BProb P = a.probs[pid];
@@ -275,15 +289,22 @@ __global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
       S* pnew = (its & 1) ? (S*)P.p0 : (S*)P.p1;
       InAxpy<C, S, 1> f{z, pold, (C)beta, its > 0};
       double acc3[BND] = {0.0, 0.0, 0.0, 0.0};
-      for (int it = 0; it < nit; ++it) {
-        const int row = r0 + it * TPB + threadIdx.x;
-        if (row >= r1) break;
-        C pc[1], w[1];
-        stencil_group<C, 1>(P.geo, M, row, f, pc, w);
-        w[0] = rnd<S, C>(w[0]);
-        store_shared(pnew + row, (S)pc[0]);
-        q[row] = (S)w[0];
-        acc3[0] += (double)(pc[0] * w[0]);
+      for (int it0 = 0; it0 < nit; it0 += RU) {
+        int row[RU];
+        bool val[RU];
+        rows_of<RU>(r0, r1, nit, it0, row, val);
+        C pc[RU][1], w[RU][1];
+#pragma unroll
+        for (int k = 0; k < RU; ++k) stencil_group<C, 1>(P.geo, M, row[k], f, pc[k], w[k]);
+#pragma unroll
+        for (int k = 0; k < RU; ++k) {
+          if (val[k]) {
+            w[k][0] = rnd<S, C>(w[k][0]);
+            store_shared(pnew + row[k], (S)pc[k][0]);
+            q[row[k]] = (S)w[k][0];
+            acc3[0] += (double)(pc[k][0] * w[k][0]);
+          }
+        }
       }
       group_reduce<BND>(acc3, 1, P, wl, parity, t);
       const double pq = t[0];
@@ -291,30 +312,42 @@ __global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
       const C alpha = (C)(rz / pq);
       // ---- C2: x += alpha p ; r -= alpha q ; z = BJ(r) ; (r, z), (r, r) ----
       double acc4[BND] = {0.0, 0.0, 0.0, 0.0};
-      for (int it = 0; it < nit; ++it) {
-        const int row = r0 + it * TPB + threadIdx.x;
-        const bool valid = row < r1;
-        C rv[1], zv[1];
-        if (valid) {
-          const C pv = (C)pnew[row];
-          const C xv = its == 0 ? alpha * pv : (C)x[row] + alpha * pv;
-          x[row] = (S)xv;
-          rv[0] = rnd<S, C>((C)r[row] - alpha * (C)q[row]);
-          if constexpr (BS > 0) r[row] = (S)rv[0];
-          else store_shared(r + row, (S)rv[0]);  // z aliases r
-        } else {
-          rv[0] = C(0);
+      for (int it0 = 0; it0 < nit; it0 += RU) {
+        int row[RU];
+        bool val[RU];
+        rows_of<RU>(r0, r1, nit, it0, row, val);
+        // every load of the RU rows first (x is read but unused in the first iteration)
+        C pv[RU], xo[RU], ro[RU], qo[RU];
+        BJRows<S, 1, BS == 0 ? 1 : BS> R[RU];
+#pragma unroll
+        for (int k = 0; k < RU; ++k) {
+          pv[k] = (C)pnew[row[k]];
+          xo[k] = (C)x[row[k]];
+          ro[k] = (C)r[row[k]];
+          qo[k] = (C)q[row[k]];
+          if constexpr (BS > 0) bj_load<S, 1, BS>(dinv, row[k], val[k], R[k]);
         }
-        if constexpr (BS > 0) {
-          bj_apply_lane<C, S, 1, BS>(dinv, row, valid, rv, zv);
-          zv[0] = rnd<S, C>(zv[0]);
-          if (valid) store_shared(z + row, (S)zv[0]);
-        } else {
-          zv[0] = rv[0];
-        }
-        if (valid) {
-          acc4[0] += (double)(rv[0] * zv[0]);
-          acc4[1] += (double)(rv[0] * rv[0]);
+#pragma unroll
+        for (int k = 0; k < RU; ++k) {
+          C rv[1], zv[1];
+          const C xv = its == 0 ? alpha * pv[k] : xo[k] + alpha * pv[k];
+          rv[0] = val[k] ? rnd<S, C>(ro[k] - alpha * qo[k]) : C(0);
+          if (val[k]) {
+            x[row[k]] = (S)xv;
+            if constexpr (BS > 0) r[row[k]] = (S)rv[0];
+            else store_shared(r + row[k], (S)rv[0]);  // z aliases r
+          }
+          if constexpr (BS > 0) {
+            bj_mul<C, S, 1, BS>(R[k], val[k], rv, zv);
+            zv[0] = rnd<S, C>(zv[0]);
+            if (val[k]) store_shared(z + row[k], (S)zv[0]);
+          } else {
+            zv[0] = rv[0];
+          }
+          if (val[k]) {
+            acc4[0] += (double)(rv[0] * zv[0]);
+            acc4[1] += (double)(rv[0] * rv[0]);
+          }
         }
       }
       group_reduce<BND>(acc4, 2, P, wl, parity, t);
@@ -393,6 +426,10 @@ struct mprk_batch {
   long long good_base = 0;
   std::vector<long long> good_seen, bad_seen;
   std::vector<int> fixed_wg;  // caller-chosen workgroups per problem (empty: planned)
+  double weight_exp = 0.5;    // exponent of the condition-number estimate in the work model
+  int ru = 2;                 // rows a thread handles together in the CG phases (1, 2, 4)
+  int capacity = 0;           // co-resident workgroups of the device for the kernel in use
+  int max_capacity = 0;       // largest capacity over the kernel variants (sizes the map)
   ~mprk_batch() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -403,26 +440,34 @@ namespace mprk {
 Coef<double> operator_coef(const mprk_grid& g, const mprk_operator& op);
 }
 
-template <typename S, typename C>
+template <typename S, typename C, int RU>
 static const void* kb_kernel_ptr(int bs) {
   switch (bs) {
-    case 0: return (const void*)kb_stage<S, C, 0>;
-    case 1: return (const void*)kb_stage<S, C, 1>;
-    case 2: return (const void*)kb_stage<S, C, 2>;
-    case 4: return (const void*)kb_stage<S, C, 4>;
-    default: return (const void*)kb_stage<S, C, 8>;
+    case 0: return (const void*)kb_stage<S, C, 0, RU>;
+    case 1: return (const void*)kb_stage<S, C, 1, RU>;
+    case 2: return (const void*)kb_stage<S, C, 2, RU>;
+    case 4: return (const void*)kb_stage<S, C, 4, RU>;
+    default: return (const void*)kb_stage<S, C, 8, RU>;
   }
 }
 
-static const void* batch_kernel(int storage, int bs) {
-  if (storage == MPRK_FP64) return kb_kernel_ptr<double, double>(bs);
-  if (storage == MPRK_FP32) return kb_kernel_ptr<float, float>(bs);
-  return kb_kernel_ptr<half_t, float>(bs);
+template <typename S, typename C>
+static const void* kb_kernel_ru(int bs, int ru) {
+  if (ru == 4) return kb_kernel_ptr<S, C, 4>(bs);
+  if (ru == 2) return kb_kernel_ptr<S, C, 2>(bs);
+  return kb_kernel_ptr<S, C, 1>(bs);
+}
+
+static const void* batch_kernel(int storage, int bs, int ru) {
+  if (storage == MPRK_FP64) return kb_kernel_ru<double, double>(bs, ru);
+  if (storage == MPRK_FP32) return kb_kernel_ru<float, float>(bs, ru);
+  return kb_kernel_ru<half_t, float>(bs, ru);
 }
 
 // Weight of a problem's stage solve: unknowns x an estimate of CG iterations, which grow
-// like the square root of the stage matrix's condition number 1 + sigma * 4 * diff * sum 1/h^2.
-static double work_weight(const mprk_problem& p, double a) {
+// like a power e of the stage matrix's condition number 1 + sigma * 4 * diff * sum 1/h^2
+// (e = 1/2 for unpreconditioned CG; the autotuner tries others).
+static double work_weight(const mprk_problem& p, double a, double e) {
   const mprk_grid& g = p.grid;
   const double N = (double)g.nx * g.ny * g.nz;
   double s = 0.0;
@@ -431,7 +476,7 @@ static double work_weight(const mprk_problem& p, double a) {
     const double h = g.bc == MPRK_BC_DIRICHLET0 ? 1.0 / (n[d] + 1) : 1.0 / n[d];
     s += 4.0 * p.op.diff / (h * h);
   }
-  return N * std::sqrt(1.0 + p.dt * a * s);
+  return N * std::pow(1.0 + p.dt * a * s, e);
 }
 
 extern "C" int32_t mprk_batch_create(int32_t count, const mprk_problem* problems,
@@ -497,7 +542,7 @@ static int plan_groups(mprk_batch* b, int capacity) {
   std::vector<double> w(b->count);
   double W = 0.0;
   for (int p = 0; p < b->count; ++p) {
-    w[p] = work_weight(b->probs[p], a);
+    w[p] = work_weight(b->probs[p], a, b->weight_exp);
     W += w[p];
   }
   (void)s;
@@ -554,22 +599,24 @@ static int batch_layout(mprk_batch* b) {
     const size_t vlp = (N * b->lp_bytes + 255) & ~(size_t)255;
     b->off_r[p] = take(6 * vlp);              // r, z, p0, p1, q, x
     b->off_dinv[p] = b->bs ? take(((N + b->bs - 1) / b->bs) * (size_t)b->bs * b->bs * b->lp_bytes) : 0;
-    b->off_part[p] = take(2 * BND * (size_t)b->nwg[p] * 8);
+    // partials for the largest group the problem can get (one workgroup per 64 rows), so that
+    // the autotuner may change the schedule after binding
+    b->off_part[p] = take(2 * BND * (size_t)std::max(1, (b->N[p] + 63) / 64) * 8);
   }
   b->o_probs = take(sizeof(BProb) * b->count);
-  b->o_map = take(sizeof(int) * b->G);
+  b->o_map = take(sizeof(int) * (size_t)std::max(b->G, b->max_capacity));
   b->o_ctl = take(sizeof(BCtl) * b->count);
   b->o_flag = take(256);
   b->ws_bytes = off;
   return MPRK_OK;
 }
 
-static int batch_capacity(mprk_batch* b, int* cap) {
+static int batch_capacity(mprk_batch* b, int ru, int* cap) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return set_error(MPRK_EDEVICE, "hipGetDevice failed");
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return set_error(MPRK_EDEVICE, "CU count query failed");
-  const void* k = batch_kernel(b->prec.storage, b->bs);
+  const void* k = batch_kernel(b->prec.storage, b->bs, ru);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, TPB, 0) != hipSuccess)
     return set_error(MPRK_EDEVICE, "occupancy query failed");
   // stay one workgroup per CU below the occupancy bound
@@ -599,9 +646,16 @@ extern "C" int64_t mprk_batch_workspace_bytes(const mprk_batch* cb) {
   if (!cb) return set_error(MPRK_EINVAL, "NULL batch");
   mprk_batch* b = const_cast<mprk_batch*>(cb);
   if (b->ws_bytes == 0) {
-    int cap = 0;
-    int rc = batch_capacity(b, &cap);
+    int cap = 0, mx = 0;
+    for (int ru : {1, 2, 4}) {
+      int rc = batch_capacity(b, ru, &cap);
+      if (rc) return rc;
+      mx = std::max(mx, cap);
+    }
+    b->max_capacity = mx;
+    int rc = batch_capacity(b, b->ru, &cap);
     if (rc) return rc;
+    b->capacity = cap;
     rc = plan_groups(b, cap);
     if (rc) return rc;
     rc = batch_layout(b);
@@ -636,20 +690,11 @@ static BArgs batch_args(mprk_batch* b) {
   return a;
 }
 
-extern "C" int32_t mprk_batch_bind(mprk_batch* b, double* const* u_dev, void* workspace_dev,
-                                   int64_t bytes) {
-  if (!b || !u_dev || !workspace_dev) return set_error(MPRK_EINVAL, "NULL argument");
-  int64_t need = mprk_batch_workspace_bytes(b);
-  if (need < 0) return (int32_t)need;
-  if (bytes < need) return set_error(MPRK_ENOMEM, "workspace smaller than mprk_batch_workspace_bytes");
-  if (((uintptr_t)workspace_dev & 255) != 0) return set_error(MPRK_EINVAL, "workspace must be 256-byte aligned");
-  b->ws = (char*)workspace_dev;
-  b->u.assign(u_dev, u_dev + b->count);
-  for (int p = 0; p < b->count; ++p)
-    if (!b->u[p]) return set_error(MPRK_EINVAL, "NULL state pointer");
+// Device descriptors of every problem for the current schedule.
+static void batch_problems(mprk_batch* b, std::vector<BProb>& hp, std::vector<int>& map) {
   const double a = b->tab.a_hi[0] + b->tab.a_lo[0];
-  std::vector<BProb> hp(b->count);
-  std::vector<int> map(b->G);
+  hp.assign(b->count, BProb{});
+  map.assign(b->G, 0);
   int wg = 0;
   for (int p = 0; p < b->count; ++p) {
     const mprk_problem& q = b->probs[p];
@@ -681,8 +726,55 @@ extern "C" int32_t mprk_batch_bind(mprk_batch* b, double* const* u_dev, void* wo
     for (int i = 0; i < P.nwg; ++i) map[wg + i] = p;
     wg += P.nwg;
   }
+}
+
+// Upload the descriptors of the current schedule and capture one step (s stage launches) as a
+// graph on a private non-blocking stream.
+static int batch_upload_capture(mprk_batch* b, const std::vector<BProb>& hp, const std::vector<int>& map) {
   BHIP(hipMemcpyAsync(b->ws + b->o_probs, hp.data(), sizeof(BProb) * b->count, hipMemcpyHostToDevice, b->stream));
   BHIP(hipMemcpyAsync(b->ws + b->o_map, map.data(), sizeof(int) * b->G, hipMemcpyHostToDevice, b->stream));
+  BHIP(hipStreamSynchronize(b->stream));  // host vectors may go out of scope
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  const BArgs args = batch_args(b);
+  const void* kern = batch_kernel(b->prec.storage, b->bs, b->ru);
+  hipStream_t cs;
+  BHIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int st = 0; st < b->tab.s && e == hipSuccess; ++st) {
+      void* kargs[] = {(void*)&args, (void*)&st};
+      e = hipLaunchKernel(kern, dim3(b->G), dim3(TPB), kargs, 0, cs);
+    }
+    hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return set_error(MPRK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_batch_bind(mprk_batch* b, double* const* u_dev, void* workspace_dev,
+                                   int64_t bytes) {
+  if (!b || !u_dev || !workspace_dev) return set_error(MPRK_EINVAL, "NULL argument");
+  int64_t need = mprk_batch_workspace_bytes(b);
+  if (need < 0) return (int32_t)need;
+  if (bytes < need) return set_error(MPRK_ENOMEM, "workspace smaller than mprk_batch_workspace_bytes");
+  if (((uintptr_t)workspace_dev & 255) != 0) return set_error(MPRK_EINVAL, "workspace must be 256-byte aligned");
+  b->ws = (char*)workspace_dev;
+  b->u.assign(u_dev, u_dev + b->count);
+  for (int p = 0; p < b->count; ++p)
+    if (!b->u[p]) return set_error(MPRK_EINVAL, "NULL state pointer");
+  std::vector<BProb> hp;
+  std::vector<int> map;
+  batch_problems(b, hp, map);
   BHIP(hipMemsetAsync(b->ws + b->o_ctl, 0, sizeof(BCtl) * b->count, b->stream));
   BHIP(hipMemsetAsync(b->ws + b->o_flag, 0, 256, b->stream));
   // block-Jacobi inverses with the single-problem setup kernel
@@ -707,35 +799,110 @@ extern "C" int32_t mprk_batch_bind(mprk_batch* b, double* const* u_dev, void* wo
   }
   BHIP(hipStreamSynchronize(b->stream));
   if (hfail) return set_error(MPRK_EINVAL, "singular block-Jacobi block in batch");
-  // capture one step (s stage launches) as a graph
-  if (b->gexec) {
-    (void)hipGraphExecDestroy(b->gexec);
-    b->gexec = nullptr;
-  }
-  if (b->graph) {
-    (void)hipGraphDestroy(b->graph);
-    b->graph = nullptr;
-  }
-  const BArgs args = batch_args(b);
-  const void* kern = batch_kernel(b->prec.storage, b->bs);
-  hipStream_t cs;
-  BHIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    for (int st = 0; st < b->tab.s && e == hipSuccess; ++st) {
-      void* kargs[] = {(void*)&args, (void*)&st};
-      e = hipLaunchKernel(kern, dim3(b->G), dim3(TPB), kargs, 0, cs);
-    }
-    hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
-    if (e == hipSuccess) e = e2;
-  }
-  if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
-  (void)hipStreamDestroy(cs);
-  if (e != hipSuccess) return set_error(MPRK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  const int rc = batch_upload_capture(b, hp, map);
+  if (rc) return rc;
   b->good_seen.assign(b->count, 0);
   b->bad_seen.assign(b->count, 0);
   b->bound = true;
   return MPRK_OK;
+}
+
+// Autotuner of the CTA-group schedule: for each exponent e of the work model (unknowns x
+// condition-number estimate^e), plan the workgroups per problem, replay one step from the
+// current state (after one untimed replay) and keep the fastest.  The problems' states and
+// statistics are restored afterwards.  A schedule fixed with mprk_batch_set_schedule is kept.
+extern "C" int32_t mprk_batch_autotune(mprk_batch* b, double* exponent_out, int32_t* rows_out) {
+  if (!b) return set_error(MPRK_EINVAL, "NULL batch");
+  if (!b->bound) return set_error(MPRK_ESTATE, "mprk_batch_autotune before mprk_batch_bind");
+  if (!b->fixed_wg.empty()) return set_error(MPRK_ESTATE, "schedule fixed by mprk_batch_set_schedule");
+  // save the states and the per-problem records on the host
+  std::vector<std::vector<double>> saved(b->count);
+  for (int p = 0; p < b->count; ++p) {
+    saved[p].resize(b->N[p]);
+    BHIP(hipMemcpyAsync(saved[p].data(), b->u[p], (size_t)b->N[p] * 8, hipMemcpyDeviceToHost, b->stream));
+  }
+  std::vector<BCtl> ctl(b->count);
+  BHIP(hipMemcpyAsync(ctl.data(), b->ws + b->o_ctl, sizeof(BCtl) * b->count, hipMemcpyDeviceToHost, b->stream));
+  BHIP(hipStreamSynchronize(b->stream));
+  auto restore = [&]() -> int {
+    for (int p = 0; p < b->count; ++p)
+      BHIP(hipMemcpyAsync(b->u[p], saved[p].data(), (size_t)b->N[p] * 8, hipMemcpyHostToDevice, b->stream));
+    BHIP(hipStreamSynchronize(b->stream));
+    return MPRK_OK;
+  };
+  hipEvent_t e0, e1;
+  BHIP(hipEventCreate(&e0));
+  BHIP(hipEventCreate(&e1));
+  // one trial: plan with the current (ru, weight_exp), replay one step twice from the saved
+  // states, return the second replay's time
+  auto trial = [&](float* ms) -> int {
+    int r = batch_capacity(b, b->ru, &b->capacity);
+    if (!r) r = plan_groups(b, b->capacity);
+    std::vector<BProb> hp;
+    std::vector<int> map;
+    if (!r) {
+      batch_problems(b, hp, map);
+      r = batch_upload_capture(b, hp, map);
+    }
+    for (int rep = 0; rep < 2 && !r; ++rep) {
+      r = restore();
+      if (r) break;
+      if (hipEventRecord(e0, b->stream) != hipSuccess || hipGraphLaunch(b->gexec, b->stream) != hipSuccess ||
+          hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        r = set_error(MPRK_EDEVICE, "autotune replay failed");
+    }
+    if (!r && hipEventElapsedTime(ms, e0, e1) != hipSuccess) r = set_error(MPRK_EDEVICE, "autotune timing failed");
+    return r;
+  };
+  int rc = MPRK_OK;
+  // rows per thread per CG iteration (the work model fixed at its default), then the work model
+  int best_ru = b->ru;
+  float best_ms = 1e30f;
+  for (int ru : {1, 2, 4}) {
+    b->ru = ru;
+    float ms = 0.f;
+    rc = trial(&ms);
+    if (rc) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_ru = ru;
+    }
+  }
+  b->ru = best_ru;
+  double best_e = b->weight_exp;
+  const double cands[] = {0.0, 0.25, 0.75, 1.0};
+  for (double e : cands) {
+    if (rc) break;
+    const double keep = b->weight_exp;
+    b->weight_exp = e;
+    float ms = 0.f;
+    rc = trial(&ms);
+    if (rc) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_e = e;
+    }
+    b->weight_exp = keep;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->weight_exp = best_e;
+  int rc2 = batch_capacity(b, b->ru, &b->capacity);
+  if (!rc2) rc2 = plan_groups(b, b->capacity);
+  if (!rc2) {
+    std::vector<BProb> hp;
+    std::vector<int> map;
+    batch_problems(b, hp, map);
+    rc2 = batch_upload_capture(b, hp, map);
+  }
+  if (!rc2) rc2 = restore();
+  if (!rc2) {
+    BHIP(hipMemcpyAsync(b->ws + b->o_ctl, ctl.data(), sizeof(BCtl) * b->count, hipMemcpyHostToDevice, b->stream));
+    BHIP(hipStreamSynchronize(b->stream));
+  }
+  if (exponent_out) *exponent_out = best_e;
+  if (rows_out) *rows_out = b->ru;
+  return rc ? rc : rc2;
 }
 
 extern "C" int32_t mprk_batch_step(mprk_batch* b, int32_t nsteps) {

@@ -173,6 +173,13 @@ class Batch:
     def step(self, nsteps: int = 1) -> None:
         A.check(A.mprk_batch_step(self.h, nsteps), 'mprk_batch_step')
 
+    def autotune(self):
+        """Pick rows per thread and the CTA-group schedule by timing one step per candidate;
+        returns (work-model exponent, rows per thread)."""
+        e, ru = A.mprk_batch_autotune(self.h)
+        self.schedule = A.mprk_batch_get_schedule(self.h, len(self.shapes))
+        return e, ru
+
     def stats(self, i: int) -> dict:
         return A.mprk_batch_stats_sync(self.h, i)
 

@@ -80,3 +80,34 @@ def test_full_batch_64_problems():
         assert s['steps'] == 20
     print('batch64 worst rel-L2', worst)
     assert worst <= 1e-6
+
+
+def test_autotune_restores_state_and_keeps_parity():
+    probs = W.heat_batch(count=6, nmin=13, nmax=40, nsteps=3)
+    log_case('batch_autotune', sizes=[p.n for p in probs])
+    b = M.Batch([{'shape': p.n, 'diff': p.diff, 'dt': p.dt} for p in probs], 'SDIRK3',
+                M.precisions('fp32', 'cg'))
+    for i, p in enumerate(probs):
+        b.set_u(i, p.u0)
+    e, ru = b.autotune()
+    assert e in (0.0, 0.25, 0.5, 0.75, 1.0) and ru in (1, 2, 4)
+    assert sum(b.schedule) >= len(probs) and min(b.schedule) >= 1
+    for i, p in enumerate(probs):  # autotuning leaves the states as they were
+        assert np.array_equal(b.get_u(i), p.u0.reshape(b.get_u(i).shape))
+        assert b.stats(i)['steps'] == 0
+    b.step(3)
+    for i, p in enumerate(probs):
+        p.nsteps = 3
+        assert b.stats(i)['steps'] == 3
+        assert rel_l2_floor(b.get_u(i), reference_solution(p), p.u0) <= 1e-6
+    b.close()
+
+
+def test_autotune_refuses_a_fixed_schedule():
+    probs = W.heat_batch(count=2, nmin=16, nmax=20, nsteps=1)
+    log_case('batch_autotune_fixed')
+    b = M.Batch([{'shape': p.n, 'diff': p.diff, 'dt': p.dt} for p in probs], 'SDIRK3',
+                M.precisions('fp32', 'cg'), schedule=[2, 3])
+    with pytest.raises(A.MprkError):
+        b.autotune()
+    b.close()
