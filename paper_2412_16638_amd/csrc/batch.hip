@@ -123,7 +123,12 @@ __device__ bool group_barrier(BCtl* c, int nwg) {
   return true;
 }
 
-// Group reduction of nd values; every workgroup of the group returns the same totals.
+// Group reduction of nd values; every workgroup of the group returns the same totals.  Each
+// workgroup publishes its partials (device-scope stores), passes the group barrier, then sums
+// all the group's partials itself in workgroup order (every thread a strided slice, fixed
+// shuffle tree and wave order), so all workgroups take identical decisions without a second
+// round trip.  Partials are double-buffered by `parity` (a fast workgroup may publish the next
+// reduction's partials while a slow one still reads these).
 template <int ND>
 __device__ void group_reduce(const double (&v)[ND], int nd, const BProb& P, int wl, int& parity,
                              double (&out)[ND]) {
@@ -138,22 +143,31 @@ __device__ void group_reduce(const double (&v)[ND], int nd, const BProb& P, int 
     }
   }
   __syncthreads();
-  double* part = P.part + (size_t)parity * BND * P.nwg;
+  const int nwg = P.nwg;
+  double* part = P.part + (size_t)parity * BND * nwg;
   if (threadIdx.x < nd) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < NWAVE; ++w) s += wsum[w][threadIdx.x];
-    if (P.nwg > 1)
-      __hip_atomic_store(part + threadIdx.x * P.nwg + wl, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-      tot[threadIdx.x] = s;
+    if (nwg > 1) store_dev(part + (size_t)threadIdx.x * nwg + wl, s);
+    else tot[threadIdx.x] = s;
   }
-  if (P.nwg > 1) {
-    group_barrier(P.ctl, P.nwg);
+  if (nwg > 1) {
+    group_barrier(P.ctl, nwg);
+    __shared__ double wt[NWAVE][BND];
+#pragma unroll 1
+    for (int d = 0; d < nd; ++d) {
+      double s = 0.0;
+#pragma unroll 1
+      for (int w = threadIdx.x; w < nwg; w += TPB) s += load_dev(part + (size_t)d * nwg + w);
+      s = wave_sum(s);
+      if (lane == 0) wt[wave][d] = s;
+    }
+    __syncthreads();
     if (threadIdx.x < nd) {
       double s = 0.0;
-      for (int w = 0; w < P.nwg; ++w)
-        s += __hip_atomic_load(part + threadIdx.x * P.nwg + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int w = 0; w < NWAVE; ++w) s += wt[w][threadIdx.x];
       tot[threadIdx.x] = s;
     }
   }
@@ -188,8 +202,14 @@ __device__ __forceinline__ void rows_of(int r0, int r1, int nit, int it0, int (&
   }
 }
 
+// Minimum waves per SIMD the compiler must allow (register budget) for each row unroll.
+template <typename S, int RU>
+constexpr int kb_min_waves() {
+  return sizeof(S) == 8 ? (RU == 1 ? 4 : RU == 2 ? 3 : 2) : (RU == 1 ? 6 : RU == 2 ? 5 : 3);
+}
+
 template <typename S, typename C, int BS, int RU>
-__global__ __launch_bounds__(TPB) void kb_stage(BArgs a, int stage) {
+__global__ __launch_bounds__(TPB, (kb_min_waves<S, RU>())) void kb_stage(BArgs a, int stage) {
   const int pid = a.wg2prob[blockIdx.x];
   const BProb P = a.probs[pid];
   BCtl* ctl = P.ctl;
