@@ -165,10 +165,32 @@ __device__ __forceinline__ int xcd_block(int G) {
   return (b & 7) * (G >> 3) + (b >> 3);
 }
 
+// One DPP step: v + (v moved by the DPP pattern CTRL; 0 where the pattern has no source or the
+// row is masked off).  A double moves as its two 32-bit halves.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  const long long m = ((long long)hi << 32) | (unsigned int)lo;
+  return v + __builtin_bit_cast(double, m);
+}
+
+// Sum over the 64 lanes of a wave, in a fixed order, returned to every lane: an inclusive scan
+// inside each row of 16 lanes (row_shr 1, 2, 4, 8), then row 0's total added into row 1 and
+// row 2's into row 3 (row_bcast15), then rows 0-1 into rows 2-3 (row_bcast31); lane 63 then
+// holds the total, which is read back as a scalar.  Only DPP moves: no LDS round trips.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
 // Workspace of a grid reduction.  Level 1: one partial per block, p1[d * s1 + L]; level 2: one
