@@ -25,9 +25,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def kernel_source_hash() -> str:
-    """Hash of the device sources; a traffic figure is valid only for the sources it was taken on."""
+    """Hash of the sources that define the solver kernels (device helpers and kernel bodies); a
+    traffic figure is valid only for the sources it was taken on."""
     h = hashlib.sha256()
-    for f in ('device.hpp', 'kernels.hpp', 'engine.hpp'):
+    for f in ('device.hpp', 'kernels.hpp'):
         with open(os.path.join(ROOT, 'paper_2412_16638_amd', 'csrc', f), 'rb') as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
