@@ -1,0 +1,62 @@
+"""Pins of the oracle's fast-diagonalisation preconditioner (eqs. preconbasic, Pinvform,
+TensorDecomp): P equals the stage matrix, P^-1 is the exact inverse, the contractions follow
+their index definitions, and the heat factors have the analytic Dirichlet spectrum."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import fdm, operators
+
+CASES = [
+    ((5, 4, 3), operators.DIRICHLET, 0, 1.3, (0.0, 0.0, 0.0), 2e-3),
+    ((6, 5, 4), operators.PERIODIC, 1, 1e-2, (1.0, 0.5, -0.25), 2e-2),
+    ((4, 6, 5), operators.PERIODIC, 0, 0.7, (0.0, 0.0, 0.0), 1e-2),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_preconditioner_equals_stage_matrix(case):
+    shape, bc, kind, diff, b, sigma = case
+    K = operators.operator(shape, bc, kind, diff, b)
+    M = operators.stage_matrix(K, sigma).toarray()
+    P = fdm.assemble(*fdm.preconditioner_factors(shape, bc, kind, diff, b, sigma)).toarray()
+    assert np.max(np.abs(P - M)) <= 1e-12 * np.max(np.abs(M))
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_inverse_action_is_a_direct_solve(case):
+    shape, bc, kind, diff, b, sigma = case
+    K = operators.operator(shape, bc, kind, diff, b)
+    M = operators.stage_matrix(K, sigma)
+    r = np.random.default_rng(7).standard_normal(M.shape[0])
+    ref = spla.spsolve(M.tocsc(), r)
+    z = fdm.FDM(shape, bc, kind, diff, b, sigma).apply(r)
+    assert np.linalg.norm(z - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_contractions_follow_their_index_definitions():
+    rng = np.random.default_rng(3)
+    nx, ny, nz = 3, 4, 5
+    x = rng.standard_normal((nz, ny, nx))
+    Qa, Qb, Qc = rng.standard_normal((nx, nx)), rng.standard_normal((ny, ny)), rng.standard_normal((nz, nz))
+    r = np.zeros_like(x)
+    m = np.zeros_like(x)
+    l = np.zeros_like(x)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                r[k, j, i] = sum(Qa[i, q] * x[k, j, q] for q in range(nx))
+                m[k, j, i] = sum(Qb[j, q] * x[k, q, i] for q in range(ny))
+                l[k, j, i] = sum(Qc[k, q] * x[q, j, i] for q in range(nz))
+    assert np.allclose(fdm.t_r(Qa, x), r, atol=1e-13)
+    assert np.allclose(fdm.t_m(Qb, x), m, atol=1e-13)
+    assert np.allclose(fdm.t_l(Qc, x), l, atol=1e-13)
+
+
+def test_heat_factor_has_the_analytic_dirichlet_spectrum():
+    n, kappa, sigma = 9, 2.0, 3e-3
+    A, B, _ = fdm.preconditioner_factors((n, n, n), operators.DIRICHLET, 0, kappa, (0, 0, 0), sigma)
+    h = 1.0 / (n + 1)
+    mu = (4.0 / h ** 2) * np.sin(np.arange(1, n + 1) * np.pi * h / 2.0) ** 2
+    assert np.allclose(np.sort(np.linalg.eigvalsh(A)), np.sort(1.0 + sigma * kappa * mu), rtol=1e-13)
+    assert np.allclose(np.sort(np.linalg.eigvalsh(B)), np.sort(sigma * kappa * mu), rtol=1e-12)
