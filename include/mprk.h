@@ -56,13 +56,14 @@ enum { MPRK_OP_HEAT = 0, MPRK_OP_ADVDIFF = 1 };
 enum { MPRK_FMT_STENCIL = 0, MPRK_FMT_CSR = 1 };
 enum { MPRK_FP64 = 0, MPRK_FP32 = 1, MPRK_FP16 = 2 };
 enum { MPRK_CG = 0, MPRK_GMRES = 1 };
-enum { MPRK_PRECOND_NONE = 0, MPRK_PRECOND_BJ = 1 };
+enum { MPRK_PRECOND_NONE = 0, MPRK_PRECOND_BJ = 1, MPRK_PRECOND_FDM = 2 };
 enum { MPRK_TAB_SDIRK2 = 0, MPRK_TAB_SDIRK3 = 1, MPRK_TAB_MID = 2,
        MPRK_TAB_4S3PA = 3, MPRK_TAB_4S3PB = 4, MPRK_TAB_4S3PC = 5 };
 enum { MPRK_APPLY_K64 = 0,     /* y = K x, FP64 in/out */
        MPRK_APPLY_M_LP = 1,    /* y = (I - sigma_stage K) x in the LP storage type, compute type arithmetic */
        MPRK_APPLY_BJ_LP = 2,   /* y = blockdiag(M)^{-1} x, LP storage type */
-       MPRK_APPLY_M64 = 3 };   /* y = (I - sigma_stage K) x, FP64 */
+       MPRK_APPLY_M64 = 3,     /* y = (I - sigma_stage K) x, FP64 */
+       MPRK_APPLY_FDM_LP = 4 }; /* y = P^{-1} x, fast-diagonalisation preconditioner, LP storage type */
 
 /* Grid: nx*ny*nz unknowns on the unit cube.  bc = MPRK_BC_DIRICHLET0: zero
  * Dirichlet, n interior nodes per axis, h = 1/(n+1).  bc = MPRK_BC_PERIODIC:
@@ -91,7 +92,13 @@ typedef struct {
  *           and block-Jacobi inverses.  compute: MPRK_FP64 (only with FP64 storage) | MPRK_FP32.
  *  krylov: MPRK_CG (SPD only) | MPRK_GMRES (right preconditioned, restart = cycle length m).
  *  precond: MPRK_PRECOND_NONE | MPRK_PRECOND_BJ with block in {1,2,4,8}: consecutive blocks of
- *           `block` rows in lexicographic order, inverses computed in FP64 per block.
+ *           `block` rows in lexicographic order, inverses computed in FP64 per block |
+ *           MPRK_PRECOND_FDM: the fast-diagonalisation preconditioner of eqs. preconbasic and
+ *           Pinvform (Section "Problem setting and solver design"), P = I (x) I (x) A +
+ *           I (x) B (x) I + C (x) I (x) I with A = I - sigma Kx, B = -sigma Ky, C = -sigma Kz, its
+ *           inverse applied through the one-axis contractions of eq. TensorDecomp in the compute
+ *           type.  Implemented for the heat operator (zero Dirichlet or periodic ends, where P is
+ *           the stage matrix itself) with CG; other combinations return MPRK_EUNSUPPORTED.
  *  rtol/atol/maxit: inner Krylov stop ||r|| <= max(rtol ||b||, atol) or maxit iterations per
  *           outer pass (the paper stops on the absolute or the relative residual with at most 40
  *           iterations; Section "Linear solvers and setup of the numerical experiments").
@@ -182,8 +189,10 @@ int32_t mprk_solve(mprk_handle *h, int32_t stage, const double *rhs_dev, double 
                    mprk_solve_info *info);
 
 /* Apply one component operator (kernel-level access for verification):
- * MPRK_APPLY_K64 / MPRK_APPLY_M64: x, y are N doubles; MPRK_APPLY_M_LP / MPRK_APPLY_BJ_LP:
- * x, y are N values of the LP storage type (FP16 = IEEE binary16).  `stage` selects
+ * MPRK_APPLY_K64 / MPRK_APPLY_M64: x, y are N doubles; MPRK_APPLY_M_LP / MPRK_APPLY_BJ_LP /
+ * MPRK_APPLY_FDM_LP: x, y are N values of the LP storage type (FP16 = IEEE binary16); BJ_LP
+ * needs the block-Jacobi preconditioner and FDM_LP the fast-diagonalisation one (else
+ * MPRK_EINVAL).  `stage` selects
  * sigma = dt a_ii (ignored for K64).  Enqueued on the stream; waits before returning. */
 int32_t mprk_apply(mprk_handle *h, int32_t op, int32_t stage, const void *x_dev, void *y_dev);
 
@@ -207,7 +216,8 @@ int32_t mprk_autotune(mprk_handle *h, int32_t *nit_vec, int32_t *nit_row);
 /* Kernel classes for mprk_profile_read. */
 enum { MPRK_KC_STAGE_RHS = 0, MPRK_KC_RESIDUAL, MPRK_KC_CG_BEGIN, MPRK_KC_CG_DIR, MPRK_KC_CG_UPD,
        MPRK_KC_PROMOTE, MPRK_KC_GM_BEGIN, MPRK_KC_GM_PREC, MPRK_KC_GM_MATVEC, MPRK_KC_GM_ORTH,
-       MPRK_KC_GM_FINISH, MPRK_KC_KEPS, MPRK_KC_COMBINE, MPRK_KC_APPLY, MPRK_KC_COUNT };
+       MPRK_KC_GM_FINISH, MPRK_KC_KEPS, MPRK_KC_COMBINE, MPRK_KC_APPLY, MPRK_KC_CG_RZ,
+       MPRK_KC_FDM, MPRK_KC_COUNT };
 
 /* Per-kernel timing.  enable = 1 waits for the stream, clears the records and starts
  * recording a HIP event immediately before and after every kernel the handle launches (on its

@@ -511,6 +511,8 @@ extern "C" int32_t mprk_batch_create(int32_t count, const mprk_problem* problems
   if (prec->storage != MPRK_FP64 && prec->compute != MPRK_FP32)
     return set_error(MPRK_EUNSUPPORTED, "LP storage needs FP32 compute");
   if (prec->reorth) return set_error(MPRK_EUNSUPPORTED, "reorth is a GMRES option");
+  if (prec->precond == MPRK_PRECOND_FDM)
+    return set_error(MPRK_EUNSUPPORTED, "batched form implements block-Jacobi or no preconditioner");
   // one distinct nonzero diagonal, no eps off-diagonals needing k^eps, all stages implicit
   double diag = 0.0;
   for (int i = 0; i < tab->s; ++i) {

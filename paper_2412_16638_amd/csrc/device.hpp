@@ -67,7 +67,7 @@ constexpr int MAXPASS = 32;  // passes whose iteration counts are recorded
 enum KClass {
   KC_STAGE_RHS = 0, KC_RESIDUAL, KC_CG_BEGIN, KC_CG_DIR, KC_CG_UPD, KC_PROMOTE,
   KC_GM_BEGIN, KC_GM_PREC, KC_GM_MATVEC, KC_GM_ORTH, KC_GM_FINISH, KC_KEPS, KC_COMBINE,
-  KC_APPLY64, KC_COUNT
+  KC_APPLY64, KC_CG_RZ, KC_FDM, KC_COUNT
 };
 
 // Device control record of one solve context (one per problem).  The first 64 bytes

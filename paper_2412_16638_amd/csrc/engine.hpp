@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "fdm.hpp"
 
 namespace mprk {
 
@@ -72,6 +73,13 @@ struct EngineCtx {
   double kscale;
   Ctl* ctl;
   Red red;            // grid-reduction workspace
+  // fast-diagonalisation preconditioner (fdm_on): per-axis eigenbasis (compute type, n x n),
+  // eigenvalues of the axis second difference / h^2 (FP64), two compute-type scratch vectors
+  int fdm_on;
+  const void* fdm_Q[3];
+  const double* fdm_lam[3];
+  void* fdm_t[2];
+  double kappa;
   // LP vectors (S*)
   void *r, *z, *p0, *p1, *q, *x;
   void* V;
@@ -96,6 +104,8 @@ class Engine {
   virtual hipError_t cg_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
                              const BJDesc& dinv, int it) = 0;
   virtual hipError_t cg_finish(const EngineCtx& c) = 0;
+  // z = P^-1 r with the fast-diagonalisation preconditioner for stage shift sigma (S storage)
+  virtual hipError_t fdm_apply(const EngineCtx& c, double sigma, const void* r, void* z) = 0;
   // GMRES
   virtual hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) = 0;
   // Arnoldi step k of the cycle (k = the device's j for every step that does work)
@@ -161,8 +171,26 @@ class EngineT final : public Engine {
                 bj_typed<S>(dinv), cfg, c.ctl, c.red);
   }
   hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) override {
+    if (c.fdm_on) {
+      dispatch_vec(c, [&](auto vec) {
+        constexpr int VEC = decltype(vec)::value;
+        MPRK_LAUNCH_KC(c, KC_CG_BEGIN, (k_cg_begin_ext<S, C, VEC>), c.ln_red, c.ln_red, c.res, (S*)c.r,
+                       cfg, c.ctl, c.red);
+      });
+      fdm_apply(c, cfg.sigma, c.r, c.z);
+      cg_rz_t<1>(c);
+      return hipGetLastError();
+    }
     dispatch_vec_bs(c, [&](auto vec, auto bs) { cg_begin_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
     return hipGetLastError();
+  }
+  template <int BEGIN>
+  void cg_rz_t(const EngineCtx& c) {
+    dispatch_vec(c, [&](auto vec) {
+      constexpr int VEC = decltype(vec)::value;
+      MPRK_LAUNCH_KC(c, KC_CG_RZ, (k_cg_rz<S, C, VEC, BEGIN>), c.ln_red, c.ln_red, (const S*)c.r,
+                     (const S*)c.z, c.ctl, c.red);
+    });
   }
 
   template <int VEC, int FMT>
@@ -181,16 +209,62 @@ class EngineT final : public Engine {
   }
   hipError_t cg_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
                      const BJDesc& dinv, int it) override {
-    const S* z = c.bs > 0 ? (const S*)c.z : (const S*)c.r;
+    const S* z = (c.bs > 0 || c.fdm_on) ? (const S*)c.z : (const S*)c.r;
     const S* pold = (it & 1) ? (const S*)c.p1 : (const S*)c.p0;
     S* pnew = (it & 1) ? (S*)c.p0 : (S*)c.p1;
     if (c.fmt == 1) cg_dir_t<1, 1>(c, cfg, Mc, z, pold, pnew);
     else if (c.vec == 8) cg_dir_t<V8, 0>(c, cfg, Mc, z, pold, pnew);
     else if (c.vec == 4) cg_dir_t<4, 0>(c, cfg, Mc, z, pold, pnew);
     else cg_dir_t<1, 0>(c, cfg, Mc, z, pold, pnew);
+    if (c.fdm_on) {
+      dispatch_vec(c, [&](auto vec) {
+        constexpr int VEC = decltype(vec)::value;
+        MPRK_LAUNCH_KC(c, KC_CG_UPD, (k_cg_upd_ext<S, C, VEC>), c.ln_red, c.ln_red, (S*)c.x,
+                       (const S*)pnew, (S*)c.r, (const S*)c.q, cfg, c.ctl, c.red);
+      });
+      fdm_apply(c, cfg.sigma, c.r, c.z);
+      cg_rz_t<0>(c);
+      return hipGetLastError();
+    }
     dispatch_vec_bs(c, [&](auto vec, auto bs) {
       cg_upd_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, pnew, dinv);
     });
+    return hipGetLastError();
+  }
+
+  // ---------------- fast-diagonalisation preconditioner ----------------
+  template <typename TI, typename TO>
+  void fdm_row(const EngineCtx& c, int n, int nr, const void* Q, const TI* in, TO* out) {
+    FdmGeo g{n, nr, 0, 0, 0, 1};
+    const FdmScale none{nullptr, nullptr, nullptr, 0.0, 1, 0};
+    const dim3 grid((unsigned)((nr + FT_M - 1) / FT_M), (unsigned)((n + FT_N - 1) / FT_N), 1);
+    if (c.prof) c.prof->before(KC_FDM);
+    hipLaunchKernelGGL((k_fdm_contract<TI, TO, C, 1>), grid, dim3(256), 0, c.stream, g, (const C*)Q,
+                       in, out, none, (const Ctl*)c.ctl);
+    if (c.prof) c.prof->after();
+  }
+  void fdm_col(const EngineCtx& c, int n, int nc, int ld, long bstride, int nb, const void* Q,
+               const C* in, C* out, const FdmScale& sc) {
+    FdmGeo g{n, 0, nc, ld, bstride, nb};
+    const dim3 grid((unsigned)((n + FT_M - 1) / FT_M), (unsigned)((nc + FT_N - 1) / FT_N), (unsigned)nb);
+    if (c.prof) c.prof->before(KC_FDM);
+    hipLaunchKernelGGL((k_fdm_contract<C, C, C, 0>), grid, dim3(256), 0, c.stream, g, (const C*)Q,
+                       in, out, sc, (const Ctl*)c.ctl);
+    if (c.prof) c.prof->after();
+  }
+  hipError_t fdm_apply(const EngineCtx& c, double sigma, const void* r, void* z) override {
+    const int nx = c.geo.nx, ny = c.geo.ny, nz = c.geo.nz;
+    C* t0 = (C*)c.fdm_t[0];
+    C* t1 = (C*)c.fdm_t[1];
+    const FdmScale none{nullptr, nullptr, nullptr, 0.0, nx, 0};
+    const FdmScale sc{c.fdm_lam[0], c.fdm_lam[1], c.fdm_lam[2], sigma * c.kappa, nx, 1};
+    // (Q_C (x) Q_B (x) Q_A) applied as T_R, T_M, T_L (Q is its own inverse), then P_D^-1
+    fdm_row<S, C>(c, nx, ny * nz, c.fdm_Q[0], (const S*)r, t0);
+    fdm_col(c, ny, nx, nx, (long)nx * ny, nz, c.fdm_Q[1], t0, t1, none);
+    fdm_col(c, nz, nx * ny, nx * ny, 0, 1, c.fdm_Q[2], t1, t0, sc);
+    fdm_col(c, nz, nx * ny, nx * ny, 0, 1, c.fdm_Q[2], t0, t1, none);
+    fdm_col(c, ny, nx, nx, (long)nx * ny, nz, c.fdm_Q[1], t1, t0, none);
+    fdm_row<C, S>(c, nx, ny * nz, c.fdm_Q[0], t0, (S*)z);
     return hipGetLastError();
   }
   hipError_t cg_finish(const EngineCtx& c) override {
@@ -302,6 +376,12 @@ class EngineT final : public Engine {
   struct IC {
     static constexpr int value = V;
   };
+  template <typename F>
+  static void dispatch_vec(const EngineCtx& c, F&& f) {
+    if (c.vec == 8) f(IC<V8>{});
+    else if (c.vec == 4) f(IC<4>{});
+    else f(IC<1>{});
+  }
   template <typename F>
   static void dispatch_vec_bs(const EngineCtx& c, F&& f) {
     if (c.vec == 8) {

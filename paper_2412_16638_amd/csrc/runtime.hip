@@ -45,6 +45,7 @@ using namespace mprk;
   } while (0)
 
 namespace mprk {
+static_assert((int)KC_COUNT == (int)MPRK_KC_COUNT, "kernel classes of the C ABI and the device");
 
 thread_local std::string g_err;
 
@@ -389,7 +390,15 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
   if (p->krylov != MPRK_CG && p->krylov != MPRK_GMRES) return set_error(MPRK_EINVAL, "bad krylov");
   if (p->krylov == MPRK_GMRES && (p->restart < 1 || p->restart > MPRK_MAX_RESTART))
     return set_error(MPRK_EINVAL, "GMRES restart must be in [1, 32]");
-  if (p->precond != MPRK_PRECOND_NONE && p->precond != MPRK_PRECOND_BJ) return set_error(MPRK_EINVAL, "bad precond");
+  if (p->precond != MPRK_PRECOND_NONE && p->precond != MPRK_PRECOND_BJ && p->precond != MPRK_PRECOND_FDM)
+    return set_error(MPRK_EINVAL, "bad precond");
+  if (p->precond == MPRK_PRECOND_FDM) {
+    // implemented case: the heat operator (real symmetric eigenbases) with CG
+    if (op->kind != MPRK_OP_HEAT)
+      return set_error(MPRK_EUNSUPPORTED, "fast-diagonalisation preconditioner implemented for the heat operator");
+    if (p->krylov != MPRK_CG)
+      return set_error(MPRK_EUNSUPPORTED, "fast-diagonalisation preconditioner implemented with CG");
+  }
   if (p->precond == MPRK_PRECOND_BJ && !(p->block == 1 || p->block == 2 || p->block == 4 || p->block == 8))
     return set_error(MPRK_EINVAL, "block size must be 1, 2, 4 or 8");
   if (!(p->rtol >= 0.0) || !(p->atol >= 0.0) || !(p->outer_tol >= 0.0))
@@ -499,9 +508,10 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   o_k = take(v64 * nstages);
   o_keps = need_keps ? take(v64 * nstages) : 0;
   o_scr = take(v64);  // scratch FP64 vector (solve output of k, verification)
+  fdm = p.precond == MPRK_PRECOND_FDM;
   if (p.krylov == MPRK_CG) {
     o_r = take(vlp);
-    o_z = bs ? take(vlp) : o_r;
+    o_z = (bs || fdm) ? take(vlp) : o_r;
     o_p0 = take(vlp);
     o_p1 = take(vlp);
     o_q = take(vlp);
@@ -536,6 +546,16 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
     o_col = take((size_t)nnz * 4);
     o_kval = take((size_t)nnz * 8);
     o_mval = take((size_t)nnz * lp_bytes);
+  }
+  if (fdm) {
+    const size_t cb = p.compute == MPRK_FP64 ? 8 : 4;
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    for (int d = 0; d < 3; ++d) {
+      o_fdm_Q[d] = take((size_t)n3[d] * n3[d] * cb);
+      o_fdm_lam[d] = take((size_t)n3[d] * 8);
+    }
+    o_fdm_t[0] = take((size_t)N * cb);
+    o_fdm_t[1] = take((size_t)N * cb);
   }
   o_ctl = take(sizeof(Ctl));
   o_flag = take(256);
@@ -611,6 +631,14 @@ EngineCtx mprk_handle::ctx() const {
   c.kscale = kscale;
   c.ctl = (Ctl*)(ws + o_ctl);
   c.red = red();
+  c.fdm_on = fdm ? 1 : 0;
+  for (int d = 0; d < 3; ++d) {
+    c.fdm_Q[d] = fdm ? ws + o_fdm_Q[d] : nullptr;
+    c.fdm_lam[d] = fdm ? (const double*)(ws + o_fdm_lam[d]) : nullptr;
+  }
+  c.fdm_t[0] = fdm ? ws + o_fdm_t[0] : nullptr;
+  c.fdm_t[1] = fdm ? ws + o_fdm_t[1] : nullptr;
+  c.kappa = op.diff;
   c.r = ws + o_r;
   c.z = ws + o_z;
   c.p0 = ws + o_p0;
@@ -666,6 +694,25 @@ extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev,
     else
       HIPCHK(h->eng->bj_setup_stencil(c, stage_coef(h->Kc, h->sigmas[q]), dinv, fail, B.nslot, reps,
                                       B.mode == 3 ? h->vec_lp : 0));
+  }
+  if (h->fdm) {
+    // fast-diagonalisation: per-axis eigenbasis (compute type) and eigenvalues (FP64)
+    const int n3[3] = {h->grid.nx, h->grid.ny, h->grid.nz};
+    const bool f64 = h->prec.compute == MPRK_FP64;
+    for (int d = 0; d < 3; ++d) {
+      const int n = n3[d];
+      std::vector<double> Q((size_t)n * n), lam(n);
+      fdm_axis_basis(n, h->grid.bc == MPRK_BC_PERIODIC, Q.data(), lam.data());
+      if (f64) {
+        HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_Q[d], Q.data(), Q.size() * 8, hipMemcpyHostToDevice, h->stream));
+      } else {
+        std::vector<float> Qf(Q.begin(), Q.end());
+        HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_Q[d], Qf.data(), Qf.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));  // Qf goes out of scope
+      }
+      HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_lam[d], lam.data(), lam.size() * 8, hipMemcpyHostToDevice, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
   }
   int hfail = 0;
   HIPCHK(hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -1044,6 +1091,16 @@ extern "C" int32_t mprk_apply(mprk_handle* h, int32_t which, int32_t stage, cons
       if (!h->bs) return set_error(MPRK_EINVAL, "no block-Jacobi preconditioner configured");
       HIPCHK(h->eng->apply_bj(c, h->bj_desc(si), x, y));
       break;
+    case MPRK_APPLY_FDM_LP: {
+      if (!h->fdm) return set_error(MPRK_EINVAL, "no fast-diagonalisation preconditioner configured");
+      // the contraction kernels skip once a solve is finished: clear the flags first
+      Ctl* ctl = (Ctl*)(h->ws + h->o_ctl);
+      const int zero[2] = {0, 0};
+      HIPCHK(hipMemcpyAsync(&ctl->outer_done, zero, sizeof(int) * 2, hipMemcpyHostToDevice, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      HIPCHK(h->eng->fdm_apply(c, sigma, x, y));
+      break;
+    }
     default:
       return set_error(MPRK_EINVAL, "unknown apply op");
   }

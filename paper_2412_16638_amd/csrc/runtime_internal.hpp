@@ -73,6 +73,8 @@ struct mprk_handle {
   std::vector<BJSet> bjsets;
   size_t o_rowptr = 0, o_col = 0, o_kval = 0, o_mval = 0;
   size_t o_ctl = 0, o_flag = 0, o_part = 0, o_part2 = 0, o_tick = 0;
+  bool fdm = false;  // fast-diagonalisation preconditioner
+  size_t o_fdm_Q[3] = {}, o_fdm_lam[3] = {}, o_fdm_t[2] = {};
   size_t ws_bytes = 0;
   // binding
   double* u = nullptr;

@@ -29,7 +29,7 @@ def precisions(storage: str = 'fp64', krylov: str = 'cg', **overrides) -> A.mprk
     p = A.mprk_precisions_default(STORAGE[storage], KRYLOV[krylov])
     for k, v in overrides.items():
         if k == 'precond':
-            v = {'none': A.PRECOND_NONE, 'bj': A.PRECOND_BJ}.get(v, v)
+            v = {'none': A.PRECOND_NONE, 'bj': A.PRECOND_BJ, 'fdm': A.PRECOND_FDM}.get(v, v)
         setattr(p, k, v)
     return p
 

@@ -134,3 +134,25 @@ def test_shared_block_inverses_shrink_the_workspace():
     assert saved >= 32 ** 3 * 8 * 2 - 4096     # the per-block FP16 table (8 values per row)
     A.lib.mprk_destroy(h1)
     A.lib.mprk_destroy(h2)
+
+
+def test_fdm_preconditioner_scope_is_validated():
+    p = A.mprk_precisions_default(A.FP32, A.CG)
+    p.precond = A.PRECOND_FDM
+    rc, h = _create(prec=p, grid=(12, 10, 8))
+    assert rc == A.OK, A.mprk_last_error()
+    # workspace: the Krylov vectors plus per-axis bases (compute type), eigenvalues and two
+    # compute-type scratch vectors
+    N = 12 * 10 * 8
+    n = A.lib.mprk_workspace_bytes(h)
+    assert n >= 6 * N * 4 + (144 + 100 + 64) * 4 + (12 + 10 + 8) * 8 + 2 * N * 4
+    A.lib.mprk_destroy(h)
+    p = A.mprk_precisions_default(A.FP32, A.GMRES)
+    p.precond = A.PRECOND_FDM
+    rc, _ = _create(prec=p, kind=1, b=(1.0, 0.0, 0.0))
+    assert rc == A.EUNSUPPORTED  # advection: complex eigenbasis not implemented
+    rc, _ = _create(prec=p)
+    assert rc == A.EUNSUPPORTED  # GMRES with this preconditioner not implemented
+    p.precond = 3
+    rc, _ = _create(prec=p)
+    assert rc == A.EINVAL

@@ -1,0 +1,71 @@
+"""Fast-diagonalisation preconditioner on the GPU (eqs. preconbasic, Pinvform, TensorDecomp)
+against the FP64 oracle: the preconditioner apply, a stage solve, and a short integration."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle import closed_form, fdm, operators, tableaus
+from tests.gpu_util import log_case
+
+pytestmark = pytest.mark.gpu
+
+M = pytest.importorskip('paper_2412_16638_amd')
+A = M._abi
+torch = pytest.importorskip('torch')
+
+DT = {'fp64': torch.float64, 'fp32': torch.float32, 'fp16': torch.float16}
+TOL = {'fp64': 1e-12, 'fp32': 3e-6, 'fp16': 3e-3}
+
+
+def _stepper(shape, bc, storage, kappa=1.3, dt=2e-3, **over):
+    prec = M.precisions(storage, 'cg', precond='fdm', **over)
+    return M.Stepper(shape, bc, W.HEAT, kappa, (0, 0, 0), A.FMT_STENCIL, 'SDIRK3', prec, dt)
+
+
+@pytest.mark.parametrize("storage", ['fp64', 'fp32', 'fp16'])
+@pytest.mark.parametrize("shape,bc", [((20, 12, 9), W.DIRICHLET), ((16, 24, 10), W.PERIODIC),
+                                      ((70, 66, 65), W.DIRICHLET)])
+def test_fdm_apply_matches_the_oracle(shape, bc, storage):
+    log_case('fdm_apply', shape=shape, bc=bc, storage=storage)
+    st = _stepper(shape, bc, storage)
+    sigma = st.dt * (st.tab.a_hi[0] + st.tab.a_lo[0])
+    x = np.random.default_rng(11).standard_normal(st.N)
+    xd = torch.from_numpy(x).to('cuda', DT[storage])
+    y = st.apply(A.APPLY_FDM_LP, xd, stage=0).double().cpu().numpy()
+    ref = fdm.FDM(shape, bc, 0, 1.3, (0, 0, 0), sigma).apply(xd.double().cpu().numpy())
+    st.close()
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    assert err <= TOL[storage], err
+
+
+@pytest.mark.parametrize("storage,bound", [('fp64', 1e-10), ('fp32', 1e-8), ('fp16', 1e-6)])
+def test_fdm_stage_solve_matches_sparse_lu(storage, bound):
+    shape = (24, 20, 18)
+    log_case('fdm_solve', storage=storage)
+    st = _stepper(shape, W.DIRICHLET, storage, dt=5e-3)
+    rhs = np.random.default_rng(4).standard_normal(st.N)
+    x, info = st.solve(1, torch.from_numpy(rhs).cuda())
+    K = operators.operator(shape, W.DIRICHLET, W.HEAT, 1.3, (0, 0, 0))
+    Mx = operators.stage_matrix(K, 5e-3 * st.tab.a_lo[st.tab.s + 1] + 5e-3 * st.tab.a_hi[st.tab.s + 1])
+    ref = spla.spsolve(Mx.tocsc(), rhs)
+    st.close()
+    err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert info['converged'] == 1, info
+    assert err <= bound, (err, info)
+    if storage == 'fp64':  # the exact inverse: one CG iteration per pass
+        assert info['iters'] <= 2 * info['passes'], info
+
+
+@pytest.mark.parametrize("storage,bound", [('fp32', 1e-6), ('fp16', 1e-3)])
+def test_fdm_integration_matches_the_oracle(storage, bound):
+    p = W.heat_modes(n=32, nsteps=6)
+    log_case('fdm_integration', storage=storage)
+    st = M.from_problem(p, prec=M.precisions(storage, 'cg', precond='fdm'))
+    stats = st.step(p.nsteps)
+    u = st.get_u()
+    st.close()
+    ref = closed_form.evolve_heat(p.u0, p.diff, p.dt, p.nsteps, tableaus.sdirk3())
+    err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    assert err <= bound, err
+    assert max(stats['iters']) <= 8 * max(stats['passes']), stats
