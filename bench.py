@@ -33,7 +33,7 @@ def log(*a):
 
 
 def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, units: int,
-                      nv_total: int = 0) -> float:
+                      nv_total: int = 0, fdm: bool = False) -> float:
     """Bytes each kernel class must move per its definition (each array touched once; halos
     and reduction partials not counted).  s = LP storage bytes, m = LP matrix bytes, bs = block."""
     inv = bs * m  # block-Jacobi inverse row per unknown
@@ -53,7 +53,9 @@ def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, uni
     if kc == 'cg_dir':
         return N * worked * 4 * s
     if kc == 'cg_upd':
-        return N * worked * (7 * s + inv)
+        return N * worked * ((6 if fdm else 7) * s + inv)
+    if kc == 'cg_rz':
+        return N * worked * 2 * s
     if kc == 'promote':
         return N * worked * (16 + s)
     if kc == 'stage_rhs':
@@ -70,13 +72,21 @@ def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, uni
 MIXED_TOL = {'heat128': dict(rtol=1e-3, outer_tol=1e-6), 'advdiff256': {}}
 
 
-def make_problem(name: str):
+def make_problem(name: str, precond: str = 'bj'):
     import workloads as W
     if name == 'advdiff256':
-        return W.advdiff_bump()
-    if name == 'heat128':
-        return W.heat_modes()
-    raise SystemExit(f'unknown workload {name}')
+        p = W.advdiff_bump()
+    elif name == 'heat128':
+        p = W.heat_modes()
+    else:
+        raise SystemExit(f'unknown workload {name}')
+    if precond == 'fdm':
+        p.precond = 'fdm'
+    return p
+
+
+# MI355X vector peaks (TFLOP/s) for the compute-bound contraction kernels
+ALU_PEAK = {'fp64': 78.6, 'fp32': 157.3, 'fp16': 157.3}
 
 
 def oracle_reference(p):
@@ -183,6 +193,9 @@ def main():
                     help='profiling runs: skip the full-integration error check and side legs')
     ap.add_argument('--bj', default='per-block', choices=['per-block', 'shared'],
                     help='block-Jacobi inverse storage of the headline run')
+    ap.add_argument('--precond', default='bj', choices=['bj', 'fdm'],
+                    help='stage-solve preconditioner: block-Jacobi(8) (the configurations) or the '
+                         'paper\'s fast-diagonalisation one (heat128 only)')
     ap.add_argument('--reps', type=int, default=3,
                     help='timed repetitions of the K steps (value = median)')
     ap.add_argument('--calib-copy', type=int, default=0, metavar='MIB',
@@ -213,7 +226,9 @@ def main():
         torch.cuda.synchronize()
         log(f'calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written')
         del src, dst
-    p = make_problem(args.workload)
+    if args.precond == 'fdm' and args.workload != 'heat128':
+        raise SystemExit('--precond fdm is implemented for the heat workload (heat128)')
+    p = make_problem(args.workload, args.precond)
     N = p.N
     K, Wm = args.steps, args.warmup
     log(f'workload {args.workload}: N={N} ({p.n}^3), {p.tableau}, dt={p.dt}, {p.krylov}, '
@@ -264,7 +279,8 @@ def main():
             nv_total = r['worked'] // p_stages(p) * nv['stage_rhs']
         if kc == 'combine':
             nv_total = r['worked'] * nv['combine']
-        b = algorithmic_bytes(kc, N, s_bytes, s_bytes, bs, r['worked'], r['units'], nv_total)
+        b = algorithmic_bytes(kc, N, s_bytes, s_bytes, bs, r['worked'], r['units'], nv_total,
+                              fdm=args.precond == 'fdm')
         rows.append((kc, r, b))
     total_ms = sum(r['ms'] for _, r, _ in rows)
     dom = max(rows, key=lambda x: x[1]['ms'])
@@ -274,6 +290,10 @@ def main():
     avg_ms = r['ms'] / r['launches']
     bytes_per_launch = b / r['launches']
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    if 'fdm' in prof and prof['fdm']['launches']:
+        fr = prof['fdm']
+        fdm_tflops = 2.0 * fr['units'] * N / (fr['ms'] * 1e-3) / 1e12
+        log(f'fdm contractions: {fdm_tflops:.2f} TFLOP/s over {fr["launches"]} launches')
     kernel_table = {k: {'launches': rr['launches'], 'worked': rr['worked'],
                         'ms': round(rr['ms'], 3),
                         'share': round(rr['ms'] / total_ms, 4) if total_ms else None,
@@ -289,11 +309,22 @@ def main():
         if tr.get("kernel_hash") == kernel_source_hash():
             # counters give bytes per working dispatch; spread over all launches like `achieved`
             traffic = tr['bytes_per_worked_launch'] * r['worked'] / r['launches']
-    roofline = {'bound': 'hbm', 'kernel': kc, 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS,
-                'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4), 'traffic': traffic,
-                'bytes_per_launch': bytes_per_launch, 'avg_launch_us': round(avg_ms * 1e3, 2),
-                'launches': r['launches'], 'worked': r['worked'],
-                'all_kernels_GBps': round(sum(bb for _, _, bb in rows) / (total_ms * 1e-3) / 1e9, 1)}
+    if kc == 'fdm':
+        # the contractions are dense: 2 n flops per unknown per launch (n = axis length)
+        flops_per_launch = 2.0 * r['units'] * N / r['launches']
+        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        peak = ALU_PEAK[p.precision]
+        roofline = {'bound': 'alu', 'kernel': kc, 'achieved': round(achieved, 2), 'peak': peak,
+                    'unit': 'TFLOP/s', 'frac': round(achieved / peak, 4), 'traffic': None,
+                    'flops_per_launch': flops_per_launch, 'avg_launch_us': round(avg_ms * 1e3, 2),
+                    'launches': r['launches'], 'worked': r['worked']}
+    else:
+        roofline = {'bound': 'hbm', 'kernel': kc, 'achieved': round(achieved, 1),
+                    'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4),
+                    'traffic': traffic, 'bytes_per_launch': bytes_per_launch,
+                    'avg_launch_us': round(avg_ms * 1e3, 2), 'launches': r['launches'],
+                    'worked': r['worked'],
+                    'all_kernels_GBps': round(sum(bb for _, _, bb in rows) / (total_ms * 1e-3) / 1e9, 1)}
     st.close()
 
     # ---- FP64 path at matched error ----
@@ -304,7 +335,7 @@ def main():
         for tol in (1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8, 1e-9, 1e-10,
                     3e-11, 1e-11, 3e-12, 1e-12):
             over = dict(rtol=tol, outer_tol=tol, bj_shared=bjs)
-            q = make_problem(args.workload)
+            q = make_problem(args.workload, args.precond)
             q.precision = 'fp64'
             u64, s64 = run_integration(M, q, fmt, **over)
             e64 = float(np.linalg.norm(u64 - ref) / np.linalg.norm(ref))
@@ -322,7 +353,7 @@ def main():
                 break
         # the FP64 path at a tight tolerance, for reference
         tight = 1e-10
-        q = make_problem(args.workload)
+        q = make_problem(args.workload, args.precond)
         q.precision = 'fp64'
         over = dict(rtol=tight, outer_tol=tight, bj_shared=bjs)
         if tight not in sweep:
@@ -339,7 +370,7 @@ def main():
 
     # ---- the other block-Jacobi storage (same values; per-block inverse stream or not) ----
     other = None
-    if not args.no_fp64 and not args.quick:
+    if not args.no_fp64 and not args.quick and args.precond == 'bj':
         st2 = M.from_problem(p, fmt=fmt, bj_shared=1 - bjs, **MIXED_TOL[args.workload])
         st2.autotune()
         t2, _, _ = time_steps(st2, p.u0, K, Wm)
@@ -364,7 +395,9 @@ def main():
         'data': 'synthetic',
         'config': {'workload': ('advdiff_upwind_periodic_256^3_sdirk3_dt2e-3_gmres30_bj8_fp16'
                                 if args.workload == 'advdiff256'
-                                else 'heat_dirichlet_128^3_sdirk3_dt5e-4_cg_bj8_fp32'),
+                                else 'heat_dirichlet_128^3_sdirk3_dt5e-4_cg_bj8_fp32'
+                                if args.precond == 'bj'
+                                else 'heat_dirichlet_128^3_sdirk3_dt5e-4_cg_fdm_fp32'),
                    'N': N, 'format': args.fmt, 'lp_storage': p.precision, 'lp_compute': 'f32',
                    'explicit_parts': 'f64', 'krylov': p.krylov},
         'err_vs_oracle': err_mixed,
@@ -372,7 +405,7 @@ def main():
         'timed_reps_ms_per_step': [round(t * 1e3 / K, 4) for t in reps],
         'fp64_matched': fp64,
         'fp64_tight': fp64_tight,
-        'bj_storage': args.bj,
+        'bj_storage': args.bj if args.precond == 'bj' else None,
         'autotuned_groups_per_thread': list(tuned),
         'other_bj_storage': other,
         'speedup_vs_fp64_matched': (value / fp64['value']) if fp64 else None,

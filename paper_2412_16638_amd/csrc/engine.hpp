@@ -240,7 +240,7 @@ class EngineT final : public Engine {
     const dim3 grid((unsigned)((nr + FT_M - 1) / FT_M), (unsigned)((n + FT_N - 1) / FT_N), 1);
     if (c.prof) c.prof->before(KC_FDM);
     hipLaunchKernelGGL((k_fdm_contract<TI, TO, C, 1>), grid, dim3(256), 0, c.stream, g, (const C*)Q,
-                       in, out, none, (const Ctl*)c.ctl);
+                       in, out, none, c.ctl);
     if (c.prof) c.prof->after();
   }
   void fdm_col(const EngineCtx& c, int n, int nc, int ld, long bstride, int nb, const void* Q,
@@ -249,7 +249,7 @@ class EngineT final : public Engine {
     const dim3 grid((unsigned)((n + FT_M - 1) / FT_M), (unsigned)((nc + FT_N - 1) / FT_N), (unsigned)nb);
     if (c.prof) c.prof->before(KC_FDM);
     hipLaunchKernelGGL((k_fdm_contract<C, C, C, 0>), grid, dim3(256), 0, c.stream, g, (const C*)Q,
-                       in, out, sc, (const Ctl*)c.ctl);
+                       in, out, sc, c.ctl);
     if (c.prof) c.prof->after();
   }
   hipError_t fdm_apply(const EngineCtx& c, double sigma, const void* r, void* z) override {

@@ -12,8 +12,9 @@
 // Every contraction is a GEMM with K = n (the axis length): along x the rows of x are
 // contiguous (out = X Q^T, "row" form); along y and z the contracted index is strided and the
 // remaining index contiguous (out_b = Q X_b, "column" form).  One LDS-tiled kernel does both:
-// 64 x 64 output tiles, K in slices of 16, 256 threads with 4 x 4 outputs each, FP32 (FP64 for
-// FP64 storage) accumulation.  The P_D^-1 scaling is fused into the third forward contraction.
+// 64 x 64 output tiles, K staged in LDS in chunks of 32 (FP32) or 16 (FP64), 256 threads with
+// 4 x 4 outputs each, FP32 (FP64 for FP64 storage) accumulation.  The P_D^-1 scaling is fused
+// into the third forward contraction.
 #pragma once
 
 #include <cmath>
@@ -24,7 +25,15 @@ namespace mprk {
 
 constexpr int FT_M = 64;  // output tile rows
 constexpr int FT_N = 64;  // output tile columns
-constexpr int FT_K = 16;  // contraction slice
+
+// Contraction chunk staged in LDS per pass: both 64 x KC operand tiles are loaded with all their
+// loads in flight, then KC rank-1 updates run from LDS (17 KB for either type, so that several
+// blocks share a CU).
+template <typename C>
+constexpr int fdm_kc() {
+  return sizeof(C) == 8 ? 16 : 32;
+}
+static_assert(fdm_kc<float>() % 4 == 0 && fdm_kc<double>() % 4 == 0, "k steps of 4");
 
 // Geometry of one contraction.  ROW form (along x): out[r][a] = sum_q in[r][q] Q[a][q] for
 // r < nr rows of length n.  COL form: out[b][a][c] = sum_q Q[a][q] in[b][q][c], c < nc
@@ -52,12 +61,16 @@ struct FdmScale {
 template <typename TI, typename TO, typename C, int ROW>
 __global__ __launch_bounds__(256) void k_fdm_contract(FdmGeo g, const C* __restrict__ Q,
                                                       const TI* __restrict__ in, TO* __restrict__ out,
-                                                      FdmScale sc, const Ctl* ctl) {
+                                                      FdmScale sc, Ctl* ctl) {
   if (ctl->outer_done | ctl->inner_done) return;
-  __shared__ C As[FT_K][FT_M + 4];  // As[k][m]: the operand indexed by the output row
-  __shared__ C Bs[FT_K][FT_N + 4];  // Bs[k][n]: the operand indexed by the output column
+  count_work(ctl, KC_FDM, g.n);
+  constexpr int KC = fdm_kc<C>();
+  // rows padded by 4 elements (4-wide vector reads stay aligned)
+  __shared__ __align__(32) C As[KC][FT_M + 4];  // As[k][m]: the operand indexed by the output row
+  __shared__ __align__(32) C Bs[KC][FT_N + 4];  // Bs[k][n]: the operand indexed by the output column
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
+  static_assert(FT_M * fdm_kc<C>() % 256 == 0 && FT_M == FT_N, "whole chunks per thread");
   const int m0 = blockIdx.x * FT_M;  // ROW: rows r; COL: a
   const int n0 = blockIdx.y * FT_N;  // ROW: a;      COL: c
   const int b = blockIdx.z;
@@ -68,44 +81,59 @@ __global__ __launch_bounds__(256) void k_fdm_contract(FdmGeo g, const C* __restr
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = C(0);
-  for (int q0 = 0; q0 < n; q0 += FT_K) {
-    // 64 x 16 of each operand: thread t loads 4 elements of row (t / 4), slice (t % 4) * 4
-    const int lr = tid >> 2, lk = (tid & 3) * 4;
+  // Each thread stages PER elements of each operand per chunk; the next chunk's elements are
+  // loaded into registers while the current chunk is multiplied from LDS.
+  constexpr int PER = FT_M * KC / 256;
+  C ra[PER], rb[PER];
+  auto load_chunk = [&](int q0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = q0 + lk + u;
+    for (int u = 0; u < PER; ++u) {
+      // operands indexed (row, k) with k contiguous in memory: e -> row e / KC, k e % KC
+      const int e = threadIdx.x + u * 256;
+      const int lr = e / KC, kk = e % KC, q = q0 + kk;
       if constexpr (ROW) {
         const int r = m0 + lr, a = n0 + lr;
-        As[lk + u][lr] = (r < g.nr && q < n) ? (C)inb[(size_t)r * n + q] : C(0);
-        Bs[lk + u][lr] = (a < n && q < n) ? Q[(size_t)a * n + q] : C(0);
+        ra[u] = (r < g.nr && q < n) ? (C)inb[(size_t)r * n + q] : C(0);
+        rb[u] = (a < n && q < n) ? Q[(size_t)a * n + q] : C(0);
       } else {
         const int a = m0 + lr;
-        As[lk + u][lr] = (a < n && q < n) ? Q[(size_t)a * n + q] : C(0);
+        ra[u] = (a < n && q < n) ? Q[(size_t)a * n + q] : C(0);
+        // in[b][q][c], contiguous along c: e -> row e / 64, column e % 64
+        const int kq = e / FT_N, lc = e % FT_N, qq = q0 + kq, c = n0 + lc;
+        rb[u] = (qq < n && c < g.nc) ? (C)inb[(size_t)qq * g.ld + c] : C(0);
       }
     }
-    if constexpr (!ROW) {
-      // 16 x 64 slice of in[b][q][c], contiguous along c: thread t loads row (t / 16),
-      // columns (t % 16) * 4 .. + 3
-      const int kq = tid >> 4, lc = (tid & 15) * 4;
-      const int q = q0 + kq;
+  };
+  auto store_chunk = [&]() {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int c = n0 + lc + u;
-        Bs[kq][lc + u] = (q < n && c < g.nc) ? (C)inb[(size_t)q * g.ld + c] : C(0);
-      }
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * 256;
+      As[e % KC][e / KC] = ra[u];
+      if constexpr (ROW) Bs[e % KC][e / KC] = rb[u];
+      else Bs[e / FT_N][e % FT_N] = rb[u];
     }
+  };
+  load_chunk(0);
+  for (int q0 = 0; q0 < n; q0 += KC) {
+    store_chunk();
     __syncthreads();
+    if (q0 + KC < n) load_chunk(q0 + KC);  // in flight during the multiply below
+    // k in steps of 4 (the tiles are zero past n, and KC is a multiple of 4); each thread reads
+    // its 4 rows and 4 columns of a k-slice as one 4-wide LDS vector each
+    const int kend = min(KC, (n - q0 + 3) & ~3);
+    for (int k0 = 0; k0 < kend; k0 += 4) {
+      Vec<C, 4> av[4], bv[4];
 #pragma unroll
-    for (int k = 0; k < FT_K; ++k) {
-      C av[4], bv[4];
+      for (int kk = 0; kk < 4; ++kk) {
+        av[kk] = *reinterpret_cast<const Vec<C, 4>*>(&As[k0 + kk][ty * 4]);
+        bv[kk] = *reinterpret_cast<const Vec<C, 4>*>(&Bs[k0 + kk][tx * 4]);
+      }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[k][ty * 4 + i];
+      for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[k][tx * 4 + j];
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+          for (int j = 0; j < 4; ++j) acc[i][j] += av[kk].v[i] * bv[kk].v[j];
     }
     __syncthreads();
   }
