@@ -233,24 +233,39 @@ class EngineT final : public Engine {
   }
 
   // ---------------- fast-diagonalisation preconditioner ----------------
+  template <typename TI, typename TO, int V4, int BM, int KC>
+  void fdm_launch(const EngineCtx& c, FdmGeo g, int row, const void* Q, const TI* in, TO* out,
+                  const FdmScale& sc) {
+    const int n = g.n;
+    g.tiles = row ? ((g.nr + BM - 1) / BM) * ((n + FT_N - 1) / FT_N)
+                  : ((n + BM - 1) / BM) * ((g.nc + FT_N - 1) / FT_N) * g.nb;
+    const dim3 grid((unsigned)((g.tiles + 7) & ~7));
+    if (c.prof) c.prof->before(KC_FDM);
+    if (row)
+      hipLaunchKernelGGL((k_fdm_contract<TI, TO, C, 1, V4, BM, KC>), grid, dim3(256), 0, c.stream, g,
+                         (const C*)Q, in, out, sc, c.ctl);
+    else
+      hipLaunchKernelGGL((k_fdm_contract<TI, TO, C, 0, V4, BM, KC>), grid, dim3(256), 0, c.stream, g,
+                         (const C*)Q, in, out, sc, c.ctl);
+    if (c.prof) c.prof->after();
+  }
+  // the data operand is read 4 elements at a time when its rows have a multiple of 4 elements
+  template <typename TI, typename TO>
+  void fdm_go(const EngineCtx& c, const FdmGeo& g, int row, const void* Q, const TI* in, TO* out,
+              const FdmScale& sc) {
+    if (c.geo.nx % 4 == 0) fdm_launch<TI, TO, 1, 64, FT_KC>(c, g, row, Q, in, out, sc);
+    else fdm_launch<TI, TO, 0, 64, FT_KC>(c, g, row, Q, in, out, sc);
+  }
   template <typename TI, typename TO>
   void fdm_row(const EngineCtx& c, int n, int nr, const void* Q, const TI* in, TO* out) {
-    FdmGeo g{n, nr, 0, 0, 0, 1};
+    const FdmGeo g{n, fdm_ldq(n), nr, 0, 0, 0, 1, 0};
     const FdmScale none{nullptr, nullptr, nullptr, 0.0, 1, 0};
-    const dim3 grid((unsigned)((nr + FT_M - 1) / FT_M), (unsigned)((n + FT_N - 1) / FT_N), 1);
-    if (c.prof) c.prof->before(KC_FDM);
-    hipLaunchKernelGGL((k_fdm_contract<TI, TO, C, 1>), grid, dim3(256), 0, c.stream, g, (const C*)Q,
-                       in, out, none, c.ctl);
-    if (c.prof) c.prof->after();
+    fdm_go<TI, TO>(c, g, 1, Q, in, out, none);
   }
   void fdm_col(const EngineCtx& c, int n, int nc, int ld, long bstride, int nb, const void* Q,
                const C* in, C* out, const FdmScale& sc) {
-    FdmGeo g{n, 0, nc, ld, bstride, nb};
-    const dim3 grid((unsigned)((n + FT_M - 1) / FT_M), (unsigned)((nc + FT_N - 1) / FT_N), (unsigned)nb);
-    if (c.prof) c.prof->before(KC_FDM);
-    hipLaunchKernelGGL((k_fdm_contract<C, C, C, 0>), grid, dim3(256), 0, c.stream, g, (const C*)Q,
-                       in, out, sc, c.ctl);
-    if (c.prof) c.prof->after();
+    const FdmGeo g{n, fdm_ldq(n), 0, nc, ld, bstride, nb, 0};
+    fdm_go<C, C>(c, g, 0, Q, in, out, sc);
   }
   hipError_t fdm_apply(const EngineCtx& c, double sigma, const void* r, void* z) override {
     const int nx = c.geo.nx, ny = c.geo.ny, nz = c.geo.nz;

@@ -11,10 +11,12 @@
 //
 // Every contraction is a GEMM with K = n (the axis length): along x the rows of x are
 // contiguous (out = X Q^T, "row" form); along y and z the contracted index is strided and the
-// remaining index contiguous (out_b = Q X_b, "column" form).  One LDS-tiled kernel does both:
-// 64 x 64 output tiles, K staged in LDS in chunks of 32 (FP32) or 16 (FP64), 256 threads with
-// 4 x 4 outputs each, FP32 (FP64 for FP64 storage) accumulation.  The P_D^-1 scaling is fused
-// into the third forward contraction.
+// remaining index contiguous (out_b = Q X_b, "column" form).  One kernel does both on the
+// matrix cores (FP32 MFMA, FP64 MFMA for FP64 storage): 64 x 64 output tiles, 4 waves of 2 x 2
+// 16 x 16 products, K staged in LDS in chunks of 32 with the next chunk prefetched into
+// registers.  (Tile heights 32/64 and chunks 32/64 measured alike at 128^3, within 5 %: a
+// launch there is bound by its fixed latency, not by the matrix cores or HBM.)  The P_D^-1
+// scaling is fused into the third forward contraction.
 #pragma once
 
 #include <cmath>
@@ -25,26 +27,24 @@ namespace mprk {
 
 constexpr int FT_M = 64;  // output tile rows
 constexpr int FT_N = 64;  // output tile columns
+constexpr int FT_KC = 32; // contraction chunk staged in LDS per pass
 
-// Contraction chunk staged in LDS per pass: both 64 x KC operand tiles are loaded with all their
-// loads in flight, then KC rank-1 updates run from LDS (17 KB for either type, so that several
-// blocks share a CU).
-template <typename C>
-constexpr int fdm_kc() {
-  return sizeof(C) == 8 ? 16 : 32;
-}
-static_assert(fdm_kc<float>() % 4 == 0 && fdm_kc<double>() % 4 == 0, "k steps of 4");
+// Row stride of a stored eigenbasis: n rounded up to 4 (zero padded), so that every 4-wide load
+// of a basis row is aligned and in bounds.
+inline int fdm_ldq(int n) { return (n + 3) & ~3; }
 
 // Geometry of one contraction.  ROW form (along x): out[r][a] = sum_q in[r][q] Q[a][q] for
 // r < nr rows of length n.  COL form: out[b][a][c] = sum_q Q[a][q] in[b][q][c], c < nc
 // contiguous, rows of `in` / `out` ld elements apart, batches bstride apart.
 struct FdmGeo {
   int n;         // axis length (= contraction length)
+  int ldq;       // row stride of Q (fdm_ldq(n))
   int nr;        // ROW form: number of rows
   int nc;        // COL form: contiguous extent
   int ld;        // COL form: elements between consecutive q (and a) rows
   long bstride;  // COL form: elements between batches
   int nb;        // COL form: batches
+  int tiles;     // output tiles (the grid is this rounded up to a multiple of 8)
 };
 
 // Scaling by P_D^-1 (fused into a COL-form contraction along z): the output element with
@@ -58,105 +58,226 @@ struct FdmScale {
   int on;
 };
 
-template <typename TI, typename TO, typename C, int ROW>
+// One 16 x 16 x 4 matrix-core product-accumulate: D = A B + D, A 16 x 4, B 4 x 16.  Lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; its i-th accumulator (i < 4) holds
+// D[row(l / 16, i)][l % 16], row = 4 (l / 16) + i for FP32 and 4 i + l / 16 for FP64.
+template <typename C>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef float acc __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g4, int i) { return 4 * g4 + i; }
+};
+template <>
+struct Mfma<double> {
+  typedef double acc __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g4, int i) { return 4 * i + g4; }
+};
+
+// One contraction (either form) on the matrix cores.  A block computes a 64 x 64 output tile;
+// each of its 4 waves a 32 x 32 quarter as 2 x 2 MFMA tiles.  K runs in chunks of FT_KC staged
+// in LDS, the next chunk loaded into registers while the current one is multiplied.  Since the
+// sum over q may visit q in any order common to both operands, lane group g of the j-th product
+// of a 16-wide k block takes k = 4 g + j: each lane then reads its 4 k values of an operand
+// whose k is contiguous as one 4-wide LDS vector.  Tiles are zero past the problem edges, so
+// padded rows and k values add nothing.  V4: the data operand is loaded 4 elements at a time
+// (its contiguous extent is a multiple of 4), else element by element.
+template <typename TI, typename TO, typename C, int ROW, int V4, int BM, int KC>
 __global__ __launch_bounds__(256) void k_fdm_contract(FdmGeo g, const C* __restrict__ Q,
                                                       const TI* __restrict__ in, TO* __restrict__ out,
                                                       FdmScale sc, Ctl* ctl) {
+  static_assert((BM == 32 || BM == 64) && (KC == 32 || KC == 64), "tile shapes");
   if (ctl->outer_done | ctl->inner_done) return;
   count_work(ctl, KC_FDM, g.n);
-  constexpr int KC = fdm_kc<C>();
-  // rows padded by 4 elements (4-wide vector reads stay aligned)
-  __shared__ __align__(32) C As[KC][FT_M + 4];  // As[k][m]: the operand indexed by the output row
-  __shared__ __align__(32) C Bs[KC][FT_N + 4];  // Bs[k][n]: the operand indexed by the output column
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  static_assert(FT_M * fdm_kc<C>() % 256 == 0 && FT_M == FT_N, "whole chunks per thread");
-  const int m0 = blockIdx.x * FT_M;  // ROW: rows r; COL: a
-  const int n0 = blockIdx.y * FT_N;  // ROW: a;      COL: c
-  const int b = blockIdx.z;
+  constexpr int PK = KC + 4, PN = FT_N + 4;
+  constexpr int MI = BM / 32;              // 16-row MFMA tiles per wave (waves 2 x 2)
+  constexpr int KV = KC / 4;               // 4-wide vectors per k-contiguous row of a chunk
+  constexpr int NA = BM * KV / 256;        // staged vectors per thread: A operand
+  constexpr int NB = FT_N * KV / 256;      //                            B operand
+  typedef typename Mfma<C>::acc Acc;
+  // As[m][k]: the operand indexed by the output row.  ROW: Bs[n][k] (basis rows, k contiguous);
+  // COL: Bs[k][n] (data rows, n contiguous).  Row strides of KC + 4 and 68 elements keep the
+  // 16-lane groups of an MFMA operand read on distinct banks.
+  __shared__ __align__(32) C As[BM][PK];
+  __shared__ __align__(32) C Bs[ROW ? FT_N : KC][ROW ? PK : PN];
   const int n = g.n;
+  const int T = xcd_block((g.tiles + 7) & ~7);
+  if (T >= g.tiles) return;
+  // tiles that read the same data rows are consecutive (same XCD, same L2)
+  int mt, nt, b = 0;
+  if constexpr (ROW) {
+    const int NT = (n + FT_N - 1) / FT_N;
+    nt = T % NT;
+    mt = T / NT;
+  } else {
+    const int MT = (n + BM - 1) / BM, NT = (g.nc + FT_N - 1) / FT_N;
+    mt = T % MT;
+    nt = (T / MT) % NT;
+    b = T / (MT * NT);
+  }
+  const int m0 = mt * BM;    // ROW: rows r; COL: a
+  const int n0 = nt * FT_N;  // ROW: a;      COL: c
   const TI* inb = ROW ? in : in + (size_t)b * g.bstride;
-  C acc[4][4];
+  const int tid = threadIdx.x;
+  // staging: vector e of a k-contiguous operand covers row e / KV, k 4 (e % KV) .. + 3; vector e
+  // of the COL data covers k e / 16, n 4 (e % 16) .. + 3
+  Vec<C, 4> ra[NA], rb[NB];
+  auto zero4 = [](Vec<C, 4>& v) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) v.v[j] = C(0);
+  };
+  auto load_q = [&](Vec<C, 4>& v, int a, int q) {  // Q[a][q .. q + 3]
+    if (a < n && q < g.ldq) v = *reinterpret_cast<const Vec<C, 4>*>(Q + (size_t)a * g.ldq + q);
+    else zero4(v);
+  };
+  // data rows with k contiguous (ROW form): in[r][q .. q + 3]
+  auto load_row = [&](Vec<C, 4>& v, int r, int q) {
+    const TI* src = inb + (size_t)r * n + q;
+    if constexpr (V4) {
+      if (r < g.nr && q < n) {
+        const Vec<TI, 4> t = *reinterpret_cast<const Vec<TI, 4>*>(src);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = C(0);
-  // Each thread stages PER elements of each operand per chunk; the next chunk's elements are
-  // loaded into registers while the current chunk is multiplied from LDS.
-  constexpr int PER = FT_M * KC / 256;
-  C ra[PER], rb[PER];
+        for (int j = 0; j < 4; ++j) v.v[j] = (C)t.v[j];
+      } else {
+        zero4(v);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v.v[j] = (r < g.nr && q + j < n) ? (C)src[j] : C(0);
+    }
+  };
+  // data rows with n contiguous (COL form): in[b][qq][c .. c + 3]
+  auto load_col = [&](Vec<C, 4>& v, int qq, int c) {
+    const TI* src = inb + (size_t)qq * g.ld + c;
+    if constexpr (V4) {
+      if (qq < n && c < g.nc) {
+        const Vec<TI, 4> t = *reinterpret_cast<const Vec<TI, 4>*>(src);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v.v[j] = (C)t.v[j];
+      } else {
+        zero4(v);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v.v[j] = (qq < n && c + j < g.nc) ? (C)src[j] : C(0);
+    }
+  };
   auto load_chunk = [&](int q0) {
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      // operands indexed (row, k) with k contiguous in memory: e -> row e / KC, k e % KC
-      const int e = threadIdx.x + u * 256;
-      const int lr = e / KC, kk = e % KC, q = q0 + kk;
-      if constexpr (ROW) {
-        const int r = m0 + lr, a = n0 + lr;
-        ra[u] = (r < g.nr && q < n) ? (C)inb[(size_t)r * n + q] : C(0);
-        rb[u] = (a < n && q < n) ? Q[(size_t)a * n + q] : C(0);
-      } else {
-        const int a = m0 + lr;
-        ra[u] = (a < n && q < n) ? Q[(size_t)a * n + q] : C(0);
-        // in[b][q][c], contiguous along c: e -> row e / 64, column e % 64
-        const int kq = e / FT_N, lc = e % FT_N, qq = q0 + kq, c = n0 + lc;
-        rb[u] = (qq < n && c < g.nc) ? (C)inb[(size_t)qq * g.ld + c] : C(0);
-      }
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + u * 256, row = e / KV, q = q0 + (e % KV) * 4;
+      if constexpr (ROW) load_row(ra[u], m0 + row, q);
+      else load_q(ra[u], m0 + row, q);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + u * 256;
+      if constexpr (ROW) load_q(rb[u], n0 + e / KV, q0 + (e % KV) * 4);
+      else load_col(rb[u], q0 + e / 16, n0 + (e % 16) * 4);
     }
   };
   auto store_chunk = [&]() {
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + u * 256;
-      As[e % KC][e / KC] = ra[u];
-      if constexpr (ROW) Bs[e % KC][e / KC] = rb[u];
-      else Bs[e / FT_N][e % FT_N] = rb[u];
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + u * 256;
+      *reinterpret_cast<Vec<C, 4>*>(&As[e / KV][(e % KV) * 4]) = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + u * 256;
+      if constexpr (ROW) *reinterpret_cast<Vec<C, 4>*>(&Bs[e / KV][(e % KV) * 4]) = rb[u];
+      else *reinterpret_cast<Vec<C, 4>*>(&Bs[e / 16][(e % 16) * 4]) = rb[u];
     }
   };
+  const int lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int wm = (w >> 1) * (BM / 2), wn = (w & 1) * 32;
+  constexpr int NKB = KC / 16;  // 16-wide k blocks per chunk
+  Acc acc[MI][2];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = Acc{};
+  auto products = [&](const Vec<C, 4> (&av)[MI], const Vec<C, 4> (&bv)[2]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = Mfma<C>::op(av[mi].v[j], bv[ni].v[j], acc[mi][ni]);
+  };
+  // Pipeline per chunk: read all of its operands from LDS into registers, barrier, then the
+  // products of the first k block, the LDS store of the next chunk (loaded one chunk earlier)
+  // and the global loads of the one after, and the remaining products, so that matrix-core
+  // work overlaps the memory traffic.  Tiles are zero past n, so every k block is multiplied.
   load_chunk(0);
+  store_chunk();
+  __syncthreads();
+  if (KC < n) load_chunk(KC);
   for (int q0 = 0; q0 < n; q0 += KC) {
-    store_chunk();
-    __syncthreads();
-    if (q0 + KC < n) load_chunk(q0 + KC);  // in flight during the multiply below
-    // k in steps of 4 (the tiles are zero past n, and KC is a multiple of 4); each thread reads
-    // its 4 rows and 4 columns of a k-slice as one 4-wide LDS vector each
-    const int kend = min(KC, (n - q0 + 3) & ~3);
-    for (int k0 = 0; k0 < kend; k0 += 4) {
-      Vec<C, 4> av[4], bv[4];
+    Vec<C, 4> av[NKB][MI], bv[NKB][2];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        av[kk] = *reinterpret_cast<const Vec<C, 4>*>(&As[k0 + kk][ty * 4]);
-        bv[kk] = *reinterpret_cast<const Vec<C, 4>*>(&Bs[k0 + kk][tx * 4]);
-      }
+    for (int kb = 0; kb < NKB; ++kb) {
+      const int k = kb * 16 + 4 * g4;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
+      for (int i = 0; i < MI; ++i) av[kb][i] = *reinterpret_cast<const Vec<C, 4>*>(&As[wm + 16 * i + l16][k]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i) {
+        if constexpr (ROW) {
+          bv[kb][i] = *reinterpret_cast<const Vec<C, 4>*>(&Bs[wn + 16 * i + l16][k]);
+        } else {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] += av[kk].v[i] * bv[kk].v[j];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int mi = m0 + ty * 4 + i;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int nj = n0 + tx * 4 + j;
-      if constexpr (ROW) {
-        if (mi < g.nr && nj < n) out[(size_t)mi * n + nj] = (TO)acc[i][j];
-      } else {
-        if (mi < n && nj < g.nc) {
-          C v = acc[i][j];
-          if (sc.on) {
-            const int ix = nj % sc.nx, jy = nj / sc.nx;
-            v = (C)((double)v / (1.0 - sc.sk * (sc.lx[ix] + sc.ly[jy] + sc.lz[mi])));
-          }
-          out[(size_t)b * g.bstride + (size_t)mi * g.ld + nj] = (TO)v;
+          for (int j = 0; j < 4; ++j) bv[kb][i].v[j] = Bs[k + j][wn + 16 * i + l16];
         }
       }
     }
+    __syncthreads();  // every wave holds this chunk: the LDS tiles may be overwritten
+    products(av[0], bv[0]);
+    if (q0 + KC < n) {
+      store_chunk();
+      if (q0 + 2 * KC < n) load_chunk(q0 + 2 * KC);
+    }
+#pragma unroll
+    for (int kb = 1; kb < NKB; ++kb) products(av[kb], bv[kb]);
+    __syncthreads();  // the next chunk is in LDS
   }
+  // P_D^-1 factors of this lane's rows and columns, loaded together (indices clamped in range)
+  double sxy[2] = {0.0, 0.0}, sz[MI][4] = {};
+  if constexpr (!ROW) {
+    if (sc.on) {
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        const int col = min(n0 + wn + 16 * ni + l16, g.nc - 1);
+        sxy[ni] = sc.lx[col % sc.nx] + sc.ly[col / sc.nx];
+      }
+#pragma unroll
+      for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sz[mi][i] = sc.lz[min(m0 + wm + 16 * mi + Mfma<C>::row(g4, i), n - 1)];
+    }
+  }
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = m0 + wm + 16 * mi + Mfma<C>::row(g4, i);
+        const int col = n0 + wn + 16 * ni + l16;
+        C v = acc[mi][ni][i];
+        if constexpr (ROW) {
+          if (m < g.nr && col < n) out[(size_t)m * n + col] = (TO)v;
+        } else {
+          if (sc.on) v = (C)((double)v / (1.0 - sc.sk * (sxy[ni] + sz[mi][i])));
+          if (m < n && col < g.nc) out[(size_t)b * g.bstride + (size_t)m * g.ld + col] = (TO)v;
+        }
+      }
 }
 
 // Host-side description of one axis: orthogonal symmetric eigenbasis Q (n x n, row-major) and

@@ -509,6 +509,9 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   o_keps = need_keps ? take(v64 * nstages) : 0;
   o_scr = take(v64);  // scratch FP64 vector (solve output of k, verification)
   fdm = p.precond == MPRK_PRECOND_FDM;
+  // the fast-diagonalisation inverse is exact for the operators it accepts: one Krylov iteration
+  // per pass, so no predicted iteration beyond the last solve's count
+  predict_margin = fdm ? 0 : 1;
   if (p.krylov == MPRK_CG) {
     o_r = take(vlp);
     o_z = (bs || fdm) ? take(vlp) : o_r;
@@ -551,7 +554,7 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
     const size_t cb = p.compute == MPRK_FP64 ? 8 : 4;
     const int n3[3] = {g.nx, g.ny, g.nz};
     for (int d = 0; d < 3; ++d) {
-      o_fdm_Q[d] = take((size_t)n3[d] * n3[d] * cb);
+      o_fdm_Q[d] = take((size_t)n3[d] * fdm_ldq(n3[d]) * cb);  // rows padded to fdm_ldq
       o_fdm_lam[d] = take((size_t)n3[d] * 8);
     }
     o_fdm_t[0] = take((size_t)N * cb);
@@ -703,10 +706,14 @@ extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev,
       const int n = n3[d];
       std::vector<double> Q((size_t)n * n), lam(n);
       fdm_axis_basis(n, h->grid.bc == MPRK_BC_PERIODIC, Q.data(), lam.data());
+      const int ldq = fdm_ldq(n);  // rows padded with zeros
+      std::vector<double> Qp((size_t)n * ldq, 0.0);
+      for (int a = 0; a < n; ++a)
+        for (int q = 0; q < n; ++q) Qp[(size_t)a * ldq + q] = Q[(size_t)a * n + q];
       if (f64) {
-        HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_Q[d], Q.data(), Q.size() * 8, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_Q[d], Qp.data(), Qp.size() * 8, hipMemcpyHostToDevice, h->stream));
       } else {
-        std::vector<float> Qf(Q.begin(), Q.end());
+        std::vector<float> Qf(Qp.begin(), Qp.end());
         HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_Q[d], Qf.data(), Qf.size() * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));  // Qf goes out of scope
       }

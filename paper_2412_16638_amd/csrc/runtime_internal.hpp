@@ -89,7 +89,7 @@ struct mprk_handle {
   int cg_chunk = 4;
   int gm_chunk = 2;
   int lookahead = 1;
-  int predict_margin = 1;
+  int predict_margin = 1;  // iterations enqueued beyond the last solve's count (0 with FDM)
   // per-stage history of the last completed solve (slot s = mprk_solve), used to enqueue each
   // pass's Krylov iterations without waiting for the device
   struct StageHist {
