@@ -86,7 +86,9 @@ def make_problem(name: str, precond: str = 'bj'):
 
 
 # MI355X vector peaks (TFLOP/s) for the compute-bound contraction kernels
-ALU_PEAK = {'fp64': 78.6, 'fp32': 157.3, 'fp16': 157.3}
+# dense matrix-core peaks of the FDM contractions' arithmetic (FP64 MFMA for FP64 storage, FP32
+# MFMA otherwise), TFLOP/s
+MFMA_PEAK = {'fp64': 78.6, 'fp32': 157.3, 'fp16': 157.3}
 
 
 def oracle_reference(p):
@@ -98,32 +100,40 @@ def oracle_reference(p):
     return ref, time.perf_counter() - t0
 
 
-def cpu_oracle_rate(workload: str):
+def cpu_oracle_rate(workload: str, precond: str = 'bj'):
     """The oracle stepping the method on the host: FP64 DIRK with its own Krylov stage solver
-    (GMRES(30) or CG + block-Jacobi(8), rtol 1e-10), one thread, one step (setup excluded).  The
-    sample is the workload's PDE on a smaller grid (128^3 for the 256^3 advection-diffusion run,
-    96^3 for the 128^3 heat run), sized to 10-30 s of CPU work."""
+    (GMRES(30) or CG + block-Jacobi(8), rtol 1e-10), one thread, setup excluded.  The sample is
+    one step of the workload's PDE on a smaller grid (128^3 for the 256^3 advection-diffusion
+    run, 96^3 for the 128^3 heat run), sized to 10-30 s of CPU work.  With the fast-
+    diagonalisation preconditioner the oracle's CG uses its FDM inverse, and the sample is two
+    steps of the 128^3 heat workload itself."""
     from threadpoolctl import threadpool_limits
     import workloads as W
     from oracle import dirk, operators, tableaus
-    p = W.advdiff_bump(n=128) if workload == 'advdiff256' else W.heat_modes(n=96)
+    fdm = precond == 'fdm'
+    p = (W.advdiff_bump(n=128) if workload == 'advdiff256'
+         else W.heat_modes(n=128 if fdm else 96))
     K = operators.operator((p.n,) * 3, p.bc, p.kind, p.diff, p.b)
     tab = tableaus.by_name(p.tableau)
     solve = dirk.StageSolver(K, 'gmres' if p.krylov == 'gmres' else 'cg', rtol=1e-10, block=8,
-                             restart=30)
+                             restart=30,
+                             fdm_problem=((p.n,) * 3, p.bc, p.kind, p.diff, p.b) if fdm else None)
+    steps = 2 if fdm else 1
     u = np.asarray(p.u0, dtype=np.float64).ravel().copy()
     with threadpool_limits(limits=1):
         for i in range(tab.s):
             if tab.A[i, i] != 0.0:
                 solve._factor(p.dt * tab.A[i, i])
         t0 = time.perf_counter()
-        dirk.dirk_step(K, u, p.dt, tab, solve)
+        for _ in range(steps):
+            u = dirk.dirk_step(K, u, p.dt, tab, solve)
         t = time.perf_counter() - t0
-    sample = (f'one {p.tableau} step of the {"advection-diffusion" if p.kind else "heat"} problem '
+    sample = (f'{"two" if steps == 2 else "one"} {p.tableau} step{"s" if steps > 1 else ""} of the '
+              f'{"advection-diffusion" if p.kind else "heat"} problem '
               f'on a {p.n}^3 grid ({p.N} unknowns), FP64 oracle DIRK with its '
-              f'{p.krylov.upper()} + block-Jacobi(8) stage solver to rtol 1e-10 '
+              f'{p.krylov.upper()} + {"FDM" if fdm else "block-Jacobi(8)"} stage solver to rtol 1e-10 '
               f'({sum(solve.iterations)} iterations), one thread, setup excluded; {t:.1f} s')
-    return p.N / t, sample, t
+    return p.N * steps / t, sample, t
 
 
 def run_integration(M, p, fmt, **over):
@@ -313,8 +323,8 @@ def main():
         # the contractions are dense: 2 n flops per unknown per launch (n = axis length)
         flops_per_launch = 2.0 * r['units'] * N / r['launches']
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-        peak = ALU_PEAK[p.precision]
-        roofline = {'bound': 'alu', 'kernel': kc, 'achieved': round(achieved, 2), 'peak': peak,
+        peak = MFMA_PEAK[p.precision]
+        roofline = {'bound': 'mfma', 'kernel': kc, 'achieved': round(achieved, 2), 'peak': peak,
                     'unit': 'TFLOP/s', 'frac': round(achieved / peak, 4), 'traffic': None,
                     'flops_per_launch': flops_per_launch, 'avg_launch_us': round(avg_ms * 1e3, 2),
                     'launches': r['launches'], 'worked': r['worked']}
@@ -382,7 +392,7 @@ def main():
     cpu = None
     if t_oracle is not None:
         log('cpu baseline: the oracle stepping the method on the host ...')
-        v_cpu, sample, t_cpu = cpu_oracle_rate(args.workload)
+        v_cpu, sample, t_cpu = cpu_oracle_rate(args.workload, args.precond)
         log(f'cpu baseline: {v_cpu:.4e} DOF-steps/s ({t_cpu:.1f} s)')
         cpu = {'value': v_cpu, 'unit': 'DOF-steps/s', 'cores': 1, 'kind': 'oracle',
                'host': host_info(), 'sample': sample,

@@ -12,7 +12,7 @@ oracle applies the full A.
 
 Stage solvers: 'dense' (LU of the dense stage matrix, N <= ~4096), 'splu'
 (sparse LU), 'cg' / 'gmres' (the oracle's own FP64 Krylov to rtol 1e-13,
-block-Jacobi preconditioned).
+block-Jacobi preconditioned, or by the fast-diagonalisation inverse of eq. Pinvform).
 Pins: closed-form modal evolution R(tau lambda)^N, dt-halving order, agreement
 between the three solvers (tests/test_oracle_dirk.py).
 """
@@ -23,20 +23,24 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import krylov
+from . import fdm, krylov
 from .operators import stage_matrix
 
 
 class StageSolver:
-    """Solves (I - sigma K) y = rhs; factorizations are cached per sigma."""
+    """Solves (I - sigma K) y = rhs; factorizations are cached per sigma.
+
+    Krylov methods take block-Jacobi(block) as preconditioner, or with fdm_problem =
+    (shape, bc, kind, diff, b) of K the fast-diagonalisation inverse of eq. Pinvform."""
 
     def __init__(self, K: sp.csr_matrix, method: str = 'splu', rtol: float = 1e-13,
-                 block: int = 8, restart: int = 30):
+                 block: int = 8, restart: int = 30, fdm_problem=None):
         self.K = K.tocsr()
         self.method = method
         self.rtol = rtol
         self.block = block
         self.restart = restart
+        self.fdm_problem = fdm_problem
         self._cache = {}
         self.iterations = []
 
@@ -48,6 +52,8 @@ class StageSolver:
             f = ('dense', sla.lu_factor(M.toarray()))
         elif self.method == 'splu':
             f = ('splu', spla.splu(M.tocsc()))
+        elif self.fdm_problem is not None:
+            f = (self.method, (M, fdm.FDM(*self.fdm_problem, sigma)))
         else:
             inv = krylov.block_jacobi_inverses(M, self.block)
             f = (self.method, (M, inv))
@@ -61,7 +67,10 @@ class StageSolver:
         if kind == 'splu':
             return f.solve(rhs)
         M, inv = f
-        prec = lambda r: krylov.block_jacobi_apply(inv, r, self.block)
+        if self.fdm_problem is not None:
+            prec = inv.apply
+        else:
+            prec = lambda r: krylov.block_jacobi_apply(inv, r, self.block)
         if kind == 'cg':
             y, it, _ = krylov.cg(M, rhs, prec, rtol=self.rtol, x0=rhs.copy())
         else:

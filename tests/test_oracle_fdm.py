@@ -60,3 +60,18 @@ def test_heat_factor_has_the_analytic_dirichlet_spectrum():
     mu = (4.0 / h ** 2) * np.sin(np.arange(1, n + 1) * np.pi * h / 2.0) ** 2
     assert np.allclose(np.sort(np.linalg.eigvalsh(A)), np.sort(1.0 + sigma * kappa * mu), rtol=1e-13)
     assert np.allclose(np.sort(np.linalg.eigvalsh(B)), np.sort(sigma * kappa * mu), rtol=1e-12)
+
+
+def test_fdm_preconditioned_cg_stage_solve_is_one_iteration_and_matches_splu():
+    """CG with the exact inverse as preconditioner reaches the sparse-LU stage solution in one
+    iteration (the preconditioned operator is the identity)."""
+    from oracle import dirk
+    shape, kappa, sigma = (10, 8, 7), 1.3, 4e-3
+    K = operators.operator(shape, operators.DIRICHLET, 0, kappa, (0, 0, 0))
+    rhs = np.random.default_rng(6).standard_normal(K.shape[0])
+    s_fdm = dirk.StageSolver(K, 'cg', rtol=1e-12,
+                             fdm_problem=(shape, operators.DIRICHLET, 0, kappa, (0, 0, 0)))
+    y = s_fdm(sigma, rhs)
+    ref = dirk.StageSolver(K, 'splu')(sigma, rhs)
+    assert s_fdm.iterations == [1]
+    assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
