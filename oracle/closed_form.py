@@ -13,7 +13,13 @@ precision".  Hence u_N = Q diag(R(tau lambda)^N) Q^{-1} u_0 exactly, at any size
   * Periodic advection-diffusion: the DFT diagonalises K, with, per axis,
     nu (2 cos theta - 2)/h^2 - b (1 - e^{-i theta})/h for b >= 0 (backward
     upwind difference) and - b (e^{i theta} - 1)/h for b < 0, theta = 2 pi m / n
-    (numpy's FFT sign convention).
+    (numpy's FFT sign convention); with central differences - i b sin(theta) / h.
+  * Constant forcing g along the lowest Dirichlet sine mode (the paper's forced heat test,
+    Section "Heat equation", u(0) = 0): the solution stays a(t) g.  For a' = lambda a + 1
+    one DIRK step with exact stage solves has stage values Y = (I - zA)^{-1}(a e + tau A e),
+    z = tau lambda, so a_{n+1} = a_n + tau b^T (lambda Y + e) = R(z) a_n + tau b^T (I - zA)^{-1} e
+    (using z (I - zA)^{-1} A e + e = (I - zA)^{-1} e); the semi-discrete exact amplitude is
+    (e^{lambda t} - 1) / lambda, and the continuum one (1 - e^{-3 pi^2 kappa t}) / (3 pi^2 kappa).
 The continuum decay of the lowest heat mode is exp(-3 pi^2 kappa t) (Section
 "Heat equation": the analytic solution decays at rate 3 pi^2).
 Fields are arrays of shape (nz, ny, nx) (x fastest when flattened).
@@ -51,14 +57,16 @@ def heat_sine_mode(shape, kvec) -> np.ndarray:
     return fz[:, None, None] * fy[None, :, None] * fx[None, None, :]
 
 
-def periodic_eigenvalues(shape, nu: float, b) -> np.ndarray:
-    """DFT symbol of nu Lap_h - sum_d b_d D_d^upwind, as an array (nz, ny, nx)."""
+def periodic_eigenvalues(shape, nu: float, b, central: bool = False) -> np.ndarray:
+    """DFT symbol of nu Lap_h - sum_d b_d D_d (upwind, or central), as an array (nz, ny, nx)."""
     parts = []
     for d, n in enumerate(shape):
         h = _spacing(n, True)
         theta = 2.0 * np.pi * np.arange(n) / n
         lam = nu * (2.0 * np.cos(theta) - 2.0) / h ** 2
-        if b[d] >= 0.0:
+        if central:
+            lam = lam - 1j * b[d] * np.sin(theta) / h
+        elif b[d] >= 0.0:
             lam = lam - b[d] * (1.0 - np.exp(-1j * theta)) / h
         else:
             lam = lam - b[d] * (np.exp(1j * theta) - 1.0) / h
@@ -84,18 +92,20 @@ def evolve_heat_exact(u0: np.ndarray, kappa: float, t: float) -> np.ndarray:
     return sfft.idstn(c * np.exp(t * lam), type=1)
 
 
-def evolve_periodic(u0: np.ndarray, nu: float, b, tau: float, nsteps: int, tab) -> np.ndarray:
+def evolve_periodic(u0: np.ndarray, nu: float, b, tau: float, nsteps: int, tab,
+                    central: bool = False) -> np.ndarray:
     """u_N of the DIRK with exact solves for periodic advection-diffusion, via FFT."""
     nz, ny, nx = u0.shape
-    lam = periodic_eigenvalues((nx, ny, nz), nu, b)
+    lam = periodic_eigenvalues((nx, ny, nz), nu, b, central)
     amp = stability_function(tab, tau * lam) ** nsteps
     return np.real(sfft.ifftn(sfft.fftn(u0) * amp))
 
 
-def evolve_periodic_exact(u0: np.ndarray, nu: float, b, t: float) -> np.ndarray:
+def evolve_periodic_exact(u0: np.ndarray, nu: float, b, t: float,
+                          central: bool = False) -> np.ndarray:
     """Semi-discrete exact solution exp(t K) u0 for periodic advection-diffusion."""
     nz, ny, nx = u0.shape
-    lam = periodic_eigenvalues((nx, ny, nz), nu, b)
+    lam = periodic_eigenvalues((nx, ny, nz), nu, b, central)
     return np.real(sfft.ifftn(sfft.fftn(u0) * np.exp(t * lam)))
 
 
@@ -105,5 +115,52 @@ def evolve(u0: np.ndarray, kind: int, bc: int, diff: float, b, tau: float, nstep
         return evolve_heat(u0, diff, tau, nsteps, tab)
     if bc == 1:
         bb = (0.0, 0.0, 0.0) if kind == 0 else b
-        return evolve_periodic(u0, diff, bb, tau, nsteps, tab)
+        return evolve_periodic(u0, diff, bb, tau, nsteps, tab, central=kind == 2)
     raise ValueError('no closed form for Dirichlet advection-diffusion')
+
+
+def stage_sum(tab, z):
+    """b^T (I - z A)^{-1} e for an array of complex z (forward substitution per stage)."""
+    z = np.asarray(z, dtype=np.complex128)
+    A, b = tab.A, tab.b
+    X = []
+    for i in range(tab.s):
+        acc = np.ones_like(z)
+        for j in range(i):
+            acc = acc + z * A[i, j] * X[j]
+        X.append(acc / (1.0 - z * A[i, i]))
+    return sum(b[i] * X[i] for i in range(tab.s))
+
+
+def forced_mode_amplitude(tab, lam: float, tau: float, nsteps: int) -> float:
+    """a_N of the DIRK for a' = lambda a + 1, a_0 = 0 (exact stage solves)."""
+    z = tau * lam
+    R = complex(stability_function(tab, z))
+    beta = complex(stage_sum(tab, z))
+    a = 0.0
+    for _ in range(nsteps):
+        a = (R * a + tau * beta).real
+    return a
+
+
+def forced_heat_lowest_eigenvalue(shape, kappa: float) -> float:
+    """lambda of the (1, 1, 1) sine mode of kappa Lap_h (zero Dirichlet)."""
+    return float(heat_eigenvalues(shape, kappa)[0, 0, 0])
+
+
+def evolve_forced_heat(g: np.ndarray, kappa: float, tau: float, nsteps: int, tab) -> np.ndarray:
+    """u_N of the DIRK for du/dt = K u + g, u_0 = 0, g the lowest sine mode (array (nz,ny,nx))."""
+    nz, ny, nx = g.shape
+    lam = forced_heat_lowest_eigenvalue((nx, ny, nz), kappa)
+    return forced_mode_amplitude(tab, lam, tau, nsteps) * g
+
+
+def forced_heat_exact(g: np.ndarray, kappa: float, t: float, continuum: bool = False) -> np.ndarray:
+    """Exact solution at t: semi-discrete (e^{lambda t} - 1)/lambda g, or the continuum
+    (1 - e^{-3 pi^2 kappa t}) / (3 pi^2 kappa) g."""
+    if continuum:
+        c = 3.0 * np.pi ** 2 * kappa
+        return (1.0 - np.exp(-c * t)) / c * g
+    nz, ny, nx = g.shape
+    lam = forced_heat_lowest_eigenvalue((nx, ny, nz), kappa)
+    return (np.exp(lam * t) - 1.0) / lam * g

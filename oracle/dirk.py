@@ -80,8 +80,11 @@ class StageSolver:
         return y
 
 
-def dirk_step(K, u: np.ndarray, tau: float, tab, solve, stage_hook=None) -> np.ndarray:
-    """One step of eq. (RKstep) for du/dt = K u with the full tableau A.
+def dirk_step(K, u: np.ndarray, tau: float, tab, solve, stage_hook=None, g=None) -> np.ndarray:
+    """One step of eq. (RKstep) for du/dt = K u (+ g, a constant forcing) with the full tableau A.
+
+    With forcing, f(y) = K y + g: stage i solves (I - tau a_ii K) y_i = rhs_i + tau a_ii g
+    and k_i = K y_i + g.
 
     stage_hook(i, y) -> y, if given, replaces each implicit stage solution (used
     to model an inexact low-precision solve, e.g. for the corrector-divergence
@@ -94,12 +97,12 @@ def dirk_step(K, u: np.ndarray, tau: float, tab, solve, stage_hook=None) -> np.n
             if A[i, j] != 0.0:
                 rhs += tau * A[i, j] * ks[j]
         if A[i, i] != 0.0:
-            y = solve(tau * A[i, i], rhs)
+            y = solve(tau * A[i, i], rhs if g is None else rhs + tau * A[i, i] * g)
             if stage_hook is not None:
                 y = stage_hook(i, y)
         else:
             y = rhs
-        ks.append(K @ y)
+        ks.append(K @ y if g is None else K @ y + g)
     out = u.copy()
     for i in range(tab.s):
         if b[i] != 0.0:
@@ -108,12 +111,13 @@ def dirk_step(K, u: np.ndarray, tau: float, tab, solve, stage_hook=None) -> np.n
 
 
 def integrate(K, u0: np.ndarray, tau: float, nsteps: int, tab, method: str = 'splu',
-              **solver_kw) -> np.ndarray:
-    """nsteps DIRK steps from u0 (a flat lexicographic vector)."""
+              g=None, **solver_kw) -> np.ndarray:
+    """nsteps DIRK steps from u0 (a flat lexicographic vector), forcing g (flat) if given."""
     solve = StageSolver(K, method, **solver_kw)
     u = np.asarray(u0, dtype=np.float64).ravel().copy()
+    gf = None if g is None else np.asarray(g, dtype=np.float64).ravel()
     for _ in range(nsteps):
-        u = dirk_step(K, u, tau, tab, solve)
+        u = dirk_step(K, u, tau, tab, solve, g=gf)
     return u
 
 

@@ -5,6 +5,10 @@ with zero Dirichlet boundaries (Section "Heat equation").  Here K = kappa * Lap_
 Advection-diffusion: K = nu * Lap_h - sum_d b_d D_d with D_d the first-order
 upwind difference along axis d (backward when b_d >= 0, forward when b_d < 0)
 and periodic wrap (the paper's advection boundary, Section "Advection equation").
+Central advection(-diffusion), kind 2: D_d the second-order central difference
+(u_{i+1} - u_{i-1}) / (2h), the paper's discretisation of its advection test (Section
+"Test cases": second-order central stencils; the 1-D factor Tridiag(-1, 0, 1) / (2h) with
+periodic corners of Section "Advection equation").
 
 Grid spacing (reading of the paper's h = 1/(n-1), which counts boundary
 nodes): Dirichlet uses n interior nodes and h = 1/(n+1); periodic uses
@@ -69,6 +73,18 @@ def upwind_difference_1d(n: int, bc: int, direction_positive: bool) -> sp.csr_ma
     return D.tocsr()
 
 
+def central_difference_1d(n: int, bc: int) -> sp.csr_matrix:
+    """Unscaled 1-D central difference (u_{i+1} - u_{i-1}) / 2 (periodic wrap or zero ends)."""
+    D = sp.lil_matrix((n, n))
+    for i in range(n):
+        for j, w in ((i + 1, 0.5), (i - 1, -0.5)):
+            if 0 <= j < n:
+                D[i, j] += w
+            elif bc == PERIODIC:
+                D[i, j % n] += w
+    return D.tocsr()
+
+
 def kron_sum(Kx, Ky, Kz) -> sp.csr_matrix:
     """I (x) I (x) Kx + I (x) Ky (x) I + Kz (x) I (x) I for x-fastest ordering."""
     nx, ny, nz = Kx.shape[0], Ky.shape[0], Kz.shape[0]
@@ -92,15 +108,16 @@ def heat_operator(shape, bc: int, kappa: float) -> sp.csr_matrix:
     return K
 
 
-def advdiff_operator(shape, bc: int, nu: float, b) -> sp.csr_matrix:
-    """K = nu Lap_h - sum_d b_d D_d^upwind."""
+def advdiff_operator(shape, bc: int, nu: float, b, central: bool = False) -> sp.csr_matrix:
+    """K = nu Lap_h - sum_d b_d D_d, D_d upwind (or central)."""
     nx, ny, nz = shape
     Z = [sp.csr_matrix((n, n)) for n in (nx, ny, nz)]
     K = nu * laplacian(shape, bc)
     for d, n in enumerate((nx, ny, nz)):
         if b[d] == 0.0:
             continue
-        D1 = upwind_difference_1d(n, bc, b[d] >= 0.0) / spacing(n, bc)
+        D1 = (central_difference_1d(n, bc) if central
+              else upwind_difference_1d(n, bc, b[d] >= 0.0)) / spacing(n, bc)
         facs = list(Z)
         facs[d] = D1
         # kron_sum with only axis d non-zero
@@ -112,10 +129,11 @@ def advdiff_operator(shape, bc: int, nu: float, b) -> sp.csr_matrix:
 
 
 def operator(shape, bc: int, kind: int, diff: float, b=(0.0, 0.0, 0.0)) -> sp.csr_matrix:
-    """Dispatch: kind 0 = heat (kappa = diff), kind 1 = advection-diffusion (nu = diff)."""
+    """Dispatch: kind 0 = heat (kappa = diff), kind 1 = upwind advection-diffusion, kind 2 =
+    central advection-diffusion (nu = diff)."""
     if kind == 0:
         return heat_operator(shape, bc, diff)
-    return advdiff_operator(shape, bc, diff, b)
+    return advdiff_operator(shape, bc, diff, b, central=kind == 2)
 
 
 def stage_matrix(K: sp.csr_matrix, sigma: float) -> sp.csr_matrix:

@@ -24,6 +24,7 @@ PERIODIC = 1
 
 HEAT = 0
 ADVDIFF = 1
+CENTRAL = 2   # advection(-diffusion) with central differences (the paper's advection test)
 
 
 def axis_nodes(n: int, bc: int) -> np.ndarray:
@@ -72,7 +73,7 @@ class Problem:
     name: str
     n: int
     bc: int
-    kind: int                  # HEAT or ADVDIFF
+    kind: int                  # HEAT, ADVDIFF or CENTRAL
     diff: float                # kappa (heat) or nu (advection-diffusion)
     b: tuple                   # advection velocity (0,0,0) for heat
     tableau: str               # 'SDIRK2' | 'SDIRK3' | ...
@@ -81,8 +82,9 @@ class Problem:
     u0: np.ndarray             # shape (n, n, n), float64
     precision: str = 'fp64'    # 'fp64' | 'fp32' | 'fp16' (storage of the implicit solve)
     krylov: str = 'cg'         # 'cg' | 'gmres'
-    precond: str = 'bj'        # 'none' | 'bj'
+    precond: str = 'bj'        # 'none' | 'bj' | 'fdm'
     meta: dict = dataclasses.field(default_factory=dict)
+    forcing: np.ndarray = None # constant source g of du/dt = K u + g, shape (n, n, n), or None
 
     @property
     def N(self) -> int:
@@ -116,6 +118,40 @@ def advdiff_bump(n: int = 256, seed: int = 3, nsteps: int = 20, dt: float = 2e-3
     return Problem(f'advdiff_bump_{n}', n, PERIODIC, ADVDIFF, nu, tuple(b), 'SDIRK3',
                    dt, nsteps, u0, precision='fp16', krylov='gmres', precond='bj',
                    meta={'center': c, 'seed': seed})
+
+
+def paper_heat(n: int = 128, tableau: str = 'MID1', dt: float = 1.0 / 80, t_end: float = 0.1,
+               precision: str = 'fp32') -> Problem:
+    """The paper's heat test (Section "Heat equation"): du/dt = Lap u + g on the unit cube,
+    zero Dirichlet, g = sin(pi x) sin(pi y) sin(pi z) at the nodes, u(0) = 0, to t_end."""
+    g = sine_mode((n, n, n), (1, 1, 1), DIRICHLET)
+    return Problem(f'paper_heat_{n}', n, DIRICHLET, HEAT, 1.0, (0.0, 0.0, 0.0), tableau, dt,
+                   int(round(t_end / dt)), np.zeros((n, n, n)), precision=precision,
+                   krylov='cg', precond='bj', forcing=g)
+
+
+def paper_advection(n: int = 128, tableau: str = 'MID1', dt: float = 1.0 / 80,
+                    t_end: float = 0.1, precision: str = 'fp32') -> Problem:
+    """The paper's advection test (Section "Advection equation"): du/dt + div(beta u) = 0,
+    beta = (1, 1, 1), periodic, u(0) = exp(-100 |x - 1/2|^2) at the nodes, to t_end;
+    central differences."""
+    u0 = gaussian_bump(n, (0.5, 0.5, 0.5), 100.0, PERIODIC)
+    return Problem(f'paper_advection_{n}', n, PERIODIC, CENTRAL, 0.0, (1.0, 1.0, 1.0), tableau,
+                   dt, int(round(t_end / dt)), u0, precision=precision, krylov='gmres',
+                   precond='bj')
+
+
+def translated_gaussian(n: int, shift, width: float = 100.0) -> np.ndarray:
+    """exp(-width |x - 1/2 - shift|^2) at the periodic nodes with the nearest periodic image:
+    the exact solution of the constant-velocity advection test at time t (shift = beta t)."""
+    x = axis_nodes(n, PERIODIC)
+    parts = []
+    for d in range(3):
+        r = x - 0.5 - shift[d]
+        r = r - np.round(r)
+        parts.append(np.exp(-width * r ** 2))
+    gx, gy, gz = parts
+    return gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
 
 
 def random_field(n: int, seed: int) -> np.ndarray:
