@@ -52,7 +52,7 @@ enum mprk_status {
 };
 
 enum { MPRK_BC_DIRICHLET0 = 0, MPRK_BC_PERIODIC = 1 };
-enum { MPRK_OP_HEAT = 0, MPRK_OP_ADVDIFF = 1 };
+enum { MPRK_OP_HEAT = 0, MPRK_OP_ADVDIFF = 1, MPRK_OP_CENTRAL = 2 };
 enum { MPRK_FMT_STENCIL = 0, MPRK_FMT_CSR = 1 };
 enum { MPRK_FP64 = 0, MPRK_FP32 = 1, MPRK_FP16 = 2 };
 enum { MPRK_CG = 0, MPRK_GMRES = 1 };
@@ -73,6 +73,9 @@ typedef struct { int32_t nx, ny, nz, bc; } mprk_grid;
 /* Operator K.  kind = MPRK_OP_HEAT: K = diff * Lap_h (7-point, second-order central;
  * Section "Test cases").  kind = MPRK_OP_ADVDIFF: K = diff * Lap_h - sum_d b[d] D_d, D_d the
  * first-order upwind difference (backward for b[d] >= 0, forward for b[d] < 0).
+ * kind = MPRK_OP_CENTRAL: the same with D_d the second-order central difference
+ * (u_{i+1} - u_{i-1}) / (2h), the discretisation of the paper's advection test (Section
+ * "Advection equation"); nonsymmetric, so GMRES only.
  * format: MPRK_FMT_STENCIL (matrix-free) or MPRK_FMT_CSR (int32 row pointers and
  * column indices; FP64 values for the explicit parts, LP values for the solve). */
 typedef struct { int32_t kind, format; double diff; double b[3]; } mprk_operator;
@@ -172,6 +175,14 @@ int64_t mprk_workspace_bytes(const mprk_handle *h);
  * Synchronises the stream before returning.  Errors: MPRK_EINVAL, MPRK_ENOMEM (bytes too
  * small), MPRK_EDEVICE. */
 int32_t mprk_bind(mprk_handle *h, double *u_dev, void *workspace_dev, int64_t bytes);
+
+/* Constant forcing: from the next step on, integrate du/dt = K u + g instead of du/dt = K u
+ * (the paper's heat test has g = sin(pi x) sin(pi y) sin(pi z), Section "Heat equation").
+ * g_dev: N doubles of caller-owned device memory, read by the FP64 explicit parts (k_i =
+ * K y_i + g, so the stage systems solve (I - dt a_ii K) y = rhs + dt a_ii g); it must stay
+ * valid and unchanged while steps or solves run.  NULL removes the forcing.  mprk_apply is
+ * unaffected (it applies the operators alone).  Errors: MPRK_EINVAL (null handle). */
+int32_t mprk_set_forcing(mprk_handle *h, const double *g_dev);
 
 /* Advance u by nsteps time steps.  The calling thread steers the Krylov loops by polling
  * small device-side status records; all arithmetic runs in the library's kernels on the

@@ -18,7 +18,7 @@ MAX_RESTART = 32
 # status codes
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ENOTCONV, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 BC_DIRICHLET0, BC_PERIODIC = 0, 1
-OP_HEAT, OP_ADVDIFF = 0, 1
+OP_HEAT, OP_ADVDIFF, OP_CENTRAL = 0, 1, 2
 FMT_STENCIL, FMT_CSR = 0, 1
 FP64, FP32, FP16 = 0, 1, 2
 CG, GMRES = 0, 1
@@ -107,6 +107,7 @@ _sig = {
     'mprk_step': (C.c_int32, [_P, C.c_int32, C.POINTER(mprk_stats)]),
     'mprk_solve': (C.c_int32, [_P, C.c_int32, _P, _P, C.POINTER(mprk_solve_info)]),
     'mprk_apply': (C.c_int32, [_P, C.c_int32, C.c_int32, _P, _P]),
+    'mprk_set_forcing': (C.c_int32, [_P, _P]),
     'mprk_get_state': (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     'mprk_set_state': (C.c_int32, [_P, C.c_double, C.c_int64]),
     'mprk_stats_sync': (C.c_int32, [_P, C.POINTER(mprk_stats)]),
@@ -192,6 +193,10 @@ def mprk_solve(h: int, stage: int, rhs_ptr: int, x_ptr: int):
     rc = lib.mprk_solve(_P(h), stage, _P(rhs_ptr), _P(x_ptr), C.byref(info))
     return rc, {'iters': info.iters, 'passes': info.passes, 'converged': info.converged,
                 'resid': info.resid}
+
+
+def mprk_set_forcing(h: int, g_ptr: int) -> None:
+    check(lib.mprk_set_forcing(_P(h), _P(g_ptr) if g_ptr else None), 'mprk_set_forcing')
 
 
 def mprk_apply(h: int, op: int, stage: int, x_ptr: int, y_ptr: int) -> None:

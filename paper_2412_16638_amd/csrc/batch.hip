@@ -537,7 +537,11 @@ extern "C" int32_t mprk_batch_create(int32_t count, const mprk_problem* problems
       delete b;
       return set_error(MPRK_EUNSUPPORTED, "batched form uses the matrix-free stencil");
     }
-    if (q.op.kind == MPRK_OP_ADVDIFF && (q.op.b[0] != 0.0 || q.op.b[1] != 0.0 || q.op.b[2] != 0.0)) {
+    if (q.op.kind != MPRK_OP_HEAT && q.op.kind != MPRK_OP_ADVDIFF && q.op.kind != MPRK_OP_CENTRAL) {
+      delete b;
+      return set_error(MPRK_EINVAL, "bad operator kind");
+    }
+    if (q.op.kind != MPRK_OP_HEAT && (q.op.b[0] != 0.0 || q.op.b[1] != 0.0 || q.op.b[2] != 0.0)) {
       delete b;
       return set_error(MPRK_EINVAL, "CG needs a symmetric operator");
     }

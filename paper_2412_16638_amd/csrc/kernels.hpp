@@ -4,7 +4,7 @@
 // work and implicit low-precision (LP) solves (Section "Implementation of the
 // Mixed-precision Runge--Kutta methods"):
 //   k_stage_rhs  (FP64)  rhs = u + tau sum_{j<i}(a^h_ij k_j + a^eps_ij k^eps_j); y = rhs
-//   k_residual   (FP64)  k = K y ; res = rhs - y + sigma k ; ||res||, ||rhs|| ; outer decision
+//   k_residual   (FP64)  k = K y (+ g) ; res = rhs - y + sigma k ; ||res||, ||rhs|| ; outer decision
 //   k_cg_begin / k_gm_begin   res -> LP, scaled to unit RMS (FP16 range; Section "Method
 //                        stability in the context of mixed precision" on rescaling)
 //   k_cg_dir, k_cg_upd   fused preconditioned CG iteration (heat, SPD)
@@ -111,8 +111,9 @@ __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<doubl
                                                   const double* __restrict__ y,
                                                   const double* __restrict__ rhs,
                                                   double* __restrict__ kout,
-                                                  double* __restrict__ res, SolveCfg cfg, Ctl* ctl,
-                                                  Red red) {
+                                                  double* __restrict__ res,
+                                                  const double* __restrict__ force, SolveCfg cfg,
+                                                  Ctl* ctl, Red red) {
   if (ctl->outer_done) return;
   count_work(ctl, KC_RESIDUAL);
   const int L = xcd_block(ln.G);
@@ -124,6 +125,12 @@ __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<doubl
     double yc[VEC], ky[VEC], b[VEC], rr[VEC];
     k64_group<VEC, FMT>(geo, K, csr, kval, y, g, yc, ky);
     loadv<double, double, VEC>(rhs + e, b);
+    if (force) {  // constant forcing: f(y) = K y + g, so the stage solves y - sigma f(y) = rhs
+      double fv[VEC];
+      loadv<double, double, VEC>(force + e, fv);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) ky[v] += fv[v];
+    }
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       rr[v] = b[v] - yc[v] + cfg.sigma * ky[v];
@@ -166,13 +173,20 @@ template <int VEC, int FMT>
 __global__ __launch_bounds__(TPB) void k_apply64(Launch ln, Geo geo, Coef<double> K, Csr csr,
                                                  const double* __restrict__ kval,
                                                  const double* __restrict__ x,
-                                                 double* __restrict__ y, double sigma, int mode) {
+                                                 double* __restrict__ y, double sigma, int mode,
+                                                 const double* __restrict__ force) {
   const int L = xcd_block(ln.G);
   for (int it = 0; it < ln.nit; ++it) {
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;
     if (g >= ln.ng) break;
     double xc[VEC], kx[VEC];
     k64_group<VEC, FMT>(geo, K, csr, kval, x, g, xc, kx);
+    if (force) {  // mode 0 with forcing: y = K x + g (an explicit stage's slope)
+      double fv[VEC];
+      loadv<double, double, VEC>(force + g * VEC, fv);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) kx[v] += fv[v];
+    }
     if (mode == 1) {
 #pragma unroll
       for (int v = 0; v < VEC; ++v) kx[v] = xc[v] - sigma * kx[v];

@@ -75,11 +75,17 @@ Coef<double> operator_coef(const mprk_grid& g, const mprk_operator& op) {
   double km[3], kp[3], kc = 0.0;
   for (int d = 0; d < 3; ++d) {
     const double h = g.bc == MPRK_BC_DIRICHLET0 ? 1.0 / (n[d] + 1) : 1.0 / n[d];
-    const double b = op.kind == MPRK_OP_ADVDIFF ? op.b[d] : 0.0;
+    const double b = op.kind == MPRK_OP_HEAT ? 0.0 : op.b[d];
     const double dif = op.diff / (h * h);
-    km[d] = dif + (b >= 0.0 ? b / h : 0.0);
-    kp[d] = dif + (b < 0.0 ? -b / h : 0.0);
-    kc -= 2.0 * dif + std::fabs(b) / h;
+    if (op.kind == MPRK_OP_CENTRAL) {  // - b (u_{i+1} - u_{i-1}) / (2h)
+      km[d] = dif + b / (2.0 * h);
+      kp[d] = dif - b / (2.0 * h);
+      kc -= 2.0 * dif;
+    } else {                           // upwind: backward for b >= 0, forward for b < 0
+      km[d] = dif + (b >= 0.0 ? b / h : 0.0);
+      kp[d] = dif + (b < 0.0 ? -b / h : 0.0);
+      kc -= 2.0 * dif + std::fabs(b) / h;
+    }
   }
   return Coef<double>{kc, km[0], kp[0], km[1], kp[1], km[2], kp[2]};
 }
@@ -366,7 +372,8 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
   if (g->bc != MPRK_BC_DIRICHLET0 && g->bc != MPRK_BC_PERIODIC) return set_error(MPRK_EINVAL, "bad bc");
   const double N = (double)g->nx * g->ny * g->nz;
   if (N * 7.0 >= 2147483647.0) return set_error(MPRK_EINVAL, "grid too large for int32 indexing");
-  if (op->kind != MPRK_OP_HEAT && op->kind != MPRK_OP_ADVDIFF) return set_error(MPRK_EINVAL, "bad operator kind");
+  if (op->kind != MPRK_OP_HEAT && op->kind != MPRK_OP_ADVDIFF && op->kind != MPRK_OP_CENTRAL)
+    return set_error(MPRK_EINVAL, "bad operator kind");
   if (op->format != MPRK_FMT_STENCIL && op->format != MPRK_FMT_CSR) return set_error(MPRK_EINVAL, "bad format");
   if (!(op->diff >= 0.0) || !std::isfinite(op->diff)) return set_error(MPRK_EINVAL, "diffusion must be finite and >= 0");
   for (int d = 0; d < 3; ++d)
@@ -404,7 +411,7 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
   if (!(p->rtol >= 0.0) || !(p->atol >= 0.0) || !(p->outer_tol >= 0.0))
     return set_error(MPRK_EINVAL, "tolerances must be >= 0");
   if (p->maxit < 0 || p->refine_max < 0) return set_error(MPRK_EINVAL, "maxit and refine_max must be >= 0");
-  if (p->krylov == MPRK_CG && op->kind == MPRK_OP_ADVDIFF &&
+  if (p->krylov == MPRK_CG && op->kind != MPRK_OP_HEAT &&
       (op->b[0] != 0.0 || op->b[1] != 0.0 || op->b[2] != 0.0))
     return set_error(MPRK_EINVAL, "CG needs a symmetric operator; use GMRES for advection");
   if (p->reorth) return set_error(MPRK_EUNSUPPORTED, "CGS2 re-orthogonalisation is not implemented");
@@ -797,7 +804,8 @@ BJDesc mprk_handle::bj_desc(int si) const {
   return BJDesc{ws + B.o_inv, B.mode == 1 ? (const int*)(ws + B.o_idx) : nullptr, B.mode};
 }
 
-int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* kout) {
+int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* kout,
+                                 const double* force) {
   const SolveCfg& cfg = cfgs[si];
   Ctl* ctl = (Ctl*)(ws + o_ctl);
   const Red rd = red();
@@ -806,13 +814,13 @@ int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* k
   const double* kval = (const double*)(ws + o_kval);
   if (op.format == MPRK_FMT_CSR)
     PLAUNCH(KC_RESIDUAL, (k_residual<1, 1>), dim3(ln_row_red.G), dim3(TPB), 0, stream, ln_row_red, geo, Kc, csr,
-                       kval, y, rhs, kout, res, cfg, ctl, rd);
+                       kval, y, rhs, kout, res, force, cfg, ctl, rd);
   else if (vec == 4)
     PLAUNCH(KC_RESIDUAL, (k_residual<4, 0>), dim3(ln_vec_red.G), dim3(TPB), 0, stream, ln_vec_red, geo, Kc, csr,
-                       kval, y, rhs, kout, res, cfg, ctl, rd);
+                       kval, y, rhs, kout, res, force, cfg, ctl, rd);
   else
     PLAUNCH(KC_RESIDUAL, (k_residual<1, 0>), dim3(ln_vec_red.G), dim3(TPB), 0, stream, ln_vec_red, geo, Kc, csr,
-                       kval, y, rhs, kout, res, cfg, ctl, rd);
+                       kval, y, rhs, kout, res, force, cfg, ctl, rd);
   HIPCHK(hipGetLastError());
   return MPRK_OK;
 }
@@ -822,7 +830,8 @@ int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* k
 // enqueues its Krylov iterations (last count + margin) and its promotion without waiting: an
 // inner solve cut short only leaves a larger FP64 residual for the next pass.  The host waits
 // for the device only where the history says the stage may already be finished.
-int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, double* kout) {
+int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, double* kout,
+                           const double* force) {
   int rc = update_hist(slot);
   if (rc) return rc;
   const StageHist H = hist[slot];
@@ -836,7 +845,7 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
   const int maxp = cfg.maxit;
   const int chunk = cg ? cg_chunk : gm_chunk;
   for (int pass = 0; pass <= P; ++pass) {
-    rc = launch_residual(si, rhs, y, kout);
+    rc = launch_residual(si, rhs, y, kout, force);
     if (rc) return rc;
     if (pass == P) break;
     const bool certain = H.valid && pass < H.passes;
@@ -928,11 +937,11 @@ int mprk_handle::enqueue_step() {
       PLAUNCH(KC_STAGE_RHS, (k_stage_rhs<1>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, rhs, y, ctl, reset);
     HIPCHK(hipGetLastError());
     if (!implicit_[i]) {
-      int rc = launch_apply64(y, kvec(i), 0.0, 0);
+      int rc = launch_apply64(y, kvec(i), 0.0, 0, force);
       if (rc) return rc;
       continue;
     }
-    int rc = run_solve(sig_idx[i], i, rhs, y, kvec(i));
+    int rc = run_solve(sig_idx[i], i, rhs, y, kvec(i), force);
     if (rc) return rc;
     if (need_keps) {
       const double inv = 1.0 / cfgs[sig_idx[i]].sigma;
@@ -958,18 +967,19 @@ int mprk_handle::enqueue_step() {
   return MPRK_OK;
 }
 
-int mprk_handle::launch_apply64(const double* x, double* y, double sigma, int mode) {
+int mprk_handle::launch_apply64(const double* x, double* y, double sigma, int mode,
+                                const double* force) {
   const Csr csr{(const int*)(ws + o_rowptr), (const int*)(ws + o_col)};
   const double* kval = (const double*)(ws + o_kval);
   if (op.format == MPRK_FMT_CSR)
     PLAUNCH(KC_APPLY64, (k_apply64<1, 1>), dim3(ln_row.G), dim3(TPB), 0, stream, ln_row, geo, Kc, csr, kval,
-                       x, y, sigma, mode);
+                       x, y, sigma, mode, force);
   else if (vec == 4)
     PLAUNCH(KC_APPLY64, (k_apply64<4, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr, kval,
-                       x, y, sigma, mode);
+                       x, y, sigma, mode, force);
   else
     PLAUNCH(KC_APPLY64, (k_apply64<1, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr, kval,
-                       x, y, sigma, mode);
+                       x, y, sigma, mode, force);
   HIPCHK(hipGetLastError());
   return MPRK_OK;
 }
@@ -1053,7 +1063,8 @@ extern "C" int32_t mprk_solve(mprk_handle* h, int32_t stage, const double* rhs_d
     hipLaunchKernelGGL((k_stage_rhs<1>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, rhs_dev, a, rhs,
                        x_dev, ctl, 1);
   HIPCHK(hipGetLastError());
-  int rc = h->run_solve(h->sig_idx[stage], MPRK_MAX_STAGES, rhs, x_dev, (double*)(h->ws + h->o_scr));
+  int rc = h->run_solve(h->sig_idx[stage], MPRK_MAX_STAGES, rhs, x_dev, (double*)(h->ws + h->o_scr),
+                        nullptr);
   if (rc) return rc;
   CtlHead hd;
   HIPCHK(hipMemcpyAsync(&hd, ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, h->stream));
@@ -1065,6 +1076,12 @@ extern "C" int32_t mprk_solve(mprk_handle* h, int32_t stage, const double* rhs_d
     info->resid = hd.outer_rel;
   }
   if (hd.nonfinite) return set_error(MPRK_ENONFINITE, "non-finite residual in mprk_solve");
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_set_forcing(mprk_handle* h, const double* g_dev) {
+  if (!h) return set_error(MPRK_EINVAL, "handle is NULL");
+  h->force = g_dev;
   return MPRK_OK;
 }
 
@@ -1313,7 +1330,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
         hipLaunchKernelGGL((k_stage_rhs<1>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, y64, ca, rhs, x64, ctl, 1);
       hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.23, 0.017, x64);
       if (hipGetLastError() != hipSuccess) { rc = MPRK_EDEVICE; break; }
-      rc = h->launch_residual(si, rhs, x64, y64);
+      rc = h->launch_residual(si, rhs, x64, y64, nullptr);
       if (rc) break;
       if ((cg ? h->eng->cg_begin(c, cfg, dinv) : h->eng->gm_begin(c, cfg, dinv)) != hipSuccess) { rc = MPRK_EDEVICE; break; }
       if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = MPRK_EDEVICE; break; }

@@ -76,6 +76,7 @@ struct mprk_handle {
   bool fdm = false;  // fast-diagonalisation preconditioner
   size_t o_fdm_Q[3] = {}, o_fdm_lam[3] = {}, o_fdm_t[2] = {};
   size_t ws_bytes = 0;
+  const double* force = nullptr;  // constant forcing g (caller-owned, N doubles) or null
   // binding
   double* u = nullptr;
   char* ws = nullptr;
@@ -124,9 +125,9 @@ struct mprk_handle {
   int update_hist(int slot);
   mprk::BJDesc bj_desc(int si) const;
   mprk::Red red() const;
-  int launch_residual(int si, const double* rhs, double* y, double* kout);
-  int launch_apply64(const double* x, double* y, double sigma, int mode);
-  int run_solve(int si, int slot, const double* rhs, double* y, double* kout);
+  int launch_residual(int si, const double* rhs, double* y, double* kout, const double* force);
+  int launch_apply64(const double* x, double* y, double sigma, int mode, const double* force = nullptr);
+  int run_solve(int si, int slot, const double* rhs, double* y, double* kout, const double* force);
   int enqueue_step();
   int sync_counters();
   void fill_stats(mprk_stats* st);

@@ -78,6 +78,19 @@ class Stepper:
             out = self.u.detach().cpu().numpy()
         return out.reshape(self.shape[2], self.shape[1], self.shape[0])
 
+    def set_forcing(self, g) -> None:
+        """Constant forcing g of du/dt = K u + g (host or device field), or None to remove it.
+        The device copy is kept alive here while the handle uses it."""
+        if g is None:
+            A.mprk_set_forcing(self.h, 0)
+            self.g = None
+            return
+        if isinstance(g, np.ndarray):
+            g = torch.from_numpy(np.ascontiguousarray(g, dtype=np.float64).ravel())
+        self.g = g.reshape(-1).to(self.device, torch.float64).contiguous()
+        torch.cuda.synchronize(self.device)
+        A.mprk_set_forcing(self.h, self.g.data_ptr())
+
     def step(self, nsteps: int = 1, check: bool = True):
         rc, st = A.mprk_step(self.h, nsteps, True)
         if check:
@@ -125,6 +138,8 @@ def from_problem(p, fmt: int = A.FMT_STENCIL, prec=None, device: str = 'cuda:0',
     s = Stepper(p.n, p.bc, p.kind, p.diff, p.b, fmt, p.tableau, prec, p.dt, device)
     if p.u0 is not None:
         s.set_u(p.u0)
+    if getattr(p, 'forcing', None) is not None:
+        s.set_forcing(p.forcing)
     return s
 
 

@@ -69,6 +69,8 @@ def test_create_and_workspace_bytes_on_host():
     dict(grid=(0, 4, 4)),
     dict(bc=7),
     dict(kind=1, b=(1.0, 0, 0)),            # CG on a nonsymmetric operator
+    dict(kind=2, b=(0, 1.0, 0)),            # CG on central advection
+    dict(kind=3),                           # no such operator
     dict(dt=-1.0),
     dict(diff=float('nan')),
 ])
@@ -156,3 +158,13 @@ def test_fdm_preconditioner_scope_is_validated():
     p.precond = 3
     rc, _ = _create(prec=p)
     assert rc == A.EINVAL
+
+
+def test_central_operator_and_forcing_entry_points_on_host():
+    p = A.mprk_precisions_default(A.FP32, A.GMRES)
+    rc, h = _create(prec=p, kind=2, b=(1.0, 1.0, 1.0), bc=1)
+    assert rc == A.OK, A.mprk_last_error()
+    # forcing is a pointer handed over at any time (read only by the kernels of a step)
+    assert A.lib.mprk_set_forcing(h, None) == A.OK
+    A.lib.mprk_destroy(h)
+    assert A.lib.mprk_set_forcing(None, None) == A.EINVAL

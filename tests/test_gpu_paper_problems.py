@@ -1,0 +1,93 @@
+"""The paper's own test problems through the C ABI (Section "Test cases"): the forced heat
+equation (constant source g = sin sin sin, u(0) = 0) and periodic advection with central
+differences, for the methods of its experiments (implicit midpoint with a corrector, 4s3pA/B/C),
+against the oracle's closed forms (the forced sine-mode recursion; the FFT evolution)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import closed_form, tableaus
+from tests.gpu_util import log_case, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+M = pytest.importorskip('paper_2412_16638_amd')
+A = M._abi
+
+TOL = {'fp64': 1e-10, 'fp32': 1e-6, 'fp16': 1e-3}
+
+
+def run(p, fmt=A.FMT_STENCIL, **over):
+    st = M.from_problem(p, fmt=fmt, **over)
+    stats = st.step(p.nsteps)
+    u = st.get_u()
+    st.close()
+    return u, stats
+
+
+def forced_ref(p):
+    return closed_form.evolve_forced_heat(p.forcing, p.diff, p.dt, p.nsteps, tableaus.by_name(p.tableau))
+
+
+def advection_ref(p):
+    return closed_form.evolve(p.u0, 2, p.bc, p.diff, p.b, p.dt, p.nsteps, tableaus.by_name(p.tableau))
+
+
+@pytest.mark.parametrize("fmt", [A.FMT_STENCIL, A.FMT_CSR])
+@pytest.mark.parametrize("tab", ['MID1', '4S3PB', '4S3PC', 'SDIRK3'])
+def test_forced_heat_fp64(tab, fmt):
+    p = W.paper_heat(n=18, tableau=tab, dt=1.0 / 160, t_end=0.05, precision='fp64')
+    log_case('paper_heat_18', tab=tab, fmt=fmt)
+    u, stats = run(p, fmt, rtol=1e-12, outer_tol=1e-12)
+    err = rel_l2(u, forced_ref(p))
+    print(tab, fmt, 'rel-L2', err, stats['iters'])
+    assert err <= TOL['fp64'], err
+
+
+@pytest.mark.parametrize("storage", ['fp32', 'fp16'])
+@pytest.mark.parametrize("tab", ['MID1', '4S3PC'])
+def test_forced_heat_mixed(tab, storage):
+    p = W.paper_heat(n=20, tableau=tab, dt=1.0 / 160, t_end=0.05, precision=storage)
+    log_case('paper_heat_20', tab=tab, storage=storage)
+    u, stats = run(p)
+    err = rel_l2(u, forced_ref(p))
+    assert err <= TOL[storage], err
+
+
+@pytest.mark.parametrize("fmt", [A.FMT_STENCIL, A.FMT_CSR])
+@pytest.mark.parametrize("tab", ['MID1', '4S3PA', '4S3PB', '4S3PC'])
+def test_central_advection_fp64(tab, fmt):
+    p = W.paper_advection(n=16, tableau=tab, dt=1.0 / 80, t_end=0.05, precision='fp64')
+    log_case('paper_advection_16', tab=tab, fmt=fmt)
+    u, stats = run(p, fmt, rtol=1e-12, outer_tol=1e-12)
+    err = rel_l2(u, advection_ref(p))
+    print(tab, fmt, 'rel-L2', err, stats['iters'])
+    assert err <= TOL['fp64'], err
+
+
+@pytest.mark.parametrize("storage", ['fp32', 'fp16'])
+def test_central_advection_mixed(storage):
+    p = W.paper_advection(n=24, tableau='4S3PC', dt=1.0 / 80, t_end=0.05, precision=storage)
+    log_case('paper_advection_24', storage=storage)
+    u, stats = run(p)
+    err = rel_l2(u, advection_ref(p))
+    assert err <= TOL[storage], err
+
+
+def test_stage_solve_ignores_the_forcing_and_removal_restores_the_unforced_step():
+    p = W.paper_heat(n=12, tableau='SDIRK3', dt=1e-2, t_end=0.02, precision='fp64')
+    log_case('forcing_scope')
+    st = M.from_problem(p, rtol=1e-12, outer_tol=1e-12)
+    rhs = torch.from_numpy(W.random_field(12, 9).ravel()).cuda()
+    x_forced, _ = st.solve(1, rhs)
+    st.set_forcing(None)
+    x_plain, _ = st.solve(1, rhs)
+    assert torch.equal(x_forced, x_plain)  # mprk_solve solves (I - sigma K) x = rhs alone
+    u0 = W.random_field(12, 10)
+    st.set_u(u0)
+    st.step(2)
+    u = st.get_u()
+    st.close()
+    ref = closed_form.evolve_heat(u0, 1.0, p.dt, 2, tableaus.by_name('SDIRK3'))
+    assert rel_l2(u, ref) <= TOL['fp64']
