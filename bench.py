@@ -196,9 +196,12 @@ def main():
     ap.add_argument('--fmt', default='stencil', choices=['stencil', 'csr'])
     ap.add_argument('--no-fp64', action='store_true', help='skip the FP64 matched-error leg')
     ap.add_argument('--no-cpu', action='store_true', help='skip the oracle / cpu_baseline leg')
-    ap.add_argument('--mode', default='step', choices=['step', 'batch', 'serve'],
+    ap.add_argument('--mode', default='step', choices=['step', 'batch', 'serve', 'sweep'],
                     help='step: the 256^3 / 128^3 single-problem line (default); batch: 64 heat '
-                         'problems in one persistent launch per stage; serve: 512 Poisson requests')
+                         'problems in one persistent launch per stage; serve: 512 Poisson '
+                         'requests; sweep: the paper\'s time-step and tolerance experiments')
+    ap.add_argument('--n', type=int, default=128,
+                    help='sweep mode: grid points per axis of the paper\'s test problems')
     ap.add_argument('--quick', action='store_true',
                     help='profiling runs: skip the full-integration error check and side legs')
     ap.add_argument('--bj', default='per-block', choices=['per-block', 'shared'],
@@ -226,6 +229,8 @@ def main():
         return bench_batch(args)
     if args.mode == 'serve':
         return bench_serve(args)
+    if args.mode == 'sweep':
+        return bench_sweep(args)
     fmt = AB.FMT_STENCIL if args.fmt == 'stencil' else AB.FMT_CSR
     bjs = 1 if args.bj == 'shared' else 0
     if args.calib_copy:
@@ -426,6 +431,110 @@ def main():
     prec = M.precisions(p.precision, p.krylov, **MIXED_TOL[args.workload])
     out['config']['outer_tol'] = prec.outer_tol
     out['config']['inner_rtol'] = prec.rtol
+    print(json.dumps(out), flush=True)
+
+
+SWEEP_TAUS = (1 / 10, 1 / 20, 1 / 40, 1 / 80, 1 / 160, 1 / 320, 1 / 640, 1 / 1280)
+SWEEP_METHODS = {'heat': ('MID1', '4S3PB', '4S3PC'),            # 4s3pA excluded for heat
+                 'advection': ('MID1', '4S3PA', '4S3PB', '4S3PC')}
+
+
+def bench_sweep(args):
+    """The paper's experiments (Section "Linear solvers and setup of the numerical experiments",
+    Figure CombinedErrors, Table iterations) on its two test problems: final-time error and
+    wall time against tau in {1/10 .. 1/1280} to T = 1/10 for the methods M (implicit midpoint
+    with one corrector), A, B, C, with FP32 and FP64 implicit solves in the paper's setting
+    (one solve per stage to an absolute-or-relative residual tol = 1e-3, at most 40 Krylov
+    iterations (GMRES: one cycle of at most 32, the longest built), the tableau's FP64
+    corrector stages, no outer refinement); then the Krylov
+    iterations per solve of method C against tol.  Heat: CG with the fast-diagonalisation
+    preconditioner; advection: GMRES(30) with block-Jacobi(8) (no complex FDM here).
+    Errors: relative L2 against the continuum solution (the paper's measure: spatial error
+    included) and against the oracle's exact-solve DIRK (the solver's own error)."""
+    import torch
+    import paper_2412_16638_amd as M
+    import workloads as W
+    from oracle import closed_form, tableaus
+
+    n, T = args.n, 0.1
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    def make(prob, tab, tau, prec):
+        if prob == 'heat':
+            return W.paper_heat(n, tab, tau, T, prec)
+        return W.paper_advection(n, tab, tau, T, prec)
+
+    def run(p, tol, maxit=40):
+        p.precond = 'fdm' if p.kind == W.HEAT else 'bj'
+        over = {} if p.kind == W.HEAT else {'restart': 32}  # the longest GMRES cycle built
+        st = M.from_problem(p, rtol=tol, atol=tol, maxit=maxit, refine_max=0, **over)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, stats = st.step(p.nsteps, check=False)  # a non-finite step is a result here
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        u = st.get_u()
+        st.close()
+        stats['rc'] = rc
+        return u, stats, t
+
+    # warm-up (first launches, library initialisation)
+    for prob in ('heat', 'advection'):
+        for prec in ('fp32', 'fp64'):
+            run(make(prob, '4S3PC', 1 / 10, prec), 1e-3)
+
+    rows = []
+    for prob, methods in SWEEP_METHODS.items():
+        cont = (closed_form.forced_heat_exact(W.sine_mode((n,) * 3, (1, 1, 1)), 1.0, T, continuum=True)
+                if prob == 'heat' else W.translated_gaussian(n, (T, T, T)))
+        for tab in methods:
+            for tau in SWEEP_TAUS:
+                p = make(prob, tab, tau, 'fp64')
+                tb = tableaus.by_name(tab)
+                ref = (closed_form.evolve_forced_heat(p.forcing, 1.0, tau, p.nsteps, tb)
+                       if prob == 'heat' else
+                       closed_form.evolve(p.u0, p.kind, p.bc, p.diff, p.b, tau, p.nsteps, tb))
+                row = {'problem': prob, 'method': tab, 'tau': tau, 'steps': p.nsteps}
+                for prec in ('fp32', 'fp64'):
+                    u, stats, t = run(make(prob, tab, tau, prec), 1e-3)
+                    row[prec] = {'ms': round(t * 1e3, 3),
+                                 'err_vs_continuum': rel(u, cont),
+                                 'err_vs_exact_dirk': rel(u, ref),
+                                 'iters_per_solve': round(stats['total_iters'] / max(1, stats['total_passes']), 2),
+                                 'rc': stats['rc'], 'nonfinite': stats['nonfinite']}
+                row['speedup'] = row['fp64']['ms'] / row['fp32']['ms']
+                rows.append(row)
+                log(f"sweep {prob:9s} {tab:5s} tau=1/{round(1 / tau):4d}: "
+                    f"err fp32 {row['fp32']['err_vs_continuum']:.3e} fp64 {row['fp64']['err_vs_continuum']:.3e} "
+                    f"(vs exact DIRK {row['fp32']['err_vs_exact_dirk']:.1e} / {row['fp64']['err_vs_exact_dirk']:.1e}); "
+                    f"iters {row['fp32']['iters_per_solve']} / {row['fp64']['iters_per_solve']}; "
+                    f"{row['fp32']['ms']:.1f} / {row['fp64']['ms']:.1f} ms -> {row['speedup']:.2f}x")
+    # Krylov iterations per solve against the tolerance (method C, tau = 1/80)
+    iters = []
+    for prob in SWEEP_METHODS:
+        for tol in (1e-3, 1e-4, 1e-5, 1e-6, 1e-8):
+            rec = {'problem': prob, 'tol': tol}
+            for prec in ('fp32', 'fp64'):
+                _, stats, t = run(make(prob, '4S3PC', 1 / 80, prec), tol)
+                rec[prec] = round(stats['total_iters'] / max(1, stats['total_passes']), 2)
+                rec[prec + '_ms'] = round(t * 1e3, 3)
+            iters.append(rec)
+            log(f"iterations {prob:9s} tol={tol:.0e}: fp32 {rec['fp32']} fp64 {rec['fp64']} per solve")
+    sp = np.array([r['speedup'] for r in rows])
+    total_dof_steps = sum(n ** 3 * r['steps'] for r in rows)
+    total_s = sum(r['fp32']['ms'] for r in rows) * 1e-3
+    out = {'metric': 'paper experiments: final-time error and wall time vs tau, FP32 vs FP64 '
+                     'implicit solves', 'mode': 'sweep',
+           'value': total_dof_steps / total_s, 'unit': 'DOF-steps/s (all FP32 sweep runs)',
+           'n_gpus': 1, 'higher_is_better': True, 'dtype': 'f32', 'data': 'synthetic',
+           'vs_baseline': None,
+           'config': {'workload': f'paper forced heat and central advection, {n}^3, T = 0.1, '
+                                  f'tol 1e-3, maxit 40, one solve per stage',
+                      'n': n, 'taus': list(SWEEP_TAUS)},
+           'speedup_geomean': float(np.exp(np.mean(np.log(sp)))),
+           'rows': rows, 'iterations_vs_tol': iters}
     print(json.dumps(out), flush=True)
 
 
