@@ -105,7 +105,7 @@ def cpu_oracle_rate(workload: str, precond: str = 'bj'):
     (GMRES(30) or CG + block-Jacobi(8), rtol 1e-10), one thread, setup excluded.  The sample is
     one step of the workload's PDE on a smaller grid (128^3 for the 256^3 advection-diffusion
     run, 96^3 for the 128^3 heat run), sized to 10-30 s of CPU work.  With the fast-
-    diagonalisation preconditioner the oracle's CG uses its FDM inverse, and the sample is two
+    diagonalisation preconditioner the oracle's CG uses its FDM inverse, and the sample is eight
     steps of the 128^3 heat workload itself."""
     from threadpoolctl import threadpool_limits
     import workloads as W
@@ -118,7 +118,7 @@ def cpu_oracle_rate(workload: str, precond: str = 'bj'):
     solve = dirk.StageSolver(K, 'gmres' if p.krylov == 'gmres' else 'cg', rtol=1e-10, block=8,
                              restart=30,
                              fdm_problem=((p.n,) * 3, p.bc, p.kind, p.diff, p.b) if fdm else None)
-    steps = 2 if fdm else 1
+    steps = 8 if fdm else 1
     u = np.asarray(p.u0, dtype=np.float64).ravel().copy()
     with threadpool_limits(limits=1):
         for i in range(tab.s):
@@ -128,7 +128,7 @@ def cpu_oracle_rate(workload: str, precond: str = 'bj'):
         for _ in range(steps):
             u = dirk.dirk_step(K, u, p.dt, tab, solve)
         t = time.perf_counter() - t0
-    sample = (f'{"two" if steps == 2 else "one"} {p.tableau} step{"s" if steps > 1 else ""} of the '
+    sample = (f'{steps} {p.tableau} step{"s" if steps > 1 else ""} of the '
               f'{"advection-diffusion" if p.kind else "heat"} problem '
               f'on a {p.n}^3 grid ({p.N} unknowns), FP64 oracle DIRK with its '
               f'{p.krylov.upper()} + {"FDM" if fdm else "block-Jacobi(8)"} stage solver to rtol 1e-10 '
@@ -209,7 +209,7 @@ def main():
     ap.add_argument('--precond', default='bj', choices=['bj', 'fdm'],
                     help='stage-solve preconditioner: block-Jacobi(8) (the configurations) or the '
                          'paper\'s fast-diagonalisation one (heat128 only)')
-    ap.add_argument('--reps', type=int, default=3,
+    ap.add_argument('--reps', type=int, default=5,
                     help='timed repetitions of the K steps (value = median)')
     ap.add_argument('--calib-copy', type=int, default=0, metavar='MIB',
                     help='first run a plain device copy of this many MiB (counter calibration)')

@@ -18,11 +18,11 @@ struct Profiler {
   hipStream_t stream = nullptr;
   std::vector<hipEvent_t> pool;
   struct Rec {
-    int kc, e0, e1;
+    int kc, e0, e1, n;  // n: launches between the two events
   };
   std::vector<Rec> recs;
   size_t used = 0;
-  int cur_kc = -1, cur_e0 = -1;
+  int cur_kc = -1, cur_e0 = -1, cur_n = 1;
   bool failed = false;
   int next() {
     if (used == pool.size()) {
@@ -35,15 +35,18 @@ struct Profiler {
     }
     return (int)used++;
   }
-  void before(int kc) {
+  // n > 1: one event pair around n back-to-back launches of one class (event overhead would
+  // otherwise dominate launches of a few microseconds)
+  void before(int kc, int n = 1) {
     cur_kc = kc;
+    cur_n = n;
     cur_e0 = next();
     if (cur_e0 >= 0 && hipEventRecord(pool[cur_e0], stream) != hipSuccess) failed = true;
   }
   void after() {
     const int e1 = next();
     if (e1 >= 0 && hipEventRecord(pool[e1], stream) != hipSuccess) failed = true;
-    if (cur_e0 >= 0 && e1 >= 0) recs.push_back(Rec{cur_kc, cur_e0, e1});
+    if (cur_e0 >= 0 && e1 >= 0) recs.push_back(Rec{cur_kc, cur_e0, e1, cur_n});
   }
   void reset() {
     recs.clear();
@@ -240,14 +243,12 @@ class EngineT final : public Engine {
     g.tiles = row ? ((g.nr + BM - 1) / BM) * ((n + FT_N - 1) / FT_N)
                   : ((n + BM - 1) / BM) * ((g.nc + FT_N - 1) / FT_N) * g.nb;
     const dim3 grid((unsigned)((g.tiles + 7) & ~7));
-    if (c.prof) c.prof->before(KC_FDM);
     if (row)
       hipLaunchKernelGGL((k_fdm_contract<TI, TO, C, 1, V4, BM, KC>), grid, dim3(256), 0, c.stream, g,
                          (const C*)Q, in, out, sc, c.ctl);
     else
       hipLaunchKernelGGL((k_fdm_contract<TI, TO, C, 0, V4, BM, KC>), grid, dim3(256), 0, c.stream, g,
                          (const C*)Q, in, out, sc, c.ctl);
-    if (c.prof) c.prof->after();
   }
   // the data operand is read 4 elements at a time when its rows have a multiple of 4 elements
   template <typename TI, typename TO>
@@ -274,12 +275,14 @@ class EngineT final : public Engine {
     const FdmScale none{nullptr, nullptr, nullptr, 0.0, nx, 0};
     const FdmScale sc{c.fdm_lam[0], c.fdm_lam[1], c.fdm_lam[2], sigma * c.kappa, nx, 1};
     // (Q_C (x) Q_B (x) Q_A) applied as T_R, T_M, T_L (Q is its own inverse), then P_D^-1
+    if (c.prof) c.prof->before(KC_FDM, 6);
     fdm_row<S, C>(c, nx, ny * nz, c.fdm_Q[0], (const S*)r, t0);
     fdm_col(c, ny, nx, nx, (long)nx * ny, nz, c.fdm_Q[1], t0, t1, none);
     fdm_col(c, nz, nx * ny, nx * ny, 0, 1, c.fdm_Q[2], t1, t0, sc);
     fdm_col(c, nz, nx * ny, nx * ny, 0, 1, c.fdm_Q[2], t0, t1, none);
     fdm_col(c, ny, nx, nx, (long)nx * ny, nz, c.fdm_Q[1], t1, t0, none);
     fdm_row<C, S>(c, nx, ny * nz, c.fdm_Q[0], t0, (S*)z);
+    if (c.prof) c.prof->after();
     return hipGetLastError();
   }
   hipError_t cg_finish(const EngineCtx& c) override {

@@ -1194,7 +1194,7 @@ extern "C" int32_t mprk_profile_read(mprk_handle* h, int32_t kclass, int64_t* la
     float t = 0.f;
     HIPCHK(hipEventElapsedTime(&t, h->prof.pool[r.e0], h->prof.pool[r.e1]));
     ms += t;
-    ++n;
+    n += r.n;
   }
   if (launches) *launches = n;
   if (worked) *worked = w[kclass] - h->worked0[kclass];
