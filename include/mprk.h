@@ -92,7 +92,11 @@ typedef struct {
 
 /* Solver precisions and parameters of the implicit stage solves.
  *  storage: MPRK_FP64 | MPRK_FP32 | MPRK_FP16 -- storage of Krylov vectors, LP matrix values
- *           and block-Jacobi inverses.  compute: MPRK_FP64 (only with FP64 storage) | MPRK_FP32.
+ *           and block-Jacobi inverses.  compute: MPRK_FP32 (with FP32 / FP16 storage) |
+ *           MPRK_FP64: with FP64 storage the all-FP64 solve; with FP32 / FP16 storage the
+ *           compressed-basis variant (every Krylov vector, the GMRES basis and the LP operator
+ *           values stored in the low precision, all arithmetic in FP64; the Ginkgo-style
+ *           alternative cited in the Introduction).
  *  krylov: MPRK_CG (SPD only) | MPRK_GMRES (right preconditioned, restart = cycle length m).
  *  precond: MPRK_PRECOND_NONE | MPRK_PRECOND_BJ with block in {1,2,4,8}: consecutive blocks of
  *           `block` rows in lexicographic order, inverses computed in FP64 per block |

@@ -126,6 +126,8 @@ class Engine {
 Engine* make_engine_fp64();
 Engine* make_engine_fp32();
 Engine* make_engine_fp16();
+Engine* make_engine_cb16();  // FP16 storage, FP64 arithmetic
+Engine* make_engine_cb32();  // FP32 storage, FP64 arithmetic
 
 template <typename C>
 inline Coef<C> cast_coef(const Coef<double>& a) {

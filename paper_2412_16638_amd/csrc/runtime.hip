@@ -390,8 +390,6 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
   }
   if (p->storage < MPRK_FP64 || p->storage > MPRK_FP16) return set_error(MPRK_EINVAL, "bad storage");
   if (p->compute != MPRK_FP64 && p->compute != MPRK_FP32) return set_error(MPRK_EINVAL, "bad compute");
-  if (p->compute == MPRK_FP64 && p->storage != MPRK_FP64)
-    return set_error(MPRK_EUNSUPPORTED, "FP64 compute needs FP64 storage");
   if (p->storage == MPRK_FP64 && p->compute != MPRK_FP64)
     return set_error(MPRK_EUNSUPPORTED, "FP64 storage needs FP64 compute");
   if (p->krylov != MPRK_CG && p->krylov != MPRK_GMRES) return set_error(MPRK_EINVAL, "bad krylov");
@@ -449,10 +447,12 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   vec = (g.nx % 4 == 0) ? 4 : 1;
   vec_lp = (p.storage == MPRK_FP16 && g.nx % 8 == 0) ? 8 : vec;
   Kc = operator_coef(g, o);
+  // FP64 arithmetic over FP32 / FP16 storage: the compressed-basis variants
+  const bool cb = p.compute == MPRK_FP64 && p.storage != MPRK_FP64;
   switch (p.storage) {
     case MPRK_FP64: eng.reset(make_engine_fp64()); break;
-    case MPRK_FP32: eng.reset(make_engine_fp32()); break;
-    default: eng.reset(make_engine_fp16()); break;
+    case MPRK_FP32: eng.reset(cb ? make_engine_cb32() : make_engine_fp32()); break;
+    default: eng.reset(cb ? make_engine_cb16() : make_engine_fp16()); break;
   }
   lp_bytes = eng->elem_bytes();
   nstages = t.s;
@@ -1206,9 +1206,10 @@ extern "C" int32_t mprk_profile_read(mprk_handle* h, int32_t kclass, int64_t* la
 // ---- autotuner ----
 namespace {
 struct TuneKey {
-  int nx, ny, nz, bc, kind, fmt, storage;
+  int nx, ny, nz, bc, kind, fmt, storage, compute;
   bool operator<(const TuneKey& o) const {
-    return std::tie(nx, ny, nz, bc, kind, fmt, storage) < std::tie(o.nx, o.ny, o.nz, o.bc, o.kind, o.fmt, o.storage);
+    return std::tie(nx, ny, nz, bc, kind, fmt, storage, compute) <
+           std::tie(o.nx, o.ny, o.nz, o.bc, o.kind, o.fmt, o.storage, o.compute);
   }
 };
 struct TuneVal {
@@ -1224,7 +1225,8 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
   if (!h->bound) return set_error(MPRK_ESTATE, "mprk_autotune before mprk_bind");
   const bool csr = h->op.format == MPRK_FMT_CSR;
   const long ngv = h->N / h->vec, ngr = h->N, ngl = h->N / h->vec_lp;
-  const TuneKey key{h->grid.nx, h->grid.ny, h->grid.nz, h->grid.bc, h->op.kind, h->op.format, h->prec.storage};
+  const TuneKey key{h->grid.nx, h->grid.ny, h->grid.nz, h->grid.bc, h->op.kind, h->op.format, h->prec.storage,
+                    h->prec.compute};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(key);

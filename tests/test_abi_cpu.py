@@ -89,8 +89,8 @@ def test_create_rejects_upper_triangular_tableau():
 
 
 def test_create_rejects_bad_precisions():
-    p = A.mprk_precisions_default(A.FP16, A.CG)
-    p.compute = A.FP64
+    p = A.mprk_precisions_default(A.FP64, A.CG)
+    p.compute = A.FP32   # FP64 storage with FP32 arithmetic is not a built combination
     rc, _ = _create(prec=p)
     assert rc == A.EUNSUPPORTED
     p = A.mprk_precisions_default(A.FP32, A.GMRES)
@@ -168,3 +168,23 @@ def test_central_operator_and_forcing_entry_points_on_host():
     assert A.lib.mprk_set_forcing(h, None) == A.OK
     A.lib.mprk_destroy(h)
     assert A.lib.mprk_set_forcing(None, None) == A.EINVAL
+
+
+def test_compressed_basis_precisions_are_accepted_for_single_problems():
+    # FP64 arithmetic over FP16 / FP32 storage (compressed-basis Krylov); the batched form
+    # keeps FP32 arithmetic for LP storage
+    for storage, krylov, kw in ((A.FP16, A.GMRES, dict(kind=1, b=(1.0, 0.5, 0.25), bc=1)),
+                                (A.FP32, A.CG, {})):
+        p = A.mprk_precisions_default(storage, krylov)
+        p.compute = A.FP64
+        rc, h = _create(prec=p, **kw)
+        assert rc == A.OK, A.mprk_last_error()
+        A.lib.mprk_destroy(h)
+    p = A.mprk_precisions_default(A.FP16, A.CG)
+    p.compute = A.FP64
+    g = A.mprk_grid(8, 8, 8, 0)
+    o = A.mprk_operator(0, 0, 1.0, (C.c_double * 3)(0, 0, 0))
+    probs = (A.mprk_problem * 1)(A.mprk_problem(g, o, 1e-3))
+    t = A.mprk_tableau_builtin(A.TAB_SDIRK3)
+    h = C.c_void_p()
+    assert A.lib.mprk_batch_create(1, probs, C.byref(t), C.byref(p), None, C.byref(h)) == A.EUNSUPPORTED
