@@ -85,7 +85,6 @@ def make_problem(name: str, precond: str = 'bj'):
     return p
 
 
-# MI355X vector peaks (TFLOP/s) for the compute-bound contraction kernels
 # dense matrix-core peaks of the FDM contractions' arithmetic (FP64 MFMA for FP64 storage, FP32
 # MFMA otherwise), TFLOP/s
 MFMA_PEAK = {'fp64': 78.6, 'fp32': 157.3, 'fp16': 157.3}
@@ -209,6 +208,9 @@ def main():
     ap.add_argument('--precond', default='bj', choices=['bj', 'fdm'],
                     help='stage-solve preconditioner: block-Jacobi(8) (the configurations) or the '
                          'paper\'s fast-diagonalisation one (heat128 only)')
+    ap.add_argument('--compute', default='fp32', choices=['fp32', 'fp64'],
+                    help='arithmetic of the low-precision solves: fp32 (the configurations) or '
+                         'fp64 over the same storage (compressed-basis Krylov)')
     ap.add_argument('--reps', type=int, default=5,
                     help='timed repetitions of the K steps (value = median)')
     ap.add_argument('--calib-copy', type=int, default=0, metavar='MIB',
@@ -244,6 +246,9 @@ def main():
     if args.precond == 'fdm' and args.workload != 'heat128':
         raise SystemExit('--precond fdm is implemented for the heat workload (heat128)')
     p = make_problem(args.workload, args.precond)
+    mixed_over = dict(MIXED_TOL[args.workload])
+    if args.compute == 'fp64':
+        mixed_over['compute'] = AB.FP64
     N = p.N
     K, Wm = args.steps, args.warmup
     log(f'workload {args.workload}: N={N} ({p.n}^3), {p.tableau}, dt={p.dt}, {p.krylov}, '
@@ -261,14 +266,14 @@ def main():
     st_mixed = None
     if not args.quick:
         log('mixed path: full integration for the error check ...')
-        u_mixed, st_mixed = run_integration(M, p, fmt, bj_shared=bjs, **MIXED_TOL[args.workload])
+        u_mixed, st_mixed = run_integration(M, p, fmt, bj_shared=bjs, **mixed_over)
     if ref is not None and st_mixed is not None:
         err_mixed = float(np.linalg.norm(u_mixed - ref) / np.linalg.norm(ref))
         log(f'mixed rel-L2 vs oracle = {err_mixed:.3e}  iters/stage={st_mixed["iters"]} '
             f'passes/stage={st_mixed["passes"]}')
 
     # ---- timed mixed run ----
-    st = M.from_problem(p, fmt=fmt, bj_shared=bjs, **MIXED_TOL[args.workload])
+    st = M.from_problem(p, fmt=fmt, bj_shared=bjs, **mixed_over)
     tuned = st.autotune()
     log(f'autotuned groups per thread (vector, row) = {tuned}')
     reps = []
@@ -328,7 +333,7 @@ def main():
         # the contractions are dense: 2 n flops per unknown per launch (n = axis length)
         flops_per_launch = 2.0 * r['units'] * N / r['launches']
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-        peak = MFMA_PEAK[p.precision]
+        peak = MFMA_PEAK['fp64' if args.compute == 'fp64' else p.precision]
         roofline = {'bound': 'mfma', 'kernel': kc, 'achieved': round(achieved, 2), 'peak': peak,
                     'unit': 'TFLOP/s', 'frac': round(achieved / peak, 4), 'traffic': None,
                     'flops_per_launch': flops_per_launch, 'avg_launch_us': round(avg_ms * 1e3, 2),
@@ -386,7 +391,7 @@ def main():
     # ---- the other block-Jacobi storage (same values; per-block inverse stream or not) ----
     other = None
     if not args.no_fp64 and not args.quick and args.precond == 'bj':
-        st2 = M.from_problem(p, fmt=fmt, bj_shared=1 - bjs, **MIXED_TOL[args.workload])
+        st2 = M.from_problem(p, fmt=fmt, bj_shared=1 - bjs, **mixed_over)
         st2.autotune()
         t2, _, _ = time_steps(st2, p.u0, K, Wm)
         st2.close()
@@ -406,14 +411,16 @@ def main():
     out = {
         'metric': METRIC, 'value': value, 'unit': 'DOF-steps/s', 'n_gpus': 1, 'steps': K,
         'warmup': Wm, 'ms_per_step': t_mixed * 1e3 / K, 'higher_is_better': True,
-        'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f32',
+        'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64' if args.compute == 'fp64' else 'f32',
         'data': 'synthetic',
         'config': {'workload': ('advdiff_upwind_periodic_256^3_sdirk3_dt2e-3_gmres30_bj8_fp16'
                                 if args.workload == 'advdiff256'
                                 else 'heat_dirichlet_128^3_sdirk3_dt5e-4_cg_bj8_fp32'
                                 if args.precond == 'bj'
-                                else 'heat_dirichlet_128^3_sdirk3_dt5e-4_cg_fdm_fp32'),
-                   'N': N, 'format': args.fmt, 'lp_storage': p.precision, 'lp_compute': 'f32',
+                                else 'heat_dirichlet_128^3_sdirk3_dt5e-4_cg_fdm_fp32')
+                               + ('_fp64arith' if args.compute == 'fp64' else ''),
+                   'N': N, 'format': args.fmt, 'lp_storage': p.precision,
+                   'lp_compute': 'f64' if args.compute == 'fp64' else 'f32',
                    'explicit_parts': 'f64', 'krylov': p.krylov},
         'err_vs_oracle': err_mixed,
         'iters_per_stage': stats['iters'], 'passes_per_stage': stats['passes'],
@@ -453,6 +460,7 @@ def bench_sweep(args):
     included) and against the oracle's exact-solve DIRK (the solver's own error)."""
     import torch
     import paper_2412_16638_amd as M
+    from paper_2412_16638_amd import _abi as AB
     import workloads as W
     from oracle import closed_form, tableaus
 
@@ -466,10 +474,10 @@ def bench_sweep(args):
             return W.paper_heat(n, tab, tau, T, prec)
         return W.paper_advection(n, tab, tau, T, prec)
 
-    def run(p, tol, maxit=40):
+    def run(p, tol, maxit=40, **extra):
         p.precond = 'fdm' if p.kind == W.HEAT else 'bj'
         over = {} if p.kind == W.HEAT else {'restart': 32}  # the longest GMRES cycle built
-        st = M.from_problem(p, rtol=tol, atol=tol, maxit=maxit, refine_max=0, **over)
+        st = M.from_problem(p, rtol=tol, atol=tol, maxit=maxit, refine_max=0, **over, **extra)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc, stats = st.step(p.nsteps, check=False)  # a non-finite step is a result here
@@ -522,6 +530,25 @@ def bench_sweep(args):
                 rec[prec + '_ms'] = round(t * 1e3, 3)
             iters.append(rec)
             log(f"iterations {prob:9s} tol={tol:.0e}: fp32 {rec['fp32']} fp64 {rec['fp64']} per solve")
+    # FP16 storage with FP32 against FP64 arithmetic (compressed basis), same setting, method C,
+    # tau = 1/80: the error of the one-solve-per-stage integration against the exact-solve DIRK
+    cbrows = []
+    for prob in SWEEP_METHODS:
+        p0 = make(prob, '4S3PC', 1 / 80, 'fp16')
+        tb = tableaus.by_name('4S3PC')
+        ref = (closed_form.evolve_forced_heat(p0.forcing, 1.0, p0.dt, p0.nsteps, tb)
+               if prob == 'heat' else
+               closed_form.evolve(p0.u0, p0.kind, p0.bc, p0.diff, p0.b, p0.dt, p0.nsteps, tb))
+        for tol in (1e-3, 1e-5, 1e-8):
+            rec = {'problem': prob, 'tol': tol}
+            for lab, extra in (('fp16_fp32arith', {}), ('fp16_fp64arith', {'compute': AB.FP64})):
+                u, stats, t = run(make(prob, '4S3PC', 1 / 80, 'fp16'), tol, **extra)
+                rec[lab] = {'err_vs_exact_dirk': rel(u, ref), 'ms': round(t * 1e3, 3),
+                            'iters_per_solve': round(stats['total_iters'] / max(1, stats['total_passes']), 2)}
+            cbrows.append(rec)
+            log(f"fp16 storage {prob:9s} tol={tol:.0e}: err vs exact DIRK fp32-arith "
+                f"{rec['fp16_fp32arith']['err_vs_exact_dirk']:.2e} ({rec['fp16_fp32arith']['iters_per_solve']} it) "
+                f"fp64-arith {rec['fp16_fp64arith']['err_vs_exact_dirk']:.2e} ({rec['fp16_fp64arith']['iters_per_solve']} it)")
     sp = np.array([r['speedup'] for r in rows])
     total_dof_steps = sum(n ** 3 * r['steps'] for r in rows)
     total_s = sum(r['fp32']['ms'] for r in rows) * 1e-3
@@ -534,7 +561,7 @@ def bench_sweep(args):
                                   f'tol 1e-3, maxit 40, one solve per stage',
                       'n': n, 'taus': list(SWEEP_TAUS)},
            'speedup_geomean': float(np.exp(np.mean(np.log(sp)))),
-           'rows': rows, 'iterations_vs_tol': iters}
+           'rows': rows, 'iterations_vs_tol': iters, 'fp16_storage_arithmetic': cbrows}
     print(json.dumps(out), flush=True)
 
 
