@@ -83,6 +83,7 @@ struct EngineCtx {
   const double* fdm_lam[3];
   void* fdm_t[2];
   double kappa;
+  double fdm_sigma;  // sigma of the solve in progress (the end-of-cycle preconditioner apply)
   // LP vectors (S*)
   void *r, *z, *p0, *p1, *q, *x;
   void* V;
@@ -260,31 +261,37 @@ class EngineT final : public Engine {
     else fdm_launch<TI, TO, 0, 64, FT_KC>(c, g, row, Q, in, out, sc);
   }
   template <typename TI, typename TO>
-  void fdm_row(const EngineCtx& c, int n, int nr, const void* Q, const TI* in, TO* out) {
-    const FdmGeo g{n, fdm_ldq(n), nr, 0, 0, 0, 1, 0};
+  void fdm_row(const EngineCtx& c, int n, int nr, const void* Q, const TI* in, TO* out, int skip = 1) {
+    const FdmGeo g{n, fdm_ldq(n), nr, 0, 0, 0, 1, 0, skip};
     const FdmScale none{nullptr, nullptr, nullptr, 0.0, 1, 0};
     fdm_go<TI, TO>(c, g, 1, Q, in, out, none);
   }
   void fdm_col(const EngineCtx& c, int n, int nc, int ld, long bstride, int nb, const void* Q,
-               const C* in, C* out, const FdmScale& sc) {
-    const FdmGeo g{n, fdm_ldq(n), 0, nc, ld, bstride, nb, 0};
+               const C* in, C* out, const FdmScale& sc, int skip = 1) {
+    const FdmGeo g{n, fdm_ldq(n), 0, nc, ld, bstride, nb, 0, skip};
     fdm_go<C, C>(c, g, 0, Q, in, out, sc);
   }
-  hipError_t fdm_apply(const EngineCtx& c, double sigma, const void* r, void* z) override {
+  // z = P^-1 r: T_R, T_M, T_L with the basis (its own inverse), P_D^-1, then back.  in and out
+  // may be t1 (the chain never reads and writes one buffer in the same launch).  skip: the
+  // launches return once the inner solve is done (inside a Krylov loop).
+  template <typename TI, typename TO>
+  void fdm_chain(const EngineCtx& c, double sigma, const TI* in, TO* out, int skip) {
     const int nx = c.geo.nx, ny = c.geo.ny, nz = c.geo.nz;
     C* t0 = (C*)c.fdm_t[0];
     C* t1 = (C*)c.fdm_t[1];
     const FdmScale none{nullptr, nullptr, nullptr, 0.0, nx, 0};
     const FdmScale sc{c.fdm_lam[0], c.fdm_lam[1], c.fdm_lam[2], sigma * c.kappa, nx, 1};
-    // (Q_C (x) Q_B (x) Q_A) applied as T_R, T_M, T_L (Q is its own inverse), then P_D^-1
     if (c.prof) c.prof->before(KC_FDM, 6);
-    fdm_row<S, C>(c, nx, ny * nz, c.fdm_Q[0], (const S*)r, t0);
-    fdm_col(c, ny, nx, nx, (long)nx * ny, nz, c.fdm_Q[1], t0, t1, none);
-    fdm_col(c, nz, nx * ny, nx * ny, 0, 1, c.fdm_Q[2], t1, t0, sc);
-    fdm_col(c, nz, nx * ny, nx * ny, 0, 1, c.fdm_Q[2], t0, t1, none);
-    fdm_col(c, ny, nx, nx, (long)nx * ny, nz, c.fdm_Q[1], t1, t0, none);
-    fdm_row<C, S>(c, nx, ny * nz, c.fdm_Q[0], t0, (S*)z);
+    fdm_row<TI, C>(c, nx, ny * nz, c.fdm_Q[0], in, t0, skip);
+    fdm_col(c, ny, nx, nx, (long)nx * ny, nz, c.fdm_Q[1], t0, t1, none, skip);
+    fdm_col(c, nz, nx * ny, nx * ny, 0, 1, c.fdm_Q[2], t1, t0, sc, skip);
+    fdm_col(c, nz, nx * ny, nx * ny, 0, 1, c.fdm_Q[2], t0, t1, none, skip);
+    fdm_col(c, ny, nx, nx, (long)nx * ny, nz, c.fdm_Q[1], t1, t0, none, skip);
+    fdm_row<C, TO>(c, nx, ny * nz, c.fdm_Q[0], t0, out, skip);
     if (c.prof) c.prof->after();
+  }
+  hipError_t fdm_apply(const EngineCtx& c, double sigma, const void* r, void* z) override {
+    fdm_chain<S, S>(c, sigma, (const S*)r, (S*)z, 1);
     return hipGetLastError();
   }
   hipError_t cg_finish(const EngineCtx& c) override {
@@ -305,6 +312,7 @@ class EngineT final : public Engine {
   }
   hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) override {
     dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_begin_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
+    if (c.fdm_on) fdm_chain<S, S>(c, cfg.sigma, (const S*)c.V, (S*)c.z, 1);  // z = P^-1 v_0
     return hipGetLastError();
   }
   template <int VEC, int FMT, int PREC, int NDM>
@@ -321,7 +329,7 @@ class EngineT final : public Engine {
   }
   template <int NDM>
   void gm_iter_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc, const BJDesc& dinv) {
-    const bool prec = c.bs > 0;
+    const bool prec = c.bs > 0 || c.fdm_on;  // the product reads z = P^-1 v_j
     if (c.fmt == 1) {
       if (prec) gm_matvec_t<1, 1, 1, NDM>(c, cfg, Mc); else gm_matvec_t<1, 1, 0, NDM>(c, cfg, Mc);
     } else if (c.vec == 8) {
@@ -342,6 +350,9 @@ class EngineT final : public Engine {
     else if (k < 8) gm_iter_t<8>(c, cfg, Mc, dinv);
     else if (k < 16) gm_iter_t<16>(c, cfg, Mc, dinv);
     else gm_iter_t<MAXD>(c, cfg, Mc, dinv);
+    // z = P^-1 v_{k+1} for the next step (the launches return once the cycle has ended)
+    if (c.fdm_on && k + 1 <= cfg.m)
+      fdm_chain<S, S>(c, cfg.sigma, (const S*)c.V + (size_t)(k + 1) * c.vstride, (S*)c.z, 1);
     return hipGetLastError();
   }
   template <int VEC, int BS, int NDM>
@@ -351,6 +362,21 @@ class EngineT final : public Engine {
   }
   template <int NDM>
   void gm_finish_n(const EngineCtx& c, const BJDesc& dinv) {
+    if (c.fdm_on) {
+      // t = sum_i y_i v_i -> t1; z = P^-1 t (also after the cycle's end) -> t1; y += scale z
+      C* t1 = (C*)c.fdm_t[1];
+      dispatch_vec(c, [&](auto vec) {
+        constexpr int V = decltype(vec)::value;
+        MPRK_LAUNCH_KC(c, KC_GM_FINISH, (k_gm_combine_ext<S, C, V, NDM>), c.ln_vec, c.ln_vec, t1,
+                       (const S*)c.V, c.vstride, c.ctl);
+      });
+      fdm_chain<C, C>(c, c.fdm_sigma, t1, t1, 0);
+      dispatch_vec(c, [&](auto vec) {
+        constexpr int V = decltype(vec)::value;
+        MPRK_LAUNCH_KC(c, KC_PROMOTE, (k_gm_update_ext<C, V>), c.ln_vec, c.ln_vec, c.y, t1, c.ctl);
+      });
+      return;
+    }
     dispatch_vec_bs(c, [&](auto vec, auto bs) {
       gm_finish_t<decltype(vec)::value, decltype(bs)::value, NDM>(c, dinv);
     });

@@ -45,6 +45,7 @@ struct FdmGeo {
   long bstride;  // COL form: elements between batches
   int nb;        // COL form: batches
   int tiles;     // output tiles (the grid is this rounded up to a multiple of 8)
+  int skip_inner;  // 1: return once the inner solve is done (applies inside a Krylov loop)
 };
 
 // Scaling by P_D^-1 (fused into a COL-form contraction along z): the output element with
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(256) void k_fdm_contract(FdmGeo g, const C* __restr
                                                       const TI* __restrict__ in, TO* __restrict__ out,
                                                       FdmScale sc, Ctl* ctl) {
   static_assert((BM == 32 || BM == 64) && (KC == 32 || KC == 64), "tile shapes");
-  if (ctl->outer_done | ctl->inner_done) return;
+  if (ctl->outer_done | (g.skip_inner & ctl->inner_done)) return;
   count_work(ctl, KC_FDM, g.n);
   constexpr int PK = KC + 4, PN = FT_N + 4;
   constexpr int MI = BM / 32;              // 16-row MFMA tiles per wave (waves 2 x 2)
@@ -429,6 +430,89 @@ __global__ __launch_bounds__(TPB) void k_cg_rz(Launch ln, const S* __restrict__ 
     if (!BEGIN) ctl->beta = rz / ctl->rz;
     ctl->rz = rz;
     if (!__builtin_isfinite(rz)) ctl->inner_done = 1;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// GMRES with a preconditioner applied by separate launches: the Arnoldi kernels run without
+// the fused block-Jacobi (the matrix-vector product reads z = P^-1 v_j of the stored vector j,
+// applied between the launches), and the end of a cycle is split into the combination
+// t = sum_i y_i v_i, z = P^-1 t, y += scale z.
+// ------------------------------------------------------------------------------------------
+
+// Least-squares solution of the cycle (back substitution of the rotated Hessenberg system)
+// and t = sum_i ys_i vscale_i v_i in the compute type; counts the pass.
+template <typename S, typename C, int VEC, int NDM>
+__global__ __launch_bounds__(TPB) void k_gm_combine_ext(Launch ln, C* __restrict__ t,
+                                                        const S* __restrict__ V, size_t vstride,
+                                                        Ctl* ctl) {
+  if (ctl->outer_done) return;
+  const int J = ctl->J;
+  count_work(ctl, KC_GM_FINISH, J);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (ctl->passes < MAXPASS) ctl->pass_iters[ctl->passes] = ctl->iters;
+    ctl->passes += 1;
+    ctl->life_passes += 1;
+  }
+  if (J == 0) return;
+  if (J > NDM) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctl->nonfinite = 1;
+      ctl->step_nonfinite = 1;
+    }
+    return;
+  }
+  __shared__ double ys[MAXM];
+  if (threadIdx.x == 0) {
+    for (int i = J - 1; i >= 0; --i) {
+      double acc = ctl->g[i];
+      for (int k = i + 1; k < J; ++k) acc -= ctl->H[k * (MAXM + 1) + i] * ys[k];
+      const double d = ctl->H[i * (MAXM + 1) + i];
+      ys[i] = (d != 0.0 && __builtin_isfinite(acc)) ? acc / d : 0.0;
+    }
+  }
+  __syncthreads();
+  C cf[NDM];
+#pragma unroll
+  for (int i = 0; i < NDM; ++i) cf[i] = i < J ? (C)(ys[i] * ctl->vscale[i]) : C(0);
+  const int L = xcd_block(ln.G);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    const int e = g * VEC;
+    C acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = C(0);
+#pragma unroll
+    for (int i = 0; i < NDM; ++i) {
+      if (i < J) {
+        C vv[VEC];
+        loadv<C, S, VEC>(V + (size_t)i * vstride + e, vv);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] += cf[i] * vv[v];
+      }
+    }
+    storev<C, C, VEC>(t + e, acc);
+  }
+}
+
+// y += scale z (z = P^-1 t in the compute type) when the cycle produced a correction.
+template <typename C, int VEC>
+__global__ __launch_bounds__(TPB) void k_gm_update_ext(Launch ln, double* __restrict__ y,
+                                                       const C* __restrict__ z, Ctl* ctl) {
+  if (ctl->outer_done || ctl->J == 0 || ctl->nonfinite) return;  // no correction, or J beyond the bound
+  const double sc = ctl->scale;
+  const int L = xcd_block(ln.G);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    double yv[VEC];
+    C zv[VEC];
+    loadv<double, double, VEC>(y + g * VEC, yv);
+    loadv<C, C, VEC>(z + g * VEC, zv);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) yv[v] += sc * (double)zv[v];
+    storev<double, double, VEC>(y + g * VEC, yv);
   }
 }
 

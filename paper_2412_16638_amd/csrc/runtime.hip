@@ -398,11 +398,9 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
   if (p->precond != MPRK_PRECOND_NONE && p->precond != MPRK_PRECOND_BJ && p->precond != MPRK_PRECOND_FDM)
     return set_error(MPRK_EINVAL, "bad precond");
   if (p->precond == MPRK_PRECOND_FDM) {
-    // implemented case: the heat operator (real symmetric eigenbases) with CG
+    // implemented case: the heat operator (real symmetric eigenbases), with CG or GMRES
     if (op->kind != MPRK_OP_HEAT)
       return set_error(MPRK_EUNSUPPORTED, "fast-diagonalisation preconditioner implemented for the heat operator");
-    if (p->krylov != MPRK_CG)
-      return set_error(MPRK_EUNSUPPORTED, "fast-diagonalisation preconditioner implemented with CG");
   }
   if (p->precond == MPRK_PRECOND_BJ && !(p->block == 1 || p->block == 2 || p->block == 4 || p->block == 8))
     return set_error(MPRK_EINVAL, "block size must be 1, 2, 4 or 8");
@@ -529,7 +527,7 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
     o_V = 0;
   } else {
     o_V = take(vlp * (size_t)(p.restart + 1));
-    o_z = bs ? take(vlp) : 0;
+    o_z = (bs || fdm) ? take(vlp) : 0;
     o_r = o_p0 = o_p1 = o_q = o_x = 0;
   }
   vstride = vlp / lp_bytes;
@@ -838,6 +836,7 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
   const SolveCfg& cfg = cfgs[si];
   EngineCtx c = ctx();
   c.y = y;
+  c.fdm_sigma = cfg.sigma;
   const BJDesc dinv = bj_desc(si);
   const Coef<double> Mc = stage_coef(Kc, cfg.sigma);
   const bool cg = prec.krylov == MPRK_CG;

@@ -153,8 +153,9 @@ def test_fdm_preconditioner_scope_is_validated():
     p.precond = A.PRECOND_FDM
     rc, _ = _create(prec=p, kind=1, b=(1.0, 0.0, 0.0))
     assert rc == A.EUNSUPPORTED  # advection: complex eigenbasis not implemented
-    rc, _ = _create(prec=p)
-    assert rc == A.EUNSUPPORTED  # GMRES with this preconditioner not implemented
+    rc, h = _create(prec=p)
+    assert rc == A.OK, A.mprk_last_error()  # GMRES with the separately applied preconditioner
+    A.lib.mprk_destroy(h)
     p.precond = 3
     rc, _ = _create(prec=p)
     assert rc == A.EINVAL

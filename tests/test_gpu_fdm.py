@@ -69,3 +69,39 @@ def test_fdm_integration_matches_the_oracle(storage, bound):
     err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
     assert err <= bound, err
     assert max(stats['iters']) <= 8 * max(stats['passes']), stats
+
+
+@pytest.mark.parametrize("fmt", [A.FMT_STENCIL, A.FMT_CSR])
+@pytest.mark.parametrize("storage,bound", [('fp64', 1e-10), ('fp32', 1e-8), ('fp16', 1e-6)])
+def test_gmres_with_fdm_stage_solve_matches_sparse_lu(storage, bound, fmt):
+    """Right-preconditioned GMRES with the separately applied FDM inverse (begin, per-step and
+    end-of-cycle applies)."""
+    shape = (20, 16, 14)
+    log_case('fdm_gmres_solve', storage=storage, fmt=fmt)
+    prec = M.precisions(storage, 'gmres', precond='fdm', rtol=1e-12, atol=0.0)
+    st = M.Stepper(shape, W.DIRICHLET, W.HEAT, 1.3, (0, 0, 0), fmt, 'SDIRK3', prec, 5e-3)
+    rhs = np.random.default_rng(5).standard_normal(st.N)
+    x, info = st.solve(1, torch.from_numpy(rhs).cuda())
+    K = operators.operator(shape, W.DIRICHLET, W.HEAT, 1.3, (0, 0, 0))
+    Mx = operators.stage_matrix(K, 5e-3 * st.tab.a_lo[st.tab.s + 1] + 5e-3 * st.tab.a_hi[st.tab.s + 1])
+    ref = spla.spsolve(Mx.tocsc(), rhs)
+    st.close()
+    err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert info['converged'] == 1, info
+    assert err <= bound, (err, info)
+
+
+@pytest.mark.parametrize("storage,tol", [('fp32', 1e-6), ('fp16', 1e-3)])
+def test_gmres_with_fdm_integration(storage, tol):
+    p = W.heat_modes(n=28, nsteps=6)
+    p.precision = storage
+    p.krylov = 'gmres'
+    p.precond = 'fdm'
+    log_case('fdm_gmres_heat_28', storage=storage)
+    st = M.from_problem(p)
+    stats = st.step(p.nsteps)
+    u = st.get_u()
+    st.close()
+    ref = closed_form.evolve_heat(p.u0, p.diff, p.dt, p.nsteps, tableaus.by_name(p.tableau))
+    err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    assert err <= tol, (err, stats)
