@@ -27,17 +27,21 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .operators import second_difference_1d, spacing, upwind_difference_1d
+from .operators import central_difference_1d, second_difference_1d, spacing, upwind_difference_1d
 
 
 def one_d_factors(shape, bc: int, kind: int, diff: float, b=(0.0, 0.0, 0.0)):
-    """Dense 1-D operators (Kx, Ky, Kz) whose Kronecker sum is the semi-discrete K."""
+    """Dense 1-D operators (Kx, Ky, Kz) whose Kronecker sum is the semi-discrete K (kind 1:
+    upwind advection; kind 2: central, the factor Tridiag(-1, 0, 1) / (2h) with periodic corners
+    of Section "Advection equation")."""
     out = []
     for d, n in enumerate(shape):
         h = spacing(n, bc)
         Kd = diff * second_difference_1d(n, bc).toarray() / h ** 2
         if kind == 1 and b[d] != 0.0:
             Kd = Kd - b[d] * upwind_difference_1d(n, bc, b[d] >= 0.0).toarray() / h
+        elif kind == 2 and b[d] != 0.0:
+            Kd = Kd - b[d] * central_difference_1d(n, bc).toarray() / h
         out.append(Kd)
     return tuple(out)
 
