@@ -84,6 +84,12 @@ struct EngineCtx {
   void* fdm_t[2];
   double kappa;
   double fdm_sigma;  // sigma of the solve in progress (the end-of-cycle preconditioner apply)
+  // complex eigenbases (periodic advection operators): imaginary parts of the bases and
+  // eigenvalues, imaginary halves of the two scratch vectors
+  int fdm_cx;
+  const void* fdm_Qi[3];
+  const double* fdm_lami[3];
+  void* fdm_ti[2];
   // LP vectors (S*)
   void *r, *z, *p0, *p1, *q, *x;
   void* V;
@@ -271,16 +277,67 @@ class EngineT final : public Engine {
     const FdmGeo g{n, fdm_ldq(n), 0, nc, ld, bstride, nb, 0, skip};
     fdm_go<C, C>(c, g, 0, Q, in, out, sc);
   }
+  // complex-basis contractions: V4 dispatch as for the real ones
+  template <typename TI, typename TO, int INR, int OUTR, int V4>
+  void fdm_launch_cx(const EngineCtx& c, FdmGeo g, int row, const FdmCx& cx, const TI* in_r,
+                     const TI* in_i, TO* out_r, TO* out_i, const FdmScale& sc) {
+    const int n = g.n;
+    g.tiles = row ? ((g.nr + 63) / 64) * ((n + FT_N - 1) / FT_N)
+                  : ((n + 63) / 64) * ((g.nc + FT_N - 1) / FT_N) * g.nb;
+    const dim3 grid((unsigned)((g.tiles + 7) & ~7));
+    if (row)
+      hipLaunchKernelGGL((k_fdm_contract_cx<TI, TO, C, 1, V4, INR, OUTR>), grid, dim3(256), 0,
+                         c.stream, g, cx, in_r, in_i, out_r, out_i, sc, c.ctl);
+    else
+      hipLaunchKernelGGL((k_fdm_contract_cx<TI, TO, C, 0, V4, INR, OUTR>), grid, dim3(256), 0,
+                         c.stream, g, cx, in_r, in_i, out_r, out_i, sc, c.ctl);
+  }
+  template <typename TI, typename TO, int INR, int OUTR>
+  void fdm_go_cx(const EngineCtx& c, const FdmGeo& g, int row, const FdmCx& cx, const TI* in_r,
+                 const TI* in_i, TO* out_r, TO* out_i, const FdmScale& sc) {
+    if (c.geo.nx % 4 == 0) fdm_launch_cx<TI, TO, INR, OUTR, 1>(c, g, row, cx, in_r, in_i, out_r, out_i, sc);
+    else fdm_launch_cx<TI, TO, INR, OUTR, 0>(c, g, row, cx, in_r, in_i, out_r, out_i, sc);
+  }
+  // z = Re(conj(U) P_D^-1 U r), U the 3-D unitary DFT (axis by axis), for the circulant factors
+  // of the periodic advection operators; planar complex scratch (t0, t0i), (t1, t1i).
+  template <typename TI, typename TO>
+  void fdm_chain_cx(const EngineCtx& c, double sigma, const TI* in, TO* out, int skip) {
+    const int nx = c.geo.nx, ny = c.geo.ny, nz = c.geo.nz;
+    C* t0 = (C*)c.fdm_t[0];
+    C* t1 = (C*)c.fdm_t[1];
+    C* t0i = (C*)c.fdm_ti[0];
+    C* t1i = (C*)c.fdm_ti[1];
+    const FdmScale none{nullptr, nullptr, nullptr, 0.0, nx, 0};
+    const FdmScale sc{c.fdm_lam[0], c.fdm_lam[1], c.fdm_lam[2], sigma, nx, 1};
+    auto cxd = [&](int d, double sign) {
+      return FdmCx{c.fdm_Q[d], c.fdm_Qi[d], sign, c.fdm_lami[0], c.fdm_lami[1], c.fdm_lami[2]};
+    };
+    const FdmGeo gx{nx, fdm_ldq(nx), ny * nz, 0, 0, 0, 1, 0, skip};
+    const FdmGeo gy{ny, fdm_ldq(ny), 0, nx, nx, (long)nx * ny, nz, 0, skip};
+    const FdmGeo gz{nz, fdm_ldq(nz), 0, nx * ny, nx * ny, 0, 1, 0, skip};
+    if (c.prof) c.prof->before(KC_FDM, 6);
+    fdm_go_cx<TI, C, 1, 0>(c, gx, 1, cxd(0, 1.0), in, nullptr, t0, t0i, none);
+    fdm_go_cx<C, C, 0, 0>(c, gy, 0, cxd(1, 1.0), t0, t0i, t1, t1i, none);
+    fdm_go_cx<C, C, 0, 0>(c, gz, 0, cxd(2, 1.0), t1, t1i, t0, t0i, sc);
+    fdm_go_cx<C, C, 0, 0>(c, gz, 0, cxd(2, -1.0), t0, t0i, t1, t1i, none);
+    fdm_go_cx<C, C, 0, 0>(c, gy, 0, cxd(1, -1.0), t1, t1i, t0, t0i, none);
+    fdm_go_cx<C, TO, 0, 1>(c, gx, 1, cxd(0, -1.0), t0, t0i, out, nullptr, none);
+    if (c.prof) c.prof->after();
+  }
   // z = P^-1 r: T_R, T_M, T_L with the basis (its own inverse), P_D^-1, then back.  in and out
   // may be t1 (the chain never reads and writes one buffer in the same launch).  skip: the
   // launches return once the inner solve is done (inside a Krylov loop).
   template <typename TI, typename TO>
   void fdm_chain(const EngineCtx& c, double sigma, const TI* in, TO* out, int skip) {
+    if (c.fdm_cx) {
+      fdm_chain_cx<TI, TO>(c, sigma, in, out, skip);
+      return;
+    }
     const int nx = c.geo.nx, ny = c.geo.ny, nz = c.geo.nz;
     C* t0 = (C*)c.fdm_t[0];
     C* t1 = (C*)c.fdm_t[1];
     const FdmScale none{nullptr, nullptr, nullptr, 0.0, nx, 0};
-    const FdmScale sc{c.fdm_lam[0], c.fdm_lam[1], c.fdm_lam[2], sigma * c.kappa, nx, 1};
+    const FdmScale sc{c.fdm_lam[0], c.fdm_lam[1], c.fdm_lam[2], sigma, nx, 1};
     if (c.prof) c.prof->before(KC_FDM, 6);
     fdm_row<TI, C>(c, nx, ny * nz, c.fdm_Q[0], in, t0, skip);
     fdm_col(c, ny, nx, nx, (long)nx * ny, nz, c.fdm_Q[1], t0, t1, none, skip);

@@ -281,9 +281,241 @@ __global__ __launch_bounds__(256) void k_fdm_contract(FdmGeo g, const C* __restr
       }
 }
 
+// Complex eigenbases (the periodic advection operators: circulant 1-D factors, diagonalised by
+// the unitary DFT Q_{aq} = e^{-2 pi i a q / n} / sqrt(n), inverse conj(Q)).  Planar storage: a
+// complex array is a real and an imaginary array of the compute type.
+struct FdmCx {
+  const void* qr;   // Re Q (n x ldq)
+  const void* qi;   // Im Q
+  double qsign;     // +1: Q (forward), -1: conj(Q) (backward)
+  const double* lxi;  // imaginary parts of the axis eigenvalues (real parts in FdmScale)
+  const double* lyi;
+  const double* lzi;
+};
+
+// One contraction with the complex basis on the matrix cores: the tile layout, staging and
+// k-order of k_fdm_contract, with a real and an imaginary tile per operand and four real
+// products per complex one (two when the data operand is real, INR, or only the real part of
+// the result is kept, OUTR).  The epilogue of the forward z contraction divides by the complex
+// P_D = 1 - sk (lx + ly + lz).
+template <typename TI, typename TO, typename C, int ROW, int V4, int INR, int OUTR>
+__global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
+                                                         const TI* __restrict__ in_r,
+                                                         const TI* __restrict__ in_i,
+                                                         TO* __restrict__ out_r,
+                                                         TO* __restrict__ out_i, FdmScale sc,
+                                                         Ctl* ctl) {
+  static_assert(!(INR && OUTR), "a contraction of the chain has a complex side");
+  if (ctl->outer_done | (g.skip_inner & ctl->inner_done)) return;
+  count_work(ctl, KC_FDM, g.n);
+  constexpr int BM = 64, KC = FT_KC, PK = KC + 4, PN = FT_N + 4, KV = KC / 4;
+  typedef typename Mfma<C>::acc Acc;
+  const C* Qr = (const C*)cx.qr;
+  const C* Qi = (const C*)cx.qi;
+  const C qs = (C)cx.qsign;
+  // As: the operand indexed by the output row ([m][k]); Bs: ROW [n][k], COL [k][n]
+  __shared__ __align__(32) C Ar_s[BM][PK];
+  __shared__ __align__(32) C Ai_s[BM][PK];
+  __shared__ __align__(32) C Br_s[ROW ? FT_N : KC][ROW ? PK : PN];
+  __shared__ __align__(32) C Bi_s[ROW ? FT_N : KC][ROW ? PK : PN];
+  const int n = g.n;
+  const int T = xcd_block((g.tiles + 7) & ~7);
+  if (T >= g.tiles) return;
+  int mt, nt, b = 0;
+  if constexpr (ROW) {
+    const int NT = (n + FT_N - 1) / FT_N;
+    nt = T % NT;
+    mt = T / NT;
+  } else {
+    const int MT = (n + BM - 1) / BM, NT = (g.nc + FT_N - 1) / FT_N;
+    mt = T % MT;
+    nt = (T / MT) % NT;
+    b = T / (MT * NT);
+  }
+  const int m0 = mt * BM, n0 = nt * FT_N;
+  const size_t boff = ROW ? 0 : (size_t)b * g.bstride;
+  const int tid = threadIdx.x;
+  auto zero4 = [](Vec<C, 4>& v) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v.v[j] = C(0);
+  };
+  auto load_q = [&](Vec<C, 4>& vr, Vec<C, 4>& vi, int a, int q) {
+    if (a < n && q < g.ldq) {
+      vr = *reinterpret_cast<const Vec<C, 4>*>(Qr + (size_t)a * g.ldq + q);
+      vi = *reinterpret_cast<const Vec<C, 4>*>(Qi + (size_t)a * g.ldq + q);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) vi.v[j] *= qs;
+    } else {
+      zero4(vr);
+      zero4(vi);
+    }
+  };
+  // 4 consecutive data elements at src (row-contiguous), masked by `ok` / per element by lim
+  auto load_data = [&](Vec<C, 4>& v, const TI* src, bool ok, int lim) {
+    if constexpr (V4) {
+      if (ok) {
+        const Vec<TI, 4> t = *reinterpret_cast<const Vec<TI, 4>*>(src);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v.v[j] = (C)t.v[j];
+      } else {
+        zero4(v);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v.v[j] = (ok && j < lim) ? (C)src[j] : C(0);
+    }
+  };
+  Vec<C, 4> rar[2], rai[2], rbr[2], rbi[2];
+  auto load_chunk = [&](int q0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + u * 256;
+      const int row = e / KV, q = q0 + (e % KV) * 4;
+      if constexpr (ROW) {
+        const int r = m0 + row;
+        const size_t off = (size_t)r * n + q;
+        load_data(rar[u], in_r + off, r < g.nr && q < n, n - q);
+        if constexpr (!INR) load_data(rai[u], in_i + off, r < g.nr && q < n, n - q);
+        load_q(rbr[u], rbi[u], n0 + row, q);
+      } else {
+        load_q(rar[u], rai[u], m0 + row, q);
+        const int kk = e >> 4, c = n0 + (e & 15) * 4, qq = q0 + kk;
+        const size_t off = boff + (size_t)qq * g.ld + c;
+        load_data(rbr[u], in_r + off, qq < n && c < g.nc, g.nc - c);
+        if constexpr (!INR) load_data(rbi[u], in_i + off, qq < n && c < g.nc, g.nc - c);
+      }
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + u * 256;
+      const int row = e / KV, kq = (e % KV) * 4;
+      *reinterpret_cast<Vec<C, 4>*>(&Ar_s[row][kq]) = rar[u];
+      if constexpr (!(ROW && INR)) *reinterpret_cast<Vec<C, 4>*>(&Ai_s[row][kq]) = rai[u];
+      if constexpr (ROW) {
+        *reinterpret_cast<Vec<C, 4>*>(&Br_s[row][kq]) = rbr[u];
+        *reinterpret_cast<Vec<C, 4>*>(&Bi_s[row][kq]) = rbi[u];
+      } else {
+        *reinterpret_cast<Vec<C, 4>*>(&Br_s[e >> 4][(e & 15) * 4]) = rbr[u];
+        if constexpr (!INR) *reinterpret_cast<Vec<C, 4>*>(&Bi_s[e >> 4][(e & 15) * 4]) = rbi[u];
+      }
+    }
+  };
+  const int lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  // the data operand's imaginary part is zero (INR): A for ROW, B for COL
+  constexpr bool AR = ROW && INR, BR = !ROW && INR;
+  Acc accr[2][2], acci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accr[i][j] = Acc{};
+      acci[i][j] = Acc{};
+    }
+  load_chunk(0);
+  for (int q0 = 0; q0 < n; q0 += KC) {
+    store_chunk();
+    __syncthreads();
+    if (q0 + KC < n) load_chunk(q0 + KC);
+#pragma unroll
+    for (int kb = 0; kb < KC; kb += 16) {
+      const int k = kb + 4 * g4;
+      Vec<C, 4> avr[2], avi[2], bvr[2], bvi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        avr[i] = *reinterpret_cast<const Vec<C, 4>*>(&Ar_s[wm + 16 * i + l16][k]);
+        if constexpr (!AR) avi[i] = *reinterpret_cast<const Vec<C, 4>*>(&Ai_s[wm + 16 * i + l16][k]);
+        if constexpr (ROW) {
+          bvr[i] = *reinterpret_cast<const Vec<C, 4>*>(&Br_s[wn + 16 * i + l16][k]);
+          bvi[i] = *reinterpret_cast<const Vec<C, 4>*>(&Bi_s[wn + 16 * i + l16][k]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            bvr[i].v[j] = Br_s[k + j][wn + 16 * i + l16];
+            if constexpr (!BR) bvi[i].v[j] = Bi_s[k + j][wn + 16 * i + l16];
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni) {
+            // re += Ar Br - Ai Bi ; im += Ar Bi + Ai Br
+            accr[mi][ni] = Mfma<C>::op(avr[mi].v[j], bvr[ni].v[j], accr[mi][ni]);
+            if constexpr (!AR && !BR) accr[mi][ni] = Mfma<C>::op(-avi[mi].v[j], bvi[ni].v[j], accr[mi][ni]);
+            if constexpr (!OUTR) {
+              if constexpr (!BR) acci[mi][ni] = Mfma<C>::op(avr[mi].v[j], bvi[ni].v[j], acci[mi][ni]);
+              if constexpr (!AR) acci[mi][ni] = Mfma<C>::op(avi[mi].v[j], bvr[ni].v[j], acci[mi][ni]);
+            }
+          }
+    }
+    __syncthreads();
+  }
+  // complex P_D factors of this lane's rows and columns (indices clamped in range)
+  double sxr[2] = {0.0, 0.0}, sxi[2] = {0.0, 0.0}, szr[2][4] = {}, szi[2][4] = {};
+  if constexpr (!ROW) {
+    if (sc.on) {
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        const int col = min(n0 + wn + 16 * ni + l16, g.nc - 1);
+        const int ix = col % sc.nx, jy = col / sc.nx;
+        sxr[ni] = sc.lx[ix] + sc.ly[jy];
+        sxi[ni] = cx.lxi[ix] + cx.lyi[jy];
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = min(m0 + wm + 16 * mi + Mfma<C>::row(g4, i), n - 1);
+          szr[mi][i] = sc.lz[m];
+          szi[mi][i] = cx.lzi[m];
+        }
+    }
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = m0 + wm + 16 * mi + Mfma<C>::row(g4, i);
+        const int col = n0 + wn + 16 * ni + l16;
+        C vr = accr[mi][ni][i], vi = OUTR ? C(0) : acci[mi][ni][i];
+        if constexpr (!ROW) {
+          if (sc.on) {  // (vr + i vi) / (dr + i di)
+            const double dr = 1.0 - sc.sk * (sxr[ni] + szr[mi][i]);
+            const double di = -sc.sk * (sxi[ni] + szi[mi][i]);
+            const double den = dr * dr + di * di;
+            const double xr = ((double)vr * dr + (double)vi * di) / den;
+            const double xi = ((double)vi * dr - (double)vr * di) / den;
+            vr = (C)xr;
+            vi = (C)xi;
+          }
+        }
+        size_t off;
+        bool ok;
+        if constexpr (ROW) {
+          ok = m < g.nr && col < n;
+          off = (size_t)m * n + col;
+        } else {
+          ok = m < n && col < g.nc;
+          off = boff + (size_t)m * g.ld + col;
+        }
+        if (ok) {
+          out_r[off] = (TO)vr;
+          if constexpr (!OUTR) out_i[off] = (TO)vi;
+        }
+      }
+}
+
 // Host-side description of one axis: orthogonal symmetric eigenbasis Q (n x n, row-major) and
-// eigenvalues lam of the unscaled 1-D second difference divided by h^2 (so that the axis factor
-// of sigma K is sigma kappa lam).
+// eigenvalues lam of the unscaled 1-D second difference divided by h^2 (the caller multiplies
+// them by kappa, so that the axis factor of sigma K is sigma lam).
 //   Dirichlet (h = 1/(n+1)): Q_{ik} = sqrt(2/(n+1)) sin(pi (i+1)(k+1)/(n+1)),
 //     lam_k = -(4/h^2) sin^2(pi (k+1) h / 2);
 //   periodic (h = 1/n): Q_{ik} = (cos(2 pi i k/n) + sin(2 pi i k/n)) / sqrt(n) (Hartley),
@@ -314,6 +546,27 @@ inline void fdm_axis_basis(int n, int periodic, double* Q, double* lam) {
   }
 }
 
+// Periodic advection axis (h = 1/n): the 1-D factor nu D2 / h^2 - b D1 / h is circulant, so the
+// unitary DFT Q_{aq} = e^{-2 pi i a q / n} / sqrt(n) diagonalises it, with eigenvalue (theta =
+// 2 pi k / n) nu (2 cos theta - 2) / h^2 - |b| (1 - cos theta) / h - i b sin theta / h for the
+// upwind difference (backward for b >= 0, forward for b < 0) and the same without the |b| term
+// for the central difference.
+inline void fdm_axis_dft(int n, bool central, double nu, double b, double* Qr, double* Qi,
+                         double* lr, double* li) {
+  const double pi = 3.14159265358979323846;
+  const double h = 1.0 / n, s = 1.0 / std::sqrt((double)n);
+  for (int a = 0; a < n; ++a)
+    for (int q = 0; q < n; ++q) {
+      const double th = 2.0 * pi * (double)(((long)a * q) % n) / n;
+      Qr[(size_t)a * n + q] = s * std::cos(th);
+      Qi[(size_t)a * n + q] = -s * std::sin(th);
+    }
+  for (int k = 0; k < n; ++k) {
+    const double th = 2.0 * pi * k / n;
+    lr[k] = nu * (2.0 * std::cos(th) - 2.0) / (h * h) - (central ? 0.0 : std::fabs(b) * (1.0 - std::cos(th)) / h);
+    li[k] = -b * std::sin(th) / h;
+  }
+}
 
 // ------------------------------------------------------------------------------------------
 // CG with a preconditioner applied by separate launches (the contractions above): the

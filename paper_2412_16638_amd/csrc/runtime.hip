@@ -398,9 +398,11 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
   if (p->precond != MPRK_PRECOND_NONE && p->precond != MPRK_PRECOND_BJ && p->precond != MPRK_PRECOND_FDM)
     return set_error(MPRK_EINVAL, "bad precond");
   if (p->precond == MPRK_PRECOND_FDM) {
-    // implemented case: the heat operator (real symmetric eigenbases), with CG or GMRES
-    if (op->kind != MPRK_OP_HEAT)
-      return set_error(MPRK_EUNSUPPORTED, "fast-diagonalisation preconditioner implemented for the heat operator");
+    // implemented cases: the heat operator (real symmetric eigenbases) and the periodic
+    // advection operators (circulant factors, the complex DFT basis), with CG or GMRES
+    if (op->kind != MPRK_OP_HEAT && g->bc != MPRK_BC_PERIODIC)
+      return set_error(MPRK_EUNSUPPORTED,
+                       "fast-diagonalisation preconditioner for advection needs periodic boundaries");
   }
   if (p->precond == MPRK_PRECOND_BJ && !(p->block == 1 || p->block == 2 || p->block == 4 || p->block == 8))
     return set_error(MPRK_EINVAL, "block size must be 1, 2, 4 or 8");
@@ -555,15 +557,22 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
     o_kval = take((size_t)nnz * 8);
     o_mval = take((size_t)nnz * lp_bytes);
   }
+  fdm_cx = fdm && o.kind != MPRK_OP_HEAT;
   if (fdm) {
     const size_t cb = p.compute == MPRK_FP64 ? 8 : 4;
     const int n3[3] = {g.nx, g.ny, g.nz};
     for (int d = 0; d < 3; ++d) {
       o_fdm_Q[d] = take((size_t)n3[d] * fdm_ldq(n3[d]) * cb);  // rows padded to fdm_ldq
       o_fdm_lam[d] = take((size_t)n3[d] * 8);
+      if (fdm_cx) {
+        o_fdm_Qi[d] = take((size_t)n3[d] * fdm_ldq(n3[d]) * cb);
+        o_fdm_lami[d] = take((size_t)n3[d] * 8);
+      }
     }
-    o_fdm_t[0] = take((size_t)N * cb);
-    o_fdm_t[1] = take((size_t)N * cb);
+    for (int k = 0; k < 2; ++k) {
+      o_fdm_t[k] = take((size_t)N * cb);
+      if (fdm_cx) o_fdm_ti[k] = take((size_t)N * cb);
+    }
   }
   o_ctl = take(sizeof(Ctl));
   o_flag = take(256);
@@ -646,6 +655,12 @@ EngineCtx mprk_handle::ctx() const {
   }
   c.fdm_t[0] = fdm ? ws + o_fdm_t[0] : nullptr;
   c.fdm_t[1] = fdm ? ws + o_fdm_t[1] : nullptr;
+  c.fdm_cx = fdm_cx ? 1 : 0;
+  for (int d = 0; d < 3; ++d) {
+    c.fdm_Qi[d] = fdm_cx ? ws + o_fdm_Qi[d] : nullptr;
+    c.fdm_lami[d] = fdm_cx ? (const double*)(ws + o_fdm_lami[d]) : nullptr;
+  }
+  for (int k = 0; k < 2; ++k) c.fdm_ti[k] = fdm_cx ? ws + o_fdm_ti[k] : nullptr;
   c.kappa = op.diff;
   c.r = ws + o_r;
   c.z = ws + o_z;
@@ -704,23 +719,41 @@ extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev,
                                       B.mode == 3 ? h->vec_lp : 0));
   }
   if (h->fdm) {
-    // fast-diagonalisation: per-axis eigenbasis (compute type) and eigenvalues (FP64)
+    // fast-diagonalisation: per-axis eigenbasis (compute type, rows padded with zeros to
+    // fdm_ldq) and eigenvalues (FP64); complex for the periodic advection operators
     const int n3[3] = {h->grid.nx, h->grid.ny, h->grid.nz};
     const bool f64 = h->prec.compute == MPRK_FP64;
-    for (int d = 0; d < 3; ++d) {
-      const int n = n3[d];
-      std::vector<double> Q((size_t)n * n), lam(n);
-      fdm_axis_basis(n, h->grid.bc == MPRK_BC_PERIODIC, Q.data(), lam.data());
-      const int ldq = fdm_ldq(n);  // rows padded with zeros
+    auto upload = [&](size_t off, const std::vector<double>& Q, int n) -> int {
+      const int ldq = fdm_ldq(n);
       std::vector<double> Qp((size_t)n * ldq, 0.0);
       for (int a = 0; a < n; ++a)
         for (int q = 0; q < n; ++q) Qp[(size_t)a * ldq + q] = Q[(size_t)a * n + q];
       if (f64) {
-        HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_Q[d], Qp.data(), Qp.size() * 8, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->ws + off, Qp.data(), Qp.size() * 8, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
       } else {
         std::vector<float> Qf(Qp.begin(), Qp.end());
-        HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_Q[d], Qf.data(), Qf.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->ws + off, Qf.data(), Qf.size() * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));  // Qf goes out of scope
+      }
+      return MPRK_OK;
+    };
+    for (int d = 0; d < 3; ++d) {
+      const int n = n3[d];
+      std::vector<double> Q((size_t)n * n), lam(n);
+      if (!h->fdm_cx) {
+        fdm_axis_basis(n, h->grid.bc == MPRK_BC_PERIODIC, Q.data(), lam.data());
+        for (auto& l : lam) l *= h->op.diff;  // the axis factor of sigma K is sigma lam
+        int rc = upload(h->o_fdm_Q[d], Q, n);
+        if (rc) return rc;
+      } else {
+        std::vector<double> Qi((size_t)n * n), lami(n);
+        fdm_axis_dft(n, h->op.kind == MPRK_OP_CENTRAL, h->op.diff, h->op.b[d], Q.data(), Qi.data(),
+                     lam.data(), lami.data());
+        int rc = upload(h->o_fdm_Q[d], Q, n);
+        if (!rc) rc = upload(h->o_fdm_Qi[d], Qi, n);
+        if (rc) return rc;
+        HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_lami[d], lami.data(), lami.size() * 8, hipMemcpyHostToDevice, h->stream));
       }
       HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_lam[d], lam.data(), lam.size() * 8, hipMemcpyHostToDevice, h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));

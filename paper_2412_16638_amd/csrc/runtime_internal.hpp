@@ -75,6 +75,8 @@ struct mprk_handle {
   size_t o_ctl = 0, o_flag = 0, o_part = 0, o_part2 = 0, o_tick = 0;
   bool fdm = false;  // fast-diagonalisation preconditioner
   size_t o_fdm_Q[3] = {}, o_fdm_lam[3] = {}, o_fdm_t[2] = {};
+  bool fdm_cx = false;  // complex eigenbases (periodic advection): imaginary parts below
+  size_t o_fdm_Qi[3] = {}, o_fdm_lami[3] = {}, o_fdm_ti[2] = {};
   size_t ws_bytes = 0;
   const double* force = nullptr;  // constant forcing g (caller-owned, N doubles) or null
   // binding

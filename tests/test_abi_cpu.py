@@ -152,7 +152,11 @@ def test_fdm_preconditioner_scope_is_validated():
     p = A.mprk_precisions_default(A.FP32, A.GMRES)
     p.precond = A.PRECOND_FDM
     rc, _ = _create(prec=p, kind=1, b=(1.0, 0.0, 0.0))
-    assert rc == A.EUNSUPPORTED  # advection: complex eigenbasis not implemented
+    assert rc == A.EUNSUPPORTED  # advection with Dirichlet ends: factors not diagonalisable by the DFT
+    for kind in (1, 2):
+        rc, h = _create(prec=p, kind=kind, b=(1.0, 0.5, 0.25), bc=1, grid=(12, 10, 8))
+        assert rc == A.OK, A.mprk_last_error()  # periodic advection: the complex DFT basis
+        A.lib.mprk_destroy(h)
     rc, h = _create(prec=p)
     assert rc == A.OK, A.mprk_last_error()  # GMRES with the separately applied preconditioner
     A.lib.mprk_destroy(h)

@@ -105,3 +105,83 @@ def test_gmres_with_fdm_integration(storage, tol):
     ref = closed_form.evolve_heat(p.u0, p.diff, p.dt, p.nsteps, tableaus.by_name(p.tableau))
     err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
     assert err <= tol, (err, stats)
+
+
+ADV_CASES = [
+    # shape, kind, diff, b : periodic advection operators (complex DFT basis on the GPU)
+    ((16, 12, 10), W.ADVDIFF, 1e-2, (1.0, 0.5, -0.25)),
+    ((14, 10, 8), W.CENTRAL, 0.0, (1.0, 1.0, 1.0)),
+    ((18, 10, 9), W.CENTRAL, 2e-2, (1.0, -0.7, 0.3)),     # nx % 4 != 0: element-wise loads
+    ((70, 66, 65), W.ADVDIFF, 1e-2, (1.0, 0.5, 0.25)),    # ragged tiles
+]
+
+
+@pytest.mark.parametrize("storage", ['fp64', 'fp32', 'fp16'])
+@pytest.mark.parametrize("case", ADV_CASES)
+def test_complex_fdm_apply_is_the_stage_inverse(case, storage):
+    """For the periodic advection operators P equals the stage matrix, so P^-1 x is its exact
+    inverse: ifftn(fftn(x) / (1 - sigma lambda)) with the oracle's Fourier symbol, pinned to the
+    sparse operator (independent of the oracle's general eigensolver, whose bases lose accuracy
+    where pure central advection repeats eigenvalues)."""
+    shape, kind, diff, b = case
+    log_case('fdm_cx_apply', shape=shape, kind=kind, storage=storage)
+    prec = M.precisions(storage, 'gmres', precond='fdm')
+    st = M.Stepper(shape, W.PERIODIC, kind, diff, b, A.FMT_STENCIL, 'SDIRK3', prec, 2e-3)
+    sigma = st.dt * (st.tab.a_hi[0] + st.tab.a_lo[0])
+    x = np.random.default_rng(12).standard_normal(st.N)
+    xd = torch.from_numpy(x).to('cuda', DT[storage])
+    y = st.apply(A.APPLY_FDM_LP, xd, stage=0).double().cpu().numpy()
+    lam = closed_form.periodic_eigenvalues(shape, diff, b, central=kind == W.CENTRAL)
+    xr = xd.double().cpu().numpy().reshape(shape[::-1])
+    ref = np.real(np.fft.ifftn(np.fft.fftn(xr) / (1.0 - sigma * lam))).ravel()
+    st.close()
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    assert err <= TOL[storage], err
+
+
+def test_complex_fdm_apply_matches_the_oracle_eigendecomposition():
+    shape, kind, diff, b = ADV_CASES[0]
+    log_case('fdm_cx_oracle')
+    prec = M.precisions('fp64', 'gmres', precond='fdm')
+    st = M.Stepper(shape, W.PERIODIC, kind, diff, b, A.FMT_STENCIL, 'SDIRK3', prec, 2e-3)
+    sigma = st.dt * (st.tab.a_hi[0] + st.tab.a_lo[0])
+    x = np.random.default_rng(13).standard_normal(st.N)
+    y = st.apply(A.APPLY_FDM_LP, torch.from_numpy(x).cuda(), stage=0).cpu().numpy()
+    ref = fdm.FDM(shape, W.PERIODIC, kind, diff, b, sigma).apply(x)
+    st.close()
+    assert np.linalg.norm(y - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("storage,bound", [('fp64', 1e-10), ('fp32', 1e-8), ('fp16', 1e-6)])
+@pytest.mark.parametrize("kind", [W.ADVDIFF, W.CENTRAL])
+def test_gmres_with_complex_fdm_stage_solve(kind, storage, bound):
+    shape, b = (20, 16, 12), (1.0, 0.5, 0.25)
+    log_case('fdm_cx_solve', kind=kind, storage=storage)
+    prec = M.precisions(storage, 'gmres', precond='fdm', rtol=1e-12, atol=0.0)
+    st = M.Stepper(shape, W.PERIODIC, kind, 1e-2, b, A.FMT_STENCIL, 'SDIRK3', prec, 5e-3)
+    rhs = np.random.default_rng(6).standard_normal(st.N)
+    x, info = st.solve(1, torch.from_numpy(rhs).cuda())
+    Mx = operators.stage_matrix(operators.operator(shape, W.PERIODIC, kind, 1e-2, b),
+                                5e-3 * (st.tab.a_lo[st.tab.s + 1] + st.tab.a_hi[st.tab.s + 1]))
+    ref = spla.spsolve(Mx.tocsc(), rhs)
+    st.close()
+    err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert info['converged'] == 1, info
+    assert err <= bound, (err, info)
+    if storage == 'fp64':  # the exact inverse
+        assert info['iters'] <= 2 * info['passes'], info
+
+
+@pytest.mark.parametrize("storage,tol", [('fp32', 1e-6), ('fp16', 1e-3)])
+def test_advection_integration_with_complex_fdm(storage, tol):
+    p = W.advdiff_bump(n=24, nsteps=6)
+    p.precision = storage
+    p.precond = 'fdm'
+    log_case('fdm_cx_advdiff_24', storage=storage)
+    st = M.from_problem(p)
+    stats = st.step(p.nsteps)
+    u = st.get_u()
+    st.close()
+    ref = closed_form.evolve(p.u0, p.kind, p.bc, p.diff, p.b, p.dt, p.nsteps, tableaus.by_name(p.tableau))
+    err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    assert err <= tol, (err, stats)
