@@ -99,25 +99,34 @@ def oracle_reference(p):
     return ref, time.perf_counter() - t0
 
 
+def workload_name(args) -> str:
+    """The configuration a step-mode line measures, named by what it is."""
+    pc = 'fdm' if args.precond == 'fdm' else 'bj8'
+    base = (f'advdiff_upwind_periodic_256^3_sdirk3_dt2e-3_gmres30_{pc}_fp16'
+            if args.workload == 'advdiff256' else f'heat_dirichlet_128^3_sdirk3_dt5e-4_cg_{pc}_fp32')
+    return base + ('_fp64arith' if args.compute == 'fp64' else '')
+
+
 def cpu_oracle_rate(workload: str, precond: str = 'bj'):
     """The oracle stepping the method on the host: FP64 DIRK with its own Krylov stage solver
     (GMRES(30) or CG + block-Jacobi(8), rtol 1e-10), one thread, setup excluded.  The sample is
     one step of the workload's PDE on a smaller grid (128^3 for the 256^3 advection-diffusion
     run, 96^3 for the 128^3 heat run), sized to 10-30 s of CPU work.  With the fast-
-    diagonalisation preconditioner the oracle's CG uses its FDM inverse, and the sample is eight
-    steps of the 128^3 heat workload itself."""
+    diagonalisation preconditioner the oracle's Krylov solver uses its FDM inverse, and the
+    sample is eight steps of the 128^3 heat workload itself, or one step of the advection-
+    diffusion problem on 96^3 (complex bases)."""
     from threadpoolctl import threadpool_limits
     import workloads as W
     from oracle import dirk, operators, tableaus
     fdm = precond == 'fdm'
-    p = (W.advdiff_bump(n=128) if workload == 'advdiff256'
+    p = (W.advdiff_bump(n=96 if fdm else 128) if workload == 'advdiff256'
          else W.heat_modes(n=128 if fdm else 96))
     K = operators.operator((p.n,) * 3, p.bc, p.kind, p.diff, p.b)
     tab = tableaus.by_name(p.tableau)
     solve = dirk.StageSolver(K, 'gmres' if p.krylov == 'gmres' else 'cg', rtol=1e-10, block=8,
                              restart=30,
                              fdm_problem=((p.n,) * 3, p.bc, p.kind, p.diff, p.b) if fdm else None)
-    steps = 8 if fdm else 1
+    steps = 8 if fdm and workload != 'advdiff256' else 1
     u = np.asarray(p.u0, dtype=np.float64).ravel().copy()
     with threadpool_limits(limits=1):
         for i in range(tab.s):
@@ -207,7 +216,8 @@ def main():
                     help='block-Jacobi inverse storage of the headline run')
     ap.add_argument('--precond', default='bj', choices=['bj', 'fdm'],
                     help='stage-solve preconditioner: block-Jacobi(8) (the configurations) or the '
-                         'paper\'s fast-diagonalisation one (heat128 only)')
+                         'paper\'s fast-diagonalisation one (real basis for heat, complex DFT '
+                         'basis with GMRES for the periodic advection-diffusion)')
     ap.add_argument('--compute', default='fp32', choices=['fp32', 'fp64'],
                     help='arithmetic of the low-precision solves: fp32 (the configurations) or '
                          'fp64 over the same storage (compressed-basis Krylov)')
@@ -243,8 +253,6 @@ def main():
         torch.cuda.synchronize()
         log(f'calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written')
         del src, dst
-    if args.precond == 'fdm' and args.workload != 'heat128':
-        raise SystemExit('--precond fdm is implemented for the heat workload (heat128)')
     p = make_problem(args.workload, args.precond)
     mixed_over = dict(MIXED_TOL[args.workload])
     if args.compute == 'fp64':
@@ -330,8 +338,11 @@ def main():
             # counters give bytes per working dispatch; spread over all launches like `achieved`
             traffic = tr['bytes_per_worked_launch'] * r['worked'] / r['launches']
     if kc == 'fdm':
-        # the contractions are dense: 2 n flops per unknown per launch (n = axis length)
-        flops_per_launch = 2.0 * r['units'] * N / r['launches']
+        # the contractions are dense: 2 n flops per unknown per launch (n = axis length); with
+        # the complex basis of the advection operator an apply does 20 real products per
+        # unknown and axis point instead of 6 (2 at each real end, 4 in the four middle ones)
+        cxf = 20.0 / 6.0 if p.kind != 0 else 1.0
+        flops_per_launch = 2.0 * r['units'] * N / r['launches'] * cxf
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
         peak = MFMA_PEAK['fp64' if args.compute == 'fp64' else p.precision]
         roofline = {'bound': 'mfma', 'kernel': kc, 'achieved': round(achieved, 2), 'peak': peak,
@@ -413,12 +424,7 @@ def main():
         'warmup': Wm, 'ms_per_step': t_mixed * 1e3 / K, 'higher_is_better': True,
         'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64' if args.compute == 'fp64' else 'f32',
         'data': 'synthetic',
-        'config': {'workload': ('advdiff_upwind_periodic_256^3_sdirk3_dt2e-3_gmres30_bj8_fp16'
-                                if args.workload == 'advdiff256'
-                                else 'heat_dirichlet_128^3_sdirk3_dt5e-4_cg_bj8_fp32'
-                                if args.precond == 'bj'
-                                else 'heat_dirichlet_128^3_sdirk3_dt5e-4_cg_fdm_fp32')
-                               + ('_fp64arith' if args.compute == 'fp64' else ''),
+        'config': {'workload': workload_name(args),
                    'N': N, 'format': args.fmt, 'lp_storage': p.precision,
                    'lp_compute': 'f64' if args.compute == 'fp64' else 'f32',
                    'explicit_parts': 'f64', 'krylov': p.krylov},
@@ -474,8 +480,8 @@ def bench_sweep(args):
             return W.paper_heat(n, tab, tau, T, prec)
         return W.paper_advection(n, tab, tau, T, prec)
 
-    def run(p, tol, maxit=40, **extra):
-        p.precond = 'fdm' if p.kind == W.HEAT else 'bj'
+    def run(p, tol, maxit=40, precond=None, **extra):
+        p.precond = precond or ('fdm' if p.kind == W.HEAT else 'bj')
         over = {} if p.kind == W.HEAT else {'restart': 32}  # the longest GMRES cycle built
         st = M.from_problem(p, rtol=tol, atol=tol, maxit=maxit, refine_max=0, **over, **extra)
         torch.cuda.synchronize()
@@ -530,6 +536,15 @@ def bench_sweep(args):
                 rec[prec + '_ms'] = round(t * 1e3, 3)
             iters.append(rec)
             log(f"iterations {prob:9s} tol={tol:.0e}: fp32 {rec['fp32']} fp64 {rec['fp64']} per solve")
+    # the advection problem with the paper's own preconditioner (complex FDM), as in its table
+    for tol in (1e-3, 1e-4, 1e-5, 1e-6, 1e-8):
+        rec = {'problem': 'advection', 'precond': 'fdm', 'tol': tol}
+        for prec in ('fp32', 'fp64'):
+            _, stats, t = run(make('advection', '4S3PC', 1 / 80, prec), tol, precond='fdm')
+            rec[prec] = round(stats['total_iters'] / max(1, stats['total_passes']), 2)
+            rec[prec + '_ms'] = round(t * 1e3, 3)
+        iters.append(rec)
+        log(f"iterations advection+FDM tol={tol:.0e}: fp32 {rec['fp32']} fp64 {rec['fp64']} per solve")
     # FP16 storage with FP32 against FP64 arithmetic (compressed basis), same setting, method C,
     # tau = 1/80: the error of the one-solve-per-stage integration against the exact-solve DIRK
     cbrows = []
