@@ -110,10 +110,10 @@ def workload_name(args) -> str:
 def cpu_oracle_rate(workload: str, precond: str = 'bj'):
     """The oracle stepping the method on the host: FP64 DIRK with its own Krylov stage solver
     (GMRES(30) or CG + block-Jacobi(8), rtol 1e-10), one thread, setup excluded.  The sample is
-    one step of the workload's PDE on a smaller grid (128^3 for the 256^3 advection-diffusion
+    two steps of the workload's PDE on a smaller grid (128^3 for the 256^3 advection-diffusion
     run, 96^3 for the 128^3 heat run), sized to 10-30 s of CPU work.  With the fast-
     diagonalisation preconditioner the oracle's Krylov solver uses its FDM inverse, and the
-    sample is eight steps of the 128^3 heat workload itself, or one step of the advection-
+    sample is eight steps of the 128^3 heat workload itself, or three steps of the advection-
     diffusion problem on 96^3 (complex bases)."""
     from threadpoolctl import threadpool_limits
     import workloads as W
@@ -126,7 +126,9 @@ def cpu_oracle_rate(workload: str, precond: str = 'bj'):
     solve = dirk.StageSolver(K, 'gmres' if p.krylov == 'gmres' else 'cg', rtol=1e-10, block=8,
                              restart=30,
                              fdm_problem=((p.n,) * 3, p.bc, p.kind, p.diff, p.b) if fdm else None)
-    steps = 8 if fdm and workload != 'advdiff256' else 1
+    # steps sized to 10-30 s of host work: the BJ samples take ~6-10 s per step on the GPU
+    # box's host, the FDM ones ~1.3 s (heat, 128^3) and ~3 s (advection, 96^3)
+    steps = (8 if workload != 'advdiff256' else 3) if fdm else 2
     u = np.asarray(p.u0, dtype=np.float64).ravel().copy()
     with threadpool_limits(limits=1):
         for i in range(tab.s):

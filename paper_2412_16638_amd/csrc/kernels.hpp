@@ -122,12 +122,13 @@ __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<doubl
     const int g = (L * ln.nit + it) * TPB + threadIdx.x;
     if (g >= ln.ng) break;
     const int e = g * VEC;
-    double yc[VEC], ky[VEC], b[VEC], rr[VEC];
-    k64_group<VEC, FMT>(geo, K, csr, kval, y, g, yc, ky);
+    double yc[VEC], ky[VEC], b[VEC], rr[VEC], fv[VEC];
+    // rhs and the forcing do not depend on the stencil: issued first, so that one memory
+    // round trip covers all of this group's loads
     loadv<double, double, VEC>(rhs + e, b);
+    if (force) loadv<double, double, VEC>(force + e, fv);
+    k64_group<VEC, FMT>(geo, K, csr, kval, y, g, yc, ky);
     if (force) {  // constant forcing: f(y) = K y + g, so the stage solves y - sigma f(y) = rhs
-      double fv[VEC];
-      loadv<double, double, VEC>(force + e, fv);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) ky[v] += fv[v];
     }
