@@ -104,8 +104,11 @@ typedef struct {
  *           Pinvform (Section "Problem setting and solver design"), P = I (x) I (x) A +
  *           I (x) B (x) I + C (x) I (x) I with A = I - sigma Kx, B = -sigma Ky, C = -sigma Kz, its
  *           inverse applied through the one-axis contractions of eq. TensorDecomp in the compute
- *           type.  Implemented for the heat operator (zero Dirichlet or periodic ends, where P is
- *           the stage matrix itself) with CG; other combinations return MPRK_EUNSUPPORTED.
+ *           type.  P is the stage matrix itself for the operators implemented: the heat
+ *           operator (zero Dirichlet or periodic ends; real orthogonal bases) and the advection
+ *           operators with periodic ends (circulant factors; the complex unitary DFT basis), with
+ *           CG or GMRES (the preconditioner applied by separate launches).  Advection with
+ *           Dirichlet ends returns MPRK_EUNSUPPORTED; so does the batched form.
  *  rtol/atol/maxit: inner Krylov stop ||r|| <= max(rtol ||b||, atol) or maxit iterations per
  *           outer pass (the paper stops on the absolute or the relative residual with at most 40
  *           iterations; Section "Linear solvers and setup of the numerical experiments").

@@ -1,13 +1,15 @@
 // fdm.hpp -- fast-diagonalisation preconditioner kernels (gfx950).
 //
 // The preconditioner of Section "Problem setting and solver design", eq. preconbasic, with
-// A = I - sigma Kx, B = -sigma Ky, C = -sigma Kz is the stage matrix itself for the heat
-// operator; eq. Pinvform applies its inverse as
+// A = I - sigma Kx, B = -sigma Ky, C = -sigma Kz is the stage matrix itself for every operator
+// here (Kronecker sums); eq. Pinvform applies its inverse as
 //   z = (Q_C (x) Q_B (x) Q_A) P_D^-1 (Q_C^-1 (x) Q_B^-1 (x) Q_A^-1) r,
 // each Kronecker factor being the product of the three one-axis contractions of eq.
 // TensorDecomp, (T_R x)_{ijk} = sum_q Q_{iq} x_{qjk} (along x), T_M along y, T_L along z.
-// Here the 1-D eigenbases are real, orthogonal and symmetric (Q^-1 = Q): the sine basis for
-// zero Dirichlet ends and the Hartley basis for periodic ones, so both halves use the same Q.
+// For the heat operator the 1-D eigenbases are real, orthogonal and symmetric (Q^-1 = Q): the
+// sine basis for zero Dirichlet ends and the Hartley basis for periodic ones, so both halves
+// use the same Q.  For the periodic advection operators the 1-D factors are circulant and the
+// basis is the unitary DFT (complex; Q^-1 = conj(Q)), see k_fdm_contract_cx.
 //
 // Every contraction is a GEMM with K = n (the axis length): along x the rows of x are
 // contiguous (out = X Q^T, "row" form); along y and z the contracted index is strided and the
