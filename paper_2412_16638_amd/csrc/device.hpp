@@ -15,6 +15,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace mprk {
@@ -337,9 +339,15 @@ __device__ __forceinline__ Nbr neighbours(const Geo& g, int e) {
 // Apply a 7-point stencil to the group at e.  `F` supplies input values:
 //   F::vec(idx, C (&)[VEC]) -- VEC consecutive values starting at idx (aligned group)
 //   F::one(idx) -> C        -- one value
-template <typename C, int VEC, typename F>
+// With a loader `pre` (possibly empty), the caller's other independent loads are issued right
+// after the seven and a scheduling barrier keeps them in flight together (the compiler would
+// otherwise sink a single-value load behind waits for the others: a second memory round trip).
+struct NoPre {
+  __device__ __forceinline__ void operator()() const {}
+};
+template <typename C, int VEC, typename F, typename P = NoPre>
 __device__ __forceinline__ void stencil_group(const Geo& g, const Coef<C>& k, int e, const F& f,
-                                              C (&ctr)[VEC], C (&out)[VEC]) {
+                                              C (&ctr)[VEC], C (&out)[VEC], const P& pre = P()) {
   const Nbr n = neighbours<VEC>(g, e);
   // every load is issued unconditionally (a missing Dirichlet neighbour reads the group itself)
   // and masked afterwards, so the seven loads are in flight together
@@ -351,6 +359,10 @@ __device__ __forceinline__ void stencil_group(const Geo& g, const Coef<C>& k, in
   f.vec(n.yp >= 0 ? n.yp : e, yp);
   f.vec(n.zm >= 0 ? n.zm : e, zm);
   f.vec(n.zp >= 0 ? n.zp : e, zp);
+  if constexpr (!std::is_same<P, NoPre>::value) {
+    pre();
+    __builtin_amdgcn_sched_barrier(0);
+  }
   if (n.xm < 0) l = C(0);
   if (n.xp < 0) r = C(0);
 #pragma unroll
