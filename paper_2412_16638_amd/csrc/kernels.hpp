@@ -522,6 +522,7 @@ __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __res
     loadv<double, double, VEC>(res + e, t);
     BJRows<S, VEC, bj_early<S, VEC, BS>() ? BS : 1> R;
     if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS>(dinv, e, valid, R);
+    __builtin_amdgcn_sched_barrier(0);  // res and the rows in flight together
     C rv[VEC];
     C s = C(0);
 #pragma unroll
@@ -675,6 +676,9 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
       v0[k] = *reinterpret_cast<const Vec<S, VEC>*>(V + (size_t)min(k, nd - 1) * vstride + e);
     BJRows<S, VEC, EARLY ? BS : 1> R;
     if constexpr (EARLY) bj_load<S, VEC, BS>(dinv, e, valid, R);
+    // keep them in flight together (the scheduler would otherwise wait for w and the basis
+    // chunk before issuing the block-Jacobi rows: a second memory round trip)
+    __builtin_amdgcn_sched_barrier(0);
     C wv[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) wv[v] = (C)wr.v[v];
