@@ -130,3 +130,21 @@ def test_fdm_apply_with_fp64_arithmetic(storage, tol):
     ref = fdm.FDM(shape, W.DIRICHLET, 0, 1.3, (0, 0, 0), sigma).apply(xd.double().cpu().numpy())
     st.close()
     assert np.linalg.norm(y - ref) <= tol * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("storage,tol", [('fp32', 1e-6), ('fp16', 3e-3)])
+def test_complex_fdm_apply_with_fp64_arithmetic(storage, tol):
+    """The complex-basis contractions in FP64 (FP64 MFMA) over FP32 / FP16 storage, against the
+    exact Fourier inverse of the periodic stage matrix."""
+    shape, kind, diff, b = (16, 12, 10), W.ADVDIFF, 1e-2, (1.0, 0.5, -0.25)
+    log_case('cb_fdm_cx', storage=storage)
+    prec = cb(storage, 'gmres', precond='fdm')
+    st = M.Stepper(shape, W.PERIODIC, kind, diff, b, A.FMT_STENCIL, 'SDIRK3', prec, 2e-3)
+    sigma = st.dt * (st.tab.a_hi[0] + st.tab.a_lo[0])
+    xd = torch.from_numpy(np.random.default_rng(14).standard_normal(st.N)).to('cuda', DT[storage])
+    y = st.apply(A.APPLY_FDM_LP, xd, stage=0).double().cpu().numpy()
+    lam = closed_form.periodic_eigenvalues(shape, diff, b)
+    xr = xd.double().cpu().numpy().reshape(shape[::-1])
+    ref = np.real(np.fft.ifftn(np.fft.fftn(xr) / (1.0 - sigma * lam))).ravel()
+    st.close()
+    assert np.linalg.norm(y - ref) <= tol * np.linalg.norm(ref)

@@ -152,13 +152,14 @@ def test_complex_fdm_apply_matches_the_oracle_eigendecomposition():
     assert np.linalg.norm(y - ref) <= 1e-11 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("fmt", [A.FMT_STENCIL, A.FMT_CSR])
 @pytest.mark.parametrize("storage,bound", [('fp64', 1e-10), ('fp32', 1e-8), ('fp16', 1e-6)])
 @pytest.mark.parametrize("kind", [W.ADVDIFF, W.CENTRAL])
-def test_gmres_with_complex_fdm_stage_solve(kind, storage, bound):
+def test_gmres_with_complex_fdm_stage_solve(kind, storage, bound, fmt):
     shape, b = (20, 16, 12), (1.0, 0.5, 0.25)
-    log_case('fdm_cx_solve', kind=kind, storage=storage)
+    log_case('fdm_cx_solve', kind=kind, storage=storage, fmt=fmt)
     prec = M.precisions(storage, 'gmres', precond='fdm', rtol=1e-12, atol=0.0)
-    st = M.Stepper(shape, W.PERIODIC, kind, 1e-2, b, A.FMT_STENCIL, 'SDIRK3', prec, 5e-3)
+    st = M.Stepper(shape, W.PERIODIC, kind, 1e-2, b, fmt, 'SDIRK3', prec, 5e-3)
     rhs = np.random.default_rng(6).standard_normal(st.N)
     x, info = st.solve(1, torch.from_numpy(rhs).cuda())
     Mx = operators.stage_matrix(operators.operator(shape, W.PERIODIC, kind, 1e-2, b),
