@@ -193,3 +193,16 @@ def test_compressed_basis_precisions_are_accepted_for_single_problems():
     t = A.mprk_tableau_builtin(A.TAB_SDIRK3)
     h = C.c_void_p()
     assert A.lib.mprk_batch_create(1, probs, C.byref(t), C.byref(p), None, C.byref(h)) == A.EUNSUPPORTED
+
+
+def test_size_limit_of_int32_indexing():
+    """7N must stay below 2^31 (int32 CSR indices and row offsets): 700^3 is rejected; 659^3,
+    the largest cube under the limit, is accepted and its workspace (no allocation here) holds
+    at least the FP64 stage vectors."""
+    rc, _ = _create(grid=(700, 700, 700))
+    assert rc == A.EINVAL and 'too large' in A.mprk_last_error()
+    rc, h = _create(grid=(659, 659, 659))
+    assert rc == A.OK, A.mprk_last_error()
+    N = 659 ** 3
+    assert A.lib.mprk_workspace_bytes(h) >= (3 + 3 + 1) * 8 * N
+    A.lib.mprk_destroy(h)
