@@ -101,6 +101,20 @@ def evolve_periodic(u0: np.ndarray, nu: float, b, tau: float, nsteps: int, tab,
     return np.real(sfft.ifftn(sfft.fftn(u0) * amp))
 
 
+class PeriodicEvolution:
+    """evolve_periodic for one initial state and many (tableau, tau, nsteps): the forward
+    transform of u0 and the DFT symbol are computed once."""
+
+    def __init__(self, u0: np.ndarray, nu: float, b, central: bool = False):
+        nz, ny, nx = u0.shape
+        self.lam = periodic_eigenvalues((nx, ny, nz), nu, b, central)
+        self.u0_hat = sfft.fftn(u0)
+
+    def __call__(self, tau: float, nsteps: int, tab) -> np.ndarray:
+        amp = stability_function(tab, tau * self.lam) ** nsteps
+        return np.real(sfft.ifftn(self.u0_hat * amp))
+
+
 def evolve_periodic_exact(u0: np.ndarray, nu: float, b, t: float,
                           central: bool = False) -> np.ndarray:
     """Semi-discrete exact solution exp(t K) u0 for periodic advection-diffusion."""

@@ -112,3 +112,12 @@ def test_semi_discrete_forced_solution_approaches_the_continuum_at_second_order(
         co = closed_form.forced_heat_exact(g, 1.0, t, continuum=True)
         gaps.append(np.max(np.abs(sd - co)))
     assert 3.5 <= gaps[0] / gaps[1] <= 4.5  # h halves: 1/16 -> 1/32
+
+
+def test_cached_periodic_evolution_equals_the_direct_one():
+    u0 = np.random.default_rng(9).standard_normal((6, 5, 8))
+    ev = closed_form.PeriodicEvolution(u0, 0.0, (1.0, 1.0, 1.0), central=True)
+    for name, tau, n in (('MID1', 0.05, 3), ('4S3PC', 0.02, 5)):
+        tab = tableaus.by_name(name)
+        ref = closed_form.evolve_periodic(u0, 0.0, (1.0, 1.0, 1.0), tau, n, tab, central=True)
+        assert np.allclose(ev(tau, n, tab), ref, atol=1e-14)
