@@ -210,6 +210,8 @@ def main():
                     help='step: the 256^3 / 128^3 single-problem line (default); batch: 64 heat '
                          'problems in one persistent launch per stage; serve: 512 Poisson '
                          'requests; sweep: the paper\'s time-step and tolerance experiments')
+    ap.add_argument('--slots', type=int, default=8,
+                    help='serve mode: jobs admitted concurrently (each on its own stream)')
     ap.add_argument('--n', type=int, default=128,
                     help='sweep mode: grid points per axis of the paper\'s test problems')
     ap.add_argument('--quick', action='store_true',
@@ -653,7 +655,7 @@ def bench_serve(args):
     import workloads as W
     reqs = W.request_stream(materialize_u0=False)
     be = serve.GpuBackend(steps_per_call=10, u0_fn=W.initial_field)
-    srv = serve.Server(be, max_active=8)
+    srv = serve.Server(be, max_active=args.slots)
     log(f'serve: {len(reqs)} requests over {reqs[-1].arrival:.1f} s, budget {srv.budget / 2**30:.1f} GiB')
     seen = [0]
 
