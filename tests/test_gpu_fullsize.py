@@ -44,8 +44,47 @@ def test_advdiff_bump_256_fp16(fmt):
     log_case('advdiff_bump_256', fmt=fmt)
     st = M.from_problem(p, fmt=fmt)
     stats = st.step(p.nsteps)
-    err = rel_l2(st.get_u(), _ref('adv256', p))
+    err = rel_l2(st.get_u(), _ref('advdiff256', p))
     st.close()
     print('advdiff 256^3 fp16 rel-L2', err, stats)
     assert stats['steps'] == 20
     assert err <= 1e-3
+
+
+# ---- the configurations bench.py runs, with its tolerances ----
+import bench  # noqa: E402
+
+
+def _bench_problem(workload, precond, precision=None):
+    p = bench.make_problem(workload, precond)
+    if precision:
+        p.precision = precision
+    return p
+
+
+@pytest.mark.parametrize("precond", ['bj', 'fdm'])
+@pytest.mark.parametrize("workload", ['heat128', 'advdiff256'])
+def test_fp64_reference_integration_matches_the_oracle(workload, precond):
+    """The bench measures its errors against the all-FP64 path solved to rtol = outer_tol =
+    1e-12; that path is pinned here to the exact-solve closed form at the full size."""
+    p = _bench_problem(workload, precond, 'fp64')
+    log_case(f'fp64_reference_{workload}', precond=precond)
+    st = M.from_problem(p, rtol=bench.REF_TOL, outer_tol=bench.REF_TOL)
+    stats = st.step(p.nsteps)
+    err = rel_l2(st.get_u(), _ref(workload, p))
+    st.close()
+    print(workload, precond, 'fp64 reference rel-L2', err, stats['iters'])
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("precond", ['bj', 'fdm'])
+@pytest.mark.parametrize("workload,bound", [('heat128', 1e-6), ('advdiff256', 1e-3)])
+def test_mixed_path_at_the_bench_tolerances(workload, bound, precond):
+    p = _bench_problem(workload, precond)
+    log_case(f'mixed_bench_{workload}', precond=precond, storage=p.precision)
+    st = M.from_problem(p, **bench.MIXED_TOL[workload])
+    stats = st.step(p.nsteps)
+    err = rel_l2(st.get_u(), _ref(workload, p))
+    st.close()
+    print(workload, precond, p.precision, 'rel-L2', err, stats['iters'])
+    assert err <= bound

@@ -91,3 +91,27 @@ def test_stage_solve_ignores_the_forcing_and_removal_restores_the_unforced_step(
     st.close()
     ref = closed_form.evolve_heat(u0, 1.0, p.dt, 2, tableaus.by_name('SDIRK3'))
     assert rel_l2(u, ref) <= TOL['fp64']
+
+
+@pytest.mark.parametrize("prob,tab,tau", [('heat', 'MID1', 1 / 10), ('heat', '4S3PC', 1 / 80),
+                                          ('advection', '4S3PA', 1 / 10),
+                                          ('advection', '4S3PC', 1 / 80)])
+def test_sweep_reference_matches_the_oracle(prob, tab, tau):
+    """The sweep's tight reference at its size (128^3, T = 0.1): the all-FP64 path with the
+    fast-diagonalisation preconditioner and the FP64 residual loop to 1e-12.
+
+    Stage derivatives are evaluated as K y + g in FP64, so a stage-solve error d (relative size
+    up to the residual tolerance, in any mode) reaches the step result as tau b_i K d: the
+    attainable accuracy is about rtol * tau * rho(K), rho(K) the spectral radius (12 (n+1)^2
+    for the Dirichlet Laplacian, 3 n for central advection with beta = (1, 1, 1))."""
+    n, rtol = 128, 1e-12
+    mk = W.paper_heat if prob == 'heat' else W.paper_advection
+    p = mk(n=n, tableau=tab, dt=tau, t_end=0.1, precision='fp64')
+    p.precond = 'fdm'
+    log_case(f'sweep_reference_{prob}_128', tab=tab, tau=tau)
+    u, stats = run(p, rtol=rtol, outer_tol=rtol)
+    err = rel_l2(u, forced_ref(p) if prob == 'heat' else advection_ref(p))
+    rho = 12.0 * (n + 1) ** 2 if prob == 'heat' else 3.0 * n
+    bound = TOL['fp64'] + 10.0 * rtol * tau * rho
+    print(prob, tab, tau, 'rel-L2', err, 'bound', bound, stats['iters'])
+    assert err <= bound, err

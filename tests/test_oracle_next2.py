@@ -121,3 +121,17 @@ def test_cached_periodic_evolution_equals_the_direct_one():
         tab = tableaus.by_name(name)
         ref = closed_form.evolve_periodic(u0, 0.0, (1.0, 1.0, 1.0), tau, n, tab, central=True)
         assert np.allclose(ev(tau, n, tab), ref, atol=1e-14)
+
+
+def test_workload_continuum_solutions_match_the_oracle():
+    """The continuum references the sweep reports against (workloads) agree with the oracle's:
+    the forced heat amplitude and, for the advection test at t = 0, the initial Gaussian."""
+    import workloads as W
+    for n, t in ((9, 0.05), (16, 0.1)):
+        g = closed_form.heat_sine_mode((n, n, n), (1, 1, 1))
+        co = closed_form.forced_heat_exact(g, 1.0, t, continuum=True)
+        assert np.allclose(W.paper_heat_exact(n, t), co, rtol=1e-14, atol=0.0)
+    p = W.paper_advection(n=12, tableau='MID1', dt=0.1, t_end=0.1)
+    assert np.allclose(W.translated_gaussian(12, (0.0, 0.0, 0.0)), p.u0, rtol=1e-14, atol=1e-300)
+    # a shift by whole periods is the identity
+    assert np.allclose(W.translated_gaussian(12, (1.0, -2.0, 3.0)), p.u0, rtol=1e-12, atol=1e-300)

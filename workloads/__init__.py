@@ -141,6 +141,14 @@ def paper_advection(n: int = 128, tableau: str = 'MID1', dt: float = 1.0 / 80,
                    precond='bj')
 
 
+def paper_heat_exact(n: int, t: float) -> np.ndarray:
+    """The continuum solution of the paper's heat test at time t, at the nodes: with u(0) = 0
+    and g the lowest Dirichlet sine mode (Laplacian eigenvalue -3 pi^2) the solution stays
+    along g, u(t) = (1 - exp(-3 pi^2 t)) / (3 pi^2) g."""
+    c = 3.0 * np.pi ** 2
+    return (1.0 - np.exp(-c * t)) / c * sine_mode((n, n, n), (1, 1, 1), DIRICHLET)
+
+
 def translated_gaussian(n: int, shift, width: float = 100.0) -> np.ndarray:
     """exp(-width |x - 1/2 - shift|^2) at the periodic nodes with the nearest periodic image:
     the exact solution of the constant-velocity advection test at time t (shift = beta t)."""
