@@ -307,7 +307,11 @@ def main():
             nv_total = r['worked'] // p_stages(p) * nv['stage_rhs']
         if kc == 'combine':
             nv_total = r['worked'] * nv['combine']
-        b = algorithmic_bytes(kc, N, s_bytes, s_bytes, bs, r['worked'], r['units'], nv_total,
+        sv = s_bytes
+        if kc == 'promote' and args.precond == 'fdm' and p.krylov == 'gmres':
+            # the GMRES correction P^-1 (V y) is formed in the arithmetic type
+            sv = 8 if args.compute == 'fp64' or p.precision == 'fp64' else 4
+        b = algorithmic_bytes(kc, N, sv, s_bytes, bs, r['worked'], r['units'], nv_total,
                               fdm=args.precond == 'fdm')
         rows.append((kc, r, b))
     total_ms = sum(r['ms'] for _, r, _ in rows)

@@ -221,6 +221,12 @@ class EngineT final : public Engine {
   }
   hipError_t cg_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
                      const BJDesc& dinv, int it) override {
+    if (c.fdm_on && it > 0) {
+      // z = P^-1 r and r.z of the previous update, issued at the start of the iteration that
+      // reads them, so the last iteration enqueued in a pass leaves no apply behind it
+      fdm_apply(c, cfg.sigma, c.r, c.z);
+      cg_rz_t<0>(c);
+    }
     const S* z = (c.bs > 0 || c.fdm_on) ? (const S*)c.z : (const S*)c.r;
     const S* pold = (it & 1) ? (const S*)c.p1 : (const S*)c.p0;
     S* pnew = (it & 1) ? (S*)c.p0 : (S*)c.p1;
@@ -234,8 +240,6 @@ class EngineT final : public Engine {
         MPRK_LAUNCH_KC(c, KC_CG_UPD, (k_cg_upd_ext<S, C, VEC>), c.ln_red, c.ln_red, (S*)c.x,
                        (const S*)pnew, (S*)c.r, (const S*)c.q, cfg, c.ctl, c.red);
       });
-      fdm_apply(c, cfg.sigma, c.r, c.z);
-      cg_rz_t<0>(c);
       return hipGetLastError();
     }
     dispatch_vec_bs(c, [&](auto vec, auto bs) {
@@ -402,14 +406,16 @@ class EngineT final : public Engine {
   }
   hipError_t gm_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
                      const BJDesc& dinv, int k) override {
+    // z = P^-1 v_k, issued at the start of the step that reads it (v_0's comes with the
+    // begin), so the last step enqueued in a pass leaves no apply behind it; the launches
+    // return once the cycle has ended
+    if (c.fdm_on && k > 0 && k <= cfg.m)
+      fdm_chain<S, S>(c, cfg.sigma, (const S*)c.V + (size_t)k * c.vstride, (S*)c.z, 1);
     // smallest compiled bound on the basis size that covers step k
     if (k < 4) gm_iter_t<4>(c, cfg, Mc, dinv);
     else if (k < 8) gm_iter_t<8>(c, cfg, Mc, dinv);
     else if (k < 16) gm_iter_t<16>(c, cfg, Mc, dinv);
     else gm_iter_t<MAXD>(c, cfg, Mc, dinv);
-    // z = P^-1 v_{k+1} for the next step (the launches return once the cycle has ended)
-    if (c.fdm_on && k + 1 <= cfg.m)
-      fdm_chain<S, S>(c, cfg.sigma, (const S*)c.V + (size_t)(k + 1) * c.vstride, (S*)c.z, 1);
     return hipGetLastError();
   }
   template <int VEC, int BS, int NDM>

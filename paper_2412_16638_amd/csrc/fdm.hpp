@@ -756,6 +756,7 @@ template <typename C, int VEC>
 __global__ __launch_bounds__(TPB) void k_gm_update_ext(Launch ln, double* __restrict__ y,
                                                        const C* __restrict__ z, Ctl* ctl) {
   if (ctl->outer_done || ctl->J == 0 || ctl->nonfinite) return;  // no correction, or J beyond the bound
+  count_work(ctl, KC_PROMOTE);
   const double sc = ctl->scale;
   const int L = xcd_block(ln.G);
   for (int it = 0; it < ln.nit; ++it) {

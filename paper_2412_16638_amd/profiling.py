@@ -2,14 +2,16 @@
 
 Two inputs are understood:
 - the `*_kernel_stats.csv` of a `rocprofv3 --kernel-trace --stats --output-format csv` run, turned
-  into a short text table (calls, average and total duration, share) with the command that made it;
+  into a short text table (calls, average and total duration, share) with the command that made it,
+  optionally with the span of runs of back-to-back dispatches of one kernel from the trace;
 - two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of a command that starts with a plain
   device copy of known size (`bench.py --calib-copy MIB`), turned into the HBM bytes one dispatch of
   a kernel moves.  Each counter is scaled by what it reads for that copy: the copy reads MIB and
   writes MIB, so factor = MIB * 1024 / counter (both counters are in KiB).
 
 Usage:
-  python -m paper_2412_16638_amd.profiling stats STATS_CSV --command CMD --out FILE
+  python -m paper_2412_16638_amd.profiling stats STATS_CSV --command CMD --out FILE \
+      [--trace TRACE_CSV --chain fdm_contract:6]
   python -m paper_2412_16638_amd.profiling traffic FETCH_CSV WRITE_CSV --kernel gm_orth \
       --workload advdiff256 --calib-mib 1024 --command-fetch CMD --command-write CMD --out FILE
 """
@@ -121,6 +123,31 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, calib_mib: int,
             'bytes_per_worked_launch': fetch_b + write_b}
 
 
+def chain_summary(trace_csv: str, kernel: str, n: int) -> str:
+    """Runs of exactly n back-to-back dispatches of `kernel` (no other kernel between them, in
+    dispatch order): the span from the first start to the last end, per launch.  This is what an
+    event pair around the n launches measures (the kernels plus the gaps between them)."""
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r['Start_Timestamp']))
+    spans, durs, run = [], [], []
+    for r in rows + [None]:
+        if r is not None and short_name(r['Kernel_Name']) == kernel:
+            run.append(r)
+            continue
+        if len(run) == n:
+            t0 = int(run[0]['Start_Timestamp'])
+            t1 = int(run[-1]['End_Timestamp'])
+            spans.append((t1 - t0) / n)
+            durs += [int(x['End_Timestamp']) - int(x['Start_Timestamp']) for x in run]
+        run = []
+    if not spans:
+        return f'\n## {kernel}: no runs of {n} back-to-back dispatches\n'
+    return (f'\n## {kernel}: runs of {n} back-to-back dispatches (one event pair in the bench)\n\n'
+            f'runs: {len(spans)}\n'
+            f'kernel duration per launch, mean: {sum(durs) / len(durs) / 1e3:.2f} us\n'
+            f'span per launch (first start to last end / {n}), mean: '
+            f'{sum(spans) / len(spans) / 1e3:.2f} us\n')
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest='what', required=True)
@@ -128,6 +155,8 @@ def main():
     a.add_argument('csv')
     a.add_argument('--command', required=True)
     a.add_argument('--out', required=True)
+    a.add_argument('--trace', help='kernel trace csv, for --chain')
+    a.add_argument('--chain', help='KERNEL:N, summarise runs of N back-to-back dispatches')
     b = sub.add_parser('traffic')
     b.add_argument('fetch_csv')
     b.add_argument('write_csv')
@@ -139,8 +168,12 @@ def main():
     b.add_argument('--out', required=True)
     args = ap.parse_args()
     if args.what == 'stats':
+        text = stats_summary(args.csv, args.command)
+        if args.chain:
+            k, n = args.chain.split(':')
+            text += chain_summary(args.trace, k, int(n))
         with open(args.out, 'w') as fh:
-            fh.write(stats_summary(args.csv, args.command))
+            fh.write(text)
     else:
         t = traffic(args.fetch_csv, args.write_csv, args.kernel, args.calib_mib)
         t.update({'workload': args.workload, 'kernel_hash': kernel_source_hash(),

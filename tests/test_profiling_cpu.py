@@ -1,0 +1,56 @@
+"""Host-side summaries of rocprofv3 output (no GPU): kernel-name shortening, the per-kernel
+table, the chain-span summary and the counter-based traffic figure."""
+import csv
+
+import pytest
+
+from paper_2412_16638_amd import profiling as P
+
+
+def _write(path, header, rows):
+    with open(path, 'w', newline='') as fh:
+        w = csv.writer(fh)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_short_names():
+    assert P.short_name('void mprk::k_gm_orth<__half, float, 4, 8, 4>(mprk::Launch)') == 'gm_orth'
+    assert P.short_name('_ZN4mprk10k_residualILi4ELi0EEEvNS_6LaunchE') == 'residual'
+    assert P.short_name('__amd_rocclr_copyBuffer') == '__amd_rocclr_copyBuffer'
+
+
+def test_chain_summary_spans_include_the_gaps(tmp_path):
+    k = 'void mprk::k_fdm_contract<float, float, float, 1, 1, 64, 32>(mprk::FdmGeo)'
+    other = 'void mprk::k_cg_rz<float, float, 4, 0>(mprk::Launch)'
+    rows, t = [], 0
+    for run in range(3):
+        for i in range(6):  # 10 us kernels, 2 us apart
+            rows.append((k, t, t + 10_000))
+            t += 12_000
+        rows.append((other, t, t + 5_000))
+        t += 7_000
+    rows.append((k, t, t + 10_000))  # a lone dispatch is not a run of six
+    path = tmp_path / 'trace.csv'
+    _write(path, ['Kernel_Name', 'Start_Timestamp', 'End_Timestamp'], rows)
+    text = P.chain_summary(str(path), 'fdm_contract', 6)
+    assert 'runs: 3' in text
+    assert 'kernel duration per launch, mean: 10.00 us' in text
+    assert f'mean: {(5 * 12 + 10) / 6:.2f} us' in text
+
+
+def test_traffic_scales_by_the_calibration_copy(tmp_path):
+    k = 'void mprk::k_gm_orth<__half, float, 4, 8, 4>(mprk::Launch)'
+    cp = '__amd_rocclr_copyBuffer'
+    f = tmp_path / 'f.csv'
+    w = tmp_path / 'w.csv'
+    hdr = ['Kernel_Name', 'Counter_Name', 'Counter_Value']
+    # the copy of 1024 MiB reads as half its size in FETCH_SIZE, as its size in WRITE_SIZE
+    _write(f, hdr, [(cp, 'FETCH_SIZE', 512 * 1024), (k, 'FETCH_SIZE', 1000), (k, 'FETCH_SIZE', 3000),
+                    (k, 'FETCH_SIZE', 1)])
+    _write(w, hdr, [(cp, 'WRITE_SIZE', 1024 * 1024), (k, 'WRITE_SIZE', 400), (k, 'WRITE_SIZE', 2)])
+    t = P.traffic(str(f), str(w), 'gm_orth', 1024)
+    assert t['fetch_factor'] == pytest.approx(2.0)
+    assert t['working_dispatches'] == 2  # the near-empty dispatch is counted apart
+    assert t['fetch_bytes_per_worked_launch'] == pytest.approx(2000 * 1024 * 2.0)
+    assert t['write_bytes_per_worked_launch'] == pytest.approx(400 * 1024)
