@@ -36,9 +36,10 @@ def log(*a):
 
 
 def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, units: int,
-                      nv_total: int = 0, fdm: bool = False) -> float:
+                      nv_total: int = 0, fdm: bool = False, cb: int = 4) -> float:
     """Bytes each kernel class must move per its definition (each array touched once; halos
-    and reduction partials not counted).  s = LP storage bytes, m = LP matrix bytes, bs = block."""
+    and reduction partials not counted).  s = LP storage bytes, m = LP matrix bytes, bs = block,
+    cb = bytes of the arithmetic type."""
     inv = bs * m  # block-Jacobi inverse row per unknown
     pre = (inv + s) if bs else 0  # fused block-Jacobi: inverse row read + preconditioned write
     if kc == 'gm_matvec':
@@ -46,6 +47,8 @@ def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, uni
     if kc == 'gm_orth':
         return N * (worked * (s + s + pre) + units * s)
     if kc == 'gm_finish':
+        if fdm:  # t = sum_i y_i v_i in the arithmetic type; P^-1 t and y += s z come after
+            return N * (worked * cb + units * s)
         return N * (worked * (inv + 16) + units * s)
     if kc == 'gm_begin':
         return N * worked * (8 + s + pre)
@@ -308,11 +311,11 @@ def main():
         if kc == 'combine':
             nv_total = r['worked'] * nv['combine']
         sv = s_bytes
+        cbytes = 8 if args.compute == 'fp64' or p.precision == 'fp64' else 4
         if kc == 'promote' and args.precond == 'fdm' and p.krylov == 'gmres':
-            # the GMRES correction P^-1 (V y) is formed in the arithmetic type
-            sv = 8 if args.compute == 'fp64' or p.precision == 'fp64' else 4
+            sv = cbytes  # the GMRES correction P^-1 (V y) is formed in the arithmetic type
         b = algorithmic_bytes(kc, N, sv, s_bytes, bs, r['worked'], r['units'], nv_total,
-                              fdm=args.precond == 'fdm')
+                              fdm=args.precond == 'fdm', cb=cbytes)
         rows.append((kc, r, b))
     total_ms = sum(r['ms'] for _, r, _ in rows)
     dom = max(rows, key=lambda x: x[1]['ms'])
@@ -324,7 +327,7 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     if 'fdm' in prof and prof['fdm']['launches']:
         fr = prof['fdm']
-        fdm_tflops = 2.0 * fr['units'] * N / (fr['ms'] * 1e-3) / 1e12
+        fdm_tflops = 2.0 * fr['units'] * N / (fr['ms'] * 1e-3) / 1e12 * (20.0 / 6.0 if p.kind else 1.0)
         log(f'fdm contractions: {fdm_tflops:.2f} TFLOP/s over {fr["launches"]} launches')
     kernel_table = {k: {'launches': rr['launches'], 'worked': rr['worked'],
                         'ms': round(rr['ms'], 3),
@@ -343,8 +346,9 @@ def main():
             traffic = tr['bytes_per_worked_launch'] * r['worked'] / r['launches']
     if kc == 'fdm':
         # the contractions are dense: 2 n flops per unknown per launch (n = axis length); with
-        # the complex basis of the advection operator an apply does 20 real products per
-        # unknown and axis point instead of 6 (2 at each real end, 4 in the four middle ones)
+        # the complex basis of the advection operator an apply's algorithmic count is 20 real
+        # products per unknown and axis point instead of 6 (2 at each real end, 4 in each of the
+        # four middle ones; the kernels execute 3 there, so 16 of the 20 reach the matrix cores)
         cxf = 20.0 / 6.0 if p.kind != 0 else 1.0
         flops_per_launch = 2.0 * r['units'] * N / r['launches'] * cxf
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12

@@ -296,9 +296,9 @@ struct FdmCx {
 };
 
 // One contraction with the complex basis on the matrix cores: the tile layout, staging and
-// k-order of k_fdm_contract, with a real and an imaginary tile per operand and four real
-// products per complex one (two when the data operand is real, INR, or only the real part of
-// the result is kept, OUTR).  The epilogue of the forward z contraction divides by the complex
+// k-order of k_fdm_contract, with a real and an imaginary tile per operand and three real
+// products per complex one by Gauss's rearrangement (two when the data operand is real, INR, or
+// only the real part of the result is kept, OUTR).  The epilogue of the forward z contraction divides by the complex
 // P_D = 1 - sk (lx + ly + lz).
 template <typename TI, typename TO, typename C, int ROW, int V4, int INR, int OUTR>
 __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
@@ -409,13 +409,17 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
   // the data operand's imaginary part is zero (INR): A for ROW, B for COL
   constexpr bool AR = ROW && INR, BR = !ROW && INR;
-  Acc accr[2][2], acci[2][2];
+  // both operands complex and the full result kept: three real products per complex one
+  // (P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi); re = P1 - P2, im = P3 - P1 - P2)
+  constexpr bool G3 = !AR && !BR && !OUTR;
+  Acc accr[2][2], acci[2][2], accq[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       accr[i][j] = Acc{};
       acci[i][j] = Acc{};
+      accq[i][j] = Acc{};
     }
   load_chunk(0);
   for (int q0 = 0; q0 < n; q0 += KC) {
@@ -442,7 +446,24 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
         }
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j) {
+        if constexpr (G3) {
+          C as[2], bs[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            as[i] = avr[i].v[j] + avi[i].v[j];
+            bs[i] = bvr[i].v[j] + bvi[i].v[j];
+          }
+#pragma unroll
+          for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni) {
+              accr[mi][ni] = Mfma<C>::op(avr[mi].v[j], bvr[ni].v[j], accr[mi][ni]);
+              accq[mi][ni] = Mfma<C>::op(avi[mi].v[j], bvi[ni].v[j], accq[mi][ni]);
+              acci[mi][ni] = Mfma<C>::op(as[mi], bs[ni], acci[mi][ni]);
+            }
+          continue;
+        }
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -455,8 +476,19 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
               if constexpr (!AR) acci[mi][ni] = Mfma<C>::op(avi[mi].v[j], bvr[ni].v[j], acci[mi][ni]);
             }
           }
+      }
     }
     __syncthreads();
+  }
+  if constexpr (G3) {
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        const Acc p1 = accr[mi][ni], p2 = accq[mi][ni], p3 = acci[mi][ni];
+        accr[mi][ni] = p1 - p2;
+        acci[mi][ni] = p3 - p1 - p2;
+      }
   }
   // complex P_D factors of this lane's rows and columns (indices clamped in range)
   double sxr[2] = {0.0, 0.0}, sxi[2] = {0.0, 0.0}, szr[2][4] = {}, szi[2][4] = {};
