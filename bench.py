@@ -99,6 +99,22 @@ def make_problem(name: str, precond: str = 'bj'):
 MFMA_PEAK = {'fp64': 78.6, 'fp32': 157.3, 'fp16': 157.3}
 
 
+def fdm_apply_flops(p) -> float:
+    """Algorithmic flops per unknown of one fast-diagonalisation apply (six dense contractions,
+    2 flops per real multiply-add).  Real basis (heat): 2 n per contraction.  Complex DFT basis
+    (periodic advection, real data): the x transforms keep H = nx/2 + 1 frequencies rounded up
+    to 4 (all nx below nx = 4); forward x real x complex (4 H), y and z forward and back complex x
+    complex on H of nx x-slices (8 n H / nx each), backward x only the real part (4 H).  The
+    kernels execute 3 real products per complex one in the middle four, 3/4 of their count."""
+    n = p.n
+    if p.kind == 0:
+        return 4.0 * 3 * n
+    H = (n // 2 + 1 + 3) & ~3
+    if H > n:
+        H = n
+    return 8.0 * H + 16.0 * (n + n) * H / n
+
+
 def workload_name(args) -> str:
     """The configuration a step-mode line measures, named by what it is."""
     pc = 'fdm' if args.precond == 'fdm' else 'bj8'
@@ -327,7 +343,7 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     if 'fdm' in prof and prof['fdm']['launches']:
         fr = prof['fdm']
-        fdm_tflops = 2.0 * fr['units'] * N / (fr['ms'] * 1e-3) / 1e12 * (20.0 / 6.0 if p.kind else 1.0)
+        fdm_tflops = fr['worked'] / 6.0 * N * fdm_apply_flops(p) / (fr['ms'] * 1e-3) / 1e12
         log(f'fdm contractions: {fdm_tflops:.2f} TFLOP/s over {fr["launches"]} launches')
     kernel_table = {k: {'launches': rr['launches'], 'worked': rr['worked'],
                         'ms': round(rr['ms'], 3),
@@ -345,12 +361,7 @@ def main():
             # counters give bytes per working dispatch; spread over all launches like `achieved`
             traffic = tr['bytes_per_worked_launch'] * r['worked'] / r['launches']
     if kc == 'fdm':
-        # the contractions are dense: 2 n flops per unknown per launch (n = axis length); with
-        # the complex basis of the advection operator an apply's algorithmic count is 20 real
-        # products per unknown and axis point instead of 6 (2 at each real end, 4 in each of the
-        # four middle ones; the kernels execute 3 there, so 16 of the 20 reach the matrix cores)
-        cxf = 20.0 / 6.0 if p.kind != 0 else 1.0
-        flops_per_launch = 2.0 * r['units'] * N / r['launches'] * cxf
+        flops_per_launch = r['worked'] / 6.0 * N * fdm_apply_flops(p) / r['launches']
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
         peak = MFMA_PEAK['fp64' if args.compute == 'fp64' else p.precision]
         roofline = {'bound': 'mfma', 'kernel': kc, 'achieved': round(achieved, 2), 'peak': peak,

@@ -90,6 +90,10 @@ struct EngineCtx {
   const void* fdm_Qi[3];
   const double* fdm_lami[3];
   void* fdm_ti[2];
+  // half spectrum along x (real data): fdm_half = frequencies kept (a multiple of 4, at most
+  // nx; 0: full spectrum) and the x basis weighted for the real inverse (real, imaginary)
+  int fdm_half;
+  const void* fdm_Qw[2];
   // LP vectors (S*)
   void *r, *z, *p0, *p1, *q, *x;
   void* V;
@@ -286,7 +290,8 @@ class EngineT final : public Engine {
   void fdm_launch_cx(const EngineCtx& c, FdmGeo g, int row, const FdmCx& cx, const TI* in_r,
                      const TI* in_i, TO* out_r, TO* out_i, const FdmScale& sc) {
     const int n = g.n;
-    g.tiles = row ? ((g.nr + 63) / 64) * ((n + FT_N - 1) / FT_N)
+    const int ro = g.ro ? g.ro : n;
+    g.tiles = row ? ((g.nr + 63) / 64) * ((ro + FT_N - 1) / FT_N)
                   : ((n + 63) / 64) * ((g.nc + FT_N - 1) / FT_N) * g.nb;
     const dim3 grid((unsigned)((g.tiles + 7) & ~7));
     if (row)
@@ -303,9 +308,17 @@ class EngineT final : public Engine {
     else fdm_launch_cx<TI, TO, INR, OUTR, 0>(c, g, row, cx, in_r, in_i, out_r, out_i, sc);
   }
   // z = Re(conj(U) P_D^-1 U r), U the 3-D unitary DFT (axis by axis), for the circulant factors
-  // of the periodic advection operators; planar complex scratch (t0, t0i), (t1, t1i).
+  // of the periodic advection operators; planar complex scratch (t0, t0i), (t1, t1i).  The data
+  // are real and the symbol is conjugate-symmetric, so the x frequencies k and nx - k carry
+  // conjugate values throughout: only k < H = fdm_half pass through the y and z contractions,
+  // and the last one sums them with weight 2 for 0 < k < nx / 2 (1 for k = 0 and k = nx / 2,
+  // 0 from nx / 2 + 1 on; the weights are in fdm_Qw).
   template <typename TI, typename TO>
   void fdm_chain_cx(const EngineCtx& c, double sigma, const TI* in, TO* out, int skip) {
+    if (c.fdm_half) {
+      fdm_chain_cx_half<TI, TO>(c, sigma, in, out, skip);
+      return;
+    }
     const int nx = c.geo.nx, ny = c.geo.ny, nz = c.geo.nz;
     C* t0 = (C*)c.fdm_t[0];
     C* t1 = (C*)c.fdm_t[1];
@@ -326,6 +339,36 @@ class EngineT final : public Engine {
     fdm_go_cx<C, C, 0, 0>(c, gz, 0, cxd(2, -1.0), t0, t0i, t1, t1i, none);
     fdm_go_cx<C, C, 0, 0>(c, gy, 0, cxd(1, -1.0), t1, t1i, t0, t0i, none);
     fdm_go_cx<C, TO, 0, 1>(c, gx, 1, cxd(0, -1.0), t0, t0i, out, nullptr, none);
+    if (c.prof) c.prof->after();
+  }
+  template <typename TI, typename TO>
+  void fdm_chain_cx_half(const EngineCtx& c, double sigma, const TI* in, TO* out, int skip) {
+    const int nx = c.geo.nx, ny = c.geo.ny, nz = c.geo.nz, H = c.fdm_half;
+    C* t0 = (C*)c.fdm_t[0];
+    C* t1 = (C*)c.fdm_t[1];
+    C* t0i = (C*)c.fdm_ti[0];
+    C* t1i = (C*)c.fdm_ti[1];
+    const FdmScale none{nullptr, nullptr, nullptr, 0.0, H, 0};
+    const FdmScale sc{c.fdm_lam[0], c.fdm_lam[1], c.fdm_lam[2], sigma, H, 1};
+    auto cxd = [&](int d, double sign) {
+      return FdmCx{c.fdm_Q[d], c.fdm_Qi[d], sign, c.fdm_lami[0], c.fdm_lami[1], c.fdm_lami[2]};
+    };
+    const FdmCx xw{c.fdm_Qw[0], c.fdm_Qw[1], -1.0, c.fdm_lami[0], c.fdm_lami[1], c.fdm_lami[2]};
+    FdmGeo gxf{nx, fdm_ldq(nx), ny * nz, 0, 0, 0, 1, 0, skip};
+    gxf.rk = nx;
+    gxf.ro = H;
+    FdmGeo gxb{nx, fdm_ldq(nx), ny * nz, 0, 0, 0, 1, 0, skip};
+    gxb.rk = H;
+    gxb.ro = nx;
+    const FdmGeo gy{ny, fdm_ldq(ny), 0, H, H, (long)H * ny, nz, 0, skip};
+    const FdmGeo gz{nz, fdm_ldq(nz), 0, H * ny, H * ny, 0, 1, 0, skip};
+    if (c.prof) c.prof->before(KC_FDM, 6);
+    fdm_go_cx<TI, C, 1, 0>(c, gxf, 1, cxd(0, 1.0), in, nullptr, t0, t0i, none);
+    fdm_go_cx<C, C, 0, 0>(c, gy, 0, cxd(1, 1.0), t0, t0i, t1, t1i, none);
+    fdm_go_cx<C, C, 0, 0>(c, gz, 0, cxd(2, 1.0), t1, t1i, t0, t0i, sc);
+    fdm_go_cx<C, C, 0, 0>(c, gz, 0, cxd(2, -1.0), t0, t0i, t1, t1i, none);
+    fdm_go_cx<C, C, 0, 0>(c, gy, 0, cxd(1, -1.0), t1, t1i, t0, t0i, none);
+    fdm_go_cx<C, TO, 0, 1>(c, gxb, 1, xw, t0, t0i, out, nullptr, none);
     if (c.prof) c.prof->after();
   }
   // z = P^-1 r: T_R, T_M, T_L with the basis (its own inverse), P_D^-1, then back.  in and out

@@ -48,6 +48,8 @@ struct FdmGeo {
   int nb;        // COL form: batches
   int tiles;     // output tiles (the grid is this rounded up to a multiple of 8)
   int skip_inner;  // 1: return once the inner solve is done (applies inside a Krylov loop)
+  int rk = 0;    // complex ROW form: contraction extent = input row stride (0: n)
+  int ro = 0;    // complex ROW form: outputs per row = output row stride (0: n)
 };
 
 // Scaling by P_D^-1 (fused into a COL-form contraction along z): the output element with
@@ -321,11 +323,15 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
   __shared__ __align__(32) C Br_s[ROW ? FT_N : KC][ROW ? PK : PN];
   __shared__ __align__(32) C Bi_s[ROW ? FT_N : KC][ROW ? PK : PN];
   const int n = g.n;
+  // ROW form: contraction extent (input row stride) and outputs per row (output row stride);
+  // below n for the half spectrum of real data
+  const int RK = (ROW && g.rk) ? g.rk : n, RO = (ROW && g.ro) ? g.ro : n;
+  const int KN = ROW ? RK : n;
   const int T = xcd_block((g.tiles + 7) & ~7);
   if (T >= g.tiles) return;
   int mt, nt, b = 0;
   if constexpr (ROW) {
-    const int NT = (n + FT_N - 1) / FT_N;
+    const int NT = (RO + FT_N - 1) / FT_N;
     nt = T % NT;
     mt = T / NT;
   } else {
@@ -375,9 +381,9 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
       const int row = e / KV, q = q0 + (e % KV) * 4;
       if constexpr (ROW) {
         const int r = m0 + row;
-        const size_t off = (size_t)r * n + q;
-        load_data(rar[u], in_r + off, r < g.nr && q < n, n - q);
-        if constexpr (!INR) load_data(rai[u], in_i + off, r < g.nr && q < n, n - q);
+        const size_t off = (size_t)r * RK + q;
+        load_data(rar[u], in_r + off, r < g.nr && q < RK, RK - q);
+        if constexpr (!INR) load_data(rai[u], in_i + off, r < g.nr && q < RK, RK - q);
         load_q(rbr[u], rbi[u], n0 + row, q);
       } else {
         load_q(rar[u], rai[u], m0 + row, q);
@@ -422,10 +428,10 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
       accq[i][j] = Acc{};
     }
   load_chunk(0);
-  for (int q0 = 0; q0 < n; q0 += KC) {
+  for (int q0 = 0; q0 < KN; q0 += KC) {
     store_chunk();
     __syncthreads();
-    if (q0 + KC < n) load_chunk(q0 + KC);
+    if (q0 + KC < KN) load_chunk(q0 + KC);
 #pragma unroll
     for (int kb = 0; kb < KC; kb += 16) {
       const int k = kb + 4 * g4;
@@ -534,8 +540,8 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
         size_t off;
         bool ok;
         if constexpr (ROW) {
-          ok = m < g.nr && col < n;
-          off = (size_t)m * n + col;
+          ok = m < g.nr && col < RO;
+          off = (size_t)m * RO + col;
         } else {
           ok = m < n && col < g.nc;
           off = boff + (size_t)m * g.ld + col;

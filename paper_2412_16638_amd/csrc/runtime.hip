@@ -573,6 +573,11 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
       o_fdm_t[k] = take((size_t)N * cb);
       if (fdm_cx) o_fdm_ti[k] = take((size_t)N * cb);
     }
+    // real data: x frequencies 0 .. nx/2 suffice (rounded up to 4 for aligned rows; needs nx >= 4)
+    const int H = (g.nx / 2 + 1 + 3) & ~3;
+    fdm_half = fdm_cx && H <= g.nx ? H : 0;
+    if (fdm_half)
+      for (int k = 0; k < 2; ++k) o_fdm_Qw[k] = take((size_t)g.nx * fdm_ldq(g.nx) * cb);
   }
   o_ctl = take(sizeof(Ctl));
   o_flag = take(256);
@@ -661,6 +666,8 @@ EngineCtx mprk_handle::ctx() const {
     c.fdm_lami[d] = fdm_cx ? (const double*)(ws + o_fdm_lami[d]) : nullptr;
   }
   for (int k = 0; k < 2; ++k) c.fdm_ti[k] = fdm_cx ? ws + o_fdm_ti[k] : nullptr;
+  c.fdm_half = fdm_half;
+  for (int k = 0; k < 2; ++k) c.fdm_Qw[k] = fdm_half ? ws + o_fdm_Qw[k] : nullptr;
   c.kappa = op.diff;
   c.r = ws + o_r;
   c.z = ws + o_z;
@@ -753,6 +760,20 @@ extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev,
         int rc = upload(h->o_fdm_Q[d], Q, n);
         if (!rc) rc = upload(h->o_fdm_Qi[d], Qi, n);
         if (rc) return rc;
+        if (d == 0 && h->fdm_half) {
+          // weights of the real inverse over frequencies 0 .. n/2: 2 where k and n - k are
+          // distinct, 1 at k = 0 and (n even) k = n/2, 0 above n/2
+          std::vector<double> Wr((size_t)n * n, 0.0), Wi((size_t)n * n, 0.0);
+          for (int a = 0; a < n; ++a)
+            for (int q = 0; q <= n / 2; ++q) {
+              const double w = (q == 0 || 2 * q == n) ? 1.0 : 2.0;
+              Wr[(size_t)a * n + q] = w * Q[(size_t)a * n + q];
+              Wi[(size_t)a * n + q] = w * Qi[(size_t)a * n + q];
+            }
+          rc = upload(h->o_fdm_Qw[0], Wr, n);
+          if (!rc) rc = upload(h->o_fdm_Qw[1], Wi, n);
+          if (rc) return rc;
+        }
         HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_lami[d], lami.data(), lami.size() * 8, hipMemcpyHostToDevice, h->stream));
       }
       HIPCHK(hipMemcpyAsync(h->ws + h->o_fdm_lam[d], lam.data(), lam.size() * 8, hipMemcpyHostToDevice, h->stream));

@@ -77,6 +77,8 @@ struct mprk_handle {
   size_t o_fdm_Q[3] = {}, o_fdm_lam[3] = {}, o_fdm_t[2] = {};
   bool fdm_cx = false;  // complex eigenbases (periodic advection): imaginary parts below
   size_t o_fdm_Qi[3] = {}, o_fdm_lami[3] = {}, o_fdm_ti[2] = {};
+  int fdm_half = 0;  // complex: x frequencies kept (real data; 0 = all), weighted x basis below
+  size_t o_fdm_Qw[2] = {};
   size_t ws_bytes = 0;
   const double* force = nullptr;  // constant forcing g (caller-owned, N doubles) or null
   // binding

@@ -64,7 +64,10 @@ def test_fdm_apply_on_degenerate_axes(shape):
     assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 1, 3), (1, 3, 2)])
+# nx < 4 keeps the full x spectrum; from nx = 4 on only frequencies 0 .. nx/2 (rounded up to
+# 4) pass through the y and z contractions: even and odd nx at the edge of that rule
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 1, 3), (1, 3, 2), (3, 2, 2), (4, 3, 2),
+                                   (5, 2, 3), (6, 1, 1), (7, 2, 1)])
 def test_complex_fdm_apply_on_degenerate_axes(shape):
     log_case('edge_fdm_cx', shape=shape)
     b = (1.0, 0.5, -0.25)

@@ -113,6 +113,8 @@ ADV_CASES = [
     ((14, 10, 8), W.CENTRAL, 0.0, (1.0, 1.0, 1.0)),
     ((18, 10, 9), W.CENTRAL, 2e-2, (1.0, -0.7, 0.3)),     # nx % 4 != 0: element-wise loads
     ((70, 66, 65), W.ADVDIFF, 1e-2, (1.0, 0.5, 0.25)),    # ragged tiles
+    ((9, 8, 6), W.ADVDIFF, 1e-2, (0.7, -0.4, 0.2)),       # odd nx: half spectrum of 8 of 9
+    ((132, 5, 7), W.CENTRAL, 1e-2, (1.0, 1.0, 1.0)),      # half spectrum 68: two column tiles
 ]
 
 
