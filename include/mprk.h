@@ -107,8 +107,11 @@ typedef struct {
  *           type.  P is the stage matrix itself for the operators implemented: the heat
  *           operator (zero Dirichlet or periodic ends; real orthogonal bases) and the advection
  *           operators with periodic ends (circulant factors; the complex unitary DFT basis), with
- *           CG or GMRES (the preconditioner applied by separate launches).  Advection with
- *           Dirichlet ends returns MPRK_EUNSUPPORTED; so does the batched form.
+ *           CG or GMRES (the preconditioner applied by separate launches).  With the DFT
+ *           basis only the x frequencies 0 .. nx/2 (rounded up to 4; all when nx < 4) pass
+ *           through the y and z transforms, since the vectors are real and the diagonal factor
+ *           conjugate-symmetric.  Advection with Dirichlet ends returns MPRK_EUNSUPPORTED; so
+ *           does the batched form.
  *  rtol/atol/maxit: inner Krylov stop ||r|| <= max(rtol ||b||, atol) or maxit iterations per
  *           outer pass (the paper stops on the absolute or the relative residual with at most 40
  *           iterations; Section "Linear solvers and setup of the numerical experiments").
