@@ -11,7 +11,7 @@ Two inputs are understood:
 
 Usage:
   python -m paper_2412_16638_amd.profiling stats STATS_CSV --command CMD --out FILE \
-      [--trace TRACE_CSV --chain fdm_contract:6]
+      [--trace TRACE_CSV --chain fdm_contract:6[:LAST]]
   python -m paper_2412_16638_amd.profiling traffic FETCH_CSV WRITE_CSV --kernel gm_orth \
       --workload advdiff256 --calib-mib 1024 --command-fetch CMD --command-write CMD --out FILE
 """
@@ -123,10 +123,11 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, calib_mib: int,
             'bytes_per_worked_launch': fetch_b + write_b}
 
 
-def chain_summary(trace_csv: str, kernel: str, n: int) -> str:
+def chain_summary(trace_csv: str, kernel: str, n: int, last: int = 0) -> str:
     """Runs of exactly n back-to-back dispatches of `kernel` (no other kernel between them, in
     dispatch order): the span from the first start to the last end, per launch.  This is what an
-    event pair around the n launches measures (the kernels plus the gaps between them)."""
+    event pair around the n launches measures (the kernels plus the gaps between them).  last > 0
+    also reports the last `last` runs alone (the bench's profiled pass comes last)."""
     rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r['Start_Timestamp']))
     spans, durs, run = [], [], []
     for r in rows + [None]:
@@ -141,11 +142,16 @@ def chain_summary(trace_csv: str, kernel: str, n: int) -> str:
         run = []
     if not spans:
         return f'\n## {kernel}: no runs of {n} back-to-back dispatches\n'
-    return (f'\n## {kernel}: runs of {n} back-to-back dispatches (one event pair in the bench)\n\n'
+    text = (f'\n## {kernel}: runs of {n} back-to-back dispatches (one event pair in the bench)\n\n'
             f'runs: {len(spans)}\n'
             f'kernel duration per launch, mean: {sum(durs) / len(durs) / 1e3:.2f} us\n'
             f'span per launch (first start to last end / {n}), mean: '
             f'{sum(spans) / len(spans) / 1e3:.2f} us\n')
+    if 0 < last <= len(spans):
+        tail_d = durs[-last * n:]
+        text += (f'last {last} runs: kernel duration per launch {sum(tail_d) / len(tail_d) / 1e3:.2f} us, '
+                 f'span per launch {sum(spans[-last:]) / last / 1e3:.2f} us\n')
+    return text
 
 
 def main():
@@ -156,7 +162,8 @@ def main():
     a.add_argument('--command', required=True)
     a.add_argument('--out', required=True)
     a.add_argument('--trace', help='kernel trace csv, for --chain')
-    a.add_argument('--chain', help='KERNEL:N, summarise runs of N back-to-back dispatches')
+    a.add_argument('--chain', help='KERNEL:N[:LAST], summarise runs of N back-to-back dispatches '
+                                   '(and the last LAST of them alone)')
     b = sub.add_parser('traffic')
     b.add_argument('fetch_csv')
     b.add_argument('write_csv')
@@ -170,8 +177,9 @@ def main():
     if args.what == 'stats':
         text = stats_summary(args.csv, args.command)
         if args.chain:
-            k, n = args.chain.split(':')
-            text += chain_summary(args.trace, k, int(n))
+            parts = args.chain.split(':')
+            text += chain_summary(args.trace, parts[0], int(parts[1]),
+                                  int(parts[2]) if len(parts) > 2 else 0)
         with open(args.out, 'w') as fh:
             fh.write(text)
     else:

@@ -37,6 +37,8 @@ def test_chain_summary_spans_include_the_gaps(tmp_path):
     assert 'runs: 3' in text
     assert 'kernel duration per launch, mean: 10.00 us' in text
     assert f'mean: {(5 * 12 + 10) / 6:.2f} us' in text
+    last = P.chain_summary(str(path), 'fdm_contract', 6, last=2)
+    assert 'last 2 runs: kernel duration per launch 10.00 us' in last
 
 
 def test_traffic_scales_by_the_calibration_copy(tmp_path):
