@@ -231,7 +231,7 @@ __global__ __launch_bounds__(TPB, (kb_min_waves<S, RU>())) void kb_stage(BArgs a
 
   if (stage == 0 && wl == 0 && threadIdx.x == 0)
     __hip_atomic_store(&ctl->step_nonfinite, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // ---- A1: rhs = u + dt sum_{j<stage} a_ij k_j ; y = rhs ----
+  // ---- stage right-hand side: rhs = u + dt sum_{j<stage} a_ij k_j ; y = rhs ----
   for (int it = 0; it < nit; ++it) {
     const int row = r0 + it * TPB + threadIdx.x;
     if (row >= r1) break;
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(TPB, (kb_min_waves<S, RU>())) void kb_stage(BArgs a
   double rel = 0.0;
   const int P_max = a.paper_mode ? 1 : a.max_passes;
   for (int pass = 0;; ++pass) {
-    // ---- A2: k = K y ; res = rhs - y + sigma k ----
+    // ---- FP64 stage residual: k = K y ; res = rhs - y + sigma k ----
     double acc[BND] = {0.0, 0.0, 0.0, 0.0};
     for (int it = 0; it < nit; ++it) {
       const int row = r0 + it * TPB + threadIdx.x;

@@ -613,7 +613,7 @@ inline void fdm_axis_dft(int n, bool central, double nu, double b, double* Qr, d
 // residual update and the (r, z) product are split around the preconditioner.
 // ------------------------------------------------------------------------------------------
 
-// A3 for CG with an external preconditioner: r = LP(res / scale), (r, r); the tolerance and the
+// Start of a CG pass with an external preconditioner: r = LP(res / scale), (r, r); the tolerance and the
 // inner decision are set here, (r, z) by k_cg_rz after z = P^-1 r.
 template <typename S, typename C, int VEC>
 __global__ __launch_bounds__(TPB) void k_cg_begin_ext(Launch ln, const double* __restrict__ res,

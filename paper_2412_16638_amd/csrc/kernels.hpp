@@ -104,7 +104,8 @@ __device__ __forceinline__ void k64_group(const Geo& geo, const Coef<double>& K,
   }
 }
 
-// A2: k = K y ; res = rhs - y + sigma k ; ||res||^2, ||rhs||^2, non-finite count.
+// FP64 explicit evaluation and stage residual: k = K y ; res = rhs - y + sigma k ; ||res||^2,
+// ||rhs||^2, non-finite count.
 // The last block decides whether the stage is finished (outer residual loop).
 template <int VEC, int FMT>
 __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<double> K, Csr csr,
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(TPB) void k_bj_apply(Launch ln, const S* __restrict
 // Preconditioned CG in LP (heat).  BS = 0: no preconditioner (z is r).
 // ------------------------------------------------------------------------------------------
 
-// A3 for CG: r = LP(res / scale), z = BJ(r), rz = (r, z), rr = (r, r)
+// Start of a CG pass: r = LP(res / scale), z = BJ(r), rz = (r, z), rr = (r, r)
 template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_cg_begin(Launch ln, const double* __restrict__ res,
                                                   S* __restrict__ r, S* __restrict__ z,
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(TPB) void k_cg_upd(Launch ln, S* __restrict__ x,
   }
 }
 
-// A8 for CG: y += scale * x ; one LP pass done.
+// End of a CG pass: y += scale * x ; one LP pass done.
 template <typename S, typename C, int VEC>
 __global__ __launch_bounds__(TPB) void k_promote(Launch ln, double* __restrict__ y,
                                                  const S* __restrict__ x, Ctl* ctl) {
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(TPB) void k_promote(Launch ln, double* __restrict__
 // residual is the FP64 residual of the outer loop.
 // ------------------------------------------------------------------------------------------
 
-// A3 for GMRES: V_0 = LP(res / scale) ; zt = BJ(V_0) (the preconditioned direction of the first
+// Start of a GMRES cycle: V_0 = LP(res / scale) ; zt = BJ(V_0) (the preconditioned direction of the first
 // Arnoldi step, before normalisation; BJ is linear) ; beta = ||V_0||_rms.
 template <typename S, typename C, int VEC, int BS>
 __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __restrict__ res,
@@ -757,7 +758,7 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
   }
 }
 
-// A8 for GMRES: y += scale * BJ(sum_{i<J} ysol_i v_i) ; one LP pass done.  The J x J
+// End of a GMRES cycle: y += scale * BJ(sum_{i<J} ysol_i v_i) ; one LP pass done.  The J x J
 // triangular least-squares system is solved here by every block (J <= 32), so a cycle the
 // host ends early (fewer iterations enqueued than the device would run) is still promoted.
 // NDM bounds J: the host passes the number of Arnoldi steps it enqueued in this cycle.
