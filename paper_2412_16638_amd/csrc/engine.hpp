@@ -360,7 +360,11 @@ class EngineT final : public Engine {
     FdmGeo gxb{nx, fdm_ldq(nx), ny * nz, 0, 0, 0, 1, 0, skip};
     gxb.rk = H;
     gxb.ro = nx;
-    const FdmGeo gy{ny, fdm_ldq(ny), 0, H, H, (long)H * ny, nz, 0, skip};
+    // y: the nz batches of H columns folded into one contiguous index of H nz columns, so the
+    // 64-wide column tiles do not each end a batch half empty
+    FdmGeo gy{ny, fdm_ldq(ny), 0, H * nz, H, 0, 1, 0, skip};
+    gy.cfold = H;
+    gy.cstride = (long)H * ny;
     const FdmGeo gz{nz, fdm_ldq(nz), 0, H * ny, H * ny, 0, 1, 0, skip};
     if (c.prof) c.prof->before(KC_FDM, 6);
     fdm_go_cx<TI, C, 1, 0>(c, gxf, 1, cxd(0, 1.0), in, nullptr, t0, t0i, none);

@@ -50,6 +50,10 @@ struct FdmGeo {
   int skip_inner;  // 1: return once the inner solve is done (applies inside a Krylov loop)
   int rk = 0;    // complex ROW form: contraction extent = input row stride (0: n)
   int ro = 0;    // complex ROW form: outputs per row = output row stride (0: n)
+  // complex COL form with folded batches (cfold > 0, nb = 1): contiguous index c stands for
+  // batch c / cfold, element c % cfold, at (c / cfold) cstride + q ld + c % cfold
+  int cfold = 0;
+  long cstride = 0;
 };
 
 // Scaling by P_D^-1 (fused into a COL-form contraction along z): the output element with
@@ -342,6 +346,12 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
   }
   const int m0 = mt * BM, n0 = nt * FT_N;
   const size_t boff = ROW ? 0 : (size_t)b * g.bstride;
+  // COL form: offset of row q, contiguous index c (folded batches when g.cfold > 0; c and the
+  // three after it share a batch, as cfold is a multiple of 4)
+  auto coff = [&](int q, int c) -> size_t {
+    if (g.cfold > 0) return (size_t)(c / g.cfold) * g.cstride + (size_t)q * g.ld + (c % g.cfold);
+    return boff + (size_t)q * g.ld + c;
+  };
   const int tid = threadIdx.x;
   auto zero4 = [](Vec<C, 4>& v) {
 #pragma unroll
@@ -388,7 +398,7 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
       } else {
         load_q(rar[u], rai[u], m0 + row, q);
         const int kk = e >> 4, c = n0 + (e & 15) * 4, qq = q0 + kk;
-        const size_t off = boff + (size_t)qq * g.ld + c;
+        const size_t off = (qq < n && c < g.nc) ? coff(qq, c) : 0;
         load_data(rbr[u], in_r + off, qq < n && c < g.nc, g.nc - c);
         if constexpr (!INR) load_data(rbi[u], in_i + off, qq < n && c < g.nc, g.nc - c);
       }
@@ -544,7 +554,7 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
           off = (size_t)m * RO + col;
         } else {
           ok = m < n && col < g.nc;
-          off = boff + (size_t)m * g.ld + col;
+          off = ok ? coff(m, col) : 0;
         }
         if (ok) {
           out_r[off] = (TO)vr;
