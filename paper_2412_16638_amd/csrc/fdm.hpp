@@ -428,6 +428,15 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
   // both operands complex and the full result kept: three real products per complex one
   // (P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi); re = P1 - P2, im = P3 - P1 - P2)
   constexpr bool G3 = !AR && !BR && !OUTR;
+  // 16 x 16 product tiles of this wave with no output in range (a partial last tile, e.g. the
+  // H = nx/2 + 1 frequencies of the half spectrum) skip their products; wave-uniform
+  bool live[2][2];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+      live[mi][ni] = ROW ? (m0 + wm + 16 * mi < g.nr && n0 + wn + 16 * ni < RO)
+                         : (m0 + wm + 16 * mi < n && n0 + wn + 16 * ni < g.nc);
   Acc accr[2][2], acci[2][2], accq[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -474,6 +483,7 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
           for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
             for (int ni = 0; ni < 2; ++ni) {
+              if (!live[mi][ni]) continue;
               accr[mi][ni] = Mfma<C>::op(avr[mi].v[j], bvr[ni].v[j], accr[mi][ni]);
               accq[mi][ni] = Mfma<C>::op(avi[mi].v[j], bvi[ni].v[j], accq[mi][ni]);
               acci[mi][ni] = Mfma<C>::op(as[mi], bs[ni], acci[mi][ni]);
@@ -484,6 +494,7 @@ __global__ __launch_bounds__(256) void k_fdm_contract_cx(FdmGeo g, FdmCx cx,
         for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
           for (int ni = 0; ni < 2; ++ni) {
+            if (!live[mi][ni]) continue;
             // re += Ar Br - Ai Bi ; im += Ar Bi + Ai Br
             accr[mi][ni] = Mfma<C>::op(avr[mi].v[j], bvr[ni].v[j], accr[mi][ni]);
             if constexpr (!AR && !BR) accr[mi][ni] = Mfma<C>::op(-avi[mi].v[j], bvi[ni].v[j], accr[mi][ni]);
