@@ -46,7 +46,7 @@ enum mprk_status {
   MPRK_ENOMEM = -2,        /* host allocation failed or workspace too small */
   MPRK_EDEVICE = -3,       /* a HIP runtime call failed */
   MPRK_ENONFINITE = -4,    /* a residual became Inf/NaN; u is left at the last completed step */
-  MPRK_ENOTCONV = -5,      /* a stage missed outer_tol (only with precisions.strict != 0) */
+  MPRK_ENOTCONV = -5,      /* a stage missed its tolerance (only with precisions.strict != 0) */
   MPRK_EUNSUPPORTED = -6,  /* valid but not implemented combination */
   MPRK_ESTATE = -7         /* call out of order (e.g. step before bind) */
 };
@@ -120,7 +120,12 @@ typedef struct {
  *           to y.  The stage stops when ||res|| <= outer_tol ||rhs|| or after refine_max passes.
  *           refine_max = 0 is the paper's one-shot mode: exactly one LP solve (for GMRES one
  *           cycle) on the converted right-hand side, no residual check.
- *  strict: make a stage that misses outer_tol an error (MPRK_ENOTCONV).
+ *  strict: make a stage that misses its tolerance an error: outer_tol after refine_max passes,
+ *           or, with refine_max = 0, the LP solve's own tolerance within maxit.  The step of
+ *           that stage is not combined and the call's later steps are skipped, so u is left at
+ *           the last step whose stages all met it; mprk_step returns MPRK_ENOTCONV.  Without
+ *           strict such stages are counted in mprk_stats.missed and stepping continues (as the
+ *           paper's experiments keep stepping after a solve that hit its iteration cap).
  *  reorth: GMRES classical Gram-Schmidt with one re-orthogonalisation pass (CGS2).
  *  bj_shared: 0 = one stored inverse per block-Jacobi block (default); 1 = store each distinct
  *           diagonal block's inverse once plus a per-block index (a single shared inverse when
@@ -147,10 +152,17 @@ typedef struct {
   int32_t iters[MPRK_MAX_STAGES];   /* Krylov iterations summed over the outer passes */
   int32_t passes[MPRK_MAX_STAGES];  /* LP solves (outer passes) */
   double resid[MPRK_MAX_STAGES];    /* final FP64 ||res|| / ||rhs|| */
-  int32_t converged[MPRK_MAX_STAGES]; /* 1 if resid <= outer_tol (or paper mode finished) */
+  int32_t converged[MPRK_MAX_STAGES]; /* 1 if resid <= outer_tol; with refine_max = 0, 1 if the
+                                         one LP solve stopped on its own tolerance */
   int64_t total_iters;              /* cumulative over all steps */
   int64_t total_passes;
   int32_t nonfinite;                /* 1 if the last step hit a non-finite residual */
+  int32_t missed;                   /* stages, over every step since the previous statistics
+                                       read (mprk_step or mprk_stats_sync), that finished
+                                       without reaching their tolerance: resid > outer_tol
+                                       after the last allowed pass, or, with refine_max = 0,
+                                       an LP solve stopped by maxit, the GMRES cycle length or
+                                       a breakdown */
 } mprk_stats;
 
 typedef struct { int32_t iters, passes, converged; double resid; } mprk_solve_info;

@@ -61,7 +61,8 @@ class mprk_stats(C.Structure):
     _fields_ = [('steps', C.c_int64), ('t', C.c_double), ('stages', C.c_int32),
                 ('iters', C.c_int32 * MAX_STAGES), ('passes', C.c_int32 * MAX_STAGES),
                 ('resid', C.c_double * MAX_STAGES), ('converged', C.c_int32 * MAX_STAGES),
-                ('total_iters', C.c_int64), ('total_passes', C.c_int64), ('nonfinite', C.c_int32)]
+                ('total_iters', C.c_int64), ('total_passes', C.c_int64), ('nonfinite', C.c_int32),
+                ('missed', C.c_int32)]
 
     def as_dict(self):
         s = self.stages
@@ -69,7 +70,7 @@ class mprk_stats(C.Structure):
                 'iters': list(self.iters[:s]), 'passes': list(self.passes[:s]),
                 'resid': list(self.resid[:s]), 'converged': list(self.converged[:s]),
                 'total_iters': self.total_iters, 'total_passes': self.total_passes,
-                'nonfinite': self.nonfinite}
+                'nonfinite': self.nonfinite, 'missed': self.missed}
 
 
 class mprk_solve_info(C.Structure):

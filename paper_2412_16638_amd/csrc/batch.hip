@@ -243,6 +243,7 @@ __global__ __launch_bounds__(TPB, (kb_min_waves<S, RU>())) void kb_stage(BArgs a
   group_barrier(ctl, P.nwg);
 
   int passes = 0, total_iters = 0, converged = 0, nonfinite = 0;
+  bool last_conv = false;  // the last LP solve stopped on its own tolerance
   double rel = 0.0;
   const int P_max = a.paper_mode ? 1 : a.max_passes;
   for (int pass = 0;; ++pass) {
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(TPB, (kb_min_waves<S, RU>())) void kb_stage(BArgs a
       nonfinite = 1;
       break;
     }
-    converged = a.paper_mode ? (passes >= 1) : (rel <= a.outer_tol);
+    converged = a.paper_mode ? (passes >= 1 && last_conv) : (rel <= a.outer_tol);
     if (converged || passes >= P_max || rn == 0.0) break;
     const double scale = rn / sqrtN;
     const double inv = 1.0 / scale;
@@ -301,6 +302,7 @@ __global__ __launch_bounds__(TPB, (kb_min_waves<S, RU>())) void kb_stage(BArgs a
     double rz = t[0];
     const double tol = fmax(a.rtol * sqrt(t[1]), a.atol / scale);
     bool inner_done = sqrt(t[1]) <= tol;
+    bool inner_conv = inner_done;
     double beta = 0.0;
     int its = 0;
     while (!inner_done && its < a.maxit) {
@@ -328,7 +330,10 @@ __global__ __launch_bounds__(TPB, (kb_min_waves<S, RU>())) void kb_stage(BArgs a
       }
       group_reduce<BND>(acc3, 1, P, wl, parity, t);
       const double pq = t[0];
-      if (!(pq > 0.0) || !__builtin_isfinite(pq)) break;
+      if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
+        inner_conv = false;
+        break;
+      }
       const C alpha = (C)(rz / pq);
       // ---- C2: x += alpha p ; r -= alpha q ; z = BJ(r) ; (r, z), (r, r) ----
       double acc4[BND] = {0.0, 0.0, 0.0, 0.0};
@@ -375,8 +380,10 @@ __global__ __launch_bounds__(TPB, (kb_min_waves<S, RU>())) void kb_stage(BArgs a
       const double rz_new = t[0];
       beta = rz_new / rz;
       rz = rz_new;
-      inner_done = !__builtin_isfinite(t[1]) || sqrt(t[1]) <= tol;
+      inner_conv = __builtin_isfinite(t[1]) && sqrt(t[1]) <= tol;
+      inner_done = !__builtin_isfinite(t[1]) || inner_conv;
     }
+    last_conv = inner_conv;
     total_iters += its;
     // ---- promote: y += scale * x ----
     if (its > 0) {

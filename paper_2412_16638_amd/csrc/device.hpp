@@ -92,6 +92,11 @@ struct Ctl {
   // ---- body ----
   long long life_iters;   // Krylov iterations since bind
   long long life_passes;  // LP solves since bind
+  long long missed;       // stages finished without reaching their tolerance, since bind
+  long long held_steps;   // strict: steps not combined because a stage missed its tolerance
+  int inner_conv;         // the current LP solve stopped because it reached its tolerance
+  int step_held;          // strict: a stage of the current step missed (gates the combination)
+  int halt;               // strict: a stage missed in this call; its remaining stages are skipped
   double rhs_norm;    // ||rhs||_2
   double scale;       // LP right-hand side = res / scale (scale = ||res||_2 / sqrt(N))
   double tol;         // inner stopping tolerance in LP units
@@ -124,11 +129,15 @@ struct CtlHead {
 static_assert(sizeof(CtlHead) == 64, "poll head must be 64 bytes");
 
 
+// k_stage_rhs reset flags: a new stage, a new step, a new library call (clears the halt)
+enum { RESET_STAGE = 1, RESET_STEP = 2, RESET_CALL = 4 };
+
 struct SolveCfg {
   double sigma;        // tau a_ii
   double outer_tol;
   int max_passes;      // LP solves per stage (>= 1)
   int paper_mode;      // refine_max == 0
+  int strict;          // a stage that misses its tolerance fails the step (u is not updated)
   double rtol, atol;
   int maxit;           // Krylov iterations per LP solve
   int m;               // GMRES cycle length

@@ -669,7 +669,8 @@ __global__ __launch_bounds__(TPB) void k_cg_begin_ext(Launch ln, const double* _
     ctl->beta = 0.0;
     ctl->iters = 0;
     ctl->tol = fmax(cfg.rtol * bn, cfg.atol / ctl->scale);
-    ctl->inner_done = (bn <= ctl->tol) || cfg.maxit <= 0;
+    ctl->inner_conv = bn <= ctl->tol;
+    ctl->inner_done = ctl->inner_conv || cfg.maxit <= 0;
   }
 }
 
@@ -714,7 +715,8 @@ __global__ __launch_bounds__(TPB) void k_cg_upd_ext(Launch ln, S* __restrict__ x
     ctl->total_iters += 1;
     ctl->life_iters += 1;
     ctl->rr = rr;
-    ctl->inner_done = !__builtin_isfinite(rr) || sqrt(rr) <= ctl->tol || its >= cfg.maxit;
+    ctl->inner_conv = __builtin_isfinite(rr) && sqrt(rr) <= ctl->tol;
+    ctl->inner_done = !__builtin_isfinite(rr) || ctl->inner_conv || its >= cfg.maxit;
   }
 }
 
@@ -743,7 +745,10 @@ __global__ __launch_bounds__(TPB) void k_cg_rz(Launch ln, const S* __restrict__ 
     const double rz = tot[0];
     if (!BEGIN) ctl->beta = rz / ctl->rz;
     ctl->rz = rz;
-    if (!__builtin_isfinite(rz)) ctl->inner_done = 1;
+    if (!__builtin_isfinite(rz)) {
+      ctl->inner_done = 1;
+      ctl->inner_conv = 0;
+    }
   }
 }
 

@@ -46,15 +46,17 @@ struct CombArgs {
 // FP64 explicit parts
 // ------------------------------------------------------------------------------------------
 
-// rhs = u + sum_j c_j v_j ; y = rhs.  reset: 1 = new stage, 2 = new step (also clears the
-// step's non-finite flag).
+// rhs = u + sum_j c_j v_j ; y = rhs.  reset: RESET_STAGE clears the stage record, RESET_STEP
+// also the step's gating flags, RESET_CALL the strict halt of an earlier call.  A halted call
+// opens every later stage finished, so its solve kernels return at once.
 template <int VEC>
 __global__ __launch_bounds__(TPB) void k_stage_rhs(Launch ln, const double* __restrict__ u,
                                                    CombArgs a, double* __restrict__ rhs,
                                                    double* __restrict__ y, Ctl* ctl, int reset) {
   count_work(ctl, KC_STAGE_RHS);
   if (reset && blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->outer_done = 0;
+    if (reset & RESET_CALL) ctl->halt = 0;
+    ctl->outer_done = ctl->halt;
     ctl->inner_done = 0;
     ctl->passes = 0;
     ctl->iters = 0;
@@ -65,7 +67,10 @@ __global__ __launch_bounds__(TPB) void k_stage_rhs(Launch ln, const double* __re
     ctl->outer_rel = 0.0;
     ctl->res_norm = 0.0;
     ctl->rhs_norm = 0.0;
-    if (reset == 2) ctl->step_nonfinite = 0;
+    if (reset & RESET_STEP) {
+      ctl->step_nonfinite = 0;
+      ctl->step_held = ctl->halt;
+    }
   }
   const int L = xcd_block(ln.G);
   for (int it = 0; it < ln.nit; ++it) {
@@ -160,10 +165,19 @@ __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<doubl
     } else {
       ctl->converged = rel <= cfg.outer_tol;
       if (cfg.paper_mode) {
+        // one LP solve and no residual test: the stage counts as converged when that solve
+        // stopped on its own tolerance (not on its iteration cap or a breakdown)
         done = ctl->passes >= 1;
-        ctl->converged = done;
+        ctl->converged = done && ctl->inner_conv;
       } else {
         done = ctl->converged || ctl->passes >= cfg.max_passes || rn == 0.0;
+      }
+      if (done && !ctl->converged) {
+        ctl->missed += 1;
+        if (cfg.strict) {
+          ctl->step_held = 1;
+          ctl->halt = 1;
+        }
       }
     }
     ctl->scale = rn > 0.0 ? rn / cfg.sqrtN : 1.0;
@@ -220,10 +234,12 @@ __global__ __launch_bounds__(TPB) void k_keps(Launch ln, const double* __restric
 template <int VEC>
 __global__ __launch_bounds__(TPB) void k_combine(Launch ln, double* __restrict__ u, CombArgs a,
                                                  Ctl* ctl) {
-  const int bad = ctl->step_nonfinite;
+  const int nonfin = ctl->step_nonfinite, held = ctl->step_held;
+  const int bad = nonfin | held;
   count_work(ctl, KC_COMBINE);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (bad) ctl->bad_steps += 1;
+    if (nonfin) ctl->bad_steps += 1;
+    else if (held) ctl->held_steps += 1;
     else ctl->good_steps += 1;
   }
   if (bad) return;
@@ -352,7 +368,8 @@ __global__ __launch_bounds__(TPB) void k_cg_begin(Launch ln, const double* __res
     ctl->beta = 0.0;
     ctl->iters = 0;
     ctl->tol = fmax(cfg.rtol * bn, cfg.atol / ctl->scale);
-    ctl->inner_done = (bn <= ctl->tol) || cfg.maxit <= 0;
+    ctl->inner_conv = bn <= ctl->tol;
+    ctl->inner_done = ctl->inner_conv || cfg.maxit <= 0;
   }
 }
 
@@ -392,6 +409,7 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(Launch ln, Geo geo, Coef<C> M, C
     ctl->pq = pq;
     if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
       ctl->inner_done = 1;  // breakdown: keep the current iterate
+      ctl->inner_conv = 0;
       ctl->alpha = 0.0;
     } else {
       ctl->alpha = ctl->rz / pq;
@@ -464,7 +482,8 @@ __global__ __launch_bounds__(TPB) void k_cg_upd(Launch ln, S* __restrict__ x,
     ctl->rz = rz;
     ctl->rr = rr;
     const bool fin = __builtin_isfinite(rr) && __builtin_isfinite(rz);
-    ctl->inner_done = !fin || sqrt(rr) <= ctl->tol || its >= cfg.maxit;
+    ctl->inner_conv = fin && sqrt(rr) <= ctl->tol;
+    ctl->inner_done = !fin || ctl->inner_conv || its >= cfg.maxit;
   }
 }
 
@@ -550,7 +569,8 @@ __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __res
     ctl->J = 0;
     ctl->iters = 0;
     ctl->tol = fmax(cfg.rtol * beta, cfg.atol / (ctl->scale * cfg.sqrtN));
-    ctl->inner_done = (beta <= ctl->tol) || beta == 0.0 || cfg.maxit <= 0;
+    ctl->inner_conv = (beta <= ctl->tol) || beta == 0.0;
+    ctl->inner_done = ctl->inner_conv || cfg.maxit <= 0;
   }
 }
 
@@ -564,6 +584,7 @@ __device__ __forceinline__ bool gm_bound_exceeded(Ctl* ctl, int nd, int ndm) {
     ctl->nonfinite = 1;
     ctl->step_nonfinite = 1;
     ctl->inner_done = 1;
+    ctl->inner_conv = 0;
   }
   return true;
 }
@@ -750,7 +771,9 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
     ctl->vscale[J] = hn > 0.0 ? 1.0 / hn : 0.0;
     const double resid = fabs(ctl->g[J]);
     const bool fin = __builtin_isfinite(resid) && __builtin_isfinite(den);
-    const bool stop = !fin || resid <= ctl->tol || hn == 0.0 || J >= cfg.m || its >= cfg.maxit;
+    const bool conv = fin && (resid <= ctl->tol || hn == 0.0);
+    const bool stop = !fin || conv || J >= cfg.m || its >= cfg.maxit;
+    ctl->inner_conv = conv;
     if (stop) ctl->inner_done = 1;
     if (!fin) {  // drop this cycle: the promoted correction is zero
       for (int i = 0; i <= J; ++i) ctl->g[i] = 0.0;

@@ -593,6 +593,7 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
     c.outer_tol = p.outer_tol;
     c.max_passes = std::max(p.refine_max, 1);
     c.paper_mode = p.refine_max == 0;
+    c.strict = p.strict != 0;
     c.rtol = p.rtol;
     c.atol = p.atol;
     c.m = p.krylov == MPRK_GMRES ? p.restart : 0;
@@ -695,6 +696,11 @@ extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev,
   HIPCHK(hipMemsetAsync(h->ws + h->o_ctl, 0, sizeof(Ctl), h->stream));
   HIPCHK(hipMemsetAsync(h->ws + h->o_flag, 0, 256, h->stream));
   HIPCHK(hipMemsetAsync(h->ws + h->o_tick, 0, red_ticks(h->pstride) * 4, h->stream));
+  // the device counters restart from zero with the control record
+  h->good_base = 0;
+  h->bad_base = 0;
+  h->missed_base = 0;
+  h->held_base = 0;
   EngineCtx c = h->ctx();
   if (h->op.format == MPRK_FMT_CSR) {
     std::vector<int> rp, cl;
@@ -881,7 +887,9 @@ int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* k
 // device marks the stage finished.  With a valid history of this stage, each predicted pass
 // enqueues its Krylov iterations (last count + margin) and its promotion without waiting: an
 // inner solve cut short only leaves a larger FP64 residual for the next pass.  The host waits
-// for the device only where the history says the stage may already be finished.
+// for the device only where the history says the stage may already be finished.  The one-solve
+// mode has no later pass to absorb a solve cut short, so there the predicted count is only the
+// first chunk: the host keeps enqueuing chunks until the device reports the solve finished.
 int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, double* kout,
                            const double* force) {
   int rc = update_hist(slot);
@@ -901,9 +909,11 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
     rc = launch_residual(si, rhs, y, kout, force);
     if (rc) return rc;
     if (pass == P) break;
-    const bool certain = H.valid && pass < H.passes;
+    const bool predicted = H.valid && pass < H.passes;
+    const bool certain = predicted && !cfg.paper_mode;
     int slot_id = 0;
-    if (!certain) {
+    // (the one-solve mode's only pass always runs: its residual sets no decision before it)
+    if (!certain && !(cfg.paper_mode && pass == 0)) {
       rc = poll_enqueue(&slot_id);
       if (rc) return rc;
       CtlHead hd;
@@ -926,7 +936,8 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
       int its = 0;
       bool inner = false, outer = false;
       while (its < maxp && !inner && !outer) {
-        const int cnt = std::min(chunk, maxp - its);
+        const int want = (predicted && its == 0) ? H.iters[pass] + predict_margin : chunk;
+        const int cnt = std::min(std::max(want, 1), maxp - its);
         for (int k = 0; k < cnt; ++k) {
           if (cg) HIPCHK(eng->cg_iter(c, cfg, Mc, dinv, its + k));
           else HIPCHK(eng->gm_iter(c, cfg, Mc, dinv, its + k));
@@ -955,7 +966,7 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
   return stage_record(slot);
 }
 
-int mprk_handle::enqueue_step() {
+int mprk_handle::enqueue_step(bool first_of_call) {
   Ctl* ctl = (Ctl*)(ws + o_ctl);
   double* rhs = (double*)(ws + o_rhs);
   double* y = (double*)(ws + o_y);
@@ -983,7 +994,8 @@ int mprk_handle::enqueue_step() {
         a.c[a.nv++] = dt * al;
       }
     }
-    const int reset = i == 0 ? 2 : 1;
+    const int reset = i > 0 ? RESET_STAGE
+                            : RESET_STAGE | RESET_STEP | (first_of_call ? RESET_CALL : 0);
     if (vec == 4)
       PLAUNCH(KC_STAGE_RHS, (k_stage_rhs<4>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, rhs, y, ctl, reset);
     else
@@ -1057,11 +1069,23 @@ void mprk_handle::fill_stats(mprk_stats* st) {
   st->total_iters = life_iters;
   st->total_passes = life_passes;
   st->nonfinite = last_nonfinite;
+  st->missed = last_missed;
+}
+
+int mprk_handle::rebase_missed() {
+  Ctl* ctl = (Ctl*)(ws + o_ctl);
+  long long m = 0;
+  HIPCHK(hipMemcpyAsync(&m, &ctl->missed, sizeof(m), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  missed_base = m;
+  return MPRK_OK;
 }
 
 int mprk_handle::sync_counters() {
   Ctl* ctl = (Ctl*)(ws + o_ctl);
-  long long lf[2];
+  long long lf[4];  // life_iters, life_passes, missed, held_steps (adjacent in Ctl)
+  static_assert(offsetof(Ctl, held_steps) == offsetof(Ctl, life_iters) + 3 * sizeof(long long),
+                "counters read together");
   CtlHead hd;
   HIPCHK(hipMemcpyAsync(&hd, ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipMemcpyAsync(lf, &ctl->life_iters, sizeof(lf), hipMemcpyDeviceToHost, stream));
@@ -1074,6 +1098,10 @@ int mprk_handle::sync_counters() {
   t_now += dt * (double)good;
   life_iters = lf[0];
   life_passes = lf[1];
+  last_missed = (int)(lf[2] - missed_base);
+  missed_base = lf[2];
+  last_held = (int)(lf[3] - held_base);
+  held_base = lf[3];
   last_nonfinite = bad > 0;
   return bad > 0 ? MPRK_ENONFINITE : MPRK_OK;
 }
@@ -1083,18 +1111,17 @@ extern "C" int32_t mprk_step(mprk_handle* h, int32_t nsteps, mprk_stats* stats) 
   if (!h->bound) return set_error(MPRK_ESTATE, "mprk_step before mprk_bind");
   if (nsteps < 0) return set_error(MPRK_EINVAL, "nsteps must be >= 0");
   for (int n = 0; n < nsteps; ++n) {
-    int rc = h->enqueue_step();
+    int rc = h->enqueue_step(n == 0);
     if (rc) return rc;
   }
   int rc = h->sync_counters();
   if (stats) h->fill_stats(stats);
   if (rc == MPRK_ENONFINITE) return set_error(rc, "non-finite residual: u left at the last completed step");
-  if (h->prec.strict) {
-    mprk_stats st;
-    h->fill_stats(&st);
-    for (int i = 0; i < h->nstages; ++i)
-      if (!st.converged[i]) return set_error(MPRK_ENOTCONV, "a stage missed outer_tol");
-  }
+  // every stage of every step of this call counts, not only the last step's record; the
+  // device stopped combining at the first step with a missed stage
+  if (h->prec.strict && (h->last_missed > 0 || h->last_held > 0))
+    return set_error(MPRK_ENOTCONV, "a stage missed its tolerance: u left at the last step whose "
+                                    "stages all met it");
   return MPRK_OK;
 }
 
@@ -1111,10 +1138,10 @@ extern "C" int32_t mprk_solve(mprk_handle* h, int32_t stage, const double* rhs_d
   double* rhs = (double*)(h->ws + h->o_rhs);
   if (h->vec == 4)
     hipLaunchKernelGGL((k_stage_rhs<4>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, rhs_dev, a, rhs,
-                       x_dev, ctl, 1);
+                       x_dev, ctl, RESET_STAGE | RESET_CALL);
   else
     hipLaunchKernelGGL((k_stage_rhs<1>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, rhs_dev, a, rhs,
-                       x_dev, ctl, 1);
+                       x_dev, ctl, RESET_STAGE | RESET_CALL);
   HIPCHK(hipGetLastError());
   int rc = h->run_solve(h->sig_idx[stage], MPRK_MAX_STAGES, rhs, x_dev, (double*)(h->ws + h->o_scr),
                         nullptr);
@@ -1122,6 +1149,9 @@ extern "C" int32_t mprk_solve(mprk_handle* h, int32_t stage, const double* rhs_d
   CtlHead hd;
   HIPCHK(hipMemcpyAsync(&hd, ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  // a missed solve here is reported in info, not by the next mprk_step
+  rc = h->rebase_missed();
+  if (rc) return rc;
   if (info) {
     info->iters = hd.total_iters;
     info->passes = hd.passes;
@@ -1380,9 +1410,11 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
       const unsigned nb = (unsigned)((h->N + 255) / 256);
       hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.37, 0.011, y64);
       if (h->vec == 4)
-        hipLaunchKernelGGL((k_stage_rhs<4>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, y64, ca, rhs, x64, ctl, 1);
+        hipLaunchKernelGGL((k_stage_rhs<4>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, y64, ca, rhs, x64, ctl,
+                           RESET_STAGE | RESET_CALL);
       else
-        hipLaunchKernelGGL((k_stage_rhs<1>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, y64, ca, rhs, x64, ctl, 1);
+        hipLaunchKernelGGL((k_stage_rhs<1>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, y64, ca, rhs, x64, ctl,
+                           RESET_STAGE | RESET_CALL);
       hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.23, 0.017, x64);
       if (hipGetLastError() != hipSuccess) { rc = MPRK_EDEVICE; break; }
       rc = h->launch_residual(si, rhs, x64, y64, nullptr);
@@ -1417,6 +1449,8 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
   h->ln_row_red = make_launch_nit(ngr, best.nrr);
   h->ln_lp = make_launch_nit(ngl, best.nl);
   h->ln_lp_red = make_launch_nit(ngl, best.nlr);
+  // the timing residuals may have counted stages as missed; they are no step's stages
+  if (h->rebase_missed()) return set_error(MPRK_EDEVICE, "autotune: counter read failed");
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[key] = best;

@@ -116,7 +116,11 @@ struct mprk_handle {
   long long good_base = 0;
   int bad_base = 0;
   long long life_iters = 0, life_passes = 0;
+  long long missed_base = 0;  // device count of missed stages at the last sync
+  long long held_base = 0;    // device count of strict-held steps at the last sync
+  int last_held = 0;          // steps held back by strict since the previous sync
   int last_nonfinite = 0;
+  int last_missed = 0;        // stages that missed their tolerance since the previous sync
 
   int init(const mprk_grid& g, const mprk_operator& o, const mprk_tableau& t,
            const mprk_precisions& p, double dt_, hipStream_t s);
@@ -132,7 +136,8 @@ struct mprk_handle {
   int launch_residual(int si, const double* rhs, double* y, double* kout, const double* force);
   int launch_apply64(const double* x, double* y, double sigma, int mode, const double* force = nullptr);
   int run_solve(int si, int slot, const double* rhs, double* y, double* kout, const double* force);
-  int enqueue_step();
+  int enqueue_step(bool first_of_call);
   int sync_counters();
+  int rebase_missed();
   void fill_stats(mprk_stats* st);
 };

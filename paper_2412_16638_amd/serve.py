@@ -31,6 +31,7 @@ class JobResult:
     ok: bool
     stats: dict | None = None
     u: np.ndarray | None = None
+    error: str | None = None
 
     @property
     def latency(self) -> float:
@@ -118,6 +119,11 @@ class FakeBackend:
     def duration(self, p) -> float:
         return self.sec_per_dof_step * p.N * p.nsteps
 
+    def run(self, p):
+        """Wall-clock stand-in for Server.run: sleeps the job's duration."""
+        time.sleep(self.duration(p))
+        return True, None, None
+
 
 class Server:
     def __init__(self, backend, max_active: int = 8, budget: int | None = None):
@@ -196,14 +202,22 @@ class Server:
         t0 = time.perf_counter()
 
         def work(r, t_adm):
-            ok, stats, u = be.run(r.problem)
-            t_fin = time.perf_counter() - t0
-            with lock:
-                state['used'] -= fps[r.rid]
-                state['active'] -= 1
-                results.append(JobResult(r.rid, r.arrival * time_scale, t_adm, t_fin,
-                                         r.problem.N * r.problem.nsteps, fps[r.rid], ok, stats, u))
-                lock.notify_all()
+            # the slot and the footprint are released whatever the job does: a job that raises
+            # (device memory exhausted, a rejected problem) is recorded as failed with its error
+            ok, stats, u, err = False, None, None, None
+            try:
+                ok, stats, u = be.run(r.problem)
+            except Exception as e:  # noqa: BLE001 -- any failure of one job is that job's result
+                err = f'{type(e).__name__}: {e}'
+            finally:
+                t_fin = time.perf_counter() - t0
+                with lock:
+                    state['used'] -= fps[r.rid]
+                    state['active'] -= 1
+                    results.append(JobResult(r.rid, r.arrival * time_scale, t_adm, t_fin,
+                                             r.problem.N * r.problem.nsteps, fps[r.rid], ok, stats,
+                                             u, err))
+                    lock.notify_all()
 
         queue = []
         i = 0

@@ -75,3 +75,28 @@ def test_seeded_request_mix_statistics():
     lat = np.array([r.latency for r in out['results']])
     assert out['p50_s'] == pytest.approx(np.percentile(lat, 50))
     assert out['p99_s'] >= out['p50_s']
+
+
+class _RaisingBackend(S.FakeBackend):
+    """Wall-clock fake whose job `bad` raises, as a job does when its device memory runs out."""
+
+    def __init__(self, bad, **kw):
+        super().__init__(**kw)
+        self.bad = bad
+
+    def run(self, p):
+        if p.name == f'r{self.bad}':
+            raise MemoryError('workspace allocation failed')
+        return super().run(p)
+
+
+def test_a_job_that_raises_releases_its_slot_and_is_reported_failed():
+    # one slot: if the raising job kept it, the three jobs queued behind it would never start
+    be = _RaisingBackend(1, sec_per_dof_step=1e-6, bytes_per_dof=1, budget=10 ** 9)
+    reqs = [_req(i, 0.0, 10, 2) for i in range(5)]            # 2 ms each
+    out = S.Server(be, max_active=1).run(reqs)
+    assert out['n'] == 5 and out['failed'] == 1
+    res = {r.rid: r for r in out['results']}
+    assert not res[1].ok and 'MemoryError' in res[1].error
+    assert all(res[i].ok and res[i].error is None for i in (0, 2, 3, 4))
+    assert out['peak_active'] == 1
