@@ -42,8 +42,9 @@ def _smooth_and_rough(krylov, n=16):
 def test_one_solve_mode_finishes_a_solve_longer_than_predicted(krylov):
     p, smooth, rough = _smooth_and_rough(krylov)
     log_case('one_solve_longer_than_predicted', krylov=krylov)
-    over = dict(refine_max=0, rtol=1e-6, precond='none')
+    over = dict(refine_max=0, rtol=1e-6)
     p.precision = 'fp32'
+    p.precond = 'none'
     # handle A: a first step whose solves take 1-2 iterations sets the history, then a rough state
     a = M.from_problem(p, **over)
     a.set_u(smooth)
@@ -89,10 +90,10 @@ def test_solve_stopped_by_its_iteration_cap_is_reported_not_an_error(krylov):
 def test_strict_miss_returns_enotconv_and_keeps_u_at_the_last_good_step():
     p, smooth, rough = _smooth_and_rough('cg')
     p.precision = 'fp64'
+    p.precond = 'none'
     log_case('strict_miss')
     # one CG iteration per pass, two passes: exact for the sine mode, far from 1e-10 otherwise
-    st = M.from_problem(p, precond='none', strict=1, maxit=1, refine_max=2, rtol=1e-12,
-                        outer_tol=1e-10)
+    st = M.from_problem(p, strict=1, maxit=1, refine_max=2, rtol=1e-12, outer_tol=1e-10)
     st.set_u(smooth)
     st.step(2)                                # both steps meet the tolerance
     assert st.state()[1] == 2
