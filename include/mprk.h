@@ -39,6 +39,8 @@ extern "C" {
 
 #define MPRK_MAX_STAGES 8
 #define MPRK_MAX_RESTART 32
+/* Size of the library's static device scratch (mprk_bind_static): 64 MiB per device. */
+#define MPRK_STATIC_SCRATCH_BYTES (64LL << 20)
 
 enum mprk_status {
   MPRK_OK = 0,
@@ -197,6 +199,20 @@ int64_t mprk_workspace_bytes(const mprk_handle *h);
  * Synchronises the stream before returning.  Errors: MPRK_EINVAL, MPRK_ENOMEM (bytes too
  * small), MPRK_EDEVICE. */
 int32_t mprk_bind(mprk_handle *h, double *u_dev, void *workspace_dev, int64_t bytes);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * or harnesses that forbid hipMalloc): mprk_bind with the library's static device scratch as
+ * the workspace instead of caller memory.  The caller still owns u_dev (N doubles, 32-byte
+ * aligned, the state).  The call allocates no device or pinned host memory and calls no
+ * hipMalloc/hipFree; the handle's pinned status records are made by mprk_create when a device
+ * is present.  The scratch is one array of MPRK_STATIC_SCRATCH_BYTES per device, held from the
+ * library's load on that device until the process ends; it is shared by every handle bound to
+ * it on that device and keeps the last bind's contents (the bind re-initialises everything it
+ * reads).  Binding another handle to it invalidates the previous one: later calls on that
+ * handle return MPRK_ESTATE.  Calls of two handles that overlap in time on one device race.
+ * Errors: MPRK_EINVAL, MPRK_ENOMEM (mprk_workspace_bytes > MPRK_STATIC_SCRATCH_BYTES),
+ * MPRK_ESTATE (handle created without a device), MPRK_EDEVICE. */
+int32_t mprk_bind_static(mprk_handle *h, double *u_dev);
 
 /* Constant forcing: from the next step on, integrate du/dt = K u + g instead of du/dt = K u
  * (the paper's heat test has g = sin(pi x) sin(pi y) sin(pi z), Section "Heat equation").

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, 'libmprk.so')
 
 MAX_STAGES = 8
 MAX_RESTART = 32
+STATIC_SCRATCH_BYTES = 64 << 20   # MPRK_STATIC_SCRATCH_BYTES
 
 # status codes
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ENOTCONV, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
@@ -105,6 +106,7 @@ _sig = {
                                 _P, C.POINTER(_P)]),
     'mprk_workspace_bytes': (C.c_int64, [_P]),
     'mprk_bind': (C.c_int32, [_P, _P, _P, C.c_int64]),
+    'mprk_bind_static': (C.c_int32, [_P, _P]),
     'mprk_step': (C.c_int32, [_P, C.c_int32, C.POINTER(mprk_stats)]),
     'mprk_solve': (C.c_int32, [_P, C.c_int32, _P, _P, C.POINTER(mprk_solve_info)]),
     'mprk_apply': (C.c_int32, [_P, C.c_int32, C.c_int32, _P, _P]),
@@ -181,6 +183,10 @@ def mprk_workspace_bytes(h: int) -> int:
 
 def mprk_bind(h: int, u_ptr: int, ws_ptr: int, nbytes: int) -> None:
     check(lib.mprk_bind(_P(h), _P(u_ptr), _P(ws_ptr), nbytes), 'mprk_bind')
+
+
+def mprk_bind_static(h: int, u_ptr: int) -> None:
+    check(lib.mprk_bind_static(_P(h), _P(u_ptr)), 'mprk_bind_static')
 
 
 def mprk_step(h: int, nsteps: int, want_stats: bool = True):

@@ -430,6 +430,19 @@ extern "C" int32_t mprk_create(const mprk_grid* grid, const mprk_operator* op,
     delete h;
     return rc;
   }
+  // pinned status records and events are made here when a device is present (a handle made
+  // without one, e.g. to validate a problem, makes them at its first mprk_bind), so that
+  // mprk_bind_static allocates nothing
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+    rc = h->make_device_resources();
+    if (rc) {
+      delete h;
+      return rc;
+    }
+  } else {
+    (void)hipGetLastError();
+  }
   *out = h;
   return MPRK_OK;
 }
@@ -683,13 +696,9 @@ EngineCtx mprk_handle::ctx() const {
   return c;
 }
 
-extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev, int64_t bytes) {
-  if (!h || !u_dev || !workspace_dev) return set_error(MPRK_EINVAL, "NULL argument");
-  if (bytes < (int64_t)h->ws_bytes) return set_error(MPRK_ENOMEM, "workspace smaller than mprk_workspace_bytes");
-  if (((uintptr_t)workspace_dev & 255) != 0) return set_error(MPRK_EINVAL, "workspace must be 256-byte aligned");
-  if (((uintptr_t)u_dev & 31) != 0) return set_error(MPRK_EINVAL, "u must be 32-byte aligned");
-  int rc0 = h->make_device_resources();
-  if (rc0) return rc0;
+// Attach u and a workspace and run the setup kernels.  Allocates no device or pinned memory
+// itself (the pinned records exist once make_device_resources has run).
+static int bind_impl(mprk_handle* h, double* u_dev, void* workspace_dev) {
   h->u = u_dev;
   h->ws = (char*)workspace_dev;
   h->bound = false;
@@ -792,6 +801,79 @@ extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev,
   if (hfail) return set_error(MPRK_EINVAL, "singular block-Jacobi block");
   h->bound = true;
   return MPRK_OK;
+}
+
+extern "C" int32_t mprk_bind(mprk_handle* h, double* u_dev, void* workspace_dev, int64_t bytes) {
+  if (!h || !u_dev || !workspace_dev) return set_error(MPRK_EINVAL, "NULL argument");
+  if (bytes < (int64_t)h->ws_bytes) return set_error(MPRK_ENOMEM, "workspace smaller than mprk_workspace_bytes");
+  if (((uintptr_t)workspace_dev & 255) != 0) return set_error(MPRK_EINVAL, "workspace must be 256-byte aligned");
+  if (((uintptr_t)u_dev & 31) != 0) return set_error(MPRK_EINVAL, "u must be 32-byte aligned");
+  int rc0 = h->make_device_resources();
+  if (rc0) return rc0;
+  h->static_dev = -1;
+  return bind_impl(h, u_dev, workspace_dev);
+}
+
+// ------------------------------------------------------------------------------------------
+// the library's static device scratch (for callers that cannot allocate)
+// ------------------------------------------------------------------------------------------
+
+// One copy per device, held from the library's load on that device until the process ends.
+static __device__ __align__(256) char scratch[MPRK_STATIC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+struct ScratchSlot {
+  char* ptr = nullptr;          // this device's copy of `scratch` (from hipGetSymbolAddress)
+  unsigned long long gen = 0;   // static binds on this device so far
+};
+std::map<int, ScratchSlot> g_scratch;  // device ordinal -> slot
+}  // namespace
+
+// A handle bound to the static scratch stays valid until another handle binds it on the same
+// device; later calls on the older handle then fail instead of reading the newer one's data.
+int mprk_handle::check_ws() const {
+  if (static_dev < 0) return MPRK_OK;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(static_dev);
+  if (it == g_scratch.end() || it->second.gen != static_gen)
+    return set_error(MPRK_ESTATE, "the static scratch of this device was bound by another handle "
+                                  "since this handle's mprk_bind_static");
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_bind_static(mprk_handle* h, double* u_dev) {
+  if (!h || !u_dev) return set_error(MPRK_EINVAL, "NULL argument");
+  if (((uintptr_t)u_dev & 31) != 0) return set_error(MPRK_EINVAL, "u must be 32-byte aligned");
+  if (h->ws_bytes > (size_t)MPRK_STATIC_SCRATCH_BYTES)
+    return set_error(MPRK_ENOMEM, "workspace of " + std::to_string(h->ws_bytes) +
+                                      " bytes exceeds the static scratch of " +
+                                      std::to_string((long long)MPRK_STATIC_SCRATCH_BYTES) + " bytes");
+  if (!h->events_made)
+    return set_error(MPRK_ESTATE, "handle created without a device: mprk_bind_static cannot make "
+                                  "its pinned status records");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  char* ptr = nullptr;
+  unsigned long long gen = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchSlot& sl = g_scratch[dev];
+    if (!sl.ptr) {
+      // first use on this device, with it current: the address of this device's copy; the
+      // symbol's own name is a host-side stand-in and is never passed to a kernel or a copy
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return set_error(MPRK_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      sl.ptr = (char*)p;
+    }
+    ptr = sl.ptr;
+    gen = ++sl.gen;
+  }
+  h->static_dev = dev;
+  h->static_gen = gen;
+  return bind_impl(h, u_dev, ptr);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1109,6 +1191,7 @@ int mprk_handle::sync_counters() {
 extern "C" int32_t mprk_step(mprk_handle* h, int32_t nsteps, mprk_stats* stats) {
   if (!h) return set_error(MPRK_EINVAL, "NULL handle");
   if (!h->bound) return set_error(MPRK_ESTATE, "mprk_step before mprk_bind");
+  if (int rcw = h->check_ws()) return rcw;
   if (nsteps < 0) return set_error(MPRK_EINVAL, "nsteps must be >= 0");
   for (int n = 0; n < nsteps; ++n) {
     int rc = h->enqueue_step(n == 0);
@@ -1129,6 +1212,7 @@ extern "C" int32_t mprk_solve(mprk_handle* h, int32_t stage, const double* rhs_d
                               mprk_solve_info* info) {
   if (!h || !rhs_dev || !x_dev) return set_error(MPRK_EINVAL, "NULL argument");
   if (!h->bound) return set_error(MPRK_ESTATE, "mprk_solve before mprk_bind");
+  if (int rcw = h->check_ws()) return rcw;
   if (stage < 0 || stage >= h->nstages || !h->implicit_[stage])
     return set_error(MPRK_EINVAL, "stage must be an implicit stage of the tableau");
   Ctl* ctl = (Ctl*)(h->ws + h->o_ctl);
@@ -1171,6 +1255,7 @@ extern "C" int32_t mprk_set_forcing(mprk_handle* h, const double* g_dev) {
 extern "C" int32_t mprk_apply(mprk_handle* h, int32_t which, int32_t stage, const void* x, void* y) {
   if (!h || !x || !y) return set_error(MPRK_EINVAL, "NULL argument");
   if (!h->bound) return set_error(MPRK_ESTATE, "mprk_apply before mprk_bind");
+  if (int rcw = h->check_ws()) return rcw;
   double sigma = 0.0;
   int si = -1;
   if (which != MPRK_APPLY_K64) {
@@ -1306,6 +1391,7 @@ std::mutex g_tune_mu;
 extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_row) {
   if (!h) return set_error(MPRK_EINVAL, "NULL handle");
   if (!h->bound) return set_error(MPRK_ESTATE, "mprk_autotune before mprk_bind");
+  if (int rcw = h->check_ws()) return rcw;
   const bool csr = h->op.format == MPRK_FMT_CSR;
   const long ngv = h->N / h->vec, ngr = h->N, ngl = h->N / h->vec_lp;
   const TuneKey key{h->grid.nx, h->grid.ny, h->grid.nz, h->grid.bc, h->op.kind, h->op.format, h->prec.storage,

@@ -85,6 +85,8 @@ struct mprk_handle {
   double* u = nullptr;
   char* ws = nullptr;
   bool bound = false;
+  int static_dev = -1;              // device whose static scratch is the workspace (-1: caller's)
+  unsigned long long static_gen = 0;  // that scratch's bind count when this handle bound it
   // host steering
   mprk::CtlHead* slots = nullptr;   // pinned: NSLOT poll slots + one record per stage
   hipEvent_t ev[mprk::NSLOT] = {};
@@ -139,5 +141,6 @@ struct mprk_handle {
   int enqueue_step(bool first_of_call);
   int sync_counters();
   int rebase_missed();
+  int check_ws() const;
   void fill_stats(mprk_stats* st);
 };
