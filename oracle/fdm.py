@@ -16,15 +16,22 @@ Kronecker factor is the product T_L T_M T_R of one-axis contractions, which in t
 0-based index notation (x_{ijk} = x[i + j nx + k nx ny]) read
     (T_R x)_{ijk} = sum_q Q_{iq} x_{qjk},  (T_M x)_{ijk} = sum_q Q_{jq} x_{iqk},
     (T_L x)_{ijk} = sum_q Q_{kq} x_{ijq}.
-Here the decompositions come from numpy's general eigensolver (complex for the non-symmetric
-advection operator); arrays are held as (nz, ny, nx).
+Every factor built here is a normal matrix (symmetric for the heat operator, circulant for the
+periodic advection operators), so it has a unitary eigenbasis: the decompositions come from the
+symmetric eigensolver (heat) or the complex Schur form A = Z T Z^H, whose triangular T is then
+diagonal (checked; Q_A = Z, Q_A^-1 = Z^H).  A general eigensolver would also diagonalise these factors, but where pure
+central advection repeats eigenvalues (the symbol sin(theta) takes each value twice) its bases
+are ill-conditioned and their inverse loses digits; a non-normal factor (advection with
+Dirichlet ends) is rejected rather than decomposed.  Arrays are held as (nz, ny, nx).
 
 Pins (tests/test_oracle_fdm.py): P assembled from A, B, C equals the stage matrix; P^-1 r
-equals a sparse direct solve; each contraction matches a brute-force loop on a non-cubic grid.
+equals a sparse direct solve to 1e-11 for every case, including pure central advection; the
+bases are unitary; each contraction matches a brute-force loop on a non-cubic grid.
 """
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg as sla
 import scipy.sparse as sp
 
 from .operators import central_difference_1d, second_difference_1d, spacing, upwind_difference_1d
@@ -61,6 +68,22 @@ def assemble(A, B, C) -> sp.csr_matrix:
     return P.tocsr()
 
 
+def unitary_eigenbasis(M):
+    """(lam, Z) with M = Z diag(lam) Z^H, Z unitary, for a normal matrix M: the symmetric
+    eigensolver for a symmetric M (real orthogonal Z), else the complex Schur form.  Raises
+    ValueError when the Schur form is not diagonal (M not normal)."""
+    M = np.asarray(M)
+    if np.isrealobj(M) and np.array_equal(M, M.T):
+        return sla.eigh(M)
+    T, Z = sla.schur(M.astype(np.complex128), output='complex')
+    scale = max(float(np.abs(M).max()), np.finfo(float).tiny)
+    off = float(np.abs(np.triu(T, 1)).max(initial=0.0))
+    if off > 1e-12 * scale:
+        raise ValueError(f'factor is not normal (Schur off-diagonal {off / scale:.1e} of its '
+                         'largest entry): no unitary eigenbasis')
+    return np.diag(T).copy(), Z
+
+
 def t_r(Q, x):
     """(T_R x)_{ijk} = sum_q Q_{iq} x_{qjk}; x has shape (nz, ny, nx)."""
     return np.einsum('iq,kjq->kji', Q, x)
@@ -85,10 +108,10 @@ class FDM:
         self.factors = (A, B, C)
         self.lam, self.Q, self.Qinv = [], [], []
         for M in (A, B, C):
-            w, Q = np.linalg.eig(M)
+            w, Q = unitary_eigenbasis(M)
             self.lam.append(w)
             self.Q.append(Q)
-            self.Qinv.append(np.linalg.inv(Q))
+            self.Qinv.append(Q.conj().T)
         la, lb, lc = self.lam
         self.PD = lc[:, None, None] + lb[None, :, None] + la[None, None, :]
 

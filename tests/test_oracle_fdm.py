@@ -34,10 +34,37 @@ def test_inverse_action_is_a_direct_solve(case):
     ref = spla.spsolve(M.tocsc(), r)
     F = fdm.FDM(shape, bc, kind, diff, b, sigma)
     z = F.apply(r)
-    # the general eigensolver's bases lose accuracy where eigenvalues repeat (pure central
-    # advection: sin theta = sin(pi - theta)); the bound scales with their conditioning
-    cond = float(np.prod([np.linalg.cond(Q) for Q in F.Q]))
-    assert np.linalg.norm(z - ref) <= 1e-11 * max(1.0, cond) * np.linalg.norm(ref)
+    assert np.linalg.norm(z - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_bases_are_unitary_and_diagonalise_their_factor(case):
+    shape, bc, kind, diff, b, sigma = case
+    F = fdm.FDM(shape, bc, kind, diff, b, sigma)
+    for M, Q, lam in zip(F.factors, F.Q, F.lam):
+        n = M.shape[0]
+        assert np.abs(Q.conj().T @ Q - np.eye(n)).max() <= 1e-13
+        assert np.abs(M @ Q - Q * lam[None, :]).max() <= 1e-13 * max(1.0, np.abs(M).max())
+
+
+def test_pure_central_advection_repeats_eigenvalues_and_still_inverts_exactly():
+    # beta = (1, 1, 1), nu = 0 (the paper's advection test): the 1-D factor's eigenvalues
+    # 1 - i sigma b sin(theta) / h repeat for theta and pi - theta; the inverse is still exact
+    shape, sigma = (8, 8, 8), 3e-2
+    F = fdm.FDM(shape, operators.PERIODIC, 2, 0.0, (1.0, 1.0, 1.0), sigma)
+    lam = np.round(F.lam[0], 12)
+    assert len(set(lam.tolist())) < shape[0]                   # repeated eigenvalues
+    K = operators.operator(shape, operators.PERIODIC, 2, 0.0, (1.0, 1.0, 1.0))
+    Mst = operators.stage_matrix(K, sigma)
+    r = np.random.default_rng(8).standard_normal(Mst.shape[0])
+    ref = spla.spsolve(Mst.tocsc(), r)
+    assert np.linalg.norm(F.apply(r) - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_non_normal_factor_is_rejected():
+    # upwind advection with Dirichlet ends: a non-normal factor without a unitary eigenbasis
+    with pytest.raises(ValueError):
+        fdm.FDM((6, 5, 4), operators.DIRICHLET, 1, 1e-2, (1.0, 0.5, 0.25), 2e-2)
 
 
 def test_contractions_follow_their_index_definitions():
