@@ -16,7 +16,7 @@ M = pytest.importorskip('paper_2412_16638_amd')
 A = M._abi
 
 SHAPES = [(1, 1, 1), (1, 1, 17), (2, 1, 3), (3, 2, 1), (1, 5, 1)]
-TOL = {'fp64': 1e-10, 'fp16': 1e-3}
+TOL = {'fp64': 1e-12, 'fp16': 1e-3}   # FP64: the all-FP64 bar (measured <= 5e-16 here)
 
 
 def _run(shape, bc, kind, diff, b, krylov, storage, fmt, nsteps=3, dt=2e-3):
@@ -37,7 +37,8 @@ def test_dirichlet_heat_on_degenerate_grids(shape, fmt, storage):
     log_case('edge_heat', shape=shape, fmt=fmt, storage=storage)
     u0, u = _run(shape, W.DIRICHLET, W.HEAT, 1.0, (0, 0, 0), 'cg', storage, fmt)
     ref = closed_form.evolve_heat(u0, 1.0, 2e-3, 3, tableaus.by_name('SDIRK3'))
-    assert rel_l2(u, ref) <= TOL[storage]
+    err = rel_l2(u, ref)
+    assert err <= TOL[storage], err
 
 
 @pytest.mark.parametrize("storage", ['fp64', 'fp16'])
@@ -48,7 +49,8 @@ def test_periodic_advection_diffusion_on_degenerate_grids(shape, fmt, storage):
     b = (1.0, 0.5, 0.25)
     u0, u = _run(shape, W.PERIODIC, W.ADVDIFF, 1e-2, b, 'gmres', storage, fmt)
     ref = closed_form.evolve(u0, W.ADVDIFF, W.PERIODIC, 1e-2, b, 2e-3, 3, tableaus.by_name('SDIRK3'))
-    assert rel_l2(u, ref) <= TOL[storage]
+    err = rel_l2(u, ref)
+    assert err <= TOL[storage], err
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (3, 2, 1), (1, 5, 2)])

@@ -74,7 +74,9 @@ def test_fp64_reference_integration_matches_the_oracle(workload, precond):
     err = rel_l2(st.get_u(), _ref(workload, p))
     st.close()
     print(workload, precond, 'fp64 reference rel-L2', err, stats['iters'])
-    assert err <= 1e-10
+    # the stated bar of the all-FP64 path (measured: 1.4e-13 heat with block-Jacobi, at most
+    # 9e-15 in the three other cases)
+    assert err <= 1e-12, (workload, precond, err, stats['iters'])
 
 
 @pytest.mark.parametrize("precond", ['bj', 'fdm'])

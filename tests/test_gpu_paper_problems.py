@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 M = pytest.importorskip('paper_2412_16638_amd')
 A = M._abi
 
-TOL = {'fp64': 1e-10, 'fp32': 1e-6, 'fp16': 1e-3}
+# FP64: the all-FP64 bar (measured at most 1e-13 on these problems)
+TOL = {'fp64': 1e-12, 'fp32': 1e-6, 'fp16': 1e-3}
 
 
 def run(p, fmt=A.FMT_STENCIL, **over):
@@ -90,7 +91,8 @@ def test_stage_solve_ignores_the_forcing_and_removal_restores_the_unforced_step(
     u = st.get_u()
     st.close()
     ref = closed_form.evolve_heat(u0, 1.0, p.dt, 2, tableaus.by_name('SDIRK3'))
-    assert rel_l2(u, ref) <= TOL['fp64']
+    err = rel_l2(u, ref)
+    assert err <= TOL['fp64'], err
 
 
 @pytest.mark.parametrize("prob,tab,tau", [('heat', 'MID1', 1 / 10), ('heat', '4S3PC', 1 / 80),
