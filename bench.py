@@ -46,6 +46,8 @@ def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, uni
         return N * (worked * (s + s) + units * s)
     if kc == 'gm_orth':
         return N * (worked * (s + s + pre) + units * s)
+    if kc == 'gm_reorth':  # w read, w' written, the basis read once (its second read hits cache)
+        return N * (worked * (s + s) + units * s)
     if kc == 'gm_finish':
         if fdm:  # t = sum_i y_i v_i in the arithmetic type; P^-1 t and y += s z come after
             return N * (worked * cb + units * s)

@@ -128,7 +128,10 @@ typedef struct {
  *           the last step whose stages all met it; mprk_step returns MPRK_ENOTCONV.  Without
  *           strict such stages are counted in mprk_stats.missed and stepping continues (as the
  *           paper's experiments keep stepping after a solve that hit its iteration cap).
- *  reorth: GMRES classical Gram-Schmidt with one re-orthogonalisation pass (CGS2).
+ *  reorth: 0 = GMRES orthogonalises each new Arnoldi vector by one classical Gram-Schmidt
+ *           pass (CGS1); 1 = by two (CGS2: the once-orthogonalised vector is stored and
+ *           orthogonalised again, the Hessenberg column is the sum of both passes'
+ *           coefficients; one extra launch per Arnoldi step).  Ignored by CG.
  *  bj_shared: 0 = one stored inverse per block-Jacobi block (default); 1 = store each distinct
  *           diagonal block's inverse once plus a per-block index (a single shared inverse when
  *           all blocks coincide, e.g. constant coefficients with block | nx).  Both modes give
@@ -182,18 +185,28 @@ int32_t mprk_tableau_builtin(int32_t id, int32_t param, mprk_tableau *out);
 /* Fill *out with the library defaults for a storage precision and Krylov method. */
 int32_t mprk_precisions_default(int32_t storage, int32_t krylov, mprk_precisions *out);
 
-/* Validate the problem and create a handle (host memory only).  dt is the time step tau;
- * hip_stream is a hipStream_t (NULL = the null stream).  Errors: MPRK_EINVAL (bad shape,
- * non-lower-triangular tableau, FP16 values that would overflow, CG on a nonsymmetric
- * operator, index range beyond int32 for CSR), MPRK_EUNSUPPORTED, MPRK_EDEVICE. */
+/* Validate the problem and create a handle (host memory; with a device present also the
+ * handle's pinned status records and events).  dt is the time step tau; hip_stream is a
+ * hipStream_t (NULL = the null stream).  FP16 storage needs no range check here: the stencil
+ * coefficients stay in the compute type, CSR values are stored scaled by a power of two into
+ * [-1, 1], right-hand sides are scaled to unit RMS (the rescaling Section "Method stability in
+ * the context of mixed precision" gives as the remedy for FP16's range); a value that still
+ * overflows shows up as a non-finite residual (MPRK_ENONFINITE from mprk_step).  Errors:
+ * MPRK_EINVAL (bad shape, non-lower-triangular tableau, CG on a nonsymmetric operator, index
+ * range beyond int32 for CSR), MPRK_EUNSUPPORTED, MPRK_EDEVICE. */
 int32_t mprk_create(const mprk_grid *grid, const mprk_operator *op, const mprk_tableau *tab,
                     const mprk_precisions *prec, double dt, void *hip_stream, mprk_handle **out);
 
-/* Exact number of bytes of device workspace the handle needs (<0 on error). */
+/* Exact number of bytes of device workspace the handle needs (<0 on error): the FP64 stage
+ * vectors of eq. RKstep (rhs, y and k_i per stage, k^eps_i for split tableaus), the LP Krylov
+ * vectors of the stage solve of eq. corelinear, the preconditioner's data and the reduction
+ * and control records.  Serving admission sizes jobs by it. */
 int64_t mprk_workspace_bytes(const mprk_handle *h);
 
-/* Attach caller-owned device memory and run the setup (CSR assembly, block-Jacobi
- * inverses) on the handle's stream.  u_dev: N doubles, the state, updated in place by
+/* Attach caller-owned device memory and run the setup on the handle's stream: CSR assembly,
+ * block-Jacobi inverses of the stage matrices I - tau a_ii K of eq. corelinear (one set per
+ * distinct a_ii, computed in FP64, stored in the LP type), the fast-diagonalisation bases of
+ * eq. Pinvform.  u_dev: N doubles, the state, updated in place by
  * mprk_step.  workspace_dev: >= mprk_workspace_bytes bytes, 256-byte aligned.  The
  * library keeps both pointers until mprk_destroy or the next bind; it never frees them.
  * Synchronises the stream before returning.  Errors: MPRK_EINVAL, MPRK_ENOMEM (bytes too
@@ -222,15 +235,19 @@ int32_t mprk_bind_static(mprk_handle *h, double *u_dev);
  * unaffected (it applies the operators alone).  Errors: MPRK_EINVAL (null handle). */
 int32_t mprk_set_forcing(mprk_handle *h, const double *g_dev);
 
-/* Advance u by nsteps time steps.  The calling thread steers the Krylov loops by polling
+/* Advance u by nsteps time steps of eq. RKstep: per implicit stage the right-hand side and
+ * the FP64 residual, the LP solve of eq. corelinear, the FP64 update and explicit evaluation
+ * k_i = K y_i, then u_{n+1} = u_n + tau sum b_i k_i (Section "Implementation of the
+ * Mixed-precision Runge--Kutta methods").  The calling thread steers the Krylov loops by polling
  * small device-side status records; all arithmetic runs in the library's kernels on the
- * bound stream.  Returns when the last step's work is enqueued (the step combination may
- * still be running).  If stats_or_null is given the call waits for the stream and fills it.
+ * bound stream.  The call waits for the stream before it returns (it reads the device's step
+ * and convergence counters) and fills stats_or_null if given.
  * Errors: MPRK_ESTATE (not bound), MPRK_ENONFINITE (u left at the last good step),
  * MPRK_ENOTCONV (strict only), MPRK_EDEVICE. */
 int32_t mprk_step(mprk_handle *h, int32_t nsteps, mprk_stats *stats_or_null);
 
-/* Solve one stage system (I - dt a_ii K) x = rhs with the handle's implicit solver
+/* Solve one stage system (I - dt a_ii K) x = rhs of eq. corelinear with the handle's implicit
+ * solver
  * (LP Krylov inside the FP64 outer loop), stage in [0, s) with a_ii != 0.  rhs_dev, x_dev:
  * N doubles each (may not alias u or the workspace).  Waits for completion; fills *info
  * if given.  Errors: MPRK_EINVAL (explicit stage), MPRK_ESTATE, MPRK_ENONFINITE, MPRK_EDEVICE. */
@@ -266,7 +283,7 @@ int32_t mprk_autotune(mprk_handle *h, int32_t *nit_vec, int32_t *nit_row);
 enum { MPRK_KC_STAGE_RHS = 0, MPRK_KC_RESIDUAL, MPRK_KC_CG_BEGIN, MPRK_KC_CG_DIR, MPRK_KC_CG_UPD,
        MPRK_KC_PROMOTE, MPRK_KC_GM_BEGIN, MPRK_KC_GM_PREC, MPRK_KC_GM_MATVEC, MPRK_KC_GM_ORTH,
        MPRK_KC_GM_FINISH, MPRK_KC_KEPS, MPRK_KC_COMBINE, MPRK_KC_APPLY, MPRK_KC_CG_RZ,
-       MPRK_KC_FDM, MPRK_KC_COUNT };
+       MPRK_KC_FDM, MPRK_KC_GM_REORTH, MPRK_KC_COUNT };
 
 /* Per-kernel timing.  enable = 1 waits for the stream, clears the records and starts
  * recording a HIP event immediately before and after every kernel the handle launches (on its

@@ -28,7 +28,7 @@ TAB_SDIRK2, TAB_SDIRK3, TAB_MID, TAB_4S3PA, TAB_4S3PB, TAB_4S3PC = range(6)
 APPLY_K64, APPLY_M_LP, APPLY_BJ_LP, APPLY_M64, APPLY_FDM_LP = range(5)
 KC_NAMES = ('stage_rhs', 'residual', 'cg_begin', 'cg_dir', 'cg_upd', 'promote', 'gm_begin',
             'gm_prec', 'gm_matvec', 'gm_orth', 'gm_finish', 'keps', 'combine', 'apply', 'cg_rz',
-            'fdm')
+            'fdm', 'gm_reorth')
 KC = {n: i for i, n in enumerate(KC_NAMES)}
 
 STATUS_NAMES = {OK: 'MPRK_OK', EINVAL: 'MPRK_EINVAL', ENOMEM: 'MPRK_ENOMEM', EDEVICE: 'MPRK_EDEVICE',

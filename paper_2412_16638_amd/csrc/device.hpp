@@ -69,7 +69,7 @@ constexpr int MAXPASS = 32;  // passes whose iteration counts are recorded
 enum KClass {
   KC_STAGE_RHS = 0, KC_RESIDUAL, KC_CG_BEGIN, KC_CG_DIR, KC_CG_UPD, KC_PROMOTE,
   KC_GM_BEGIN, KC_GM_PREC, KC_GM_MATVEC, KC_GM_ORTH, KC_GM_FINISH, KC_KEPS, KC_COMBINE,
-  KC_APPLY64, KC_CG_RZ, KC_FDM, KC_COUNT
+  KC_APPLY64, KC_CG_RZ, KC_FDM, KC_GM_REORTH, KC_COUNT
 };
 
 // Device control record of one solve context (one per problem).  The first 64 bytes
@@ -101,7 +101,8 @@ struct Ctl {
   double scale;       // LP right-hand side = res / scale (scale = ||res||_2 / sqrt(N))
   double tol;         // inner stopping tolerance in LP units
   double rz, pq, alpha, beta, rr;
-  double hcol[MAXD];                 // current Hessenberg column
+  double hcol[MAXD];                 // current Hessenberg column (latest Gram-Schmidt pass)
+  double hacc[MAXD];                 // its coefficients from the step's earlier pass (CGS2)
   double H[(MAXM + 1) * MAXM];       // Hessenberg matrix, column-major (MAXM+1 rows)
   double cs[MAXM], sn[MAXM];         // Givens rotations
   double g[MAXM + 1];                // rotated right-hand side

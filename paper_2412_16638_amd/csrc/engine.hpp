@@ -98,6 +98,7 @@ struct EngineCtx {
   void *r, *z, *p0, *p1, *q, *x;
   void* V;
   size_t vstride;     // elements between GMRES basis vectors
+  int reorth;         // GMRES: second classical Gram-Schmidt pass (CGS2)
   double* res;        // FP64 residual
   double* y;          // FP64 stage solution
 };
@@ -446,6 +447,13 @@ class EngineT final : public Engine {
       if (prec) gm_matvec_t<4, 0, 1, NDM>(c, cfg, Mc); else gm_matvec_t<4, 0, 0, NDM>(c, cfg, Mc);
     } else {
       if (prec) gm_matvec_t<1, 0, 1, NDM>(c, cfg, Mc); else gm_matvec_t<1, 0, 0, NDM>(c, cfg, Mc);
+    }
+    if (c.reorth) {
+      dispatch_vec(c, [&](auto vec) {
+        constexpr int V = decltype(vec)::value;
+        MPRK_LAUNCH_KC(c, KC_GM_REORTH, (k_gm_reorth<S, C, V, NDM>), c.ln_red, c.ln_red, (S*)c.V,
+                       c.vstride, cfg, c.ctl, c.red);
+      });
     }
     dispatch_vec_bs(c, [&](auto vec, auto bs) {
       gm_orth_t<decltype(vec)::value, decltype(bs)::value, NDM>(c, cfg, dinv);

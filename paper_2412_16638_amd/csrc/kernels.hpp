@@ -661,11 +661,94 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
   for (int i = 0; i < NDM; ++i) acc[i] = (double)dacc[i];
   __shared__ double tot[NDM];
   if (!reduce_to_last<NDM>(acc, nd, red, L, ln.G, tot)) return;
-  if (threadIdx.x < nd) ctl->hcol[threadIdx.x] = ctl->vscale[threadIdx.x] * tot[threadIdx.x] * cfg.invN;
+  if (threadIdx.x < nd) {
+    ctl->hcol[threadIdx.x] = ctl->vscale[threadIdx.x] * tot[threadIdx.x] * cfg.invN;
+    ctl->hacc[threadIdx.x] = 0.0;
+  }
 }
 
-// w -= sum_{i<=j} h_ij v_i (classical Gram-Schmidt, coefficients from k_gm_matvec);
-// h_{j+1,j} = ||w||; Givens update of the Hessenberg column; residual estimate |g_{j+1}|.
+// Re-orthogonalisation pass of classical Gram-Schmidt (CGS2), between k_gm_matvec and
+// k_gm_orth: w' = w - sum_{i<=j} h_ij v_i is formed and stored (in the storage type), then its
+// products d_i = (V_i, w') are taken in the same launch (the basis chunks are read again,
+// normally from cache).  The first pass's h moves to hacc and d becomes the coefficient set
+// that k_gm_orth subtracts; the Hessenberg column is h + d.
+template <typename S, typename C, int VEC, int NDM>
+__global__ __launch_bounds__(TPB) void k_gm_reorth(Launch ln, S* __restrict__ V, size_t vstride,
+                                                   SolveCfg cfg, Ctl* ctl, Red red) {
+  if (ctl->outer_done | ctl->inner_done) return;
+  const int j = ctl->J;
+  const int nd = j + 1;
+  if (gm_bound_exceeded(ctl, nd, NDM)) return;
+  count_work(ctl, KC_GM_REORTH, nd);
+  C cf[NDM];
+#pragma unroll
+  for (int i = 0; i < NDM; ++i) cf[i] = i < nd ? (C)(ctl->hcol[i] * ctl->vscale[i]) : C(0);
+  S* w = V + (size_t)(j + 1) * vstride;
+  const int L = xcd_block(ln.G);
+  constexpr int CH = basis_chunk<S, VEC>() < NDM ? basis_chunk<S, VEC>() : NDM;
+  C dacc[NDM];
+#pragma unroll
+  for (int i = 0; i < NDM; ++i) dacc[i] = C(0);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    const int e = g * VEC;
+    C wv[VEC];
+    loadv<C, S, VEC>(w + e, wv);
+    // w' = w - V h over chunks of CH basis vectors (indices past nd are clamped to a valid
+    // vector; their coefficient is zero)
+#pragma unroll
+    for (int c = 0; c < NDM; c += CH) {
+      if (c < nd) {
+        C vv[CH][VEC];
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          loadv<C, S, VEC>(V + (size_t)min(c + k, nd - 1) * vstride + e, vv[k]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (c + k < NDM) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) wv[v] -= cf[c + k] * vv[k][v];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) wv[v] = rnd<S, C>(wv[v]);
+    storev<S, C, VEC>(w + e, wv);
+    // d = V^T w' (the stored, rounded w')
+#pragma unroll
+    for (int c = 0; c < NDM; c += CH) {
+      if (c < nd) {
+        C vv[CH][VEC];
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          loadv<C, S, VEC>(V + (size_t)min(c + k, nd - 1) * vstride + e, vv[k]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (c + k < NDM) {
+            C s = C(0);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s += vv[k][v] * wv[v];
+            dacc[c + k] += (c + k < nd) ? s : C(0);
+          }
+        }
+      }
+    }
+  }
+  double acc[NDM];
+#pragma unroll
+  for (int i = 0; i < NDM; ++i) acc[i] = (double)dacc[i];
+  __shared__ double tot[NDM];
+  if (!reduce_to_last<NDM>(acc, nd, red, L, ln.G, tot)) return;
+  if (threadIdx.x < nd) {
+    ctl->hacc[threadIdx.x] = ctl->hcol[threadIdx.x];
+    ctl->hcol[threadIdx.x] = ctl->vscale[threadIdx.x] * tot[threadIdx.x] * cfg.invN;
+  }
+}
+
+// w -= sum_{i<=j} h_ij v_i (classical Gram-Schmidt, coefficients from k_gm_matvec, or from
+// k_gm_reorth in the second pass of CGS2); h_{j+1,j} = ||w||; Givens update of the Hessenberg column; residual estimate |g_{j+1}|.
 // With a preconditioner (BS > 0) also zt = BJ(w), the next step's preconditioned direction
 // before normalisation.
 template <typename S, typename C, int VEC, int BS, int NDM>
@@ -745,7 +828,7 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
   if (threadIdx.x == 0) {
     const double hn = sqrt(tot[0] * cfg.invN);
     double* col = ctl->H + j * (MAXM + 1);
-    for (int i = 0; i <= j; ++i) col[i] = ctl->hcol[i];
+    for (int i = 0; i <= j; ++i) col[i] = ctl->hacc[i] + ctl->hcol[i];
     col[j + 1] = hn;
     for (int i = 0; i < j; ++i) {  // previous rotations
       const double a = col[i], b = col[i + 1];

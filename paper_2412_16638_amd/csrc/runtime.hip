@@ -412,7 +412,7 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
   if (p->krylov == MPRK_CG && op->kind != MPRK_OP_HEAT &&
       (op->b[0] != 0.0 || op->b[1] != 0.0 || op->b[2] != 0.0))
     return set_error(MPRK_EINVAL, "CG needs a symmetric operator; use GMRES for advection");
-  if (p->reorth) return set_error(MPRK_EUNSUPPORTED, "CGS2 re-orthogonalisation is not implemented");
+  if (p->reorth != 0 && p->reorth != 1) return set_error(MPRK_EINVAL, "reorth must be 0 or 1");
   return MPRK_OK;
 }
 
@@ -691,6 +691,7 @@ EngineCtx mprk_handle::ctx() const {
   c.x = ws + o_x;
   c.V = ws + o_V;
   c.vstride = vstride;
+  c.reorth = prec.krylov == MPRK_GMRES && prec.reorth;
   c.res = (double*)(ws + o_res);
   c.y = (double*)(ws + o_y);
   return c;
