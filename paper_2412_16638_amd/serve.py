@@ -39,24 +39,41 @@ class JobResult:
 
 
 class GpuBackend:
-    """Runs a job as one handle on its own stream; the footprint comes from the library."""
+    """Runs a job as one handle on its own stream; the footprint comes from the library.
 
-    def __init__(self, device: str = 'cuda:0', steps_per_call: int = 10, keep_u: bool = False,
-                 u0_fn=None):
+    Handles are pooled: a finished job's handle, with its workspace (block-Jacobi inverses
+    included) and its iteration history, waits idle for the next job with the same operator,
+    grid, tableau and precisions, which then only resets the state and the step counters.  Idle
+    handles keep their device memory; the server counts it (idle_bytes) and evicts the least
+    recently used ones when an admission needs the room."""
+
+    def __init__(self, device: str = 'cuda:0', keep_u: bool = False, u0_fn=None,
+                 pool: bool = True, steps_per_call: int = 0):
         import torch
         from . import _abi as A
         from .stepper import Stepper, precisions
         self.torch, self.A, self.Stepper, self.precisions = torch, A, Stepper, precisions
         self.device = torch.device(device)
-        self.steps_per_call = steps_per_call
         self.keep_u = keep_u
         self.u0_fn = u0_fn  # builds a job's initial field when the job starts (if p.u0 is None)
+        self.pool = pool
+        self.steps_per_call = steps_per_call  # 0: all of a job's steps in one library call
+        self._idle = {}        # key -> idle Steppers (most recently used last)
+        self._idle_order = []  # (key, stepper) from least to most recently used
+        self._idle_bytes = 0
+        self._lock = threading.Lock()
+        self.created = 0       # handles made (the rest of the jobs reused a pooled one)
 
     def _args(self, p):
         A = self.A
         kind = A.OP_HEAT if p.kind == 0 else A.OP_ADVDIFF
         prec = self.precisions(p.precision, p.krylov, precond=p.precond)
         return kind, prec
+
+    @staticmethod
+    def _key(p):
+        return (p.kind, p.n, p.bc, p.diff, tuple(p.b), p.tableau, p.dt, p.precision, p.krylov,
+                p.precond)
 
     def footprint(self, p) -> int:
         A = self.A
@@ -74,30 +91,86 @@ class GpuBackend:
         free, _total = self.torch.cuda.mem_get_info(self.device)
         return int(free * fraction)
 
-    def run(self, p):
-        """Advance job p to its last step on a private stream; returns (ok, stats, u)."""
+    # ---------------- handle pool ----------------
+    def idle_bytes(self) -> int:
+        return self._idle_bytes
+
+    def has_idle(self, p) -> bool:
+        with self._lock:
+            return bool(self._idle.get(self._key(p)))
+
+    def evict(self, nbytes: int, keep=None) -> int:
+        """Close least recently used idle handles (not of job `keep`'s kind) until at least
+        nbytes are released; returns the bytes released."""
+        freed = 0
+        kk = self._key(keep) if keep is not None else None
+        with self._lock:
+            i = 0
+            while freed < nbytes and i < len(self._idle_order):
+                key, st = self._idle_order[i]
+                if key == kk:
+                    i += 1
+                    continue
+                self._idle_order.pop(i)
+                self._idle[key].remove(st)
+                fp = st.ws_bytes + 8 * st.N
+                self._idle_bytes -= fp
+                freed += fp
+                st.close()
+        return freed
+
+    def _acquire(self, p):
+        key = self._key(p)
+        with self._lock:
+            lst = self._idle.get(key)
+            if self.pool and lst:
+                st = lst.pop()
+                self._idle_order.remove((key, st))
+                self._idle_bytes -= st.ws_bytes + 8 * st.N
+                return st
         torch = self.torch
         kind, prec = self._args(p)
         stream = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(stream):
             st = self.Stepper(p.n, p.bc, kind, p.diff, p.b, self.A.FMT_STENCIL, p.tableau, prec,
                               p.dt, str(self.device))
-            try:
-                st.set_u(p.u0 if p.u0 is not None else self.u0_fn(p))
-                left = p.nsteps
-                stats = None
-                ok = True
-                while left > 0:
-                    n = min(self.steps_per_call, left)
-                    rc, stats = st.step(n, check=False)
-                    if rc != self.A.OK:
-                        ok = False
-                        break
-                    left -= n
-                u = st.get_u() if self.keep_u else None
-            finally:
-                st.close()
-                del st
+        self.created += 1
+        return st
+
+    def _release(self, p, st, ok: bool):
+        if not (self.pool and ok):
+            st.close()
+            return
+        key = self._key(p)
+        with self._lock:
+            self._idle.setdefault(key, []).append(st)
+            self._idle_order.append((key, st))
+            self._idle_bytes += st.ws_bytes + 8 * st.N
+
+    def close(self):
+        self.evict(1 << 62)
+
+    def run(self, p):
+        """Advance job p to its last step on its handle's stream; returns (ok, stats, u)."""
+        st = self._acquire(p)
+        ok = False
+        try:
+            st.set_u(p.u0 if p.u0 is not None else self.u0_fn(p))
+            st.set_state(0.0, 0)
+            left = p.nsteps
+            stats = None
+            ok = True
+            chunk = self.steps_per_call or left
+            while left > 0:
+                n = min(chunk, left)
+                rc, stats = st.step(n, check=False)
+                if rc != self.A.OK:
+                    ok = False
+                    break
+                left -= n
+            u = st.get_u().copy() if self.keep_u else None
+        finally:
+            self._release(p, st, ok)
         return ok, stats, u
 
 
@@ -133,6 +206,23 @@ class Server:
 
     def _admissible(self, fp: int, used: int, active: int) -> bool:
         return active < self.max_active and used + fp <= self.budget
+
+    def _admit_pooled(self, r, fp: int, used: int, active: int) -> bool:
+        """Admission with the backend's idle handles counted as resident: a job whose kind
+        has an idle handle reuses its memory; otherwise idle handles are evicted (least
+        recently used first) when the job would not fit beside them."""
+        be = self.backend
+        if active >= self.max_active:
+            return False
+        idle_fn = getattr(be, 'idle_bytes', None)
+        if idle_fn is None:
+            return used + fp <= self.budget
+        reuse = be.has_idle(r.problem)
+        idle = idle_fn() - (fp if reuse else 0)
+        over = used + fp + idle - self.budget
+        if over > 0:
+            over -= be.evict(over, keep=r.problem)
+        return over <= 0
 
     # ---------------- virtual-clock simulation (FakeBackend) ----------------
     def simulate(self, requests):
@@ -228,11 +318,13 @@ class Server:
                     while i < len(pending) and pending[i].arrival * time_scale <= now:
                         queue.append(pending[i])
                         i += 1
-                    while queue and self._admissible(fps[queue[0].rid], state['used'], state['active']):
+                    while queue and self._admit_pooled(queue[0], fps[queue[0].rid], state['used'],
+                                                       state['active']):
                         r = queue.pop(0)
                         state['used'] += fps[r.rid]
                         state['active'] += 1
-                        state['peak_used'] = max(state['peak_used'], state['used'])
+                        state['peak_used'] = max(state['peak_used'],
+                                                 state['used'] + getattr(be, 'idle_bytes', lambda: 0)())
                         state['peak_active'] = max(state['peak_active'], state['active'])
                         ex.submit(work, r, now)
                         if log:

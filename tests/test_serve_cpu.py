@@ -100,3 +100,48 @@ def test_a_job_that_raises_releases_its_slot_and_is_reported_failed():
     assert not res[1].ok and 'MemoryError' in res[1].error
     assert all(res[i].ok and res[i].error is None for i in (0, 2, 3, 4))
     assert out['peak_active'] == 1
+
+
+class _PoolBackend(S.FakeBackend):
+    """Fake with the pooled backend's accounting: idle handles hold memory until evicted."""
+
+    def __init__(self, idle, **kw):
+        super().__init__(**kw)
+        self.idle = dict(idle)        # key (n) -> bytes held by an idle handle of that kind
+        self.evicted = []
+
+    def idle_bytes(self):
+        return sum(self.idle.values())
+
+    def has_idle(self, p):
+        return p.n in self.idle
+
+    def evict(self, nbytes, keep=None):
+        freed = 0
+        for k in sorted(self.idle):
+            if freed >= nbytes:
+                break
+            if keep is not None and k == keep.n:
+                continue
+            freed += self.idle.pop(k)
+            self.evicted.append(k)
+        return freed
+
+
+def test_pooled_admission_counts_idle_memory_and_evicts_it_when_needed():
+    # budget 1000 B, footprint = n bytes; idle handles of n = 300 and n = 400 hold 700 B
+    be = _PoolBackend({300: 300, 400: 400}, bytes_per_dof=1, budget=1000)
+    srv = S.Server(be, max_active=4)
+    r_same = _req(0, 0.0, 1, 1)
+    r_same.problem.n = 400                     # reuses the idle n = 400 handle: no eviction
+    assert srv._admit_pooled(r_same, 400, used=0, active=0)
+    assert be.evicted == []
+    r_new = _req(1, 0.0, 1, 1)
+    r_new.problem.n = 500                      # 500 + 700 idle > 1000: evicts n = 300 only
+    assert srv._admit_pooled(r_new, 500, used=0, active=0)
+    assert be.evicted == [300]
+    r_big = _req(2, 0.0, 1, 1)
+    r_big.problem.n = 800                      # 300 used + 800 > 1000 even with no idle memory
+    assert not srv._admit_pooled(r_big, 800, used=300, active=1)
+    assert be.evicted == [300, 400]            # (what could be evicted was)
+    assert not srv._admit_pooled(r_same, 400, used=0, active=4)   # no free slot
