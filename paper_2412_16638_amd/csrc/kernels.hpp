@@ -19,6 +19,7 @@
 #pragma once
 
 #include "device.hpp"
+#include "zmarch.hpp"
 
 namespace mprk {
 
@@ -109,6 +110,42 @@ __device__ __forceinline__ void k64_group(const Geo& geo, const Coef<double>& K,
   }
 }
 
+// The stage's outer decision from the residual kernel's totals (||res||^2, ||rhs||^2,
+// non-finite count): norms, the unit-RMS scale of the next LP right-hand side, convergence,
+// pass limit or the one-solve mode's single pass, the strict halt.  One thread.
+__device__ __forceinline__ void residual_decision(const double* tot, const SolveCfg& cfg, Ctl* ctl) {
+  const double rn = sqrt(tot[0]), bn = sqrt(tot[1]);
+  const double rel = bn > 0.0 ? rn / bn : rn;
+  ctl->res_norm = rn;
+  ctl->rhs_norm = bn;
+  ctl->outer_rel = rel;
+  int done = 0;
+  if (tot[2] != 0.0 || !__builtin_isfinite(rn) || !__builtin_isfinite(bn)) {
+    ctl->nonfinite = 1;
+    ctl->step_nonfinite = 1;
+    done = 1;
+  } else {
+    ctl->converged = rel <= cfg.outer_tol;
+    if (cfg.paper_mode) {
+      // one LP solve and no residual test: the stage counts as converged when that solve
+      // stopped on its own tolerance (not on its iteration cap or a breakdown)
+      done = ctl->passes >= 1;
+      ctl->converged = done && ctl->inner_conv;
+    } else {
+      done = ctl->converged || ctl->passes >= cfg.max_passes || rn == 0.0;
+    }
+    if (done && !ctl->converged) {
+      ctl->missed += 1;
+      if (cfg.strict) {
+        ctl->step_held = 1;
+        ctl->halt = 1;
+      }
+    }
+  }
+  ctl->scale = rn > 0.0 ? rn / cfg.sqrtN : 1.0;
+  ctl->outer_done = done;
+}
+
 // FP64 explicit evaluation and stage residual: k = K y ; res = rhs - y + sigma k ; ||res||^2,
 // ||rhs||^2, non-finite count.
 // The last block decides whether the stage is finished (outer residual loop).
@@ -151,38 +188,65 @@ __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<doubl
   }
   __shared__ double tot[3];
   if (!reduce_to_last<3>(acc, 3, red, L, ln.G, tot)) return;
-  if (threadIdx.x == 0) {
-    const double rn = sqrt(tot[0]), bn = sqrt(tot[1]);
-    const double rel = bn > 0.0 ? rn / bn : rn;
-    ctl->res_norm = rn;
-    ctl->rhs_norm = bn;
-    ctl->outer_rel = rel;
-    int done = 0;
-    if (tot[2] != 0.0 || !__builtin_isfinite(rn) || !__builtin_isfinite(bn)) {
-      ctl->nonfinite = 1;
-      ctl->step_nonfinite = 1;
-      done = 1;
-    } else {
-      ctl->converged = rel <= cfg.outer_tol;
-      if (cfg.paper_mode) {
-        // one LP solve and no residual test: the stage counts as converged when that solve
-        // stopped on its own tolerance (not on its iteration cap or a breakdown)
-        done = ctl->passes >= 1;
-        ctl->converged = done && ctl->inner_conv;
-      } else {
-        done = ctl->converged || ctl->passes >= cfg.max_passes || rn == 0.0;
-      }
-      if (done && !ctl->converged) {
-        ctl->missed += 1;
-        if (cfg.strict) {
-          ctl->step_held = 1;
-          ctl->halt = 1;
-        }
-      }
-    }
-    ctl->scale = rn > 0.0 ? rn / cfg.sqrtN : 1.0;
-    ctl->outer_done = done;
+  if (threadIdx.x == 0) residual_decision(tot, cfg, ctl);
+}
+
+// Per-group work of the z-marching residual: rhs (and the forcing) of the next plane loaded
+// ahead; res = rhs - y + sigma (K y + g), the k and res stores and the norm partials.
+template <int VEC>
+struct ResidualBody {
+  const double* __restrict__ rhs;
+  const double* __restrict__ force;
+  double* __restrict__ kout;
+  double* __restrict__ res;
+  double sigma;
+  double bn[VEC], bc[VEC], fn[VEC], fc[VEC];
+  double acc[3];
+  __device__ __forceinline__ void pre(int e) {
+    loadv<double, double, VEC>(rhs + e, bn);
+    if (force) loadv<double, double, VEC>(force + e, fn);
   }
+  __device__ __forceinline__ void next() {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      bc[v] = bn[v];
+      fc[v] = fn[v];
+    }
+  }
+  __device__ __forceinline__ void fin(int e, const double (&yc)[VEC], const double (&kin)[VEC]) {
+    double ky[VEC], rr[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      ky[v] = force ? kin[v] + fc[v] : kin[v];
+      rr[v] = bc[v] - yc[v] + sigma * ky[v];
+      acc[0] += rr[v] * rr[v];
+      acc[1] += bc[v] * bc[v];
+      acc[2] += (__builtin_isfinite(rr[v]) && __builtin_isfinite(ky[v])) ? 0.0 : 1.0;
+    }
+    storev<double, double, VEC>(kout + e, ky);
+    storev<double, double, VEC>(res + e, rr);
+  }
+};
+
+// k_residual with z-marching tiles (stencil format; same arithmetic per value).
+template <int VEC>
+__global__ __launch_bounds__(TPB) void k_residual_zm(ZLaunch zl, Geo geo, Coef<double> K,
+                                                     const double* __restrict__ y,
+                                                     const double* __restrict__ rhs,
+                                                     double* __restrict__ kout,
+                                                     double* __restrict__ res,
+                                                     const double* __restrict__ force,
+                                                     SolveCfg cfg, Ctl* ctl, Red red) {
+  if (ctl->outer_done) return;
+  count_work(ctl, KC_RESIDUAL);
+  extern __shared__ double zm_lds[];
+  const int L = xcd_block(zl.G);
+  ResidualBody<VEC> body{rhs, force, kout, res, cfg.sigma, {}, {}, {}, {}, {0.0, 0.0, 0.0}};
+  auto src = [&](int e, double (&o)[VEC], bool) { loadv<double, double, VEC>(y + e, o); };
+  zmarch<double, VEC>(geo, K, zl, L, src, body, zm_lds);
+  __shared__ double tot[3];
+  if (!reduce_to_last<3>(body.acc, 3, red, L, zl.G, tot)) return;
+  if (threadIdx.x == 0) residual_decision(tot, cfg, ctl);
 }
 
 // y = K x (mode 0) or y = x - sigma K x (mode 1), FP64, no reduction (verification access).

@@ -499,8 +499,20 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   ln_row_red = make_launch_nit(N, 1);
   ln_lp = make_launch(N / vec_lp);
   ln_lp_red = make_launch_nit(N / vec_lp, 1);
+  // z-marching residual: about four workgroups per CU (planes per tile a power of two in
+  // [ZM_LZ_MIN, 32]); the autotuner may switch to another tile depth or the gather kernel
+  long zm_g_max = 0;
+  if (o.format == MPRK_FMT_STENCIL && zmarch_fits(geo, vec)) {
+    const ZLaunch z1 = make_zlaunch(geo, vec, 1);
+    const long want = (long)z1.nty * geo.nz / 1024;
+    int lz = ZM_LZ_MIN;
+    while (lz < 32 && lz < want) lz *= 2;
+    zm_lz = lz;
+    zl_res = make_zlaunch(geo, vec, zm_lz);
+    zm_g_max = make_zlaunch(geo, vec, ZM_LZ_MIN).G;
+  }
   // partials cover every reducing launch shape the autotuner may pick (nit >= 1)
-  pstride = std::max({ln_vec_red.G, ln_row_red.G, ln_lp_red.G});
+  pstride = std::max({(long)ln_vec_red.G, (long)ln_row_red.G, (long)ln_lp_red.G, zm_g_max});
   pstride2 = (pstride + RGRP - 1) / RGRP;
   bs = p.precond == MPRK_PRECOND_BJ ? p.block : 0;
   nblk = bs ? (N + bs - 1) / bs : 0;
@@ -956,6 +968,9 @@ int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* k
   if (op.format == MPRK_FMT_CSR)
     PLAUNCH(KC_RESIDUAL, (k_residual<1, 1>), dim3(ln_row_red.G), dim3(TPB), 0, stream, ln_row_red, geo, Kc, csr,
                        kval, y, rhs, kout, res, force, cfg, ctl, rd);
+  else if (zm_lz > 0)  // (zm_lz > 0 implies vec == 4)
+    PLAUNCH(KC_RESIDUAL, (k_residual_zm<4>), dim3(zl_res.G), dim3(TPB), zmarch_lds(geo, zl_res, 8), stream,
+            zl_res, geo, Kc, y, rhs, kout, res, force, cfg, ctl, rd);
   else if (vec == 4)
     PLAUNCH(KC_RESIDUAL, (k_residual<4, 0>), dim3(ln_vec_red.G), dim3(TPB), 0, stream, ln_vec_red, geo, Kc, csr,
                        kval, y, rhs, kout, res, force, cfg, ctl, rd);
@@ -1153,6 +1168,11 @@ void mprk_handle::fill_stats(mprk_stats* st) {
   st->total_passes = life_passes;
   st->nonfinite = last_nonfinite;
   st->missed = last_missed;
+}
+
+void mprk_handle::set_residual_tiles(int lz) {
+  zm_lz = lz;
+  if (lz > 0) zl_res = make_zlaunch(geo, vec, lz);
 }
 
 int mprk_handle::rebase_missed() {
@@ -1384,6 +1404,7 @@ struct TuneKey {
 struct TuneVal {
   int nv, nr, nvr, nrr;  // groups per thread: streaming vector/row, reducing vector/row
   int nl, nlr;           // LP kernels: streaming / reducing
+  int zlz;               // FP64 residual: z-marching planes per tile (0 = gather kernel)
 };
 std::map<TuneKey, TuneVal> g_tuned;
 std::mutex g_tune_mu;
@@ -1408,6 +1429,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
       h->ln_row_red = make_launch_nit(ngr, v.nrr);
       h->ln_lp = make_launch_nit(ngl, v.nl);
       h->ln_lp_red = make_launch_nit(ngl, v.nlr);
+      h->set_residual_tiles(v.zlz);
       if (nit_vec) *nit_vec = v.nv;
       if (nit_row) *nit_row = v.nr;
       return MPRK_OK;
@@ -1444,7 +1466,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
   };
   // streaming kernels: LP SpMV + FP64 operator, groups per thread in {1..16}
   TuneVal best{h->ln_vec.nit, h->ln_row.nit, h->ln_vec_red.nit, h->ln_row_red.nit,
-               h->ln_lp.nit, h->ln_lp_red.nit};
+               h->ln_lp.nit, h->ln_lp_red.nit, h->zm_lz};
   float bv = 1e30f;
   for (int nit : {1, 2, 4, 8, 16}) {
     const Launch sv = h->ln_vec, sr = h->ln_row, sl = h->ln_lp;
@@ -1525,6 +1547,36 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
       best.nrr = nrr;
       best.nlr = nlr;
     }
+  }
+  // FP64 residual: gather kernel (at the chosen groups per thread) or z-marching tiles of
+  // 2 .. 32 planes, each timed over four launches on a patterned state
+  if (rc == MPRK_OK && h->op.format == MPRK_FMT_STENCIL && zmarch_fits(h->geo, h->vec) &&
+      !h->cfgs.empty()) {
+    const Launch sv = h->ln_vec_red;
+    h->ln_vec_red = make_launch_nit(ngv, best.nvr);
+    const int keep = h->zm_lz;
+    float bz = 1e30f;
+    for (int lz : {0, 2, 4, 8, 16, 32}) {
+      if (lz > 0 && make_zlaunch(h->geo, h->vec, lz).G > h->pstride) continue;
+      h->set_residual_tiles(lz);
+      CombArgs ca{};
+      ca.nv = 0;
+      const unsigned nb = (unsigned)((h->N + 255) / 256);
+      hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.37, 0.011, y64);
+      hipLaunchKernelGGL((k_stage_rhs<4>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, y64, ca, rhs,
+                         x64, ctl, RESET_STAGE | RESET_CALL);
+      hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.23, 0.017, x64);
+      if (hipGetLastError() != hipSuccess) { rc = MPRK_EDEVICE; break; }
+      float ms;
+      time_it([&]() { return h->launch_residual(si, rhs, x64, y64, nullptr); }, &ms);
+      if (rc) break;
+      if (ms < bz) {
+        bz = ms;
+        best.zlz = lz;
+      }
+    }
+    h->ln_vec_red = sv;
+    h->set_residual_tiles(rc ? keep : best.zlz);
   }
   // leave no open stage behind: the next step's first kernel resets the record anyway
   (void)hipEventDestroy(e0);

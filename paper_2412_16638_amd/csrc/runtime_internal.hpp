@@ -49,6 +49,10 @@ struct mprk_handle {
   // launch shapes
   mprk::Launch ln_vec{}, ln_row{};          // streaming kernels
   mprk::Launch ln_vec_red{}, ln_row_red{};  // kernels with a grid reduction
+  // z-marching tiles of the FP64 residual (stencil format, whole groups per row): planes per
+  // tile, 0 = the gather kernel
+  int zm_lz = 0;
+  mprk::ZLaunch zl_res{};
   mprk::Launch ln_lp{}, ln_lp_red{};        // LP kernels (groups of vec_lp)
   int pstride = 8;   // level-1 partials per reduced value (max blocks of a reducing launch)
   int pstride2 = 1;  // level-2 partials per reduced value
@@ -142,5 +146,6 @@ struct mprk_handle {
   int sync_counters();
   int rebase_missed();
   int check_ws() const;
+  void set_residual_tiles(int lz);
   void fill_stats(mprk_stats* st);
 };
