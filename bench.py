@@ -48,6 +48,11 @@ def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, uni
         return N * (worked * (s + s + pre) + units * s)
     if kc == 'gm_reorth':  # w read, w' written, the basis read once (its second read hits cache)
         return N * (worked * (s + s) + units * s)
+    if kc == 'gm_step':  # folded step: w_{j-1} read, v_j and w_j written, block-Jacobi rows read,
+        # the basis before v_j read once (units = j + 1 vectors in the products, v_j among them)
+        return N * (worked * (3 * s + inv) + (units - worked) * s)
+    if kc == 'gm_close':  # the cycle's last norm: w and the basis read
+        return N * (worked * s + units * s)
     if kc == 'gm_finish':
         if fdm:  # t = sum_i y_i v_i in the arithmetic type; P^-1 t and y += s z come after
             return N * (worked * cb + units * s)
@@ -237,6 +242,8 @@ def main():
     ap.add_argument('--serve-requests', type=int, default=64,
                     help='step mode: requests of the serving side leg (0 = skip it)')
     ap.add_argument('--no-batch', action='store_true', help='step mode: skip the batched side leg')
+    ap.add_argument('--gm-form', default='auto', choices=['auto', 'gather', 'zsplit', 'folded'],
+                    help='GMRES Arnoldi step kernels (mprk_precisions.gm_form)')
     ap.add_argument('--n', type=int, default=128,
                     help='sweep mode: grid points per axis of the paper\'s test problems')
     ap.add_argument('--quick', action='store_true',
@@ -286,6 +293,10 @@ def main():
     mixed_over = dict(MIXED_TOL[args.workload])
     if args.compute == 'fp64':
         mixed_over['compute'] = AB.FP64
+    gmf = {'auto': AB.GMFORM_AUTO, 'gather': AB.GMFORM_GATHER, 'zsplit': AB.GMFORM_ZSPLIT,
+           'folded': AB.GMFORM_FOLDED}[args.gm_form]
+    if gmf != AB.GMFORM_AUTO:
+        mixed_over['gm_form'] = gmf
     N = p.N
     K, Wm = args.steps, args.warmup
     log(f'workload {args.workload}: N={N} ({p.n}^3), {p.tableau}, dt={p.dt}, {p.krylov}, '
@@ -311,7 +322,8 @@ def main():
     # ---- timed mixed run ----
     st = M.from_problem(p, fmt=fmt, bj_shared=bjs, **mixed_over)
     tuned = st.autotune()
-    log(f'autotuned groups per thread (vector, row) = {tuned}')
+    launch = st.launch_info()
+    log(f'autotuned groups per thread (vector, row) = {tuned}; launch shapes {launch}')
     reps = []
     for _ in range(max(1, args.reps)):
         t_rep, stats, _ = time_steps(st, p.u0, K, Wm)
@@ -495,6 +507,7 @@ def main():
         'fp64_tight': fp64_tight,
         'bj_storage': args.bj if args.precond == 'bj' else None,
         'autotuned_groups_per_thread': list(tuned),
+        'launch_shapes': launch,
         'other_bj_storage': other,
         'speedup_vs_fp64_matched': (value / fp64['value']) if fp64 else None,
         'roofline': roofline,

@@ -59,6 +59,7 @@ enum { MPRK_FMT_STENCIL = 0, MPRK_FMT_CSR = 1 };
 enum { MPRK_FP64 = 0, MPRK_FP32 = 1, MPRK_FP16 = 2 };
 enum { MPRK_CG = 0, MPRK_GMRES = 1 };
 enum { MPRK_PRECOND_NONE = 0, MPRK_PRECOND_BJ = 1, MPRK_PRECOND_FDM = 2 };
+enum { MPRK_GMFORM_AUTO = 0, MPRK_GMFORM_GATHER = 1, MPRK_GMFORM_ZSPLIT = 2, MPRK_GMFORM_FOLDED = 3 };
 enum { MPRK_TAB_SDIRK2 = 0, MPRK_TAB_SDIRK3 = 1, MPRK_TAB_MID = 2,
        MPRK_TAB_4S3PA = 3, MPRK_TAB_4S3PB = 4, MPRK_TAB_4S3PC = 5 };
 enum { MPRK_APPLY_K64 = 0,     /* y = K x, FP64 in/out */
@@ -132,6 +133,19 @@ typedef struct {
  *           pass (CGS1); 1 = by two (CGS2: the once-orthogonalised vector is stored and
  *           orthogonalised again, the Hessenberg column is the sum of both passes'
  *           coefficients; one extra launch per Arnoldi step).  Ignored by CG.
+ *  gm_form: kernel form of the GMRES Arnoldi step (same arithmetic, different memory traffic):
+ *           MPRK_GMFORM_GATHER = product and update kernels, each stencil point gathered from
+ *           memory; MPRK_GMFORM_ZSPLIT = the product on z-marching tiles (whole x-rows of a run
+ *           of planes, the plane tile staged in LDS, the z neighbours in registers) and the
+ *           update kernel; MPRK_GMFORM_FOLDED = one launch per step on z-marching tiles that
+ *           forms the orthogonalised vector of the previous step from the stored product and
+ *           applies block-Jacobi and the stencil to it (one read of the basis from memory per
+ *           step instead of two; CGS1 and block-Jacobi or no preconditioner only).
+ *           MPRK_GMFORM_AUTO (0) = the library's choice for the grid (the autotuner may time
+ *           the eligible forms).  The tiled forms need the stencil format and whole groups of
+ *           values per x-row (nx a multiple of 8 for FP16 storage, else of 4, and at most 128
+ *           groups of them per row);
+ *           a form the problem does not allow returns MPRK_EUNSUPPORTED from mprk_create.
  *  bj_shared: 0 = one stored inverse per block-Jacobi block (default); 1 = store each distinct
  *           diagonal block's inverse once plus a per-block index (a single shared inverse when
  *           all blocks coincide, e.g. constant coefficients with block | nx).  Both modes give
@@ -147,6 +161,7 @@ typedef struct {
   int32_t strict;
   int32_t reorth;
   int32_t bj_shared;
+  int32_t gm_form;
 } mprk_precisions;
 
 /* Statistics.  Per-stage entries describe the most recent step. */
@@ -279,11 +294,22 @@ int32_t mprk_stats_sync(mprk_handle *h, mprk_stats *out);
  * stream.  *nit_vec / *nit_row (may be NULL) receive the chosen groups per thread. */
 int32_t mprk_autotune(mprk_handle *h, int32_t *nit_vec, int32_t *nit_row);
 
+/* Launch shapes in use (after mprk_create's defaults or mprk_autotune): groups of values per
+ * thread of the streaming / reducing vector kernels (FP64 and LP) and CSR row kernels; planes
+ * per z-marching tile of the FP64 residual (0 = gather kernel); the GMRES step form (an
+ * MPRK_GMFORM value, 0 for CG) and its planes per tile (0 for the gather form). */
+typedef struct {
+  int32_t nit_vec, nit_row, nit_vec_red, nit_row_red, nit_lp, nit_lp_red;
+  int32_t residual_planes;
+  int32_t gm_form, gm_planes;
+} mprk_launch_info;
+int32_t mprk_launch_info_get(const mprk_handle *h, mprk_launch_info *out);
+
 /* Kernel classes for mprk_profile_read. */
 enum { MPRK_KC_STAGE_RHS = 0, MPRK_KC_RESIDUAL, MPRK_KC_CG_BEGIN, MPRK_KC_CG_DIR, MPRK_KC_CG_UPD,
        MPRK_KC_PROMOTE, MPRK_KC_GM_BEGIN, MPRK_KC_GM_PREC, MPRK_KC_GM_MATVEC, MPRK_KC_GM_ORTH,
        MPRK_KC_GM_FINISH, MPRK_KC_KEPS, MPRK_KC_COMBINE, MPRK_KC_APPLY, MPRK_KC_CG_RZ,
-       MPRK_KC_FDM, MPRK_KC_GM_REORTH, MPRK_KC_COUNT };
+       MPRK_KC_FDM, MPRK_KC_GM_REORTH, MPRK_KC_GM_STEP, MPRK_KC_GM_CLOSE, MPRK_KC_COUNT };
 
 /* Per-kernel timing.  enable = 1 waits for the stream, clears the records and starts
  * recording a HIP event immediately before and after every kernel the handle launches (on its

@@ -24,11 +24,12 @@ FMT_STENCIL, FMT_CSR = 0, 1
 FP64, FP32, FP16 = 0, 1, 2
 CG, GMRES = 0, 1
 PRECOND_NONE, PRECOND_BJ, PRECOND_FDM = 0, 1, 2
+GMFORM_AUTO, GMFORM_GATHER, GMFORM_ZSPLIT, GMFORM_FOLDED = 0, 1, 2, 3
 TAB_SDIRK2, TAB_SDIRK3, TAB_MID, TAB_4S3PA, TAB_4S3PB, TAB_4S3PC = range(6)
 APPLY_K64, APPLY_M_LP, APPLY_BJ_LP, APPLY_M64, APPLY_FDM_LP = range(5)
 KC_NAMES = ('stage_rhs', 'residual', 'cg_begin', 'cg_dir', 'cg_upd', 'promote', 'gm_begin',
             'gm_prec', 'gm_matvec', 'gm_orth', 'gm_finish', 'keps', 'combine', 'apply', 'cg_rz',
-            'fdm', 'gm_reorth')
+            'fdm', 'gm_reorth', 'gm_step', 'gm_close')
 KC = {n: i for i, n in enumerate(KC_NAMES)}
 
 STATUS_NAMES = {OK: 'MPRK_OK', EINVAL: 'MPRK_EINVAL', ENOMEM: 'MPRK_ENOMEM', EDEVICE: 'MPRK_EDEVICE',
@@ -55,7 +56,7 @@ class mprk_precisions(C.Structure):
                 ('restart', C.c_int32), ('precond', C.c_int32), ('block', C.c_int32),
                 ('rtol', C.c_double), ('atol', C.c_double), ('maxit', C.c_int32),
                 ('refine_max', C.c_int32), ('outer_tol', C.c_double), ('strict', C.c_int32),
-                ('reorth', C.c_int32), ('bj_shared', C.c_int32)]
+                ('reorth', C.c_int32), ('bj_shared', C.c_int32), ('gm_form', C.c_int32)]
 
 
 class mprk_stats(C.Structure):
@@ -77,6 +78,15 @@ class mprk_stats(C.Structure):
 class mprk_solve_info(C.Structure):
     _fields_ = [('iters', C.c_int32), ('passes', C.c_int32), ('converged', C.c_int32),
                 ('resid', C.c_double)]
+
+
+class mprk_launch_info(C.Structure):
+    _fields_ = [('nit_vec', C.c_int32), ('nit_row', C.c_int32), ('nit_vec_red', C.c_int32),
+                ('nit_row_red', C.c_int32), ('nit_lp', C.c_int32), ('nit_lp_red', C.c_int32),
+                ('residual_planes', C.c_int32), ('gm_form', C.c_int32), ('gm_planes', C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class mprk_problem(C.Structure):
@@ -116,6 +126,7 @@ _sig = {
     'mprk_stats_sync': (C.c_int32, [_P, C.POINTER(mprk_stats)]),
     'mprk_autotune': (C.c_int32, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     'mprk_profile': (C.c_int32, [_P, C.c_int32]),
+    'mprk_launch_info_get': (C.c_int32, [_P, C.POINTER(mprk_launch_info)]),
     'mprk_profile_read': (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     'mprk_last_error': (C.c_char_p, []),
@@ -235,6 +246,12 @@ def mprk_autotune(h: int):
 
 def mprk_profile(h: int, enable: bool) -> None:
     check(lib.mprk_profile(_P(h), 1 if enable else 0), 'mprk_profile')
+
+
+def mprk_launch_info_get(h: int) -> dict:
+    li = mprk_launch_info()
+    check(lib.mprk_launch_info_get(_P(h), C.byref(li)), 'mprk_launch_info_get')
+    return li.as_dict()
 
 
 def mprk_profile_read(h: int, kclass: int) -> dict:

@@ -27,6 +27,7 @@ constexpr int TPB = 256;             // threads per block of every grid kernel
 constexpr int NWAVE = TPB / 64;
 constexpr int MAXM = 32;             // max GMRES cycle length
 constexpr int MAXD = MAXM + 1;       // max simultaneous dot products
+constexpr int MAXRED = MAXD + 2;     // max values of one grid reduction (dots + two norms)
 constexpr int MAXS = 8;              // max RK stages
 constexpr int BJ_MAX = 8;            // max block-Jacobi block size
 
@@ -69,7 +70,7 @@ constexpr int MAXPASS = 32;  // passes whose iteration counts are recorded
 enum KClass {
   KC_STAGE_RHS = 0, KC_RESIDUAL, KC_CG_BEGIN, KC_CG_DIR, KC_CG_UPD, KC_PROMOTE,
   KC_GM_BEGIN, KC_GM_PREC, KC_GM_MATVEC, KC_GM_ORTH, KC_GM_FINISH, KC_KEPS, KC_COMBINE,
-  KC_APPLY64, KC_CG_RZ, KC_FDM, KC_GM_REORTH, KC_COUNT
+  KC_APPLY64, KC_CG_RZ, KC_FDM, KC_GM_REORTH, KC_GM_STEP, KC_GM_CLOSE, KC_COUNT
 };
 
 // Device control record of one solve context (one per problem).  The first 64 bytes
@@ -108,6 +109,10 @@ struct Ctl {
   double g[MAXM + 1];                // rotated right-hand side
   double ysol[MAXM];                 // least-squares solution of the cycle
   double vscale[MAXM + 1];           // basis vector i = vscale[i] * stored vector i
+  double zc;     // fused GMRES step: the stored product of the pending column is zc times the
+                 // product of the normalised basis vector
+  double znext;  // fused GMRES step: scale of the next step's stencil input (an estimate of the
+                 // inverse norm of the next stored basis vector, which keeps values O(1))
   int pass_iters[MAXPASS];           // Krylov iterations of each pass of the current stage
   long long worked[KC_COUNT];        // launches per kernel class that did work (profiling)
   long long units[KC_COUNT];         // basis vectors touched (GMRES kernels), else launches

@@ -99,6 +99,13 @@ struct EngineCtx {
   void* V;
   size_t vstride;     // elements between GMRES basis vectors
   int reorth;         // GMRES: second classical Gram-Schmidt pass (CGS2)
+  // GMRES Arnoldi step form: 0 gather kernels, 1 product on z-marching tiles + update kernel,
+  // 2 folded onto z-marching tiles (stencil, block-Jacobi or none); the tile launch, its LDS
+  // bytes, the two product buffers of the folded form
+  int gform;
+  ZLaunch zl;
+  size_t zlds;
+  void* zw[2];
   double* res;        // FP64 residual
   double* y;          // FP64 stage solution
 };
@@ -127,7 +134,8 @@ class Engine {
   virtual hipError_t gm_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
                              const BJDesc& dinv, int k) = 0;
   // nsteps: Arnoldi steps enqueued in this cycle (an upper bound on the device's J)
-  virtual hipError_t gm_finish(const EngineCtx& c, const BJDesc& dinv, int nsteps) = 0;
+  virtual hipError_t gm_finish(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv,
+                               int nsteps) = 0;
   // verification access
   virtual hipError_t apply_m(const EngineCtx& c, const Coef<double>& Mc, double sigma,
                              const void* x, void* y) = 0;
@@ -150,6 +158,14 @@ inline Coef<C> cast_coef(const Coef<double>& a) {
   do {                                                                                   \
     if ((c).prof) (c).prof->before(kc);                                                  \
     hipLaunchKernelGGL((kern), dim3((ln).G), dim3(TPB), 0, (c).stream, __VA_ARGS__);      \
+    if ((c).prof) (c).prof->after();                                                     \
+  } while (0)
+
+// the same with `lds` bytes of dynamic shared memory and G workgroups
+#define MPRK_LAUNCH_KC_LDS(c, kc, kern, G, lds, ...)                                    \
+  do {                                                                                   \
+    if ((c).prof) (c).prof->before(kc);                                                  \
+    hipLaunchKernelGGL((kern), dim3(G), dim3(TPB), (lds), (c).stream, __VA_ARGS__);       \
     if ((c).prof) (c).prof->after();                                                     \
   } while (0)
 
@@ -436,10 +452,72 @@ class EngineT final : public Engine {
     MPRK_LAUNCH_KC(c, KC_GM_ORTH, (k_gm_orth<S, C, VEC, BS, NDM>), c.ln_red, c.ln_red, (S*)c.V, c.vstride,
                    (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
   }
+  // folded steps on z-marching tiles (c.vec is 4 or 8 there)
+  template <int VEC>
+  void gm_zfirst_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc) {
+    const Coef<C> M = cast_coef<C>(Mc);
+    const S* zin = c.bs > 0 ? (const S*)c.z : (const S*)c.V;
+    MPRK_LAUNCH_KC_LDS(c, KC_GM_MATVEC, (k_gm_zfirst<S, C, VEC>), c.zl.G, c.zlds, c.zl, c.geo, M, zin,
+                       (const S*)c.V, (S*)c.zw[0], cfg, c.ctl, c.red);
+  }
+  template <int VEC, int BS, int NDM>
+  void gm_zstep_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc, const BJDesc& dinv,
+                  int k) {
+    const Coef<C> M = cast_coef<C>(Mc);
+    MPRK_LAUNCH_KC_LDS(c, KC_GM_STEP, (k_gm_zstep<S, C, VEC, BS, NDM>), c.zl.G, c.zlds, c.zl, c.geo, M,
+                       (S*)c.V, c.vstride, (const S*)c.zw[(k - 1) & 1], (S*)c.zw[k & 1],
+                       bj_typed<S>(dinv), cfg, c.ctl, c.red);
+  }
+  template <int NDM>
+  void gm_zstep_n(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc, const BJDesc& dinv,
+                  int k) {
+    dispatch_vec_bs(c, [&](auto vec, auto bs) {
+      constexpr int V = decltype(vec)::value;
+      if constexpr (V > 1) gm_zstep_t<V, decltype(bs)::value, NDM>(c, cfg, Mc, dinv, k);
+    });
+  }
+  void gm_ziter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc, const BJDesc& dinv,
+                int k) {
+    if (k == 0) {
+      dispatch_vec(c, [&](auto vec) {
+        constexpr int V = decltype(vec)::value;
+        if constexpr (V > 1) gm_zfirst_t<V>(c, cfg, Mc);
+      });
+    } else if (k < 4) {
+      gm_zstep_n<4>(c, cfg, Mc, dinv, k);
+    } else if (k < 8) {
+      gm_zstep_n<8>(c, cfg, Mc, dinv, k);
+    } else if (k < 16) {
+      gm_zstep_n<16>(c, cfg, Mc, dinv, k);
+    } else {
+      gm_zstep_n<MAXD>(c, cfg, Mc, dinv, k);
+    }
+  }
+  template <int NDM>
+  void gm_zclose_n(const EngineCtx& c, const SolveCfg& cfg, int nsteps) {
+    dispatch_vec(c, [&](auto vec) {
+      constexpr int V = decltype(vec)::value;
+      MPRK_LAUNCH_KC(c, KC_GM_CLOSE, (k_gm_zclose<S, C, V, NDM>), c.ln_red, c.ln_red, (const S*)c.V,
+                     c.vstride, (const S*)c.zw[(nsteps - 1) & 1], cfg, c.ctl, c.red);
+    });
+  }
   template <int NDM>
   void gm_iter_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc, const BJDesc& dinv) {
     const bool prec = c.bs > 0 || c.fdm_on;  // the product reads z = P^-1 v_j
-    if (c.fmt == 1) {
+    if (c.gform == 1) {
+      const Coef<C> M = cast_coef<C>(Mc);
+      dispatch_vec(c, [&](auto vec) {
+        constexpr int V = decltype(vec)::value;
+        if constexpr (V > 1) {
+          if (prec)
+            MPRK_LAUNCH_KC_LDS(c, KC_GM_MATVEC, (k_gm_zmatvec<S, C, V, 1, NDM>), c.zl.G, c.zlds, c.zl,
+                               c.geo, M, (const S*)c.z, (S*)c.V, c.vstride, cfg, c.ctl, c.red);
+          else
+            MPRK_LAUNCH_KC_LDS(c, KC_GM_MATVEC, (k_gm_zmatvec<S, C, V, 0, NDM>), c.zl.G, c.zlds, c.zl,
+                               c.geo, M, (const S*)c.z, (S*)c.V, c.vstride, cfg, c.ctl, c.red);
+        }
+      });
+    } else if (c.fmt == 1) {
       if (prec) gm_matvec_t<1, 1, 1, NDM>(c, cfg, Mc); else gm_matvec_t<1, 1, 0, NDM>(c, cfg, Mc);
     } else if (c.vec == 8) {
       if (prec) gm_matvec_t<V8, 0, 1, NDM>(c, cfg, Mc); else gm_matvec_t<V8, 0, 0, NDM>(c, cfg, Mc);
@@ -464,6 +542,10 @@ class EngineT final : public Engine {
     // z = P^-1 v_k, issued at the start of the step that reads it (v_0's comes with the
     // begin), so the last step enqueued in a pass leaves no apply behind it; the launches
     // return once the cycle has ended
+    if (c.gform == 2) {
+      gm_ziter(c, cfg, Mc, dinv, k);
+      return hipGetLastError();
+    }
     if (c.fdm_on && k > 0 && k <= cfg.m)
       fdm_chain<S, S>(c, cfg.sigma, (const S*)c.V + (size_t)k * c.vstride, (S*)c.z, 1);
     // smallest compiled bound on the basis size that covers step k
@@ -499,7 +581,14 @@ class EngineT final : public Engine {
       gm_finish_t<decltype(vec)::value, decltype(bs)::value, NDM>(c, dinv);
     });
   }
-  hipError_t gm_finish(const EngineCtx& c, const BJDesc& dinv, int nsteps) override {
+  hipError_t gm_finish(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv,
+                       int nsteps) override {
+    if (c.gform == 2 && nsteps > 0) {  // the cycle's last column
+      if (nsteps <= 4) gm_zclose_n<4>(c, cfg, nsteps);
+      else if (nsteps <= 8) gm_zclose_n<8>(c, cfg, nsteps);
+      else if (nsteps <= 16) gm_zclose_n<16>(c, cfg, nsteps);
+      else gm_zclose_n<MAXD>(c, cfg, nsteps);
+    }
     if (nsteps <= 4) gm_finish_n<4>(c, dinv);
     else if (nsteps <= 8) gm_finish_n<8>(c, dinv);
     else if (nsteps <= 16) gm_finish_n<16>(c, dinv);

@@ -638,6 +638,45 @@ __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __res
   }
 }
 
+// Completes Hessenberg column j, whose entries 0..j are already in H, with the subdiagonal
+// entry hn = h_{j+1,j}: the earlier Givens rotations and a new one, the rotated right-hand side
+// g, the iteration counters, J = j + 1 and the inner stopping test on the residual estimate
+// |g_{j+1}| (hn = 0 is an exact breakdown: the solve is exact).  One thread.
+__device__ __forceinline__ void gm_complete_column(Ctl* ctl, const SolveCfg& cfg, int j, double hn) {
+  double* col = ctl->H + j * (MAXM + 1);
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {  // previous rotations
+    const double a = col[i], b = col[i + 1];
+    col[i] = ctl->cs[i] * a + ctl->sn[i] * b;
+    col[i + 1] = -ctl->sn[i] * a + ctl->cs[i] * b;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double den = sqrt(a * a + b * b);
+  const double c = den > 0.0 ? a / den : 1.0;
+  const double sn = den > 0.0 ? b / den : 0.0;
+  ctl->cs[j] = c;
+  ctl->sn[j] = sn;
+  col[j] = den;
+  col[j + 1] = 0.0;
+  ctl->g[j + 1] = -sn * ctl->g[j];
+  ctl->g[j] = c * ctl->g[j];
+  const int its = ctl->iters + 1;
+  ctl->iters = its;
+  ctl->total_iters += 1;
+  ctl->life_iters += 1;
+  const int J = j + 1;
+  ctl->J = J;
+  const double resid = fabs(ctl->g[J]);
+  const bool fin = __builtin_isfinite(resid) && __builtin_isfinite(den);
+  const bool conv = fin && (resid <= ctl->tol || hn == 0.0);
+  const bool stop = !fin || conv || J >= cfg.m || its >= cfg.maxit;
+  ctl->inner_conv = conv;
+  if (stop) ctl->inner_done = 1;
+  if (!fin) {  // drop this cycle: the promoted correction is zero
+    for (int i = 0; i <= J; ++i) ctl->g[i] = 0.0;
+  }
+}
+
 // The launch of Arnoldi step j is compiled for a bound NDM >= j + 1 on the number of basis
 // vectors it touches (the host knows j: every step of a cycle is enqueued in order), so that
 // its per-lane dot accumulators and coefficients take NDM registers, not MAXD.  A launch whose
@@ -893,38 +932,367 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
     const double hn = sqrt(tot[0] * cfg.invN);
     double* col = ctl->H + j * (MAXM + 1);
     for (int i = 0; i <= j; ++i) col[i] = ctl->hacc[i] + ctl->hcol[i];
-    col[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {  // previous rotations
-      const double a = col[i], b = col[i + 1];
-      col[i] = ctl->cs[i] * a + ctl->sn[i] * b;
-      col[i + 1] = -ctl->sn[i] * a + ctl->cs[i] * b;
+    gm_complete_column(ctl, cfg, j, hn);
+    ctl->vscale[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+  }
+}
+
+// Per-group work of k_gm_zmatvec: the first chunk of basis vectors of the next plane loaded
+// ahead; w = LP(out) stored as V_{j+1}; its products with V_0 .. V_j.
+template <typename S, typename C, int VEC, int NDM>
+struct GmMatvecBody {
+  static constexpr int CH = basis_chunk<S, VEC>() < NDM ? basis_chunk<S, VEC>() : NDM;
+  const S* __restrict__ V;
+  size_t vstride;
+  int nd;
+  S* __restrict__ wout;
+  Vec<S, VEC> vn[CH], vc[CH];
+  C dacc[NDM];
+  __device__ __forceinline__ void pre(int e) {
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+      vn[k] = *reinterpret_cast<const Vec<S, VEC>*>(V + (size_t)min(k, nd - 1) * vstride + e);
+  }
+  __device__ __forceinline__ void next() {
+#pragma unroll
+    for (int k = 0; k < CH; ++k) vc[k] = vn[k];
+  }
+  __device__ __forceinline__ void fin(int e, const C (&)[VEC], const C (&out)[VEC]) {
+    C w[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) w[v] = rnd<S, C>(out[v]);
+    storev<S, C, VEC>(wout + e, w);
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      C s = C(0);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) s += (C)vc[k].v[v] * w[v];
+      dacc[k] += (k < nd) ? s : C(0);
     }
-    const double a = col[j], b = col[j + 1];
-    const double den = sqrt(a * a + b * b);
-    const double c = den > 0.0 ? a / den : 1.0;
-    const double sn = den > 0.0 ? b / den : 0.0;
-    ctl->cs[j] = c;
-    ctl->sn[j] = sn;
-    col[j] = den;
-    col[j + 1] = 0.0;
-    ctl->g[j + 1] = -sn * ctl->g[j];
-    ctl->g[j] = c * ctl->g[j];
-    const int its = ctl->iters + 1;
-    ctl->iters = its;
-    ctl->total_iters += 1;
-    ctl->life_iters += 1;
-    const int J = j + 1;
-    ctl->J = J;
-    ctl->vscale[J] = hn > 0.0 ? 1.0 / hn : 0.0;
-    const double resid = fabs(ctl->g[J]);
-    const bool fin = __builtin_isfinite(resid) && __builtin_isfinite(den);
-    const bool conv = fin && (resid <= ctl->tol || hn == 0.0);
-    const bool stop = !fin || conv || J >= cfg.m || its >= cfg.maxit;
-    ctl->inner_conv = conv;
-    if (stop) ctl->inner_done = 1;
-    if (!fin) {  // drop this cycle: the promoted correction is zero
-      for (int i = 0; i <= J; ++i) ctl->g[i] = 0.0;
+#pragma unroll
+    for (int c = CH; c < NDM; c += CH) {
+      if (c < nd) {
+        C vv[CH][VEC];
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          loadv<C, S, VEC>(V + (size_t)min(c + k, nd - 1) * vstride + e, vv[k]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (c + k < NDM) {
+            C s = C(0);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s += vv[k][v] * w[v];
+            dacc[c + k] += (c + k < nd) ? s : C(0);
+          }
+        }
+      }
     }
+  }
+};
+
+// k_gm_matvec on z-marching tiles (stencil format): w = M (vscale_j z_j) with z_j = BJ(V_j)
+// (PREC) or V_j, stored as V_{j+1}; d_i = (V_i, w) for i <= j.
+template <typename S, typename C, int VEC, int PREC, int NDM>
+__global__ __launch_bounds__(TPB) void k_gm_zmatvec(ZLaunch zl, Geo geo, Coef<C> M,
+                                                    const S* __restrict__ z, S* __restrict__ V,
+                                                    size_t vstride, SolveCfg cfg, Ctl* ctl,
+                                                    Red red) {
+  if (ctl->outer_done | ctl->inner_done) return;
+  const int j = ctl->J;
+  const int nd = j + 1;
+  if (gm_bound_exceeded(ctl, nd, NDM)) return;
+  count_work(ctl, KC_GM_MATVEC, nd);
+  extern __shared__ double zm_lds_d[];
+  C* lds = reinterpret_cast<C*>(zm_lds_d);
+  const int L = xcd_block(zl.G);
+  const S* zin = PREC ? z : V + (size_t)j * vstride;
+  const C sj = (C)ctl->vscale[j];
+  auto src = [&](int e, C (&o)[VEC], bool) {
+    loadv<C, S, VEC>(zin + e, o);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) o[v] *= sj;
+  };
+  GmMatvecBody<S, C, VEC, NDM> body{V, vstride, nd, V + (size_t)(j + 1) * vstride, {}, {}, {}};
+#pragma unroll
+  for (int i = 0; i < NDM; ++i) body.dacc[i] = C(0);
+  zmarch<C, VEC>(geo, M, zl, L, src, body, lds);
+  double acc[NDM];
+#pragma unroll
+  for (int i = 0; i < NDM; ++i) acc[i] = (double)body.dacc[i];
+  __shared__ double tot[NDM];
+  if (!reduce_to_last<NDM>(acc, nd, red, L, zl.G, tot)) return;
+  if (threadIdx.x < nd) {
+    ctl->hcol[threadIdx.x] = ctl->vscale[threadIdx.x] * tot[threadIdx.x] * cfg.invN;
+    ctl->hacc[threadIdx.x] = 0.0;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// GMRES Arnoldi steps on z-marching tiles (stencil format), the update of step j folded into
+// the product of step j + 1.  The separate form reads the basis twice per step (the products
+// in k_gm_matvec, the update in k_gm_orth) and writes and re-reads the product w; here one
+// launch per step forms v_j = w_{j-1} - sum_i h_{i,j-1} v_i from the stored product and the
+// basis (halo groups recompute it from the same values), stores v_j, applies block-Jacobi and
+// the stencil to it through the tile, stores the new product w_j and takes its products with
+// the basis.  The norm of v_j, the subdiagonal entry of column j - 1, is only known at the end
+// of that launch, so column j - 1's Givens rotation and stopping test run there, and the
+// stencil input is scaled by an estimate of 1 / ||v_j|| (from ||w_{j-1}||^2 - sum h^2) only to
+// keep stored values O(1): the exact factor (zc) is carried into the next column.  After the
+// cycle's last step a streaming launch (k_gm_zclose) forms the last norm and column.
+// Products are alternately stored in W0 and W1 (halo groups of step j read w_{j-1} while
+// owners write w_j).
+// ------------------------------------------------------------------------------------------
+
+// Per-group work of the first product: w_0 = LP(M (vscale_0 zt)) stored; (V_0, w_0), ||w_0||^2.
+template <typename S, typename C, int VEC>
+struct GmFirstBody {
+  const S* __restrict__ v0;
+  S* __restrict__ wout;
+  Vec<S, VEC> vn, vc;
+  C d0, ww;
+  __device__ __forceinline__ void pre(int e) { vn = *reinterpret_cast<const Vec<S, VEC>*>(v0 + e); }
+  __device__ __forceinline__ void next() { vc = vn; }
+  __device__ __forceinline__ void fin(int e, const C (&)[VEC], const C (&out)[VEC]) {
+    C w[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      w[v] = rnd<S, C>(out[v]);
+      d0 += (C)vc.v[v] * w[v];
+      ww += w[v] * w[v];
+    }
+    storev<S, C, VEC>(wout + e, w);
+  }
+};
+
+// First product of a cycle: the stencil input is vscale_0 BJ(V_0) (stored by k_gm_begin in zin)
+// or vscale_0 V_0 without a preconditioner (zin = V_0).
+template <typename S, typename C, int VEC>
+__global__ __launch_bounds__(TPB) void k_gm_zfirst(ZLaunch zl, Geo geo, Coef<C> M,
+                                                   const S* __restrict__ zin,
+                                                   const S* __restrict__ V, S* __restrict__ wout,
+                                                   SolveCfg cfg, Ctl* ctl, Red red) {
+  if (ctl->outer_done | ctl->inner_done) return;
+  count_work(ctl, KC_GM_MATVEC, 1);
+  extern __shared__ double zm_lds_d[];
+  C* lds = reinterpret_cast<C*>(zm_lds_d);
+  const int L = xcd_block(zl.G);
+  const C s0 = (C)ctl->vscale[0];
+  auto src = [&](int e, C (&o)[VEC], bool) {
+    loadv<C, S, VEC>(zin + e, o);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) o[v] *= s0;
+  };
+  GmFirstBody<S, C, VEC> body{V, wout, {}, {}, C(0), C(0)};
+  zmarch<C, VEC>(geo, M, zl, L, src, body, lds);
+  double acc[2] = {(double)body.d0, (double)body.ww};
+  __shared__ double tot[2];
+  if (!reduce_to_last<2>(acc, 2, red, L, zl.G, tot)) return;
+  if (threadIdx.x == 0) {
+    // the stored product is c0 = s0 ||V_0|| times the product of the normalised vector
+    const double c0 = ctl->vscale[0] > 0.0 ? (double)s0 / ctl->vscale[0] : 0.0;
+    const double t = ctl->vscale[0] * tot[0] * cfg.invN;
+    ctl->hcol[0] = c0 > 0.0 ? t / c0 : 0.0;
+    ctl->hacc[0] = 0.0;
+    ctl->zc = c0;
+    const double ww = tot[1] * cfg.invN;
+    const double est = fmax(ww - t * t, 1e-6 * ww);
+    ctl->znext = est > 0.0 ? 1.0 / sqrt(est) : 1.0;
+  }
+}
+
+// Per-group work of a folded step: w_j = LP(M z) stored; (V_i, w_j) for i <= j, ||w_j||^2.
+template <typename S, typename C, int VEC, int NDM>
+struct GmStepBody {
+  const S* __restrict__ V;
+  size_t vstride;
+  int nd;
+  S* __restrict__ wout;
+  C dacc[NDM];
+  C ww;
+  __device__ __forceinline__ void pre(int) {}
+  __device__ __forceinline__ void next() {}
+  __device__ __forceinline__ void fin(int e, const C (&)[VEC], const C (&out)[VEC]) {
+    constexpr int CH = basis_chunk<S, VEC>() < NDM ? basis_chunk<S, VEC>() : NDM;
+    C w[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      w[v] = rnd<S, C>(out[v]);
+      ww += w[v] * w[v];
+    }
+    storev<S, C, VEC>(wout + e, w);
+#pragma unroll
+    for (int c = 0; c < NDM; c += CH) {
+      if (c < nd) {
+        C vv[CH][VEC];
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          loadv<C, S, VEC>(V + (size_t)min(c + k, nd - 1) * vstride + e, vv[k]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (c + k < NDM) {
+            C s = C(0);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s += vv[k][v] * w[v];
+            dacc[c + k] += (c + k < nd) ? s : C(0);
+          }
+        }
+      }
+    }
+  }
+};
+
+// Folded Arnoldi step j (j = J + 1 >= 1): v_j from w_{j-1} (win) and the basis, stored; the
+// stencil of vscale-estimate * BJ(v_j) through the tile into w_j (wout); column j - 1 completed
+// with ||v_j||; column j's entries for the next launch.
+template <typename S, typename C, int VEC, int BS, int NDM>
+__global__ __launch_bounds__(TPB) void k_gm_zstep(ZLaunch zl, Geo geo, Coef<C> M,
+                                                  S* __restrict__ V, size_t vstride,
+                                                  const S* __restrict__ win,
+                                                  S* __restrict__ wout, BJ<S> dinv,
+                                                  SolveCfg cfg, Ctl* ctl, Red red) {
+  if (ctl->outer_done | ctl->inner_done) return;
+  const int j = ctl->J + 1;
+  const int nd = j + 1;
+  if (gm_bound_exceeded(ctl, nd, NDM)) return;
+  count_work(ctl, KC_GM_STEP, nd);
+  extern __shared__ double zm_lds_d[];
+  C* lds = reinterpret_cast<C*>(zm_lds_d);
+  const int L = xcd_block(zl.G);
+  // update coefficients of the stored basis: v_j = w_{j-1} - sum_{i<j} a_i V_i
+  C a[NDM];
+#pragma unroll
+  for (int i = 0; i < NDM; ++i) a[i] = i < j ? (C)(ctl->zc * ctl->hcol[i] * ctl->vscale[i]) : C(0);
+  const C sc = (C)ctl->znext;
+  S* vj = V + (size_t)j * vstride;
+  constexpr int CH = basis_chunk<S, VEC>() < NDM ? basis_chunk<S, VEC>() : NDM;
+  C nv = C(0);
+  auto src = [&](int e, C (&o)[VEC], bool own) {
+    C v[VEC];
+    loadv<C, S, VEC>(win + e, v);
+#pragma unroll
+    for (int c = 0; c < NDM; c += CH) {
+      if (c < j) {
+        C vv[CH][VEC];
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          loadv<C, S, VEC>(V + (size_t)min(c + k, j - 1) * vstride + e, vv[k]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (c + k < NDM) {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) v[q] -= a[c + k] * vv[k][q];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) v[q] = rnd<S, C>(v[q]);
+    if (own) {
+      storev<S, C, VEC>(vj + e, v);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) nv += v[q] * v[q];
+    }
+    if constexpr (BS > 0) {
+      C zv[VEC];
+      bj_apply_lane<C, S, VEC, BS>(dinv, e, true, v, zv);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) o[q] = sc * zv[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) o[q] = sc * v[q];
+    }
+  };
+  GmStepBody<S, C, VEC, NDM> body{V, vstride, nd, wout, {}, C(0)};
+#pragma unroll
+  for (int i = 0; i < NDM; ++i) body.dacc[i] = C(0);
+  // lanes of one block-Jacobi block exchange values when a block spans several groups
+  zmarch<C, VEC, (BS > VEC ? BS / VEC : 1)>(geo, M, zl, L, src, body, lds);
+  double acc[NDM + 2];
+  acc[0] = (double)nv;
+  acc[1] = (double)body.ww;
+#pragma unroll
+  for (int i = 0; i < NDM; ++i) acc[2 + i] = (double)body.dacc[i];
+  __shared__ double tot[NDM + 2];
+  if (!reduce_to_last<NDM + 2>(acc, nd + 2, red, L, zl.G, tot)) return;
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(tot[0] * cfg.invN);  // ||v_j|| (stored, rms)
+    const int jc = j - 1;                         // the column completed here
+    double* col = ctl->H + jc * (MAXM + 1);
+    for (int i = 0; i <= jc; ++i) col[i] = ctl->hcol[i];
+    const double zc = ctl->zc;
+    ctl->vscale[j] = beta > 0.0 ? 1.0 / beta : 0.0;
+    gm_complete_column(ctl, cfg, jc, zc > 0.0 ? beta / zc : 0.0);
+    // column j's entries (used by the next launch unless the solve stops here)
+    const double cj = (double)sc * beta;
+    const double ww = tot[1] * cfg.invN;
+    double est = ww;
+    for (int i = 0; i <= j; ++i) {
+      const double t = ctl->vscale[i] * tot[2 + i] * cfg.invN;
+      ctl->hcol[i] = cj > 0.0 ? t / cj : 0.0;
+      ctl->hacc[i] = 0.0;
+      est -= t * t;
+    }
+    ctl->zc = cj;
+    est = fmax(est, 1e-6 * ww);
+    ctl->znext = est > 0.0 ? 1.0 / sqrt(est) : 1.0;
+  }
+}
+
+// Last column of a cycle of folded steps: ||w_J - sum_{i<=J} h_{iJ} v_i|| (no store), then
+// column J's Givens rotation and stopping test.
+template <typename S, typename C, int VEC, int NDM>
+__global__ __launch_bounds__(TPB) void k_gm_zclose(Launch ln, const S* __restrict__ V,
+                                                   size_t vstride, const S* __restrict__ win,
+                                                   SolveCfg cfg, Ctl* ctl, Red red) {
+  if (ctl->outer_done | ctl->inner_done) return;
+  const int J = ctl->J;
+  const int nd = J + 1;
+  if (gm_bound_exceeded(ctl, nd, NDM)) return;
+  count_work(ctl, KC_GM_CLOSE, nd);
+  C a[NDM];
+#pragma unroll
+  for (int i = 0; i < NDM; ++i) a[i] = i < nd ? (C)(ctl->zc * ctl->hcol[i] * ctl->vscale[i]) : C(0);
+  const int L = xcd_block(ln.G);
+  constexpr int CH = basis_chunk<S, VEC>() < NDM ? basis_chunk<S, VEC>() : NDM;
+  C nv = C(0);
+  for (int it = 0; it < ln.nit; ++it) {
+    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    if (g >= ln.ng) break;
+    const int e = g * VEC;
+    C v[VEC];
+    loadv<C, S, VEC>(win + e, v);
+#pragma unroll
+    for (int c = 0; c < NDM; c += CH) {
+      if (c < nd) {
+        C vv[CH][VEC];
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          loadv<C, S, VEC>(V + (size_t)min(c + k, nd - 1) * vstride + e, vv[k]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (c + k < NDM) {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) v[q] -= a[c + k] * vv[k][q];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      v[q] = rnd<S, C>(v[q]);
+      nv += v[q] * v[q];
+    }
+  }
+  double acc[1] = {(double)nv};
+  __shared__ double tot[1];
+  if (!reduce_to_last<1>(acc, 1, red, L, ln.G, tot)) return;
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(tot[0] * cfg.invN);
+    double* col = ctl->H + J * (MAXM + 1);
+    for (int i = 0; i <= J; ++i) col[i] = ctl->hcol[i];
+    const double zc = ctl->zc;
+    ctl->vscale[J + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
+    gm_complete_column(ctl, cfg, J, zc > 0.0 ? beta / zc : 0.0);
   }
 }
 

@@ -342,6 +342,7 @@ extern "C" int32_t mprk_precisions_default(int32_t storage, int32_t krylov, mprk
   out->atol = 0.0;
   out->strict = 0;
   out->reorth = 0;
+  out->gm_form = MPRK_GMFORM_AUTO;
   if (storage == MPRK_FP64) {
     out->rtol = 1e-12;
     out->outer_tol = 1e-11;
@@ -413,6 +414,8 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
       (op->b[0] != 0.0 || op->b[1] != 0.0 || op->b[2] != 0.0))
     return set_error(MPRK_EINVAL, "CG needs a symmetric operator; use GMRES for advection");
   if (p->reorth != 0 && p->reorth != 1) return set_error(MPRK_EINVAL, "reorth must be 0 or 1");
+  if (p->gm_form < MPRK_GMFORM_AUTO || p->gm_form > MPRK_GMFORM_FOLDED)
+    return set_error(MPRK_EINVAL, "gm_form must be one of the MPRK_GMFORM values");
   return MPRK_OK;
 }
 
@@ -429,6 +432,12 @@ extern "C" int32_t mprk_create(const mprk_grid* grid, const mprk_operator* op,
   if (rc) {
     delete h;
     return rc;
+  }
+  if (prec->gm_form != MPRK_GMFORM_AUTO && prec->krylov == MPRK_GMRES &&
+      !(h->gform_ok & (1 << (prec->gm_form - 1)))) {
+    delete h;
+    return set_error(MPRK_EUNSUPPORTED, "this GMRES step form needs the stencil format, whole groups "
+                                        "per x-row (folded: also CGS1 and block-Jacobi or none)");
   }
   // pinned status records and events are made here when a device is present (a handle made
   // without one, e.g. to validate a problem, makes them at its first mprk_bind), so that
@@ -511,10 +520,26 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
     zl_res = make_zlaunch(geo, vec, zm_lz);
     zm_g_max = make_zlaunch(geo, vec, ZM_LZ_MIN).G;
   }
+  // GMRES Arnoldi step forms on z-marching tiles of the LP vectors
+  bs = p.precond == MPRK_PRECOND_BJ ? p.block : 0;
+  gform_ok = 1;  // the gather kernels always
+  if (p.krylov == MPRK_GMRES && o.format == MPRK_FMT_STENCIL && zmarch_fits(geo, vec_lp)) {
+    const ZLaunch z1 = make_zlaunch(geo, vec_lp, 1);
+    const long want = (long)z1.nty * geo.nz / 1024;
+    int lz = ZM_LZ_MIN;
+    while (lz < 32 && lz < want) lz *= 2;
+    zl_lp = make_zlaunch(geo, vec_lp, lz);
+    zm_g_max = std::max(zm_g_max, (long)make_zlaunch(geo, vec_lp, ZM_LZ_MIN).G);
+    gform_ok |= 2;
+    const bool blocks_ok = bs == 0 || (g.nx % bs == 0 && (bs <= vec_lp || z1.gx % (bs / vec_lp) == 0));
+    if (p.precond != MPRK_PRECOND_FDM && !p.reorth && blocks_ok) gform_ok |= 4;
+  }
+  // the library's choice: the gather kernels (measured fastest for the 256^3 FP16 step); the
+  // autotuner times the tiled forms where they apply
+  gform = p.gm_form == MPRK_GMFORM_AUTO ? 0 : p.gm_form - 1;
   // partials cover every reducing launch shape the autotuner may pick (nit >= 1)
   pstride = std::max({(long)ln_vec_red.G, (long)ln_row_red.G, (long)ln_lp_red.G, zm_g_max});
   pstride2 = (pstride + RGRP - 1) / RGRP;
-  bs = p.precond == MPRK_PRECOND_BJ ? p.block : 0;
   nblk = bs ? (N + bs - 1) / bs : 0;
   // CSR size (assembled at bind)
   nnz = 0;
@@ -556,6 +581,10 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
     o_V = take(vlp * (size_t)(p.restart + 1));
     o_z = (bs || fdm) ? take(vlp) : 0;
     o_r = o_p0 = o_p1 = o_q = o_x = 0;
+    if (gform_ok & 4) {  // folded form: products alternate between W0 and W1 (W1 reuses BJ(V_0)'s)
+      o_w0 = take(vlp);
+      o_w1 = bs ? o_z : take(vlp);
+    }
   }
   vstride = vlp / lp_bytes;
   bjsets.assign(bs ? sigmas.size() : 0, BJSet());
@@ -606,8 +635,8 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   }
   o_ctl = take(sizeof(Ctl));
   o_flag = take(256);
-  o_part = take((size_t)MAXD * pstride * 8);
-  o_part2 = take((size_t)MAXD * pstride2 * 8);
+  o_part = take((size_t)MAXRED * pstride * 8);
+  o_part2 = take((size_t)MAXRED * pstride2 * 8);
   o_tick = take(red_ticks(pstride) * 4);
   ws_bytes = off;
   // per-sigma solve configurations
@@ -704,6 +733,11 @@ EngineCtx mprk_handle::ctx() const {
   c.V = ws + o_V;
   c.vstride = vstride;
   c.reorth = prec.krylov == MPRK_GMRES && prec.reorth;
+  c.gform = gform;
+  c.zl = zl_lp;
+  c.zlds = gform ? zmarch_lds(geo, zl_lp, prec.compute == MPRK_FP64 ? 8 : 4) : 0;
+  c.zw[0] = (gform_ok & 4) ? ws + o_w0 : nullptr;
+  c.zw[1] = (gform_ok & 4) ? ws + o_w1 : nullptr;
   c.res = (double*)(ws + o_res);
   c.y = (double*)(ws + o_y);
   return c;
@@ -1059,7 +1093,7 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
       if (outer) break;
     }
     if (cg) HIPCHK(eng->cg_finish(c));
-    else HIPCHK(eng->gm_finish(c, dinv, enq));
+    else HIPCHK(eng->gm_finish(c, cfg, dinv, enq));
   }
   return stage_record(slot);
 }
@@ -1168,6 +1202,26 @@ void mprk_handle::fill_stats(mprk_stats* st) {
   st->total_passes = life_passes;
   st->nonfinite = last_nonfinite;
   st->missed = last_missed;
+}
+
+void mprk_handle::set_gm_form(int f, int lz) {
+  if (f < 0 || f > 2 || !(gform_ok & (1 << f))) f = 0;  // (a cached choice of another problem)
+  gform = f;
+  if (f > 0) zl_lp = make_zlaunch(geo, vec_lp, lz);
+}
+
+extern "C" int32_t mprk_launch_info_get(const mprk_handle* h, mprk_launch_info* out) {
+  if (!h || !out) return set_error(MPRK_EINVAL, "NULL argument");
+  out->nit_vec = h->ln_vec.nit;
+  out->nit_row = h->ln_row.nit;
+  out->nit_vec_red = h->ln_vec_red.nit;
+  out->nit_row_red = h->ln_row_red.nit;
+  out->nit_lp = h->ln_lp.nit;
+  out->nit_lp_red = h->ln_lp_red.nit;
+  out->residual_planes = h->zm_lz;
+  out->gm_form = h->prec.krylov == MPRK_GMRES ? h->gform + 1 : 0;
+  out->gm_planes = h->prec.krylov == MPRK_GMRES && h->gform > 0 ? h->zl_lp.LZ : 0;
+  return MPRK_OK;
 }
 
 void mprk_handle::set_residual_tiles(int lz) {
@@ -1405,6 +1459,7 @@ struct TuneVal {
   int nv, nr, nvr, nrr;  // groups per thread: streaming vector/row, reducing vector/row
   int nl, nlr;           // LP kernels: streaming / reducing
   int zlz;               // FP64 residual: z-marching planes per tile (0 = gather kernel)
+  int gform, glz;        // GMRES step form and its planes per tile (tiled forms)
 };
 std::map<TuneKey, TuneVal> g_tuned;
 std::mutex g_tune_mu;
@@ -1430,6 +1485,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
       h->ln_lp = make_launch_nit(ngl, v.nl);
       h->ln_lp_red = make_launch_nit(ngl, v.nlr);
       h->set_residual_tiles(v.zlz);
+      if (h->prec.krylov == MPRK_GMRES && h->prec.gm_form == MPRK_GMFORM_AUTO) h->set_gm_form(v.gform, v.glz);
       if (nit_vec) *nit_vec = v.nv;
       if (nit_row) *nit_row = v.nr;
       return MPRK_OK;
@@ -1466,7 +1522,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
   };
   // streaming kernels: LP SpMV + FP64 operator, groups per thread in {1..16}
   TuneVal best{h->ln_vec.nit, h->ln_row.nit, h->ln_vec_red.nit, h->ln_row_red.nit,
-               h->ln_lp.nit, h->ln_lp_red.nit, h->zm_lz};
+               h->ln_lp.nit, h->ln_lp_red.nit, h->zm_lz, h->gform, h->zl_lp.LZ};
   float bv = 1e30f;
   for (int nit : {1, 2, 4, 8, 16}) {
     const Launch sv = h->ln_vec, sr = h->ln_row, sl = h->ln_lp;
@@ -1577,6 +1633,69 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
     }
     h->ln_vec_red = sv;
     h->set_residual_tiles(rc ? keep : best.zlz);
+  }
+  // GMRES step form: the gather kernels, or the product on z-marching tiles (+ update kernel),
+  // or the folded step, at 2 .. 16 planes per tile; each timed over a cycle's begin, ten
+  // Arnoldi steps (or the cycle length) and the cycle's end on a patterned state, with a
+  // stopping rule that cannot end the cycle early (the step's cost grows with the basis)
+  if (rc == MPRK_OK && h->prec.krylov == MPRK_GMRES && h->prec.gm_form == MPRK_GMFORM_AUTO &&
+      (h->gform_ok & 6) && !h->cfgs.empty()) {
+    const int keep_f = h->gform, keep_lz = h->zl_lp.LZ;
+    const Launch sv = h->ln_vec_red, sl = h->ln_lp_red;
+    h->ln_vec_red = make_launch_nit(ngv, best.nvr);
+    h->ln_lp_red = make_launch_nit(ngl, best.nlr);
+    SolveCfg cfg = h->cfgs[si];
+    cfg.rtol = 0.0;
+    cfg.atol = 0.0;
+    cfg.maxit = cfg.m;
+    const int ksteps = std::min(cfg.m, 10);
+    const BJDesc dinv = h->bj_desc(si);
+    float bg = 1e30f;
+    for (int f = 0; f < 3 && rc == MPRK_OK; ++f) {
+      if (!(h->gform_ok & (1 << f))) continue;
+      for (int lz : {2, 4, 8, 16}) {
+        if (f == 0 && lz != 2) continue;  // (the gather form has no tiles)
+        if (f > 0 && make_zlaunch(h->geo, h->vec_lp, lz).G > h->pstride) continue;
+        h->set_gm_form(f, lz);
+        EngineCtx c = h->ctx();
+        c.y = x64;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && rc == MPRK_OK; ++rep) {
+          CombArgs ca{};
+          ca.nv = 0;
+          const unsigned nb = (unsigned)((h->N + 255) / 256);
+          hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.37, 0.011, y64);
+          if (h->vec == 4)
+            hipLaunchKernelGGL((k_stage_rhs<4>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, y64, ca,
+                               rhs, x64, ctl, RESET_STAGE | RESET_CALL);
+          else
+            hipLaunchKernelGGL((k_stage_rhs<1>), dim3(h->ln_vec.G), dim3(TPB), 0, h->stream, h->ln_vec, y64, ca,
+                               rhs, x64, ctl, RESET_STAGE | RESET_CALL);
+          hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.23, 0.017, x64);
+          if (hipGetLastError() != hipSuccess) { rc = MPRK_EDEVICE; break; }
+          rc = h->launch_residual(si, rhs, x64, y64, nullptr);
+          if (rc) break;
+          if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = MPRK_EDEVICE; break; }
+          if (h->eng->gm_begin(c, cfg, dinv) != hipSuccess) { rc = MPRK_EDEVICE; break; }
+          for (int k = 0; k < ksteps && rc == MPRK_OK; ++k)
+            if (h->eng->gm_iter(c, cfg, Mc, dinv, k) != hipSuccess) rc = MPRK_EDEVICE;
+          if (rc == MPRK_OK && h->eng->gm_finish(c, cfg, dinv, ksteps) != hipSuccess) rc = MPRK_EDEVICE;
+          if (rc == MPRK_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = MPRK_EDEVICE;
+          if (rc == MPRK_OK && hipEventSynchronize(e1) != hipSuccess) rc = MPRK_EDEVICE;
+          if (rc == MPRK_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MPRK_EDEVICE;
+        }
+        if (rc) break;
+        if (ms < bg) {
+          bg = ms;
+          best.gform = f;
+          best.glz = lz;
+        }
+      }
+    }
+    h->ln_vec_red = sv;
+    h->ln_lp_red = sl;
+    if (rc) h->set_gm_form(keep_f, keep_lz);
+    else h->set_gm_form(best.gform, best.glz);
   }
   // leave no open stage behind: the next step's first kernel resets the record anyway
   (void)hipEventDestroy(e0);

@@ -53,6 +53,13 @@ struct mprk_handle {
   // tile, 0 = the gather kernel
   int zm_lz = 0;
   mprk::ZLaunch zl_res{};
+  // GMRES Arnoldi step form (0 gather, 1 z-marching product + update, 2 folded on z-marching
+  // tiles), the forms this problem allows (bit f), the tiles of the LP kernels and the product
+  // buffers of the folded form
+  int gform = 0;
+  int gform_ok = 1;
+  mprk::ZLaunch zl_lp{};
+  size_t o_w0 = 0, o_w1 = 0;
   mprk::Launch ln_lp{}, ln_lp_red{};        // LP kernels (groups of vec_lp)
   int pstride = 8;   // level-1 partials per reduced value (max blocks of a reducing launch)
   int pstride2 = 1;  // level-2 partials per reduced value
@@ -147,5 +154,6 @@ struct mprk_handle {
   int rebase_missed();
   int check_ws() const;
   void set_residual_tiles(int lz);
+  void set_gm_form(int f, int lz);
   void fill_stats(mprk_stats* st);
 };

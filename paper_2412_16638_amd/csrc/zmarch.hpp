@@ -4,7 +4,7 @@
 // marches through them.  Each thread owns one group of VEC consecutive x-values of one row: it
 // keeps the stencil input of its group for planes k - 1, k and k + 1 in registers (the z
 // neighbours) while plane k + 2 is in flight, and writes plane k into an LDS tile of R + 2 rows
-// (one halo row below and above, loaded by the first 2 gx threads), double buffered, from which
+// (one halo row below and above, spread over the workgroup's threads), double buffered, from which
 // the x and y neighbours are read.  Every input value enters the CU once per tile (halo rows add
 // 2 / R, served by L2), instead of the seven loads per group of the gather form: the stencil
 // then costs the memory system about what a plain stream of the same arrays does.
@@ -59,13 +59,17 @@ __device__ __forceinline__ int zm_wrap(int p, int n, int per) {
 }
 
 // src(int e, C (&o)[VEC], bool own): stencil input of the group starting at element e (own:
-//   the thread's own group, which src may also store or accumulate; else a halo group).
+//   the thread's own group in one of the tile's planes, which src may also store or
+//   accumulate, each exactly once; else a halo group or a plane beyond the tile).
 // body.pre(int e): issue the loads of the owned group at e (the next plane's) into the body's
 //   second register set; body.next() makes that set the current one.
 // body.fin(int e, const C (&ctr)[VEC], const C (&out)[VEC]): the group's stencil result, with
 //   the current register set.
 // lds: 2 (R + 2) nx values of C (dynamic shared memory).
-template <typename C, int VEC, typename Src, typename Body>
+// The 2 gx halo groups are spread evenly over the workgroup's waves (src may be as costly as
+// an owned group's), LPB consecutive groups on consecutive lanes (src may exchange values
+// within such lane groups by shuffles; gx must then be a multiple of LPB).
+template <typename C, int VEC, int LPB = 1, typename Src, typename Body>
 __device__ __forceinline__ void zmarch(const Geo& g, const Coef<C>& k, const ZLaunch& zl, int L,
                                        const Src& src, Body& body, C* lds) {
   if (L >= zl.nty * zl.ntz) return;
@@ -80,10 +84,14 @@ __device__ __forceinline__ void zmarch(const Geo& g, const Coef<C>& k, const ZLa
   const bool own = r < Rv;
   const int x0 = xg * VEC;
   const int y = y0 + r;
-  // halo slot: thread t < 2 gx loads group t % gx of the row below (t < gx) or above the tile
-  const bool hal = t < 2 * zl.gx;
-  const int hside = t < zl.gx ? 0 : 1;
-  const int hx0 = (t - hside * zl.gx) * VEC;
+  // halo group h (0 .. 2 gx - 1; below the tile, then above) on thread (h / LPB) hs LPB +
+  // h % LPB, hs = TPB / (2 gx)
+  const int hstride = (TPB / (2 * zl.gx)) * LPB;
+  const int hq = t / hstride, hl = t - hq * hstride;
+  const int h = hq * LPB + hl;
+  const bool hal = hl < LPB && h < 2 * zl.gx;
+  const int hside = h < zl.gx ? 0 : 1;
+  const int hx0 = (h - hside * zl.gx) * VEC;
   const int hy = zm_wrap(hside ? y0 + Rv : y0 - 1, g.ny, per);
   const int hrow = hside ? Rv + 1 : 0;
   auto own_at = [&](int pz, C (&o)[VEC]) {
@@ -92,7 +100,7 @@ __device__ __forceinline__ void zmarch(const Geo& g, const Coef<C>& k, const ZLa
 #pragma unroll
       for (int v = 0; v < VEC; ++v) o[v] = C(0);
     } else {
-      src(q * g.plane + y * nx + x0, o, true);
+      src(q * g.plane + y * nx + x0, o, pz >= z0 && pz < z1);
     }
   };
   auto halo_at = [&](int pz, C (&o)[VEC]) {

@@ -112,6 +112,10 @@ class Stepper:
         """Pick the launch shape (groups per thread) by timing candidates; returns (vec, row)."""
         return A.mprk_autotune(self.h)
 
+    def launch_info(self) -> dict:
+        """Launch shapes in use (groups per thread, tile depths, GMRES step form)."""
+        return A.mprk_launch_info_get(self.h)
+
     def state(self):
         return A.mprk_get_state(self.h)
 
