@@ -36,14 +36,18 @@ def log(*a):
 
 
 def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, units: int,
-                      nv_total: int = 0, fdm: bool = False, cb: int = 4) -> float:
+                      nv_total: int = 0, fdm: bool = False, cb: int = 4,
+                      csr_nnz_row: float = 0.0) -> float:
     """Bytes each kernel class must move per its definition (each array touched once; halos
     and reduction partials not counted).  s = LP storage bytes, m = LP matrix bytes, bs = block,
-    cb = bytes of the arithmetic type."""
+    cb = bytes of the arithmetic type; csr_nnz_row > 0: CSR format with that many nonzeros per
+    row (values, int32 column indices and row pointers read once per SpMV)."""
     inv = bs * m  # block-Jacobi inverse row per unknown
     pre = (inv + s) if bs else 0  # fused block-Jacobi: inverse row read + preconditioned write
+    csr_lp = csr_nnz_row * (m + 4) + 4 if csr_nnz_row else 0.0    # LP matrix of one SpMV
+    csr_64 = csr_nnz_row * (8 + 4) + 4 if csr_nnz_row else 0.0    # FP64 matrix of one SpMV
     if kc == 'gm_matvec':
-        return N * (worked * (s + s) + units * s)
+        return N * (worked * (s + s + csr_lp) + units * s)
     if kc == 'gm_orth':
         return N * (worked * (s + s + pre) + units * s)
     if kc == 'gm_reorth':  # w read, w' written, the basis read once (its second read hits cache)
@@ -60,11 +64,11 @@ def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, uni
     if kc == 'gm_begin':
         return N * worked * (8 + s + pre)
     if kc == 'residual':
-        return N * worked * 32
+        return N * worked * (32 + csr_64)
     if kc == 'cg_begin':
         return N * worked * (8 + s + (inv + s if bs else 0))
     if kc == 'cg_dir':
-        return N * worked * 4 * s
+        return N * worked * (4 * s + csr_lp)
     if kc == 'cg_upd':
         return N * worked * ((6 if fdm else 7) * s + inv)
     if kc == 'cg_rz':
@@ -339,6 +343,11 @@ def main():
     bs = st.prec.block if st.prec.precond == AB.PRECOND_BJ else 0
     nv = {'stage_rhs': 3, 'combine': 3}  # SDIRK3: sum over stages of rhs terms; b has 3 terms
     rows = []
+    nnz_row = 0.0
+    if args.fmt == 'csr':  # 7-point rows; a zero-Dirichlet face row has one neighbour fewer
+        n3 = (p.n, p.n, p.n)
+        faces = 0 if p.bc == 1 else 2 * (n3[0] * n3[1] + n3[1] * n3[2] + n3[0] * n3[2])
+        nnz_row = (7.0 * N - faces) / N
     for kc, r in prof.items():
         if r['launches'] == 0:
             continue
@@ -352,7 +361,7 @@ def main():
         if kc == 'promote' and args.precond == 'fdm' and p.krylov == 'gmres':
             sv = cbytes  # the GMRES correction P^-1 (V y) is formed in the arithmetic type
         b = algorithmic_bytes(kc, N, sv, s_bytes, bs, r['worked'], r['units'], nv_total,
-                              fdm=args.precond == 'fdm', cb=cbytes)
+                              fdm=args.precond == 'fdm', cb=cbytes, csr_nnz_row=nnz_row)
         rows.append((kc, r, b))
     total_ms = sum(r['ms'] for _, r, _ in rows)
     dom = max(rows, key=lambda x: x[1]['ms'])
@@ -377,7 +386,7 @@ def main():
     if os.path.exists(tpath):
         with open(tpath) as fh:
             tr = json.load(fh)
-        from paper_2412_16638_amd.profiling import kernel_source_hash
+        from rocprof_summary import kernel_source_hash
         if tr.get("kernel_hash") == kernel_source_hash():
             # counters give bytes per working dispatch; spread over all launches like `achieved`
             traffic = tr['bytes_per_worked_launch'] * r['worked'] / r['launches']

@@ -1,4 +1,5 @@
-"""Summaries of rocprofv3 output for the library's kernels.
+"""Summaries of rocprofv3 output for the library's kernels (measurement tooling beside bench.py;
+not part of the library).
 
 Two inputs are understood:
 - the `*_kernel_stats.csv` of a `rocprofv3 --kernel-trace --stats --output-format csv` run, turned
@@ -10,9 +11,9 @@ Two inputs are understood:
   writes MIB, so factor = MIB * 1024 / counter (both counters are in KiB).
 
 Usage:
-  python -m paper_2412_16638_amd.profiling stats STATS_CSV --command CMD --out FILE \
+  python rocprof_summary.py stats STATS_CSV --command CMD --out FILE \
       [--trace TRACE_CSV --chain fdm_contract:6[:LAST]]
-  python -m paper_2412_16638_amd.profiling traffic FETCH_CSV WRITE_CSV --kernel gm_orth \
+  python rocprof_summary.py traffic FETCH_CSV WRITE_CSV --kernel gm_orth \
       --workload advdiff256 --calib-mib 1024 --command-fetch CMD --command-write CMD --out FILE
 """
 from __future__ import annotations
@@ -23,16 +24,19 @@ import hashlib
 import json
 import os
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sources that define the solver kernels (device helpers and kernel bodies); a
-    traffic figure is valid only for the sources it was taken on."""
+    """Hash of every library source (kernel bodies, device helpers, the engine's and runtime's
+    launch order and shapes); a traffic figure is valid only for the sources it was taken on."""
     h = hashlib.sha256()
-    for f in ('device.hpp', 'kernels.hpp'):
-        with open(os.path.join(ROOT, 'paper_2412_16638_amd', 'csrc', f), 'rb') as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, 'paper_2412_16638_amd', 'csrc')
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith(('.hpp', '.hip')):
+            with open(os.path.join(csrc, f), 'rb') as fh:
+                h.update(f.encode())
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -123,6 +127,33 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, calib_mib: int,
             'bytes_per_worked_launch': fetch_b + write_b}
 
 
+def traffic_table(fetch_csv: str, write_csv: str, calib_mib: int, unknowns: int,
+                  command_fetch: str, command_write: str) -> str:
+    """HBM bytes per working dispatch, and per unknown, of every library kernel in the two
+    counter runs, as a text table."""
+    fr = _counter_rows(fetch_csv, 'FETCH_SIZE')
+    names = sorted({short_name(r['Kernel_Name']) for r in fr
+                    if 'mprk' in r['Kernel_Name'] and short_name(r['Kernel_Name']) != r['Kernel_Name']})
+    ff = _calibration(fr, calib_mib)
+    fw = _calibration(_counter_rows(write_csv, 'WRITE_SIZE'), calib_mib)
+    lines = ['# HBM traffic per working dispatch (rocprofv3 FETCH_SIZE / WRITE_SIZE)', '',
+             f'command (FETCH_SIZE): {command_fetch}', f'command (WRITE_SIZE): {command_write}',
+             f'calibration: plain device copy of {calib_mib} MiB; fetch factor {ff:.4f}, '
+             f'write factor {fw:.4f}', f'kernel sources: {kernel_source_hash()}', '',
+             f'{"kernel":<22}{"dispatches":>11}{"working":>9}{"fetch MB":>11}{"write MB":>11}'
+             f'{"B/unknown":>11}']
+    for k in names:
+        try:
+            t = traffic(fetch_csv, write_csv, k, calib_mib)
+        except ValueError:
+            continue
+        lines.append(f'{k:<22}{t["dispatches"]:>11}{t["working_dispatches"]:>9}'
+                     f'{t["fetch_bytes_per_worked_launch"] / 1e6:>11.2f}'
+                     f'{t["write_bytes_per_worked_launch"] / 1e6:>11.2f}'
+                     f'{t["bytes_per_worked_launch"] / unknowns:>11.2f}')
+    return '\n'.join(lines) + '\n'
+
+
 def chain_summary(trace_csv: str, kernel: str, n: int, last: int = 0) -> str:
     """Runs of exactly n back-to-back dispatches of `kernel` (no other kernel between them, in
     dispatch order): the span from the first start to the last end, per launch.  This is what an
@@ -173,7 +204,20 @@ def main():
     b.add_argument('--command-fetch', required=True)
     b.add_argument('--command-write', required=True)
     b.add_argument('--out', required=True)
+    t = sub.add_parser('traffic-table')
+    t.add_argument('fetch_csv')
+    t.add_argument('write_csv')
+    t.add_argument('--calib-mib', type=int, required=True)
+    t.add_argument('--unknowns', type=int, required=True)
+    t.add_argument('--command-fetch', required=True)
+    t.add_argument('--command-write', required=True)
+    t.add_argument('--out', required=True)
     args = ap.parse_args()
+    if args.what == 'traffic-table':
+        with open(args.out, 'w') as fh:
+            fh.write(traffic_table(args.fetch_csv, args.write_csv, args.calib_mib, args.unknowns,
+                                   args.command_fetch, args.command_write))
+        return
     if args.what == 'stats':
         text = stats_summary(args.csv, args.command)
         if args.chain:

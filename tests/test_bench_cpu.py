@@ -47,3 +47,15 @@ def test_complex_fdm_apply_flops_on_the_half_spectrum(n, H):
 def test_complex_fdm_apply_flops_full_spectrum_below_four_points():
     # nx < 4 keeps all frequencies: 40 n, the full-spectrum count
     assert bench.fdm_apply_flops(_prob(3, 1)) == pytest.approx(40 * 3)
+
+
+def test_csr_spmv_bytes_per_unknown():
+    # a CSR SpMV row with 7 nonzeros: values (m) and int32 columns per nonzero, one row pointer,
+    # the vector in and out: 7 (m + 4) + 4 + 2 s; FP16 storage -> 50 B, FP64 residual 32 + 88
+    N = 1000
+    b = bench.algorithmic_bytes('gm_matvec', N, 2, 2, 8, worked=1, units=0, csr_nnz_row=7.0)
+    assert b / N == pytest.approx(7 * (2 + 4) + 4 + 2 * 2)
+    r = bench.algorithmic_bytes('residual', N, 2, 2, 8, worked=1, units=1, csr_nnz_row=7.0)
+    assert r / N == pytest.approx(32 + 7 * 12 + 4)
+    # the stencil format moves no matrix
+    assert bench.algorithmic_bytes('gm_matvec', N, 2, 2, 8, worked=1, units=0) / N == 4

@@ -4,7 +4,7 @@ import csv
 
 import pytest
 
-from paper_2412_16638_amd import profiling as P
+import rocprof_summary as P
 
 
 def _write(path, header, rows):
@@ -56,3 +56,20 @@ def test_traffic_scales_by_the_calibration_copy(tmp_path):
     assert t['working_dispatches'] == 2  # the near-empty dispatch is counted apart
     assert t['fetch_bytes_per_worked_launch'] == pytest.approx(2000 * 1024 * 2.0)
     assert t['write_bytes_per_worked_launch'] == pytest.approx(400 * 1024)
+
+
+def test_traffic_table_lists_every_library_kernel(tmp_path):
+    ko = 'void mprk::k_gm_orth<__half, float, 4, 8, 4>(mprk::Launch)'
+    kr = 'void mprk::k_residual_zm<4>(mprk::ZLaunch)'
+    cp = '__amd_rocclr_copyBuffer'
+    f = tmp_path / 'f.csv'
+    w = tmp_path / 'w.csv'
+    hdr = ['Kernel_Name', 'Counter_Name', 'Counter_Value']
+    _write(f, hdr, [(cp, 'FETCH_SIZE', 512 * 1024), (ko, 'FETCH_SIZE', 1000), (kr, 'FETCH_SIZE', 250)])
+    _write(w, hdr, [(cp, 'WRITE_SIZE', 1024 * 1024), (ko, 'WRITE_SIZE', 100), (kr, 'WRITE_SIZE', 500)])
+    text = P.traffic_table(str(f), str(w), 1024, unknowns=1024, command_fetch='cf', command_write='cw')
+    rows = {ln.split()[0]: ln.split() for ln in text.splitlines() if ln.startswith(('gm_orth', 'residual_zm'))}
+    assert set(rows) == {'gm_orth', 'residual_zm'}
+    # gm_orth: (1000 * 2 + 100) KiB per dispatch over 1024 unknowns
+    assert float(rows['gm_orth'][-1]) == pytest.approx(2100 * 1024 / 1024, rel=1e-3)
+    assert 'cf' in text and 'cw' in text
