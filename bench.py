@@ -248,6 +248,9 @@ def main():
     ap.add_argument('--no-batch', action='store_true', help='step mode: skip the batched side leg')
     ap.add_argument('--gm-form', default='auto', choices=['auto', 'gather', 'zsplit', 'folded'],
                     help='GMRES Arnoldi step kernels (mprk_precisions.gm_form)')
+    ap.add_argument('--bj-adapt', type=float, default=0.0, metavar='TOL',
+                    help='adaptive-precision block-Jacobi inverses (mprk_precisions.bj_adapt_tol) '
+                         'for the headline run; the default run also times TOL = 0.1 beside it')
     ap.add_argument('--n', type=int, default=128,
                     help='sweep mode: grid points per axis of the paper\'s test problems')
     ap.add_argument('--quick', action='store_true',
@@ -301,6 +304,8 @@ def main():
            'folded': AB.GMFORM_FOLDED}[args.gm_form]
     if gmf != AB.GMFORM_AUTO:
         mixed_over['gm_form'] = gmf
+    if args.bj_adapt > 0:
+        mixed_over['bj_adapt_tol'] = args.bj_adapt
     N = p.N
     K, Wm = args.steps, args.warmup
     log(f'workload {args.workload}: N={N} ({p.n}^3), {p.tableau}, dt={p.dt}, {p.krylov}, '
@@ -481,6 +486,25 @@ def main():
                  'ms_per_step': t2 * 1e3 / K}
         log(f'other block-Jacobi storage ({other["bj"]}): {other["value"]:.4e} DOF-steps/s')
 
+    # ---- adaptive-precision block-Jacobi beside the headline storage ----
+    adaptive = None
+    if not args.no_fp64 and not args.quick and args.precond == 'bj' and args.bj_adapt == 0:
+        tol_a = 0.1
+        sta = M.from_problem(p, fmt=fmt, bj_shared=0, bj_adapt_tol=tol_a,
+                             **{k: v for k, v in mixed_over.items() if k != 'bj_adapt_tol'})
+        sta.autotune()
+        ta, st_a, _ = time_steps(sta, p.u0, K, Wm)
+        chunks = sta.launch_info()['bj_chunks']
+        sta.close()
+        ua, _ = run_integration(M, p, fmt, bj_shared=0, bj_adapt_tol=tol_a, **mixed_over) \
+            if ref is not None else (None, None)
+        ea = float(np.linalg.norm(ua - ref) / np.linalg.norm(ref)) if ua is not None else None
+        adaptive = {'bj_adapt_tol': tol_a, 'value': N * K / ta, 'ms_per_step': ta * 1e3 / K,
+                    'chunks_fp16_fp32_fp64': chunks, 'err_vs_fp64_reference': ea,
+                    'iters_per_stage': st_a['iters']}
+        log(f'adaptive block-Jacobi (tol {tol_a}): {adaptive["value"]:.4e} DOF-steps/s, '
+            f'chunks {chunks}, rel-L2 {ea}')
+
     # ---- side legs of the metric: batched problems and serving latency ----
     batch = None
     if not args.no_batch and not args.quick:
@@ -518,6 +542,7 @@ def main():
         'autotuned_groups_per_thread': list(tuned),
         'launch_shapes': launch,
         'other_bj_storage': other,
+        'adaptive_bj': adaptive,
         'speedup_vs_fp64_matched': (value / fp64['value']) if fp64 else None,
         'roofline': roofline,
         'cpu_baseline': cpu,

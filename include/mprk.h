@@ -146,6 +146,13 @@ typedef struct {
  *           values per x-row (nx a multiple of 8 for FP16 storage, else of 4, and at most 128
  *           groups of them per row);
  *           a form the problem does not allow returns MPRK_EUNSUPPORTED from mprk_create.
+ *  bj_adapt_tol: 0 = block-Jacobi inverses stored in the storage type (default); > 0 =
+ *           adaptive precision (the Ginkgo preconditioner cited in the Introduction): each
+ *           block's inverse may be stored in FP16, FP32 or FP64, the lowest whose unit roundoff u
+ *           satisfies u * cond_1(D_b) <= bj_adapt_tol and whose range holds the inverse's
+ *           entries; blocks are grouped in chunks of 64 lane groups (the rows one wave reads)
+ *           stored in the widest type their blocks need.  The apply computes in the compute
+ *           type.  Needs bj_shared = 0; not in the batched form.
  *  bj_shared: 0 = one stored inverse per block-Jacobi block (default); 1 = store each distinct
  *           diagonal block's inverse once plus a per-block index (a single shared inverse when
  *           all blocks coincide, e.g. constant coefficients with block | nx).  Both modes give
@@ -162,6 +169,7 @@ typedef struct {
   int32_t reorth;
   int32_t bj_shared;
   int32_t gm_form;
+  double bj_adapt_tol;
 } mprk_precisions;
 
 /* Statistics.  Per-stage entries describe the most recent step. */
@@ -297,11 +305,14 @@ int32_t mprk_autotune(mprk_handle *h, int32_t *nit_vec, int32_t *nit_row);
 /* Launch shapes in use (after mprk_create's defaults or mprk_autotune): groups of values per
  * thread of the streaming / reducing vector kernels (FP64 and LP) and CSR row kernels; planes
  * per z-marching tile of the FP64 residual (0 = gather kernel); the GMRES step form (an
- * MPRK_GMFORM value, 0 for CG) and its planes per tile (0 for the gather form). */
+ * MPRK_GMFORM value, 0 for CG) and its planes per tile (0 for the gather form); the storage
+ * types of the adaptive block-Jacobi inverses.  Needs no device. */
 typedef struct {
   int32_t nit_vec, nit_row, nit_vec_red, nit_row_red, nit_lp, nit_lp_red;
   int32_t residual_planes;
   int32_t gm_form, gm_planes;
+  int64_t bj_chunks[3];  /* adaptive-precision block-Jacobi: chunks stored in FP16, FP32, FP64
+                            (summed over the distinct stage shifts; 0 without it) */
 } mprk_launch_info;
 int32_t mprk_launch_info_get(const mprk_handle *h, mprk_launch_info *out);
 

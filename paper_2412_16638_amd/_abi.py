@@ -56,7 +56,8 @@ class mprk_precisions(C.Structure):
                 ('restart', C.c_int32), ('precond', C.c_int32), ('block', C.c_int32),
                 ('rtol', C.c_double), ('atol', C.c_double), ('maxit', C.c_int32),
                 ('refine_max', C.c_int32), ('outer_tol', C.c_double), ('strict', C.c_int32),
-                ('reorth', C.c_int32), ('bj_shared', C.c_int32), ('gm_form', C.c_int32)]
+                ('reorth', C.c_int32), ('bj_shared', C.c_int32), ('gm_form', C.c_int32),
+                ('bj_adapt_tol', C.c_double)]
 
 
 class mprk_stats(C.Structure):
@@ -83,10 +84,13 @@ class mprk_solve_info(C.Structure):
 class mprk_launch_info(C.Structure):
     _fields_ = [('nit_vec', C.c_int32), ('nit_row', C.c_int32), ('nit_vec_red', C.c_int32),
                 ('nit_row_red', C.c_int32), ('nit_lp', C.c_int32), ('nit_lp_red', C.c_int32),
-                ('residual_planes', C.c_int32), ('gm_form', C.c_int32), ('gm_planes', C.c_int32)]
+                ('residual_planes', C.c_int32), ('gm_form', C.c_int32), ('gm_planes', C.c_int32),
+                ('bj_chunks', C.c_int64 * 3)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d['bj_chunks'] = list(self.bj_chunks)
+        return d
 
 
 class mprk_problem(C.Structure):

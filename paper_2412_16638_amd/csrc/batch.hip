@@ -518,6 +518,8 @@ extern "C" int32_t mprk_batch_create(int32_t count, const mprk_problem* problems
   if (prec->storage != MPRK_FP64 && prec->compute != MPRK_FP32)
     return set_error(MPRK_EUNSUPPORTED, "LP storage needs FP32 compute");
   if (prec->reorth) return set_error(MPRK_EUNSUPPORTED, "reorth is a GMRES option");
+  if (prec->bj_adapt_tol > 0.0)
+    return set_error(MPRK_EUNSUPPORTED, "batched form keeps block-Jacobi inverses in the storage type");
   if (prec->precond == MPRK_PRECOND_FDM)
     return set_error(MPRK_EUNSUPPORTED, "batched form implements block-Jacobi or no preconditioner");
   // one distinct nonzero diagonal, no eps off-diagonals needing k^eps, all stages implicit

@@ -473,10 +473,16 @@ __host__ __device__ inline size_t bj_chunks(long nrows, int vec) {
   const long groups = (nrows + vec - 1) / vec;
   return (size_t)((groups + 63) / 64) * 64 * vec;
 }
+// Mode 4 (adaptive precision): the rows of each chunk of 64 lane groups (the interleave unit
+// of mode 3) are stored in one type chosen per chunk, tag[c] = 0 FP16, 1 FP32, 2 FP64, from
+// byte offset aoff[c] of the inverse area; within a chunk, row r = VEC g + q of the lane group g
+// is at entry (q * 64 + g % 64) * BS of the chunk's type.
 struct BJDesc {
   const void* inv;
   const int* idx;
   int mode;
+  const int* tag;
+  const long long* aoff;
 };
 
 template <typename S>
@@ -484,11 +490,31 @@ struct BJ {
   const S* __restrict__ inv;
   const int* __restrict__ idx;
   int mode;
+  const int* __restrict__ tag;
+  const long long* __restrict__ aoff;
 };
 
 template <typename S>
 __host__ __device__ inline BJ<S> bj_typed(const BJDesc& d) {
-  return BJ<S>{(const S*)d.inv, d.idx, d.mode};
+  return BJ<S>{(const S*)d.inv, d.idx, d.mode, d.tag, d.aoff};
+}
+
+// One row of an adaptive-precision inverse, converted to the compute type.
+template <typename C, int BS>
+__device__ __forceinline__ void bj_row_adaptive(const void* base, int tag, size_t ent, C (&w)[BS]) {
+  if (tag == 0) {
+    const Vec<half_t, BS> t = *reinterpret_cast<const Vec<half_t, BS>*>((const half_t*)base + ent);
+#pragma unroll
+    for (int k = 0; k < BS; ++k) w[k] = (C)t.v[k];
+  } else if (tag == 1) {
+    const Vec<float, BS> t = *reinterpret_cast<const Vec<float, BS>*>((const float*)base + ent);
+#pragma unroll
+    for (int k = 0; k < BS; ++k) w[k] = (C)t.v[k];
+  } else {
+    const Vec<double, BS> t = *reinterpret_cast<const Vec<double, BS>*>((const double*)base + ent);
+#pragma unroll
+    for (int k = 0; k < BS; ++k) w[k] = (C)t.v[k];
+  }
 }
 
 // Offsets (in entries) of the stored inverse rows of this lane's VEC rows e .. e+VEC-1; an
@@ -547,17 +573,56 @@ __device__ __forceinline__ void bj_gather(const C (&r)[VEC], C (&rb)[BS > VEC ? 
 template <typename S, int VEC, int BS>
 struct BJRows {
   Vec<S, BS> row[VEC];
+  bool late;  // mode 4, chunk stored in another type than S: rows are loaded where applied
 };
 
-template <typename S, int VEC, int BS>
+// Type tag of the storage type S in the adaptive layout (0 FP16, 1 FP32, 2 FP64).
+template <typename S>
+__host__ __device__ constexpr int bj_type_tag() {
+  return sizeof(S) == 2 ? 0 : sizeof(S) == 4 ? 1 : 2;
+}
+
+// AD = 1: the adaptive-precision layout (mode 4) is possible; kernels are instantiated apart for
+// it, so that its conversions cost the other layouts no registers.
+template <typename S, int VEC, int BS, int AD = 0>
 __device__ __forceinline__ void bj_load(const BJ<S>& dinv, int e, bool valid, BJRows<S, VEC, BS>& R) {
+  R.late = false;
+  if (AD && dinv.mode == 4) {
+    // adaptive precision: a chunk stored in the storage type is loaded here like mode 3; others
+    // where the rows are applied (converted from their own type)
+    const int g = valid ? e / VEC : 0;
+    const int ch = g >> 6;
+    if (dinv.tag[ch] != bj_type_tag<S>()) {
+      R.late = true;
+      return;
+    }
+    const S* base = (const S*)((const char*)dinv.inv + dinv.aoff[ch]);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+      R.row[i] = *reinterpret_cast<const Vec<S, BS>*>(base + ((size_t)i * 64 + (g & 63)) * BS);
+    return;
+  }
   size_t off[VEC];
   bj_offsets<S, VEC, BS>(dinv, e, valid, off);
 #pragma unroll
   for (int i = 0; i < VEC; ++i) R.row[i] = *reinterpret_cast<const Vec<S, BS>*>(dinv.inv + off[i]);
 }
 
-// z = D^{-1} r with rows loaded by bj_load (every lane of the wave must call this).
+// z = D^{-1} r with rows loaded by bj_load, or (mode 4) loaded here (every lane of the wave
+// must call this).
+template <typename C, typename S, int VEC, int BS>
+__device__ __forceinline__ void bj_mul(const BJRows<S, VEC, BS>& R, bool valid, const C (&r)[VEC],
+                                       C (&z)[VEC]);
+template <typename C, typename S, int VEC, int BS, int AD = 0>
+__device__ __forceinline__ void bj_apply_lane(const BJ<S>& dinv, int e, bool valid,
+                                              const C (&r)[VEC], C (&z)[VEC]);
+template <typename C, typename S, int VEC, int BS, int AD = 0>
+__device__ __forceinline__ void bj_mul(const BJ<S>& dinv, int e, const BJRows<S, VEC, BS>& R,
+                                       bool valid, const C (&r)[VEC], C (&z)[VEC]) {
+  if (AD && dinv.mode == 4 && R.late) bj_apply_lane<C, S, VEC, BS, AD>(dinv, e, valid, r, z);
+  else bj_mul<C, S, VEC, BS>(R, valid, r, z);
+}
+
 template <typename C, typename S, int VEC, int BS>
 __device__ __forceinline__ void bj_mul(const BJRows<S, VEC, BS>& R, bool valid, const C (&r)[VEC],
                                        C (&z)[VEC]) {
@@ -573,14 +638,36 @@ __device__ __forceinline__ void bj_mul(const BJRows<S, VEC, BS>& R, bool valid, 
 // Block-Jacobi: z = D^{-1} r for the VEC rows of this lane (rows e .. e+VEC-1).  Blocks of BS
 // rows; when BS > VEC a block spans BS/VEC consecutive lanes whose values are exchanged by
 // shuffles (every lane of the wave must call this).  Inverse rows are loaded without branches,
-// RCH rows in flight at a time.
-template <typename C, typename S, int VEC, int BS>
+// RCH rows in flight at a time.  Mode 4 reads each row in its chunk's type.
+template <typename C, typename S, int VEC, int BS, int AD>
 __device__ __forceinline__ void bj_apply_lane(const BJ<S>& dinv, int e, bool valid,
                                               const C (&r)[VEC], C (&z)[VEC]) {
-  size_t off[VEC];
-  bj_offsets<S, VEC, BS>(dinv, e, valid, off);
   C rb[BS > VEC ? BS : 1];
   bj_gather<C, VEC, BS>(r, rb);
+  if (AD && dinv.mode == 4) {
+    const int g = valid ? e / VEC : 0;  // an invalid lane reads chunk 0 and discards the result
+    const int ch = g >> 6;
+    const int tag = dinv.tag[ch];
+    const void* base = (const char*)dinv.inv + dinv.aoff[ch];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      C w[BS];
+      bj_row_adaptive<C, BS>(base, tag, ((size_t)q * 64 + (g & 63)) * BS, w);
+      C acc = C(0);
+      if constexpr (BS > VEC) {
+#pragma unroll
+        for (int k = 0; k < BS; ++k) acc += w[k] * rb[k];
+      } else {
+        const int sb = q / BS;
+#pragma unroll
+        for (int k = 0; k < BS; ++k) acc += w[k] * r[sb * BS + k];
+      }
+      z[q] = valid ? acc : C(0);
+    }
+    return;
+  }
+  size_t off[VEC];
+  bj_offsets<S, VEC, BS>(dinv, e, valid, off);
   constexpr int RCH = VEC < 4 ? VEC : 4;
 #pragma unroll
   for (int i0 = 0; i0 < VEC; i0 += RCH) {

@@ -115,11 +115,14 @@ class Engine {
   virtual ~Engine() {}
   // setup
   // invert nslot diagonal blocks (block reps[i] into slot i; reps == nullptr: every block)
-  // lay: row layout of a per-block table (0 row-major, else interleaved for lanes of lay rows)
+  // lay: row layout of a per-block table (0 row-major, else interleaved for lanes of lay rows);
+  // atag/aoff (non-null): the adaptive-precision layout with per-chunk types and offsets
   virtual hipError_t bj_setup_stencil(const EngineCtx& c, const Coef<double>& Mc, void* dinv,
-                                      int* fail, int nslot, const int* reps, int lay) = 0;
+                                      int* fail, int nslot, const int* reps, int lay,
+                                      const int* atag = nullptr, const long long* aoff = nullptr) = 0;
   virtual hipError_t bj_setup_csr(const EngineCtx& c, const double* kval, double sigma, void* dinv,
-                                  int* fail, int nslot, const int* reps, int lay) = 0;
+                                  int* fail, int nslot, const int* reps, int lay,
+                                  const int* atag = nullptr, const long long* aoff = nullptr) = 0;
   virtual hipError_t csr_values(const EngineCtx& c, long nnz, const double* kval, void* out) = 0;
   // CG
   virtual hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) = 0;
@@ -173,20 +176,33 @@ template <typename S, typename C>
 class EngineT final : public Engine {
   // 16-byte groups for 2-byte storage; wider types never use an 8-wide group
   static constexpr int V8 = sizeof(S) == 2 ? 8 : 4;
+  // the block-Jacobi kernels' instantiation for the adaptive-precision layout (mode 4)
+  template <int BS, typename F>
+  static void with_ad(const BJDesc& d, F&& f) {
+    if constexpr (BS > 0) {
+      if (d.mode == 4) {
+        f(IC<1>{});
+        return;
+      }
+    }
+    f(IC<0>{});
+  }
 
  public:
   int elem_bytes() const override { return (int)sizeof(S); }
 
   hipError_t bj_setup_stencil(const EngineCtx& c, const Coef<double>& Mc, void* dinv, int* fail,
-                              int nslot, const int* reps, int lay) override {
+                              int nslot, const int* reps, int lay, const int* atag,
+                              const long long* aoff) override {
     hipLaunchKernelGGL(k_bj_setup_stencil<S>, dim3((nslot + 127) / 128), dim3(128), 0, c.stream,
-                       nslot, c.bs, c.geo, Mc, (S*)dinv, fail, reps, lay);
+                       nslot, c.bs, c.geo, Mc, (S*)dinv, fail, reps, lay, atag, aoff);
     return hipGetLastError();
   }
   hipError_t bj_setup_csr(const EngineCtx& c, const double* kval, double sigma, void* dinv, int* fail,
-                          int nslot, const int* reps, int lay) override {
+                          int nslot, const int* reps, int lay, const int* atag,
+                          const long long* aoff) override {
     hipLaunchKernelGGL(k_bj_setup_csr<S>, dim3((nslot + 127) / 128), dim3(128), 0, c.stream, nslot,
-                       c.bs, c.geo.N, c.csr, kval, sigma, (S*)dinv, fail, reps, lay);
+                       c.bs, c.geo.N, c.csr, kval, sigma, (S*)dinv, fail, reps, lay, atag, aoff);
     return hipGetLastError();
   }
   hipError_t csr_values(const EngineCtx& c, long nnz, const double* kval, void* out) override {
@@ -200,8 +216,11 @@ class EngineT final : public Engine {
   template <int VEC, int BS>
   void cg_begin_t(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) {
     S* z = BS > 0 ? (S*)c.z : (S*)c.r;
-    MPRK_LAUNCH_KC(c, KC_CG_BEGIN, (k_cg_begin<S, C, VEC, BS>), c.ln_red, c.ln_red, c.res, (S*)c.r, z,
-                bj_typed<S>(dinv), cfg, c.ctl, c.red);
+    with_ad<BS>(dinv, [&](auto ad) {
+      constexpr int AD = decltype(ad)::value;
+      MPRK_LAUNCH_KC(c, KC_CG_BEGIN, (k_cg_begin<S, C, VEC, BS, AD>), c.ln_red, c.ln_red, c.res, (S*)c.r, z,
+                    bj_typed<S>(dinv), cfg, c.ctl, c.red);
+    });
   }
   hipError_t cg_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) override {
     if (c.fdm_on) {
@@ -237,8 +256,11 @@ class EngineT final : public Engine {
   template <int VEC, int BS>
   void cg_upd_t(const EngineCtx& c, const SolveCfg& cfg, const S* p, const BJDesc& dinv) {
     S* z = BS > 0 ? (S*)c.z : (S*)c.r;
-    MPRK_LAUNCH_KC(c, KC_CG_UPD, (k_cg_upd<S, C, VEC, BS>), c.ln_red, c.ln_red, (S*)c.x, p, (S*)c.r,
-                (const S*)c.q, z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
+    with_ad<BS>(dinv, [&](auto ad) {
+      constexpr int AD = decltype(ad)::value;
+      MPRK_LAUNCH_KC(c, KC_CG_UPD, (k_cg_upd<S, C, VEC, BS, AD>), c.ln_red, c.ln_red, (S*)c.x, p, (S*)c.r,
+                    (const S*)c.q, z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
+    });
   }
   hipError_t cg_iter(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc,
                      const BJDesc& dinv, int it) override {
@@ -432,8 +454,11 @@ class EngineT final : public Engine {
   // ---------------- GMRES ----------------
   template <int VEC, int BS>
   void gm_begin_t(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) {
-    MPRK_LAUNCH_KC(c, KC_GM_BEGIN, (k_gm_begin<S, C, VEC, BS>), c.ln_red, c.ln_red, c.res, (S*)c.V,
-                   (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
+    with_ad<BS>(dinv, [&](auto ad) {
+      constexpr int AD = decltype(ad)::value;
+      MPRK_LAUNCH_KC(c, KC_GM_BEGIN, (k_gm_begin<S, C, VEC, BS, AD>), c.ln_red, c.ln_red, c.res, (S*)c.V,
+                       (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
+    });
   }
   hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) override {
     dispatch_vec_bs(c, [&](auto vec, auto bs) { gm_begin_t<decltype(vec)::value, decltype(bs)::value>(c, cfg, dinv); });
@@ -449,8 +474,11 @@ class EngineT final : public Engine {
   }
   template <int VEC, int BS, int NDM>
   void gm_orth_t(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) {
-    MPRK_LAUNCH_KC(c, KC_GM_ORTH, (k_gm_orth<S, C, VEC, BS, NDM>), c.ln_red, c.ln_red, (S*)c.V, c.vstride,
-                   (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
+    with_ad<BS>(dinv, [&](auto ad) {
+      constexpr int AD = decltype(ad)::value;
+      MPRK_LAUNCH_KC(c, KC_GM_ORTH, (k_gm_orth<S, C, VEC, BS, NDM, AD>), c.ln_red, c.ln_red, (S*)c.V, c.vstride,
+                       (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
+    });
   }
   // folded steps on z-marching tiles (c.vec is 4 or 8 there)
   template <int VEC>
@@ -464,9 +492,12 @@ class EngineT final : public Engine {
   void gm_zstep_t(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc, const BJDesc& dinv,
                   int k) {
     const Coef<C> M = cast_coef<C>(Mc);
-    MPRK_LAUNCH_KC_LDS(c, KC_GM_STEP, (k_gm_zstep<S, C, VEC, BS, NDM>), c.zl.G, c.zlds, c.zl, c.geo, M,
-                       (S*)c.V, c.vstride, (const S*)c.zw[(k - 1) & 1], (S*)c.zw[k & 1],
-                       bj_typed<S>(dinv), cfg, c.ctl, c.red);
+    with_ad<BS>(dinv, [&](auto ad) {
+      constexpr int AD = decltype(ad)::value;
+      MPRK_LAUNCH_KC_LDS(c, KC_GM_STEP, (k_gm_zstep<S, C, VEC, BS, NDM, AD>), c.zl.G, c.zlds, c.zl, c.geo, M,
+                           (S*)c.V, c.vstride, (const S*)c.zw[(k - 1) & 1], (S*)c.zw[k & 1],
+                           bj_typed<S>(dinv), cfg, c.ctl, c.red);
+    });
   }
   template <int NDM>
   void gm_zstep_n(const EngineCtx& c, const SolveCfg& cfg, const Coef<double>& Mc, const BJDesc& dinv,
@@ -557,8 +588,11 @@ class EngineT final : public Engine {
   }
   template <int VEC, int BS, int NDM>
   void gm_finish_t(const EngineCtx& c, const BJDesc& dinv) {
-    MPRK_LAUNCH_KC(c, KC_GM_FINISH, (k_gm_finish<S, C, VEC, BS, NDM>), c.ln_vec, c.ln_vec, c.y, (const S*)c.V,
-                c.vstride, bj_typed<S>(dinv), c.ctl);
+    with_ad<BS>(dinv, [&](auto ad) {
+      constexpr int AD = decltype(ad)::value;
+      MPRK_LAUNCH_KC(c, KC_GM_FINISH, (k_gm_finish<S, C, VEC, BS, NDM, AD>), c.ln_vec, c.ln_vec, c.y, (const S*)c.V,
+                    c.vstride, bj_typed<S>(dinv), c.ctl);
+    });
   }
   template <int NDM>
   void gm_finish_n(const EngineCtx& c, const BJDesc& dinv) {
@@ -614,9 +648,13 @@ class EngineT final : public Engine {
   }
   template <int VEC, int BS>
   void apply_bj_t(const EngineCtx& c, const BJDesc& dinv, const void* x, void* y) {
-    if constexpr (BS > 0)
-      MPRK_LAUNCH_KC(c, KC_APPLY64, (k_bj_apply<S, C, VEC, BS>), c.ln_vec, c.ln_vec, (const S*)x, (S*)y,
-                  bj_typed<S>(dinv));
+    if constexpr (BS > 0) {
+      with_ad<BS>(dinv, [&](auto ad) {
+        constexpr int AD = decltype(ad)::value;
+        MPRK_LAUNCH_KC(c, KC_APPLY64, (k_bj_apply<S, C, VEC, BS, AD>), c.ln_vec, c.ln_vec, (const S*)x,
+                       (S*)y, bj_typed<S>(dinv));
+      });
+    }
   }
   hipError_t apply_bj(const EngineCtx& c, const BJDesc& dinv, const void* x, void* y) override {
     if (c.bs == 0) return hipErrorInvalidValue;

@@ -358,7 +358,7 @@ __global__ __launch_bounds__(TPB) void k_apply_lp(Launch ln, Geo geo, Coef<C> M,
   }
 }
 
-template <typename S, typename C, int VEC, int BS>
+template <typename S, typename C, int VEC, int BS, int AD = 0>
 __global__ __launch_bounds__(TPB) void k_bj_apply(Launch ln, const S* __restrict__ r,
                                                   S* __restrict__ z, BJ<S> dinv) {
   const int L = xcd_block(ln.G);
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(TPB) void k_bj_apply(Launch ln, const S* __restrict
 #pragma unroll
       for (int v = 0; v < VEC; ++v) rv[v] = C(0);
     }
-    bj_apply_lane<C, S, VEC, BS>(dinv, g * VEC, valid, rv, zv);
+    bj_apply_lane<C, S, VEC, BS, AD>(dinv, g * VEC, valid, rv, zv);
     if (valid) storev<S, C, VEC>(z + g * VEC, zv);
   }
 }
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(TPB) void k_bj_apply(Launch ln, const S* __restrict
 // ------------------------------------------------------------------------------------------
 
 // Start of a CG pass: r = LP(res / scale), z = BJ(r), rz = (r, z), rr = (r, r)
-template <typename S, typename C, int VEC, int BS>
+template <typename S, typename C, int VEC, int BS, int AD = 0>
 __global__ __launch_bounds__(TPB) void k_cg_begin(Launch ln, const double* __restrict__ res,
                                                   S* __restrict__ r, S* __restrict__ z,
                                                   BJ<S> dinv, SolveCfg cfg,
@@ -398,14 +398,14 @@ __global__ __launch_bounds__(TPB) void k_cg_begin(Launch ln, const double* __res
     double t[VEC];
     loadv<double, double, VEC>(res + e, t);
     BJRows<S, VEC, bj_early<S, VEC, BS>() ? BS : 1> R;
-    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS>(dinv, e, valid, R);
+    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS, AD>(dinv, e, valid, R);
     C rv[VEC], zv[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) rv[v] = valid ? rnd<S, C>((C)(t[v] * inv)) : C(0);
     C prz = C(0), prr = C(0);
     if constexpr (BS > 0) {
-      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS>(R, valid, rv, zv);
-      else bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, rv, zv);
+      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS, AD>(dinv, e, R, valid, rv, zv);
+      else bj_apply_lane<C, S, VEC, BS, AD>(dinv, e, valid, rv, zv);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) zv[v] = rnd<S, C>(zv[v]);
     }
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(Launch ln, Geo geo, Coef<C> M, C
 }
 
 // x += alpha p (x = alpha p first), r -= alpha q, z = BJ(r), rz, rr; convergence test.
-template <typename S, typename C, int VEC, int BS>
+template <typename S, typename C, int VEC, int BS, int AD = 0>
 __global__ __launch_bounds__(TPB) void k_cg_upd(Launch ln, S* __restrict__ x,
                                                 const S* __restrict__ p, S* __restrict__ r,
                                                 const S* __restrict__ q, S* __restrict__ z,
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(TPB) void k_cg_upd(Launch ln, S* __restrict__ x,
     loadv<C, S, VEC>(r + e, rv);
     loadv<C, S, VEC>(x + e, xv);
     BJRows<S, VEC, bj_early<S, VEC, BS>() ? BS : 1> R;
-    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS>(dinv, e, valid, R);
+    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS, AD>(dinv, e, valid, R);
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       xv[v] = first ? alpha * pv[v] : xv[v] + alpha * pv[v];
@@ -517,8 +517,8 @@ __global__ __launch_bounds__(TPB) void k_cg_upd(Launch ln, S* __restrict__ x,
     }
     C prz = C(0), prr = C(0);
     if constexpr (BS > 0) {
-      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS>(R, valid, rv, zv);
-      else bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, rv, zv);
+      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS, AD>(dinv, e, R, valid, rv, zv);
+      else bj_apply_lane<C, S, VEC, BS, AD>(dinv, e, valid, rv, zv);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) zv[v] = rnd<S, C>(zv[v]);
       if (valid) storev<S, C, VEC>(z + e, zv);
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(TPB) void k_promote(Launch ln, double* __restrict__
 
 // Start of a GMRES cycle: V_0 = LP(res / scale) ; zt = BJ(V_0) (the preconditioned direction of the first
 // Arnoldi step, before normalisation; BJ is linear) ; beta = ||V_0||_rms.
-template <typename S, typename C, int VEC, int BS>
+template <typename S, typename C, int VEC, int BS, int AD = 0>
 __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __restrict__ res,
                                                   S* __restrict__ v0, S* __restrict__ zt,
                                                   BJ<S> dinv, SolveCfg cfg,
@@ -605,7 +605,7 @@ __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __res
     double t[VEC];
     loadv<double, double, VEC>(res + e, t);
     BJRows<S, VEC, bj_early<S, VEC, BS>() ? BS : 1> R;
-    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS>(dinv, e, valid, R);
+    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS, AD>(dinv, e, valid, R);
     __builtin_amdgcn_sched_barrier(0);  // res and the rows in flight together
     C rv[VEC];
     C s = C(0);
@@ -617,8 +617,8 @@ __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __res
     if (valid) storev<S, C, VEC>(v0 + e, rv);
     if constexpr (BS > 0) {
       C zv[VEC];
-      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS>(R, valid, rv, zv);
-      else bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, rv, zv);
+      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS, AD>(dinv, e, R, valid, rv, zv);
+      else bj_apply_lane<C, S, VEC, BS, AD>(dinv, e, valid, rv, zv);
       if (valid) storev<S, C, VEC>(zt + e, zv);
     }
     acc[0] += (double)s;
@@ -854,7 +854,7 @@ __global__ __launch_bounds__(TPB) void k_gm_reorth(Launch ln, S* __restrict__ V,
 // k_gm_reorth in the second pass of CGS2); h_{j+1,j} = ||w||; Givens update of the Hessenberg column; residual estimate |g_{j+1}|.
 // With a preconditioner (BS > 0) also zt = BJ(w), the next step's preconditioned direction
 // before normalisation.
-template <typename S, typename C, int VEC, int BS, int NDM>
+template <typename S, typename C, int VEC, int BS, int NDM, int AD = 0>
 __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, size_t vstride,
                                                  S* __restrict__ zt, BJ<S> dinv,
                                                  SolveCfg cfg, Ctl* ctl, Red red) {
@@ -883,7 +883,7 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
     for (int k = 0; k < CH; ++k)
       v0[k] = *reinterpret_cast<const Vec<S, VEC>*>(V + (size_t)min(k, nd - 1) * vstride + e);
     BJRows<S, VEC, EARLY ? BS : 1> R;
-    if constexpr (EARLY) bj_load<S, VEC, BS>(dinv, e, valid, R);
+    if constexpr (EARLY) bj_load<S, VEC, BS, AD>(dinv, e, valid, R);
     // keep them in flight together (the scheduler would otherwise wait for w and the basis
     // chunk before issuing the block-Jacobi rows: a second memory round trip)
     __builtin_amdgcn_sched_barrier(0);
@@ -920,8 +920,8 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
     if (valid) storev<S, C, VEC>(w + e, wv);
     if constexpr (BS > 0) {
       C zv[VEC];
-      if constexpr (EARLY) bj_mul<C, S, VEC, BS>(R, valid, wv, zv);
-      else bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, wv, zv);
+      if constexpr (EARLY) bj_mul<C, S, VEC, BS, AD>(dinv, e, R, valid, wv, zv);
+      else bj_apply_lane<C, S, VEC, BS, AD>(dinv, e, valid, wv, zv);
       if (valid) storev<S, C, VEC>(zt + e, zv);
     }
     acc[0] += (double)s;
@@ -1144,7 +1144,7 @@ struct GmStepBody {
 // Folded Arnoldi step j (j = J + 1 >= 1): v_j from w_{j-1} (win) and the basis, stored; the
 // stencil of vscale-estimate * BJ(v_j) through the tile into w_j (wout); column j - 1 completed
 // with ||v_j||; column j's entries for the next launch.
-template <typename S, typename C, int VEC, int BS, int NDM>
+template <typename S, typename C, int VEC, int BS, int NDM, int AD = 0>
 __global__ __launch_bounds__(TPB) void k_gm_zstep(ZLaunch zl, Geo geo, Coef<C> M,
                                                   S* __restrict__ V, size_t vstride,
                                                   const S* __restrict__ win,
@@ -1194,7 +1194,7 @@ __global__ __launch_bounds__(TPB) void k_gm_zstep(ZLaunch zl, Geo geo, Coef<C> M
     }
     if constexpr (BS > 0) {
       C zv[VEC];
-      bj_apply_lane<C, S, VEC, BS>(dinv, e, true, v, zv);
+      bj_apply_lane<C, S, VEC, BS, AD>(dinv, e, true, v, zv);
 #pragma unroll
       for (int q = 0; q < VEC; ++q) o[q] = sc * zv[q];
     } else {
@@ -1300,7 +1300,7 @@ __global__ __launch_bounds__(TPB) void k_gm_zclose(Launch ln, const S* __restric
 // triangular least-squares system is solved here by every block (J <= 32), so a cycle the
 // host ends early (fewer iterations enqueued than the device would run) is still promoted.
 // NDM bounds J: the host passes the number of Arnoldi steps it enqueued in this cycle.
-template <typename S, typename C, int VEC, int BS, int NDM>
+template <typename S, typename C, int VEC, int BS, int NDM, int AD = 0>
 __global__ __launch_bounds__(TPB) void k_gm_finish(Launch ln, double* __restrict__ y,
                                                    const S* __restrict__ V, size_t vstride,
                                                    BJ<S> dinv, Ctl* ctl) {
@@ -1347,7 +1347,7 @@ __global__ __launch_bounds__(TPB) void k_gm_finish(Launch ln, double* __restrict
     for (int k = 0; k < CH; ++k)
       v0[k] = *reinterpret_cast<const Vec<S, VEC>*>(V + (size_t)min(k, J - 1) * vstride + e);
     BJRows<S, VEC, bj_early<S, VEC, BS>() ? BS : 1> R;
-    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS>(dinv, e, valid, R);
+    if constexpr (bj_early<S, VEC, BS>()) bj_load<S, VEC, BS, AD>(dinv, e, valid, R);
     double yv[VEC];
     loadv<double, double, VEC>(y + e, yv);
     C t[VEC], zv[VEC];
@@ -1377,8 +1377,8 @@ __global__ __launch_bounds__(TPB) void k_gm_finish(Launch ln, double* __restrict
 #pragma unroll
     for (int v = 0; v < VEC; ++v) t[v] = valid ? t[v] : C(0);
     if constexpr (BS > 0) {
-      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS>(R, valid, t, zv);
-      else bj_apply_lane<C, S, VEC, BS>(dinv, e, valid, t, zv);
+      if constexpr (bj_early<S, VEC, BS>()) bj_mul<C, S, VEC, BS, AD>(dinv, e, R, valid, t, zv);
+      else bj_apply_lane<C, S, VEC, BS, AD>(dinv, e, valid, t, zv);
     } else {
 #pragma unroll
       for (int v = 0; v < VEC; ++v) zv[v] = t[v];
@@ -1402,7 +1402,7 @@ static __global__ void k_fill_pattern(long n, double a, double b, double* __rest
 }
 
 // In-place Gauss-Jordan inverse of an n x n (n <= BJ_MAX) matrix with partial pivoting.
-__device__ inline int gj_invert(double (&a)[BJ_MAX][BJ_MAX], double (&inv)[BJ_MAX][BJ_MAX], int n) {
+__host__ __device__ inline int gj_invert(double (&a)[BJ_MAX][BJ_MAX], double (&inv)[BJ_MAX][BJ_MAX], int n) {
   for (int i = 0; i < BJ_MAX; ++i)
     for (int k = 0; k < BJ_MAX; ++k) inv[i][k] = (i == k) ? 1.0 : 0.0;
   for (int col = 0; col < n; ++col) {
@@ -1457,13 +1457,33 @@ __device__ inline void bj_store(S* dinv, int blk, int BS, int n, const double (&
   }
 }
 
+// Block blk's inverse in the adaptive-precision layout (mode 4) for lanes of `lay` rows: each
+// row in its chunk's type (tag 0 FP16, 1 FP32, 2 FP64) at the chunk's byte offset.
+__device__ inline void bj_store_adaptive(void* base, const int* tag, const long long* aoff, int blk,
+                                         int BS, int n, const double (&inv)[BJ_MAX][BJ_MAX], int lay) {
+  for (int i = 0; i < BS; ++i) {
+    const int r = blk * BS + i;
+    const int g = r / lay, q = r % lay;
+    const int ch = g >> 6;
+    const size_t ent = ((size_t)q * 64 + (g & 63)) * BS;
+    char* p = (char*)base + aoff[ch];
+    for (int k = 0; k < BS; ++k) {
+      const double v = (i < n && k < n) ? inv[i][k] : (i == k ? 1.0 : 0.0);
+      if (tag[ch] == 0) ((half_t*)p)[ent + k] = (half_t)v;
+      else if (tag[ch] == 1) ((float*)p)[ent + k] = (float)v;
+      else ((double*)p)[ent + k] = v;
+    }
+  }
+}
+
 // Diagonal blocks of M = I - sigma K for the stencil operator (Mc = stencil of M in FP64).
 // Slot i receives the inverse of block reps[i] (reps == nullptr: block i, stored in the
 // layout `lay`), so the per-block table and the table of distinct blocks come from the same
 // arithmetic.
 template <typename S>
 __global__ void k_bj_setup_stencil(int nslot, int BS, Geo geo, Coef<double> Mc, S* dinv,
-                                   int* fail, const int* reps, int lay) {
+                                   int* fail, const int* reps, int lay, const int* atag,
+                                   const long long* aoff) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= nslot) return;
   const int blk = reps ? reps[slot] : slot;
@@ -1484,13 +1504,15 @@ __global__ void k_bj_setup_stencil(int nslot, int BS, Geo geo, Coef<double> Mc, 
     }
   }
   if (gj_invert(a, inv, n)) atomicOr(fail, 1);
-  bj_store<S>(dinv, slot, BS, n, inv, reps ? 0 : lay);
+  if (atag) bj_store_adaptive(dinv, atag, aoff, slot, BS, n, inv, lay);
+  else bj_store<S>(dinv, slot, BS, n, inv, reps ? 0 : lay);
 }
 
 // Diagonal blocks of M = I - sigma K from the FP64 CSR values of K (slots as above).
 template <typename S>
 __global__ void k_bj_setup_csr(int nslot, int BS, int N, Csr csr, const double* kval, double sigma,
-                               S* dinv, int* fail, const int* reps, int lay) {
+                               S* dinv, int* fail, const int* reps, int lay, const int* atag,
+                               const long long* aoff) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= nslot) return;
   const int blk = reps ? reps[slot] : slot;
@@ -1507,7 +1529,8 @@ __global__ void k_bj_setup_csr(int nslot, int BS, int N, Csr csr, const double* 
     }
   }
   if (gj_invert(a, inv, n)) atomicOr(fail, 1);
-  bj_store<S>(dinv, slot, BS, n, inv, reps ? 0 : lay);
+  if (atag) bj_store_adaptive(dinv, atag, aoff, slot, BS, n, inv, lay);
+  else bj_store<S>(dinv, slot, BS, n, inv, reps ? 0 : lay);
 }
 
 // LP copy of the CSR values of K, scaled by a power of two into [-1, 1].

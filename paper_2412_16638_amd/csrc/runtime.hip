@@ -216,6 +216,72 @@ static void bj_dedup(const Geo& geo, const Coef<double>& K, double sigma, int bs
   }
 }
 
+// Adaptive-precision block-Jacobi layout (Ginkgo's adaptive block-Jacobi, cited in the
+// Introduction: each diagonal block's inverse stored in the lowest precision its conditioning
+// allows).  A block may be stored in a type of unit roundoff u when u * cond_1(D_b) <= tol
+// (the rounding of the stored inverse then perturbs the preconditioned block by at most about
+// tol) and its inverse's entries are within that type's range; FP16, FP32, FP64 in that order.
+// The type is chosen per chunk of 64 lane groups of vec rows (the unit a wave reads), as the
+// widest its blocks need.  Fills tag (per chunk) and aoff (per chunk byte offsets, plus the
+// total at the end); the distinct blocks are found as for the shared-inverse table.
+static void bj_adaptive_layout(const Geo& geo, const Coef<double>& K, double sigma, int bs, int vec,
+                               double tol, std::vector<int>& tag, std::vector<long long>& aoff) {
+  std::vector<int> reps, idx;
+  bj_dedup(geo, K, sigma, bs, reps, idx);
+  const int N = geo.N;
+  std::vector<int> rtag(reps.size());
+  int c[7];
+  double v[7];
+  for (size_t s = 0; s < reps.size(); ++s) {
+    const int r0 = reps[s] * bs, n = std::min(bs, N - r0);
+    double a[BJ_MAX][BJ_MAX] = {}, inv[BJ_MAX][BJ_MAX];
+    for (int i = 0; i < n; ++i) {
+      a[i][i] += 1.0;
+      const int m = csr_row_entries(geo, K, r0 + i, c, v);
+      for (int e = 0; e < m; ++e)
+        if (c[e] >= r0 && c[e] < r0 + n) a[i][c[e] - r0] -= sigma * v[e];
+    }
+    double n1 = 0.0;
+    for (int k = 0; k < n; ++k) {
+      double cs = 0.0;
+      for (int i = 0; i < n; ++i) cs += std::fabs(a[i][k]);
+      n1 = std::max(n1, cs);
+    }
+    double a2[BJ_MAX][BJ_MAX];
+    std::memcpy(a2, a, sizeof(a));
+    int t = 2;
+    if (!gj_invert(a2, inv, n)) {
+      double ni = 0.0, mx = 0.0;
+      for (int k = 0; k < n; ++k) {
+        double cs = 0.0;
+        for (int i = 0; i < n; ++i) {
+          cs += std::fabs(inv[i][k]);
+          mx = std::max(mx, std::fabs(inv[i][k]));
+        }
+        ni = std::max(ni, cs);
+      }
+      const double kappa = n1 * ni;
+      if (std::ldexp(1.0, -11) * kappa <= tol && mx < 6.0e4) t = 0;
+      else if (std::ldexp(1.0, -24) * kappa <= tol && mx < 1.0e38) t = 1;
+    }
+    rtag[s] = t;
+  }
+  const long rows = (long)bj_chunks((long)((N + bs - 1) / bs) * bs, vec);
+  const int nch = (int)(rows / (64L * vec));
+  const int nblk = (N + bs - 1) / bs;
+  tag.assign((size_t)nch, 0);
+  for (int b = 0; b < nblk; ++b) {
+    const int ch = (int)(((long)b * bs / vec) >> 6);
+    tag[(size_t)ch] = std::max(tag[(size_t)ch], rtag[(size_t)idx[(size_t)b]]);
+  }
+  aoff.assign((size_t)nch + 1, 0);
+  const long long per = 64LL * vec * bs;  // entries per chunk
+  for (int ch = 0; ch < nch; ++ch) {
+    const long long bytes = per * (tag[(size_t)ch] == 0 ? 2 : tag[(size_t)ch] == 1 ? 4 : 8);
+    aoff[(size_t)ch + 1] = aoff[(size_t)ch] + ((bytes + 255) & ~255LL);
+  }
+}
+
 }  // namespace mprk
 
 // ------------------------------------------------------------------------------------------
@@ -416,6 +482,10 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
   if (p->reorth != 0 && p->reorth != 1) return set_error(MPRK_EINVAL, "reorth must be 0 or 1");
   if (p->gm_form < MPRK_GMFORM_AUTO || p->gm_form > MPRK_GMFORM_FOLDED)
     return set_error(MPRK_EINVAL, "gm_form must be one of the MPRK_GMFORM values");
+  if (!(p->bj_adapt_tol >= 0.0)) return set_error(MPRK_EINVAL, "bj_adapt_tol must be >= 0");
+  if (p->bj_adapt_tol > 0.0 && p->bj_shared)
+    return set_error(MPRK_EINVAL, "adaptive-precision block-Jacobi stores one inverse per block "
+                                  "(bj_shared must be 0)");
   return MPRK_OK;
 }
 
@@ -597,7 +667,15 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
       if (B.mode == 2) B.idx.clear();
     } else {
       B.nslot = nblk;
-      B.mode = 3;  // rows interleaved for the LP kernels' lanes of vec_lp rows
+      B.mode = p.bj_adapt_tol > 0.0 ? 4 : 3;  // rows interleaved for lanes of vec_lp rows
+    }
+    if (B.mode == 4) {
+      bj_adaptive_layout(geo, Kc, sigmas[q], bs, vec_lp, p.bj_adapt_tol, B.tag, B.aoff);
+      B.o_inv = take((size_t)B.aoff.back());
+      B.aoff.pop_back();
+      B.o_tag = take(B.tag.size() * 4);
+      B.o_aoff = take(B.aoff.size() * 8);
+      continue;
     }
     const size_t rows = B.mode == 3 ? std::max((size_t)nblk * bs, bj_chunks((long)nblk * bs, vec_lp))
                                     : (size_t)B.nslot * bs;
@@ -780,12 +858,22 @@ static int bind_impl(mprk_handle* h, double* u_dev, void* workspace_dev) {
     }
     if (B.mode == 1)
       HIPCHK(hipMemcpyAsync(h->ws + B.o_idx, B.idx.data(), B.idx.size() * 4, hipMemcpyHostToDevice, h->stream));
+    const int* atag = nullptr;
+    const long long* aoff = nullptr;
+    if (B.mode == 4) {
+      HIPCHK(hipMemcpyAsync(h->ws + B.o_tag, B.tag.data(), B.tag.size() * 4, hipMemcpyHostToDevice, h->stream));
+      HIPCHK(hipMemcpyAsync(h->ws + B.o_aoff, B.aoff.data(), B.aoff.size() * 8, hipMemcpyHostToDevice,
+                            h->stream));
+      atag = (const int*)(h->ws + B.o_tag);
+      aoff = (const long long*)(h->ws + B.o_aoff);
+    }
+    const int lay = (B.mode == 3 || B.mode == 4) ? h->vec_lp : 0;
     if (h->op.format == MPRK_FMT_CSR)
       HIPCHK(h->eng->bj_setup_csr(c, (const double*)(h->ws + h->o_kval), h->sigmas[q], dinv, fail,
-                                  B.nslot, reps, B.mode == 3 ? h->vec_lp : 0));
+                                  B.nslot, reps, lay, atag, aoff));
     else
       HIPCHK(h->eng->bj_setup_stencil(c, stage_coef(h->Kc, h->sigmas[q]), dinv, fail, B.nslot, reps,
-                                      B.mode == 3 ? h->vec_lp : 0));
+                                      lay, atag, aoff));
   }
   if (h->fdm) {
     // fast-diagonalisation: per-axis eigenbasis (compute type, rows padded with zeros to
@@ -988,7 +1076,9 @@ Red mprk_handle::red() const {
 BJDesc mprk_handle::bj_desc(int si) const {
   if (!bs || si < 0 || si >= (int)bjsets.size()) return BJDesc{nullptr, nullptr, 0};
   const BJSet& B = bjsets[si];
-  return BJDesc{ws + B.o_inv, B.mode == 1 ? (const int*)(ws + B.o_idx) : nullptr, B.mode};
+  return BJDesc{ws + B.o_inv, B.mode == 1 ? (const int*)(ws + B.o_idx) : nullptr, B.mode,
+                B.mode == 4 ? (const int*)(ws + B.o_tag) : nullptr,
+                B.mode == 4 ? (const long long*)(ws + B.o_aoff) : nullptr};
 }
 
 int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* kout,
@@ -1221,6 +1311,9 @@ extern "C" int32_t mprk_launch_info_get(const mprk_handle* h, mprk_launch_info* 
   out->residual_planes = h->zm_lz;
   out->gm_form = h->prec.krylov == MPRK_GMRES ? h->gform + 1 : 0;
   out->gm_planes = h->prec.krylov == MPRK_GMRES && h->gform > 0 ? h->zl_lp.LZ : 0;
+  for (int t = 0; t < 3; ++t) out->bj_chunks[t] = 0;
+  for (const auto& B : h->bjsets)
+    for (int t : B.tag) out->bj_chunks[t] += 1;
   return MPRK_OK;
 }
 

@@ -74,12 +74,15 @@ struct mprk_handle {
   // block-Jacobi inverse sets, one per distinct sigma
   struct BJSet {
     int mode = 0;          // 0 per-block (row-major), 1 distinct table + index, 2 one shared
-                           // inverse, 3 per-block with rows interleaved for lanes of vec_lp rows
+                           // inverse, 3 per-block with rows interleaved for lanes of vec_lp rows,
+                           // 4 as 3 with a storage type per chunk of 64 lane groups
     int nslot = 0;         // inverses stored
     bool table() const { return mode == 1 || mode == 2; }  // slots hold distinct inverses
-    size_t o_inv = 0, o_reps = 0, o_idx = 0;
+    size_t o_inv = 0, o_reps = 0, o_idx = 0, o_tag = 0, o_aoff = 0;
     std::vector<int> reps; // representative block of each slot (modes 1, 2)
     std::vector<int> idx;  // slot of each block (mode 1)
+    std::vector<int> tag;  // mode 4: storage type of each chunk (0 FP16, 1 FP32, 2 FP64)
+    std::vector<long long> aoff;  // mode 4: byte offset of each chunk in the inverse area
   };
   std::vector<BJSet> bjsets;
   size_t o_rowptr = 0, o_col = 0, o_kval = 0, o_mval = 0;
