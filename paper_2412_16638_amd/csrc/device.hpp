@@ -447,15 +447,6 @@ struct InScaled {
   __device__ __forceinline__ C one(int i) const { return s * (C)a[i]; }
 };
 
-// CSR row product sum_k val[k] * x[col[k]] with x provided by functor F (scalar access).
-template <typename C, typename SV, typename F>
-__device__ __forceinline__ C csr_row(const Csr& m, const SV* __restrict__ val, int row, const F& f) {
-  const int b = m.rowptr[row], e = m.rowptr[row + 1];
-  C acc = C(0);
-  for (int k = b; k < e; ++k) acc += (C)val[k] * f.one(m.col[k]);
-  return acc;
-}
-
 // Block-Jacobi inverses.  mode 0: one stored inverse per block (row r's BS entries at
 // inv[r * BS]); mode 1: a table of distinct inverses and idx[block] selecting one; mode 2: a
 // single inverse shared by every block (constant-coefficient operators with BS | nx); mode 3:

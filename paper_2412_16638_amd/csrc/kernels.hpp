@@ -92,11 +92,78 @@ __global__ __launch_bounds__(TPB) void k_stage_rhs(Launch ln, const double* __re
   }
 }
 
+// CSR row products of one wavefront's 64 consecutive rows gw .. gw + 63 (rows from ng on are
+// empty): lane l returns sum_k val[k] x[col[k]] over row gw + l, x given by functor F.  The rows'
+// entries [rowptr[gw], rowptr[gw + 64]) are one contiguous run: consecutive lanes read
+// consecutive entries (coalesced column and value loads, CSR_U of them in flight per lane), each
+// product goes to the wave's own LDS slice and each lane then adds its row's products in entry
+// order.  Only the wave takes part (no workgroup barrier).  Runs longer than 64 CSR_U entries
+// (rows averaging more than CSR_U entries) are summed row by row instead.  Every lane of the
+// wave calls it with the same gw.
+constexpr int CSR_U = 8;
+
+// orders the wave's LDS writes before its lanes read each other's values
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// first row of the calling lane's wavefront among the workgroup's rows g0 .. g0 + TPB - 1
+__device__ __forceinline__ int wave_row0(int g0) {
+  return g0 + 64 * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+template <typename C, typename SV, typename F>
+__device__ __forceinline__ C csr_wave_row(const Csr& m, const SV* __restrict__ val, int gw, int ng,
+                                          const F& f) {
+  __shared__ C prod[TPB / 64][CSR_U * 64];
+  const int lane = threadIdx.x & 63;
+  C* buf = prod[threadIdx.x >> 6];
+  const int g = gw + lane;
+  const int b0 = m.rowptr[gw], b1 = m.rowptr[min(gw + 64, ng)];
+  const int rb = g < ng ? m.rowptr[g] : 0;
+  const int re = g < ng ? m.rowptr[g + 1] : 0;
+  C acc = C(0);
+  if (b1 - b0 > CSR_U * 64) {  // uniform over the wave
+    for (int k = rb; k < re; ++k) acc += (C)val[k] * f.one(m.col[k]);
+    return acc;
+  }
+  if (b1 == b0) return acc;  // every row of the wave is empty
+  // entry loads are unconditional (indices clamped into the run) so that all of them are in
+  // flight together; the products of clamped slots land past the run's end in the slice
+  int cl[CSR_U];
+  SV vl[CSR_U];
+  C xv[CSR_U];
+#pragma unroll
+  for (int u = 0; u < CSR_U; ++u) {
+    const int k = min(b0 + u * 64 + lane, b1 - 1);
+    cl[u] = m.col[k];
+    vl[u] = val[k];
+  }
+#pragma unroll
+  for (int u = 0; u < CSR_U; ++u) xv[u] = f.one(cl[u]);
+#pragma unroll
+  for (int u = 0; u < CSR_U; ++u) buf[u * 64 + lane] = (C)vl[u] * xv[u];
+  wave_sync();
+  // the row's products are read CSR_U at a time (clamped reads, added in entry order)
+  for (int k0 = rb; k0 < re; k0 += CSR_U) {
+    C pv[CSR_U];
+#pragma unroll
+    for (int u = 0; u < CSR_U; ++u) pv[u] = buf[min(k0 + u, b1 - 1) - b0];
+#pragma unroll
+    for (int u = 0; u < CSR_U; ++u)
+      if (k0 + u < re) acc += pv[u];
+  }
+  wave_sync();  // the next call writes the slice again
+  return acc;
+}
+
 // FMT 0: matrix-free stencil (VEC values per thread); FMT 1: CSR (one row per group, VEC = 1)
+// with the row product csum from csr_wave_row.
 template <int VEC, int FMT, typename P = NoPre>
-__device__ __forceinline__ void k64_group(const Geo& geo, const Coef<double>& K, const Csr& csr,
-                                          const double* __restrict__ kval,
-                                          const double* __restrict__ y, int g,
+__device__ __forceinline__ void k64_group(const Geo& geo, const Coef<double>& K,
+                                          const double* __restrict__ y, int g, double csum,
                                           double (&yc)[VEC], double (&ky)[VEC], const P& pre = P()) {
   if constexpr (FMT == 0) {
     In1<double, double, VEC> f{y};
@@ -104,9 +171,8 @@ __device__ __forceinline__ void k64_group(const Geo& geo, const Coef<double>& K,
   } else {
     static_assert(VEC == 1, "CSR kernels use one row per group");
     pre();
-    In1<double, double, 1> f{y};
     yc[0] = y[g];
-    ky[0] = csr_row<double, double>(csr, kval, g, f);
+    ky[0] = csum;
   }
 }
 
@@ -163,15 +229,24 @@ __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<doubl
   const int L = xcd_block(ln.G);
   double acc[3] = {0.0, 0.0, 0.0};
   for (int it = 0; it < ln.nit; ++it) {
-    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
-    if (g >= ln.ng) break;
-    const int e = g * VEC;
+    const int g0 = (L * ln.nit + it) * TPB;
+    const int g = g0 + threadIdx.x;
+    const int gw = FMT == 1 ? wave_row0(g0) : g;  // CSR: the wave leaves together
+    if (gw >= ln.ng) break;
+    // for CSR, rhs and the forcing are loaded ahead of the staged row products (rows past the
+    // end load row ng - 1 unused)
+    const int e = FMT == 1 ? min(g, ln.ng - 1) : g * VEC;
     double yc[VEC], ky[VEC], b[VEC], rr[VEC], fv[VEC];
     loadv<double, double, VEC>(rhs + e, b);
     if (force) loadv<double, double, VEC>(force + e, fv);
+    double csum = 0.0;
+    if constexpr (FMT == 1) {
+      csum = csr_wave_row<double, double>(csr, kval, gw, ln.ng, In1<double, double, 1>{y});
+      if (g >= ln.ng) break;
+    }
     // the stencil's seven loads are kept in flight together (an empty loader selects the
     // scheduling barrier; moving rhs into the group measured slower)
-    k64_group<VEC, FMT>(geo, K, csr, kval, y, g, yc, ky, [] {});
+    k64_group<VEC, FMT>(geo, K, y, g, csum, yc, ky, [] {});
     if (force) {  // constant forcing: f(y) = K y + g, so the stage solves y - sigma f(y) = rhs
 #pragma unroll
       for (int v = 0; v < VEC; ++v) ky[v] += fv[v];
@@ -258,10 +333,17 @@ __global__ __launch_bounds__(TPB) void k_apply64(Launch ln, Geo geo, Coef<double
                                                  const double* __restrict__ force) {
   const int L = xcd_block(ln.G);
   for (int it = 0; it < ln.nit; ++it) {
-    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    const int g0 = (L * ln.nit + it) * TPB;
+    const int g = g0 + threadIdx.x;
+    double csum = 0.0;
+    if constexpr (FMT == 1) {
+      const int gw = wave_row0(g0);
+      if (gw >= ln.ng) break;
+      csum = csr_wave_row<double, double>(csr, kval, gw, ln.ng, In1<double, double, 1>{x});
+    }
     if (g >= ln.ng) break;
     double xc[VEC], kx[VEC];
-    k64_group<VEC, FMT>(geo, K, csr, kval, x, g, xc, kx);
+    k64_group<VEC, FMT>(geo, K, x, g, csum, xc, kx);
     if (force) {  // mode 0 with forcing: y = K x + g (an explicit stage's slope)
       double fv[VEC];
       loadv<double, double, VEC>(force + g * VEC, fv);
@@ -329,17 +411,18 @@ __global__ __launch_bounds__(TPB) void k_combine(Launch ln, double* __restrict__
 // LP operators
 // ------------------------------------------------------------------------------------------
 
-// w = M v for one group; for CSR M v = v - msig * (Kt v) with Kt the scaled LP values.
+// w = M v for one group; for CSR M v = v - msig * (Kt v) with Kt the scaled LP values, the row
+// product csum = (Kt v)_g coming from csr_wave_row.
 template <typename S, typename C, int VEC, int FMT, typename F, typename P = NoPre>
-__device__ __forceinline__ void mlp_group(const Geo& geo, const Coef<C>& M, const Csr& csr,
-                                          const S* __restrict__ mval, C msig, int g, const F& f,
-                                          C (&ctr)[VEC], C (&w)[VEC], const P& pre = P()) {
+__device__ __forceinline__ void mlp_group(const Geo& geo, const Coef<C>& M, C msig, int g, C csum,
+                                          const F& f, C (&ctr)[VEC], C (&w)[VEC],
+                                          const P& pre = P()) {
   if constexpr (FMT == 0) {
     stencil_group<C, VEC>(geo, M, g * VEC, f, ctr, w, pre);
   } else {
     static_assert(VEC == 1, "CSR kernels use one row per group");
     ctr[0] = f.one(g);
-    w[0] = ctr[0] - msig * csr_row<C, S>(csr, mval, g, f);
+    w[0] = ctr[0] - msig * csum;
   }
 }
 
@@ -348,12 +431,19 @@ __global__ __launch_bounds__(TPB) void k_apply_lp(Launch ln, Geo geo, Coef<C> M,
                                                   const S* __restrict__ mval, C msig,
                                                   const S* __restrict__ x, S* __restrict__ y) {
   const int L = xcd_block(ln.G);
+  const In1<C, S, VEC> f{x};
   for (int it = 0; it < ln.nit; ++it) {
-    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    const int g0 = (L * ln.nit + it) * TPB;
+    const int g = g0 + threadIdx.x;
+    C csum = C(0);
+    if constexpr (FMT == 1) {
+      const int gw = wave_row0(g0);
+      if (gw >= ln.ng) break;
+      csum = csr_wave_row<C, S>(csr, mval, gw, ln.ng, f);
+    }
     if (g >= ln.ng) break;
-    In1<C, S, VEC> f{x};
     C ctr[VEC], w[VEC];
-    mlp_group<S, C, VEC, FMT>(geo, M, csr, mval, msig, g, f, ctr, w);
+    mlp_group<S, C, VEC, FMT>(geo, M, msig, g, csum, f, ctr, w);
     storev<S, C, VEC>(y + g * VEC, w);
   }
 }
@@ -452,10 +542,17 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(Launch ln, Geo geo, Coef<C> M, C
   const int L = xcd_block(ln.G);
   double acc[1] = {0.0};
   for (int it = 0; it < ln.nit; ++it) {
-    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
+    const int g0 = (L * ln.nit + it) * TPB;
+    const int g = g0 + threadIdx.x;
+    C csum = C(0);
+    if constexpr (FMT == 1) {
+      const int gw = wave_row0(g0);
+      if (gw >= ln.ng) break;
+      csum = csr_wave_row<C, S>(csr, mval, gw, ln.ng, f);
+    }
     if (g >= ln.ng) break;
     C p[VEC], w[VEC];
-    mlp_group<S, C, VEC, FMT>(geo, M, csr, mval, msig, g, f, p, w);
+    mlp_group<S, C, VEC, FMT>(geo, M, msig, g, csum, f, p, w);
     C s = C(0);
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
@@ -711,23 +808,27 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
 #pragma unroll
   for (int i = 0; i < NDM; ++i) dacc[i] = C(0);
   constexpr int CH = basis_chunk<S, VEC>() < NDM ? basis_chunk<S, VEC>() : NDM;
+  const InScaled<C, S, VEC> f{PREC ? z : V + (size_t)j * vstride, (C)ctl->vscale[j]};
   for (int it = 0; it < ln.nit; ++it) {
-    const int g = (L * ln.nit + it) * TPB + threadIdx.x;
-    if (g >= ln.ng) break;
+    const int g0 = (L * ln.nit + it) * TPB;
+    const int g = g0 + threadIdx.x;
+    const int gw = FMT == 1 ? wave_row0(g0) : g;  // CSR: the wave leaves together
+    if (gw >= ln.ng) break;
     const int e = g * VEC;
     // the first chunk of basis vectors (nd >= 1) is loaded together with the stencil inputs
+    // (for CSR ahead of the staged row products; rows past the end load row ng - 1 unused)
+    const int el = FMT == 1 ? min(g, ln.ng - 1) : e;
     Vec<S, VEC> v0[CH];
 #pragma unroll
     for (int k = 0; k < CH; ++k)
-      v0[k] = *reinterpret_cast<const Vec<S, VEC>*>(V + (size_t)min(k, nd - 1) * vstride + e);
-    C ctr[VEC], w[VEC];
-    if constexpr (PREC) {
-      InScaled<C, S, VEC> f{z, (C)ctl->vscale[j]};
-      mlp_group<S, C, VEC, FMT>(geo, M, csr, mval, msig, g, f, ctr, w);
-    } else {
-      InScaled<C, S, VEC> f{V + (size_t)j * vstride, (C)ctl->vscale[j]};
-      mlp_group<S, C, VEC, FMT>(geo, M, csr, mval, msig, g, f, ctr, w);
+      v0[k] = *reinterpret_cast<const Vec<S, VEC>*>(V + (size_t)min(k, nd - 1) * vstride + el);
+    C csum = C(0);
+    if constexpr (FMT == 1) {
+      csum = csr_wave_row<C, S>(csr, mval, gw, ln.ng, f);
+      if (g >= ln.ng) break;
     }
+    C ctr[VEC], w[VEC];
+    mlp_group<S, C, VEC, FMT>(geo, M, msig, g, csum, f, ctr, w);
 #pragma unroll
     for (int v = 0; v < VEC; ++v) w[v] = rnd<S, C>(w[v]);
     storev<S, C, VEC>(wout + e, w);
