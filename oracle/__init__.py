@@ -19,10 +19,12 @@ What it computes (all float64, numpy/scipy):
                       (dense LU, sparse LU or the oracle's own FP64 Krylov).
   * krylov.py      -- plain FP64 CG, right-preconditioned GMRES(m) and block
                       Jacobi (used for large grids and for solver pins).
+  * nonlinear.py   -- the same DIRK for du/dt = K u + g + R(u) with a pointwise
+                      cubic reaction R, Newton stage solves (exact Jacobian).
   * closed_form.py -- modal closed forms: sine modes / DST-I for the Dirichlet
                       Laplacian, DFT for the periodic operator; u_N = R(tau lam)^N.
 Every function cites the passage it follows.  Parity status of each part is
 stated in its module docstring; the mixed-precision GPU paths have no oracle of
 their own beyond the FP64 result and the stated tolerances.
 """
-from . import operators, tableaus, dirk, krylov, closed_form  # noqa: F401
+from . import operators, tableaus, dirk, krylov, closed_form, nonlinear  # noqa: F401
