@@ -181,6 +181,57 @@ def run_integration(M, p, fmt, **over):
     return u, stats
 
 
+# outer-pass limit of the semi-linear runs (each pass contracts the stage error by about
+# dt a_ii max|R'|: 0.02-0.05 for the two reaction workloads)
+NONLINEAR_PASSES = 30
+
+
+def make_reaction_problem(name: str, precond: str = 'bj'):
+    """The workload with a pointwise reaction: Fisher-KPP 20 u (1 - u) on the advection-diffusion
+    bump, Allen-Cahn 50 (u - u^3) on the heat modes (scaled to max |u0| = 1)."""
+    import workloads as W
+    p = W.advdiff_fisher() if name == 'advdiff256' else W.heat_allen_cahn()
+    if precond == 'fdm':
+        p.precond = 'fdm'
+    return p
+
+
+def nonlinear_leg(M, args, fmt, bjs, mixed_over, K: int, Wm: int) -> dict:
+    """The semi-linear variant of the workload: the mixed path (the FP64 outer loop iterates the
+    non-linear stage equation, LP solves with I - sigma K) timed over K steps, its error against
+    the all-FP64 path solved to REF_TOL, and the FP64 path at the mixed path's tolerances."""
+    q = make_reaction_problem(args.workload, args.precond)
+    r64 = make_reaction_problem(args.workload, args.precond)
+    r64.precision = 'fp64'
+    # the non-linear stage needs more outer passes than the linear defaults allow
+    mixed_over = dict(mixed_over, refine_max=NONLINEAR_PASSES)
+    ref, st_ref = run_integration(M, r64, fmt, rtol=REF_TOL, outer_tol=REF_TOL, bj_shared=bjs,
+                                  refine_max=NONLINEAR_PASSES)
+    um, sm = run_integration(M, q, fmt, bj_shared=bjs, **mixed_over)
+    err = float(np.linalg.norm(um - ref) / np.linalg.norm(ref))
+    st = M.from_problem(q, fmt=fmt, bj_shared=bjs, **mixed_over)
+    st.autotune()
+    t, stats, _ = time_steps(st, q.u0, K, Wm)
+    st.close()
+    pm = M.precisions(q.precision, q.krylov, **MIXED_TOL[args.workload])
+    over64 = dict(rtol=pm.rtol, outer_tol=pm.outer_tol, bj_shared=bjs, refine_max=NONLINEAR_PASSES)
+    u64, _ = run_integration(M, r64, fmt, **over64)
+    e64 = float(np.linalg.norm(u64 - ref) / np.linalg.norm(ref))
+    st64 = M.from_problem(r64, fmt=fmt, **over64)
+    st64.autotune()
+    t64, _, _ = time_steps(st64, r64.u0, K, Wm)
+    st64.close()
+    out = {'problem': q.name, 'reaction': list(q.reaction), 'value': q.N * K / t,
+           'ms_per_step': t * 1e3 / K, 'err_vs_fp64_reference': err,
+           'passes_per_stage': stats['passes'], 'iters_per_stage': stats['iters'],
+           'reference_passes_per_stage': st_ref['passes'],
+           'fp64_at_mixed_tolerances': {'value': q.N * K / t64, 'ms_per_step': t64 * 1e3 / K,
+                                        'err_vs_fp64_reference': e64}}
+    log(f'semi-linear {q.name}: {out["value"]:.4e} DOF-steps/s, rel-L2 {err:.3e}, '
+        f'passes/stage {stats["passes"]}; FP64 at the same tolerances {q.N * K / t64:.4e}')
+    return out
+
+
 def host_info() -> dict:
     """The host the oracle ran on: core count, CPU model, BLAS threads, OMP_NUM_THREADS."""
     model = None
@@ -505,6 +556,11 @@ def main():
         log(f'adaptive block-Jacobi (tol {tol_a}): {adaptive["value"]:.4e} DOF-steps/s, '
             f'chunks {chunks}, rel-L2 {ea}')
 
+    # ---- the semi-linear variant (pointwise reaction) of the same workload ----
+    nonlin = None
+    if not args.no_fp64 and not args.quick and args.fmt == 'stencil':
+        nonlin = nonlinear_leg(M, args, fmt, bjs, mixed_over, K, Wm)
+
     # ---- side legs of the metric: batched problems and serving latency ----
     batch = None
     if not args.no_batch and not args.quick:
@@ -543,6 +599,7 @@ def main():
         'launch_shapes': launch,
         'other_bj_storage': other,
         'adaptive_bj': adaptive,
+        'nonlinear': nonlin,
         'speedup_vs_fp64_matched': (value / fp64['value']) if fp64 else None,
         'roofline': roofline,
         'cpu_baseline': cpu,

@@ -258,6 +258,24 @@ int32_t mprk_bind_static(mprk_handle *h, double *u_dev);
  * unaffected (it applies the operators alone).  Errors: MPRK_EINVAL (null handle). */
 int32_t mprk_set_forcing(mprk_handle *h, const double *g_dev);
 
+/* Pointwise cubic reaction: from the next step on, integrate the semi-linear
+ * du/dt = K u + g + R(u), R(u) = r1 u + r2 u^2 + r3 u^3 applied to each grid value (non-linear
+ * equations are the paper's first extension, Section "Summary and conclusions"; an implicit
+ * stage then is the non-linear system y - dt a_ii f(y) = rhs of eq. RKstep, Section "Runge--Kutta
+ * methods and mixed-precision").  The FP64 parts evaluate f with R (the outer residual and the
+ * explicit slopes k_i = K y_i + g + R(y_i)); the LP solves keep the stage matrix I - dt a_ii K
+ * and its preconditioner, so the outer defect-correction loop becomes a simplified Newton
+ * iteration whose Jacobian is the linear part.  Each pass contracts the stage error by about
+ * dt a_ii max|R'(y)| (on a dissipative K), so the stage needs about log(outer_tol) /
+ * log(dt a_ii max|R'|) passes: more than the defaults of mprk_precisions_default allow for
+ * linear problems (4 with FP64 CG), so raise refine_max with a reaction.  A stage that reaches
+ * refine_max counts as not converged (mprk_stats.missed; MPRK_ENOTCONV under strict); with
+ * dt a_ii max|R'| near or above 1 the iteration does not converge.  All three zero removes it.
+ * mprk_solve and mprk_apply are unaffected (they treat the linear systems alone).
+ * Errors: MPRK_EINVAL (null handle, non-finite coefficient), MPRK_EUNSUPPORTED (a non-zero
+ * reaction with refine_max = 0: the one-solve mode makes a single linearised solve). */
+int32_t mprk_set_reaction(mprk_handle *h, double r1, double r2, double r3);
+
 /* Advance u by nsteps time steps of eq. RKstep: per implicit stage the right-hand side and
  * the FP64 residual, the LP solve of eq. corelinear, the FP64 update and explicit evaluation
  * k_i = K y_i, then u_{n+1} = u_n + tau sum b_i k_i (Section "Implementation of the

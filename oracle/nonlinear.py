@@ -12,13 +12,17 @@ with the full tableau A: stage i solves the non-linear system
     y_i - sigma f(y_i) = rhs_i,   sigma = tau a_ii,   rhs_i = u_n + tau sum_{j<i} a_ij k_j,
 
 and k_i = f(y_i).  The oracle solves each stage by Newton's method in float64 with the exact
-Jacobian I - sigma (K + diag(R'(y))) (a sparse LU per iteration), from the start value rhs_i,
-until the update is below 1e-15 relative (at most 30 iterations; failing that it raises).
+Jacobian I - sigma (K + diag(R'(y))), from the start value rhs_i, until the update is below
+1e-15 relative (at most 30 iterations; failing that it raises).  Each Newton system is solved
+by a sparse LU ('splu', small grids) or by the oracle's own GMRES with block-Jacobi(8) to
+relative residual 1e-14 ('gmres', grids where the LU fill makes a factorisation per iteration
+too slow).
 
 The scalar form (scalar_integrate) is the same method for y' = lam y + R(y): the 3-D problem
 with a spatially constant state on a periodic grid reduces to it, because K maps constants to 0.
 
-Pins (tests/test_oracle_nonlinear.py): R = 0 reproduces the linear oracle; the scalar form
+Pins (tests/test_oracle_nonlinear.py): R = 0 reproduces the linear oracle; the two Newton
+solvers agree; the scalar form
 against the closed-form solutions of the Bernoulli equation y' = r1 y + r2 y^2 and of
 y' = r1 y + r3 y^3 with the tableau's convergence order on dt halving; a constant periodic state
 reproduces the scalar form at every point; each stage's residual is at rounding level and
@@ -30,6 +34,8 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
+
+from . import krylov
 
 NEWTON_TOL = 1e-15
 NEWTON_MAXIT = 30
@@ -55,7 +61,17 @@ def rhs_function(K, g, r):
     return f
 
 
-def newton_stage(K, sigma: float, rhs: np.ndarray, g, r, stats=None) -> np.ndarray:
+def _newton_solve(J, b, method: str):
+    if method == 'splu':
+        return spla.splu(J.tocsc()).solve(b)
+    inv = krylov.block_jacobi_inverses(J, 8)
+    d, _, _ = krylov.gmres(J, b, lambda v: krylov.block_jacobi_apply(inv, v, 8), restart=30,
+                           rtol=1e-14)
+    return d
+
+
+def newton_stage(K, sigma: float, rhs: np.ndarray, g, r, stats=None,
+                 method: str = 'splu') -> np.ndarray:
     """Solves y - sigma f(y) = rhs by Newton's method with the exact Jacobian."""
     f = rhs_function(K, g, r)
     n = rhs.size
@@ -63,8 +79,8 @@ def newton_stage(K, sigma: float, rhs: np.ndarray, g, r, stats=None) -> np.ndarr
     y = rhs.copy()
     for it in range(1, NEWTON_MAXIT + 1):
         F = y - sigma * f(y) - rhs
-        J = (eye - sigma * (K + sp.diags(reaction_derivative(y, r)))).tocsc()
-        d = spla.splu(J).solve(-F)
+        J = (eye - sigma * (K + sp.diags(reaction_derivative(y, r)))).tocsr()
+        d = _newton_solve(J, -F, method)
         y = y + d
         if np.linalg.norm(d) <= NEWTON_TOL * max(np.linalg.norm(y), 1e-300):
             if stats is not None:
@@ -73,7 +89,8 @@ def newton_stage(K, sigma: float, rhs: np.ndarray, g, r, stats=None) -> np.ndarr
     raise RuntimeError('Newton did not converge in the stage solve')
 
 
-def dirk_step(K, u: np.ndarray, tau: float, tab, r, g=None, stats=None) -> np.ndarray:
+def dirk_step(K, u: np.ndarray, tau: float, tab, r, g=None, stats=None,
+              method: str = 'splu') -> np.ndarray:
     """One step of eq. (RKstep) for du/dt = K u + g + R(u) with the full tableau A."""
     A, b = tab.A, tab.b
     f = rhs_function(K, g, r)
@@ -83,7 +100,7 @@ def dirk_step(K, u: np.ndarray, tau: float, tab, r, g=None, stats=None) -> np.nd
         for j in range(i):
             if A[i, j] != 0.0:
                 rhs += tau * A[i, j] * ks[j]
-        y = newton_stage(K, tau * A[i, i], rhs, g, r, stats) if A[i, i] != 0.0 else rhs
+        y = newton_stage(K, tau * A[i, i], rhs, g, r, stats, method) if A[i, i] != 0.0 else rhs
         ks.append(f(y))
     out = u.copy()
     for i in range(tab.s):
@@ -93,13 +110,14 @@ def dirk_step(K, u: np.ndarray, tau: float, tab, r, g=None, stats=None) -> np.nd
 
 
 def integrate(K, u0: np.ndarray, tau: float, nsteps: int, tab, r, g=None,
-              stats=None) -> np.ndarray:
-    """nsteps steps from u0 (flat, lexicographic); stats collects Newton iteration counts."""
+              stats=None, method: str = 'splu') -> np.ndarray:
+    """nsteps steps from u0 (flat, lexicographic); stats collects Newton iteration counts;
+    method: the Newton systems' solver, 'splu' or 'gmres'."""
     u = np.asarray(u0, dtype=np.float64).ravel().copy()
     K = sp.csr_matrix(K)
     gf = None if g is None else np.asarray(g, dtype=np.float64).ravel()
     for _ in range(nsteps):
-        u = dirk_step(K, u, tau, tab, r, g=gf, stats=stats)
+        u = dirk_step(K, u, tau, tab, r, g=gf, stats=stats, method=method)
     return u
 
 

@@ -125,6 +125,7 @@ _sig = {
     'mprk_solve': (C.c_int32, [_P, C.c_int32, _P, _P, C.POINTER(mprk_solve_info)]),
     'mprk_apply': (C.c_int32, [_P, C.c_int32, C.c_int32, _P, _P]),
     'mprk_set_forcing': (C.c_int32, [_P, _P]),
+    'mprk_set_reaction': (C.c_int32, [_P, C.c_double, C.c_double, C.c_double]),
     'mprk_get_state': (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     'mprk_set_state': (C.c_int32, [_P, C.c_double, C.c_int64]),
     'mprk_stats_sync': (C.c_int32, [_P, C.POINTER(mprk_stats)]),
@@ -219,6 +220,10 @@ def mprk_solve(h: int, stage: int, rhs_ptr: int, x_ptr: int):
 
 def mprk_set_forcing(h: int, g_ptr: int) -> None:
     check(lib.mprk_set_forcing(_P(h), _P(g_ptr) if g_ptr else None), 'mprk_set_forcing')
+
+
+def mprk_set_reaction(h: int, r1: float, r2: float, r3: float) -> None:
+    check(lib.mprk_set_reaction(_P(h), float(r1), float(r2), float(r3)), 'mprk_set_reaction')
 
 
 def mprk_apply(h: int, op: int, stage: int, x_ptr: int, y_ptr: int) -> None:

@@ -64,6 +64,16 @@ struct Csr {
   const int* col;
 };
 
+// The terms of f(y) = K y + g + R(y) besides the operator, evaluated in FP64 with it: the
+// constant forcing g (N doubles, or null) and the pointwise reaction R(y) = r1 y + r2 y^2 +
+// r3 y^3 (react = 0: none).
+struct FTerms {
+  const double* g;
+  double r1, r2, r3;
+  int react;
+  __device__ __forceinline__ double R(double y) const { return y * (r1 + y * (r2 + y * r3)); }
+};
+
 constexpr int MAXPASS = 32;  // passes whose iteration counts are recorded
 
 // Kernel classes counted for profiling (launches that did work).

@@ -221,11 +221,11 @@ __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<doubl
                                                   const double* __restrict__ y,
                                                   const double* __restrict__ rhs,
                                                   double* __restrict__ kout,
-                                                  double* __restrict__ res,
-                                                  const double* __restrict__ force, SolveCfg cfg,
-                                                  Ctl* ctl, Red red) {
+                                                  double* __restrict__ res, FTerms fx,
+                                                  SolveCfg cfg, Ctl* ctl, Red red) {
   if (ctl->outer_done) return;
   count_work(ctl, KC_RESIDUAL);
+  const double* __restrict__ force = fx.g;
   const int L = xcd_block(ln.G);
   double acc[3] = {0.0, 0.0, 0.0};
   for (int it = 0; it < ln.nit; ++it) {
@@ -251,6 +251,10 @@ __global__ __launch_bounds__(TPB) void k_residual(Launch ln, Geo geo, Coef<doubl
 #pragma unroll
       for (int v = 0; v < VEC; ++v) ky[v] += fv[v];
     }
+    if (fx.react) {  // reaction: f(y) = K y + g + R(y); the outer loop is then a simplified Newton
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) ky[v] += fx.R(yc[v]);
+    }
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       rr[v] = b[v] - yc[v] + cfg.sigma * ky[v];
@@ -272,6 +276,7 @@ template <int VEC>
 struct ResidualBody {
   const double* __restrict__ rhs;
   const double* __restrict__ force;
+  FTerms fx;
   double* __restrict__ kout;
   double* __restrict__ res;
   double sigma;
@@ -293,6 +298,7 @@ struct ResidualBody {
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       ky[v] = force ? kin[v] + fc[v] : kin[v];
+      if (fx.react) ky[v] += fx.R(yc[v]);
       rr[v] = bc[v] - yc[v] + sigma * ky[v];
       acc[0] += rr[v] * rr[v];
       acc[1] += bc[v] * bc[v];
@@ -309,14 +315,13 @@ __global__ __launch_bounds__(TPB) void k_residual_zm(ZLaunch zl, Geo geo, Coef<d
                                                      const double* __restrict__ y,
                                                      const double* __restrict__ rhs,
                                                      double* __restrict__ kout,
-                                                     double* __restrict__ res,
-                                                     const double* __restrict__ force,
+                                                     double* __restrict__ res, FTerms fx,
                                                      SolveCfg cfg, Ctl* ctl, Red red) {
   if (ctl->outer_done) return;
   count_work(ctl, KC_RESIDUAL);
   extern __shared__ double zm_lds[];
   const int L = xcd_block(zl.G);
-  ResidualBody<VEC> body{rhs, force, kout, res, cfg.sigma, {}, {}, {}, {}, {0.0, 0.0, 0.0}};
+  ResidualBody<VEC> body{rhs, fx.g, fx, kout, res, cfg.sigma, {}, {}, {}, {}, {0.0, 0.0, 0.0}};
   auto src = [&](int e, double (&o)[VEC], bool) { loadv<double, double, VEC>(y + e, o); };
   zmarch<double, VEC>(geo, K, zl, L, src, body, zm_lds);
   __shared__ double tot[3];
@@ -324,13 +329,15 @@ __global__ __launch_bounds__(TPB) void k_residual_zm(ZLaunch zl, Geo geo, Coef<d
   if (threadIdx.x == 0) residual_decision(tot, cfg, ctl);
 }
 
-// y = K x (mode 0) or y = x - sigma K x (mode 1), FP64, no reduction (verification access).
+// y = K x (mode 0) or y = x - sigma K x (mode 1), FP64, no reduction (verification access);
+// mode 0 adds the terms fx (an explicit stage's slope f(x) = K x + g + R(x)).
 template <int VEC, int FMT>
 __global__ __launch_bounds__(TPB) void k_apply64(Launch ln, Geo geo, Coef<double> K, Csr csr,
                                                  const double* __restrict__ kval,
                                                  const double* __restrict__ x,
                                                  double* __restrict__ y, double sigma, int mode,
-                                                 const double* __restrict__ force) {
+                                                 FTerms fx) {
+  const double* __restrict__ force = fx.g;
   const int L = xcd_block(ln.G);
   for (int it = 0; it < ln.nit; ++it) {
     const int g0 = (L * ln.nit + it) * TPB;
@@ -349,6 +356,10 @@ __global__ __launch_bounds__(TPB) void k_apply64(Launch ln, Geo geo, Coef<double
       loadv<double, double, VEC>(force + g * VEC, fv);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) kx[v] += fv[v];
+    }
+    if (fx.react) {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) kx[v] += fx.R(xc[v]);
     }
     if (mode == 1) {
 #pragma unroll

@@ -1082,7 +1082,7 @@ BJDesc mprk_handle::bj_desc(int si) const {
 }
 
 int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* kout,
-                                 const double* force) {
+                                 const FTerms& fx) {
   const SolveCfg& cfg = cfgs[si];
   Ctl* ctl = (Ctl*)(ws + o_ctl);
   const Red rd = red();
@@ -1091,16 +1091,16 @@ int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* k
   const double* kval = (const double*)(ws + o_kval);
   if (op.format == MPRK_FMT_CSR)
     PLAUNCH(KC_RESIDUAL, (k_residual<1, 1>), dim3(ln_row_red.G), dim3(TPB), 0, stream, ln_row_red, geo, Kc, csr,
-                       kval, y, rhs, kout, res, force, cfg, ctl, rd);
+                       kval, y, rhs, kout, res, fx, cfg, ctl, rd);
   else if (zm_lz > 0)  // (zm_lz > 0 implies vec == 4)
     PLAUNCH(KC_RESIDUAL, (k_residual_zm<4>), dim3(zl_res.G), dim3(TPB), zmarch_lds(geo, zl_res, 8), stream,
-            zl_res, geo, Kc, y, rhs, kout, res, force, cfg, ctl, rd);
+            zl_res, geo, Kc, y, rhs, kout, res, fx, cfg, ctl, rd);
   else if (vec == 4)
     PLAUNCH(KC_RESIDUAL, (k_residual<4, 0>), dim3(ln_vec_red.G), dim3(TPB), 0, stream, ln_vec_red, geo, Kc, csr,
-                       kval, y, rhs, kout, res, force, cfg, ctl, rd);
+                       kval, y, rhs, kout, res, fx, cfg, ctl, rd);
   else
     PLAUNCH(KC_RESIDUAL, (k_residual<1, 0>), dim3(ln_vec_red.G), dim3(TPB), 0, stream, ln_vec_red, geo, Kc, csr,
-                       kval, y, rhs, kout, res, force, cfg, ctl, rd);
+                       kval, y, rhs, kout, res, fx, cfg, ctl, rd);
   HIPCHK(hipGetLastError());
   return MPRK_OK;
 }
@@ -1113,7 +1113,7 @@ int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* k
 // mode has no later pass to absorb a solve cut short, so there the predicted count is only the
 // first chunk: the host keeps enqueuing chunks until the device reports the solve finished.
 int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, double* kout,
-                           const double* force) {
+                           const FTerms& fx) {
   int rc = update_hist(slot);
   if (rc) return rc;
   const StageHist H = hist[slot];
@@ -1128,7 +1128,7 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
   const int maxp = cfg.maxit;
   const int chunk = cg ? cg_chunk : gm_chunk;
   for (int pass = 0; pass <= P; ++pass) {
-    rc = launch_residual(si, rhs, y, kout, force);
+    rc = launch_residual(si, rhs, y, kout, fx);
     if (rc) return rc;
     if (pass == P) break;
     const bool predicted = H.valid && pass < H.passes;
@@ -1224,11 +1224,11 @@ int mprk_handle::enqueue_step(bool first_of_call) {
       PLAUNCH(KC_STAGE_RHS, (k_stage_rhs<1>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, u, a, rhs, y, ctl, reset);
     HIPCHK(hipGetLastError());
     if (!implicit_[i]) {
-      int rc = launch_apply64(y, kvec(i), 0.0, 0, force);
+      int rc = launch_apply64(y, kvec(i), 0.0, 0, fterms());
       if (rc) return rc;
       continue;
     }
-    int rc = run_solve(sig_idx[i], i, rhs, y, kvec(i), force);
+    int rc = run_solve(sig_idx[i], i, rhs, y, kvec(i), fterms());
     if (rc) return rc;
     if (need_keps) {
       const double inv = 1.0 / cfgs[sig_idx[i]].sigma;
@@ -1255,18 +1255,18 @@ int mprk_handle::enqueue_step(bool first_of_call) {
 }
 
 int mprk_handle::launch_apply64(const double* x, double* y, double sigma, int mode,
-                                const double* force) {
+                                const FTerms& fx) {
   const Csr csr{(const int*)(ws + o_rowptr), (const int*)(ws + o_col)};
   const double* kval = (const double*)(ws + o_kval);
   if (op.format == MPRK_FMT_CSR)
     PLAUNCH(KC_APPLY64, (k_apply64<1, 1>), dim3(ln_row.G), dim3(TPB), 0, stream, ln_row, geo, Kc, csr, kval,
-                       x, y, sigma, mode, force);
+                       x, y, sigma, mode, fx);
   else if (vec == 4)
     PLAUNCH(KC_APPLY64, (k_apply64<4, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr, kval,
-                       x, y, sigma, mode, force);
+                       x, y, sigma, mode, fx);
   else
     PLAUNCH(KC_APPLY64, (k_apply64<1, 0>), dim3(ln_vec.G), dim3(TPB), 0, stream, ln_vec, geo, Kc, csr, kval,
-                       x, y, sigma, mode, force);
+                       x, y, sigma, mode, fx);
   HIPCHK(hipGetLastError());
   return MPRK_OK;
 }
@@ -1396,7 +1396,7 @@ extern "C" int32_t mprk_solve(mprk_handle* h, int32_t stage, const double* rhs_d
                        x_dev, ctl, RESET_STAGE | RESET_CALL);
   HIPCHK(hipGetLastError());
   int rc = h->run_solve(h->sig_idx[stage], MPRK_MAX_STAGES, rhs, x_dev, (double*)(h->ws + h->o_scr),
-                        nullptr);
+                        FTerms{});
   if (rc) return rc;
   CtlHead hd;
   HIPCHK(hipMemcpyAsync(&hd, ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, h->stream));
@@ -1417,6 +1417,26 @@ extern "C" int32_t mprk_solve(mprk_handle* h, int32_t stage, const double* rhs_d
 extern "C" int32_t mprk_set_forcing(mprk_handle* h, const double* g_dev) {
   if (!h) return set_error(MPRK_EINVAL, "handle is NULL");
   h->force = g_dev;
+  return MPRK_OK;
+}
+
+// The stage systems become y - sigma (K y + g + R(y)) = rhs: the FP64 residual and the explicit
+// evaluations take R, the LP systems keep I - sigma K, so the outer defect-correction loop is a
+// simplified Newton iteration whose Jacobian is the linear part.  The one-solve mode has no
+// such loop and is refused.
+extern "C" int32_t mprk_set_reaction(mprk_handle* h, double r1, double r2, double r3) {
+  if (!h) return set_error(MPRK_EINVAL, "handle is NULL");
+  if (!std::isfinite(r1) || !std::isfinite(r2) || !std::isfinite(r3))
+    return set_error(MPRK_EINVAL, "reaction coefficients must be finite");
+  const bool on = r1 != 0.0 || r2 != 0.0 || r3 != 0.0;
+  if (on && h->prec.refine_max == 0)
+    return set_error(MPRK_EUNSUPPORTED,
+                     "a reaction needs the FP64 outer loop (refine_max > 0): the one-solve mode "
+                     "would stop after a single linearised solve");
+  h->react[0] = r1;
+  h->react[1] = r2;
+  h->react[2] = r3;
+  h->react_on = on;
   return MPRK_OK;
 }
 
@@ -1675,7 +1695,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
                            RESET_STAGE | RESET_CALL);
       hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.23, 0.017, x64);
       if (hipGetLastError() != hipSuccess) { rc = MPRK_EDEVICE; break; }
-      rc = h->launch_residual(si, rhs, x64, y64, nullptr);
+      rc = h->launch_residual(si, rhs, x64, y64, FTerms{});
       if (rc) break;
       if ((cg ? h->eng->cg_begin(c, cfg, dinv) : h->eng->gm_begin(c, cfg, dinv)) != hipSuccess) { rc = MPRK_EDEVICE; break; }
       if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = MPRK_EDEVICE; break; }
@@ -1717,7 +1737,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
       hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.23, 0.017, x64);
       if (hipGetLastError() != hipSuccess) { rc = MPRK_EDEVICE; break; }
       float ms;
-      time_it([&]() { return h->launch_residual(si, rhs, x64, y64, nullptr); }, &ms);
+      time_it([&]() { return h->launch_residual(si, rhs, x64, y64, FTerms{}); }, &ms);
       if (rc) break;
       if (ms < bz) {
         bz = ms;
@@ -1766,7 +1786,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
                                rhs, x64, ctl, RESET_STAGE | RESET_CALL);
           hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.23, 0.017, x64);
           if (hipGetLastError() != hipSuccess) { rc = MPRK_EDEVICE; break; }
-          rc = h->launch_residual(si, rhs, x64, y64, nullptr);
+          rc = h->launch_residual(si, rhs, x64, y64, FTerms{});
           if (rc) break;
           if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = MPRK_EDEVICE; break; }
           if (h->eng->gm_begin(c, cfg, dinv) != hipSuccess) { rc = MPRK_EDEVICE; break; }

@@ -95,6 +95,12 @@ struct mprk_handle {
   size_t o_fdm_Qw[2] = {};
   size_t ws_bytes = 0;
   const double* force = nullptr;  // constant forcing g (caller-owned, N doubles) or null
+  double react[3] = {0.0, 0.0, 0.0};  // reaction R(u) = r1 u + r2 u^2 + r3 u^3 of the steps
+  bool react_on = false;
+  // the FP64 terms of f besides K of the time steps (mprk_step)
+  mprk::FTerms fterms() const {
+    return mprk::FTerms{force, react[0], react[1], react[2], react_on ? 1 : 0};
+  }
   // binding
   double* u = nullptr;
   char* ws = nullptr;
@@ -149,9 +155,10 @@ struct mprk_handle {
   int update_hist(int slot);
   mprk::BJDesc bj_desc(int si) const;
   mprk::Red red() const;
-  int launch_residual(int si, const double* rhs, double* y, double* kout, const double* force);
-  int launch_apply64(const double* x, double* y, double sigma, int mode, const double* force = nullptr);
-  int run_solve(int si, int slot, const double* rhs, double* y, double* kout, const double* force);
+  int launch_residual(int si, const double* rhs, double* y, double* kout, const mprk::FTerms& fx);
+  int launch_apply64(const double* x, double* y, double sigma, int mode,
+                     const mprk::FTerms& fx = mprk::FTerms{});
+  int run_solve(int si, int slot, const double* rhs, double* y, double* kout, const mprk::FTerms& fx);
   int enqueue_step(bool first_of_call);
   int sync_counters();
   int rebase_missed();

@@ -91,6 +91,11 @@ class Stepper:
         torch.cuda.synchronize(self.device)
         A.mprk_set_forcing(self.h, self.g.data_ptr())
 
+    def set_reaction(self, r1: float = 0.0, r2: float = 0.0, r3: float = 0.0) -> None:
+        """Pointwise reaction R(u) = r1 u + r2 u^2 + r3 u^3 of du/dt = K u + g + R(u); all zero
+        removes it."""
+        A.mprk_set_reaction(self.h, r1, r2, r3)
+
     def step(self, nsteps: int = 1, check: bool = True):
         rc, st = A.mprk_step(self.h, nsteps, True)
         if check:
@@ -144,6 +149,8 @@ def from_problem(p, fmt: int = A.FMT_STENCIL, prec=None, device: str = 'cuda:0',
         s.set_u(p.u0)
     if getattr(p, 'forcing', None) is not None:
         s.set_forcing(p.forcing)
+    if getattr(p, 'reaction', None) is not None:
+        s.set_reaction(*p.reaction)
     return s
 
 

@@ -2,7 +2,7 @@
 import numpy as np
 
 import workloads as W
-from oracle import closed_form, dirk, operators, tableaus
+from oracle import closed_form, dirk, nonlinear, operators, tableaus
 
 
 def oracle_K(shape, bc, kind, diff, b):
@@ -20,6 +20,22 @@ def reference_solution(p, method='closed'):
         return closed_form.evolve(p.u0, p.kind, p.bc, p.diff, p.b, p.dt, p.nsteps, tab)
     K = oracle_K((p.n,) * 3, p.bc, p.kind, p.diff, p.b)
     return dirk.integrate(K, p.u0, p.dt, p.nsteps, tab, method).reshape(p.u0.shape)
+
+
+def reference_nonlinear(p, shape=None):
+    """FP64 oracle u_N (Newton stage solves) of a workloads.Problem with a reaction; the Newton
+    systems go to the oracle's GMRES above 4096 unknowns (sparse LU fill grows too fast)."""
+    shape = shape or (p.n,) * 3
+    K = oracle_K(shape, p.bc, p.kind, p.diff, p.b)
+    g = None if p.forcing is None else np.ravel(p.forcing)
+    method = 'splu' if np.prod(shape) <= 4096 else 'gmres'
+    return nonlinear.integrate(K, p.u0, p.dt, p.nsteps, tableaus.by_name(p.tableau), p.reaction,
+                               g=g, method=method).reshape(np.shape(p.u0))
+
+
+def reference_scalar(p, y0):
+    """The oracle's scalar form y' = R(y) (+ a constant forcing value) over the same steps."""
+    return nonlinear.scalar_integrate(y0, p.dt, p.nsteps, tableaus.by_name(p.tableau), p.reaction)
 
 
 def rel_l2(a, b):

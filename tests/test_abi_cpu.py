@@ -175,6 +175,25 @@ def test_central_operator_and_forcing_entry_points_on_host():
     assert A.lib.mprk_set_forcing(None, None) == A.EINVAL
 
 
+def test_reaction_entry_point_is_validated_on_host():
+    rc, h = _create()
+    assert rc == A.OK, A.mprk_last_error()
+    assert A.lib.mprk_set_reaction(h, 1.0, -2.0, -3.0) == A.OK
+    assert A.lib.mprk_set_reaction(h, 0.0, 0.0, 0.0) == A.OK
+    assert A.lib.mprk_set_reaction(h, float('nan'), 0.0, 0.0) == A.EINVAL
+    assert A.lib.mprk_set_reaction(h, 0.0, float('inf'), 0.0) == A.EINVAL
+    A.lib.mprk_destroy(h)
+    assert A.lib.mprk_set_reaction(None, 1.0, 0.0, 0.0) == A.EINVAL
+    # the one-solve mode has no outer loop to iterate the non-linear stage equation
+    p = A.mprk_precisions_default(A.FP32, A.CG)
+    p.refine_max = 0
+    rc, h = _create(prec=p)
+    assert rc == A.OK, A.mprk_last_error()
+    assert A.lib.mprk_set_reaction(h, 1.0, 0.0, 0.0) == A.EUNSUPPORTED
+    assert A.lib.mprk_set_reaction(h, 0.0, 0.0, 0.0) == A.OK
+    A.lib.mprk_destroy(h)
+
+
 def test_compressed_basis_precisions_are_accepted_for_single_problems():
     # FP64 arithmetic over FP16 / FP32 storage (compressed-basis Krylov); the batched form
     # keeps FP32 arithmetic for LP storage

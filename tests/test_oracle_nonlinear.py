@@ -22,6 +22,16 @@ def test_zero_reaction_is_the_linear_oracle(kind, bc, shape):
     assert D.relative_l2(got, lin) < 1e-13
 
 
+@pytest.mark.parametrize("kind,bc,shape", [(0, O.DIRICHLET, (7, 6, 5)), (1, O.PERIODIC, (6, 5, 6))])
+def test_newton_solvers_agree(kind, bc, shape):
+    K = O.operator(shape, bc, kind, 0.5, (0.9, 0.4, -0.3))
+    u0 = _field(shape, 14)
+    r = (2.0, -1.0, -3.0)
+    a = NL.integrate(K, u0, 0.01, 4, T.sdirk3(), r, method='splu')
+    b = NL.integrate(K, u0, 0.01, 4, T.sdirk3(), r, method='gmres')
+    assert D.relative_l2(b, a) < 1e-13
+
+
 def _order_errors(tab, exact, r, y0, t_end, taus):
     return [abs(NL.scalar_integrate(y0, tau, int(round(t_end / tau)), tab, r) - exact)
             for tau in taus]

@@ -85,6 +85,7 @@ class Problem:
     precond: str = 'bj'        # 'none' | 'bj' | 'fdm'
     meta: dict = dataclasses.field(default_factory=dict)
     forcing: np.ndarray = None # constant source g of du/dt = K u + g, shape (n, n, n), or None
+    reaction: tuple = None     # (r1, r2, r3) of du/dt = K u + g + r1 u + r2 u^2 + r3 u^3, or None
 
     @property
     def N(self) -> int:
@@ -118,6 +119,33 @@ def advdiff_bump(n: int = 256, seed: int = 3, nsteps: int = 20, dt: float = 2e-3
     return Problem(f'advdiff_bump_{n}', n, PERIODIC, ADVDIFF, nu, tuple(b), 'SDIRK3',
                    dt, nsteps, u0, precision='fp16', krylov='gmres', precond='bj',
                    meta={'center': c, 'seed': seed})
+
+
+def heat_allen_cahn(n: int = 128, seed: int = 2, nsteps: int = 20, dt: float = 5e-4,
+                    rho: float = 50.0) -> Problem:
+    """heat_modes' state and solver with the Allen-Cahn reaction rho (u - u^3), amplitudes
+    scaled so that the cubic term matters (max |u0| = 1)."""
+    p = heat_modes(n, seed, nsteps, dt)
+    p.u0 = p.u0 / np.max(np.abs(p.u0))
+    p.name = f'heat_allen_cahn_{n}'
+    p.reaction = (rho, 0.0, -rho)
+    p.meta['rho'] = rho
+    return p
+
+
+def advdiff_fisher(n: int = 256, seed: int = 3, nsteps: int = 20, dt: float = 2e-3,
+                   rho: float = 20.0) -> Problem:
+    """advdiff_bump's state and solver with the Fisher-KPP reaction rho u (1 - u)."""
+    p = advdiff_bump(n, seed, nsteps, dt)
+    p.name = f'advdiff_fisher_{n}'
+    p.reaction = (rho, -rho, 0.0)
+    p.meta['rho'] = rho
+    return p
+
+
+def uniform_state(n: int, value: float) -> np.ndarray:
+    """A spatially constant field, shape (n, n, n)."""
+    return np.full((n, n, n), float(value))
 
 
 def paper_heat(n: int = 128, tableau: str = 'MID1', dt: float = 1.0 / 80, t_end: float = 0.1,
