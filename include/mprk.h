@@ -191,6 +191,8 @@ typedef struct {
                                        after the last allowed pass, or, with refine_max = 0,
                                        an LP solve stopped by maxit, the GMRES cycle length or
                                        a breakdown */
+  int32_t graph_steps;              /* steps of the last mprk_step call replayed from the step
+                                       graph (mprk_set_step_graph); 0 when steered */
 } mprk_stats;
 
 typedef struct { int32_t iters, passes, converged; double resid; } mprk_solve_info;
@@ -257,6 +259,23 @@ int32_t mprk_bind_static(mprk_handle *h, double *u_dev);
  * valid and unchanged while steps or solves run.  NULL removes the forcing.  mprk_apply is
  * unaffected (it applies the operators alone).  Errors: MPRK_EINVAL (null handle). */
 int32_t mprk_set_forcing(mprk_handle *h, const double *g_dev);
+
+/* Step graph (eq. RKstep's time loop, Section "Implementation of the Mixed-precision
+ * Runge--Kutta methods"): with enable != 0, mprk_step runs its steps by replaying one captured
+ * hipGraph of a whole step on the bound stream, with no host wait between steps, once every
+ * implicit stage has a solve history from an earlier steered step (the first call, or the
+ * first steps after a change, run steered).  The graph enqueues, per stage, the passes and
+ * Krylov iterations the stage's last steered solve needed (each plus the usual margin) and one
+ * spare pass; a stage that needs more misses inside the graph, its step is not combined and the
+ * call's remaining steps run steered from there (which also records new histories, and the
+ * graph is captured again on a later call), so the results are those of steered stepping.
+ * Launches are the same kernels; what the graph saves is the host's launch and polling cost,
+ * which dominates on small grids.  The graph is captured on a stream the library creates and
+ * is rebuilt after mprk_bind, mprk_set_forcing, mprk_set_reaction or mprk_autotune.  Not used
+ * with refine_max = 0 (the one-solve mode steers every chunk) or while profiling is on.
+ * enable = 0 releases the graph.  mprk_stats.graph_steps counts the replayed steps.
+ * Errors: MPRK_EINVAL (null handle); capture failures surface from mprk_step as MPRK_EDEVICE. */
+int32_t mprk_set_step_graph(mprk_handle *h, int32_t enable);
 
 /* Pointwise cubic reaction: from the next step on, integrate the semi-linear
  * du/dt = K u + g + R(u), R(u) = r1 u + r2 u^2 + r3 u^3 applied to each grid value (non-linear

@@ -65,7 +65,7 @@ class mprk_stats(C.Structure):
                 ('iters', C.c_int32 * MAX_STAGES), ('passes', C.c_int32 * MAX_STAGES),
                 ('resid', C.c_double * MAX_STAGES), ('converged', C.c_int32 * MAX_STAGES),
                 ('total_iters', C.c_int64), ('total_passes', C.c_int64), ('nonfinite', C.c_int32),
-                ('missed', C.c_int32)]
+                ('missed', C.c_int32), ('graph_steps', C.c_int32)]
 
     def as_dict(self):
         s = self.stages
@@ -73,7 +73,8 @@ class mprk_stats(C.Structure):
                 'iters': list(self.iters[:s]), 'passes': list(self.passes[:s]),
                 'resid': list(self.resid[:s]), 'converged': list(self.converged[:s]),
                 'total_iters': self.total_iters, 'total_passes': self.total_passes,
-                'nonfinite': self.nonfinite, 'missed': self.missed}
+                'nonfinite': self.nonfinite, 'missed': self.missed,
+                'graph_steps': self.graph_steps}
 
 
 class mprk_solve_info(C.Structure):
@@ -126,6 +127,7 @@ _sig = {
     'mprk_apply': (C.c_int32, [_P, C.c_int32, C.c_int32, _P, _P]),
     'mprk_set_forcing': (C.c_int32, [_P, _P]),
     'mprk_set_reaction': (C.c_int32, [_P, C.c_double, C.c_double, C.c_double]),
+    'mprk_set_step_graph': (C.c_int32, [_P, C.c_int32]),
     'mprk_get_state': (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     'mprk_set_state': (C.c_int32, [_P, C.c_double, C.c_int64]),
     'mprk_stats_sync': (C.c_int32, [_P, C.POINTER(mprk_stats)]),
@@ -224,6 +226,10 @@ def mprk_set_forcing(h: int, g_ptr: int) -> None:
 
 def mprk_set_reaction(h: int, r1: float, r2: float, r3: float) -> None:
     check(lib.mprk_set_reaction(_P(h), float(r1), float(r2), float(r3)), 'mprk_set_reaction')
+
+
+def mprk_set_step_graph(h: int, enable: bool) -> None:
+    check(lib.mprk_set_step_graph(_P(h), 1 if enable else 0), 'mprk_set_step_graph')
 
 
 def mprk_apply(h: int, op: int, stage: int, x_ptr: int, y_ptr: int) -> None:

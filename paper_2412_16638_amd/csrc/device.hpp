@@ -75,6 +75,7 @@ struct FTerms {
 };
 
 constexpr int MAXPASS = 32;  // passes whose iteration counts are recorded
+constexpr int MAXSTG = 8;    // stages whose head records a replayed step keeps on the device
 
 // Kernel classes counted for profiling (launches that did work).
 enum KClass {
@@ -126,6 +127,7 @@ struct Ctl {
   int pass_iters[MAXPASS];           // Krylov iterations of each pass of the current stage
   long long worked[KC_COUNT];        // launches per kernel class that did work (profiling)
   long long units[KC_COUNT];         // basis vectors touched (GMRES kernels), else launches
+  long long srec[MAXSTG][8];         // steps replayed from a graph: each stage's final head
 };
 
 __device__ __forceinline__ void count_work(Ctl* ctl, int kc, int units = 1) {

@@ -369,6 +369,19 @@ __global__ __launch_bounds__(TPB) void k_apply64(Launch ln, Geo geo, Coef<double
   }
 }
 
+// Steps replayed from a graph keep each stage's final head record (the 64-byte prefix of Ctl)
+// on the device; the steered path copies it to the host after each stage instead.
+static __global__ void k_stage_snapshot(Ctl* ctl, int slot) {
+  const long long* head = reinterpret_cast<const long long*>(ctl);
+  if (threadIdx.x < 8) ctl->srec[slot][threadIdx.x] = head[threadIdx.x];
+}
+
+// The replays of a call start with the strict halt of an earlier call released (the steered
+// path does this in its first stage-rhs launch).
+static __global__ void k_release_halt(Ctl* ctl) {
+  if (threadIdx.x == 0) ctl->halt = 0;
+}
+
 // k^eps = (y - rhs) / sigma : the low-precision slope of an implicit stage.
 template <int VEC>
 __global__ __launch_bounds__(TPB) void k_keps(Launch ln, const double* __restrict__ y,

@@ -760,6 +760,8 @@ mprk_handle::~mprk_handle() {
   }
   if (slots) (void)hipHostFree(slots);
   if (rec_iters) (void)hipHostFree(rec_iters);
+  graph_drop();
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
 extern "C" int64_t mprk_workspace_bytes(const mprk_handle* h) {
@@ -824,6 +826,7 @@ EngineCtx mprk_handle::ctx() const {
 // Attach u and a workspace and run the setup kernels.  Allocates no device or pinned memory
 // itself (the pinned records exist once make_device_resources has run).
 static int bind_impl(mprk_handle* h, double* u_dev, void* workspace_dev) {
+  h->graph_epoch += 1;  // new state and workspace addresses
   h->u = u_dev;
   h->ws = (char*)workspace_dev;
   h->bound = false;
@@ -1081,9 +1084,8 @@ BJDesc mprk_handle::bj_desc(int si) const {
                 B.mode == 4 ? (const long long*)(ws + B.o_aoff) : nullptr};
 }
 
-int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* kout,
+int mprk_handle::launch_residual(const SolveCfg& cfg, const double* rhs, double* y, double* kout,
                                  const FTerms& fx) {
-  const SolveCfg& cfg = cfgs[si];
   Ctl* ctl = (Ctl*)(ws + o_ctl);
   const Red rd = red();
   double* res = (double*)(ws + o_res);
@@ -1114,6 +1116,7 @@ int mprk_handle::launch_residual(int si, const double* rhs, double* y, double* k
 // first chunk: the host keeps enqueuing chunks until the device reports the solve finished.
 int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, double* kout,
                            const FTerms& fx) {
+  if (capturing) return run_solve_graph(si, slot, rhs, y, kout, fx);
   int rc = update_hist(slot);
   if (rc) return rc;
   const StageHist H = hist[slot];
@@ -1128,7 +1131,7 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
   const int maxp = cfg.maxit;
   const int chunk = cg ? cg_chunk : gm_chunk;
   for (int pass = 0; pass <= P; ++pass) {
-    rc = launch_residual(si, rhs, y, kout, fx);
+    rc = launch_residual(cfg, rhs, y, kout, fx);
     if (rc) return rc;
     if (pass == P) break;
     const bool predicted = H.valid && pass < H.passes;
@@ -1186,6 +1189,45 @@ int mprk_handle::run_solve(int si, int slot, const double* rhs, double* y, doubl
     else HIPCHK(eng->gm_finish(c, cfg, dinv, enq));
   }
   return stage_record(slot);
+}
+
+// The stage inside a step graph: the passes and Krylov iterations of the stage's last steered
+// solve (each pass its recorded count plus the usual margin) and one spare pass, all enqueued
+// without a host wait.  The pass limit is what was enqueued, and a stage that misses its
+// tolerance within it holds its step and halts the call's remaining replays (the strict device
+// rule), so that the host can finish the call on the steered path with the same results.
+int mprk_handle::run_solve_graph(int si, int slot, const double* rhs, double* y, double* kout,
+                                 const FTerms& fx) {
+  const StageHist& H = hist[slot];
+  SolveCfg cfg = cfgs[si];
+  const int P = std::min(cfg.max_passes, H.passes + 1);
+  cfg.max_passes = P;
+  cfg.strict = 1;
+  EngineCtx c = ctx();
+  c.y = y;
+  c.fdm_sigma = cfg.sigma;
+  const BJDesc dinv = bj_desc(si);
+  const Coef<double> Mc = stage_coef(Kc, cfg.sigma);
+  const bool cg = prec.krylov == MPRK_CG;
+  int most = 1;
+  for (int p = 0; p < H.passes; ++p) most = std::max(most, H.iters[p]);
+  for (int pass = 0; pass <= P; ++pass) {
+    int rc = launch_residual(cfg, rhs, y, kout, fx);
+    if (rc) return rc;
+    if (pass == P) break;
+    if (cg) HIPCHK(eng->cg_begin(c, cfg, dinv));
+    else HIPCHK(eng->gm_begin(c, cfg, dinv));
+    const int n = std::min(cfg.maxit, (pass < H.passes ? H.iters[pass] : most) + predict_margin);
+    for (int k = 0; k < n; ++k) {
+      if (cg) HIPCHK(eng->cg_iter(c, cfg, Mc, dinv, k));
+      else HIPCHK(eng->gm_iter(c, cfg, Mc, dinv, k));
+    }
+    if (cg) HIPCHK(eng->cg_finish(c));
+    else HIPCHK(eng->gm_finish(c, cfg, dinv, n));
+  }
+  hipLaunchKernelGGL(k_stage_snapshot, dim3(1), dim3(64), 0, stream, (Ctl*)(ws + o_ctl), slot);
+  HIPCHK(hipGetLastError());
+  return MPRK_OK;
 }
 
 int mprk_handle::enqueue_step(bool first_of_call) {
@@ -1292,6 +1334,7 @@ void mprk_handle::fill_stats(mprk_stats* st) {
   st->total_passes = life_passes;
   st->nonfinite = last_nonfinite;
   st->missed = last_missed;
+  st->graph_steps = graph_steps_last;
 }
 
 void mprk_handle::set_gm_form(int f, int lz) {
@@ -1322,6 +1365,96 @@ void mprk_handle::set_residual_tiles(int lz) {
   if (lz > 0) zl_res = make_zlaunch(geo, vec, lz);
 }
 
+// ------------------------------------------------------------------------------------------
+// step graph
+// ------------------------------------------------------------------------------------------
+
+// Replays need every implicit stage's solve history (from steered steps) and the outer loop.
+bool mprk_handle::graph_ready() const {
+  if (!graph_on || prof_on) return false;
+  for (int i = 0; i < nstages; ++i) {
+    if (!implicit_[i]) continue;
+    if (cfgs[sig_idx[i]].paper_mode || !hist[i].valid) return false;
+  }
+  return true;
+}
+
+void mprk_handle::graph_drop() {
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  gexec = nullptr;
+  gexec_epoch = 0;
+}
+
+// Captures one step on the library's own stream (the caller's may be the legacy default stream,
+// which cannot be captured) and instantiates it.  Nothing runs during the capture.
+int mprk_handle::graph_capture() {
+  graph_drop();
+  if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+  for (int i = 0; i < nstages; ++i) ghist[i] = hist[i];
+  hipStream_t user = stream;
+  stream = cap_stream;
+  capturing = true;
+  const hipError_t eb = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+  int rc = eb == hipSuccess ? enqueue_step(false) : MPRK_OK;
+  hipGraph_t g = nullptr;
+  const hipError_t ee = eb == hipSuccess ? hipStreamEndCapture(cap_stream, &g) : hipSuccess;
+  capturing = false;
+  stream = user;
+  if (eb != hipSuccess)
+    return set_error(MPRK_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(eb));
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (ee != hipSuccess || !g)
+    return set_error(MPRK_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+  const hipError_t ei = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    gexec = nullptr;
+    return set_error(MPRK_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  gexec_epoch = graph_epoch;
+  return MPRK_OK;
+}
+
+// Runs up to nsteps steps from the graph; *done = steps completed (combined).  The graph is
+// captured again when anything it depends on changed or when a steered solve needed more passes
+// or iterations than the capture enqueues.  A stage that missed inside the graph held its step:
+// *done < nsteps, and the caller continues on the steered path from there.
+int mprk_handle::graph_steps(int nsteps, int* done) {
+  *done = 0;
+  for (int i = 0; i < nstages; ++i)
+    if (implicit_[i]) {
+      int rc = update_hist(i);
+      if (rc) return rc;
+    }
+  if (!graph_ready()) return MPRK_OK;
+  bool same = gexec && gexec_epoch == graph_epoch;
+  for (int i = 0; i < nstages && same; ++i) {
+    if (!implicit_[i]) continue;
+    if (hist[i].passes > ghist[i].passes) same = false;
+    for (int p = 0; p < hist[i].passes && same; ++p)
+      if (hist[i].iters[p] > ghist[i].iters[p]) same = false;
+  }
+  if (!same) {
+    int rc = graph_capture();
+    if (rc) return rc;
+  }
+  Ctl* ctl = (Ctl*)(ws + o_ctl);
+  hipLaunchKernelGGL(k_release_halt, dim3(1), dim3(64), 0, stream, ctl);
+  HIPCHK(hipGetLastError());
+  for (int n = 0; n < nsteps; ++n) HIPCHK(hipGraphLaunch(gexec, stream));
+  // the stage records of the last replayed step, for the statistics
+  HIPCHK(hipMemcpyAsync((void*)&slots[NSLOT], ctl->srec, sizeof(CtlHead) * nstages,
+                        hipMemcpyDeviceToHost, stream));
+  // counters: completed steps; a miss inside the graph is not reported (its steps are re-run)
+  int rc = sync_counters();
+  *done = last_good;
+  graph_steps_last = last_good;
+  return rc;
+}
+
 int mprk_handle::rebase_missed() {
   Ctl* ctl = (Ctl*)(ws + o_ctl);
   long long m = 0;
@@ -1342,6 +1475,7 @@ int mprk_handle::sync_counters() {
   HIPCHK(hipStreamSynchronize(stream));
   const long long good = hd.good_steps - good_base;
   const int bad = hd.bad_steps - bad_base;
+  last_good = (int)good;
   good_base = hd.good_steps;
   bad_base = hd.bad_steps;
   step_count += good;
@@ -1361,8 +1495,20 @@ extern "C" int32_t mprk_step(mprk_handle* h, int32_t nsteps, mprk_stats* stats) 
   if (!h->bound) return set_error(MPRK_ESTATE, "mprk_step before mprk_bind");
   if (int rcw = h->check_ws()) return rcw;
   if (nsteps < 0) return set_error(MPRK_EINVAL, "nsteps must be >= 0");
-  for (int n = 0; n < nsteps; ++n) {
-    int rc = h->enqueue_step(n == 0);
+  int done = 0;
+  h->graph_steps_last = 0;
+  if (h->graph_on && nsteps > 0) {
+    int rc = h->graph_steps(nsteps, &done);
+    if (rc == MPRK_ENONFINITE) {
+      if (stats) h->fill_stats(stats);
+      return set_error(rc, "non-finite residual: u left at the last completed step");
+    }
+    if (rc) return rc;
+  }
+  // steered steps (all of them, or those after a step the graph held); the first releases the
+  // halt of an earlier call or of the replays
+  for (int n = done; n < nsteps; ++n) {
+    int rc = h->enqueue_step(n == done);
     if (rc) return rc;
   }
   int rc = h->sync_counters();
@@ -1417,6 +1563,7 @@ extern "C" int32_t mprk_solve(mprk_handle* h, int32_t stage, const double* rhs_d
 extern "C" int32_t mprk_set_forcing(mprk_handle* h, const double* g_dev) {
   if (!h) return set_error(MPRK_EINVAL, "handle is NULL");
   h->force = g_dev;
+  h->graph_epoch += 1;
   return MPRK_OK;
 }
 
@@ -1437,6 +1584,15 @@ extern "C" int32_t mprk_set_reaction(mprk_handle* h, double r1, double r2, doubl
   h->react[1] = r2;
   h->react[2] = r3;
   h->react_on = on;
+  h->graph_epoch += 1;
+  return MPRK_OK;
+}
+
+extern "C" int32_t mprk_set_step_graph(mprk_handle* h, int32_t enable) {
+  if (!h) return set_error(MPRK_EINVAL, "handle is NULL");
+  static_assert(MPRK_MAX_STAGES <= MAXSTG, "a replayed step keeps a record per stage");
+  h->graph_on = enable != 0;
+  if (!h->graph_on) h->graph_drop();
   return MPRK_OK;
 }
 
@@ -1582,6 +1738,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
   if (!h) return set_error(MPRK_EINVAL, "NULL handle");
   if (!h->bound) return set_error(MPRK_ESTATE, "mprk_autotune before mprk_bind");
   if (int rcw = h->check_ws()) return rcw;
+  h->graph_epoch += 1;  // launch shapes may change
   const bool csr = h->op.format == MPRK_FMT_CSR;
   const long ngv = h->N / h->vec, ngr = h->N, ngl = h->N / h->vec_lp;
   const TuneKey key{h->grid.nx, h->grid.ny, h->grid.nz, h->grid.bc, h->op.kind, h->op.format, h->prec.storage,
@@ -1695,7 +1852,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
                            RESET_STAGE | RESET_CALL);
       hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.23, 0.017, x64);
       if (hipGetLastError() != hipSuccess) { rc = MPRK_EDEVICE; break; }
-      rc = h->launch_residual(si, rhs, x64, y64, FTerms{});
+      rc = h->launch_residual(h->cfgs[si], rhs, x64, y64, FTerms{});
       if (rc) break;
       if ((cg ? h->eng->cg_begin(c, cfg, dinv) : h->eng->gm_begin(c, cfg, dinv)) != hipSuccess) { rc = MPRK_EDEVICE; break; }
       if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = MPRK_EDEVICE; break; }
@@ -1737,7 +1894,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
       hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.23, 0.017, x64);
       if (hipGetLastError() != hipSuccess) { rc = MPRK_EDEVICE; break; }
       float ms;
-      time_it([&]() { return h->launch_residual(si, rhs, x64, y64, FTerms{}); }, &ms);
+      time_it([&]() { return h->launch_residual(h->cfgs[si], rhs, x64, y64, FTerms{}); }, &ms);
       if (rc) break;
       if (ms < bz) {
         bz = ms;
@@ -1786,7 +1943,7 @@ extern "C" int32_t mprk_autotune(mprk_handle* h, int32_t* nit_vec, int32_t* nit_
                                rhs, x64, ctl, RESET_STAGE | RESET_CALL);
           hipLaunchKernelGGL(k_fill_pattern, dim3(nb), dim3(256), 0, h->stream, (long)h->N, 0.23, 0.017, x64);
           if (hipGetLastError() != hipSuccess) { rc = MPRK_EDEVICE; break; }
-          rc = h->launch_residual(si, rhs, x64, y64, FTerms{});
+          rc = h->launch_residual(h->cfgs[si], rhs, x64, y64, FTerms{});
           if (rc) break;
           if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = MPRK_EDEVICE; break; }
           if (h->eng->gm_begin(c, cfg, dinv) != hipSuccess) { rc = MPRK_EDEVICE; break; }

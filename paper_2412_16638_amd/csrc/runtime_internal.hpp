@@ -128,6 +128,16 @@ struct mprk_handle {
   bool rec_pending[MPRK_MAX_STAGES + 1] = {};
   int* rec_iters = nullptr;                   // pinned: MAXPASS ints per slot
   hipEvent_t rec_ev[MPRK_MAX_STAGES + 1] = {};
+  // step graph (mprk_set_step_graph): one step's launches captured once, replayed per step
+  bool graph_on = false;
+  bool capturing = false;             // enqueue_step is being captured (no host waits)
+  hipStream_t cap_stream = nullptr;   // library-owned stream the step is captured on
+  hipGraphExec_t gexec = nullptr;
+  unsigned long long graph_epoch = 1;  // bumped by every change a captured step depends on
+  unsigned long long gexec_epoch = 0;
+  StageHist ghist[MPRK_MAX_STAGES];    // the histories the graph was captured with
+  int graph_steps_last = 0;           // steps of the last mprk_step call replayed from the graph
+  int last_good = 0;                  // steps combined since the previous counter sync
   // profiling
   mprk::Profiler prof;
   bool prof_on = false;
@@ -155,10 +165,17 @@ struct mprk_handle {
   int update_hist(int slot);
   mprk::BJDesc bj_desc(int si) const;
   mprk::Red red() const;
-  int launch_residual(int si, const double* rhs, double* y, double* kout, const mprk::FTerms& fx);
+  int launch_residual(const mprk::SolveCfg& cfg, const double* rhs, double* y, double* kout,
+                      const mprk::FTerms& fx);
   int launch_apply64(const double* x, double* y, double sigma, int mode,
                      const mprk::FTerms& fx = mprk::FTerms{});
   int run_solve(int si, int slot, const double* rhs, double* y, double* kout, const mprk::FTerms& fx);
+  int run_solve_graph(int si, int slot, const double* rhs, double* y, double* kout,
+                      const mprk::FTerms& fx);
+  bool graph_ready() const;
+  int graph_capture();
+  void graph_drop();
+  int graph_steps(int nsteps, int* done);
   int enqueue_step(bool first_of_call);
   int sync_counters();
   int rebase_missed();

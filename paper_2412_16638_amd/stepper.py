@@ -91,6 +91,10 @@ class Stepper:
         torch.cuda.synchronize(self.device)
         A.mprk_set_forcing(self.h, self.g.data_ptr())
 
+    def set_step_graph(self, enable: bool = True) -> None:
+        """Replay whole steps from a captured hipGraph once the stage histories exist."""
+        A.mprk_set_step_graph(self.h, enable)
+
     def set_reaction(self, r1: float = 0.0, r2: float = 0.0, r3: float = 0.0) -> None:
         """Pointwise reaction R(u) = r1 u + r2 u^2 + r3 u^3 of du/dt = K u + g + R(u); all zero
         removes it."""

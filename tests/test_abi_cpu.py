@@ -194,6 +194,15 @@ def test_reaction_entry_point_is_validated_on_host():
     A.lib.mprk_destroy(h)
 
 
+def test_step_graph_switch_on_host():
+    rc, h = _create()
+    assert rc == A.OK, A.mprk_last_error()
+    assert A.lib.mprk_set_step_graph(h, 1) == A.OK
+    assert A.lib.mprk_set_step_graph(h, 0) == A.OK
+    A.lib.mprk_destroy(h)
+    assert A.lib.mprk_set_step_graph(None, 1) == A.EINVAL
+
+
 def test_compressed_basis_precisions_are_accepted_for_single_problems():
     # FP64 arithmetic over FP16 / FP32 storage (compressed-basis Krylov); the batched form
     # keeps FP32 arithmetic for LP storage
