@@ -104,13 +104,26 @@ def _calibration(rows, mib: int) -> float:
     return mib * 1024.0 / max(copies)
 
 
+def _after(rows, kernel: str):
+    """The rows dispatched after the last dispatch of `kernel` (all rows if it never ran)."""
+    marks = [int(r['Dispatch_Id']) for r in rows if short_name(r['Kernel_Name']) == kernel]
+    if not marks:
+        return rows
+    last = max(marks)
+    return [r for r in rows if int(r['Dispatch_Id']) > last]
+
+
 def traffic(fetch_csv: str, write_csv: str, kernel: str, calib_mib: int,
-            worked_frac: float = 0.01) -> dict:
+            worked_frac: float = 0.01, after: str = None) -> dict:
     """Mean HBM bytes per working dispatch of `kernel` (dispatches that fetched less than
-    `worked_frac` of the largest one had nothing left to do and are counted apart)."""
+    `worked_frac` of the largest one had nothing left to do and are counted apart).  after:
+    count only dispatches after the last one of that kernel (the autotuner's fill kernel marks
+    the end of its trial runs, whose Krylov cycles differ from the measured steps')."""
     fr = _counter_rows(fetch_csv, 'FETCH_SIZE')
     wr = _counter_rows(write_csv, 'WRITE_SIZE')
     ff, fw = _calibration(fr, calib_mib), _calibration(wr, calib_mib)
+    if after:
+        fr, wr = _after(fr, after), _after(wr, after)
     fmine = [float(r['Counter_Value']) for r in fr if short_name(r['Kernel_Name']) == kernel]
     wmine = [float(r['Counter_Value']) for r in wr if short_name(r['Kernel_Name']) == kernel]
     if not fmine or not wmine:
@@ -122,29 +135,31 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, calib_mib: int,
     fetch_b = sum(fw_) / len(fw_) * 1024 * ff
     write_b = sum(ww_) / len(ww_) * 1024 * fw
     return {'kernel': kernel, 'fetch_factor': ff, 'write_factor': fw,
-            'dispatches': len(fmine), 'working_dispatches': len(fw_),
+            'counted_after': after, 'dispatches': len(fmine), 'working_dispatches': len(fw_),
             'fetch_bytes_per_worked_launch': fetch_b, 'write_bytes_per_worked_launch': write_b,
             'bytes_per_worked_launch': fetch_b + write_b}
 
 
 def traffic_table(fetch_csv: str, write_csv: str, calib_mib: int, unknowns: int,
-                  command_fetch: str, command_write: str) -> str:
+                  command_fetch: str, command_write: str, after: str = None) -> str:
     """HBM bytes per working dispatch, and per unknown, of every library kernel in the two
-    counter runs, as a text table."""
+    counter runs, as a text table (after: as in traffic)."""
     fr = _counter_rows(fetch_csv, 'FETCH_SIZE')
-    names = sorted({short_name(r['Kernel_Name']) for r in fr
+    sel = _after(fr, after) if after else fr
+    names = sorted({short_name(r['Kernel_Name']) for r in sel
                     if 'mprk' in r['Kernel_Name'] and short_name(r['Kernel_Name']) != r['Kernel_Name']})
     ff = _calibration(fr, calib_mib)
     fw = _calibration(_counter_rows(write_csv, 'WRITE_SIZE'), calib_mib)
     lines = ['# HBM traffic per working dispatch (rocprofv3 FETCH_SIZE / WRITE_SIZE)', '',
              f'command (FETCH_SIZE): {command_fetch}', f'command (WRITE_SIZE): {command_write}',
              f'calibration: plain device copy of {calib_mib} MiB; fetch factor {ff:.4f}, '
-             f'write factor {fw:.4f}', f'kernel sources: {kernel_source_hash()}', '',
+             f'write factor {fw:.4f}', f'kernel sources: {kernel_source_hash()}',
+             f'dispatches counted: ' + (f'after the last {after}' if after else 'all'), '',
              f'{"kernel":<22}{"dispatches":>11}{"working":>9}{"fetch MB":>11}{"write MB":>11}'
              f'{"B/unknown":>11}']
     for k in names:
         try:
-            t = traffic(fetch_csv, write_csv, k, calib_mib)
+            t = traffic(fetch_csv, write_csv, k, calib_mib, after=after)
         except ValueError:
             continue
         lines.append(f'{k:<22}{t["dispatches"]:>11}{t["working_dispatches"]:>9}'
@@ -204,6 +219,7 @@ def main():
     b.add_argument('--command-fetch', required=True)
     b.add_argument('--command-write', required=True)
     b.add_argument('--out', required=True)
+    b.add_argument('--after-kernel', help='count only dispatches after the last one of this kernel')
     t = sub.add_parser('traffic-table')
     t.add_argument('fetch_csv')
     t.add_argument('write_csv')
@@ -212,11 +228,12 @@ def main():
     t.add_argument('--command-fetch', required=True)
     t.add_argument('--command-write', required=True)
     t.add_argument('--out', required=True)
+    t.add_argument('--after-kernel', help='count only dispatches after the last one of this kernel')
     args = ap.parse_args()
     if args.what == 'traffic-table':
         with open(args.out, 'w') as fh:
             fh.write(traffic_table(args.fetch_csv, args.write_csv, args.calib_mib, args.unknowns,
-                                   args.command_fetch, args.command_write))
+                                   args.command_fetch, args.command_write, args.after_kernel))
         return
     if args.what == 'stats':
         text = stats_summary(args.csv, args.command)
@@ -227,7 +244,8 @@ def main():
         with open(args.out, 'w') as fh:
             fh.write(text)
     else:
-        t = traffic(args.fetch_csv, args.write_csv, args.kernel, args.calib_mib)
+        t = traffic(args.fetch_csv, args.write_csv, args.kernel, args.calib_mib,
+                    after=args.after_kernel)
         t.update({'workload': args.workload, 'kernel_hash': kernel_source_hash(),
                   'command_fetch': args.command_fetch, 'command_write': args.command_write,
                   'calibration': f'plain device copy of {args.calib_mib} MiB (reads and writes '
