@@ -232,6 +232,38 @@ def nonlinear_leg(M, args, fmt, bjs, mixed_over, K: int, Wm: int) -> dict:
     return out
 
 
+def fdm_leg(M, K: int, Wm: int) -> dict:
+    """Both workloads with the paper's fast-diagonalisation preconditioner instead of
+    block-Jacobi (stencil format): the mixed path timed over K steps, its error against the
+    all-FP64 FDM path solved to REF_TOL, and the FP64 path at the mixed path's tolerances."""
+    out = {}
+    for name in ('heat128', 'advdiff256'):
+        p = make_problem(name, 'fdm')
+        q = make_problem(name, 'fdm')
+        q.precision = 'fp64'
+        ref, _ = run_integration(M, q, 0, rtol=REF_TOL, outer_tol=REF_TOL)
+        over = dict(MIXED_TOL[name])
+        u, _ = run_integration(M, p, 0, **over)
+        err = float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+        st = M.from_problem(p, **over)
+        st.autotune()
+        t, stats, _ = time_steps(st, p.u0, K, Wm)
+        st.close()
+        pm = M.precisions(p.precision, p.krylov, **over)
+        st64 = M.from_problem(q, rtol=pm.rtol, outer_tol=pm.outer_tol)
+        st64.autotune()
+        t64, _, _ = time_steps(st64, q.u0, K, Wm)
+        st64.close()
+        out[name] = {'value': p.N * K / t, 'ms_per_step': t * 1e3 / K, 'err_vs_fp64_reference': err,
+                     'iters_per_stage': stats['iters'], 'passes_per_stage': stats['passes'],
+                     'fp64_at_mixed_tolerances': {'value': q.N * K / t64,
+                                                  'ms_per_step': t64 * 1e3 / K},
+                     'lp_storage': p.precision, 'krylov': p.krylov}
+        log(f'fdm {name}: {out[name]["value"]:.4e} DOF-steps/s, rel-L2 {err:.3e}; FP64 at the same '
+            f'tolerances {q.N * K / t64:.4e}')
+    return out
+
+
 def host_info() -> dict:
     """The host the oracle ran on: core count, CPU model, BLAS threads, OMP_NUM_THREADS."""
     model = None
@@ -561,6 +593,11 @@ def main():
     if not args.no_fp64 and not args.quick and args.fmt == 'stencil':
         nonlin = nonlinear_leg(M, args, fmt, bjs, mixed_over, K, Wm)
 
+    # ---- the fast-diagonalisation preconditioner on both workloads ----
+    fdm_side = None
+    if not args.no_fp64 and not args.quick and args.precond == 'bj' and args.fmt == 'stencil':
+        fdm_side = fdm_leg(M, K, Wm)
+
     # ---- side legs of the metric: batched problems and serving latency ----
     batch = None
     if not args.no_batch and not args.quick:
@@ -600,6 +637,7 @@ def main():
         'other_bj_storage': other,
         'adaptive_bj': adaptive,
         'nonlinear': nonlin,
+        'fdm': fdm_side,
         'speedup_vs_fp64_matched': (value / fp64['value']) if fp64 else None,
         'roofline': roofline,
         'cpu_baseline': cpu,
