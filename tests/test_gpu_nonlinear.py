@@ -29,7 +29,7 @@ _REF = {}
 
 
 def _ref(p, shape=None):
-    key = (p.name, p.tableau, p.n, shape)
+    key = (p.name, p.tableau, p.n, p.nsteps, shape)
     if key not in _REF:
         _REF[key] = reference_nonlinear(p, shape)
     return _REF[key]
@@ -134,3 +134,29 @@ def test_constant_periodic_state_at_full_size(workload):
     print(workload, 'max rel deviation', dev, 'value', want, stats['passes'])
     assert stats['missed'] == 0
     assert dev <= 1e-10, dev
+
+
+@pytest.mark.parametrize("storage", ['fp32', 'fp16'])
+def test_reaction_with_the_fdm_preconditioner(storage):
+    p = W.heat_allen_cahn(n=24, nsteps=6)
+    p.precision = storage
+    p.precond = 'fdm'
+    log_case('reaction_fdm', storage=storage)
+    u, stats = _run(p, A.FMT_STENCIL)
+    err = rel_l2(u, _ref(p))
+    print(storage, 'fdm rel-L2', err, stats['passes'])
+    assert stats['missed'] == 0
+    assert err <= TOL[storage], err
+
+
+@pytest.mark.parametrize("storage", ['fp32', 'fp16'])
+def test_reaction_with_fp64_arithmetic(storage):
+    # the compressed-basis engines (FP64 arithmetic over LP storage) with the reaction
+    p = W.advdiff_fisher(n=32, nsteps=4)
+    p.precision = storage
+    log_case('reaction_cb', storage=storage)
+    u, stats = _run(p, A.FMT_STENCIL, compute=A.FP64)
+    err = rel_l2(u, _ref(p))
+    print(storage, 'cb rel-L2', err, stats['passes'])
+    assert stats['missed'] == 0
+    assert err <= TOL[storage], err

@@ -155,3 +155,48 @@ def test_forcing_and_reaction_changes_rebuild_the_graph():
     b.close()
     print('rebuild diff', d)
     assert d <= AGREE['fp32'], d
+
+
+@pytest.mark.parametrize("workload", ['heat', 'advdiff'])
+def test_replays_with_the_fdm_preconditioner(workload):
+    if workload == 'heat':
+        p = W.heat_modes(n=24, nsteps=12)
+    else:
+        p = W.advdiff_bump(n=32, nsteps=12)
+    p.precond = 'fdm'
+    log_case('step_graph_fdm', workload=workload)
+    a, b = _pair(p, A.FMT_STENCIL)
+    a.step(2)
+    b.step(2)
+    sa = a.step(10)
+    b.step(10)
+    assert sa['graph_steps'] > 0 and sa['missed'] == 0
+    d = rel_l2(a.get_u(), b.get_u())
+    e = rel_l2(a.get_u(), reference_solution(p))
+    a.close()
+    b.close()
+    print(workload, 'fdm diff', d, 'oracle', e)
+    assert d <= AGREE[p.precision] and e <= TOL[p.precision]
+
+
+def test_strict_miss_inside_and_outside_the_graph_reports_enotconv():
+    # a stage that cannot converge within refine_max even when steered: the graph holds the
+    # step, the steered rerun misses too, the call returns MPRK_ENOTCONV and u stays at the last
+    # step whose stages all converged -- as for a handle without the graph
+    p = W.heat_modes(n=16, nsteps=6)
+    log_case('step_graph_strict')
+    a, b = _pair(p, A.FMT_STENCIL, refine_max=3, strict=1)
+    a.step(2)
+    b.step(2)
+    ua0, ub0 = a.get_u(), b.get_u()
+    for st in (a, b):
+        st.set_reaction(2000.0, 0.0, 0.0)  # needs ~25 passes: 3 are not enough
+    ra, sa = a.step(3, check=False)
+    rb, sb = b.step(3, check=False)
+    ua, ub = a.get_u(), b.get_u()
+    a.close()
+    b.close()
+    print('strict rc', ra, rb, sa['steps'], sb['steps'], sa['missed'], sb['missed'])
+    assert ra == A.ENOTCONV and rb == A.ENOTCONV
+    assert sa['steps'] == sb['steps'] == 2
+    assert np.array_equal(ua, ua0) and np.array_equal(ub, ub0)
