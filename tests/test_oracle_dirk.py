@@ -88,7 +88,7 @@ def test_dirk_matches_fft_closed_form_periodic(name):
     assert D.relative_l2(u, ref) < 1e-12
 
 
-def test_closed_form_periodic_equals_dft_of_dirk_at_cfg3_shape_small():
+def test_closed_form_periodic_equals_dft_of_dirk_for_the_advdiff_workload_on_16():
     # same physics as the 256^3 advection-diffusion workload, on 16^3
     p = W.advdiff_bump(n=16, nsteps=3)
     K = O.advdiff_operator((16,) * 3, O.PERIODIC, p.diff, p.b)

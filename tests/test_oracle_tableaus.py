@@ -54,7 +54,9 @@ def test_4s3pA_low_precision_part_is_invisible_to_b():
     assert np.abs(tab.b @ tab.A_lo).max() < 1e-15
 
 
-def test_c_row_sums_match_survey_of_table_values():
+def test_c_row_sums_and_diagonals_match_the_printed_tables():
+    # Table ButchertabA: a11 = a33 = 0.788675134594813 and a21 = 0.211324865405187 (so c1 and c2
+    # are these, c3 the sum of the third row); Table ButchertabC: the diagonal as printed
     np.testing.assert_allclose(T.s4p3a().c, [0.788675134594813, 0.211324865405187,
                                              0.684800648252415, 0.788675134594813], atol=1e-14)
     np.testing.assert_allclose(np.diag(T.s4p3c().A), [0.511243008730995, 1.957161067302390,
