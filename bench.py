@@ -837,13 +837,28 @@ def batch_leg(K: int, Wm: int, quick: bool) -> dict:
     for i, p in enumerate(probs):
         b.set_u(i, p.u0)
     expo, ru = b.autotune()
-    log(f'autotuned: {ru} rows per thread per CG sweep, work-model exponent {expo}; workgroups '
+    model = 'measured work of the last step' if expo < 0 else f'work-model exponent {expo}'
+    log(f'autotuned: {ru} rows per thread per CG sweep, {model}; workgroups '
         f'per problem {min(b.schedule)}..{max(b.schedule)}, total {sum(b.schedule)}')
     t = timed()
     st = [b.stats(i) for i in range(len(probs))]
-    wg = sum(b.schedule)
+    sched = list(b.schedule)
+    wg = sum(sched)
     b.close()
     log(f'batch: {dof * K / t:.4e} DOF-steps/s')
+    # where the time goes: the step's CG work (iterations x unknowns, from each problem's last
+    # step) at the FP32 per-block BJ(8) bytes of one iteration (11 s + 8 m = 76 B), the FP64
+    # outer passes (about 120 B per unknown each), stage right-hand sides and the combination
+    # (about 136 B): an effective bandwidth; and the share of workgroup time that does work when
+    # each problem's workgroups take N x iterations / workgroups and the stage ends with the
+    # slowest (1 = every group finishes together)
+    it_dofs = sum(p.N * sum(x['iters']) for p, x in zip(probs, st))
+    pass_dofs = sum(p.N * sum(x['passes']) for p, x in zip(probs, st))
+    bytes_step = 76.0 * it_dofs + 120.0 * pass_dofs + 136.0 * dof
+    span = max(p.N * sum(x['iters']) / g for p, x, g in zip(probs, st, sched))
+    balance = it_dofs / (wg * span) if span > 0 else None
+    log(f'batch: {it_dofs / dof:.1f} CG iterations per unknown per step, effective '
+        f'{bytes_step * K / t / 1e9:.0f} GB/s (byte model), workgroup balance {balance:.2f}')
     return {'value': dof * K / t, 'unit': 'DOF-steps/s', 'steps': K, 'warmup': Wm,
             'ms_per_step': t * 1e3 / K,
             'config': {'workload': 'batch_64_heat_n16-96_kappa0.1-10_sdirk3_dt5e-4_cg_bj8_fp32',
@@ -855,7 +870,10 @@ def batch_leg(K: int, Wm: int, quick: bool) -> dict:
             'autotuned_rows_per_thread': ru,
             'workgroups': wg,
             'worst_err_vs_fp64_reference': worst,
-            'iters_per_stage_max': max(max(x['iters']) for x in st)}
+            'iters_per_stage_max': max(max(x['iters']) for x in st),
+            'cg_iterations_per_unknown_per_step': it_dofs / dof,
+            'effective_GBps_byte_model': bytes_step * K / t / 1e9,
+            'workgroup_balance': balance}
 
 
 def bench_batch(args):

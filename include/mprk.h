@@ -399,10 +399,11 @@ int32_t mprk_batch_get_schedule(mprk_batch *b, int32_t *wg_per_problem);
 /* Autotune a bound batch by replaying one step from the current states per candidate: first
  * the rows a thread handles together in the CG phases (1, 2 or 4: loads in flight vs
  * registers, hence co-resident workgroups), then the planned schedule's work model, unknowns x
- * (condition-number estimate)^e for e in {0, 1/4, 1/2, 3/4, 1}.  The fastest choice is kept and
- * written to *exponent_out / *rows_out (either may be NULL).  States and statistics are
- * restored; the call synchronises the stream.  MPRK_ESTATE if unbound or if set_schedule fixed
- * the schedule. */
+ * (condition-number estimate)^e for e in {0, 1/4, 1/2, 3/4, 1}, and, when a step has run, the
+ * measured work of the last step (unknowns x (CG iterations + 1.6 x outer passes) per problem).
+ * The fastest choice is kept and written to *exponent_out (-1 for the measured model) /
+ * *rows_out (either may be NULL).  States and statistics are restored; the call synchronises
+ * the stream.  MPRK_ESTATE if unbound or if set_schedule fixed the schedule. */
 int32_t mprk_batch_autotune(mprk_batch *b, double *exponent_out, int32_t *rows_out);
 int64_t mprk_batch_workspace_bytes(const mprk_batch *b);
 /* u_dev: array of `count` device pointers (problem p's state, N_p doubles each). */

@@ -454,6 +454,10 @@ struct mprk_batch {
   std::vector<long long> good_seen, bad_seen;
   std::vector<int> fixed_wg;  // caller-chosen workgroups per problem (empty: planned)
   double weight_exp = 0.5;    // exponent of the condition-number estimate in the work model
+  // measured work model (autotuner): per problem, unknowns x (CG iterations + 1.6 x outer passes)
+  // of the last step; used by plan_groups while use_measured is set
+  std::vector<double> measured_w;
+  bool use_measured = false;
   int ru = 2;                 // rows a thread handles together in the CG phases (1, 2, 4)
   int capacity = 0;           // co-resident workgroups of the device for the kernel in use
   int max_capacity = 0;       // largest capacity over the kernel variants (sizes the map)
@@ -577,7 +581,9 @@ static int plan_groups(mprk_batch* b, int capacity) {
   std::vector<double> w(b->count);
   double W = 0.0;
   for (int p = 0; p < b->count; ++p) {
-    w[p] = work_weight(b->probs[p], a, b->weight_exp);
+    w[p] = (b->use_measured && (int)b->measured_w.size() == b->count)
+               ? b->measured_w[p]
+               : work_weight(b->probs[p], a, b->weight_exp);
     W += w[p];
   }
   (void)s;
@@ -919,6 +925,34 @@ extern "C" int32_t mprk_batch_autotune(mprk_batch* b, double* exponent_out, int3
     }
     b->weight_exp = keep;
   }
+  // the measured work of the last step (when one ran): unknowns x (CG iterations + 1.6 x outer
+  // passes, an FP64 pass moving about 1.6 times a CG iteration's bytes), each problem's real
+  // share instead of the condition-number estimate
+  bool best_measured = false;
+  {
+    std::vector<double> mw(b->count);
+    double tot = 0.0;
+    for (int p = 0; p < b->count; ++p) {
+      double it = 0.0, ps = 0.0;
+      for (int i = 0; i < b->tab.s && i < MAXS; ++i) {
+        it += ctl[p].iters[i];
+        ps += ctl[p].passes[i];
+      }
+      mw[p] = (double)b->N[p] * (it + 1.6 * ps);
+      tot += mw[p];
+    }
+    if (!rc && tot > 0.0) {
+      b->measured_w = mw;
+      b->use_measured = true;
+      float ms = 0.f;
+      rc = trial(&ms);
+      if (!rc && ms < best_ms) {
+        best_ms = ms;
+        best_measured = true;
+      }
+      b->use_measured = best_measured;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->weight_exp = best_e;
@@ -935,7 +969,7 @@ extern "C" int32_t mprk_batch_autotune(mprk_batch* b, double* exponent_out, int3
     BHIP(hipMemcpyAsync(b->ws + b->o_ctl, ctl.data(), sizeof(BCtl) * b->count, hipMemcpyHostToDevice, b->stream));
     BHIP(hipStreamSynchronize(b->stream));
   }
-  if (exponent_out) *exponent_out = best_e;
+  if (exponent_out) *exponent_out = best_measured ? -1.0 : best_e;
   if (rows_out) *rows_out = b->ru;
   return rc ? rc : rc2;
 }
