@@ -200,3 +200,21 @@ def test_strict_miss_inside_and_outside_the_graph_reports_enotconv():
     assert ra == A.ENOTCONV and rb == A.ENOTCONV
     assert sa['steps'] == sb['steps'] == 2
     assert np.array_equal(ua, ua0) and np.array_equal(ub, ub0)
+
+
+def test_replays_with_fp64_arithmetic_over_fp16_storage():
+    # the compressed-basis engine (FP64 arithmetic, FP16 basis) under the graph
+    p = W.advdiff_bump(n=32, nsteps=12)
+    log_case('step_graph_cb')
+    a, b = _pair(p, A.FMT_STENCIL, compute=A.FP64)
+    a.step(2)
+    b.step(2)
+    sa = a.step(10)
+    b.step(10)
+    assert sa['graph_steps'] > 0 and sa['missed'] == 0
+    d = rel_l2(a.get_u(), b.get_u())
+    e = rel_l2(a.get_u(), reference_solution(p))
+    a.close()
+    b.close()
+    print('cb diff', d, 'oracle', e)
+    assert d <= AGREE['fp16'] and e <= TOL['fp16']
