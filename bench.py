@@ -37,7 +37,7 @@ def log(*a):
 
 def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, units: int,
                       nv_total: int = 0, fdm: bool = False, cb: int = 4,
-                      csr_nnz_row: float = 0.0) -> float:
+                      csr_nnz_row: float = 0.0, zstored: bool = False) -> float:
     """Bytes each kernel class must move per its definition (each array touched once; halos
     and reduction partials not counted).  s = LP storage bytes, m = LP matrix bytes, bs = block,
     cb = bytes of the arithmetic type; csr_nnz_row > 0: CSR format with that many nonzeros per
@@ -60,6 +60,8 @@ def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, uni
     if kc == 'gm_finish':
         if fdm:  # t = sum_i y_i v_i in the arithmetic type; P^-1 t and y += s z come after
             return N * (worked * cb + units * s)
+        if zstored:  # y += s sum_i y_i BJ(v_i) from the stored directions: no inverse read
+            return N * (worked * 16 + units * s)
         return N * (worked * (inv + 16) + units * s)
     if kc == 'gm_begin':
         return N * worked * (8 + s + pre)
@@ -448,8 +450,11 @@ def main():
         cbytes = 8 if args.compute == 'fp64' or p.precision == 'fp64' else 4
         if kc == 'promote' and args.precond == 'fdm' and p.krylov == 'gmres':
             sv = cbytes  # the GMRES correction P^-1 (V y) is formed in the arithmetic type
+        # GMRES with block-Jacobi in the gather form stores each direction BJ(v_j)
+        zst = (p.krylov == 'gmres' and bs > 0 and args.precond == 'bj' and launch.get('gm_form') == 1)
         b = algorithmic_bytes(kc, N, sv, s_bytes, bs, r['worked'], r['units'], nv_total,
-                              fdm=args.precond == 'fdm', cb=cbytes, csr_nnz_row=nnz_row)
+                              fdm=args.precond == 'fdm', cb=cbytes, csr_nnz_row=nnz_row,
+                              zstored=zst)
         rows.append((kc, r, b))
     total_ms = sum(r['ms'] for _, r, _ in rows)
     dom = max(rows, key=lambda x: x[1]['ms'])

@@ -98,6 +98,9 @@ struct EngineCtx {
   void *r, *z, *p0, *p1, *q, *x;
   void* V;
   size_t vstride;     // elements between GMRES basis vectors
+  void* Zb;           // GMRES with block-Jacobi, gather form: the stored preconditioned directions
+                      // BJ(V_j), vstride apart (the cycle's end then combines them without the
+                      // inverse); null: one direction buffer z
   int reorth;         // GMRES: second classical Gram-Schmidt pass (CGS2)
   // GMRES Arnoldi step form: 0 gather kernels, 1 product on z-marching tiles + update kernel,
   // 2 folded onto z-marching tiles (stencil, block-Jacobi or none); the tile launch, its LDS
@@ -457,7 +460,7 @@ class EngineT final : public Engine {
     with_ad<BS>(dinv, [&](auto ad) {
       constexpr int AD = decltype(ad)::value;
       MPRK_LAUNCH_KC(c, KC_GM_BEGIN, (k_gm_begin<S, C, VEC, BS, AD>), c.ln_red, c.ln_red, c.res, (S*)c.V,
-                       (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
+                       (S*)(c.Zb ? c.Zb : c.z), bj_typed<S>(dinv), cfg, c.ctl, c.red);
     });
   }
   hipError_t gm_begin(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) override {
@@ -470,14 +473,16 @@ class EngineT final : public Engine {
     const Coef<C> M = cast_coef<C>(Mc);
     const C msig = (C)(cfg.sigma * c.kscale);
     MPRK_LAUNCH_KC(c, KC_GM_MATVEC, (k_gm_matvec<S, C, VEC, FMT, PREC, NDM>), c.ln_mv_red, c.ln_mv_red, c.geo, M, c.csr,
-                (const S*)c.mval, msig, (const S*)c.z, (S*)c.V, c.vstride, cfg, c.ctl, c.red);
+                (const S*)c.mval, msig, (const S*)(c.Zb ? c.Zb : c.z), c.Zb ? c.vstride : (size_t)0,
+                (S*)c.V, c.vstride, cfg, c.ctl, c.red);
   }
   template <int VEC, int BS, int NDM>
   void gm_orth_t(const EngineCtx& c, const SolveCfg& cfg, const BJDesc& dinv) {
     with_ad<BS>(dinv, [&](auto ad) {
       constexpr int AD = decltype(ad)::value;
       MPRK_LAUNCH_KC(c, KC_GM_ORTH, (k_gm_orth<S, C, VEC, BS, NDM, AD>), c.ln_red, c.ln_red, (S*)c.V, c.vstride,
-                       (S*)c.z, bj_typed<S>(dinv), cfg, c.ctl, c.red);
+                       (S*)(c.Zb ? c.Zb : c.z), c.Zb ? c.vstride : (size_t)0, bj_typed<S>(dinv), cfg,
+                       c.ctl, c.red);
     });
   }
   // folded steps on z-marching tiles (c.vec is 4 or 8 there)
@@ -608,6 +613,15 @@ class EngineT final : public Engine {
       dispatch_vec(c, [&](auto vec) {
         constexpr int V = decltype(vec)::value;
         MPRK_LAUNCH_KC(c, KC_PROMOTE, (k_gm_update_ext<C, V>), c.ln_vec, c.ln_vec, c.y, t1, c.ctl);
+      });
+      return;
+    }
+    if (c.Zb) {
+      // y += scale * sum_i ysol_i vscale_i BJ(V_i): the stored directions, no inverse read
+      dispatch_vec(c, [&](auto vec) {
+        constexpr int V = decltype(vec)::value;
+        MPRK_LAUNCH_KC(c, KC_GM_FINISH, (k_gm_finish<S, C, V, 0, NDM, 0>), c.ln_vec, c.ln_vec, c.y,
+                       (const S*)c.Zb, c.vstride, BJ<S>{}, c.ctl);
       });
       return;
     }

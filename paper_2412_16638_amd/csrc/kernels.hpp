@@ -813,14 +813,15 @@ __device__ __forceinline__ bool gm_bound_exceeded(Ctl* ctl, int nd, int ndm) {
   return true;
 }
 
-// w = M BJ(v_j) (PREC: zt holds BJ of the stored vector j, scaled here by vscale[j]) or
-// w = M v_j ; V_{j+1} := LP(w) ; d_i = (V_i, LP(w)) for i <= j.
+// w = M BJ(v_j) (PREC: z + j zstride holds BJ of the stored vector j, scaled here by vscale[j];
+// zstride = 0 for a single preconditioned-direction buffer) or w = M v_j ; V_{j+1} := LP(w) ;
+// d_i = (V_i, LP(w)) for i <= j.
 template <typename S, typename C, int VEC, int FMT, int PREC, int NDM>
 __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M, Csr csr,
                                                    const S* __restrict__ mval, C msig,
-                                                   const S* __restrict__ z, S* __restrict__ V,
-                                                   size_t vstride, SolveCfg cfg, Ctl* ctl,
-                                                   Red red) {
+                                                   const S* __restrict__ z, size_t zstride,
+                                                   S* __restrict__ V, size_t vstride, SolveCfg cfg,
+                                                   Ctl* ctl, Red red) {
   if (ctl->outer_done | ctl->inner_done) return;
   const int j = ctl->J;
   const int nd = j + 1;
@@ -832,7 +833,8 @@ __global__ __launch_bounds__(TPB) void k_gm_matvec(Launch ln, Geo geo, Coef<C> M
 #pragma unroll
   for (int i = 0; i < NDM; ++i) dacc[i] = C(0);
   constexpr int CH = basis_chunk<S, VEC>() < NDM ? basis_chunk<S, VEC>() : NDM;
-  const InScaled<C, S, VEC> f{PREC ? z : V + (size_t)j * vstride, (C)ctl->vscale[j]};
+  const InScaled<C, S, VEC> f{PREC ? z + (size_t)j * zstride : V + (size_t)j * vstride,
+                              (C)ctl->vscale[j]};
   for (int it = 0; it < ln.nit; ++it) {
     const int g0 = (L * ln.nit + it) * TPB;
     const int g = g0 + threadIdx.x;
@@ -977,11 +979,11 @@ __global__ __launch_bounds__(TPB) void k_gm_reorth(Launch ln, S* __restrict__ V,
 
 // w -= sum_{i<=j} h_ij v_i (classical Gram-Schmidt, coefficients from k_gm_matvec, or from
 // k_gm_reorth in the second pass of CGS2); h_{j+1,j} = ||w||; Givens update of the Hessenberg column; residual estimate |g_{j+1}|.
-// With a preconditioner (BS > 0) also zt = BJ(w), the next step's preconditioned direction
-// before normalisation.
+// With a preconditioner (BS > 0) also BJ(w), the next step's preconditioned direction before
+// normalisation, stored at zt + (j + 1) zstride (zstride = 0: the single buffer zt).
 template <typename S, typename C, int VEC, int BS, int NDM, int AD = 0>
 __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, size_t vstride,
-                                                 S* __restrict__ zt, BJ<S> dinv,
+                                                 S* __restrict__ zt, size_t zstride, BJ<S> dinv,
                                                  SolveCfg cfg, Ctl* ctl, Red red) {
   if (ctl->outer_done | ctl->inner_done) return;
   const int j = ctl->J;
@@ -992,6 +994,7 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
 #pragma unroll
   for (int i = 0; i < NDM; ++i) cf[i] = i < nd ? (C)(ctl->hcol[i] * ctl->vscale[i]) : C(0);
   S* w = V + (size_t)(j + 1) * vstride;
+  S* zw = zt + (size_t)(j + 1) * zstride;
   const int L = xcd_block(ln.G);
   constexpr int CH = basis_chunk<S, VEC>() < NDM ? basis_chunk<S, VEC>() : NDM;
   constexpr bool EARLY = bj_early<S, VEC, BS>();
@@ -1047,7 +1050,7 @@ __global__ __launch_bounds__(TPB) void k_gm_orth(Launch ln, S* __restrict__ V, s
       C zv[VEC];
       if constexpr (EARLY) bj_mul<C, S, VEC, BS, AD>(dinv, e, R, valid, wv, zv);
       else bj_apply_lane<C, S, VEC, BS, AD>(dinv, e, valid, wv, zv);
-      if (valid) storev<S, C, VEC>(zt + e, zv);
+      if (valid) storev<S, C, VEC>(zw + e, zv);
     }
     acc[0] += (double)s;
   }

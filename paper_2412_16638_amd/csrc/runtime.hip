@@ -650,6 +650,8 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   } else {
     o_V = take(vlp * (size_t)(p.restart + 1));
     o_z = (bs || fdm) ? take(vlp) : 0;
+    // the stored preconditioned directions BJ(V_0) .. BJ(V_m) of the gather form
+    o_Zb = (bs && !fdm) ? take(vlp * (size_t)(p.restart + 1)) : 0;
     o_r = o_p0 = o_p1 = o_q = o_x = 0;
     if (gform_ok & 4) {  // folded form: products alternate between W0 and W1 (W1 reuses BJ(V_0)'s)
       o_w0 = take(vlp);
@@ -812,6 +814,7 @@ EngineCtx mprk_handle::ctx() const {
   c.x = ws + o_x;
   c.V = ws + o_V;
   c.vstride = vstride;
+  c.Zb = (o_Zb && gform == 0) ? ws + o_Zb : nullptr;
   c.reorth = prec.krylov == MPRK_GMRES && prec.reorth;
   c.gform = gform;
   c.zl = zl_lp;

@@ -69,7 +69,7 @@ struct mprk_handle {
   double kscale = 1.0;
   // workspace layout (byte offsets)
   size_t o_rhs = 0, o_y = 0, o_res = 0, o_k = 0, o_keps = 0, o_scr = 0;
-  size_t o_r = 0, o_z = 0, o_p0 = 0, o_p1 = 0, o_q = 0, o_x = 0, o_V = 0;
+  size_t o_r = 0, o_z = 0, o_p0 = 0, o_p1 = 0, o_q = 0, o_x = 0, o_V = 0, o_Zb = 0;
   size_t vstride = 0;
   // block-Jacobi inverse sets, one per distinct sigma
   struct BJSet {

@@ -21,6 +21,8 @@ def test_gmres_block_jacobi_bytes_per_unknown():
     assert bench.algorithmic_bytes('gm_finish', N, s, m, bs, 1, 5) == N * (16 + 16 + 10)
     # with the FDM the combination writes t in the arithmetic type instead
     assert bench.algorithmic_bytes('gm_finish', N, s, m, 0, 1, 5, fdm=True, cb=4) == N * (4 + 10)
+    # stored directions BJ(v_i): the cycle's end reads no inverse
+    assert bench.algorithmic_bytes('gm_finish', N, s, m, bs, 1, 5, zstored=True) == N * (16 + 10)
     # work scales with the launches that worked
     assert bench.algorithmic_bytes('residual', N, s, m, bs, 3, 3) == 3 * N * 32
 
