@@ -148,9 +148,10 @@ typedef struct {
  *           a form the problem does not allow returns MPRK_EUNSUPPORTED from mprk_create.
  *  bj_adapt_tol: 0 = block-Jacobi inverses stored in the storage type (default); > 0 =
  *           adaptive precision (the Ginkgo preconditioner cited in the Introduction): each
- *           block's inverse may be stored in FP16, FP32 or FP64, the lowest whose unit roundoff u
- *           satisfies u * cond_1(D_b) <= bj_adapt_tol and whose range holds the inverse's
- *           entries; blocks are grouped in chunks of 64 lane groups (the rows one wave reads)
+ *           block's inverse may be stored in FP8 (E4M3), FP16, FP32 or FP64, the lowest whose unit
+ *           roundoff u satisfies u * cond_1(D_b) <= bj_adapt_tol (for FP8 plus
+ *           bs * 2^-10 * ||D_b||_1, its flush of entries below 2^-9) and whose range holds the
+ *           inverse's entries; blocks are grouped in chunks of 64 lane groups (the rows one wave reads)
  *           stored in the widest type their blocks need.  The apply computes in the compute
  *           type.  Needs bj_shared = 0; not in the batched form.
  *  bj_shared: 0 = one stored inverse per block-Jacobi block (default); 1 = store each distinct
@@ -348,8 +349,8 @@ typedef struct {
   int32_t nit_vec, nit_row, nit_vec_red, nit_row_red, nit_lp, nit_lp_red;
   int32_t residual_planes;
   int32_t gm_form, gm_planes;
-  int64_t bj_chunks[3];  /* adaptive-precision block-Jacobi: chunks stored in FP16, FP32, FP64
-                            (summed over the distinct stage shifts; 0 without it) */
+  int64_t bj_chunks[4];  /* adaptive-precision block-Jacobi: chunks stored in FP8 (E4M3), FP16,
+                            FP32, FP64 (summed over the distinct stage shifts; 0 without it) */
 } mprk_launch_info;
 int32_t mprk_launch_info_get(const mprk_handle *h, mprk_launch_info *out);
 

@@ -86,7 +86,7 @@ class mprk_launch_info(C.Structure):
     _fields_ = [('nit_vec', C.c_int32), ('nit_row', C.c_int32), ('nit_vec_red', C.c_int32),
                 ('nit_row_red', C.c_int32), ('nit_lp', C.c_int32), ('nit_lp_red', C.c_int32),
                 ('residual_planes', C.c_int32), ('gm_form', C.c_int32), ('gm_planes', C.c_int32),
-                ('bj_chunks', C.c_int64 * 3)]
+                ('bj_chunks', C.c_int64 * 4)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

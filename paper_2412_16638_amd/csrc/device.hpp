@@ -477,9 +477,9 @@ __host__ __device__ inline size_t bj_chunks(long nrows, int vec) {
   return (size_t)((groups + 63) / 64) * 64 * vec;
 }
 // Mode 4 (adaptive precision): the rows of each chunk of 64 lane groups (the interleave unit
-// of mode 3) are stored in one type chosen per chunk, tag[c] = 0 FP16, 1 FP32, 2 FP64, from
-// byte offset aoff[c] of the inverse area; within a chunk, row r = VEC g + q of the lane group g
-// is at entry (q * 64 + g % 64) * BS of the chunk's type.
+// of mode 3) are stored in one type chosen per chunk, tag[c] = 0 FP8 E4M3, 1 FP16, 2 FP32,
+// 3 FP64, from byte offset aoff[c] of the inverse area; within a chunk, row r = VEC g + q of the
+// lane group g is at entry (q * 64 + g % 64) * BS of the chunk's type.
 struct BJDesc {
   const void* inv;
   const int* idx;
@@ -502,14 +502,33 @@ __host__ __device__ inline BJ<S> bj_typed(const BJDesc& d) {
   return BJ<S>{(const S*)d.inv, d.idx, d.mode, d.tag, d.aoff};
 }
 
-// One row of an adaptive-precision inverse, converted to the compute type.
+// One row of an adaptive-precision inverse, converted to the compute type (tag 0 FP8 E4M3,
+// 1 FP16, 2 FP32, 3 FP64).
 template <typename C, int BS>
 __device__ __forceinline__ void bj_row_adaptive(const void* base, int tag, size_t ent, C (&w)[BS]) {
   if (tag == 0) {
+    const unsigned char* pb = (const unsigned char*)base + ent;
+    if constexpr (BS >= 4) {
+#pragma unroll
+      for (int q = 0; q < BS / 4; ++q) {
+        const int word = *reinterpret_cast<const int*>(pb + 4 * q);
+        w[4 * q + 0] = (C)__builtin_amdgcn_cvt_f32_fp8(word, 0);
+        w[4 * q + 1] = (C)__builtin_amdgcn_cvt_f32_fp8(word, 1);
+        w[4 * q + 2] = (C)__builtin_amdgcn_cvt_f32_fp8(word, 2);
+        w[4 * q + 3] = (C)__builtin_amdgcn_cvt_f32_fp8(word, 3);
+      }
+    } else {
+      int word = 0;
+#pragma unroll
+      for (int k = 0; k < BS; ++k) word |= (int)pb[k] << (8 * k);
+      w[0] = (C)__builtin_amdgcn_cvt_f32_fp8(word, 0);
+      if constexpr (BS > 1) w[1] = (C)__builtin_amdgcn_cvt_f32_fp8(word, 1);
+    }
+  } else if (tag == 1) {
     const Vec<half_t, BS> t = *reinterpret_cast<const Vec<half_t, BS>*>((const half_t*)base + ent);
 #pragma unroll
     for (int k = 0; k < BS; ++k) w[k] = (C)t.v[k];
-  } else if (tag == 1) {
+  } else if (tag == 2) {
     const Vec<float, BS> t = *reinterpret_cast<const Vec<float, BS>*>((const float*)base + ent);
 #pragma unroll
     for (int k = 0; k < BS; ++k) w[k] = (C)t.v[k];
@@ -576,13 +595,71 @@ __device__ __forceinline__ void bj_gather(const C (&r)[VEC], C (&rb)[BS > VEC ? 
 template <typename S, int VEC, int BS>
 struct BJRows {
   Vec<S, BS> row[VEC];
-  bool late;  // mode 4, chunk stored in another type than S: rows are loaded where applied
+  bool late;  // mode 4, chunk stored in a wider type than S: rows are loaded where applied
+  int tag;    // mode 4: type tag of the rows held (a narrower type's rows are kept as raw bits)
 };
 
-// Type tag of the storage type S in the adaptive layout (0 FP16, 1 FP32, 2 FP64).
+// Type tag of the storage type S in the adaptive layout (0 FP8 E4M3, 1 FP16, 2 FP32, 3 FP64).
 template <typename S>
 __host__ __device__ constexpr int bj_type_tag() {
-  return sizeof(S) == 2 ? 0 : sizeof(S) == 4 ? 1 : 2;
+  return sizeof(S) == 2 ? 1 : sizeof(S) == 4 ? 2 : 3;
+}
+
+// Rows of a chunk stored in a narrower type than S (W 32-bit words per row), kept as raw bits
+// in the first W words of each row of S.
+template <typename S, int VEC, int BS, int W>
+__device__ __forceinline__ void bj_load_narrow(const char* base, int g, BJRows<S, VEC, BS>& R) {
+  if constexpr (W > 0 && W * 4 <= (int)sizeof(S) * BS && (W * 4) % BS == 0) {
+    constexpr int NW = (int)sizeof(S) * BS / 4;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      const Vec<unsigned, W> u =
+          *reinterpret_cast<const Vec<unsigned, W>*>(base + ((size_t)i * 64 + (g & 63)) * (W * 4));
+      Vec<unsigned, NW> full{};
+#pragma unroll
+      for (int k = 0; k < W; ++k) full.v[k] = u.v[k];
+      R.row[i] = __builtin_bit_cast(Vec<S, BS>, full);
+    }
+  }
+}
+
+// The BS entries of a row held as raw bits of the narrower type of tag (0 FP8 E4M3, 1 FP16,
+// 2 FP32), converted to the compute type.
+template <typename C, typename S, int BS>
+__device__ __forceinline__ void bj_decode_narrow(const Vec<S, BS>& row, int tag, C (&w)[BS]) {
+  constexpr int NW = (int)sizeof(S) * BS / 4;
+#pragma unroll
+  for (int k = 0; k < BS; ++k) w[k] = C(0);
+  if constexpr (NW == 0 || (int)sizeof(S) * BS % 4 != 0) {
+    return;  // no narrower row fits (never loaded as such)
+  } else {
+    const Vec<unsigned, NW> u = __builtin_bit_cast(Vec<unsigned, NW>, row);
+    if (tag == 0) {
+      if constexpr (BS % 4 == 0 && BS / 4 <= NW) {
+#pragma unroll
+        for (int q = 0; q < BS / 4; ++q) {
+          w[4 * q + 0] = (C)__builtin_amdgcn_cvt_f32_fp8((int)u.v[q], 0);
+          w[4 * q + 1] = (C)__builtin_amdgcn_cvt_f32_fp8((int)u.v[q], 1);
+          w[4 * q + 2] = (C)__builtin_amdgcn_cvt_f32_fp8((int)u.v[q], 2);
+          w[4 * q + 3] = (C)__builtin_amdgcn_cvt_f32_fp8((int)u.v[q], 3);
+        }
+      }
+    } else if (tag == 1) {
+      if constexpr (BS % 2 == 0 && BS / 2 <= NW) {
+#pragma unroll
+        for (int q = 0; q < BS / 2; ++q) {
+          const Vec<half_t, 2> h = __builtin_bit_cast(Vec<half_t, 2>, u.v[q]);
+          w[2 * q + 0] = (C)h.v[0];
+          w[2 * q + 1] = (C)h.v[1];
+        }
+      }
+    } else {
+      if constexpr (BS <= NW) {
+#pragma unroll
+        for (int k = 0; k < BS; ++k) w[k] = (C)__builtin_bit_cast(float, u.v[k]);
+      }
+    }
+  }
 }
 
 // AD = 1: the adaptive-precision layout (mode 4) is possible; kernels are instantiated apart for
@@ -591,18 +668,29 @@ template <typename S, int VEC, int BS, int AD = 0>
 __device__ __forceinline__ void bj_load(const BJ<S>& dinv, int e, bool valid, BJRows<S, VEC, BS>& R) {
   R.late = false;
   if (AD && dinv.mode == 4) {
-    // adaptive precision: a chunk stored in the storage type is loaded here like mode 3; others
-    // where the rows are applied (converted from their own type)
+    // adaptive precision: a chunk stored in the storage type or a narrower one is loaded here
+    // (a narrower row's bits fill the first bytes of a row of S); a wider one where the rows are
+    // applied
+    constexpr int TS = bj_type_tag<S>();
     const int g = valid ? e / VEC : 0;
     const int ch = g >> 6;
-    if (dinv.tag[ch] != bj_type_tag<S>()) {
-      R.late = true;
-      return;
-    }
-    const S* base = (const S*)((const char*)dinv.inv + dinv.aoff[ch]);
+    const int tag = dinv.tag[ch];
+    R.tag = tag;
+    const char* base = (const char*)dinv.inv + dinv.aoff[ch];
+    if (tag == TS) {
 #pragma unroll
-    for (int i = 0; i < VEC; ++i)
-      R.row[i] = *reinterpret_cast<const Vec<S, BS>*>(base + ((size_t)i * 64 + (g & 63)) * BS);
+      for (int i = 0; i < VEC; ++i)
+        R.row[i] = *reinterpret_cast<const Vec<S, BS>*>((const S*)base +
+                                                         ((size_t)i * 64 + (g & 63)) * BS);
+    } else if (tag == 0 && TS > 0 && BS % 4 == 0) {
+      bj_load_narrow<S, VEC, BS, BS / 4>(base, g, R);
+    } else if (tag == 1 && TS > 1 && BS % 2 == 0) {
+      bj_load_narrow<S, VEC, BS, BS / 2>(base, g, R);
+    } else if (tag == 2 && TS > 2) {
+      bj_load_narrow<S, VEC, BS, BS>(base, g, R);
+    } else {
+      R.late = true;
+    }
     return;
   }
   size_t off[VEC];
@@ -622,8 +710,29 @@ __device__ __forceinline__ void bj_apply_lane(const BJ<S>& dinv, int e, bool val
 template <typename C, typename S, int VEC, int BS, int AD = 0>
 __device__ __forceinline__ void bj_mul(const BJ<S>& dinv, int e, const BJRows<S, VEC, BS>& R,
                                        bool valid, const C (&r)[VEC], C (&z)[VEC]) {
-  if (AD && dinv.mode == 4 && R.late) bj_apply_lane<C, S, VEC, BS, AD>(dinv, e, valid, r, z);
-  else bj_mul<C, S, VEC, BS>(R, valid, r, z);
+  if (AD && dinv.mode == 4 && R.late) {
+    bj_apply_lane<C, S, VEC, BS, AD>(dinv, e, valid, r, z);
+  } else if (AD && dinv.mode == 4 && R.tag != bj_type_tag<S>()) {
+    C rb[BS > VEC ? BS : 1];
+    bj_gather<C, VEC, BS>(r, rb);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      C w[BS];
+      bj_decode_narrow<C, S, BS>(R.row[q], R.tag, w);
+      C acc = C(0);
+      if constexpr (BS > VEC) {
+#pragma unroll
+        for (int k = 0; k < BS; ++k) acc += w[k] * rb[k];
+      } else {
+        const int sb = q / BS;
+#pragma unroll
+        for (int k = 0; k < BS; ++k) acc += w[k] * r[sb * BS + k];
+      }
+      z[q] = valid ? acc : C(0);
+    }
+  } else {
+    bj_mul<C, S, VEC, BS>(R, valid, r, z);
+  }
 }
 
 template <typename C, typename S, int VEC, int BS>

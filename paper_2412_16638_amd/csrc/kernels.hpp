@@ -1586,7 +1586,8 @@ __device__ inline void bj_store(S* dinv, int blk, int BS, int n, const double (&
 }
 
 // Block blk's inverse in the adaptive-precision layout (mode 4) for lanes of `lay` rows: each
-// row in its chunk's type (tag 0 FP16, 1 FP32, 2 FP64) at the chunk's byte offset.
+// row in its chunk's type (tag 0 FP8 E4M3, rounded to nearest even; 1 FP16, 2 FP32, 3 FP64) at
+// the chunk's byte offset.
 __device__ inline void bj_store_adaptive(void* base, const int* tag, const long long* aoff, int blk,
                                          int BS, int n, const double (&inv)[BJ_MAX][BJ_MAX], int lay) {
   for (int i = 0; i < BS; ++i) {
@@ -1597,8 +1598,11 @@ __device__ inline void bj_store_adaptive(void* base, const int* tag, const long 
     char* p = (char*)base + aoff[ch];
     for (int k = 0; k < BS; ++k) {
       const double v = (i < n && k < n) ? inv[i][k] : (i == k ? 1.0 : 0.0);
-      if (tag[ch] == 0) ((half_t*)p)[ent + k] = (half_t)v;
-      else if (tag[ch] == 1) ((float*)p)[ent + k] = (float)v;
+      if (tag[ch] == 0)
+        ((unsigned char*)p)[ent + k] =
+            (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32((float)v, 0.0f, 0, false) & 0xff);
+      else if (tag[ch] == 1) ((half_t*)p)[ent + k] = (half_t)v;
+      else if (tag[ch] == 2) ((float*)p)[ent + k] = (float)v;
       else ((double*)p)[ent + k] = v;
     }
   }

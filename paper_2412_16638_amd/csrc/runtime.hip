@@ -220,7 +220,8 @@ static void bj_dedup(const Geo& geo, const Coef<double>& K, double sigma, int bs
 // Introduction: each diagonal block's inverse stored in the lowest precision its conditioning
 // allows).  A block may be stored in a type of unit roundoff u when u * cond_1(D_b) <= tol
 // (the rounding of the stored inverse then perturbs the preconditioned block by at most about
-// tol) and its inverse's entries are within that type's range; FP16, FP32, FP64 in that order.
+// tol) and its inverse's entries are within that type's range; FP8, FP16, FP32, FP64 in that
+// order.
 // The type is chosen per chunk of 64 lane groups of vec rows (the unit a wave reads), as the
 // widest its blocks need.  Fills tag (per chunk) and aoff (per chunk byte offsets, plus the
 // total at the end); the distinct blocks are found as for the shared-inverse table.
@@ -249,7 +250,7 @@ static void bj_adaptive_layout(const Geo& geo, const Coef<double>& K, double sig
     }
     double a2[BJ_MAX][BJ_MAX];
     std::memcpy(a2, a, sizeof(a));
-    int t = 2;
+    int t = 3;
     if (!gj_invert(a2, inv, n)) {
       double ni = 0.0, mx = 0.0;
       for (int k = 0; k < n; ++k) {
@@ -261,8 +262,12 @@ static void bj_adaptive_layout(const Geo& geo, const Coef<double>& K, double sig
         ni = std::max(ni, cs);
       }
       const double kappa = n1 * ni;
-      if (std::ldexp(1.0, -11) * kappa <= tol && mx < 6.0e4) t = 0;
-      else if (std::ldexp(1.0, -24) * kappa <= tol && mx < 1.0e38) t = 1;
+      // FP8 (E4M3: unit roundoff 2^-4, largest finite 448, spacing 2^-9 below its smallest
+      // normal 2^-6): an entry's error is at most max(2^-4 |x|, 2^-10), so the inverse's
+      // relative 1-norm error adds n 2^-10 / ||D^-1||_1, i.e. n 2^-10 ||D||_1 to u kappa
+      if (std::ldexp(1.0, -4) * kappa + std::ldexp(1.0, -10) * n * n1 <= tol && mx <= 448.0) t = 0;
+      else if (std::ldexp(1.0, -11) * kappa <= tol && mx < 6.0e4) t = 1;
+      else if (std::ldexp(1.0, -24) * kappa <= tol && mx < 1.0e38) t = 2;
     }
     rtag[s] = t;
   }
@@ -277,7 +282,7 @@ static void bj_adaptive_layout(const Geo& geo, const Coef<double>& K, double sig
   aoff.assign((size_t)nch + 1, 0);
   const long long per = 64LL * vec * bs;  // entries per chunk
   for (int ch = 0; ch < nch; ++ch) {
-    const long long bytes = per * (tag[(size_t)ch] == 0 ? 2 : tag[(size_t)ch] == 1 ? 4 : 8);
+    const long long bytes = per * (1LL << tag[(size_t)ch]);  // 1, 2, 4, 8 bytes per entry
     aoff[(size_t)ch + 1] = aoff[(size_t)ch] + ((bytes + 255) & ~255LL);
   }
 }
@@ -1357,7 +1362,7 @@ extern "C" int32_t mprk_launch_info_get(const mprk_handle* h, mprk_launch_info* 
   out->residual_planes = h->zm_lz;
   out->gm_form = h->prec.krylov == MPRK_GMRES ? h->gform + 1 : 0;
   out->gm_planes = h->prec.krylov == MPRK_GMRES && h->gform > 0 ? h->zl_lp.LZ : 0;
-  for (int t = 0; t < 3; ++t) out->bj_chunks[t] = 0;
+  for (int t = 0; t < 4; ++t) out->bj_chunks[t] = 0;
   for (const auto& B : h->bjsets)
     for (int t : B.tag) out->bj_chunks[t] += 1;
   return MPRK_OK;

@@ -81,7 +81,7 @@ struct mprk_handle {
     size_t o_inv = 0, o_reps = 0, o_idx = 0, o_tag = 0, o_aoff = 0;
     std::vector<int> reps; // representative block of each slot (modes 1, 2)
     std::vector<int> idx;  // slot of each block (mode 1)
-    std::vector<int> tag;  // mode 4: storage type of each chunk (0 FP16, 1 FP32, 2 FP64)
+    std::vector<int> tag;  // mode 4: storage type of each chunk (0 FP8 E4M3, 1 FP16, 2 FP32, 3 FP64)
     std::vector<long long> aoff;  // mode 4: byte offset of each chunk in the inverse area
   };
   std::vector<BJSet> bjsets;

@@ -1,8 +1,9 @@
 """The adaptive-precision block-Jacobi layout on the host (no device): the storage type the
 library picks for every chunk of 64 lane groups equals the rule evaluated here from the oracle's
-stage matrix -- the lowest of FP16, FP32, FP64 whose unit roundoff times the block's 1-norm
-condition number is within the tolerance (Ginkgo's adaptive block-Jacobi, cited in the paper's
-Introduction; the rule's constants are this library's reading)."""
+stage matrix -- the lowest of FP8 (E4M3), FP16, FP32, FP64 whose unit roundoff times the block's
+1-norm condition number (for FP8 plus its flush of entries below 2^-9, n 2^-10 ||D||_1) is within
+the tolerance and whose range holds the inverse (Ginkgo's adaptive block-Jacobi, cited in the
+paper's Introduction; the rule's constants are this library's reading)."""
 import ctypes as C
 
 import numpy as np
@@ -13,7 +14,7 @@ from oracle import operators
 
 A = pytest.importorskip('paper_2412_16638_amd._abi')
 
-U = [2.0 ** -11, 2.0 ** -24, 2.0 ** -53]
+U = [2.0 ** -4, 2.0 ** -11, 2.0 ** -24, 2.0 ** -53]  # FP8 (E4M3), FP16, FP32, FP64
 
 
 def expected_chunk_types(shape, bc, kind, diff, b, sigma, bs, vec, tol):
@@ -24,12 +25,15 @@ def expected_chunk_types(shape, bc, kind, diff, b, sigma, bs, vec, tol):
     for s in range(0, N, bs):
         D = M[s:min(s + bs, N), s:min(s + bs, N)].toarray()
         Di = np.linalg.inv(D)
-        kappa = np.abs(D).sum(axis=0).max() * np.abs(Di).sum(axis=0).max()
-        t = 2
-        if U[0] * kappa <= tol and np.abs(Di).max() < 6.0e4:
+        n1 = np.abs(D).sum(axis=0).max()
+        kappa = n1 * np.abs(Di).sum(axis=0).max()
+        t = 3
+        if U[0] * kappa + 2.0 ** -10 * D.shape[0] * n1 <= tol and np.abs(Di).max() <= 448.0:
             t = 0
-        elif U[1] * kappa <= tol:
+        elif U[1] * kappa <= tol and np.abs(Di).max() < 6.0e4:
             t = 1
+        elif U[2] * kappa <= tol:
+            t = 2
         t_blk.append(t)
     groups = -(-nblk * bs // vec)
     nch = -(-groups // 64)
@@ -37,7 +41,7 @@ def expected_chunk_types(shape, bc, kind, diff, b, sigma, bs, vec, tol):
     for bi, t in enumerate(t_blk):
         ch = (bi * bs // vec) // 64
         tags[ch] = max(tags[ch], t)
-    return [tags.count(k) for k in range(3)]
+    return [tags.count(k) for k in range(4)]
 
 
 def _launch_info(shape, bc, kind, diff, b, storage, krylov, tol, dt=2e-3):
@@ -53,7 +57,7 @@ def _launch_info(shape, bc, kind, diff, b, storage, krylov, tol, dt=2e-3):
         A.mprk_destroy(h)
 
 
-@pytest.mark.parametrize("tol", [1e-1, 1e-5, 1e-12])
+@pytest.mark.parametrize("tol", [5e-1, 1e-1, 1e-5, 1e-12])
 @pytest.mark.parametrize("case", [
     ((16, 12, 10), W.DIRICHLET, W.HEAT, 1.0, (0, 0, 0), A.FP32, A.CG, 4),
     ((13, 9, 7), W.DIRICHLET, W.HEAT, 2.5, (0, 0, 0), A.FP64, A.CG, 1),
@@ -82,7 +86,7 @@ def test_a_tolerance_between_block_conditions_mixes_types():
                                    sg).tocsr()
         D = M[0:8, 0:8].toarray()
         kap.append(np.abs(D).sum(axis=0).max() * np.abs(np.linalg.inv(D)).sum(axis=0).max())
-    tol = U[0] * np.sqrt(min(kap) * max(kap))
+    tol = U[1] * np.sqrt(min(kap) * max(kap))
     g = A.mprk_grid(*shape, W.DIRICHLET)
     o = A.mprk_operator(W.HEAT, A.FMT_STENCIL, 1.0, (C.c_double * 3)(0, 0, 0))
     p = A.mprk_precisions_default(A.FP32, A.CG)
@@ -90,12 +94,23 @@ def test_a_tolerance_between_block_conditions_mixes_types():
     h = A.mprk_create(g, o, t, p, dt, 0)
     li = A.mprk_launch_info_get(h)
     A.mprk_destroy(h)
-    want = [0, 0, 0]
+    want = [0, 0, 0, 0]
     for sg in sigmas:
         c = expected_chunk_types(shape, W.DIRICHLET, W.HEAT, 1.0, (0, 0, 0), sg, 8, 4, tol)
         want = [a + b for a, b in zip(want, c)]
     assert li['bj_chunks'] == want
-    assert want[0] > 0 and want[1] > 0
+    assert want[1] > 0 and want[2] > 0
+
+
+def test_a_loose_tolerance_stores_fp8_inverses():
+    # advection-diffusion blocks on a small periodic grid: cond_1 about 1.09, so the FP8 bound
+    # 2^-4 kappa + 8 2^-10 ||D||_1 (about 0.077) qualifies at 0.1 and not at 0.05
+    case = ((32, 16, 8), W.PERIODIC, W.ADVDIFF, 1e-2, (1.0, 0.5, 0.25))
+    for tol, fp8 in ((0.1, True), (0.05, False)):
+        li, t = _launch_info(*case, A.FP16, A.GMRES, tol)
+        want = expected_chunk_types(*case, 2e-3 * t.a_lo[0], 8, 8, tol)
+        assert li['bj_chunks'] == want
+        assert (want[0] > 0) == fp8, (tol, want)
 
 
 def test_adaptive_needs_one_inverse_per_block():

@@ -23,6 +23,8 @@ def test_gmres_block_jacobi_bytes_per_unknown():
     assert bench.algorithmic_bytes('gm_finish', N, s, m, 0, 1, 5, fdm=True, cb=4) == N * (4 + 10)
     # stored directions BJ(v_i): the cycle's end reads no inverse
     assert bench.algorithmic_bytes('gm_finish', N, s, m, bs, 1, 5, zstored=True) == N * (16 + 10)
+    # adaptive inverses: FP8 entries (1 byte) in place of the storage type's
+    assert bench.algorithmic_bytes('gm_orth', N, s, m, bs, 1, 3, inv_entry=1.0) == N * (2 + 2 + 8 + 2 + 6)
     # work scales with the launches that worked
     assert bench.algorithmic_bytes('residual', N, s, m, bs, 3, 3) == 3 * N * 32
 

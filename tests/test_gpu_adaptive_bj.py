@@ -16,7 +16,7 @@ M = pytest.importorskip('paper_2412_16638_amd')
 A = M._abi
 
 U = {A.FP64: 2.0 ** -53, A.FP32: 2.0 ** -24, A.FP16: 2.0 ** -11}
-UT = [2.0 ** -11, 2.0 ** -24, 2.0 ** -53]      # chunk type 0, 1, 2
+UT = [2.0 ** -4, 2.0 ** -11, 2.0 ** -24, 2.0 ** -53]  # chunk type 0 FP8 (E4M3), 1, 2, 3
 TINY = {A.FP64: 0.0, A.FP32: 2.0 ** -150, A.FP16: 2.0 ** -25}
 NP = {A.FP64: np.float64, A.FP32: np.float32, A.FP16: np.float16}
 CASES = [
@@ -32,12 +32,15 @@ def row_types(inv, N, bs, vec, tol):
     t_blk = []
     for bi, Di in enumerate(inv):
         s = bi * bs
-        kappa = np.abs(np.linalg.inv(Di)).sum(axis=0).max() * np.abs(Di).sum(axis=0).max()
-        t = 2
-        if UT[0] * kappa <= tol and np.abs(Di).max() < 6.0e4:
+        n1 = np.abs(np.linalg.inv(Di)).sum(axis=0).max()
+        kappa = n1 * np.abs(Di).sum(axis=0).max()
+        t = 3
+        if UT[0] * kappa + 2.0 ** -10 * Di.shape[0] * n1 <= tol and np.abs(Di).max() <= 448.0:
             t = 0
-        elif UT[1] * kappa <= tol:
+        elif UT[1] * kappa <= tol and np.abs(Di).max() < 6.0e4:
             t = 1
+        elif UT[2] * kappa <= tol:
+            t = 2
         t_blk.append(t)
     nch = -(-(-(-len(inv) * bs // vec)) // 64)
     tags = [0] * nch
@@ -46,7 +49,7 @@ def row_types(inv, N, bs, vec, tol):
     return np.array([tags[(r // vec) // 64] for r in range(N)])
 
 
-@pytest.mark.parametrize("tol", [1e-1, 1e-5, 1e-13])
+@pytest.mark.parametrize("tol", [5e-1, 1e-1, 1e-5, 1e-13])
 @pytest.mark.parametrize("storage", ['fp64', 'fp32', 'fp16'])
 @pytest.mark.parametrize("fmt", [A.FMT_STENCIL, A.FMT_CSR])
 @pytest.mark.parametrize("case", CASES)
@@ -65,7 +68,7 @@ def test_adaptive_block_jacobi_apply(case, fmt, storage, tol):
     Mx = operators.stage_matrix(operators.operator(shape, bc, kind, diff, b), sigma)
     inv = krylov.block_jacobi_inverses(Mx, 8)
     types = row_types(inv, st.N, 8, lanes, tol)
-    counts = [int(np.sum(types[::1] == k)) for k in range(3)]
+    counts = [int(np.sum(types[::1] == k)) for k in range(4)]
     st.close()
     assert sum(1 for c in vec['bj_chunks'] if c) == sum(1 for c in counts if c)
     xf = x_lp.astype(np.float64)
@@ -73,12 +76,17 @@ def test_adaptive_block_jacobi_apply(case, fmt, storage, tol):
     absd = krylov.block_jacobi_apply([np.abs(d) for d in inv], np.abs(xf), 8)
     u_c = U[A.FP64] if sd == A.FP64 else U[A.FP32]
     u_inv = np.array(UT)[types]
-    bound = 2 * U[sd] * np.abs(ref) + (16 * u_c + 2 * u_inv) * absd + TINY[sd]
+    # FP8 entries: error at most max(2^-4 |x|, 2^-10) (spacing 2^-9 below the smallest normal)
+    flush = np.where(types == 0, 2.0 ** -10, 0.0)
+    absx_blk = krylov.block_jacobi_apply([np.ones_like(d) for d in inv], np.abs(xf), 8)
+    bound = (2 * U[sd] * np.abs(ref) + (16 * u_c + 2 * u_inv) * absd + 2 * flush * absx_blk
+             + TINY[sd])
     assert np.all(np.abs(z - ref) <= bound + 1e-300)
 
 
 @pytest.mark.parametrize("fmt", [A.FMT_STENCIL, A.FMT_CSR])
-@pytest.mark.parametrize("storage,tol", [('fp32', 1e-1), ('fp16', 1e-5), ('fp64', 1e-1)])
+@pytest.mark.parametrize("storage,tol", [('fp32', 1e-1), ('fp16', 1e-5), ('fp64', 1e-1),
+                                         ('fp16', 5e-1), ('fp32', 5e-1)])
 def test_adaptive_block_jacobi_heat_steps(storage, tol, fmt):
     # FP32 vectors with FP16 inverses, FP16 vectors with FP32 inverses, an all-FP64 solve with
     # FP16 inverses (the preconditioner's precision bounds only its quality, not the result)
@@ -97,7 +105,7 @@ def test_adaptive_block_jacobi_heat_steps(storage, tol, fmt):
     assert all(stats['converged'])
 
 
-@pytest.mark.parametrize("storage,tol", [('fp16', 1e-5), ('fp32', 1e-1)])
+@pytest.mark.parametrize("storage,tol", [('fp16', 1e-5), ('fp32', 1e-1), ('fp16', 2.5e-1)])
 def test_adaptive_block_jacobi_advection_steps(storage, tol):
     p = W.advdiff_bump(n=32, nsteps=4)
     p.precision = storage
