@@ -148,12 +148,12 @@ typedef struct {
  *           a form the problem does not allow returns MPRK_EUNSUPPORTED from mprk_create.
  *  bj_adapt_tol: 0 = block-Jacobi inverses stored in the storage type (default); > 0 =
  *           adaptive precision (the Ginkgo preconditioner cited in the Introduction): each
- *           block's inverse may be stored in FP8 (E4M3), FP16, FP32 or FP64, the lowest whose unit
- *           roundoff u satisfies u * cond_1(D_b) <= bj_adapt_tol (for FP8 plus
+ *           block's inverse may be stored in FP8 (E4M3), FP16, FP32 or FP64, the lowest whose
+ *           unit roundoff u satisfies u * cond_1(D_b) <= bj_adapt_tol (for FP8 plus
  *           bs * 2^-10 * ||D_b||_1, its flush of entries below 2^-9) and whose range holds the
- *           inverse's entries; blocks are grouped in chunks of 64 lane groups (the rows one wave reads)
- *           stored in the widest type their blocks need.  The apply computes in the compute
- *           type.  Needs bj_shared = 0; not in the batched form.
+ *           inverse's entries; blocks are grouped in chunks of 64 lane groups (the rows one
+ *           wave reads) stored in the widest type their blocks need.  The apply computes in the
+ *           compute type.  Needs bj_shared = 0; not in the batched form.
  *  bj_shared: 0 = one stored inverse per block-Jacobi block (default); 1 = store each distinct
  *           diagonal block's inverse once plus a per-block index (a single shared inverse when
  *           all blocks coincide, e.g. constant coefficients with block | nx).  Both modes give
