@@ -77,6 +77,8 @@ def algorithmic_bytes(kc: str, N: int, s: int, m: int, bs: int, worked: int, uni
         return N * worked * ((6 if fdm else 7) * s + inv)
     if kc == 'cg_rz':
         return N * worked * 2 * s
+    if kc == 'apply64':  # f(u): u read, k written (the stencil's neighbours gathered)
+        return N * worked * (16 + csr_64)
     if kc == 'promote':
         return N * worked * (16 + s)
     if kc == 'stage_rhs':
@@ -338,6 +340,8 @@ def main():
     ap.add_argument('--bj-adapt', type=float, default=0.0, metavar='TOL',
                     help='adaptive-precision block-Jacobi inverses (mprk_precisions.bj_adapt_tol) '
                          'for the headline run; the default run also times TOL = 0.25 beside it')
+    ap.add_argument('--stage-start', default='auto', choices=['auto', 'rhs', 'slope', 'eval'],
+                    help='start value of the implicit stage solves (mprk_precisions.stage_start)')
     ap.add_argument('--n', type=int, default=128,
                     help='sweep mode: grid points per axis of the paper\'s test problems')
     ap.add_argument('--quick', action='store_true',
@@ -393,6 +397,9 @@ def main():
         mixed_over['gm_form'] = gmf
     if args.bj_adapt > 0:
         mixed_over['bj_adapt_tol'] = args.bj_adapt
+    if args.stage_start != 'auto':
+        mixed_over['stage_start'] = {'rhs': AB.START_RHS, 'slope': AB.START_SLOPE,
+                                     'eval': AB.START_SLOPE_EVAL}[args.stage_start]
     N = p.N
     K, Wm = args.steps, args.warmup
     log(f'workload {args.workload}: N={N} ({p.n}^3), {p.tableau}, dt={p.dt}, {p.krylov}, '
@@ -434,6 +441,10 @@ def main():
     s_bytes = {'fp64': 8, 'fp32': 4, 'fp16': 2}[p.precision]
     bs = st.prec.block if st.prec.precond == AB.PRECOND_BJ else 0
     nv = {'stage_rhs': 3, 'combine': 3}  # SDIRK3: sum over stages of rhs terms; b has 3 terms
+    # stages starting from rhs + sigma k_{i-1} (or + sigma f(u)) read one more FP64 vector
+    ss = launch['stage_start']
+    slope_starts = (p_stages(p) - (0 if ss == AB.START_SLOPE_EVAL else 1)) \
+        if ss in (AB.START_SLOPE, AB.START_SLOPE_EVAL) else 0
     rows = []
     nnz_row = 0.0
     if args.fmt == 'csr':  # 7-point rows; a zero-Dirichlet face row has one neighbour fewer
@@ -448,7 +459,7 @@ def main():
             continue
         nv_total = 0
         if kc == 'stage_rhs':
-            nv_total = r['worked'] // p_stages(p) * nv['stage_rhs']
+            nv_total = r['worked'] // p_stages(p) * (nv['stage_rhs'] + slope_starts)
         if kc == 'combine':
             nv_total = r['worked'] * nv['combine']
         sv = s_bytes

@@ -60,6 +60,7 @@ enum { MPRK_FP64 = 0, MPRK_FP32 = 1, MPRK_FP16 = 2 };
 enum { MPRK_CG = 0, MPRK_GMRES = 1 };
 enum { MPRK_PRECOND_NONE = 0, MPRK_PRECOND_BJ = 1, MPRK_PRECOND_FDM = 2 };
 enum { MPRK_GMFORM_AUTO = 0, MPRK_GMFORM_GATHER = 1, MPRK_GMFORM_ZSPLIT = 2, MPRK_GMFORM_FOLDED = 3 };
+enum { MPRK_START_AUTO = 0, MPRK_START_RHS = 1, MPRK_START_SLOPE = 2, MPRK_START_SLOPE_EVAL = 3 };
 enum { MPRK_TAB_SDIRK2 = 0, MPRK_TAB_SDIRK3 = 1, MPRK_TAB_MID = 2,
        MPRK_TAB_4S3PA = 3, MPRK_TAB_4S3PB = 4, MPRK_TAB_4S3PC = 5 };
 enum { MPRK_APPLY_K64 = 0,     /* y = K x, FP64 in/out */
@@ -157,7 +158,18 @@ typedef struct {
  *  bj_shared: 0 = one stored inverse per block-Jacobi block (default); 1 = store each distinct
  *           diagonal block's inverse once plus a per-block index (a single shared inverse when
  *           all blocks coincide, e.g. constant coefficients with block | nx).  Both modes give
- *           bitwise-identical inverses; mode 1 removes the inverse stream from the apply. */
+ *           bitwise-identical inverses; mode 1 removes the inverse stream from the apply.
+ *  stage_start: start value of an implicit stage's solve (the paper leaves it open):
+ *           MPRK_START_RHS = y = rhs_i; MPRK_START_SLOPE = y = rhs_i + sigma k_{i-1} for a stage
+ *           after the step's first, i.e. the stage slope taken equal to the previous stage's
+ *           (the first stage starts from rhs); MPRK_START_SLOPE_EVAL = as SLOPE, and an
+ *           implicit first stage from rhs + sigma f(u), f(u) evaluated in FP64 at the step's
+ *           start (one more operator evaluation per step).  A step thus depends on u alone,
+ *           never on an earlier call.  MPRK_START_AUTO (0) = with GMRES and the FP64 outer loop
+ *           SLOPE_EVAL for the FDM preconditioner and SLOPE otherwise; RHS for CG and in the
+ *           one-solve mode (refine_max = 0), whose result depends on the start value.  Every
+ *           start value is iterated to the same tolerances; it changes iteration and pass
+ *           counts (mprk_launch_info_get reports the one in use). */
 typedef struct {
   int32_t storage, compute;
   int32_t krylov, restart;
@@ -171,6 +183,7 @@ typedef struct {
   int32_t bj_shared;
   int32_t gm_form;
   double bj_adapt_tol;
+  int32_t stage_start;
 } mprk_precisions;
 
 /* Statistics.  Per-stage entries describe the most recent step. */
@@ -344,13 +357,14 @@ int32_t mprk_autotune(mprk_handle *h, int32_t *nit_vec, int32_t *nit_row);
  * thread of the streaming / reducing vector kernels (FP64 and LP) and CSR row kernels; planes
  * per z-marching tile of the FP64 residual (0 = gather kernel); the GMRES step form (an
  * MPRK_GMFORM value, 0 for CG) and its planes per tile (0 for the gather form); the storage
- * types of the adaptive block-Jacobi inverses.  Needs no device. */
+ * types of the adaptive block-Jacobi inverses; the stage start value.  Needs no device. */
 typedef struct {
   int32_t nit_vec, nit_row, nit_vec_red, nit_row_red, nit_lp, nit_lp_red;
   int32_t residual_planes;
   int32_t gm_form, gm_planes;
   int64_t bj_chunks[4];  /* adaptive-precision block-Jacobi: chunks stored in FP8 (E4M3), FP16,
                             FP32, FP64 (summed over the distinct stage shifts; 0 without it) */
+  int32_t stage_start;   /* the stage start value in use: an MPRK_START value other than AUTO */
 } mprk_launch_info;
 int32_t mprk_launch_info_get(const mprk_handle *h, mprk_launch_info *out);
 

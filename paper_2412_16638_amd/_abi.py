@@ -25,6 +25,7 @@ FP64, FP32, FP16 = 0, 1, 2
 CG, GMRES = 0, 1
 PRECOND_NONE, PRECOND_BJ, PRECOND_FDM = 0, 1, 2
 GMFORM_AUTO, GMFORM_GATHER, GMFORM_ZSPLIT, GMFORM_FOLDED = 0, 1, 2, 3
+START_AUTO, START_RHS, START_SLOPE, START_SLOPE_EVAL = 0, 1, 2, 3
 TAB_SDIRK2, TAB_SDIRK3, TAB_MID, TAB_4S3PA, TAB_4S3PB, TAB_4S3PC = range(6)
 APPLY_K64, APPLY_M_LP, APPLY_BJ_LP, APPLY_M64, APPLY_FDM_LP = range(5)
 KC_NAMES = ('stage_rhs', 'residual', 'cg_begin', 'cg_dir', 'cg_upd', 'promote', 'gm_begin',
@@ -57,7 +58,7 @@ class mprk_precisions(C.Structure):
                 ('rtol', C.c_double), ('atol', C.c_double), ('maxit', C.c_int32),
                 ('refine_max', C.c_int32), ('outer_tol', C.c_double), ('strict', C.c_int32),
                 ('reorth', C.c_int32), ('bj_shared', C.c_int32), ('gm_form', C.c_int32),
-                ('bj_adapt_tol', C.c_double)]
+                ('bj_adapt_tol', C.c_double), ('stage_start', C.c_int32)]
 
 
 class mprk_stats(C.Structure):
@@ -86,7 +87,7 @@ class mprk_launch_info(C.Structure):
     _fields_ = [('nit_vec', C.c_int32), ('nit_row', C.c_int32), ('nit_vec_red', C.c_int32),
                 ('nit_row_red', C.c_int32), ('nit_lp', C.c_int32), ('nit_lp_red', C.c_int32),
                 ('residual_planes', C.c_int32), ('gm_form', C.c_int32), ('gm_planes', C.c_int32),
-                ('bj_chunks', C.c_int64 * 4)]
+                ('bj_chunks', C.c_int64 * 4), ('stage_start', C.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -41,15 +41,18 @@ struct CombArgs {
   const double* v[2 * MAXS];
   double c[2 * MAXS];
   int nv;
+  const double* pv;  // k_stage_rhs: start value y = rhs + pc pv when set
+  double pc;
 };
 
 // ------------------------------------------------------------------------------------------
 // FP64 explicit parts
 // ------------------------------------------------------------------------------------------
 
-// rhs = u + sum_j c_j v_j ; y = rhs.  reset: RESET_STAGE clears the stage record, RESET_STEP
-// also the step's gating flags, RESET_CALL the strict halt of an earlier call.  A halted call
-// opens every later stage finished, so its solve kernels return at once.
+// rhs = u + sum_j c_j v_j ; y = rhs, or rhs + pc pv with a start value pv.  reset: RESET_STAGE
+// clears the stage record, RESET_STEP also the step's gating flags, RESET_CALL the strict halt of
+// an earlier call.  A halted call opens every later stage finished, so its solve kernels return
+// at once.
 template <int VEC>
 __global__ __launch_bounds__(TPB) void k_stage_rhs(Launch ln, const double* __restrict__ u,
                                                    CombArgs a, double* __restrict__ rhs,
@@ -88,6 +91,12 @@ __global__ __launch_bounds__(TPB) void k_stage_rhs(Launch ln, const double* __re
       for (int v = 0; v < VEC; ++v) acc[v] += c * t[v];
     }
     storev<double, double, VEC>(rhs + e, acc);
+    if (a.pv) {
+      double t[VEC];
+      loadv<double, double, VEC>(a.pv + e, t);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] += a.pc * t[v];
+    }
     storev<double, double, VEC>(y + e, acc);
   }
 }

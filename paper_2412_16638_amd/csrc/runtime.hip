@@ -488,6 +488,8 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
   if (p->gm_form < MPRK_GMFORM_AUTO || p->gm_form > MPRK_GMFORM_FOLDED)
     return set_error(MPRK_EINVAL, "gm_form must be one of the MPRK_GMFORM values");
   if (!(p->bj_adapt_tol >= 0.0)) return set_error(MPRK_EINVAL, "bj_adapt_tol must be >= 0");
+  if (p->stage_start < MPRK_START_AUTO || p->stage_start > MPRK_START_SLOPE_EVAL)
+    return set_error(MPRK_EINVAL, "stage_start must be one of the MPRK_START values");
   if (p->bj_adapt_tol > 0.0 && p->bj_shared)
     return set_error(MPRK_EINVAL, "adaptive-precision block-Jacobi stores one inverse per block "
                                   "(bj_shared must be 0)");
@@ -644,6 +646,18 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   // the fast-diagonalisation inverse is exact for the operators it accepts: one Krylov iteration
   // per pass, so no predicted iteration beyond the last solve's count
   predict_margin = fdm ? 0 : 1;
+  // the start value of the stage solves: with GMRES and the outer loop, the previous stage's
+  // slope is close enough to the new one on advection-dominated stages to save outer passes;
+  // the FP64 evaluation of f(u) pays for itself on the first stage only under the FDM
+  // preconditioner, whose passes reduce the residual further; with CG on stiff diffusion
+  // neither saves a pass (sigma K amplifies the slopes' high-frequency part)
+  start_mode = p.stage_start;
+  if (start_mode == MPRK_START_AUTO)
+    start_mode = (p.krylov == MPRK_GMRES && p.refine_max > 0)
+                     ? (fdm ? MPRK_START_SLOPE_EVAL : MPRK_START_SLOPE)
+                     : MPRK_START_RHS;
+  start_slope = start_mode >= MPRK_START_SLOPE;
+  start_eval = start_mode == MPRK_START_SLOPE_EVAL;
   if (p.krylov == MPRK_CG) {
     o_r = take(vlp);
     o_z = (bs || fdm) ? take(vlp) : o_r;
@@ -1245,6 +1259,11 @@ int mprk_handle::enqueue_step(bool first_of_call) {
   auto kvec = [&](int j) { return (double*)(ws + o_k + (size_t)j * N * 8); };
   auto evec = [&](int j) { return (double*)(ws + o_keps + (size_t)j * N * 8); };
   const int s = nstages;
+  double* f0 = (double*)(ws + o_scr);
+  if (start_eval && implicit_[0]) {  // f(u) for the first stage's start value
+    int rc = launch_apply64(u, f0, 0.0, 0, fterms());
+    if (rc) return rc;
+  }
   for (int i = 0; i < s; ++i) {
     CombArgs a{};
     a.nv = 0;
@@ -1265,6 +1284,13 @@ int mprk_handle::enqueue_step(bool first_of_call) {
         a.v[a.nv] = evec(j);
         a.c[a.nv++] = dt * al;
       }
+    }
+    if (start_slope && implicit_[i] && i > 0) {  // start value rhs + sigma k_{i-1}
+      a.pv = kvec(i - 1);
+      a.pc = cfgs[sig_idx[i]].sigma;
+    } else if (start_eval && implicit_[i] && i == 0) {  // rhs + sigma f(u)
+      a.pv = f0;
+      a.pc = cfgs[sig_idx[i]].sigma;
     }
     const int reset = i > 0 ? RESET_STAGE
                             : RESET_STAGE | RESET_STEP | (first_of_call ? RESET_CALL : 0);
@@ -1361,6 +1387,7 @@ extern "C" int32_t mprk_launch_info_get(const mprk_handle* h, mprk_launch_info* 
   out->nit_lp_red = h->ln_lp_red.nit;
   out->residual_planes = h->zm_lz;
   out->gm_form = h->prec.krylov == MPRK_GMRES ? h->gform + 1 : 0;
+  out->stage_start = h->start_mode;
   out->gm_planes = h->prec.krylov == MPRK_GMRES && h->gform > 0 ? h->zl_lp.LZ : 0;
   for (int t = 0; t < 4; ++t) out->bj_chunks[t] = 0;
   for (const auto& B : h->bjsets)

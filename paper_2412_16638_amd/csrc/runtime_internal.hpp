@@ -117,6 +117,9 @@ struct mprk_handle {
   int gm_chunk = 2;
   int lookahead = 1;
   int predict_margin = 1;  // iterations enqueued beyond the last solve's count (0 with FDM)
+  int start_mode = 0;        // the MPRK_START value in use (resolved from AUTO)
+  bool start_slope = false;  // implicit stages after the first start from rhs + sigma k_{i-1}
+  bool start_eval = false;   // the first implicit stage from rhs + sigma f(u)
   // per-stage history of the last completed solve (slot s = mprk_solve), used to enqueue each
   // pass's Krylov iterations without waiting for the device
   struct StageHist {

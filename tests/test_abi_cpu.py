@@ -234,3 +234,37 @@ def test_size_limit_of_int32_indexing():
     N = 659 ** 3
     assert A.lib.mprk_workspace_bytes(h) >= (3 + 3 + 1) * 8 * N
     A.lib.mprk_destroy(h)
+
+
+@pytest.mark.parametrize("krylov,precond,refine_max,want", [
+    (A.GMRES, A.PRECOND_BJ, 20, A.START_SLOPE),
+    (A.GMRES, A.PRECOND_FDM, 20, A.START_SLOPE_EVAL),
+    (A.GMRES, A.PRECOND_BJ, 0, A.START_RHS),      # one-solve mode: the result depends on it
+    (A.CG, A.PRECOND_BJ, 8, A.START_RHS),
+    (A.CG, A.PRECOND_FDM, 8, A.START_RHS),
+])
+def test_automatic_stage_start_resolution(krylov, precond, refine_max, want):
+    p = A.mprk_precisions_default(A.FP32, krylov)
+    p.precond = precond
+    p.refine_max = refine_max
+    rc, h = _create(prec=p, kind=1 if krylov == A.GMRES else 0, b=(1.0, 0.5, 0.25), bc=1,
+                    grid=(12, 10, 8))
+    assert rc == A.OK, A.mprk_last_error()
+    assert A.mprk_launch_info_get(h.value)['stage_start'] == want
+    A.lib.mprk_destroy(h)
+
+
+def test_stage_start_is_validated_and_kept_when_explicit():
+    for v in (A.START_RHS, A.START_SLOPE, A.START_SLOPE_EVAL):
+        p = A.mprk_precisions_default(A.FP32, A.CG)
+        p.stage_start = v
+        rc, h = _create(prec=p)
+        assert rc == A.OK, A.mprk_last_error()
+        assert A.mprk_launch_info_get(h.value)['stage_start'] == v
+        A.lib.mprk_destroy(h)
+    for v in (-1, 4):
+        p = A.mprk_precisions_default(A.FP32, A.CG)
+        p.stage_start = v
+        rc, _ = _create(prec=p)
+        assert rc == A.EINVAL
+        assert 'stage_start' in A.mprk_last_error()
