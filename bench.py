@@ -441,10 +441,9 @@ def main():
     s_bytes = {'fp64': 8, 'fp32': 4, 'fp16': 2}[p.precision]
     bs = st.prec.block if st.prec.precond == AB.PRECOND_BJ else 0
     nv = {'stage_rhs': 3, 'combine': 3}  # SDIRK3: sum over stages of rhs terms; b has 3 terms
-    # stages starting from rhs + sigma k_{i-1} (or + sigma f(u)) read one more FP64 vector
-    ss = launch['stage_start']
-    slope_starts = (p_stages(p) - (0 if ss == AB.START_SLOPE_EVAL else 1)) \
-        if ss in (AB.START_SLOPE, AB.START_SLOPE_EVAL) else 0
+    # start values: k_{i-1} is already a term of rhs_i (a_{i,i-1} != 0 in SDIRK3), so the slope
+    # start reads nothing new; the first stage's rhs + sigma f(u) reads f(u)
+    slope_starts = 1 if launch['stage_start'] == AB.START_SLOPE_EVAL else 0
     rows = []
     nnz_row = 0.0
     if args.fmt == 'csr':  # 7-point rows; a zero-Dirichlet face row has one neighbour fewer
