@@ -340,7 +340,7 @@ def main():
     ap.add_argument('--bj-adapt', type=float, default=0.0, metavar='TOL',
                     help='adaptive-precision block-Jacobi inverses (mprk_precisions.bj_adapt_tol) '
                          'for the headline run; the default run also times TOL = 0.25 beside it')
-    ap.add_argument('--stage-start', default='auto', choices=['auto', 'rhs', 'slope', 'eval'],
+    ap.add_argument('--stage-start', default='auto', choices=['auto', 'rhs', 'slope', 'eval', 'extrap'],
                     help='start value of the implicit stage solves (mprk_precisions.stage_start)')
     ap.add_argument('--n', type=int, default=128,
                     help='sweep mode: grid points per axis of the paper\'s test problems')
@@ -399,7 +399,8 @@ def main():
         mixed_over['bj_adapt_tol'] = args.bj_adapt
     if args.stage_start != 'auto':
         mixed_over['stage_start'] = {'rhs': AB.START_RHS, 'slope': AB.START_SLOPE,
-                                     'eval': AB.START_SLOPE_EVAL}[args.stage_start]
+                                     'eval': AB.START_SLOPE_EVAL,
+                                     'extrap': AB.START_EXTRAP}[args.stage_start]
     N = p.N
     K, Wm = args.steps, args.warmup
     log(f'workload {args.workload}: N={N} ({p.n}^3), {p.tableau}, dt={p.dt}, {p.krylov}, '
@@ -441,9 +442,9 @@ def main():
     s_bytes = {'fp64': 8, 'fp32': 4, 'fp16': 2}[p.precision]
     bs = st.prec.block if st.prec.precond == AB.PRECOND_BJ else 0
     nv = {'stage_rhs': 3, 'combine': 3}  # SDIRK3: sum over stages of rhs terms; b has 3 terms
-    # start values: k_{i-1} is already a term of rhs_i (a_{i,i-1} != 0 in SDIRK3), so the slope
-    # start reads nothing new; the first stage's rhs + sigma f(u) reads f(u)
-    slope_starts = 1 if launch['stage_start'] == AB.START_SLOPE_EVAL else 0
+    # start values: k_{i-1} and k_{i-2} are already terms of rhs_i (SDIRK3's A is full below
+    # the diagonal), so only f(u) is a new read (first stage, or second under EXTRAP)
+    slope_starts = 1 if launch['stage_start'] in (AB.START_SLOPE_EVAL, AB.START_EXTRAP) else 0
     rows = []
     nnz_row = 0.0
     if args.fmt == 'csr':  # 7-point rows; a zero-Dirichlet face row has one neighbour fewer

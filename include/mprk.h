@@ -60,7 +60,10 @@ enum { MPRK_FP64 = 0, MPRK_FP32 = 1, MPRK_FP16 = 2 };
 enum { MPRK_CG = 0, MPRK_GMRES = 1 };
 enum { MPRK_PRECOND_NONE = 0, MPRK_PRECOND_BJ = 1, MPRK_PRECOND_FDM = 2 };
 enum { MPRK_GMFORM_AUTO = 0, MPRK_GMFORM_GATHER = 1, MPRK_GMFORM_ZSPLIT = 2, MPRK_GMFORM_FOLDED = 3 };
-enum { MPRK_START_AUTO = 0, MPRK_START_RHS = 1, MPRK_START_SLOPE = 2, MPRK_START_SLOPE_EVAL = 3 };
+enum {
+  MPRK_START_AUTO = 0, MPRK_START_RHS = 1, MPRK_START_SLOPE = 2, MPRK_START_SLOPE_EVAL = 3,
+  MPRK_START_EXTRAP = 4
+};
 enum { MPRK_TAB_SDIRK2 = 0, MPRK_TAB_SDIRK3 = 1, MPRK_TAB_MID = 2,
        MPRK_TAB_4S3PA = 3, MPRK_TAB_4S3PB = 4, MPRK_TAB_4S3PC = 5 };
 enum { MPRK_APPLY_K64 = 0,     /* y = K x, FP64 in/out */
@@ -159,14 +162,16 @@ typedef struct {
  *           diagonal block's inverse once plus a per-block index (a single shared inverse when
  *           all blocks coincide, e.g. constant coefficients with block | nx).  Both modes give
  *           bitwise-identical inverses; mode 1 removes the inverse stream from the apply.
- *  stage_start: start value of an implicit stage's solve (the paper leaves it open):
- *           MPRK_START_RHS = y = rhs_i; MPRK_START_SLOPE = y = rhs_i + sigma k_{i-1} for a stage
- *           after the step's first, i.e. the stage slope taken equal to the previous stage's
- *           (the first stage starts from rhs); MPRK_START_SLOPE_EVAL = as SLOPE, and an
- *           implicit first stage from rhs + sigma f(u), f(u) evaluated in FP64 at the step's
- *           start (one more operator evaluation per step).  A step thus depends on u alone,
- *           never on an earlier call.  MPRK_START_AUTO (0) = with GMRES and the FP64 outer loop
- *           SLOPE_EVAL for the FDM preconditioner and SLOPE otherwise; RHS for CG and in the
+ *  stage_start: start value of an implicit stage's solve y_i = rhs_i + sigma k_i (the paper
+ *           leaves it open), i.e. a guess of the stage slope k_i: MPRK_START_RHS = none
+ *           (y = rhs_i); MPRK_START_SLOPE = the previous stage's slope k_{i-1} for the stages
+ *           after the step's first; MPRK_START_SLOPE_EVAL = as SLOPE, and the first implicit
+ *           stage from f(u), evaluated in FP64 at the step's start (one more operator
+ *           evaluation per step); MPRK_START_EXTRAP = the slopes of the two latest stages
+ *           extrapolated linearly in c to c_i (f(u), evaluated at the step's start, taken as the
+ *           slope at c = 0; the first stage from rhs).  A step thus depends on u alone, never on
+ *           an earlier call.  MPRK_START_AUTO (0) = with the FP64 outer loop: GMRES -> SLOPE
+ *           (SLOPE_EVAL under the FDM preconditioner), CG -> EXTRAP (RHS under FDM); RHS in the
  *           one-solve mode (refine_max = 0), whose result depends on the start value.  Every
  *           start value is iterated to the same tolerances; it changes iteration and pass
  *           counts (mprk_launch_info_get reports the one in use). */

@@ -25,7 +25,7 @@ FP64, FP32, FP16 = 0, 1, 2
 CG, GMRES = 0, 1
 PRECOND_NONE, PRECOND_BJ, PRECOND_FDM = 0, 1, 2
 GMFORM_AUTO, GMFORM_GATHER, GMFORM_ZSPLIT, GMFORM_FOLDED = 0, 1, 2, 3
-START_AUTO, START_RHS, START_SLOPE, START_SLOPE_EVAL = 0, 1, 2, 3
+START_AUTO, START_RHS, START_SLOPE, START_SLOPE_EVAL, START_EXTRAP = 0, 1, 2, 3, 4
 TAB_SDIRK2, TAB_SDIRK3, TAB_MID, TAB_4S3PA, TAB_4S3PB, TAB_4S3PC = range(6)
 APPLY_K64, APPLY_M_LP, APPLY_BJ_LP, APPLY_M64, APPLY_FDM_LP = range(5)
 KC_NAMES = ('stage_rhs', 'residual', 'cg_begin', 'cg_dir', 'cg_upd', 'promote', 'gm_begin',

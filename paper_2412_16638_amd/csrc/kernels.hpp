@@ -41,8 +41,10 @@ struct CombArgs {
   const double* v[2 * MAXS];
   double c[2 * MAXS];
   int nv;
-  const double* pv;  // k_stage_rhs: start value y = rhs + pc pv when set
+  const double* pv;  // k_stage_rhs: start value y = rhs + pc pv (+ pc2 pv2) when set
   double pc;
+  const double* pv2;
+  double pc2;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -96,6 +98,11 @@ __global__ __launch_bounds__(TPB) void k_stage_rhs(Launch ln, const double* __re
       loadv<double, double, VEC>(a.pv + e, t);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[v] += a.pc * t[v];
+      if (a.pv2) {
+        loadv<double, double, VEC>(a.pv2 + e, t);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] += a.pc2 * t[v];
+      }
     }
     storev<double, double, VEC>(y + e, acc);
   }

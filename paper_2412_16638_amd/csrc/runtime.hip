@@ -488,7 +488,7 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
   if (p->gm_form < MPRK_GMFORM_AUTO || p->gm_form > MPRK_GMFORM_FOLDED)
     return set_error(MPRK_EINVAL, "gm_form must be one of the MPRK_GMFORM values");
   if (!(p->bj_adapt_tol >= 0.0)) return set_error(MPRK_EINVAL, "bj_adapt_tol must be >= 0");
-  if (p->stage_start < MPRK_START_AUTO || p->stage_start > MPRK_START_SLOPE_EVAL)
+  if (p->stage_start < MPRK_START_AUTO || p->stage_start > MPRK_START_EXTRAP)
     return set_error(MPRK_EINVAL, "stage_start must be one of the MPRK_START values");
   if (p->bj_adapt_tol > 0.0 && p->bj_shared)
     return set_error(MPRK_EINVAL, "adaptive-precision block-Jacobi stores one inverse per block "
@@ -646,18 +646,24 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
   // the fast-diagonalisation inverse is exact for the operators it accepts: one Krylov iteration
   // per pass, so no predicted iteration beyond the last solve's count
   predict_margin = fdm ? 0 : 1;
-  // the start value of the stage solves: with GMRES and the outer loop, the previous stage's
-  // slope is close enough to the new one on advection-dominated stages to save outer passes;
-  // the FP64 evaluation of f(u) pays for itself on the first stage only under the FDM
-  // preconditioner, whose passes reduce the residual further; with CG on stiff diffusion
-  // neither saves a pass (sigma K amplifies the slopes' high-frequency part)
+  // the start value of the stage solves (the automatic choice follows what saved outer passes):
+  // with GMRES the previous stage's slope, and under the FDM preconditioner, whose passes reduce
+  // the residual furthest, also the first stage from f(u); with CG (symmetric, diffusion
+  // operators) the slopes extrapolated linearly in c, which the previous slope alone did not
+  // make close enough; the FDM-preconditioned CG already needs one pass, and the one-solve
+  // mode's result would depend on the start value
   start_mode = p.stage_start;
-  if (start_mode == MPRK_START_AUTO)
-    start_mode = (p.krylov == MPRK_GMRES && p.refine_max > 0)
-                     ? (fdm ? MPRK_START_SLOPE_EVAL : MPRK_START_SLOPE)
-                     : MPRK_START_RHS;
+  if (start_mode == MPRK_START_AUTO) {
+    start_mode = MPRK_START_RHS;
+    if (p.refine_max > 0 && p.krylov == MPRK_GMRES)
+      start_mode = fdm ? MPRK_START_SLOPE_EVAL : MPRK_START_SLOPE;
+    else if (p.refine_max > 0 && !fdm)
+      start_mode = MPRK_START_EXTRAP;
+  }
   start_slope = start_mode >= MPRK_START_SLOPE;
-  start_eval = start_mode == MPRK_START_SLOPE_EVAL;
+  start_eval = start_mode == MPRK_START_SLOPE_EVAL || start_mode == MPRK_START_EXTRAP;
+  start_first_eval = start_mode == MPRK_START_SLOPE_EVAL;
+  start_extrap = start_mode == MPRK_START_EXTRAP;
   if (p.krylov == MPRK_CG) {
     o_r = take(vlp);
     o_z = (bs || fdm) ? take(vlp) : o_r;
@@ -1259,11 +1265,19 @@ int mprk_handle::enqueue_step(bool first_of_call) {
   auto kvec = [&](int j) { return (double*)(ws + o_k + (size_t)j * N * 8); };
   auto evec = [&](int j) { return (double*)(ws + o_keps + (size_t)j * N * 8); };
   const int s = nstages;
+  // f(u), the slope at the step's start, for the start values (an explicit first stage
+  // computes it as k_0)
   double* f0 = (double*)(ws + o_scr);
-  if (start_eval && implicit_[0]) {  // f(u) for the first stage's start value
+  const bool have_f0 = start_eval && implicit_[0];
+  if (have_f0) {
     int rc = launch_apply64(u, f0, 0.0, 0, fterms());
     if (rc) return rc;
   }
+  auto stage_c = [&](int r) {  // c_r = sum_j a_rj; the step's start (r = -1) is c = 0
+    double c = 0.0;
+    for (int j = 0; j <= r; ++j) c += tab.a_hi[r * s + j] + tab.a_lo[r * s + j];
+    return c;
+  };
   for (int i = 0; i < s; ++i) {
     CombArgs a{};
     a.nv = 0;
@@ -1285,12 +1299,24 @@ int mprk_handle::enqueue_step(bool first_of_call) {
         a.c[a.nv++] = dt * al;
       }
     }
+    const double sg = cfgs[sig_idx[i]].sigma;
     if (start_slope && implicit_[i] && i > 0) {  // start value rhs + sigma k_{i-1}
       a.pv = kvec(i - 1);
-      a.pc = cfgs[sig_idx[i]].sigma;
-    } else if (start_eval && implicit_[i] && i == 0) {  // rhs + sigma f(u)
+      a.pc = sg;
+      // linear in c through k_{i-1} and k_{i-2} (f(u) at c = 0 before the first stage)
+      const int j2 = i - 2;
+      if (start_extrap && (j2 >= 0 || have_f0)) {
+        const double d1 = stage_c(i) - stage_c(i - 1), d0 = stage_c(i - 1) - stage_c(j2);
+        if (std::fabs(d0) > 1e-12) {
+          const double th = d1 / d0;
+          a.pc = sg * (1.0 + th);
+          a.pv2 = j2 >= 0 ? kvec(j2) : f0;
+          a.pc2 = -sg * th;
+        }
+      }
+    } else if (start_first_eval && have_f0 && i == 0) {  // rhs + sigma f(u)
       a.pv = f0;
-      a.pc = cfgs[sig_idx[i]].sigma;
+      a.pc = sg;
     }
     const int reset = i > 0 ? RESET_STAGE
                             : RESET_STAGE | RESET_STEP | (first_of_call ? RESET_CALL : 0);

@@ -119,7 +119,9 @@ struct mprk_handle {
   int predict_margin = 1;  // iterations enqueued beyond the last solve's count (0 with FDM)
   int start_mode = 0;        // the MPRK_START value in use (resolved from AUTO)
   bool start_slope = false;  // implicit stages after the first start from rhs + sigma k_{i-1}
-  bool start_eval = false;   // the first implicit stage from rhs + sigma f(u)
+  bool start_eval = false;        // f(u) evaluated at the step's start
+  bool start_first_eval = false;  // the first implicit stage from rhs + sigma f(u)
+  bool start_extrap = false;      // later stages from the slopes extrapolated linearly in c
   // per-stage history of the last completed solve (slot s = mprk_solve), used to enqueue each
   // pass's Krylov iterations without waiting for the device
   struct StageHist {

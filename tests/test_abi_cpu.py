@@ -240,8 +240,9 @@ def test_size_limit_of_int32_indexing():
     (A.GMRES, A.PRECOND_BJ, 20, A.START_SLOPE),
     (A.GMRES, A.PRECOND_FDM, 20, A.START_SLOPE_EVAL),
     (A.GMRES, A.PRECOND_BJ, 0, A.START_RHS),      # one-solve mode: the result depends on it
-    (A.CG, A.PRECOND_BJ, 8, A.START_RHS),
+    (A.CG, A.PRECOND_BJ, 8, A.START_EXTRAP),
     (A.CG, A.PRECOND_FDM, 8, A.START_RHS),
+    (A.CG, A.PRECOND_BJ, 0, A.START_RHS),
 ])
 def test_automatic_stage_start_resolution(krylov, precond, refine_max, want):
     p = A.mprk_precisions_default(A.FP32, krylov)
@@ -255,14 +256,14 @@ def test_automatic_stage_start_resolution(krylov, precond, refine_max, want):
 
 
 def test_stage_start_is_validated_and_kept_when_explicit():
-    for v in (A.START_RHS, A.START_SLOPE, A.START_SLOPE_EVAL):
+    for v in (A.START_RHS, A.START_SLOPE, A.START_SLOPE_EVAL, A.START_EXTRAP):
         p = A.mprk_precisions_default(A.FP32, A.CG)
         p.stage_start = v
         rc, h = _create(prec=p)
         assert rc == A.OK, A.mprk_last_error()
         assert A.mprk_launch_info_get(h.value)['stage_start'] == v
         A.lib.mprk_destroy(h)
-    for v in (-1, 4):
+    for v in (-1, 5):
         p = A.mprk_precisions_default(A.FP32, A.CG)
         p.stage_start = v
         rc, _ = _create(prec=p)

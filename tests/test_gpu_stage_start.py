@@ -1,7 +1,8 @@
 """Start values of the implicit stage solves (mprk_precisions.stage_start) through the C ABI.
 
 The start value is the library's choice (the paper leaves it open): rhs, rhs + sigma k_{i-1}
-for the stages after the first, and additionally rhs + sigma f(u) for the first.  Each is
+for the stages after the first, additionally rhs + sigma f(u) for the first, or the slopes
+extrapolated linearly in c (f(u) at c = 0).  Each is
 iterated to the same tolerances, so every mode must match the FP64 oracle to the storage's
 bound and the modes must agree with each other; a step depends on u alone, so the result does
 not depend on how the steps are split into calls; AUTO is bitwise the mode it resolves to.
@@ -18,7 +19,7 @@ M = pytest.importorskip('paper_2412_16638_amd')
 A = M._abi
 
 TOL = {'fp64': 1e-12, 'fp32': 1e-6, 'fp16': 1e-3}
-MODES = [A.START_RHS, A.START_SLOPE, A.START_SLOPE_EVAL]
+MODES = [A.START_RHS, A.START_SLOPE, A.START_SLOPE_EVAL, A.START_EXTRAP]
 
 
 def _problem(name):
@@ -94,8 +95,9 @@ def test_auto_is_bitwise_the_mode_it_resolves_to(name):
     assert sa['iters'] == sb['iters'] and sa['passes'] == sb['passes']
 
 
-@pytest.mark.parametrize("mode", [A.START_SLOPE, A.START_SLOPE_EVAL])
-@pytest.mark.parametrize("name", ['advdiff_fp16_gmres_bj', 'advdiff_fp16_gmres_fdm'])
+@pytest.mark.parametrize("mode", [A.START_SLOPE, A.START_SLOPE_EVAL, A.START_EXTRAP])
+@pytest.mark.parametrize("name", ['advdiff_fp16_gmres_bj', 'advdiff_fp16_gmres_fdm',
+                                  'heat_fp32_cg_bj'])
 def test_result_does_not_depend_on_the_call_split(name, mode):
     # a step starts from values of its own stages (and f(u)), never from an earlier call
     p, fmt = _problem(name)
@@ -105,18 +107,47 @@ def test_result_does_not_depend_on_the_call_split(name, mode):
     assert np.array_equal(u1, u2)
 
 
-def test_set_u_between_calls_restarts_cleanly():
+@pytest.mark.parametrize("mode", [A.START_SLOPE, A.START_EXTRAP])
+def test_set_u_between_calls_restarts_cleanly(mode):
     # a new state between calls: the next step's first stage must not start from the old slopes
     p, fmt = _problem('advdiff_fp16_gmres_bj')
-    log_case('stage_start_set_u')
-    a = M.from_problem(p, fmt=fmt, stage_start=A.START_SLOPE)
+    log_case('stage_start_set_u', mode=mode)
+    a = M.from_problem(p, fmt=fmt, stage_start=mode)
     a.step(3)
     a.set_u(p.u0)
     a.step(p.nsteps)
     ua = a.get_u()
     a.close()
-    ub, _, _ = _run(p, fmt, stage_start=A.START_SLOPE)
+    ub, _, _ = _run(p, fmt, stage_start=mode)
     assert np.array_equal(ua, ub)
+
+
+def test_extrapolation_with_an_explicit_first_stage():
+    # a first stage with a_11 = 0 computes f(u) as k_0 itself: the second stage starts from
+    # k_0, the third extrapolates from k_0 and k_1
+    p = W.heat_modes(n=16, nsteps=6)
+    log_case('stage_start_explicit_first')
+    us = []
+    for mode in (A.START_RHS, A.START_EXTRAP):
+        t = A.mprk_tableau_builtin(A.TAB_SDIRK3)
+        s = t.s
+        # a 4-stage tableau: an explicit first stage, then SDIRK3 (stiffly accurate, order 3)
+        e = A.mprk_tableau()
+        e.s = s + 1
+        for i in range(s):
+            for j in range(s):
+                e.a_hi[(i + 1) * (s + 1) + (j + 1)] = t.a_hi[i * s + j]
+                e.a_lo[(i + 1) * (s + 1) + (j + 1)] = t.a_lo[i * s + j]
+        for i in range(s):
+            e.b[i + 1] = t.b[i]
+        prec = M.precisions('fp32', 'cg', stage_start=mode, rtol=1e-3, outer_tol=1e-10)
+        st = M.Stepper(p.n, p.bc, p.kind, p.diff, p.b, A.FMT_STENCIL, e, prec, p.dt)
+        st.set_u(p.u0)
+        stats = st.step(p.nsteps)
+        assert stats['missed'] == 0
+        us.append(st.get_u())
+        st.close()
+    assert rel_l2(us[1], us[0]) <= 1e-8
 
 
 @pytest.mark.parametrize("mode", MODES)
