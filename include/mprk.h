@@ -407,7 +407,9 @@ typedef struct { mprk_grid grid; mprk_operator op; double dt; } mprk_problem;
 typedef struct mprk_batch mprk_batch;
 
 /* Create a batch of `count` problems (count >= 1).  Errors as mprk_create; MPRK_EUNSUPPORTED
- * for GMRES, CSR or FP16/FP32 compute combinations the batched kernel does not implement. */
+ * for GMRES, CSR or FP16/FP32 compute combinations the batched kernel does not implement.
+ * stage_start as for one problem; AUTO = EXTRAP with the outer loop, RHS in the one-solve
+ * mode. */
 int32_t mprk_batch_create(int32_t count, const mprk_problem *problems, const mprk_tableau *tab,
                           const mprk_precisions *prec, void *hip_stream, mprk_batch **out);
 /* CTA-group schedule: workgroups per problem.  By default they are planned in proportion to an

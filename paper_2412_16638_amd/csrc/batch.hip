@@ -60,6 +60,12 @@ struct BArgs {
   double b[MAXS];
   double rtol, atol, outer_tol;
   int maxit, max_passes, paper_mode, bs;
+  // start values of the stage solves: y = rhs + sigma (ya[i] k_{i-1} + yb[i] k_{yj[i]}) for a
+  // stage i > 0; the first stage y = rhs + sigma y0f f(u) when feval, f(u) also kept in the
+  // last stage's slope slot until the second stage reads it when fkeep
+  double ya[MAXS], yb[MAXS], y0f;
+  int yj[MAXS];
+  int feval, fkeep;
 };
 
 // Data one workgroup writes and another reads inside a stage launch (the stencil inputs y, p
@@ -231,14 +237,24 @@ __global__ __launch_bounds__(TPB, (kb_min_waves<S, RU>())) void kb_stage(BArgs a
 
   if (stage == 0 && wl == 0 && threadIdx.x == 0)
     __hip_atomic_store(&ctl->step_nonfinite, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // ---- stage right-hand side: rhs = u + dt sum_{j<stage} a_ij k_j ; y = rhs ----
+  // ---- stage right-hand side: rhs = u + dt sum_{j<stage} a_ij k_j ; y = its start value ----
   for (int it = 0; it < nit; ++it) {
     const int row = r0 + it * TPB + threadIdx.x;
     if (row >= r1) break;
     double acc = P.u[row];
     for (int j = 0; j < stage; ++j) acc += P.dt * a.A[stage][j] * P.k[(size_t)j * N + row];
     P.rhs[row] = acc;
-    store_shared(P.y + row, acc);
+    double yv = acc;
+    if (stage == 0 && a.feval) {
+      double uc;
+      const double fu = k64_row(P.geo, P.K, P.u, row, uc);
+      yv += sigma * a.y0f * fu;
+      if (a.fkeep) P.k[(size_t)(a.s - 1) * N + row] = fu;
+    } else if (stage > 0) {
+      yv += sigma * a.ya[stage] * P.k[(size_t)(stage - 1) * N + row];
+      if (a.yb[stage] != 0.0) yv += sigma * a.yb[stage] * P.k[(size_t)a.yj[stage] * N + row];
+    }
+    store_shared(P.y + row, yv);
   }
   group_barrier(ctl, P.nwg);
 
@@ -526,6 +542,8 @@ extern "C" int32_t mprk_batch_create(int32_t count, const mprk_problem* problems
     return set_error(MPRK_EUNSUPPORTED, "batched form keeps block-Jacobi inverses in the storage type");
   if (prec->precond == MPRK_PRECOND_FDM)
     return set_error(MPRK_EUNSUPPORTED, "batched form implements block-Jacobi or no preconditioner");
+  if (prec->stage_start < MPRK_START_AUTO || prec->stage_start > MPRK_START_EXTRAP)
+    return set_error(MPRK_EINVAL, "stage_start must be one of the MPRK_START values");
   // one distinct nonzero diagonal, no eps off-diagonals needing k^eps, all stages implicit
   double diag = 0.0;
   for (int i = 0; i < tab->s; ++i) {
@@ -728,6 +746,30 @@ static BArgs batch_args(mprk_batch* b) {
   a.max_passes = std::max(b->prec.refine_max, 1);
   a.paper_mode = b->prec.refine_max == 0;
   a.bs = b->bs;
+  // start values (as for a single problem; every stage is implicit here): AUTO takes the
+  // extrapolated slopes with the outer loop, rhs in the one-solve mode
+  int mode = b->prec.stage_start;
+  if (mode == MPRK_START_AUTO) mode = a.paper_mode ? MPRK_START_RHS : MPRK_START_EXTRAP;
+  auto cst = [&](int r) {  // c_r; the step's start (r = -1) is c = 0
+    double c = 0.0;
+    for (int j = 0; j <= r; ++j) c += a.A[r][j];
+    return c;
+  };
+  a.feval = mode == MPRK_START_SLOPE_EVAL || (mode == MPRK_START_EXTRAP && a.s > 1);
+  a.fkeep = mode == MPRK_START_EXTRAP && a.s > 1;
+  a.y0f = mode == MPRK_START_SLOPE_EVAL ? 1.0 : 0.0;
+  for (int i = 1; i < a.s; ++i) {
+    a.ya[i] = mode == MPRK_START_RHS ? 0.0 : 1.0;
+    a.yb[i] = 0.0;
+    a.yj[i] = 0;
+    if (mode != MPRK_START_EXTRAP) continue;
+    const double d1 = cst(i) - cst(i - 1), d0 = cst(i - 1) - cst(i - 2);
+    if (std::fabs(d0) <= 1e-12) continue;
+    const double th = d1 / d0;
+    a.ya[i] = 1.0 + th;
+    a.yb[i] = -th;
+    a.yj[i] = i >= 2 ? i - 2 : a.s - 1;  // the slot holding f(u) before the second stage
+  }
   return a;
 }
 

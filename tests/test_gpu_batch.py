@@ -111,3 +111,26 @@ def test_autotune_refuses_a_fixed_schedule():
     with pytest.raises(A.MprkError):
         b.autotune()
     b.close()
+
+
+@pytest.mark.parametrize("mode", [A.START_RHS, A.START_SLOPE, A.START_SLOPE_EVAL, A.START_EXTRAP])
+def test_batch_start_values_reach_the_oracle(mode):
+    # every start value is iterated to the same tolerances: each problem within the FP32 bound
+    probs = W.heat_batch(count=4, nmin=14, nmax=36, nsteps=4)
+    log_case('batch_start', mode=mode, sizes=[p.n for p in probs])
+    us, st = _run_batch(probs, M.precisions('fp32', 'cg', stage_start=mode), 4)
+    for p, u, s in zip(probs, us, st):
+        p.nsteps = 4
+        err = rel_l2_floor(u, reference_solution(p), p.u0)
+        print(mode, p.n, err, s['iters'], s['passes'])
+        assert s['steps'] == 4
+        assert err <= 1e-6
+
+
+def test_batch_auto_start_is_the_extrapolation():
+    probs = W.heat_batch(count=3, nmin=16, nmax=32, nsteps=3)
+    log_case('batch_start_auto')
+    a, _ = _run_batch(probs, M.precisions('fp32', 'cg'), 3)
+    b, _ = _run_batch(probs, M.precisions('fp32', 'cg', stage_start=A.START_EXTRAP), 3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
