@@ -1299,7 +1299,7 @@ int mprk_handle::enqueue_step(bool first_of_call) {
         a.c[a.nv++] = dt * al;
       }
     }
-    const double sg = cfgs[sig_idx[i]].sigma;
+    const double sg = implicit_[i] ? cfgs[sig_idx[i]].sigma : 0.0;  // (no shift when explicit)
     if (start_slope && implicit_[i] && i > 0) {  // start value rhs + sigma k_{i-1}
       a.pv = kvec(i - 1);
       a.pc = sg;
