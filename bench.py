@@ -671,6 +671,9 @@ def main():
     prec = M.precisions(p.precision, p.krylov, **MIXED_TOL[args.workload])
     out['config']['outer_tol'] = prec.outer_tol
     out['config']['inner_rtol'] = prec.rtol
+    out['config']['stage_start'] = {AB.START_RHS: 'rhs', AB.START_SLOPE: 'slope',
+                                    AB.START_SLOPE_EVAL: 'slope_eval',
+                                    AB.START_EXTRAP: 'extrap'}.get(launch['stage_start'])
     print(json.dumps(out), flush=True)
 
 
