@@ -125,8 +125,10 @@ typedef struct {
  *  refine_max/outer_tol: the FP64 outer residual loop.  Each pass computes the FP64 residual
  *           res = rhs - (I - sigma K) y, solves the scaled correction system in LP and adds it
  *           to y.  The stage stops when ||res|| <= outer_tol ||rhs|| or after refine_max passes.
- *           refine_max = 0 is the paper's one-shot mode: exactly one LP solve (for GMRES one
- *           cycle) on the converted right-hand side, no residual check.
+ *           With LP storage an inner solve also stops once its residual shows that the update
+ *           meets half of outer_tol (rtol stays the bound on its iterations); FP64 storage
+ *           solves each pass to rtol.  refine_max = 0 is the paper's one-shot mode: exactly one
+ *           LP solve (for GMRES one cycle) on the converted right-hand side, no residual check.
  *  strict: make a stage that misses its tolerance an error: outer_tol after refine_max passes,
  *           or, with refine_max = 0, the LP solve's own tolerance within maxit.  The step of
  *           that stage is not combined and the call's later steps are skipped, so u is left at

@@ -60,6 +60,7 @@ struct BArgs {
   double b[MAXS];
   double rtol, atol, outer_tol;
   int maxit, max_passes, paper_mode, bs;
+  int outer_stop;  // inner solves also stop at the outer target (as SolveCfg::outer_stop)
   // start values of the stage solves: y = rhs + sigma (ya[i] k_{i-1} + yb[i] k_{yj[i]}) for a
   // stage i > 0; the first stage y = rhs + sigma y0f f(u) when feval, f(u) also kept in the
   // last stage's slope slot until the second stage reads it when fkeep
@@ -316,7 +317,9 @@ __global__ __launch_bounds__(TPB, (kb_min_waves<S, RU>())) void kb_stage(BArgs a
     }
     group_reduce<BND>(acc2, 2, P, wl, parity, t);
     double rz = t[0];
-    const double tol = fmax(a.rtol * sqrt(t[1]), a.atol / scale);
+    // (the outer target as for a single problem: the 2-norm of the LP residual, unit = scale)
+    const double tol = fmax(fmax(a.rtol * sqrt(t[1]), a.atol / scale),
+                            a.outer_stop ? 0.5 * a.outer_tol * bn / scale : 0.0);
     bool inner_done = sqrt(t[1]) <= tol;
     bool inner_conv = inner_done;
     double beta = 0.0;
@@ -745,6 +748,7 @@ static BArgs batch_args(mprk_batch* b) {
   a.maxit = b->prec.maxit;
   a.max_passes = std::max(b->prec.refine_max, 1);
   a.paper_mode = b->prec.refine_max == 0;
+  a.outer_stop = !a.paper_mode && b->prec.storage != MPRK_FP64;
   a.bs = b->bs;
   // start values (as for a single problem; every stage is implicit here): AUTO takes the
   // extrapolated slopes with the outer loop, rhs in the one-solve mode

@@ -668,7 +668,8 @@ __global__ __launch_bounds__(TPB) void k_cg_begin_ext(Launch ln, const double* _
     ctl->rr = rr;
     ctl->beta = 0.0;
     ctl->iters = 0;
-    ctl->tol = fmax(cfg.rtol * bn, cfg.atol / ctl->scale);
+    ctl->tol = fmax(fmax(cfg.rtol * bn, cfg.atol / ctl->scale),
+                    outer_target(cfg, ctl, ctl->scale));
     ctl->inner_conv = bn <= ctl->tol;
     ctl->inner_done = ctl->inner_conv || cfg.maxit <= 0;
   }

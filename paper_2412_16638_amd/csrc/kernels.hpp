@@ -561,7 +561,8 @@ __global__ __launch_bounds__(TPB) void k_cg_begin(Launch ln, const double* __res
     ctl->rr = rr;
     ctl->beta = 0.0;
     ctl->iters = 0;
-    ctl->tol = fmax(cfg.rtol * bn, cfg.atol / ctl->scale);
+    ctl->tol = fmax(fmax(cfg.rtol * bn, cfg.atol / ctl->scale),
+                    outer_target(cfg, ctl, ctl->scale));
     ctl->inner_conv = bn <= ctl->tol;
     ctl->inner_done = ctl->inner_conv || cfg.maxit <= 0;
   }
@@ -769,7 +770,8 @@ __global__ __launch_bounds__(TPB) void k_gm_begin(Launch ln, const double* __res
     for (int i = 1; i <= MAXM; ++i) ctl->g[i] = 0.0;
     ctl->J = 0;
     ctl->iters = 0;
-    ctl->tol = fmax(cfg.rtol * beta, cfg.atol / (ctl->scale * cfg.sqrtN));
+    ctl->tol = fmax(fmax(cfg.rtol * beta, cfg.atol / (ctl->scale * cfg.sqrtN)),
+                    outer_target(cfg, ctl, ctl->scale * cfg.sqrtN));
     ctl->inner_conv = (beta <= ctl->tol) || beta == 0.0;
     ctl->inner_done = ctl->inner_conv || cfg.maxit <= 0;
   }

@@ -752,6 +752,7 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
     c.outer_tol = p.outer_tol;
     c.max_passes = std::max(p.refine_max, 1);
     c.paper_mode = p.refine_max == 0;
+    c.outer_stop = !c.paper_mode && p.storage != MPRK_FP64;
     c.strict = p.strict != 0;
     c.rtol = p.rtol;
     c.atol = p.atol;
