@@ -97,6 +97,10 @@ MIXED_TOL = {'heat128': dict(rtol=1e-3, outer_tol=1e-6), 'advdiff256': {}}
 # residual tolerance (inner and outer) of the all-FP64 reference integration
 REF_TOL = 1e-12
 
+# FP64 comparison runs stop their inner solves at the outer target too, as the mixed path does
+# by default (the FP64 references solved to REF_TOL keep solving each pass to rtol)
+FP64_CMP = {'inner_stop': 1}
+
 
 def make_problem(name: str, precond: str = 'bj'):
     import workloads as W
@@ -220,7 +224,8 @@ def nonlinear_leg(M, args, fmt, bjs, mixed_over, K: int, Wm: int) -> dict:
     t, stats, _ = time_steps(st, q.u0, K, Wm)
     st.close()
     pm = M.precisions(q.precision, q.krylov, **MIXED_TOL[args.workload])
-    over64 = dict(rtol=pm.rtol, outer_tol=pm.outer_tol, bj_shared=bjs, refine_max=NONLINEAR_PASSES)
+    over64 = dict(rtol=pm.rtol, outer_tol=pm.outer_tol, bj_shared=bjs, refine_max=NONLINEAR_PASSES,
+                  **FP64_CMP)
     u64, _ = run_integration(M, r64, fmt, **over64)
     e64 = float(np.linalg.norm(u64 - ref) / np.linalg.norm(ref))
     st64 = M.from_problem(r64, fmt=fmt, **over64)
@@ -256,7 +261,7 @@ def fdm_leg(M, K: int, Wm: int) -> dict:
         t, stats, _ = time_steps(st, p.u0, K, Wm)
         st.close()
         pm = M.precisions(p.precision, p.krylov, **over)
-        st64 = M.from_problem(q, rtol=pm.rtol, outer_tol=pm.outer_tol)
+        st64 = M.from_problem(q, rtol=pm.rtol, outer_tol=pm.outer_tol, **FP64_CMP)
         st64.autotune()
         t64, _, _ = time_steps(st64, q.u0, K, Wm)
         st64.close()
@@ -524,7 +529,7 @@ def main():
     if not args.no_fp64 and ref is not None:
         for tol in (1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8, 1e-9, 1e-10,
                     3e-11, 1e-11):
-            over = dict(rtol=tol, outer_tol=tol, bj_shared=bjs)
+            over = dict(rtol=tol, outer_tol=tol, bj_shared=bjs, **FP64_CMP)
             q = make_problem(args.workload, args.precond)
             q.precision = 'fp64'
             u64, s64 = run_integration(M, q, fmt, **over)
@@ -546,7 +551,7 @@ def main():
         pm = M.precisions(p.precision, p.krylov, **MIXED_TOL[args.workload])
         q = make_problem(args.workload, args.precond)
         q.precision = 'fp64'
-        over = dict(rtol=pm.rtol, outer_tol=pm.outer_tol, bj_shared=bjs)
+        over = dict(rtol=pm.rtol, outer_tol=pm.outer_tol, bj_shared=bjs, **FP64_CMP)
         u64, s64 = run_integration(M, q, fmt, **over)
         e64 = float(np.linalg.norm(u64 - ref) / np.linalg.norm(ref))
         st64 = M.from_problem(q, fmt=fmt, **over)

@@ -64,6 +64,7 @@ enum {
   MPRK_START_AUTO = 0, MPRK_START_RHS = 1, MPRK_START_SLOPE = 2, MPRK_START_SLOPE_EVAL = 3,
   MPRK_START_EXTRAP = 4
 };
+enum { MPRK_STOP_AUTO = 0, MPRK_STOP_OUTER = 1, MPRK_STOP_RTOL = 2 };
 enum { MPRK_TAB_SDIRK2 = 0, MPRK_TAB_SDIRK3 = 1, MPRK_TAB_MID = 2,
        MPRK_TAB_4S3PA = 3, MPRK_TAB_4S3PB = 4, MPRK_TAB_4S3PC = 5 };
 enum { MPRK_APPLY_K64 = 0,     /* y = K x, FP64 in/out */
@@ -125,10 +126,12 @@ typedef struct {
  *  refine_max/outer_tol: the FP64 outer residual loop.  Each pass computes the FP64 residual
  *           res = rhs - (I - sigma K) y, solves the scaled correction system in LP and adds it
  *           to y.  The stage stops when ||res|| <= outer_tol ||rhs|| or after refine_max passes.
- *           With LP storage an inner solve also stops once its residual shows that the update
- *           meets half of outer_tol (rtol stays the bound on its iterations); FP64 storage
- *           solves each pass to rtol.  refine_max = 0 is the paper's one-shot mode: exactly one
- *           LP solve (for GMRES one cycle) on the converted right-hand side, no residual check.
+ *           inner_stop = MPRK_STOP_OUTER: an inner solve also stops once its residual shows
+ *           that the update meets half of outer_tol (rtol stays the bound on its iterations);
+ *           MPRK_STOP_RTOL: each pass solves to rtol; MPRK_STOP_AUTO (0): OUTER with LP
+ *           storage, RTOL with FP64 storage (whose inner tolerance is the accuracy asked for).
+ *           refine_max = 0 is the paper's one-shot mode: exactly one LP solve (for GMRES one
+ *           cycle) on the converted right-hand side, no residual check (inner_stop unused).
  *  strict: make a stage that misses its tolerance an error: outer_tol after refine_max passes,
  *           or, with refine_max = 0, the LP solve's own tolerance within maxit.  The step of
  *           that stage is not combined and the call's later steps are skipped, so u is left at
@@ -191,6 +194,7 @@ typedef struct {
   int32_t gm_form;
   double bj_adapt_tol;
   int32_t stage_start;
+  int32_t inner_stop;
 } mprk_precisions;
 
 /* Statistics.  Per-stage entries describe the most recent step. */

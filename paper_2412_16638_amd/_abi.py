@@ -26,6 +26,7 @@ CG, GMRES = 0, 1
 PRECOND_NONE, PRECOND_BJ, PRECOND_FDM = 0, 1, 2
 GMFORM_AUTO, GMFORM_GATHER, GMFORM_ZSPLIT, GMFORM_FOLDED = 0, 1, 2, 3
 START_AUTO, START_RHS, START_SLOPE, START_SLOPE_EVAL, START_EXTRAP = 0, 1, 2, 3, 4
+STOP_AUTO, STOP_OUTER, STOP_RTOL = 0, 1, 2
 TAB_SDIRK2, TAB_SDIRK3, TAB_MID, TAB_4S3PA, TAB_4S3PB, TAB_4S3PC = range(6)
 APPLY_K64, APPLY_M_LP, APPLY_BJ_LP, APPLY_M64, APPLY_FDM_LP = range(5)
 KC_NAMES = ('stage_rhs', 'residual', 'cg_begin', 'cg_dir', 'cg_upd', 'promote', 'gm_begin',
@@ -58,7 +59,8 @@ class mprk_precisions(C.Structure):
                 ('rtol', C.c_double), ('atol', C.c_double), ('maxit', C.c_int32),
                 ('refine_max', C.c_int32), ('outer_tol', C.c_double), ('strict', C.c_int32),
                 ('reorth', C.c_int32), ('bj_shared', C.c_int32), ('gm_form', C.c_int32),
-                ('bj_adapt_tol', C.c_double), ('stage_start', C.c_int32)]
+                ('bj_adapt_tol', C.c_double), ('stage_start', C.c_int32),
+                ('inner_stop', C.c_int32)]
 
 
 class mprk_stats(C.Structure):

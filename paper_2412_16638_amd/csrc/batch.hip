@@ -547,6 +547,8 @@ extern "C" int32_t mprk_batch_create(int32_t count, const mprk_problem* problems
     return set_error(MPRK_EUNSUPPORTED, "batched form implements block-Jacobi or no preconditioner");
   if (prec->stage_start < MPRK_START_AUTO || prec->stage_start > MPRK_START_EXTRAP)
     return set_error(MPRK_EINVAL, "stage_start must be one of the MPRK_START values");
+  if (prec->inner_stop < MPRK_STOP_AUTO || prec->inner_stop > MPRK_STOP_RTOL)
+    return set_error(MPRK_EINVAL, "inner_stop must be one of the MPRK_STOP values");
   // one distinct nonzero diagonal, no eps off-diagonals needing k^eps, all stages implicit
   double diag = 0.0;
   for (int i = 0; i < tab->s; ++i) {
@@ -748,7 +750,9 @@ static BArgs batch_args(mprk_batch* b) {
   a.maxit = b->prec.maxit;
   a.max_passes = std::max(b->prec.refine_max, 1);
   a.paper_mode = b->prec.refine_max == 0;
-  a.outer_stop = !a.paper_mode && b->prec.storage != MPRK_FP64;
+  a.outer_stop = !a.paper_mode && (b->prec.inner_stop == MPRK_STOP_OUTER ||
+                                   (b->prec.inner_stop == MPRK_STOP_AUTO &&
+                                    b->prec.storage != MPRK_FP64));
   a.bs = b->bs;
   // start values (as for a single problem; every stage is implicit here): AUTO takes the
   // extrapolated slopes with the outer loop, rhs in the one-solve mode

@@ -155,7 +155,7 @@ struct SolveCfg {
   double outer_tol;
   int max_passes;      // LP solves per stage (>= 1)
   int paper_mode;      // refine_max == 0
-  int outer_stop;      // inner solves also stop at the outer target (LP storage, outer loop)
+  int outer_stop;      // inner solves also stop at the outer target (outer loop only)
   int strict;          // a stage that misses its tolerance fails the step (u is not updated)
   double rtol, atol;
   int maxit;           // Krylov iterations per LP solve
@@ -167,9 +167,9 @@ struct SolveCfg {
 // Inner stopping target from the outer test: the update y += scale x leaves an FP64 residual
 // of about unit times the LP residual's norm, so an LP residual below half of
 // outer_tol ||rhs|| / unit already meets the outer tolerance and further iterations are not
-// needed (the inner rtol stays the bound on them).  Only with LP storage and the outer loop
-// (outer_stop): the one-solve mode has no outer test, and an FP64 inner solve's own tolerance
-// is the accuracy asked for.  unit: the FP64 norm of one unit of the LP norm (scale for the
+// needed (the inner rtol stays the bound on them).  Only where outer_stop is set (by default
+// with LP storage and the outer loop: the one-solve mode has no outer test, and an FP64 inner
+// solve's own tolerance is the accuracy asked for).  unit: the FP64 norm of one unit of the LP norm (scale for the
 // 2-norm, scale sqrt N for the RMS norm).
 __device__ __forceinline__ double outer_target(const SolveCfg& cfg, const Ctl* ctl, double unit) {
   return cfg.outer_stop ? 0.5 * cfg.outer_tol * ctl->rhs_norm / unit : 0.0;

@@ -490,6 +490,8 @@ static int validate(const mprk_grid* g, const mprk_operator* op, const mprk_tabl
   if (!(p->bj_adapt_tol >= 0.0)) return set_error(MPRK_EINVAL, "bj_adapt_tol must be >= 0");
   if (p->stage_start < MPRK_START_AUTO || p->stage_start > MPRK_START_EXTRAP)
     return set_error(MPRK_EINVAL, "stage_start must be one of the MPRK_START values");
+  if (p->inner_stop < MPRK_STOP_AUTO || p->inner_stop > MPRK_STOP_RTOL)
+    return set_error(MPRK_EINVAL, "inner_stop must be one of the MPRK_STOP values");
   if (p->bj_adapt_tol > 0.0 && p->bj_shared)
     return set_error(MPRK_EINVAL, "adaptive-precision block-Jacobi stores one inverse per block "
                                   "(bj_shared must be 0)");
@@ -752,7 +754,8 @@ int mprk_handle::init(const mprk_grid& g, const mprk_operator& o, const mprk_tab
     c.outer_tol = p.outer_tol;
     c.max_passes = std::max(p.refine_max, 1);
     c.paper_mode = p.refine_max == 0;
-    c.outer_stop = !c.paper_mode && p.storage != MPRK_FP64;
+    c.outer_stop = !c.paper_mode && (p.inner_stop == MPRK_STOP_OUTER ||
+                                     (p.inner_stop == MPRK_STOP_AUTO && p.storage != MPRK_FP64));
     c.strict = p.strict != 0;
     c.rtol = p.rtol;
     c.atol = p.atol;

@@ -269,3 +269,18 @@ def test_stage_start_is_validated_and_kept_when_explicit():
         rc, _ = _create(prec=p)
         assert rc == A.EINVAL
         assert 'stage_start' in A.mprk_last_error()
+
+
+def test_inner_stop_is_validated():
+    for v in (A.STOP_AUTO, A.STOP_OUTER, A.STOP_RTOL):
+        p = A.mprk_precisions_default(A.FP64, A.CG)
+        p.inner_stop = v
+        rc, h = _create(prec=p)
+        assert rc == A.OK, A.mprk_last_error()
+        A.lib.mprk_destroy(h)
+    for v in (-1, 3):
+        p = A.mprk_precisions_default(A.FP32, A.CG)
+        p.inner_stop = v
+        rc, _ = _create(prec=p)
+        assert rc == A.EINVAL
+        assert 'inner_stop' in A.mprk_last_error()

@@ -134,3 +134,18 @@ def test_batch_auto_start_is_the_extrapolation():
     b, _ = _run_batch(probs, M.precisions('fp32', 'cg', stage_start=A.START_EXTRAP), 3)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_batch_fp64_with_the_outer_stop_meets_the_outer_tolerance():
+    # FP64 storage stopping its inner solves at the outer target: each problem within the outer
+    # tolerance's reach of the oracle, and not more accurate than needed (the stop takes effect)
+    probs = W.heat_batch(count=3, nmin=16, nmax=24, nsteps=3)
+    log_case('batch3_fp64_outer_stop')
+    tight, _ = _run_batch(probs, M.precisions('fp64', 'cg'), 3)
+    loose, _ = _run_batch(probs, M.precisions('fp64', 'cg', inner_stop=A.STOP_OUTER), 3)
+    for p, ut, ul in zip(probs, tight, loose):
+        p.nsteps = 3
+        ref = reference_solution(p)
+        et, el = rel_l2_floor(ut, ref, p.u0), rel_l2_floor(ul, ref, p.u0)
+        print(p.n, 'rtol stop', et, 'outer stop', el)
+        assert et <= 1e-12 and el <= 1e-10
